@@ -1,0 +1,283 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and
+by the benchmark's CPU-baseline leg.  The HIP engine never imports it.
+
+The wrapper marshals NumPy arrays; all arithmetic is in ``oracle.c``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MAX_BASIS = 8
+MAX_SHELLS = 8
+MAX_BONDS = MAX_BASIS * 256
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True, cwd=_HERE)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("bravais", ctypes.c_double * 9),
+                ("n_basis", ctypes.c_int),
+                ("basis", ctypes.c_double * (3 * MAX_BASIS)),
+                ("n_cells", ctypes.c_int * 3),
+                ("periodic", ctypes.c_int * 3),
+                ("lattice_constant", ctypes.c_double)]
+
+
+class Hamiltonian(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double * MAX_BASIS),
+                ("B", ctypes.c_double * 3),
+                ("K", ctypes.c_double * MAX_BASIS),
+                ("K_axis", ctypes.c_double * (3 * MAX_BASIS)),
+                ("n_exch", ctypes.c_int),
+                ("J", ctypes.c_double * MAX_SHELLS),
+                ("n_dmi", ctypes.c_int),
+                ("D", ctypes.c_double * MAX_SHELLS),
+                ("dmi_kind", ctypes.c_int),
+                ("ddi", ctypes.c_int)]
+
+
+class Bond(ctypes.Structure):
+    _fields_ = [("bi", ctypes.c_int), ("bj", ctypes.c_int), ("da", ctypes.c_int),
+                ("db", ctypes.c_int), ("dc", ctypes.c_int), ("shell", ctypes.c_int),
+                ("J", ctypes.c_double), ("D", ctypes.c_double * 3)]
+
+
+class LLGParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("dt", ctypes.c_double), ("T", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("replica", ctypes.c_uint32)]
+
+
+class Observation(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("E", ctypes.c_double),
+                ("per_term", ctypes.c_double * 5), ("max_torque", ctypes.c_double),
+                ("M", ctypes.c_double * 3), ("max_norm_dev", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.ora_create.restype = ctypes.c_void_p
+        L.ora_create.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Hamiltonian)]
+        L.ora_destroy.argtypes = [ctypes.c_void_p]
+        L.ora_num_sites.restype = ctypes.c_int64
+        L.ora_num_sites.argtypes = [ctypes.c_void_p]
+        L.ora_bonds.restype = ctypes.c_int
+        L.ora_bonds.argtypes = [ctypes.c_void_p, ctypes.POINTER(Bond), ctypes.c_int]
+        L.ora_site_neighbours.restype = ctypes.c_int
+        L.ora_site_neighbours.argtypes = [ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+        L.ora_shell_distances.restype = ctypes.c_int
+        L.ora_shell_distances.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, ctypes.c_int]
+        L.ora_gradient.argtypes = [ctypes.c_void_p, dp, dp, dp]
+        L.ora_dipole_gradient_sites.argtypes = [ctypes.c_void_p, dp,
+                                                ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp]
+        L.ora_energy.restype = ctypes.c_double
+        L.ora_energy.argtypes = [ctypes.c_void_p, dp, dp]
+        L.ora_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32),
+                                        ctypes.POINTER(ctypes.c_uint32),
+                                        ctypes.POINTER(ctypes.c_uint32)]
+        L.ora_thermal_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                          ctypes.c_uint32, dp]
+        L.ora_depondt_step.argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(LLGParams),
+                                       ctypes.c_uint64]
+        L.ora_rotate.argtypes = [dp, dp, ctypes.c_double, dp]
+        L.ora_observe.argtypes = [ctypes.c_void_p, dp, ctypes.c_int64,
+                                  ctypes.POINTER(Observation)]
+        L.ora_run.restype = ctypes.c_int64
+        L.ora_run.argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(LLGParams), ctypes.c_uint64,
+                              ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(Observation)]
+        for name in ("ora_const_mu_B", "ora_const_k_B", "ora_const_gamma", "ora_const_C_dd"):
+            getattr(L, name).restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def constants() -> dict:
+    L = lib()
+    return {"mu_B": L.ora_const_mu_B(), "k_B": L.ora_const_k_B(),
+            "gamma": L.ora_const_gamma(), "C_dd": L.ora_const_C_dd()}
+
+
+def _geometry(geo) -> Geometry:
+    g = Geometry()
+    for r in range(3):
+        for k in range(3):
+            g.bravais[3 * r + k] = geo.bravais[r][k]
+    g.n_basis = len(geo.basis)
+    for b, p in enumerate(geo.basis):
+        for k in range(3):
+            g.basis[3 * b + k] = p[k]
+    for k in range(3):
+        g.n_cells[k] = geo.n_cells[k]
+        g.periodic[k] = geo.periodic[k]
+    g.lattice_constant = geo.lattice_constant
+    return g
+
+
+def _hamiltonian(ham) -> Hamiltonian:
+    h = Hamiltonian()
+    for b, m in enumerate(ham.mu):
+        h.mu[b] = m
+    for k in range(3):
+        h.B[k] = ham.B[k]
+    for b, kk in enumerate(ham.K):
+        h.K[b] = kk
+    for b, ax in enumerate(ham.K_axis):
+        for k in range(3):
+            h.K_axis[3 * b + k] = ax[k]
+    h.n_exch = len(ham.J)
+    for s, j in enumerate(ham.J):
+        h.J[s] = j
+    h.n_dmi = len(ham.D)
+    for s, d in enumerate(ham.D):
+        h.D[s] = d
+    h.dmi_kind = ham.dmi_kind
+    h.ddi = 1 if ham.ddi else 0
+    return h
+
+
+class System:
+    """One oracle system (geometry + Hamiltonian); see ``oracle.h``."""
+
+    def __init__(self, geometry, hamiltonian):
+        L = lib()
+        self._g = _geometry(geometry)
+        self._h = _hamiltonian(hamiltonian)
+        self._p = L.ora_create(ctypes.byref(self._g), ctypes.byref(self._h))
+        if not self._p:
+            raise ValueError("oracle rejected the geometry/Hamiltonian")
+        self.N = int(L.ora_num_sites(self._p))
+        self.geometry = geometry
+        self.hamiltonian = hamiltonian
+
+    def __del__(self):
+        p = getattr(self, "_p", None)
+        if p and _lib is not None:
+            _lib.ora_destroy(p)
+            self._p = None
+
+    def _spins(self, n) -> np.ndarray:
+        n = np.ascontiguousarray(n, dtype=np.float64).reshape(3, self.N)
+        return n
+
+    def bonds(self):
+        buf = (Bond * MAX_BONDS)()
+        k = lib().ora_bonds(self._p, buf, MAX_BONDS)
+        return [(b.bi, b.bj, b.da, b.db, b.dc, b.shell, b.J, tuple(b.D)) for b in buf[:k]]
+
+    def neighbours(self, i: int):
+        js = (ctypes.c_int64 * 512)()
+        bs = (ctypes.c_int * 512)()
+        d = lib().ora_site_neighbours(self._p, i, js, bs, 512)
+        return list(js[:d]), list(bs[:d])
+
+    def shell_distances(self, beta: int = 0):
+        out = np.zeros(MAX_SHELLS)
+        k = lib().ora_shell_distances(self._p, beta, _dp(out), MAX_SHELLS)
+        return out[:k]
+
+    def gradient(self, n, terms: bool = False):
+        n = self._spins(n)
+        g = np.zeros((3, self.N))
+        t = np.zeros((5, 3, self.N)) if terms else None
+        lib().ora_gradient(self._p, _dp(n), _dp(g), _dp(t) if terms else None)
+        return (g, t) if terms else g
+
+    def dipole_gradient_sites(self, n, sites):
+        n = self._spins(n)
+        sites = np.ascontiguousarray(sites, dtype=np.int64)
+        out = np.zeros((len(sites), 3))
+        lib().ora_dipole_gradient_sites(self._p, _dp(n),
+                                        sites.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        len(sites), _dp(out))
+        return out.T.copy()
+
+    def energy(self, n, per_term: bool = False):
+        n = self._spins(n)
+        pt = np.zeros(5)
+        E = lib().ora_energy(self._p, _dp(n), _dp(pt))
+        return (E, pt) if per_term else E
+
+    def depondt_step(self, n, alpha, dt, T=0.0, seed=0, step=0, replica=0) -> np.ndarray:
+        n = self._spins(n).copy()
+        p = LLGParams(alpha, dt, T, seed, replica)
+        lib().ora_depondt_step(self._p, _dp(n), ctypes.byref(p), step)
+        return n
+
+    def observe(self, n, step=0) -> dict:
+        n = self._spins(n)
+        o = Observation()
+        lib().ora_observe(self._p, _dp(n), step, ctypes.byref(o))
+        return _obs_dict(o)
+
+    def run(self, n, alpha, dt, n_steps, T=0.0, seed=0, step0=0, replica=0,
+            observe_every=0):
+        n = self._spins(n).copy()
+        p = LLGParams(alpha, dt, T, seed, replica)
+        n_obs = n_steps // observe_every if observe_every > 0 else 0
+        obs = (Observation * max(n_obs, 1))()
+        k = lib().ora_run(self._p, _dp(n), ctypes.byref(p), step0, n_steps, observe_every, obs)
+        return n, [_obs_dict(o) for o in obs[:k]]
+
+
+def _obs_dict(o: Observation) -> dict:
+    return {"step": o.step, "E": o.E, "per_term": list(o.per_term),
+            "max_torque": o.max_torque, "M": list(o.M), "max_norm_dev": o.max_norm_dev}
+
+
+def philox4x32_10(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().ora_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def thermal_normals(seed, step, site, replica=0) -> np.ndarray:
+    out = np.zeros(3)
+    lib().ora_thermal_normals(seed, step, site, replica, _dp(out))
+    return out
+
+
+def rotate(n, omega, dt) -> np.ndarray:
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    w = np.ascontiguousarray(omega, dtype=np.float64)
+    out = np.zeros(3)
+    lib().ora_rotate(_dp(n), _dp(w), dt, _dp(out))
+    return out
+
+
+Optional

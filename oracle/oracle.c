@@ -1,0 +1,587 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle for the atomistic spin hot path of
+ * "Spirit: Multifunctional Framework for Atomistic Spin Simulations"
+ * (arXiv:1901.11350).
+ *
+ * TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU
+ * baseline of the benchmark call it; the HIP engine never does, and the
+ * two share no code.  Built with  gcc -O2 -ffp-contract=off -fopenmp.
+ *
+ * Sources followed (the paper's text):
+ *   - Hamiltonian: Sec. III.A, the extended Heisenberg Hamiltonian equation
+ *     (Zeeman, uniaxial anisotropy, exchange and DMI over unique pairs,
+ *     dipole-dipole), pairs of any distance.
+ *   - LLG: Sec. III.C, LLG equation terms (i) precession and (ii) damping,
+ *     stochastic thermal field with fluctuation-dissipation amplitude and the
+ *     1/sqrt(dt) normalisation.
+ *   - Depondt's rotation-based Heun scheme: Appendix B (predictor rotates
+ *     n(t) by R(A(t)); corrector rotates n(t) by R of the averaged field).
+ *   - Energy from fields: Appendix H (linear + quadratic decomposition of H).
+ * Readings where the paper is silent, garbled or ambiguous are marked
+ * "Reading:" next to the code that takes them.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- constants
+ * Reading: the paper prints no unit system.  CODATA 2018 values in
+ * meV / Tesla / ps / Angstrom. */
+#define J_PER_MEV 1.602176634e-22
+#define MU_B_J_PER_T 9.2740100783e-24
+#define K_B_J_PER_K 1.380649e-23
+#define MU0_OVER_4PI 1.00000000055e-7
+#define GAMMA_RAD_PER_PS_T 0.176085963023
+#define PI 3.14159265358979323846
+
+double ora_const_mu_B(void) { return MU_B_J_PER_T / J_PER_MEV; }
+double ora_const_k_B(void) { return K_B_J_PER_K / J_PER_MEV; }
+double ora_const_gamma(void) { return GAMMA_RAD_PER_PS_T; }
+/* mu0/(4 pi) * mu_B^2 / (1 Angstrom)^3, in meV. */
+double ora_const_C_dd(void) { return MU0_OVER_4PI * MU_B_J_PER_T * MU_B_J_PER_T / 1e-30 / J_PER_MEV; }
+
+/* ------------------------------------------------------------- small vecs */
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double norm3(const double *a) { return sqrt(dot3(a, a)); }
+
+/* ------------------------------------------------------------------ system */
+struct ora_system {
+    ora_geometry geo;
+    ora_hamiltonian ham;
+    int64_t N;
+    int n_bonds;
+    ora_bond bonds[ORA_MAX_BASIS * ORA_MAX_BONDS_PER_BASIS];
+    int n_shell_dist[ORA_MAX_BASIS];
+    double shell_dist[ORA_MAX_BASIS][ORA_MAX_SHELLS];
+    /* explicit neighbour lists: site i's bonds are nb_j[nb_start[i] .. nb_start[i+1]) */
+    int64_t *nb_start;
+    int64_t *nb_j;
+    int *nb_bond;
+    double *pos;   /* 3N cartesian positions in Angstrom (SoA) */
+};
+
+static void cell_of(const ora_system *s, int64_t i, int *a, int *b, int *c, int *beta) {
+    const int na = s->geo.n_cells[0], nb = s->geo.n_cells[1], nc = s->geo.n_cells[2];
+    *a = (int)(i % na);
+    *b = (int)((i / na) % nb);
+    *c = (int)((i / ((int64_t)na * nb)) % nc);
+    *beta = (int)(i / ((int64_t)na * nb * nc));
+}
+
+static int64_t site_of(const ora_system *s, int a, int b, int c, int beta) {
+    const int64_t na = s->geo.n_cells[0], nb = s->geo.n_cells[1], nc = s->geo.n_cells[2];
+    return a + na * (b + nb * (c + nc * (int64_t)beta));
+}
+
+/* Cartesian vector (units of the lattice constant) from basis atom bi in a
+ * cell to basis atom bj in the cell shifted by (da, db, dc). */
+static void bond_vector(const ora_geometry *g, int bi, int bj, int da, int db, int dc, double r[3]) {
+    for (int k = 0; k < 3; ++k)
+        r[k] = da * g->bravais[0 + k] + db * g->bravais[3 + k] + dc * g->bravais[6 + k]
+             + g->basis[3 * bj + k] - g->basis[3 * bi + k];
+}
+
+/* Neighbour shells and bonds.  Sec. III.A: exchange/DMI act on unique pairs
+ * with no limit on their number or distance; shells are given per shell
+ * index.  Reading: for each basis atom, candidate neighbours are sorted by
+ * distance; distinct distances (tie tolerance 1e-6 a) are shells 0, 1, 2, ...
+ * An axis with a single cell and open boundary carries no translations, so
+ * a 2D lattice's shells are in-plane ones. */
+static int build_bonds(ora_system *s) {
+    const ora_geometry *g = &s->geo;
+    const ora_hamiltonian *h = &s->ham;
+    const int R = 4;
+    int n_shells = h->n_exch > h->n_dmi ? h->n_exch : h->n_dmi;
+    int allow[3];
+    for (int k = 0; k < 3; ++k) allow[k] = (g->n_cells[k] > 1 || g->periodic[k]) ? R : 0;
+    s->n_bonds = 0;
+    for (int bi = 0; bi < g->n_basis; ++bi) {
+        /* collect distinct distances */
+        double dist[ORA_MAX_SHELLS];
+        int nd = 0;
+        for (int bj = 0; bj < g->n_basis; ++bj)
+            for (int da = -allow[0]; da <= allow[0]; ++da)
+                for (int db = -allow[1]; db <= allow[1]; ++db)
+                    for (int dc = -allow[2]; dc <= allow[2]; ++dc) {
+                        double r[3];
+                        bond_vector(g, bi, bj, da, db, dc, r);
+                        double d = norm3(r);
+                        if (d < 1e-6) continue;
+                        /* insert d into the sorted list of the ORA_MAX_SHELLS smallest distances */
+                        int dup = 0;
+                        for (int q = 0; q < nd; ++q)
+                            if (fabs(dist[q] - d) < 1e-6) dup = 1;
+                        if (dup) continue;
+                        if (nd < ORA_MAX_SHELLS) {
+                            dist[nd++] = d;
+                        } else if (d < dist[nd - 1]) {
+                            dist[nd - 1] = d;
+                        } else {
+                            continue;
+                        }
+                        for (int q = nd - 1; q > 0 && dist[q] < dist[q - 1]; --q) {
+                            double t = dist[q]; dist[q] = dist[q - 1]; dist[q - 1] = t;
+                        }
+                    }
+        s->n_shell_dist[bi] = nd;
+        for (int q = 0; q < nd; ++q) s->shell_dist[bi][q] = dist[q];
+        if (n_shells > nd) return -1;
+        /* emit one directed bond per candidate in the requested shells */
+        for (int bj = 0; bj < g->n_basis; ++bj)
+            for (int da = -allow[0]; da <= allow[0]; ++da)
+                for (int db = -allow[1]; db <= allow[1]; ++db)
+                    for (int dc = -allow[2]; dc <= allow[2]; ++dc) {
+                        double r[3];
+                        bond_vector(g, bi, bj, da, db, dc, r);
+                        double d = norm3(r);
+                        if (d < 1e-6) continue;
+                        int shell = -1;
+                        for (int q = 0; q < n_shells; ++q)
+                            if (fabs(dist[q] - d) < 1e-6) shell = q;
+                        if (shell < 0) continue;
+                        if (s->n_bonds >= ORA_MAX_BASIS * ORA_MAX_BONDS_PER_BASIS) return -2;
+                        ora_bond *bd = &s->bonds[s->n_bonds++];
+                        bd->bi = bi; bd->bj = bj; bd->da = da; bd->db = db; bd->dc = dc;
+                        bd->shell = shell;
+                        bd->J = shell < h->n_exch ? h->J[shell] : 0.0;
+                        double rhat[3] = {r[0] / d, r[1] / d, r[2] / d};
+                        double Dm = shell < h->n_dmi ? h->D[shell] : 0.0;
+                        /* Reading: the scalar D of a shell becomes a vector along the
+                         * bond (bulk) or along z x r_hat (interfacial); D_ji = -D_ij
+                         * follows from r_hat_ji = -r_hat_ij. */
+                        if (h->dmi_kind == ORA_DMI_BULK) {
+                            for (int k = 0; k < 3; ++k) bd->D[k] = Dm * rhat[k];
+                        } else {
+                            double zhat[3] = {0.0, 0.0, 1.0}, zr[3];
+                            cross3(zhat, rhat, zr);
+                            for (int k = 0; k < 3; ++k) bd->D[k] = Dm * zr[k];
+                        }
+                    }
+    }
+    return 0;
+}
+
+/* Site neighbour lists from the bond table.  Reading: periodic axes wrap,
+ * open axes drop the bond, and a bond that wraps onto its own site is
+ * dropped.  On tiny periodic lattices two translations may reach the same
+ * partner; each is a separate pair of the periodic crystal. */
+static int build_neighbours(ora_system *s) {
+    const int64_t N = s->N;
+    s->nb_start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N + 1));
+    if (!s->nb_start) return -1;
+    int64_t total = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        total = 0;
+        for (int64_t i = 0; i < N; ++i) {
+            int a, b, c, beta;
+            cell_of(s, i, &a, &b, &c, &beta);
+            if (pass == 0) s->nb_start[i] = total;
+            for (int q = 0; q < s->n_bonds; ++q) {
+                const ora_bond *bd = &s->bonds[q];
+                if (bd->bi != beta) continue;
+                int t[3] = {a + bd->da, b + bd->db, c + bd->dc};
+                int ok = 1;
+                for (int k = 0; k < 3; ++k) {
+                    int n_k = s->geo.n_cells[k];
+                    if (t[k] < 0 || t[k] >= n_k) {
+                        if (s->geo.periodic[k]) {
+                            t[k] %= n_k;
+                            if (t[k] < 0) t[k] += n_k;
+                        } else {
+                            ok = 0;
+                        }
+                    }
+                }
+                if (!ok) continue;
+                int64_t j = site_of(s, t[0], t[1], t[2], bd->bj);
+                if (j == i) continue;
+                if (pass == 1) {
+                    s->nb_j[total] = j;
+                    s->nb_bond[total] = q;
+                }
+                ++total;
+            }
+        }
+        if (pass == 0) {
+            s->nb_start[N] = total;
+            s->nb_j = (int64_t *)malloc(sizeof(int64_t) * (size_t)(total > 0 ? total : 1));
+            s->nb_bond = (int *)malloc(sizeof(int) * (size_t)(total > 0 ? total : 1));
+            if (!s->nb_j || !s->nb_bond) return -1;
+        }
+    }
+    return 0;
+}
+
+ora_system *ora_create(const ora_geometry *g, const ora_hamiltonian *h) {
+    if (g->n_basis < 1 || g->n_basis > ORA_MAX_BASIS) return NULL;
+    if (h->n_exch < 0 || h->n_exch > ORA_MAX_SHELLS || h->n_dmi < 0 || h->n_dmi > ORA_MAX_SHELLS) return NULL;
+    for (int k = 0; k < 3; ++k)
+        if (g->n_cells[k] < 1) return NULL;
+    ora_system *s = (ora_system *)calloc(1, sizeof(ora_system));
+    if (!s) return NULL;
+    s->geo = *g;
+    s->ham = *h;
+    s->N = (int64_t)g->n_cells[0] * g->n_cells[1] * g->n_cells[2] * g->n_basis;
+    if (build_bonds(s) != 0 || build_neighbours(s) != 0) {
+        ora_destroy(s);
+        return NULL;
+    }
+    s->pos = (double *)malloc(sizeof(double) * 3 * (size_t)s->N);
+    if (!s->pos) { ora_destroy(s); return NULL; }
+    for (int64_t i = 0; i < s->N; ++i) {
+        int a, b, c, beta;
+        cell_of(s, i, &a, &b, &c, &beta);
+        for (int k = 0; k < 3; ++k) {
+            double r = a * g->bravais[k] + b * g->bravais[3 + k] + c * g->bravais[6 + k] + g->basis[3 * beta + k];
+            s->pos[k * s->N + i] = r * g->lattice_constant;
+        }
+    }
+    return s;
+}
+
+void ora_destroy(ora_system *s) {
+    if (!s) return;
+    free(s->nb_start);
+    free(s->nb_j);
+    free(s->nb_bond);
+    free(s->pos);
+    free(s);
+}
+
+int64_t ora_num_sites(const ora_system *s) { return s->N; }
+
+int ora_bonds(const ora_system *s, ora_bond *out, int max_bonds) {
+    int n = s->n_bonds < max_bonds ? s->n_bonds : max_bonds;
+    memcpy(out, s->bonds, sizeof(ora_bond) * (size_t)n);
+    return s->n_bonds;
+}
+
+int ora_site_neighbours(const ora_system *s, int64_t i, int64_t *j_out, int *bond_out, int max_out) {
+    int64_t deg = s->nb_start[i + 1] - s->nb_start[i];
+    for (int64_t q = 0; q < deg && q < max_out; ++q) {
+        j_out[q] = s->nb_j[s->nb_start[i] + q];
+        bond_out[q] = s->nb_bond[s->nb_start[i] + q];
+    }
+    return (int)deg;
+}
+
+int ora_shell_distances(const ora_system *s, int beta, double *out, int max_out) {
+    int n = s->n_shell_dist[beta];
+    for (int q = 0; q < n && q < max_out; ++q) out[q] = s->shell_dist[beta][q];
+    return n;
+}
+
+static int basis_of(const ora_system *s, int64_t i) {
+    const int64_t cells = (int64_t)s->geo.n_cells[0] * s->geo.n_cells[1] * s->geo.n_cells[2];
+    return (int)(i / cells);
+}
+
+static void load(const double *v, int64_t N, int64_t i, double out[3]) {
+    out[0] = v[i]; out[1] = v[N + i]; out[2] = v[2 * N + i];
+}
+
+/* Dipole-dipole gradient at site i.  Reading: the printed dipole term lacks
+ * the factor 3 and has its sign inverted; the textbook dipolar energy
+ * 1/2 C_dd sum_{i!=j} mu_i mu_j [n_i.n_j - 3 (n_i.r)(n_j.r)] / r^3 is used,
+ * summed over the sites of the sample only (no periodic images).  Its
+ * gradient is C_dd mu_i sum_j mu_j [n_j - 3 (n_j.r) r] / r^3. */
+static void dipole_gradient_at(const ora_system *s, const double *n, int64_t i, double out[3]) {
+    const int64_t N = s->N;
+    const double Cdd = ora_const_C_dd();
+    double acc[3] = {0.0, 0.0, 0.0};
+    double pi[3];
+    load(s->pos, N, i, pi);
+    for (int64_t j = 0; j < N; ++j) {
+        if (j == i) continue;
+        double r[3], nj[3];
+        load(s->pos, N, j, r);
+        for (int k = 0; k < 3; ++k) r[k] -= pi[k];
+        double d = norm3(r);
+        double rh[3] = {r[0] / d, r[1] / d, r[2] / d};
+        load(n, N, j, nj);
+        double mu_j = s->ham.mu[basis_of(s, j)];
+        double nr = dot3(nj, rh);
+        double inv_r3 = 1.0 / (d * d * d);
+        for (int k = 0; k < 3; ++k) acc[k] += mu_j * (nj[k] - 3.0 * nr * rh[k]) * inv_r3;
+    }
+    double mu_i = s->ham.mu[basis_of(s, i)];
+    for (int k = 0; k < 3; ++k) out[k] = Cdd * mu_i * acc[k];
+}
+
+void ora_dipole_gradient_sites(const ora_system *s, const double *n, const int64_t *sites,
+                               int64_t n_req, double *g_out) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < n_req; ++q) dipole_gradient_at(s, n, sites[q], g_out + 3 * q);
+}
+
+/* Gradient dH/dn_i of the Hamiltonian (Sec. III.A) in the embedding space:
+ *   Zeeman      -mu_i mu_B B
+ *   anisotropy  -2 K (K_hat . n_i) K_hat
+ *   exchange    -sum_j J_ij n_j
+ *   DMI         -sum_j n_j x D_ij        (from d/dn_i [D.(n_i x n_j)] = n_j x D)
+ *   dipole      see dipole_gradient_at. */
+void ora_gradient(const ora_system *s, const double *n, double *g, double *terms) {
+    const int64_t N = s->N;
+    const double muB = ora_const_mu_B();
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        int beta = basis_of(s, i);
+        double ni[3];
+        load(n, N, i, ni);
+        double gz[3], gk[3], gj[3] = {0, 0, 0}, gd[3] = {0, 0, 0}, gdd[3] = {0, 0, 0};
+        for (int k = 0; k < 3; ++k) gz[k] = -s->ham.mu[beta] * muB * s->ham.B[k];
+        const double *ax = &s->ham.K_axis[3 * beta];
+        double kn = dot3(ax, ni);
+        for (int k = 0; k < 3; ++k) gk[k] = -2.0 * s->ham.K[beta] * kn * ax[k];
+        for (int64_t q = s->nb_start[i]; q < s->nb_start[i + 1]; ++q) {
+            const ora_bond *bd = &s->bonds[s->nb_bond[q]];
+            double nj[3], c[3];
+            load(n, N, s->nb_j[q], nj);
+            cross3(nj, bd->D, c);
+            for (int k = 0; k < 3; ++k) {
+                gj[k] -= bd->J * nj[k];
+                gd[k] -= c[k];
+            }
+        }
+        if (s->ham.ddi) dipole_gradient_at(s, n, i, gdd);
+        for (int k = 0; k < 3; ++k) g[k * N + i] = gz[k] + gk[k] + gj[k] + gd[k] + gdd[k];
+        if (terms) {
+            for (int k = 0; k < 3; ++k) {
+                terms[0 * 3 * N + k * N + i] = gz[k];
+                terms[1 * 3 * N + k * N + i] = gk[k];
+                terms[2 * 3 * N + k * N + i] = gj[k];
+                terms[3 * 3 * N + k * N + i] = gd[k];
+                terms[4 * 3 * N + k * N + i] = gdd[k];
+            }
+        }
+    }
+}
+
+/* Energy by the definition of the Hamiltonian (Sec. III.A).  The unique-pair
+ * sums of exchange and DMI are taken as 1/2 of the sums over directed bonds
+ * (every unique pair appears once from each side). */
+double ora_energy(const ora_system *s, const double *n, double *per_term) {
+    const int64_t N = s->N;
+    const double muB = ora_const_mu_B();
+    const double Cdd = ora_const_C_dd();
+    double ez = 0.0, ek = 0.0, ej = 0.0, ed = 0.0, edd = 0.0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : ez, ek, ej, ed, edd)
+    for (int64_t i = 0; i < N; ++i) {
+        int beta = basis_of(s, i);
+        double ni[3];
+        load(n, N, i, ni);
+        ez += -s->ham.mu[beta] * muB * dot3(s->ham.B, ni);
+        double kn = dot3(&s->ham.K_axis[3 * beta], ni);
+        ek += -s->ham.K[beta] * kn * kn;
+        for (int64_t q = s->nb_start[i]; q < s->nb_start[i + 1]; ++q) {
+            const ora_bond *bd = &s->bonds[s->nb_bond[q]];
+            double nj[3], c[3];
+            load(n, N, s->nb_j[q], nj);
+            cross3(ni, nj, c);
+            ej += -0.5 * bd->J * dot3(ni, nj);
+            ed += -0.5 * dot3(bd->D, c);
+        }
+        if (s->ham.ddi) {
+            double pi[3];
+            load(s->pos, N, i, pi);
+            for (int64_t j = 0; j < N; ++j) {
+                if (j == i) continue;
+                double r[3], nj[3];
+                load(s->pos, N, j, r);
+                for (int k = 0; k < 3; ++k) r[k] -= pi[k];
+                double d = norm3(r);
+                double rh[3] = {r[0] / d, r[1] / d, r[2] / d};
+                load(n, N, j, nj);
+                double mm = s->ham.mu[beta] * s->ham.mu[basis_of(s, j)];
+                edd += 0.5 * Cdd * mm * (dot3(ni, nj) - 3.0 * dot3(ni, rh) * dot3(nj, rh)) / (d * d * d);
+            }
+        }
+    }
+    if (per_term) {
+        per_term[0] = ez; per_term[1] = ek; per_term[2] = ej; per_term[3] = ed; per_term[4] = edd;
+    }
+    return ez + ek + ej + ed + edd;
+}
+
+/* ------------------------------------------------------------------ Philox
+ * Philox4x32-10 as published by Salmon, Moraes, Dror and Shaw (SC'11):
+ * each round multiplies counter words 0 and 2 by the round multipliers
+ * (full 64-bit products), permutes and xors with the key; the key is
+ * incremented by the Weyl constants between rounds. */
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Sec. III.C: eta_i holds three independent standard normals per step.
+ * Reading: uniforms u_k = (x_k + 1/2) 2^-32 from one Philox block, then the
+ * Box-Muller transform on (u0, u1) and (u2, u3); the first three normals
+ * are used. */
+void ora_thermal_normals(uint64_t seed, uint64_t step, uint32_t site, uint32_t replica, double eta[3]) {
+    uint32_t ctr[4] = {site, (uint32_t)step, (uint32_t)(step >> 32), replica};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    ora_philox4x32_10(ctr, key, x);
+    double u[4];
+    for (int k = 0; k < 4; ++k) u[k] = ((double)x[k] + 0.5) * (1.0 / 4294967296.0);
+    double r0 = sqrt(-2.0 * log(u[0]));
+    double r1 = sqrt(-2.0 * log(u[2]));
+    eta[0] = r0 * cos(2.0 * PI * u[1]);
+    eta[1] = r0 * sin(2.0 * PI * u[1]);
+    eta[2] = r1 * cos(2.0 * PI * u[3]);
+}
+
+/* ------------------------------------------------------------------ LLG */
+
+/* Rotation of n about omega by the angle |omega| dt (Rodrigues' formula).
+ * Reading: the rotation matrix R(A) of Appendix B is not printed; with
+ * dn/dt = n x A = (-A) x n the exact motion for constant A is a rotation
+ * about omega = -A at angular speed |A|. */
+void ora_rotate(const double n[3], const double omega[3], double dt, double out[3]) {
+    double w = norm3(omega);
+    double theta = w * dt;
+    if (theta < 1e-12) {
+        /* second-order Taylor form of the same rotation */
+        double c1[3], c2[3];
+        cross3(omega, n, c1);
+        cross3(omega, c1, c2);
+        for (int k = 0; k < 3; ++k) out[k] = n[k] + c1[k] * dt + 0.5 * c2[k] * dt * dt;
+        return;
+    }
+    double e[3] = {omega[0] / w, omega[1] / w, omega[2] / w};
+    double exn[3];
+    cross3(e, n, exn);
+    double en = dot3(e, n);
+    double ct = cos(theta), st = sin(theta);
+    for (int k = 0; k < 3; ++k) out[k] = n[k] * ct + exn[k] * st + e[k] * en * (1.0 - ct);
+}
+
+/* A_i of the LLG equation written as dn/dt = n x A (Appendix B), terms (i)
+ * precession and (ii) damping of Sec. III.C:
+ *   A = -gamma/(1+alpha^2) (B + alpha n x B),  B in Tesla.
+ * Reading: B_eff = -dH/dn is an energy; dividing by mu_i mu_B gives Tesla,
+ * which is what the 1/mu_i of the printed prefactor expresses. */
+static void llg_A(const double n[3], const double Bt[3], double alpha, double A[3]) {
+    const double gp = ora_const_gamma() / (1.0 + alpha * alpha);
+    double nxB[3];
+    cross3(n, Bt, nxB);
+    for (int k = 0; k < 3; ++k) A[k] = -gp * (Bt[k] + alpha * nxB[k]);
+}
+
+/* Thermal field amplitude in Tesla per component (Sec. III.C):
+ * sqrt(2 alpha k_B T / (gamma mu_i mu_B)) / sqrt(dt). */
+static double thermal_sigma(double alpha, double T, double mu, double dt) {
+    if (T <= 0.0) return 0.0;
+    return sqrt(2.0 * alpha * ora_const_k_B() * T / (ora_const_gamma() * mu * ora_const_mu_B() * dt));
+}
+
+/* Depondt's scheme (Appendix B):
+ *   n^p = R(A(n)) n;   A^c = (A(n) + A(n^p)) / 2;   n(t+dt) = R(A^c) n.
+ * Reading: the same thermal normals enter predictor and corrector
+ * (stochastic Heun); rotation keeps |n| so no renormalisation is applied. */
+void ora_depondt_step(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step) {
+    const int64_t N = s->N;
+    const double muB = ora_const_mu_B();
+    double *g = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    double *np_ = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    double *A = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    double *Bth = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    ora_gradient(s, n, g, NULL);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double mu = s->ham.mu[basis_of(s, i)];
+        double sigma = thermal_sigma(p->alpha, p->T, mu, p->dt);
+        double eta[3] = {0.0, 0.0, 0.0};
+        if (sigma > 0.0) ora_thermal_normals(p->seed, step, (uint32_t)i, p->replica, eta);
+        double ni[3], Bt[3], Ai[3], w[3], out[3];
+        load(n, N, i, ni);
+        for (int k = 0; k < 3; ++k) {
+            Bth[k * N + i] = sigma * eta[k];
+            Bt[k] = -g[k * N + i] / (mu * muB) + Bth[k * N + i];
+        }
+        llg_A(ni, Bt, p->alpha, Ai);
+        for (int k = 0; k < 3; ++k) {
+            A[k * N + i] = Ai[k];
+            w[k] = -Ai[k];
+        }
+        ora_rotate(ni, w, p->dt, out);
+        for (int k = 0; k < 3; ++k) np_[k * N + i] = out[k];
+    }
+    ora_gradient(s, np_, g, NULL);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double mu = s->ham.mu[basis_of(s, i)];
+        double npi[3], ni[3], Bt[3], Ap[3], w[3], out[3];
+        load(np_, N, i, npi);
+        load(n, N, i, ni);
+        for (int k = 0; k < 3; ++k) Bt[k] = -g[k * N + i] / (mu * muB) + Bth[k * N + i];
+        llg_A(npi, Bt, p->alpha, Ap);
+        for (int k = 0; k < 3; ++k) w[k] = -0.5 * (A[k * N + i] + Ap[k]);
+        ora_rotate(ni, w, p->dt, out);
+        for (int k = 0; k < 3; ++k) n[k * N + i] = out[k];
+    }
+    free(g);
+    free(np_);
+    free(A);
+    free(Bth);
+}
+
+/* Observables: energy with per-term split, maximum torque |n x dH/dn|,
+ * mean spin, maximum deviation of |n| from 1. */
+void ora_observe(const ora_system *s, const double *n, int64_t step, ora_observation *obs) {
+    const int64_t N = s->N;
+    double *g = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    ora_gradient(s, n, g, NULL);
+    obs->step = step;
+    obs->E = ora_energy(s, n, obs->per_term);
+    double tmax = 0.0, M[3] = {0, 0, 0}, dev = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        double ni[3], gi[3], t[3];
+        load(n, N, i, ni);
+        load(g, N, i, gi);
+        cross3(ni, gi, t);
+        double tn = norm3(t);
+        if (!(tn <= tmax)) tmax = tn; /* propagates NaN */
+        for (int k = 0; k < 3; ++k) M[k] += ni[k];
+        double dn = fabs(norm3(ni) - 1.0);
+        if (dn > dev) dev = dn;
+    }
+    obs->max_torque = tmax;
+    for (int k = 0; k < 3; ++k) obs->M[k] = M[k] / (double)N;
+    obs->max_norm_dev = dev;
+    free(g);
+}
+
+int64_t ora_run(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step0,
+                int64_t n_steps, int64_t observe_every, ora_observation *obs) {
+    int64_t n_obs = 0;
+    for (int64_t t = 0; t < n_steps; ++t) {
+        ora_depondt_step(s, n, p, step0 + (uint64_t)t);
+        if (observe_every > 0 && (t + 1) % observe_every == 0 && obs)
+            ora_observe(s, n, (int64_t)step0 + t + 1, &obs[n_obs++]);
+    }
+    return n_obs;
+}

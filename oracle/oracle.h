@@ -1,0 +1,133 @@
+/*
+ * oracle.h -- plain FP64 CPU oracle for the atomistic spin hot path of
+ * "Spirit: Multifunctional Framework for Atomistic Spin Simulations"
+ * (arXiv:1901.11350).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no source,
+ * header, table or helper with the HIP engine; both only receive the same
+ * seeded input arrays.
+ *
+ * Everything is double precision, scalar loops, no FMA contraction
+ * (built with -ffp-contract=off), optional OpenMP over sites.
+ *
+ * Units: meV, Tesla, Bohr magneton, Angstrom, picosecond, Kelvin.
+ * Spin / field arrays are structure-of-arrays: x[N], y[N], z[N] stored
+ * contiguously (3N doubles), site index i = a + Na*(b + Nb*(c + Nc*beta)).
+ */
+#ifndef SPIN_ORACLE_H
+#define SPIN_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORA_MAX_BASIS 8
+#define ORA_MAX_SHELLS 8
+#define ORA_MAX_BONDS_PER_BASIS 256
+
+enum { ORA_DMI_BULK = 1, ORA_DMI_INTERFACIAL = 2 };
+
+typedef struct {
+    double bravais[9];                 /* rows a1, a2, a3 (units of the lattice constant) */
+    int n_basis;
+    double basis[3 * ORA_MAX_BASIS];   /* cartesian, units of the lattice constant */
+    int n_cells[3];
+    int periodic[3];
+    double lattice_constant;           /* Angstrom */
+} ora_geometry;
+
+typedef struct {
+    double mu[ORA_MAX_BASIS];          /* Bohr magnetons per basis atom */
+    double B[3];                       /* Tesla */
+    double K[ORA_MAX_BASIS];           /* meV per basis atom */
+    double K_axis[3 * ORA_MAX_BASIS];  /* unit axes per basis atom */
+    int n_exch;
+    double J[ORA_MAX_SHELLS];          /* meV per shell */
+    int n_dmi;
+    double D[ORA_MAX_SHELLS];          /* meV per shell */
+    int dmi_kind;                      /* ORA_DMI_BULK or ORA_DMI_INTERFACIAL */
+    int ddi;                           /* 1: include dipole-dipole direct sum */
+} ora_hamiltonian;
+
+/* One directed bond of a basis atom: from basis atom `bi` in cell x to basis
+ * atom `bj` in cell x + (da, db, dc). */
+typedef struct {
+    int bi, bj, da, db, dc, shell;
+    double J;
+    double D[3];
+} ora_bond;
+
+typedef struct ora_system ora_system;
+
+ora_system *ora_create(const ora_geometry *g, const ora_hamiltonian *h);
+void ora_destroy(ora_system *s);
+int64_t ora_num_sites(const ora_system *s);
+
+/* Bond table (per basis atom, both directions kept).  Returns the number of
+ * bonds written (at most max_bonds). */
+int ora_bonds(const ora_system *s, ora_bond *out, int max_bonds);
+/* Explicit neighbour list of one site: returns its degree, fills j / bond ids. */
+int ora_site_neighbours(const ora_system *s, int64_t i, int64_t *j_out, int *bond_out, int max_out);
+/* Shell distances of basis atom beta (units of the lattice constant). */
+int ora_shell_distances(const ora_system *s, int beta, double *out, int max_out);
+
+/* dH/dn per site (embedding space).  terms, if non-NULL, receives the five
+ * contributions Zeeman, anisotropy, exchange, DMI, dipole as 5 blocks of 3N. */
+void ora_gradient(const ora_system *s, const double *n, double *g, double *terms);
+/* Dipole gradient at a subset of sites only (rows of 3 per requested site). */
+void ora_dipole_gradient_sites(const ora_system *s, const double *n, const int64_t *sites,
+                               int64_t n_req, double *g_out /* 3*n_req, xyz per site */);
+/* Energy by the definition of the Hamiltonian; per_term (may be NULL) gets
+ * Zeeman, anisotropy, exchange, DMI, dipole. */
+double ora_energy(const ora_system *s, const double *n, double *per_term);
+
+/* Philox4x32-10 block (Salmon, Moraes, Dror, Shaw, SC'11). */
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Three standard normals of site `site` at step `step` of replica `replica`:
+ * counter (site, step_lo, step_hi, replica), key (seed_lo, seed_hi). */
+void ora_thermal_normals(uint64_t seed, uint64_t step, uint32_t site, uint32_t replica,
+                         double eta[3]);
+
+typedef struct {
+    double alpha;
+    double dt;       /* ps */
+    double T;        /* K */
+    uint64_t seed;
+    uint32_t replica;
+} ora_llg_params;
+
+/* One Depondt step at step counter `step` (used as the Philox counter). n is
+ * updated in place. */
+void ora_depondt_step(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step);
+/* Rotation of one vector about omega by |omega|*dt (exposed for tests). */
+void ora_rotate(const double n[3], const double omega[3], double dt, double out[3]);
+
+typedef struct {
+    int64_t step;
+    double E;
+    double per_term[5];
+    double max_torque;
+    double M[3];
+    double max_norm_dev;
+} ora_observation;
+
+void ora_observe(const ora_system *s, const double *n, int64_t step, ora_observation *obs);
+/* n_steps Depondt steps starting at step counter step0; an observation is
+ * recorded after every observe_every steps (if > 0).  Returns the number of
+ * observations written. */
+int64_t ora_run(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step0,
+                int64_t n_steps, int64_t observe_every, ora_observation *obs);
+
+/* Physical constants used by the oracle. */
+double ora_const_mu_B(void);
+double ora_const_k_B(void);
+double ora_const_gamma(void);
+double ora_const_C_dd(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
