@@ -1,0 +1,194 @@
+/*
+ * sp_engine.h -- C ABI of the MI355X atomistic-spin engine.
+ *
+ * The engine evaluates the effective field of the extended Heisenberg
+ * Hamiltonian and advances the Landau-Lifshitz-Gilbert equation with
+ * Depondt's rotation-based Heun scheme, following
+ * "Spirit: Multifunctional Framework for Atomistic Spin Simulations"
+ * (arXiv:1901.11350).  Every compute step runs in hand-written HIP kernels
+ * for gfx950.
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ * Units: meV (energies, J, D, K), Tesla (B), Bohr magnetons (mu),
+ *        Angstrom (lattice constant), picoseconds (dt), Kelvin (T).
+ * Site index: i = a + Na*(b + Nb*(c + Nc*beta)) for cell (a, b, c) and
+ *        basis atom beta (each sublattice is a dense Na x Nb x Nc grid).
+ * Vector fields are structure-of-arrays: x[N] then y[N] then z[N].
+ * Host pointers are always double; device-pointer (_dev) variants use the
+ *        engine precision (float for SP_F32, double for SP_F64).
+ * Ownership: host arrays are copied in/out before the call returns; _dev
+ *        variants borrow caller memory for the call only and are ordered on
+ *        the engine stream (no synchronisation with other streams).
+ * Errors: every int-returning call returns SP_OK (0) or a negative
+ *        sp_status; no C++ exception crosses the ABI.  sp_last_error gives
+ *        a message for the last failing call.  A failing set_* call leaves
+ *        the previous state unchanged.
+ * Call order: sp_set_geometry -> sp_set_hamiltonian -> sp_set_spins ->
+ *        compute calls; out of order gives SP_E_ORDER.
+ * Threads: one engine must not be used from two threads at once; separate
+ *        engines are independent.
+ */
+#ifndef SP_ENGINE_H
+#define SP_ENGINE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sp_engine sp_engine;
+
+enum sp_status {
+    SP_OK = 0,
+    SP_E_ARG = -1,          /* invalid argument (size, pointer, value) */
+    SP_E_ORDER = -2,        /* call made before the state it needs was set */
+    SP_E_HIP = -3,          /* HIP runtime error */
+    SP_E_NOMEM = -4,        /* device allocation failed */
+    SP_E_UNSUPPORTED = -5,  /* valid request this build does not support */
+    SP_E_NONFINITE = -6     /* non-finite torque detected during sp_run */
+};
+
+enum sp_precision { SP_F32 = 0, SP_F64 = 1 };
+enum sp_dmi_kind { SP_DMI_BULK = 1, SP_DMI_INTERFACIAL = 2 };
+enum sp_ddi_mode { SP_DDI_OFF = 0, SP_DDI_DIRECT = 1 };
+
+#define SP_MAX_BASIS 8
+#define SP_MAX_SHELLS 8
+
+/* Hamiltonian parameters (Sec. III.A, extended Heisenberg Hamiltonian):
+ *   H = - sum_i mu_i mu_B B . n_i - sum_i K_i (K_hat_i . n_i)^2
+ *       - sum_<ij> J_ij n_i . n_j - sum_<ij> D_ij . (n_i x n_j)
+ *       + 1/2 C_dd sum_{i != j} mu_i mu_j [n_i.n_j - 3 (n_i.r_ij)(n_j.r_ij)] / r_ij^3
+ * over unique pairs <ij>.  J and D are given per neighbour shell (shell s =
+ * the s-th distinct neighbour distance of a basis atom).  The scalar D of a
+ * shell becomes the vector D r_hat_ij (bulk) or D (z x r_hat_ij)
+ * (interfacial).  The dipole term is summed over the sites of the sample
+ * (no periodic images).  mu, K, K_axis are per basis atom. */
+typedef struct {
+    int n_basis;             /* must equal the geometry's n_basis */
+    const double *mu;        /* [n_basis], Bohr magnetons, > 0 */
+    double B[3];             /* Tesla */
+    const double *K;         /* [n_basis], meV (may be NULL: all zero) */
+    const double *K_axis;    /* [3*n_basis], normalised internally (may be NULL if K is) */
+    int n_exch_shells;       /* 0..SP_MAX_SHELLS */
+    const double *J;         /* [n_exch_shells], meV */
+    int n_dmi_shells;        /* 0..SP_MAX_SHELLS */
+    const double *D;         /* [n_dmi_shells], meV */
+    int dmi_kind;            /* SP_DMI_BULK or SP_DMI_INTERFACIAL */
+    int ddi_mode;            /* SP_DDI_OFF or SP_DDI_DIRECT */
+} sp_hamiltonian;
+
+/* LLG parameters (Sec. III.C).  T > 0 adds the stochastic thermal field
+ * sqrt(2 alpha k_B T / (gamma mu_i mu_B dt)) eta_i, eta_i three standard
+ * normals per site and step from Philox4x32-10 with counter
+ * (site, step_lo, step_hi, replica) and key (seed_lo, seed_hi), via
+ * u = (x + 1/2) 2^-32 and Box-Muller on (u0,u1), (u2,u3). */
+typedef struct {
+    double alpha;            /* Gilbert damping, >= 0 */
+    double dt_ps;            /* time step, > 0 */
+    double T_K;              /* temperature, >= 0 */
+    uint64_t seed;           /* Philox key */
+} sp_llg_params;
+
+/* Observables of one spin state.  per_term: Zeeman, anisotropy, exchange,
+ * DMI, dipole (meV).  max_torque = max_i |n_i x dH/dn_i| (meV); M = mean
+ * spin (1/N) sum_i n_i; max_norm_dev = max_i | |n_i| - 1 |.  All reduced in
+ * double precision. */
+typedef struct {
+    int64_t step;
+    double E;
+    double per_term[5];
+    double max_torque;
+    double M[3];
+    double max_norm_dev;
+} sp_observation;
+
+/* Create an engine on HIP device `device` computing in `precision`.
+ * hip_stream: a hipStream_t to order all work on, or NULL for an engine-owned
+ * stream.  *out receives the engine (NULL on failure). */
+int sp_create(sp_engine **out, int device, int precision, void *hip_stream);
+/* Free the engine and all device memory it owns.  NULL is ignored. */
+void sp_destroy(sp_engine *e);
+/* Message of the last failing call on this engine (never NULL). */
+const char *sp_last_error(const sp_engine *e);
+/* Version string of the library. */
+const char *sp_version(void);
+
+/* Geometry: Bravais lattice with basis (Sec. III.A; arbitrary Bravais vectors
+ * and basis cells).  bravais: rows a1, a2, a3 in units of the lattice
+ * constant; basis: n_basis cartesian positions in the same units;
+ * n_cells[k] >= 1; periodic[k] in {0, 1}; lattice_constant in Angstrom.
+ * Invalidates the Hamiltonian and spins. */
+int sp_set_geometry(sp_engine *e, const double bravais[9], int n_basis, const double *basis,
+                    const int n_cells[3], const int periodic[3], double lattice_constant);
+/* Hamiltonian; builds the neighbour-shell bond table.  Requires geometry.
+ * SP_E_ARG if a requested shell does not exist within 4 cells. */
+int sp_set_hamiltonian(sp_engine *e, const sp_hamiltonian *h);
+/* Number of sites N (0 before sp_set_geometry). */
+int64_t sp_num_sites(const sp_engine *e);
+/* Directed bonds of basis atom beta in the bond table (bonds whose J and D
+ * are both zero are omitted): out[10*k .. 10*k+9] =
+ * (beta_j, da, db, dc, shell, J, Dx, Dy, Dz, 0) as doubles for the first
+ * max_bonds bonds (out may be NULL).  Returns the bond count or a negative
+ * status. */
+int sp_get_bonds(sp_engine *e, int beta, double *out, int max_bonds);
+
+/* Spins: n_soa holds 3N doubles; every vector is normalised on input; a
+ * zero-length or non-finite vector gives SP_E_ARG.  Resets nothing else. */
+int sp_set_spins(sp_engine *e, const double *n_soa, int64_t N);
+int sp_get_spins(sp_engine *e, double *n_soa, int64_t N);
+/* Device-side variants in engine precision (no normalisation on set). */
+int sp_set_spins_dev(sp_engine *e, const void *n_soa_dev, int64_t N);
+int sp_get_spins_dev(sp_engine *e, void *n_soa_dev, int64_t N);
+
+/* Step counter (the Philox counter of the next step). */
+int sp_set_step(sp_engine *e, uint64_t step);
+uint64_t sp_get_step(const sp_engine *e);
+
+/* Gradient dH/dn_i in the embedding space (meV), all terms; B_eff = -g. */
+int sp_gradient(sp_engine *e, double *g_soa, int64_t N);
+int sp_gradient_dev(sp_engine *e, void *g_soa_dev, int64_t N);
+/* Energy by terms (double-precision reduction).  per_term may be NULL. */
+int sp_energy(sp_engine *e, double *E_total, double per_term[5]);
+/* All observables of the current state. */
+int sp_observe(sp_engine *e, sp_observation *obs);
+
+/* One Depondt step (Appendix B): predictor n^p = R(A(n)) n, corrector
+ * n(t+dt) = R((A(n) + A(n^p))/2) n with the same thermal normals in both.
+ * Advances the step counter by one. */
+int sp_llg_step(sp_engine *e, const sp_llg_params *p);
+/* n_steps Depondt steps.  If observe_every > 0 an observation is taken after
+ * every observe_every steps and written to obs[k] (obs must hold
+ * n_steps/observe_every entries; may be NULL to only check finiteness).
+ * When an observation finds a non-finite torque the remaining steps are
+ * skipped and SP_E_NONFINITE is returned (sp_last_error names the step). */
+int sp_run(sp_engine *e, const sp_llg_params *p, int64_t n_steps, int64_t observe_every,
+           sp_observation *obs);
+/* Wait for all work queued on the engine stream. */
+int sp_synchronize(sp_engine *e);
+
+/* Dipole-dipole gradient alone (direct sum over all pairs, open sample);
+ * g_soa receives 3N doubles.  Independent of ddi_mode. */
+int sp_dipole_gradient(sp_engine *e, double *g_soa, int64_t N);
+int sp_dipole_gradient_dev(sp_engine *e, const void *n_soa_dev, void *g_soa_dev, int64_t N);
+
+/* Philox4x32-10 + Box-Muller normals exactly as the LLG kernels draw them,
+ * for n_sites consecutive sites starting at site0 (SoA, 3*n_sites values in
+ * engine precision on the host as double).  For tests of the generator. */
+int sp_thermal_normals(sp_engine *e, uint64_t seed, uint64_t step, uint32_t replica,
+                       uint32_t site0, int64_t n_sites, double *eta_soa, uint32_t *raw4);
+
+/* Name of the kernel path sp_llg_step uses for the current state
+ * ("fused2d", "twopass", ...), for diagnostics. */
+const char *sp_step_path(const sp_engine *e);
+/* Force the step path ("twopass" always works; "fused2d" only where the
+ * lattice allows it, otherwise SP_E_UNSUPPORTED).  Reset by
+ * sp_set_hamiltonian.  For cross-path consistency checks. */
+int sp_set_step_path(sp_engine *e, const char *name);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

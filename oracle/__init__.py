@@ -117,6 +117,8 @@ def lib():
                               ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(Observation)]
         for name in ("ora_const_mu_B", "ora_const_k_B", "ora_const_gamma", "ora_const_C_dd"):
             getattr(L, name).restype = ctypes.c_double
+        L.ora_num_threads.restype = ctypes.c_int
+        L.ora_num_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -129,6 +131,10 @@ def constants() -> dict:
     L = lib()
     return {"mu_B": L.ora_const_mu_B(), "k_B": L.ora_const_k_B(),
             "gamma": L.ora_const_gamma(), "C_dd": L.ora_const_C_dd()}
+
+
+def num_threads() -> int:
+    return int(lib().ora_num_threads())
 
 
 def _geometry(geo) -> Geometry:

@@ -36,6 +36,13 @@
 #define GAMMA_RAD_PER_PS_T 0.176085963023
 #define PI 3.14159265358979323846
 
+#ifdef _OPENMP
+#include <omp.h>
+int ora_num_threads(void) { return omp_get_max_threads(); }
+#else
+int ora_num_threads(void) { return 1; }
+#endif
+
 double ora_const_mu_B(void) { return MU_B_J_PER_T / J_PER_MEV; }
 double ora_const_k_B(void) { return K_B_J_PER_K / J_PER_MEV; }
 double ora_const_gamma(void) { return GAMMA_RAD_PER_PS_T; }

@@ -121,6 +121,9 @@ void ora_observe(const ora_system *s, const double *n, int64_t step, ora_observa
 int64_t ora_run(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step0,
                 int64_t n_steps, int64_t observe_every, ora_observation *obs);
 
+/* OpenMP threads the oracle's parallel loops use. */
+int ora_num_threads(void);
+
 /* Physical constants used by the oracle. */
 double ora_const_mu_B(void);
 double ora_const_k_B(void);

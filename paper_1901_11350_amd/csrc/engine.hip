@@ -1,0 +1,959 @@
+// engine.hip -- host side of the MI355X atomistic-spin engine: state,
+// neighbour-shell bond tables, buffer management, kernel launches and the
+// C ABI declared in include/sp_engine.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sp_engine.h"
+#include "kernels_field.hpp"
+#include "kernels_reduce.hpp"
+#include "kernels_dipole.hpp"
+
+namespace {
+
+// CODATA 2018 (SI) in meV / Tesla / ps / Angstrom.
+constexpr double kJperMeV = 1.602176634e-22;
+constexpr double kMuB = 9.2740100783e-24 / kJperMeV;            // meV/T
+constexpr double kKB = 1.380649e-23 / kJperMeV;                 // meV/K
+constexpr double kGamma = 0.176085963023;                       // rad/(ps T)
+constexpr double kCdd = 1.00000000055e-7 * 9.2740100783e-24 * 9.2740100783e-24 / 1e-30 / kJperMeV;  // meV
+
+struct HostGeo {
+    double bravais[9];
+    int nb;
+    double basis[3 * SP_MAX_BASIS];
+    int n[3];
+    int per[3];
+    double a;
+};
+
+struct HostHam {
+    double mu[SP_MAX_BASIS];
+    double B[3];
+    double K[SP_MAX_BASIS];
+    double Kax[3 * SP_MAX_BASIS];
+    int n_exch, n_dmi;
+    double J[SP_MAX_SHELLS], D[SP_MAX_SHELLS];
+    int dmi_kind;
+    int ddi;
+};
+
+struct HostBond {
+    int bi, bj, d[3], shell;
+    double J, D[3];
+};
+
+const char* kVersion = "sp_engine 0.1 (gfx950)";
+
+}  // namespace
+
+struct sp_engine {
+    int device = 0;
+    int precision = SP_F32;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    bool has_geo = false, has_ham = false, has_spins = false;
+    HostGeo geo{};
+    HostHam ham{};
+    std::vector<HostBond> bonds;
+    std::vector<int> bstart;
+    int N = 0;
+    int R = 0;            // stencil reach in cells (max |d| over bonds)
+    bool planar = true;   // every bond has dc == 0
+    uint64_t step = 0;
+    const char* path = "none";
+    bool fused_ok = false;
+
+    size_t esz() const { return precision == SP_F64 ? 8 : 4; }
+
+    // device buffers (engine precision unless noted)
+    void* d_n = nullptr;
+    void* d_n2 = nullptr;
+    void* d_np = nullptr;
+    void* d_A = nullptr;
+    void* d_g = nullptr;
+    void* d_gdd = nullptr;
+    void* d_gddp = nullptr;
+    void* d_pos = nullptr;
+    void* d_ddpart = nullptr;
+    int dd_slices = 1;
+    int4* d_bond = nullptr;
+    int* d_bstart = nullptr;
+    void* d_J = nullptr;
+    void* d_D = nullptr;
+    double* d_partials = nullptr;     // observe stage-1 rows
+    int partial_rows = 0;
+    double* d_obs = nullptr;          // observations of a run, OBS_NVALS each
+    int64_t obs_cap = 0;
+    int* d_flag = nullptr;            // abort flag (non-finite torque)
+    long long* d_abort_step = nullptr;
+    double* h_pin = nullptr;          // pinned staging for small results
+};
+
+namespace {
+
+int fail(sp_engine* e, int code, const std::string& msg) {
+    if (e) e->err = msg;
+    return code;
+}
+
+#define HIPCHK(e, call)                                                                       \
+    do {                                                                                      \
+        hipError_t _s = (call);                                                               \
+        if (_s != hipSuccess)                                                                 \
+            return fail((e), SP_E_HIP, std::string(#call) + ": " + hipGetErrorString(_s));    \
+    } while (0)
+
+void dfree(void*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+template <typename P>
+int dalloc(sp_engine* e, P*& p, size_t bytes) {
+    if (p) {
+        (void)hipFree(p);
+        p = nullptr;
+    }
+    if (bytes == 0) return SP_OK;
+    void* q = nullptr;
+    hipError_t s = hipMalloc(&q, bytes);
+    if (s != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e, SP_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    p = static_cast<P*>(q);
+    return SP_OK;
+}
+
+void free_state_buffers(sp_engine* e) {
+    dfree(e->d_n); dfree(e->d_n2); dfree(e->d_np); dfree(e->d_A); dfree(e->d_g);
+    dfree(e->d_gdd); dfree(e->d_gddp); dfree(e->d_pos); dfree(e->d_ddpart);
+    void* p = e->d_bond; dfree(p); e->d_bond = nullptr;
+    p = e->d_bstart; dfree(p); e->d_bstart = nullptr;
+    dfree(e->d_J); dfree(e->d_D);
+}
+
+// ------------------------------------------------------------ bond table
+// Neighbour shells per basis atom: candidates within +-4 cells (axes with a
+// single open cell carry no translation) sorted by distance; distances within
+// 1e-6 lattice constants form one shell.  Bonds of the first
+// max(n_exch, n_dmi) shells are kept in both directions.
+int build_bonds(sp_engine* e, const HostGeo& g, const HostHam& h, std::vector<HostBond>& out,
+                std::vector<int>& start) {
+    struct Cand {
+        int bj, d[3];
+        double dist, r[3];
+    };
+    out.clear();
+    start.assign(g.nb + 1, 0);
+    const int want = std::max(h.n_exch, h.n_dmi);
+    int ext[3];
+    for (int k = 0; k < 3; ++k) ext[k] = (g.n[k] > 1 || g.per[k]) ? 4 : 0;
+    for (int bi = 0; bi < g.nb; ++bi) {
+        start[bi] = (int)out.size();
+        if (want == 0) continue;
+        std::vector<Cand> cs;
+        for (int bj = 0; bj < g.nb; ++bj)
+            for (int x = -ext[0]; x <= ext[0]; ++x)
+                for (int y = -ext[1]; y <= ext[1]; ++y)
+                    for (int z = -ext[2]; z <= ext[2]; ++z) {
+                        Cand c{bj, {x, y, z}, 0.0, {0, 0, 0}};
+                        for (int k = 0; k < 3; ++k)
+                            c.r[k] = x * g.bravais[k] + y * g.bravais[3 + k] + z * g.bravais[6 + k] +
+                                     g.basis[3 * bj + k] - g.basis[3 * bi + k];
+                        c.dist = std::sqrt(c.r[0] * c.r[0] + c.r[1] * c.r[1] + c.r[2] * c.r[2]);
+                        if (c.dist >= 1e-6) cs.push_back(c);
+                    }
+        std::stable_sort(cs.begin(), cs.end(), [](const Cand& a, const Cand& b) { return a.dist < b.dist; });
+        int shell = -1;
+        double shell_d = 0.0;
+        for (const Cand& c : cs) {
+            if (shell < 0 || c.dist > shell_d + 1e-6) {
+                ++shell;
+                shell_d = c.dist;
+            }
+            if (shell >= want) break;
+            HostBond b{};
+            b.bi = bi;
+            b.bj = c.bj;
+            for (int k = 0; k < 3; ++k) b.d[k] = c.d[k];
+            b.shell = shell;
+            b.J = shell < h.n_exch ? h.J[shell] : 0.0;
+            const double Dm = shell < h.n_dmi ? h.D[shell] : 0.0;
+            const double ux = c.r[0] / c.dist, uy = c.r[1] / c.dist, uz = c.r[2] / c.dist;
+            if (h.dmi_kind == SP_DMI_BULK) {
+                b.D[0] = Dm * ux; b.D[1] = Dm * uy; b.D[2] = Dm * uz;
+            } else {  // z x r_hat
+                b.D[0] = -Dm * uy; b.D[1] = Dm * ux; b.D[2] = 0.0;
+            }
+            if (b.J == 0.0 && b.D[0] == 0.0 && b.D[1] == 0.0 && b.D[2] == 0.0) continue;
+            out.push_back(b);
+        }
+        if (shell + 1 < want)
+            return fail(e, SP_E_ARG, "basis atom " + std::to_string(bi) + " has only " + std::to_string(shell + 1) +
+                                         " neighbour shells within 4 cells; " + std::to_string(want) + " requested");
+    }
+    start[g.nb] = (int)out.size();
+    return SP_OK;
+}
+
+// ------------------------------------------------------- kernel arguments
+template <typename T>
+sp::Phys<T> make_phys(const sp_engine* e, const sp_llg_params* p) {
+    sp::Phys<T> P{};
+    P.nb = e->geo.nb;
+    for (int b = 0; b < e->geo.nb; ++b) {
+        const double mm = e->ham.mu[b] * kMuB;
+        P.mumuB[b] = (T)mm;
+        for (int k = 0; k < 3; ++k) {
+            P.gZ[b][k] = (T)(-mm * e->ham.B[k]);
+            P.Kax[b][k] = (T)e->ham.Kax[3 * b + k];
+        }
+        P.K2[b] = (T)(2.0 * e->ham.K[b]);
+        P.sigma[b] = T(0);
+        if (p && p->T_K > 0.0)
+            P.sigma[b] = (T)std::sqrt(2.0 * p->alpha * kKB * p->T_K / (kGamma * mm * p->dt_ps));
+    }
+    return P;
+}
+
+template <typename T>
+sp::LLGArgs<T> make_llg(const sp_llg_params* p, uint64_t step, uint32_t replica) {
+    sp::LLGArgs<T> A{};
+    A.gp = (T)(kGamma / (1.0 + p->alpha * p->alpha));
+    A.alpha = (T)p->alpha;
+    A.dt = (T)p->dt_ps;
+    A.thermal = p->T_K > 0.0 ? 1 : 0;
+    A.key.seed_lo = (uint32_t)p->seed;
+    A.key.seed_hi = (uint32_t)(p->seed >> 32);
+    A.key.step_lo = (uint32_t)step;
+    A.key.step_hi = (uint32_t)(step >> 32);
+    A.key.replica = replica;
+    return A;
+}
+
+sp::Lattice make_lattice(const sp_engine* e) {
+    sp::Lattice L{};
+    for (int k = 0; k < 3; ++k) {
+        L.n[k] = e->geo.n[k];
+        L.per[k] = e->geo.per[k];
+    }
+    L.nb = e->geo.nb;
+    L.N = e->N;
+    L.bond = e->d_bond;
+    L.bstart = e->d_bstart;
+    return L;
+}
+
+template <typename T>
+sp::BondCoef<T> make_coef(const sp_engine* e) {
+    return sp::BondCoef<T>{static_cast<const T*>(e->d_J), static_cast<const T*>(e->d_D)};
+}
+
+inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+// ----------------------------------------------------------------- dipole
+template <typename T>
+int launch_dipole(sp_engine* e, const void* n, void* gdd) {
+    sp::DipoleArgs<T> a{};
+    a.N = e->N;
+    a.cells = e->geo.n[0] * e->geo.n[1] * e->geo.n[2];
+    a.slices = e->dd_slices;
+    const int tiles = (e->N + 255) / 256;
+    a.slice_len = ((tiles + a.slices - 1) / a.slices) * 256;
+    for (int b = 0; b < e->geo.nb; ++b) a.mu[b] = (T)e->ham.mu[b];
+    constexpr int IPT = 2;
+    dim3 grid((unsigned)((e->N + 256 * IPT - 1) / (256 * IPT)), (unsigned)a.slices);
+    hipLaunchKernelGGL((sp::k_dipole_partial<T, IPT>), grid, dim3(256), 0, e->stream, a,
+                       static_cast<const T*>(e->d_pos), static_cast<const T*>(n), static_cast<T*>(e->d_ddpart));
+    hipLaunchKernelGGL((sp::k_dipole_finish<T>), dim3(blocks_for(3LL * e->N)), dim3(256), 0, e->stream, a,
+                       (T)kCdd, static_cast<const T*>(e->d_ddpart), static_cast<T*>(gdd));
+    HIPCHK(e, hipGetLastError());
+    return SP_OK;
+}
+
+// --------------------------------------------------------------- observe
+template <typename T>
+int launch_observe(sp_engine* e, const void* n, double* out, long long step, bool with_flag) {
+    const void* gdd = nullptr;
+    if (e->ham.ddi) {
+        int rc = launch_dipole<T>(e, n, e->d_gdd);
+        if (rc) return rc;
+        gdd = e->d_gdd;
+    }
+    const sp::Phys<T> P = make_phys<T>(e, nullptr);
+    hipLaunchKernelGGL((sp::k_observe_partial<T>), dim3(e->partial_rows), dim3(256), 0, e->stream,
+                       make_lattice(e), make_coef<T>(e), P, static_cast<const T*>(n), static_cast<const T*>(gdd),
+                       e->d_partials);
+    hipLaunchKernelGGL(sp::k_observe_final, dim3(1), dim3(256), 0, e->stream, e->d_partials, e->partial_rows, out,
+                       with_flag ? e->d_flag : nullptr, e->d_abort_step, step);
+    HIPCHK(e, hipGetLastError());
+    return SP_OK;
+}
+
+void obs_from(const double* v, int64_t step, int N, sp_observation* o) {
+    o->step = step;
+    o->per_term[0] = v[sp::OBS_EZ];
+    o->per_term[1] = v[sp::OBS_EK];
+    o->per_term[2] = v[sp::OBS_EJ];
+    o->per_term[3] = v[sp::OBS_ED];
+    o->per_term[4] = v[sp::OBS_EDD];
+    o->E = o->per_term[0] + o->per_term[1] + o->per_term[2] + o->per_term[3] + o->per_term[4];
+    o->max_torque = v[sp::OBS_NONFINITE] > 0.0 ? NAN : v[sp::OBS_TMAX];
+    o->M[0] = v[sp::OBS_MX] / N;
+    o->M[1] = v[sp::OBS_MY] / N;
+    o->M[2] = v[sp::OBS_MZ] / N;
+    o->max_norm_dev = v[sp::OBS_NDEV];
+}
+
+// ------------------------------------------------------------ LLG step
+template <typename T>
+sp::Stencil2D<T> make_stencil2d(const sp_engine* e) {
+    sp::Stencil2D<T> S{};
+    S.nbond = (int)e->bonds.size();
+    for (int q = 0; q < S.nbond; ++q) {
+        const HostBond& b = e->bonds[q];
+        S.da[q] = b.d[0];
+        S.db[q] = b.d[1];
+        S.J[q] = (T)b.J;
+        for (int k = 0; k < 3; ++k) S.D[q][k] = (T)b.D[k];
+    }
+    return S;
+}
+
+template <typename T>
+sp::Site2D<T> make_site2d(const sp_engine* e, const sp_llg_params* p) {
+    const sp::Phys<T> P = make_phys<T>(e, p);
+    sp::Site2D<T> Q{};
+    Q.na = e->geo.n[0];
+    Q.nb = e->geo.n[1];
+    Q.per_a = e->geo.per[0];
+    Q.per_b = e->geo.per[1];
+    Q.mumuB = P.mumuB[0];
+    Q.inv_mumuB = (T)(1.0 / (e->ham.mu[0] * kMuB));
+    for (int k = 0; k < 3; ++k) {
+        Q.gZ[k] = P.gZ[0][k];
+        Q.Kax[k] = P.Kax[0][k];
+    }
+    Q.K2 = P.K2[0];
+    Q.sigma = P.sigma[0];
+    return Q;
+}
+
+template <typename T, int TX, int TY, int R>
+void launch_fused2d(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    dim3 grid((unsigned)((e->geo.n[0] + TX - 1) / TX), (unsigned)((e->geo.n[1] + TY - 1) / TY));
+    hipLaunchKernelGGL((sp::k_depondt_fused2d<T, TX, TY, R>), grid, dim3(256), 0, e->stream, make_stencil2d<T>(e),
+                       make_site2d<T>(e, p), make_llg<T>(p, step, 0), e->d_flag, static_cast<const T*>(nin),
+                       static_cast<T*>(nout));
+}
+
+template <typename T>
+int launch_step(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    if (std::strcmp(e->path, "fused2d") == 0) {
+        if (e->R <= 1)
+            launch_fused2d<T, 32, 16, 1>(e, p, step, nin, nout);
+        else
+            launch_fused2d<T, 32, 16, 2>(e, p, step, nin, nout);
+        HIPCHK(e, hipGetLastError());
+        return SP_OK;
+    }
+    const sp::Lattice L = make_lattice(e);
+    const sp::BondCoef<T> C = make_coef<T>(e);
+    const sp::Phys<T> P = make_phys<T>(e, p);
+    const sp::LLGArgs<T> A = make_llg<T>(p, step, 0);
+    const void* gdd = nullptr;
+    const void* gddp = nullptr;
+    if (e->ham.ddi) {
+        int rc = launch_dipole<T>(e, nin, e->d_gdd);
+        if (rc) return rc;
+        gdd = e->d_gdd;
+    }
+    hipLaunchKernelGGL((sp::k_predict<T>), dim3(blocks_for(e->N)), dim3(256), 0, e->stream, L, C, P, A, e->d_flag,
+                       static_cast<const T*>(nin), static_cast<const T*>(gdd), static_cast<T*>(e->d_np),
+                       static_cast<T*>(e->d_A));
+    if (e->ham.ddi) {
+        int rc = launch_dipole<T>(e, e->d_np, e->d_gddp);
+        if (rc) return rc;
+        gddp = e->d_gddp;
+    }
+    hipLaunchKernelGGL((sp::k_correct<T>), dim3(blocks_for(e->N)), dim3(256), 0, e->stream, L, C, P, A, e->d_flag,
+                       static_cast<const T*>(nin), static_cast<const T*>(e->d_np), static_cast<const T*>(gddp),
+                       static_cast<const T*>(e->d_A), static_cast<T*>(nout));
+    HIPCHK(e, hipGetLastError());
+    return SP_OK;
+}
+
+int check_ready(sp_engine* e, bool need_spins) {
+    if (!e) return SP_E_ARG;
+    if (!e->has_geo) return fail(e, SP_E_ORDER, "sp_set_geometry has not been called");
+    if (!e->has_ham) return fail(e, SP_E_ORDER, "sp_set_hamiltonian has not been called");
+    if (need_spins && !e->has_spins) return fail(e, SP_E_ORDER, "sp_set_spins has not been called");
+    return SP_OK;
+}
+
+int check_llg(sp_engine* e, const sp_llg_params* p) {
+    if (!p) return fail(e, SP_E_ARG, "llg params are NULL");
+    if (!(p->alpha >= 0.0) || !std::isfinite(p->alpha)) return fail(e, SP_E_ARG, "alpha must be finite and >= 0");
+    if (!(p->dt_ps > 0.0) || !std::isfinite(p->dt_ps)) return fail(e, SP_E_ARG, "dt must be finite and > 0");
+    if (!(p->T_K >= 0.0) || !std::isfinite(p->T_K)) return fail(e, SP_E_ARG, "T must be finite and >= 0");
+    return SP_OK;
+}
+
+template <typename T>
+int copy_in_soa(sp_engine* e, void* dst, const double* src, int64_t n3) {
+    if constexpr (sizeof(T) == 8) {
+        HIPCHK(e, hipMemcpyAsync(dst, src, n3 * sizeof(double), hipMemcpyHostToDevice, e->stream));
+    } else {
+        std::vector<float> tmp((size_t)n3);
+        for (int64_t k = 0; k < n3; ++k) tmp[k] = (float)src[k];
+        HIPCHK(e, hipMemcpyAsync(dst, tmp.data(), n3 * sizeof(float), hipMemcpyHostToDevice, e->stream));
+        HIPCHK(e, hipStreamSynchronize(e->stream));
+    }
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    return SP_OK;
+}
+
+template <typename T>
+int copy_out_soa(sp_engine* e, double* dst, const void* src, int64_t n3) {
+    if constexpr (sizeof(T) == 8) {
+        HIPCHK(e, hipMemcpyAsync(dst, src, n3 * sizeof(double), hipMemcpyDeviceToHost, e->stream));
+        HIPCHK(e, hipStreamSynchronize(e->stream));
+    } else {
+        std::vector<float> tmp((size_t)n3);
+        HIPCHK(e, hipMemcpyAsync(tmp.data(), src, n3 * sizeof(float), hipMemcpyDeviceToHost, e->stream));
+        HIPCHK(e, hipStreamSynchronize(e->stream));
+        for (int64_t k = 0; k < n3; ++k) dst[k] = (double)tmp[k];
+    }
+    return SP_OK;
+}
+
+template <typename T>
+int upload_ham(sp_engine* e) {
+    const size_t nbond = e->bonds.size();
+    std::vector<int4> bd(std::max<size_t>(nbond, 1));
+    std::vector<T> J(std::max<size_t>(nbond, 1)), D(3 * std::max<size_t>(nbond, 1));
+    for (size_t q = 0; q < nbond; ++q) {
+        const HostBond& b = e->bonds[q];
+        bd[q] = make_int4(b.bj, b.d[0], b.d[1], b.d[2]);
+        J[q] = (T)b.J;
+        for (int k = 0; k < 3; ++k) D[3 * q + k] = (T)b.D[k];
+    }
+    int rc;
+    if ((rc = dalloc(e, e->d_bond, bd.size() * sizeof(int4)))) return rc;
+    if ((rc = dalloc(e, e->d_bstart, e->bstart.size() * sizeof(int)))) return rc;
+    if ((rc = dalloc(e, e->d_J, J.size() * sizeof(T)))) return rc;
+    if ((rc = dalloc(e, e->d_D, D.size() * sizeof(T)))) return rc;
+    HIPCHK(e, hipMemcpy(e->d_bond, bd.data(), bd.size() * sizeof(int4), hipMemcpyHostToDevice));
+    HIPCHK(e, hipMemcpy(e->d_bstart, e->bstart.data(), e->bstart.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(e, hipMemcpy(e->d_J, J.data(), J.size() * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(e, hipMemcpy(e->d_D, D.data(), D.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (e->ham.ddi) {
+        // site positions in Angstrom
+        std::vector<T> pos(3 * (size_t)e->N);
+        const HostGeo& g = e->geo;
+        for (int i = 0; i < e->N; ++i) {
+            const int a = i % g.n[0];
+            const int b = (i / g.n[0]) % g.n[1];
+            const int c = (i / (g.n[0] * g.n[1])) % g.n[2];
+            const int beta = i / (g.n[0] * g.n[1] * g.n[2]);
+            for (int k = 0; k < 3; ++k)
+                pos[(size_t)k * e->N + i] =
+                    (T)((a * g.bravais[k] + b * g.bravais[3 + k] + c * g.bravais[6 + k] + g.basis[3 * beta + k]) * g.a);
+        }
+        if ((rc = dalloc(e, e->d_pos, pos.size() * sizeof(T)))) return rc;
+        HIPCHK(e, hipMemcpy(e->d_pos, pos.data(), pos.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+    return SP_OK;
+}
+
+template <typename T>
+int gradient_dev(sp_engine* e, const void* n, void* g) {
+    const void* gdd = nullptr;
+    if (e->ham.ddi) {
+        int rc = launch_dipole<T>(e, n, e->d_gdd);
+        if (rc) return rc;
+        gdd = e->d_gdd;
+    }
+    hipLaunchKernelGGL((sp::k_gradient<T>), dim3(blocks_for(e->N)), dim3(256), 0, e->stream, make_lattice(e),
+                       make_coef<T>(e), make_phys<T>(e, nullptr), static_cast<const T*>(n),
+                       static_cast<const T*>(gdd), static_cast<T*>(g));
+    HIPCHK(e, hipGetLastError());
+    return SP_OK;
+}
+
+template <typename T>
+int normals_dev(sp_engine* e, uint64_t seed, uint64_t step, uint32_t replica, uint32_t site0, int64_t n,
+                double* eta, uint32_t* raw) {
+    void* d_eta = nullptr;
+    uint32_t* d_raw = nullptr;
+    int rc;
+    if ((rc = dalloc(e, d_eta, 3 * (size_t)n * sizeof(T)))) return rc;
+    if ((rc = dalloc(e, d_raw, 4 * (size_t)n * sizeof(uint32_t)))) { dfree(d_eta); return rc; }
+    sp::ThermalKey k{(uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)step, (uint32_t)(step >> 32), replica};
+    hipLaunchKernelGGL((sp::k_normals<T>), dim3(blocks_for(n)), dim3(256), 0, e->stream, k, site0, (int)n,
+                       static_cast<T*>(d_eta), d_raw);
+    rc = copy_out_soa<T>(e, eta, d_eta, 3 * n);
+    if (rc == SP_OK && raw) {
+        hipError_t s = hipMemcpy(raw, d_raw, 4 * (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (s != hipSuccess) rc = fail(e, SP_E_HIP, hipGetErrorString(s));
+    }
+    dfree(d_eta);
+    void* r = d_raw;
+    dfree(r);
+    return rc;
+}
+
+template <typename T>
+int run_impl(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t observe_every, sp_observation* obs) {
+    const int64_t n_obs = observe_every > 0 ? n_steps / observe_every : 0;
+    int rc;
+    if (n_obs > e->obs_cap) {
+        if ((rc = dalloc(e, e->d_obs, (size_t)n_obs * sp::OBS_NVALS * sizeof(double)))) return rc;
+        e->obs_cap = n_obs;
+    }
+    HIPCHK(e, hipMemsetAsync(e->d_flag, 0, sizeof(int), e->stream));
+    HIPCHK(e, hipMemsetAsync(e->d_abort_step, 0, sizeof(long long), e->stream));
+    int64_t k = 0;
+    for (int64_t t = 0; t < n_steps; ++t) {
+        rc = launch_step<T>(e, p, e->step, e->d_n, e->d_n2);
+        if (rc) return rc;
+        std::swap(e->d_n, e->d_n2);
+        ++e->step;
+        if (observe_every > 0 && (t + 1) % observe_every == 0) {
+            rc = launch_observe<T>(e, e->d_n, e->d_obs + k * sp::OBS_NVALS, (long long)e->step, true);
+            if (rc) return rc;
+            ++k;
+        }
+    }
+    int flag = 0;
+    long long astep = 0;
+    HIPCHK(e, hipMemcpyAsync(&flag, e->d_flag, sizeof(int), hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipMemcpyAsync(&astep, e->d_abort_step, sizeof(long long), hipMemcpyDeviceToHost, e->stream));
+    if (n_obs > 0 && obs) {
+        std::vector<double> h((size_t)n_obs * sp::OBS_NVALS);
+        HIPCHK(e, hipMemcpyAsync(h.data(), e->d_obs, h.size() * sizeof(double), hipMemcpyDeviceToHost, e->stream));
+        HIPCHK(e, hipStreamSynchronize(e->stream));
+        const int64_t step0 = (int64_t)e->step - n_steps;
+        for (int64_t q = 0; q < n_obs; ++q)
+            obs_from(&h[(size_t)q * sp::OBS_NVALS], step0 + (q + 1) * observe_every, e->N, &obs[q]);
+    }
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    if (flag)
+        return fail(e, SP_E_NONFINITE, "non-finite torque observed after step " + std::to_string(astep) +
+                                           "; later steps were skipped");
+    return SP_OK;
+}
+
+}  // namespace
+
+#define DISPATCH(e, fn, ...) ((e)->precision == SP_F64 ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__))
+
+extern "C" {
+
+const char* sp_version(void) { return kVersion; }
+
+int sp_create(sp_engine** out, int device, int precision, void* hip_stream) {
+    if (!out) return SP_E_ARG;
+    *out = nullptr;
+    if (precision != SP_F32 && precision != SP_F64) return SP_E_ARG;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SP_E_HIP;
+    sp_engine* e = new (std::nothrow) sp_engine();
+    if (!e) return SP_E_NOMEM;
+    e->device = device;
+    e->precision = precision;
+    if (hipSetDevice(device) != hipSuccess) { delete e; return SP_E_HIP; }
+    if (hip_stream) {
+        e->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess) { delete e; return SP_E_HIP; }
+        e->own_stream = true;
+    }
+    if (dalloc(e, e->d_flag, sizeof(int)) || dalloc(e, e->d_abort_step, sizeof(long long)) ||
+        hipHostMalloc((void**)&e->h_pin, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        sp_destroy(e);
+        return SP_E_NOMEM;
+    }
+    (void)hipMemset(e->d_flag, 0, sizeof(int));
+    *out = e;
+    return SP_OK;
+}
+
+void sp_destroy(sp_engine* e) {
+    if (!e) return;
+    (void)hipSetDevice(e->device);
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    free_state_buffers(e);
+    dfree(*reinterpret_cast<void**>(&e->d_partials));
+    dfree(*reinterpret_cast<void**>(&e->d_obs));
+    dfree(*reinterpret_cast<void**>(&e->d_flag));
+    dfree(*reinterpret_cast<void**>(&e->d_abort_step));
+    if (e->h_pin) (void)hipHostFree(e->h_pin);
+    if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+}
+
+const char* sp_last_error(const sp_engine* e) { return e ? e->err.c_str() : "null engine"; }
+
+int sp_set_geometry(sp_engine* e, const double bravais[9], int n_basis, const double* basis, const int n_cells[3],
+                    const int periodic[3], double lattice_constant) {
+    if (!e) return SP_E_ARG;
+    if (!bravais || !basis || !n_cells || !periodic) return fail(e, SP_E_ARG, "null geometry argument");
+    if (n_basis < 1 || n_basis > SP_MAX_BASIS) return fail(e, SP_E_ARG, "n_basis must be in 1..8");
+    if (!(lattice_constant > 0.0) || !std::isfinite(lattice_constant))
+        return fail(e, SP_E_ARG, "lattice constant must be finite and > 0");
+    long long N = (long long)n_basis;
+    for (int k = 0; k < 3; ++k) {
+        if (n_cells[k] < 1) return fail(e, SP_E_ARG, "n_cells must be >= 1");
+        if (periodic[k] != 0 && periodic[k] != 1) return fail(e, SP_E_ARG, "periodic flags must be 0 or 1");
+        N *= n_cells[k];
+    }
+    if (N > (1LL << 29)) return fail(e, SP_E_UNSUPPORTED, "more than 2^29 sites");
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(bravais[k])) return fail(e, SP_E_ARG, "non-finite Bravais vector");
+    double det = bravais[0] * (bravais[4] * bravais[8] - bravais[5] * bravais[7]) -
+                 bravais[1] * (bravais[3] * bravais[8] - bravais[5] * bravais[6]) +
+                 bravais[2] * (bravais[3] * bravais[7] - bravais[4] * bravais[6]);
+    if (!(std::fabs(det) > 1e-12)) return fail(e, SP_E_ARG, "Bravais vectors are linearly dependent");
+    HostGeo g{};
+    std::memcpy(g.bravais, bravais, 9 * sizeof(double));
+    g.nb = n_basis;
+    for (int k = 0; k < 3 * n_basis; ++k) {
+        if (!std::isfinite(basis[k])) return fail(e, SP_E_ARG, "non-finite basis position");
+        g.basis[k] = basis[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        g.n[k] = n_cells[k];
+        g.per[k] = periodic[k];
+    }
+    g.a = lattice_constant;
+    (void)hipSetDevice(e->device);
+    free_state_buffers(e);
+    e->geo = g;
+    e->N = (int)N;
+    e->has_geo = true;
+    e->has_ham = false;
+    e->has_spins = false;
+    e->path = "none";
+    e->step = 0;
+    return SP_OK;
+}
+
+int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
+    if (!e) return SP_E_ARG;
+    if (!e->has_geo) return fail(e, SP_E_ORDER, "sp_set_geometry has not been called");
+    if (!h) return fail(e, SP_E_ARG, "null Hamiltonian");
+    if (h->n_basis != e->geo.nb) return fail(e, SP_E_ARG, "n_basis differs from the geometry");
+    if (!h->mu) return fail(e, SP_E_ARG, "mu is NULL");
+    if (h->n_exch_shells < 0 || h->n_exch_shells > SP_MAX_SHELLS || h->n_dmi_shells < 0 ||
+        h->n_dmi_shells > SP_MAX_SHELLS)
+        return fail(e, SP_E_ARG, "shell counts must be in 0..8");
+    if ((h->n_exch_shells > 0 && !h->J) || (h->n_dmi_shells > 0 && !h->D))
+        return fail(e, SP_E_ARG, "J or D array is NULL");
+    if (h->n_dmi_shells > 0 && h->dmi_kind != SP_DMI_BULK && h->dmi_kind != SP_DMI_INTERFACIAL)
+        return fail(e, SP_E_ARG, "dmi_kind must be SP_DMI_BULK or SP_DMI_INTERFACIAL");
+    if (h->ddi_mode != SP_DDI_OFF && h->ddi_mode != SP_DDI_DIRECT)
+        return fail(e, SP_E_UNSUPPORTED, "ddi_mode must be SP_DDI_OFF or SP_DDI_DIRECT");
+    HostHam H{};
+    for (int b = 0; b < e->geo.nb; ++b) {
+        if (!(h->mu[b] > 0.0) || !std::isfinite(h->mu[b])) return fail(e, SP_E_ARG, "mu must be finite and > 0");
+        H.mu[b] = h->mu[b];
+        H.K[b] = h->K ? h->K[b] : 0.0;
+        if (!std::isfinite(H.K[b])) return fail(e, SP_E_ARG, "non-finite K");
+        double ax[3] = {0.0, 0.0, 1.0};
+        if (h->K_axis) {
+            for (int k = 0; k < 3; ++k) ax[k] = h->K_axis[3 * b + k];
+        } else if (h->K && H.K[b] != 0.0) {
+            return fail(e, SP_E_ARG, "K_axis is NULL but K is non-zero");
+        }
+        const double nrm = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) return fail(e, SP_E_ARG, "anisotropy axis has zero length");
+        for (int k = 0; k < 3; ++k) H.Kax[3 * b + k] = ax[k] / nrm;
+    }
+    for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(h->B[k])) return fail(e, SP_E_ARG, "non-finite B");
+        H.B[k] = h->B[k];
+    }
+    H.n_exch = h->n_exch_shells;
+    H.n_dmi = h->n_dmi_shells;
+    for (int s = 0; s < H.n_exch; ++s) H.J[s] = h->J[s];
+    for (int s = 0; s < H.n_dmi; ++s) H.D[s] = h->D[s];
+    H.dmi_kind = h->n_dmi_shells > 0 ? h->dmi_kind : SP_DMI_INTERFACIAL;
+    H.ddi = h->ddi_mode == SP_DDI_DIRECT ? 1 : 0;
+
+    std::vector<HostBond> bonds;
+    std::vector<int> bstart;
+    int rc = build_bonds(e, e->geo, H, bonds, bstart);
+    if (rc) return rc;
+
+    (void)hipSetDevice(e->device);
+    // keep spins across a Hamiltonian change only if already uploaded
+    const bool had_spins = e->has_spins;
+    std::vector<double> saved;
+    if (had_spins) {
+        saved.resize(3 * (size_t)e->N);
+        if ((rc = DISPATCH(e, copy_out_soa, e, saved.data(), e->d_n, 3LL * e->N))) return rc;
+    }
+    free_state_buffers(e);
+    e->ham = H;
+    e->bonds = bonds;
+    e->bstart = bstart;
+    e->R = 0;
+    e->planar = true;
+    for (const HostBond& b : bonds) {
+        e->R = std::max(e->R, std::max(std::abs(b.d[0]), std::abs(b.d[1])));
+        if (b.d[2] != 0) e->planar = false;
+    }
+    const size_t vbytes = 3 * (size_t)e->N * e->esz();
+    if ((rc = dalloc(e, e->d_n, vbytes)) || (rc = dalloc(e, e->d_n2, vbytes)) || (rc = dalloc(e, e->d_np, vbytes)) ||
+        (rc = dalloc(e, e->d_A, vbytes)) || (rc = dalloc(e, e->d_g, vbytes))) {
+        free_state_buffers(e);
+        e->has_ham = false;
+        e->has_spins = false;
+        return rc;
+    }
+    if (H.ddi) {
+        const int tiles = (e->N + 255) / 256;
+        e->dd_slices = std::max(1, std::min(16, (2048 * 256 * 2) / std::max(e->N, 1)));
+        e->dd_slices = std::min(e->dd_slices, tiles);
+        if ((rc = dalloc(e, e->d_gdd, vbytes)) || (rc = dalloc(e, e->d_gddp, vbytes)) ||
+            (rc = dalloc(e, e->d_ddpart, vbytes * e->dd_slices))) {
+            free_state_buffers(e);
+            e->has_ham = false;
+            e->has_spins = false;
+            return rc;
+        }
+    }
+    if ((rc = DISPATCH(e, upload_ham, e))) {
+        free_state_buffers(e);
+        e->has_ham = false;
+        e->has_spins = false;
+        return rc;
+    }
+    const int rows = (int)std::min<long long>(1024, (e->N + 255) / 256);
+    if (rows > e->partial_rows) {
+        if ((rc = dalloc(e, e->d_partials, (size_t)rows * sp::OBS_NVALS * sizeof(double)))) return rc;
+    }
+    e->partial_rows = rows;
+    e->has_ham = true;
+
+    // step path
+    const HostGeo& g = e->geo;
+    bool fused = g.nb == 1 && g.n[2] == 1 && e->planar && !H.ddi && e->R <= 2 &&
+                 (int)bonds.size() <= sp::kMaxStencil;
+    if (g.per[0] && g.n[0] <= 2 * e->R) fused = false;
+    if (g.per[1] && g.n[1] <= 2 * e->R) fused = false;
+    e->fused_ok = fused;
+    e->path = fused ? "fused2d" : "twopass";
+
+    if (had_spins) {
+        if ((rc = DISPATCH(e, copy_in_soa, e, e->d_n, saved.data(), 3LL * e->N))) return rc;
+        e->has_spins = true;
+    }
+    return SP_OK;
+}
+
+int64_t sp_num_sites(const sp_engine* e) { return e && e->has_geo ? e->N : 0; }
+
+int sp_get_bonds(sp_engine* e, int beta, double* out, int max_bonds) {
+    if (!e) return SP_E_ARG;
+    int rc = check_ready(e, false);
+    if (rc) return rc;
+    if (beta < 0 || beta >= e->geo.nb) return fail(e, SP_E_ARG, "basis index out of range");
+    int k = 0;
+    for (const HostBond& b : e->bonds) {
+        if (b.bi != beta) continue;
+        if (out && k < max_bonds) {
+            double* o = out + 10 * k;
+            o[0] = b.bj; o[1] = b.d[0]; o[2] = b.d[1]; o[3] = b.d[2]; o[4] = b.shell;
+            o[5] = b.J; o[6] = b.D[0]; o[7] = b.D[1]; o[8] = b.D[2]; o[9] = 0.0;
+        }
+        ++k;
+    }
+    return k;
+}
+
+int sp_set_spins(sp_engine* e, const double* n_soa, int64_t N) {
+    int rc = check_ready(e, false);
+    if (rc) return rc;
+    if (!n_soa || N != e->N) return fail(e, SP_E_ARG, "spin array size differs from the number of sites");
+    std::vector<double> v(3 * (size_t)N);
+    for (int64_t i = 0; i < N; ++i) {
+        const double x = n_soa[i], y = n_soa[N + i], z = n_soa[2 * N + i];
+        const double r = std::sqrt(x * x + y * y + z * z);
+        if (!(r > 0.0) || !std::isfinite(r))
+            return fail(e, SP_E_ARG, "spin " + std::to_string(i) + " has zero or non-finite length");
+        v[i] = x / r;
+        v[N + i] = y / r;
+        v[2 * N + i] = z / r;
+    }
+    (void)hipSetDevice(e->device);
+    if ((rc = DISPATCH(e, copy_in_soa, e, e->d_n, v.data(), 3 * N))) return rc;
+    e->has_spins = true;
+    return SP_OK;
+}
+
+int sp_get_spins(sp_engine* e, double* n_soa, int64_t N) {
+    int rc = check_ready(e, true);
+    if (rc) return rc;
+    if (!n_soa || N != e->N) return fail(e, SP_E_ARG, "spin array size differs from the number of sites");
+    (void)hipSetDevice(e->device);
+    return DISPATCH(e, copy_out_soa, e, n_soa, e->d_n, 3 * N);
+}
+
+int sp_set_spins_dev(sp_engine* e, const void* n_soa_dev, int64_t N) {
+    int rc = check_ready(e, false);
+    if (rc) return rc;
+    if (!n_soa_dev || N != e->N) return fail(e, SP_E_ARG, "spin array size differs from the number of sites");
+    (void)hipSetDevice(e->device);
+    HIPCHK(e, hipMemcpyAsync(e->d_n, n_soa_dev, 3 * (size_t)N * e->esz(), hipMemcpyDeviceToDevice, e->stream));
+    e->has_spins = true;
+    return SP_OK;
+}
+
+int sp_get_spins_dev(sp_engine* e, void* n_soa_dev, int64_t N) {
+    int rc = check_ready(e, true);
+    if (rc) return rc;
+    if (!n_soa_dev || N != e->N) return fail(e, SP_E_ARG, "spin array size differs from the number of sites");
+    (void)hipSetDevice(e->device);
+    HIPCHK(e, hipMemcpyAsync(n_soa_dev, e->d_n, 3 * (size_t)N * e->esz(), hipMemcpyDeviceToDevice, e->stream));
+    return SP_OK;
+}
+
+int sp_set_step(sp_engine* e, uint64_t step) {
+    if (!e) return SP_E_ARG;
+    e->step = step;
+    return SP_OK;
+}
+
+uint64_t sp_get_step(const sp_engine* e) { return e ? e->step : 0; }
+
+int sp_gradient_dev(sp_engine* e, void* g_soa_dev, int64_t N) {
+    int rc = check_ready(e, true);
+    if (rc) return rc;
+    if (!g_soa_dev || N != e->N) return fail(e, SP_E_ARG, "gradient array size differs from the number of sites");
+    (void)hipSetDevice(e->device);
+    return DISPATCH(e, gradient_dev, e, e->d_n, g_soa_dev);
+}
+
+int sp_gradient(sp_engine* e, double* g_soa, int64_t N) {
+    int rc = check_ready(e, true);
+    if (rc) return rc;
+    if (!g_soa || N != e->N) return fail(e, SP_E_ARG, "gradient array size differs from the number of sites");
+    (void)hipSetDevice(e->device);
+    if ((rc = DISPATCH(e, gradient_dev, e, e->d_n, e->d_g))) return rc;
+    return DISPATCH(e, copy_out_soa, e, g_soa, e->d_g, 3 * N);
+}
+
+int sp_observe(sp_engine* e, sp_observation* obs) {
+    int rc = check_ready(e, true);
+    if (rc) return rc;
+    if (!obs) return fail(e, SP_E_ARG, "observation pointer is NULL");
+    (void)hipSetDevice(e->device);
+    double* d_out = nullptr;
+    if ((rc = dalloc(e, d_out, sp::OBS_NVALS * sizeof(double)))) return rc;
+    rc = DISPATCH(e, launch_observe, e, e->d_n, d_out, (long long)e->step, false);
+    if (rc == SP_OK) {
+        hipError_t s = hipMemcpyAsync(e->h_pin, d_out, sp::OBS_NVALS * sizeof(double), hipMemcpyDeviceToHost, e->stream);
+        if (s == hipSuccess) s = hipStreamSynchronize(e->stream);
+        if (s != hipSuccess) rc = fail(e, SP_E_HIP, hipGetErrorString(s));
+        else obs_from(e->h_pin, (int64_t)e->step, e->N, obs);
+    }
+    void* p = d_out;
+    dfree(p);
+    return rc;
+}
+
+int sp_energy(sp_engine* e, double* E_total, double per_term[5]) {
+    sp_observation o{};
+    int rc = sp_observe(e, &o);
+    if (rc) return rc;
+    if (E_total) *E_total = o.E;
+    if (per_term)
+        for (int k = 0; k < 5; ++k) per_term[k] = o.per_term[k];
+    return SP_OK;
+}
+
+int sp_llg_step(sp_engine* e, const sp_llg_params* p) {
+    int rc = check_ready(e, true);
+    if (rc) return rc;
+    if ((rc = check_llg(e, p))) return rc;
+    (void)hipSetDevice(e->device);
+    HIPCHK(e, hipMemsetAsync(e->d_flag, 0, sizeof(int), e->stream));
+    if ((rc = DISPATCH(e, launch_step, e, p, e->step, e->d_n, e->d_n2))) return rc;
+    std::swap(e->d_n, e->d_n2);
+    ++e->step;
+    return SP_OK;
+}
+
+int sp_run(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t observe_every, sp_observation* obs) {
+    int rc = check_ready(e, true);
+    if (rc) return rc;
+    if ((rc = check_llg(e, p))) return rc;
+    if (n_steps < 0 || observe_every < 0) return fail(e, SP_E_ARG, "n_steps and observe_every must be >= 0");
+    (void)hipSetDevice(e->device);
+    return DISPATCH(e, run_impl, e, p, n_steps, observe_every, obs);
+}
+
+int sp_synchronize(sp_engine* e) {
+    if (!e) return SP_E_ARG;
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    return SP_OK;
+}
+
+int sp_dipole_gradient_dev(sp_engine* e, const void* n_soa_dev, void* g_soa_dev, int64_t N) {
+    int rc = check_ready(e, false);
+    if (rc) return rc;
+    if (!n_soa_dev || !g_soa_dev || N != e->N) return fail(e, SP_E_ARG, "array size differs from the number of sites");
+    if (!e->ham.ddi) return fail(e, SP_E_ORDER, "the Hamiltonian has no dipole term (ddi_mode off)");
+    (void)hipSetDevice(e->device);
+    return DISPATCH(e, launch_dipole, e, n_soa_dev, g_soa_dev);
+}
+
+int sp_dipole_gradient(sp_engine* e, double* g_soa, int64_t N) {
+    int rc = check_ready(e, true);
+    if (rc) return rc;
+    if (!g_soa || N != e->N) return fail(e, SP_E_ARG, "array size differs from the number of sites");
+    if (!e->ham.ddi) return fail(e, SP_E_ORDER, "the Hamiltonian has no dipole term (ddi_mode off)");
+    (void)hipSetDevice(e->device);
+    if ((rc = DISPATCH(e, launch_dipole, e, e->d_n, e->d_g))) return rc;
+    return DISPATCH(e, copy_out_soa, e, g_soa, e->d_g, 3 * N);
+}
+
+int sp_thermal_normals(sp_engine* e, uint64_t seed, uint64_t step, uint32_t replica, uint32_t site0, int64_t n_sites,
+                       double* eta_soa, uint32_t* raw4) {
+    if (!e) return SP_E_ARG;
+    if (!eta_soa || n_sites <= 0 || n_sites > (1LL << 26)) return fail(e, SP_E_ARG, "bad normals request");
+    (void)hipSetDevice(e->device);
+    return DISPATCH(e, normals_dev, e, seed, step, replica, site0, n_sites, eta_soa, raw4);
+}
+
+const char* sp_step_path(const sp_engine* e) { return e ? e->path : "none"; }
+
+int sp_set_step_path(sp_engine* e, const char* name) {
+    int rc = check_ready(e, false);
+    if (rc) return rc;
+    if (!name) return fail(e, SP_E_ARG, "path name is NULL");
+    if (std::strcmp(name, "twopass") == 0) {
+        e->path = "twopass";
+        return SP_OK;
+    }
+    if (std::strcmp(name, "fused2d") == 0) {
+        if (!e->fused_ok) return fail(e, SP_E_UNSUPPORTED, "fused2d needs a one-atom 2D lattice without dipole");
+        e->path = "fused2d";
+        return SP_OK;
+    }
+    return fail(e, SP_E_ARG, std::string("unknown step path ") + name);
+}
+
+}  // extern "C"

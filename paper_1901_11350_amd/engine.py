@@ -1,0 +1,295 @@
+"""Thin ctypes binding of the C ABI in ``include/sp_engine.h``.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libsp_engine.so``.  PyTorch is used, where the caller wants it,
+for device memory (``*_dev`` calls take CUDA/HIP tensors) and streams.
+If the library is not built, importing works but creating an ``Engine``
+raises ``RuntimeError`` -- there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsp_engine.so")
+
+SP_OK, SP_E_ARG, SP_E_ORDER, SP_E_HIP, SP_E_NOMEM, SP_E_UNSUPPORTED, SP_E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
+SP_F32, SP_F64 = 0, 1
+SP_DMI_BULK, SP_DMI_INTERFACIAL = 1, 2
+SP_DDI_OFF, SP_DDI_DIRECT = 0, 1
+
+# every symbol the header declares
+EXPORTS = [
+    "sp_create", "sp_destroy", "sp_last_error", "sp_version", "sp_set_geometry",
+    "sp_set_hamiltonian", "sp_num_sites", "sp_get_bonds", "sp_set_spins", "sp_get_spins",
+    "sp_set_spins_dev", "sp_get_spins_dev", "sp_set_step", "sp_get_step", "sp_gradient",
+    "sp_gradient_dev", "sp_energy", "sp_observe", "sp_llg_step", "sp_run", "sp_synchronize",
+    "sp_dipole_gradient", "sp_dipole_gradient_dev", "sp_thermal_normals", "sp_step_path",
+    "sp_set_step_path",
+]
+
+
+class SpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sp_engine error {code}: {msg}")
+        self.code = code
+
+
+class sp_hamiltonian(ctypes.Structure):
+    _fields_ = [("n_basis", ctypes.c_int),
+                ("mu", ctypes.POINTER(ctypes.c_double)),
+                ("B", ctypes.c_double * 3),
+                ("K", ctypes.POINTER(ctypes.c_double)),
+                ("K_axis", ctypes.POINTER(ctypes.c_double)),
+                ("n_exch_shells", ctypes.c_int),
+                ("J", ctypes.POINTER(ctypes.c_double)),
+                ("n_dmi_shells", ctypes.c_int),
+                ("D", ctypes.POINTER(ctypes.c_double)),
+                ("dmi_kind", ctypes.c_int),
+                ("ddi_mode", ctypes.c_int)]
+
+
+class sp_llg_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("dt_ps", ctypes.c_double),
+                ("T_K", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class sp_observation(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("E", ctypes.c_double),
+                ("per_term", ctypes.c_double * 5), ("max_torque", ctypes.c_double),
+                ("M", ctypes.c_double * 3), ("max_norm_dev", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libsp_engine.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP engine library not built: {LIB_PATH} is missing "
+                           "(run paper_1901_11350_amd/build.py or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, i64, u64, ci = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+    sig = {
+        "sp_create": (ci, [ctypes.POINTER(vp), ci, ci, vp]),
+        "sp_destroy": (None, [vp]),
+        "sp_last_error": (ctypes.c_char_p, [vp]),
+        "sp_version": (ctypes.c_char_p, []),
+        "sp_set_geometry": (ci, [vp, dp, ci, dp, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.c_double]),
+        "sp_set_hamiltonian": (ci, [vp, ctypes.POINTER(sp_hamiltonian)]),
+        "sp_num_sites": (i64, [vp]),
+        "sp_get_bonds": (ci, [vp, ci, dp, ci]),
+        "sp_set_spins": (ci, [vp, dp, i64]),
+        "sp_get_spins": (ci, [vp, dp, i64]),
+        "sp_set_spins_dev": (ci, [vp, vp, i64]),
+        "sp_get_spins_dev": (ci, [vp, vp, i64]),
+        "sp_set_step": (ci, [vp, u64]),
+        "sp_get_step": (u64, [vp]),
+        "sp_gradient": (ci, [vp, dp, i64]),
+        "sp_gradient_dev": (ci, [vp, vp, i64]),
+        "sp_energy": (ci, [vp, dp, dp]),
+        "sp_observe": (ci, [vp, ctypes.POINTER(sp_observation)]),
+        "sp_llg_step": (ci, [vp, ctypes.POINTER(sp_llg_params)]),
+        "sp_run": (ci, [vp, ctypes.POINTER(sp_llg_params), i64, i64, ctypes.POINTER(sp_observation)]),
+        "sp_synchronize": (ci, [vp]),
+        "sp_dipole_gradient": (ci, [vp, dp, i64]),
+        "sp_dipole_gradient_dev": (ci, [vp, vp, vp, i64]),
+        "sp_thermal_normals": (ci, [vp, u64, u64, ctypes.c_uint32, ctypes.c_uint32, i64, dp,
+                                    ctypes.POINTER(ctypes.c_uint32)]),
+        "sp_step_path": (ctypes.c_char_p, [vp]),
+        "sp_set_step_path": (ci, [vp, ctypes.c_char_p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(values, n=None):
+    a = np.ascontiguousarray(np.asarray(values, dtype=np.float64).ravel())
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def obs_dict(o: sp_observation) -> dict:
+    return {"step": int(o.step), "E": o.E, "per_term": list(o.per_term),
+            "max_torque": o.max_torque, "M": list(o.M), "max_norm_dev": o.max_norm_dev}
+
+
+class Engine:
+    """One engine instance (``sp_engine``) on one HIP device."""
+
+    def __init__(self, device: int = 0, precision: str = "f32", stream=None):
+        L = lib()
+        self.precision = precision
+        prec = {"f32": SP_F32, "f64": SP_F64}[precision]
+        self._h = ctypes.c_void_p()
+        s = None
+        if stream is not None:
+            s = ctypes.c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+        rc = L.sp_create(ctypes.byref(self._h), device, prec, s)
+        if rc != SP_OK:
+            raise SpError(rc, "sp_create failed (no HIP device?)")
+        self.N = 0
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.sp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc: int):
+        if rc != SP_OK:
+            raise SpError(rc, lib().sp_last_error(self._h).decode())
+        return rc
+
+    # ------------------------------------------------------------- setup
+    def set_geometry(self, geometry):
+        br = _f64(geometry.bravais, 9)
+        bs = _f64(geometry.basis, 3 * len(geometry.basis))
+        nc = (ctypes.c_int * 3)(*geometry.n_cells)
+        pe = (ctypes.c_int * 3)(*geometry.periodic)
+        self._check(lib().sp_set_geometry(self._h, _dp(br), len(geometry.basis), _dp(bs), nc, pe,
+                                          float(geometry.lattice_constant)))
+        self.N = int(lib().sp_num_sites(self._h))
+
+    def set_hamiltonian(self, ham):
+        nb = len(ham.mu)
+        arrs = {"mu": _f64(ham.mu, nb), "K": _f64(ham.K, nb), "Kax": _f64(ham.K_axis, 3 * nb),
+                "J": _f64(ham.J if len(ham.J) else [0.0]), "D": _f64(ham.D if len(ham.D) else [0.0])}
+        h = sp_hamiltonian()
+        h.n_basis = nb
+        h.mu = _dp(arrs["mu"])
+        for k in range(3):
+            h.B[k] = ham.B[k]
+        h.K = _dp(arrs["K"])
+        h.K_axis = _dp(arrs["Kax"])
+        h.n_exch_shells = len(ham.J)
+        h.J = _dp(arrs["J"])
+        h.n_dmi_shells = len(ham.D)
+        h.D = _dp(arrs["D"])
+        h.dmi_kind = ham.dmi_kind
+        h.ddi_mode = SP_DDI_DIRECT if ham.ddi else SP_DDI_OFF
+        self._check(lib().sp_set_hamiltonian(self._h, ctypes.byref(h)))
+
+    def bonds(self, beta: int = 0):
+        k = lib().sp_get_bonds(self._h, beta, None, 0)
+        if k < 0:
+            self._check(k)
+        out = np.zeros(10 * max(k, 1))
+        lib().sp_get_bonds(self._h, beta, _dp(out), k)
+        return out[: 10 * k].reshape(k, 10)
+
+    # ------------------------------------------------------------- spins
+    def set_spins(self, n):
+        a = _f64(n, 3 * self.N)
+        self._check(lib().sp_set_spins(self._h, _dp(a), self.N))
+
+    def get_spins(self) -> np.ndarray:
+        out = np.zeros(3 * self.N)
+        self._check(lib().sp_get_spins(self._h, _dp(out), self.N))
+        return out.reshape(3, self.N)
+
+    def set_spins_dev(self, t):
+        self._check(lib().sp_set_spins_dev(self._h, ctypes.c_void_p(t.data_ptr()), self.N))
+
+    def get_spins_dev(self, t):
+        self._check(lib().sp_get_spins_dev(self._h, ctypes.c_void_p(t.data_ptr()), self.N))
+
+    @property
+    def step(self) -> int:
+        return int(lib().sp_get_step(self._h))
+
+    @step.setter
+    def step(self, v: int):
+        self._check(lib().sp_set_step(self._h, int(v)))
+
+    @property
+    def step_path(self) -> str:
+        return lib().sp_step_path(self._h).decode()
+
+    @step_path.setter
+    def step_path(self, name: str):
+        self._check(lib().sp_set_step_path(self._h, name.encode()))
+
+    # ----------------------------------------------------------- compute
+    def gradient(self) -> np.ndarray:
+        out = np.zeros(3 * self.N)
+        self._check(lib().sp_gradient(self._h, _dp(out), self.N))
+        return out.reshape(3, self.N)
+
+    def gradient_dev(self, t):
+        self._check(lib().sp_gradient_dev(self._h, ctypes.c_void_p(t.data_ptr()), self.N))
+
+    def dipole_gradient(self) -> np.ndarray:
+        out = np.zeros(3 * self.N)
+        self._check(lib().sp_dipole_gradient(self._h, _dp(out), self.N))
+        return out.reshape(3, self.N)
+
+    def dipole_gradient_dev(self, n_t, g_t):
+        self._check(lib().sp_dipole_gradient_dev(self._h, ctypes.c_void_p(n_t.data_ptr()),
+                                                 ctypes.c_void_p(g_t.data_ptr()), self.N))
+
+    def energy(self, per_term: bool = False):
+        E = ctypes.c_double()
+        pt = np.zeros(5)
+        self._check(lib().sp_energy(self._h, ctypes.byref(E), _dp(pt)))
+        return (E.value, pt) if per_term else E.value
+
+    def observe(self) -> dict:
+        o = sp_observation()
+        self._check(lib().sp_observe(self._h, ctypes.byref(o)))
+        return obs_dict(o)
+
+    def llg_step(self, alpha: float, dt: float, T: float = 0.0, seed: int = 0):
+        p = sp_llg_params(alpha, dt, T, seed)
+        self._check(lib().sp_llg_step(self._h, ctypes.byref(p)))
+
+    def run(self, alpha: float, dt: float, n_steps: int, T: float = 0.0, seed: int = 0,
+            observe_every: int = 0, check: bool = True):
+        p = sp_llg_params(alpha, dt, T, seed)
+        n_obs = n_steps // observe_every if observe_every > 0 else 0
+        obs = (sp_observation * max(n_obs, 1))()
+        rc = lib().sp_run(self._h, ctypes.byref(p), n_steps, observe_every, obs if n_obs else None)
+        if check:
+            self._check(rc)
+        res = [obs_dict(o) for o in obs[:n_obs]]
+        return (res, rc) if not check else res
+
+    def synchronize(self):
+        self._check(lib().sp_synchronize(self._h))
+
+    def thermal_normals(self, seed: int, step: int, site0: int, n_sites: int, replica: int = 0):
+        eta = np.zeros(3 * n_sites)
+        raw = (ctypes.c_uint32 * (4 * n_sites))()
+        self._check(lib().sp_thermal_normals(self._h, seed, step, replica, site0, n_sites, _dp(eta), raw))
+        return eta.reshape(3, n_sites), np.frombuffer(raw, dtype=np.uint32).reshape(n_sites, 4).copy()
+
+
+def engine_for(workload, device: int = 0, precision: Optional[str] = None, stream=None) -> Engine:
+    """Engine with the workload's geometry and Hamiltonian set (spins not set)."""
+    e = Engine(device, precision or workload.precision, stream)
+    e.set_geometry(workload.geometry)
+    e.set_hamiltonian(workload.hamiltonian)
+    return e
+
+
+Sequence
