@@ -48,16 +48,43 @@ def cpu_baseline(workload, budget_s: float = 12.0) -> dict:
             "sample": f"{steps} FP64 Depondt steps of the full {s.N}-spin workload ({el:.1f} s)"}
 
 
+def calibrate_copy(mib: int, reps: int = 5) -> None:
+    """A plain device-to-device copy of known size: the reference that HBM
+    byte counters (FETCH_SIZE / WRITE_SIZE) are scaled against."""
+    import torch
+
+    n = mib * 1024 * 1024 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    print(json.dumps({"calibration": "copy", "bytes_read_per_launch": 4 * n,
+                      "bytes_written_per_launch": 4 * n, "ms_per_launch": ms,
+                      "GBps": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
+                    help="only run a device copy of this size (counter calibration)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="triangular512_sllg")
     ap.add_argument("--observe-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -79,8 +106,11 @@ def main():
     else:
         n0 = si.uniform_sphere(e.N, w.init_seed)
     e.set_spins(n0)
-    print(f"[bench] workload={w.name} N={e.N} path={e.step_path} precision={w.precision}",
-          file=sys.stderr, flush=True)
+    tuned_ms = None
+    if not args.no_autotune:
+        tuned_ms = e.autotune(d.alpha, d.dt, d.T, d.seed, n_steps=50)
+    print(f"[bench] workload={w.name} N={e.N} path={e.step_path} precision={w.precision} "
+          f"autotune_ms={tuned_ms}", file=sys.stderr, flush=True)
 
     # warm-up
     e.run(d.alpha, d.dt, args.warmup, T=d.T, seed=d.seed)
@@ -109,7 +139,7 @@ def main():
     e.run(d.alpha, d.dt, K2, T=d.T, seed=d.seed)
     k_ev1.record(stream)
     torch.cuda.synchronize()
-    launches_per_step = 1 if e.step_path == "fused2d" else 2
+    launches_per_step = 2 if e.step_path == "twopass" else 1
     t_launch = k_ev0.elapsed_time(k_ev1) * 1e-3 / (K2 * launches_per_step)
     bytes_per_launch = BYTES_PER_UPDATE[w.precision] * e.N / launches_per_step
     achieved = bytes_per_launch / t_launch / 1e9
@@ -134,7 +164,8 @@ def main():
         "hbm_gbps_algorithmic": value * BYTES_PER_UPDATE[w.precision] / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "k_depondt_fused2d" if e.step_path == "fused2d" else "k_predict+k_correct",
+                     "kernel": {"fused2d": "k_depondt_fused2d", "twopass": "k_predict+k_correct"}.get(
+                         e.step_path, "k_fused2d_shape"),
                      "bytes_per_launch": bytes_per_launch, "us_per_launch": t_launch * 1e6},
         "wall_s": wall,
         "final_observation": {"E_per_spin": last["E"] / e.N, "max_norm_dev": last["max_norm_dev"]},

@@ -183,10 +183,19 @@ int sp_thermal_normals(sp_engine *e, uint64_t seed, uint64_t step, uint32_t repl
 /* Name of the kernel path sp_llg_step uses for the current state
  * ("fused2d", "twopass", ...), for diagnostics. */
 const char *sp_step_path(const sp_engine *e);
-/* Force the step path ("twopass" always works; "fused2d" only where the
- * lattice allows it, otherwise SP_E_UNSUPPORTED).  Reset by
- * sp_set_hamiltonian.  For cross-path consistency checks. */
+/* Force the step path: "twopass" (any lattice), "fused2d" (one-atom 2D
+ * lattice, runtime bond loop) or "shape2d[/TXxTYxNT]" (one-atom 2D lattice
+ * whose bond table matches a compile-time stencil; optional tile
+ * configuration such as "shape2d/32x16x256").  A path the current lattice
+ * does not allow gives SP_E_UNSUPPORTED, an unknown name SP_E_ARG.  Reset by
+ * sp_set_hamiltonian (which picks the fastest allowed path by default). */
 int sp_set_step_path(sp_engine *e, const char *name);
+/* Autotuner: times every step path and tile configuration the current
+ * lattice allows (n_steps steps each, after one warm-up step, HIP events on
+ * the engine stream) from the current spins, then keeps the fastest.  Spins
+ * and the step counter are restored.  *ms_per_step (may be NULL) receives the
+ * best time per step. */
+int sp_autotune(sp_engine *e, const sp_llg_params *p, int n_steps, double *ms_per_step);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,7 @@
 #include "kernels_field.hpp"
 #include "kernels_reduce.hpp"
 #include "kernels_dipole.hpp"
+#include "kernels_fused2d.hpp"
 
 namespace {
 
@@ -71,6 +72,12 @@ struct sp_engine {
     uint64_t step = 0;
     const char* path = "none";
     bool fused_ok = false;
+    std::vector<HostBond> all_bonds;  // every bond of the requested shells (zero ones included)
+    int n_shells = 0;
+    int shape = -1;                   // sp::Shape2D matched by the bond table, or -1
+    int shape_ndmi = 0;               // 0: no DMI, 1: DMI on the first shell only
+    int tile_cfg = 0;                 // index into the shape-path tile configurations
+    std::string path_label;
 
     size_t esz() const { return precision == SP_F64 ? 8 : 4; }
 
@@ -148,12 +155,13 @@ void free_state_buffers(sp_engine* e) {
 // 1e-6 lattice constants form one shell.  Bonds of the first
 // max(n_exch, n_dmi) shells are kept in both directions.
 int build_bonds(sp_engine* e, const HostGeo& g, const HostHam& h, std::vector<HostBond>& out,
-                std::vector<int>& start) {
+                std::vector<int>& start, std::vector<HostBond>& all) {
     struct Cand {
         int bj, d[3];
         double dist, r[3];
     };
     out.clear();
+    all.clear();
     start.assign(g.nb + 1, 0);
     const int want = std::max(h.n_exch, h.n_dmi);
     int ext[3];
@@ -195,6 +203,7 @@ int build_bonds(sp_engine* e, const HostGeo& g, const HostHam& h, std::vector<Ho
             } else {  // z x r_hat
                 b.D[0] = -Dm * uy; b.D[1] = Dm * ux; b.D[2] = 0.0;
             }
+            all.push_back(b);
             if (b.J == 0.0 && b.D[0] == 0.0 && b.D[1] == 0.0 && b.D[2] == 0.0) continue;
             out.push_back(b);
         }
@@ -357,8 +366,108 @@ void launch_fused2d(sp_engine* e, const sp_llg_params* p, uint64_t step, const v
                        static_cast<T*>(nout));
 }
 
+// ------------------------------------------- compile-time-shape fused path
+struct TileCfg {
+    const char* name;
+    int TX, TY, NT;
+};
+constexpr TileCfg kTileCfgs[] = {{"32x16x256", 32, 16, 256},  {"64x16x512", 64, 16, 512},
+                                 {"32x16x512", 32, 16, 512},  {"32x32x1024", 32, 32, 1024},
+                                 {"64x16x1024", 64, 16, 1024}};
+constexpr int kNumTileCfgs = 5;
+constexpr int kNumTileCfgsF64 = 1;
+
+template <int S>
+bool match_shape(const sp_engine* e) {
+    using SH = sp::ShapeTab<S>;
+    if (e->n_shells != SH::NS || (int)e->all_bonds.size() != SH::NB) return false;
+    for (int q = 0; q < SH::NB; ++q) {
+        bool found = false;
+        for (const HostBond& b : e->all_bonds)
+            if (b.d[0] == SH::da[q] && b.d[1] == SH::db[q] && b.d[2] == 0 && b.shell == SH::sh[q]) found = true;
+        if (!found) return false;
+    }
+    return true;
+}
+
+int detect_shape(const sp_engine* e) {
+    if (match_shape<sp::SH_SQ1>(e)) return sp::SH_SQ1;
+    if (match_shape<sp::SH_SQ2>(e)) return sp::SH_SQ2;
+    if (match_shape<sp::SH_SQ3>(e)) return sp::SH_SQ3;
+    if (match_shape<sp::SH_TRI1>(e)) return sp::SH_TRI1;
+    if (match_shape<sp::SH_TRI2>(e)) return sp::SH_TRI2;
+    if (match_shape<sp::SH_TRI3>(e)) return sp::SH_TRI3;
+    return -1;
+}
+
+template <typename T, int S>
+sp::ShapeCoef<T> shape_coef_for(const sp_engine* e) {
+    using SH = sp::ShapeTab<S>;
+    sp::ShapeCoef<T> C{};
+    for (int s = 0; s < SH::NS; ++s) C.J[s] = (T)(s < e->ham.n_exch ? e->ham.J[s] : 0.0);
+    for (int q = 0; q < SH::NB; ++q)
+        for (const HostBond& b : e->all_bonds)
+            if (b.d[0] == SH::da[q] && b.d[1] == SH::db[q] && b.shell == SH::sh[q]) {
+                C.Dx[q] = (T)b.D[0];
+                C.Dy[q] = (T)b.D[1];
+            }
+    return C;
+}
+
+template <typename T, int S, int NDMI, int TX, int TY, int NT>
+void go_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    sp::TileMap M{};
+    M.tiles_x = (e->geo.n[0] + TX - 1) / TX;
+    M.tiles_y = (e->geo.n[1] + TY - 1) / TY;
+    const int ntiles = M.tiles_x * M.tiles_y;
+    M.xcd_bands = (ntiles >= 8 && ntiles % 8 == 0) ? 1 : 0;
+    hipLaunchKernelGGL((sp::k_fused2d_shape<T, S, NDMI, TX, TY, NT>), dim3((unsigned)ntiles), dim3(NT), 0, e->stream,
+                       shape_coef_for<T, S>(e), make_site2d<T>(e, p), make_llg<T>(p, step, 0), M, e->d_flag,
+                       static_cast<const T*>(nin), static_cast<T*>(nout));
+}
+
+template <typename T, int S, int TX, int TY, int NT>
+void go_ndmi(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    if (e->shape_ndmi)
+        go_shape<T, S, sp::ShapeTab<S>::NB0, TX, TY, NT>(e, p, step, nin, nout);
+    else
+        go_shape<T, S, 0, TX, TY, NT>(e, p, step, nin, nout);
+}
+
+template <typename T, int TX, int TY, int NT>
+void go_tile(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    switch (e->shape) {
+        case sp::SH_SQ1: go_ndmi<T, sp::SH_SQ1, TX, TY, NT>(e, p, step, nin, nout); break;
+        case sp::SH_SQ2: go_ndmi<T, sp::SH_SQ2, TX, TY, NT>(e, p, step, nin, nout); break;
+        case sp::SH_SQ3: go_ndmi<T, sp::SH_SQ3, TX, TY, NT>(e, p, step, nin, nout); break;
+        case sp::SH_TRI1: go_ndmi<T, sp::SH_TRI1, TX, TY, NT>(e, p, step, nin, nout); break;
+        case sp::SH_TRI2: go_ndmi<T, sp::SH_TRI2, TX, TY, NT>(e, p, step, nin, nout); break;
+        default: go_ndmi<T, sp::SH_TRI3, TX, TY, NT>(e, p, step, nin, nout); break;
+    }
+}
+
+template <typename T>
+void launch_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    if constexpr (sizeof(T) == 8) {
+        go_tile<T, 32, 16, 256>(e, p, step, nin, nout);
+    } else {
+        switch (e->tile_cfg) {
+            case 1: go_tile<T, 64, 16, 512>(e, p, step, nin, nout); break;
+            case 2: go_tile<T, 32, 16, 512>(e, p, step, nin, nout); break;
+            case 3: go_tile<T, 32, 32, 1024>(e, p, step, nin, nout); break;
+            case 4: go_tile<T, 64, 16, 1024>(e, p, step, nin, nout); break;
+            default: go_tile<T, 32, 16, 256>(e, p, step, nin, nout); break;
+        }
+    }
+}
+
 template <typename T>
 int launch_step(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    if (std::strcmp(e->path, "shape2d") == 0) {
+        launch_shape<T>(e, p, step, nin, nout);
+        HIPCHK(e, hipGetLastError());
+        return SP_OK;
+    }
     if (std::strcmp(e->path, "fused2d") == 0) {
         if (e->R <= 1)
             launch_fused2d<T, 32, 16, 1>(e, p, step, nin, nout);
@@ -691,9 +800,9 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
     H.dmi_kind = h->n_dmi_shells > 0 ? h->dmi_kind : SP_DMI_INTERFACIAL;
     H.ddi = h->ddi_mode == SP_DDI_DIRECT ? 1 : 0;
 
-    std::vector<HostBond> bonds;
+    std::vector<HostBond> bonds, all_bonds;
     std::vector<int> bstart;
-    int rc = build_bonds(e, e->geo, H, bonds, bstart);
+    int rc = build_bonds(e, e->geo, H, bonds, bstart, all_bonds);
     if (rc) return rc;
 
     (void)hipSetDevice(e->device);
@@ -707,6 +816,8 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
     free_state_buffers(e);
     e->ham = H;
     e->bonds = bonds;
+    e->all_bonds = all_bonds;
+    e->n_shells = std::max(H.n_exch, H.n_dmi);
     e->bstart = bstart;
     e->R = 0;
     e->planar = true;
@@ -755,6 +866,25 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
     if (g.per[1] && g.n[1] <= 2 * e->R) fused = false;
     e->fused_ok = fused;
     e->path = fused ? "fused2d" : "twopass";
+    // compile-time stencil: the bond table must match a known shape, DMI may
+    // sit on the first shell only, and every DMI vector must be in-plane
+    e->shape = -1;
+    e->shape_ndmi = 0;
+    e->tile_cfg = 0;
+    if (fused) {
+        bool ok = true;
+        for (const HostBond& b : all_bonds)
+            if (b.D[2] != 0.0 || (b.shell > 0 && (b.D[0] != 0.0 || b.D[1] != 0.0))) ok = false;
+        const int shp = ok ? detect_shape(e) : -1;
+        if (shp >= 0) {
+            e->shape = shp;
+            for (const HostBond& b : all_bonds)
+                if (b.shell == 0 && (b.D[0] != 0.0 || b.D[1] != 0.0)) e->shape_ndmi = 1;
+            e->path = "shape2d";
+        }
+    }
+    e->path_label = e->path;
+    if (e->shape >= 0) e->path_label += std::string("/") + kTileCfgs[e->tile_cfg].name;
 
     if (had_spins) {
         if ((rc = DISPATCH(e, copy_in_soa, e, e->d_n, saved.data(), 3LL * e->N))) return rc;
@@ -938,22 +1068,93 @@ int sp_thermal_normals(sp_engine* e, uint64_t seed, uint64_t step, uint32_t repl
     return DISPATCH(e, normals_dev, e, seed, step, replica, site0, n_sites, eta_soa, raw4);
 }
 
-const char* sp_step_path(const sp_engine* e) { return e ? e->path : "none"; }
+const char* sp_step_path(const sp_engine* e) { return e ? e->path_label.c_str() : "none"; }
 
 int sp_set_step_path(sp_engine* e, const char* name) {
     int rc = check_ready(e, false);
     if (rc) return rc;
     if (!name) return fail(e, SP_E_ARG, "path name is NULL");
-    if (std::strcmp(name, "twopass") == 0) {
+    const std::string s(name);
+    if (s == "twopass") {
         e->path = "twopass";
-        return SP_OK;
-    }
-    if (std::strcmp(name, "fused2d") == 0) {
+    } else if (s == "fused2d") {
         if (!e->fused_ok) return fail(e, SP_E_UNSUPPORTED, "fused2d needs a one-atom 2D lattice without dipole");
         e->path = "fused2d";
-        return SP_OK;
+    } else if (s.rfind("shape2d", 0) == 0) {
+        if (e->shape < 0)
+            return fail(e, SP_E_UNSUPPORTED, "shape2d needs a bond table matching a compile-time stencil");
+        int cfg = 0;
+        if (s.size() > 7) {
+            if (s[7] != '/') return fail(e, SP_E_ARG, "unknown step path " + s);
+            cfg = -1;
+            const int ncfg = e->precision == SP_F64 ? kNumTileCfgsF64 : kNumTileCfgs;
+            for (int k = 0; k < ncfg; ++k)
+                if (s.substr(8) == kTileCfgs[k].name) cfg = k;
+            if (cfg < 0) return fail(e, SP_E_ARG, "unknown tile configuration in " + s);
+        }
+        e->path = "shape2d";
+        e->tile_cfg = cfg;
+    } else {
+        return fail(e, SP_E_ARG, "unknown step path " + s);
     }
-    return fail(e, SP_E_ARG, std::string("unknown step path ") + name);
+    e->path_label = e->path;
+    if (std::strcmp(e->path, "shape2d") == 0) e->path_label += std::string("/") + kTileCfgs[e->tile_cfg].name;
+    return SP_OK;
+}
+
+int sp_autotune(sp_engine* e, const sp_llg_params* p, int n_steps, double* ms_per_step) {
+    int rc = check_ready(e, true);
+    if (rc) return rc;
+    if ((rc = check_llg(e, p))) return rc;
+    if (n_steps < 1 || n_steps > 100000) return fail(e, SP_E_ARG, "n_steps must be in 1..100000");
+    (void)hipSetDevice(e->device);
+    std::vector<std::string> cands{"twopass"};
+    if (e->fused_ok) cands.push_back("fused2d");
+    if (e->shape >= 0) {
+        const int ncfg = e->precision == SP_F64 ? kNumTileCfgsF64 : kNumTileCfgs;
+        for (int k = 0; k < ncfg; ++k) cands.push_back(std::string("shape2d/") + kTileCfgs[k].name);
+    }
+    const std::string keep_label = e->path_label;
+    const uint64_t keep_step = e->step;
+    const size_t bytes = 3 * (size_t)e->N * e->esz();
+    void* backup = nullptr;
+    if ((rc = dalloc(e, backup, bytes))) return rc;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    double best = 1e300;
+    std::string best_name = keep_label;
+    int out = SP_OK;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess ||
+        hipMemcpyAsync(backup, e->d_n, bytes, hipMemcpyDeviceToDevice, e->stream) != hipSuccess) {
+        out = fail(e, SP_E_HIP, "autotune set-up failed");
+    }
+    for (size_t c = 0; out == SP_OK && c < cands.size(); ++c) {
+        if ((rc = sp_set_step_path(e, cands[c].c_str()))) { out = rc; break; }
+        float ms = 0.0f;
+        // warm-up (code load, caches), then the timed steps
+        rc = DISPATCH(e, launch_step, e, p, e->step, e->d_n, e->d_n2);
+        if (!rc && hipEventRecord(t0, e->stream) != hipSuccess) rc = SP_E_HIP;
+        for (int k = 0; !rc && k < n_steps; ++k) {
+            rc = DISPATCH(e, launch_step, e, p, keep_step + k, (k & 1) ? e->d_n2 : e->d_n, (k & 1) ? e->d_n : e->d_n2);
+        }
+        if (!rc && (hipEventRecord(t1, e->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, t0, t1) != hipSuccess))
+            rc = SP_E_HIP;
+        if (!rc && hipMemcpyAsync(e->d_n, backup, bytes, hipMemcpyDeviceToDevice, e->stream) != hipSuccess)
+            rc = SP_E_HIP;
+        if (rc) { out = rc == SP_E_HIP ? fail(e, SP_E_HIP, "autotune timing failed") : rc; break; }
+        if (ms / n_steps < best) {
+            best = ms / n_steps;
+            best_name = cands[c];
+        }
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    (void)hipStreamSynchronize(e->stream);
+    dfree(backup);
+    e->step = keep_step;
+    const int rc2 = sp_set_step_path(e, out == SP_OK ? best_name.c_str() : keep_label.c_str());
+    if (out == SP_OK && ms_per_step) *ms_per_step = best;
+    return out != SP_OK ? out : rc2;
 }
 
 }  // extern "C"

@@ -1,0 +1,266 @@
+// kernels_fused2d.hpp -- fused Depondt step for one-atom 2D lattices with a
+// compile-time neighbour stencil.
+//
+// A stencil "shape" is the list of cell offsets (da, db) of the bonds of one
+// site, grouped by neighbour shell; the host matches the bond table against
+// the shapes below and passes the per-shell exchange constants and per-bond
+// DMI vectors at run time.  With the offsets known at compile time the LDS
+// neighbour reads use immediate offsets, exchange is summed per shell before
+// multiplying by J, and (bonds being in-plane) every DMI vector has D_z = 0,
+// so n_j x D costs four FMAs.
+//
+// Per workgroup (NT threads, TX x TY output tile):
+//   1. stage n(t) on the tile plus a 2R halo into LDS (periodic axes wrap,
+//      open axes pad with zero spins, which drop out of every bond sum);
+//   2. predictor on the tile plus an R halo: field, thermal normals
+//      (Philox, counter = global site), A = -gp (B + alpha n x B),
+//      n^p = R(A) n into LDS; A and the thermal field of tile sites kept;
+//   3. corrector on the tile: A^p from n^p, n(t+dt) = R((A + A^p)/2) n(t),
+//      written once to HBM.
+// Workgroups are mapped to tiles so that each XCD (workgroups are dealt to
+// the 8 XCDs round-robin) owns a contiguous band of tile rows: neighbouring
+// tiles, whose halos overlap, then share one L2.
+#pragma once
+
+#include "kernels_field.hpp"
+
+namespace sp {
+
+enum Shape2D { SH_SQ1 = 0, SH_SQ2, SH_SQ3, SH_TRI1, SH_TRI2, SH_TRI3, SH_COUNT };
+
+template <int S>
+struct ShapeTab;
+
+// square lattice: shells at 1, sqrt2, 2
+template <>
+struct ShapeTab<SH_SQ1> {
+    static constexpr int NB = 4, NS = 1, R = 1, NB0 = 4;
+    static constexpr int da[NB] = {1, -1, 0, 0};
+    static constexpr int db[NB] = {0, 0, 1, -1};
+    static constexpr int sh[NB] = {0, 0, 0, 0};
+};
+template <>
+struct ShapeTab<SH_SQ2> {
+    static constexpr int NB = 8, NS = 2, R = 1, NB0 = 4;
+    static constexpr int da[NB] = {1, -1, 0, 0, 1, -1, 1, -1};
+    static constexpr int db[NB] = {0, 0, 1, -1, 1, -1, -1, 1};
+    static constexpr int sh[NB] = {0, 0, 0, 0, 1, 1, 1, 1};
+};
+template <>
+struct ShapeTab<SH_SQ3> {
+    static constexpr int NB = 12, NS = 3, R = 2, NB0 = 4;
+    static constexpr int da[NB] = {1, -1, 0, 0, 1, -1, 1, -1, 2, -2, 0, 0};
+    static constexpr int db[NB] = {0, 0, 1, -1, 1, -1, -1, 1, 0, 0, 2, -2};
+    static constexpr int sh[NB] = {0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2};
+};
+// triangular lattice a1 = (1,0), a2 = (1/2, sqrt3/2): shells at 1, sqrt3, 2
+template <>
+struct ShapeTab<SH_TRI1> {
+    static constexpr int NB = 6, NS = 1, R = 1, NB0 = 6;
+    static constexpr int da[NB] = {1, -1, 0, 0, 1, -1};
+    static constexpr int db[NB] = {0, 0, 1, -1, -1, 1};
+    static constexpr int sh[NB] = {0, 0, 0, 0, 0, 0};
+};
+template <>
+struct ShapeTab<SH_TRI2> {
+    static constexpr int NB = 12, NS = 2, R = 2, NB0 = 6;
+    static constexpr int da[NB] = {1, -1, 0, 0, 1, -1, 1, -1, 2, -2, 1, -1};
+    static constexpr int db[NB] = {0, 0, 1, -1, -1, 1, 1, -1, -1, 1, -2, 2};
+    static constexpr int sh[NB] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1};
+};
+template <>
+struct ShapeTab<SH_TRI3> {
+    static constexpr int NB = 18, NS = 3, R = 2, NB0 = 6;
+    static constexpr int da[NB] = {1, -1, 0, 0, 1, -1, 1, -1, 2, -2, 1, -1, 2, -2, 0, 0, 2, -2};
+    static constexpr int db[NB] = {0, 0, 1, -1, -1, 1, 1, -1, -1, 1, -2, 2, 0, 0, 2, -2, -2, 2};
+    static constexpr int sh[NB] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2};
+};
+
+// Run-time coefficients in shape order.
+template <typename T>
+struct ShapeCoef {
+    T J[4];            // per shell
+    T Dx[24], Dy[24];  // per bond (D_z = 0 for in-plane bonds)
+};
+
+template <typename T>
+__device__ __forceinline__ void native_sincos(T x, T* s, T* c) {
+    if constexpr (sizeof(T) == 4) {
+        const float r = x * 0.15915494309189535f;  // radians -> revolutions
+        *s = __builtin_amdgcn_sinf(r);
+        *c = __builtin_amdgcn_cosf(r);
+    } else {
+        sincos(x, s, c);
+    }
+}
+
+// Rotation of n about w by |w| dt, in the form
+//   n' = n + s1 (w x n) + s2 (w (w.n) - |w|^2 n),
+//   s1 = sin(theta)/|w|, s2 = (1 - cos theta)/|w|^2 = 2 sin^2(theta/2)/|w|^2.
+template <typename T>
+__device__ __forceinline__ V3<T> rotate_fast(V3<T> n, V3<T> w, T dt) {
+    const T w2 = dot(w, w);
+    T inv;
+    if constexpr (sizeof(T) == 4) {
+        inv = w2 > 0.0f ? __builtin_amdgcn_rsqf(w2) : 0.0f;
+    } else {
+        inv = w2 > 0.0 ? 1.0 / sqrt(w2) : 0.0;
+    }
+    const T half = T(0.5) * dt * (w2 * inv);
+    T sh, ch;
+    native_sincos(half, &sh, &ch);
+    const T s1 = T(2) * sh * ch * inv;
+    const T s2 = T(2) * sh * sh * (inv * inv);
+    const V3<T> wxn = cross(w, n);
+    const T wn = dot(w, n);
+    return V3<T>{n.x + s1 * wxn.x + s2 * (w.x * wn - w2 * n.x),
+                 n.y + s1 * wxn.y + s2 * (w.y * wn - w2 * n.y),
+                 n.z + s1 * wxn.z + s2 * (w.z * wn - w2 * n.z)};
+}
+
+template <typename T, int S, int NDMI, int W>
+__device__ __forceinline__ V3<T> shape_field(const ShapeCoef<T>& C, const Site2D<T>& Q, const T* __restrict__ sx,
+                                             const T* __restrict__ sy, const T* __restrict__ sz, int c, V3<T> ni) {
+    using SH = ShapeTab<S>;
+    V3<T> acc[SH::NS];
+#pragma unroll
+    for (int s = 0; s < SH::NS; ++s) acc[s] = V3<T>{T(0), T(0), T(0)};
+    T dx = T(0), dy = T(0), dz = T(0);
+#pragma unroll
+    for (int q = 0; q < SH::NB; ++q) {
+        const int o = c + SH::da[q] + SH::db[q] * W;
+        const T jx = sx[o], jy = sy[o], jz = sz[o];
+        acc[SH::sh[q]].x += jx;
+        acc[SH::sh[q]].y += jy;
+        acc[SH::sh[q]].z += jz;
+        if (q < NDMI) {
+            // n_j x D with D = (Dx, Dy, 0)
+            dx -= jz * C.Dy[q];
+            dy += jz * C.Dx[q];
+            dz += jx * C.Dy[q] - jy * C.Dx[q];
+        }
+    }
+    const T kn = Q.K2 * (Q.Kax[0] * ni.x + Q.Kax[1] * ni.y + Q.Kax[2] * ni.z);
+    V3<T> g{Q.gZ[0] - kn * Q.Kax[0] - dx, Q.gZ[1] - kn * Q.Kax[1] - dy, Q.gZ[2] - kn * Q.Kax[2] - dz};
+#pragma unroll
+    for (int s = 0; s < SH::NS; ++s) {
+        g.x -= C.J[s] * acc[s].x;
+        g.y -= C.J[s] * acc[s].y;
+        g.z -= C.J[s] * acc[s].z;
+    }
+    return g;
+}
+
+struct TileMap {
+    int tiles_x, tiles_y;
+    int xcd_bands;   // 1: XCD-banded mapping (tile count divisible by 8), 0: identity
+};
+
+__device__ __forceinline__ int wrap_once(int g, int n, int per, bool& in) {
+    if (g < 0) {
+        if (per) return g + n;
+        in = false;
+    } else if (g >= n) {
+        if (per) return g - n;
+        in = false;
+    }
+    return g;
+}
+
+template <typename T, int S, int NDMI, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_fused2d_shape(ShapeCoef<T> C, Site2D<T> Q, LLGArgs<T> A, TileMap M,
+                                                      const int* __restrict__ abort_flag, const T* __restrict__ n,
+                                                      T* __restrict__ nout) {
+    if (abort_flag && *abort_flag) return;
+    constexpr int R = ShapeTab<S>::R;
+    constexpr int WN = TX + 4 * R, HN = TY + 4 * R;
+    constexpr int WP = TX + 2 * R, HP = TY + 2 * R;
+    constexpr int PN = WN * HN, PP = WP * HP, PT = TX * TY;
+    __shared__ T sN[3 * PN];
+    __shared__ T sP[3 * PP];
+    __shared__ T sA[3 * PT];
+    __shared__ T sB[3 * PT];
+
+    const int ntiles = M.tiles_x * M.tiles_y;
+    int tile = blockIdx.x;
+    if (M.xcd_bands) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+    const int ty0 = tile / M.tiles_x;
+    const int x0 = (tile - ty0 * M.tiles_x) * TX, y0 = ty0 * TY;
+    const int N = Q.na * Q.nb;
+    const int tid = threadIdx.x;
+
+    // 1) stage n(t) on the tile plus 2R halo
+    for (int idx = tid; idx < PN; idx += NT) {
+        const int ly = idx / WN, lx = idx - ly * WN;
+        bool in = true;
+        const int gx = wrap_once(x0 - 2 * R + lx, Q.na, Q.per_a, in);
+        const int gy = wrap_once(y0 - 2 * R + ly, Q.nb, Q.per_b, in);
+        T vx = T(0), vy = T(0), vz = T(0);
+        if (in) {
+            const int g = gx + gy * Q.na;
+            vx = n[g];
+            vy = n[N + g];
+            vz = n[2 * N + g];
+        }
+        sN[idx] = vx;
+        sN[PN + idx] = vy;
+        sN[2 * PN + idx] = vz;
+    }
+    __syncthreads();
+
+    // 2) predictor on the tile plus R halo
+    for (int idx = tid; idx < PP; idx += NT) {
+        const int py = idx / WP, px = idx - py * WP;
+        bool in = true;
+        const int gx = wrap_once(x0 - R + px, Q.na, Q.per_a, in);
+        const int gy = wrap_once(y0 - R + py, Q.nb, Q.per_b, in);
+        V3<T> out{T(0), T(0), T(0)};
+        if (in) {
+            const int c = (py + R) * WN + (px + R);
+            const V3<T> ni{sN[c], sN[PN + c], sN[2 * PN + c]};
+            const V3<T> g = shape_field<T, S, NDMI, WN>(C, Q, sN, sN + PN, sN + 2 * PN, c, ni);
+            V3<T> B = (-Q.inv_mumuB) * g;
+            V3<T> Bth{T(0), T(0), T(0)};
+            if (A.thermal) {
+                Bth = Q.sigma * normals3(thermal_bits(A.key, (uint32_t)(gx + gy * Q.na)), T(0));
+                B = B + Bth;
+            }
+            const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
+            // n^p only feeds the corrector's field; its FP32 length error
+            // (~1 ulp) is left in place, only n(t+dt) is renormalised.
+            out = rotate_fast(ni, T(-1) * Ai, A.dt);
+            const int tx = px - R, ty = py - R;
+            if (tx >= 0 && tx < TX && ty >= 0 && ty < TY) {
+                const int t = ty * TX + tx;
+                sA[t] = Ai.x; sA[PT + t] = Ai.y; sA[2 * PT + t] = Ai.z;
+                sB[t] = Bth.x; sB[PT + t] = Bth.y; sB[2 * PT + t] = Bth.z;
+            }
+        }
+        sP[idx] = out.x;
+        sP[PP + idx] = out.y;
+        sP[2 * PP + idx] = out.z;
+    }
+    __syncthreads();
+
+    // 3) corrector on the tile
+    for (int t = tid; t < PT; t += NT) {
+        const int ty = t / TX, tx = t - ty * TX;
+        const int gx = x0 + tx, gy = y0 + ty;
+        if (gx >= Q.na || gy >= Q.nb) continue;
+        const int c = (ty + R) * WP + (tx + R);
+        const V3<T> npi{sP[c], sP[PP + c], sP[2 * PP + c]};
+        const V3<T> g = shape_field<T, S, NDMI, WP>(C, Q, sP, sP + PP, sP + 2 * PP, c, npi);
+        const V3<T> B = (-Q.inv_mumuB) * g + V3<T>{sB[t], sB[PT + t], sB[2 * PT + t]};
+        const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
+        const V3<T> w{T(-0.5) * (sA[t] + Ap.x), T(-0.5) * (sA[PT + t] + Ap.y), T(-0.5) * (sA[2 * PT + t] + Ap.z)};
+        const int cn = (ty + 2 * R) * WN + (tx + 2 * R);
+        const V3<T> ni{sN[cn], sN[PN + cn], sN[2 * PN + cn]};
+        const V3<T> o = renorm_if_float(rotate_fast(ni, w, A.dt));
+        const int gi = gx + gy * Q.na;
+        nout[gi] = o.x;
+        nout[N + gi] = o.y;
+        nout[2 * N + gi] = o.z;
+    }
+}
+
+}  // namespace sp

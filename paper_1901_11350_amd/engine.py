@@ -30,7 +30,7 @@ EXPORTS = [
     "sp_set_spins_dev", "sp_get_spins_dev", "sp_set_step", "sp_get_step", "sp_gradient",
     "sp_gradient_dev", "sp_energy", "sp_observe", "sp_llg_step", "sp_run", "sp_synchronize",
     "sp_dipole_gradient", "sp_dipole_gradient_dev", "sp_thermal_normals", "sp_step_path",
-    "sp_set_step_path",
+    "sp_set_step_path", "sp_autotune",
 ]
 
 
@@ -106,6 +106,7 @@ def lib():
                                     ctypes.POINTER(ctypes.c_uint32)]),
         "sp_step_path": (ctypes.c_char_p, [vp]),
         "sp_set_step_path": (ci, [vp, ctypes.c_char_p]),
+        "sp_autotune": (ci, [vp, ctypes.POINTER(sp_llg_params), ci, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -273,6 +274,14 @@ class Engine:
             self._check(rc)
         res = [obs_dict(o) for o in obs[:n_obs]]
         return (res, rc) if not check else res
+
+    def autotune(self, alpha: float, dt: float, T: float = 0.0, seed: int = 0, n_steps: int = 50) -> float:
+        """Time every allowed step path / tile configuration, keep the fastest;
+        returns its milliseconds per step."""
+        p = sp_llg_params(alpha, dt, T, seed)
+        ms = ctypes.c_double()
+        self._check(lib().sp_autotune(self._h, ctypes.byref(p), n_steps, ctypes.byref(ms)))
+        return ms.value
 
     def synchronize(self):
         self._check(lib().sp_synchronize(self._h))

@@ -115,17 +115,60 @@ def test_depondt_steps_parity(ora, case, precision, T):
     assert e.step == 8
 
 
+PATH_CASES = {
+    "square32": (W["square32_fp64"].geometry, HAM0),
+    "tri40x24_ragged": (si.triangular(40, 24), HAM1),
+    "tri37x29_open": (si.triangular(37, 29, periodic=(0, 1, 0)), HAM1),
+    "sq45x33_2shell_nodmi": (si.square(45, 33), dataclasses.replace(HAM0, J=(1.0, 0.3), D=())),
+    "sq40x36_3shell_open": (si.square(40, 36, periodic=(1, 0, 0)), dataclasses.replace(HAM0, J=(1.0, 0.3, -0.1))),
+    "tri50x20_1shell": (si.triangular(50, 20), dataclasses.replace(HAM1, J=(1.0,), D=(0.2,))),
+    "tri66x34_2shell_bulk": (si.triangular(66, 34), dataclasses.replace(HAM1, J=(1.0, -0.3), D=(0.25,),
+                                                                        dmi_kind=si.DMI_BULK)),
+}
+SHAPE_CFGS = {"f32": ["32x16x256", "64x16x512", "32x16x512", "32x32x1024", "64x16x1024"],
+              "f64": ["32x16x256"]}
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("case", ["square32", "tri40x24_ragged", "tri37x29_open"])
-def test_fused_and_twopass_paths_agree_with_oracle(ora, case, precision):
+@pytest.mark.parametrize("case", sorted(PATH_CASES))
+def test_every_step_path_agrees_with_oracle(ora, case, precision):
+    """Every step path and tile configuration the lattice allows gives the
+    oracle's 4-step stochastic trajectory (ragged tiles, open edges)."""
+    geo, ham = PATH_CASES[case]
     announce(f"paths {case} {precision}")
+    e, s = make_pair(ora, geo, ham, precision)
+    assert e.step_path.startswith("shape2d"), e.step_path
+    n0 = si.uniform_sphere(s.N, 23)
+    n_ora, _ = s.run(n0, 0.3, 0.001, 4, T=25.0, seed=99, step0=5)
     res = {}
-    for path in ("fused2d", "twopass"):
-        e, s, n_gpu, n_ora = _step_case(ora, case, precision, 25.0, steps=4, path=path)
+    for path in ["twopass", "fused2d"] + ["shape2d/" + c for c in SHAPE_CFGS[precision]]:
+        e.step_path = path
         assert e.step_path == path
-        assert_close(n_gpu, n_ora, precision, what=f"{path} {case}")
-        res[path] = n_gpu
-    assert rel_err(res["fused2d"], res["twopass"]) <= 2 * TOL[precision]
+        e.set_spins(n0)
+        e.step = 5
+        e.run(0.3, 0.001, 4, T=25.0, seed=99)
+        res[path] = e.get_spins()
+        assert_close(res[path], n_ora, precision, what=f"{path} {case}")
+    for path in res:
+        assert rel_err(res[path], res["twopass"]) <= 2 * TOL[precision]
+
+
+def test_autotune_restores_state_and_picks_a_path(ora):
+    import paper_1901_11350_amd as pk
+
+    announce("autotune")
+    w = W["triangular512_sllg"]
+    e = pk.engine_for(w)
+    n0 = si.uniform_sphere(e.N, 1)
+    e.set_spins(n0)
+    e.step = 17
+    before = e.get_spins()
+    ms = e.autotune(w.dynamics.alpha, w.dynamics.dt, w.dynamics.T, w.dynamics.seed, n_steps=20)
+    assert ms > 0
+    assert e.step == 17
+    assert np.array_equal(e.get_spins(), before)
+    assert e.step_path in ["twopass", "fused2d"] + ["shape2d/" + c for c in SHAPE_CFGS["f32"]]
+    announce(f"autotune picked {e.step_path} at {ms:.4f} ms/step")
 
 
 def test_trajectory_square32_fp64_1000_steps(ora):
@@ -172,7 +215,7 @@ def test_full_size_triangular512_steps(ora):
     w = W["triangular512_sllg"]
     announce("full triangular512 10 steps")
     e, s = make_pair(ora, w.geometry, w.hamiltonian, "f32")
-    assert e.step_path == "fused2d"
+    assert e.step_path.startswith("shape2d")
     n0 = si.uniform_sphere(s.N, w.init_seed)
     e.set_spins(n0)
     d = w.dynamics
