@@ -69,8 +69,81 @@ def calibrate_copy(mib: int, reps: int = 5) -> None:
                       "GBps": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
 
 
+_STREAM = None
+
+
+def work_stream():
+    """One dedicated (non-default, default-priority) stream: the engines
+    launch every kernel on it and the timing events are recorded on it."""
+    global _STREAM
+    import torch
+
+    if _STREAM is None:
+        _STREAM = torch.cuda.Stream()
+        assert _STREAM.cuda_stream != 0
+    return _STREAM
+
+
+def bench_batch(args) -> dict:
+    """96 replicas (sides from {32, 64, 128, 256}, T uniform in 0-100 K, the
+    square32 Hamiltonian, FP32) advanced as one batch, against the same
+    replicas advanced one engine at a time."""
+    import torch
+
+    import paper_1901_11350_amd as pk
+    import spin_inputs as si
+    from spin_inputs.workloads import batch_replica_table
+
+    table = batch_replica_table(96, 11353)
+    ham = si.WORKLOADS["square32_fp64"].hamiltonian
+    alpha, dt, seed = 0.3, 0.001, 11353
+    stream = work_stream()
+    b = pk.Batch(0, stream=stream)
+    engines = []
+    for r, (L, T) in enumerate(table):
+        e = pk.Engine(0, "f32", stream=stream)
+        e.set_geometry(si.square(L, L))
+        e.set_hamiltonian(ham)
+        e.set_spins(si.uniform_sphere(e.N, 20000 + r))
+        b.add(e, alpha, dt, T=T, seed=seed, replica=r)
+        engines.append((e, T, r))
+    total = sum(L * L for L, _ in table)
+    b.set_chunk(args.batch_chunk)
+    tuned = b.autotune(8)
+    b.run(args.batch_chunk)
+    torch.cuda.synchronize()
+    K = args.batch_steps
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    b.run(K)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    # the same replicas, one engine (one launch per step each) at a time
+    Ks = max(10, K // 10)
+    for e, T, r in engines:
+        e.run(alpha, dt, 2, T=T, seed=seed, replica=r)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for e, T, r in engines:
+        e.run(alpha, dt, Ks, T=T, seed=seed, replica=r)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_sep = ev0.elapsed_time(ev1)
+    n_res = sum(1 for r in range(len(table)) if b.info(r)[1])
+    return {"workload": "batch96_square", "replicas": len(table), "resident_replicas": n_res,
+            "total_spins": total, "steps": K, "chunk": args.batch_chunk,
+            "spin_updates_per_s": total * K / (ms * 1e-3), "ms_per_step": ms / K,
+            "separate_engines_spin_updates_per_s": total * Ks / (ms_sep * 1e-3),
+            "batch_gain": (total * K / ms) / (total * Ks / ms_sep), "autotune_ms_per_step": tuned}
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--batch", action="store_true",
+                    help="also time the 96-replica batch (reported under 'batch')")
+    ap.add_argument("--batch-steps", type=int, default=256)
+    ap.add_argument("--batch-chunk", type=int, default=32)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="only run a device copy of this size (counter calibration)")
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,7 +172,7 @@ def main():
     w = si.WORKLOADS[args.workload]
     d = w.dynamics
     torch.cuda.init()
-    stream = torch.cuda.current_stream()
+    stream = work_stream()
     e = pk.engine_for(w, 0, w.precision, stream=stream)
     if w.init == "conical_helix":
         n0 = si.conical_helix(w.geometry, seed=w.init_seed)
@@ -170,6 +243,8 @@ def main():
         "wall_s": wall,
         "final_observation": {"E_per_spin": last["E"] / e.N, "max_norm_dev": last["max_norm_dev"]},
     }
+    if args.batch:
+        line["batch"] = bench_batch(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -90,6 +90,7 @@ typedef struct {
     double dt_ps;            /* time step, > 0 */
     double T_K;              /* temperature, >= 0 */
     uint64_t seed;           /* Philox key */
+    uint32_t replica;        /* Philox counter word 3 (replica index) */
 } sp_llg_params;
 
 /* Observables of one spin state.  per_term: Zeeman, anisotropy, exchange,
@@ -196,6 +197,43 @@ int sp_set_step_path(sp_engine *e, const char *name);
  * and the step counter are restored.  *ms_per_step (may be NULL) receives the
  * best time per step. */
 int sp_autotune(sp_engine *e, const sp_llg_params *p, int n_steps, double *ms_per_step);
+
+/* ------------------------------------------------------------------------
+ * Replica batches.  Many independent systems that share one Hamiltonian but
+ * differ in size, temperature, damping, time step and Philox replica index
+ * advance together: replicas small enough for one workgroup's LDS (32x32 and
+ * 64x64) stay resident in LDS for a whole chunk of steps; larger ones run as
+ * (replica, tile) work items of one launch per step.  A chunk of K steps is
+ * captured once as a HIP graph (resident branch in parallel with the K tiled
+ * launches) and replayed; the step number lives in device memory.  Small
+ * systems are otherwise bound by launch overhead, which the paper notes for
+ * its GPU back end at small sizes (Sec. II).  FP32 only.
+ * ------------------------------------------------------------------------ */
+typedef struct sp_batch sp_batch;
+
+int sp_batch_create(sp_batch **out, int device, void *hip_stream);
+void sp_batch_destroy(sp_batch *b);
+const char *sp_batch_last_error(const sp_batch *b);
+/* Add a replica taking geometry, Hamiltonian and current spins from engine e
+ * (FP32, one-atom 2D lattice whose bond table matches a compile-time
+ * stencil, spins set) and LLG parameters p (p->replica is its Philox replica
+ * index).  Every replica must have the same Hamiltonian.  The batch copies
+ * what it needs; e may be destroyed afterwards.  Returns the slot (>= 0) or a
+ * negative status.  No replica can be added after the first sp_batch_run. */
+int sp_batch_add(sp_batch *b, sp_engine *e, const sp_llg_params *p);
+/* Advance every replica by n_steps Depondt steps. */
+int sp_batch_run(sp_batch *b, int64_t n_steps);
+/* Spins of one replica (3N doubles, SoA). */
+int sp_batch_get_spins(sp_batch *b, int slot, double *n_soa, int64_t N);
+/* Size of one replica and whether it runs LDS-resident (1) or tiled (0). */
+int sp_batch_replica_info(sp_batch *b, int slot, int64_t *n_sites, int *resident);
+/* Graph chunk length in steps (even, 2..1024; default 32). */
+int sp_batch_set_chunk(sp_batch *b, int steps);
+/* Step number of the next batch step (shared by all replicas). */
+uint64_t sp_batch_get_step(const sp_batch *b);
+/* Times each tile configuration of the tiled kernel for n_steps steps,
+ * keeps the fastest, restores all replicas.  *ms_per_step may be NULL. */
+int sp_batch_autotune(sp_batch *b, int n_steps, double *ms_per_step);
 
 #ifdef __cplusplus
 }

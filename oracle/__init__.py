@@ -68,6 +68,11 @@ class LLGParams(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("replica", ctypes.c_uint32)]
 
 
+class GnebParams(ctypes.Structure):
+    _fields_ = [("k_spring", ctypes.c_double), ("vp_dt", ctypes.c_double),
+                ("vp_mass", ctypes.c_double)]
+
+
 class Observation(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("E", ctypes.c_double),
                 ("per_term", ctypes.c_double * 5), ("max_torque", ctypes.c_double),
@@ -117,6 +122,10 @@ def lib():
                               ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(Observation)]
         for name in ("ora_const_mu_B", "ora_const_k_B", "ora_const_gamma", "ora_const_C_dd"):
             getattr(L, name).restype = ctypes.c_double
+        L.ora_gneb_forces.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, ctypes.POINTER(GnebParams),
+                                      dp, dp, dp, dp]
+        L.ora_gneb_vp.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp, dp,
+                                  ctypes.POINTER(GnebParams), ctypes.c_int]
         L.ora_num_threads.restype = ctypes.c_int
         L.ora_num_threads.argtypes = []
         _lib = L
@@ -257,6 +266,35 @@ class System:
         obs = (Observation * max(n_obs, 1))()
         k = lib().ora_run(self._p, _dp(n), ctypes.byref(p), step0, n_steps, observe_every, obs)
         return n, [_obs_dict(o) for o in obs[:k]]
+
+
+class Gneb:
+    """GNEB chain on an oracle system: forces and velocity-projection
+    iterations (state: chain, velocity, previous force)."""
+
+    def __init__(self, system: "System", chain, k_spring=1.0, vp_dt=0.1, vp_mass=1.0):
+        self.s = system
+        self.chain = np.ascontiguousarray(chain, dtype=np.float64).reshape(-1, 3, system.N).copy()
+        self.M = self.chain.shape[0]
+        self.p = GnebParams(k_spring, vp_dt, vp_mass)
+        self.v = np.zeros_like(self.chain)
+        f = self.forces()
+        self.F_prev = f["F"].copy()
+
+    def forces(self, chain=None) -> dict:
+        c = self.chain if chain is None else np.ascontiguousarray(chain, dtype=np.float64)
+        M, N = self.M, self.s.N
+        E = np.zeros(M)
+        tau = np.zeros((M, 3, N))
+        l = np.zeros(max(M - 1, 1))
+        F = np.zeros((M, 3, N))
+        lib().ora_gneb_forces(self.s._p, M, _dp(c), ctypes.byref(self.p), _dp(E), _dp(tau),
+                              _dp(l), _dp(F))
+        return {"E": E, "tau": tau, "l": l[: M - 1], "F": F}
+
+    def iterate(self, n_iter: int):
+        lib().ora_gneb_vp(self.s._p, self.M, _dp(self.chain), _dp(self.v), _dp(self.F_prev),
+                          ctypes.byref(self.p), n_iter)
 
 
 def _obs_dict(o: Observation) -> dict:

@@ -592,3 +592,130 @@ int64_t ora_run(const ora_system *s, double *n, const ora_llg_params *p, uint64_
     }
     return n_obs;
 }
+
+/* ------------------------------------------------------------------ GNEB
+ * Geodesic nudged elastic band (Sec. III.D, Appendices D and F). */
+
+/* Great-circle angle between two unit vectors. */
+static double geodesic_angle(const double a[3], const double b[3]) {
+    double c[3];
+    cross3(a, b, c);
+    return atan2(norm3(c), dot3(a, b));
+}
+
+void ora_gneb_forces(const ora_system *s, int M, const double *chain, const ora_gneb_params *p,
+                     double *E, double *tau, double *l, double *F) {
+    const int64_t N = s->N, L = 3 * N;
+    double *g = (double *)malloc(sizeof(double) * (size_t)L);
+    for (int v = 0; v < M; ++v) E[v] = ora_energy(s, chain + v * L, NULL);
+    /* geodesic distance between neighbouring images (Appendix F): the
+     * Euclidean norm of the per-spin great-circle angles */
+    for (int v = 0; v + 1 < M; ++v) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
+            double a[3], b[3];
+            load(chain + v * L, N, i, a);
+            load(chain + (v + 1) * L, N, i, b);
+            double t = geodesic_angle(a, b);
+            acc += t * t;
+        }
+        l[v] = sqrt(acc);
+    }
+    for (int v = 0; v < M; ++v) {
+        double *tv = tau + v * L, *Fv = F + v * L;
+        if (v == 0 || v == M - 1) {
+            for (int64_t k = 0; k < L; ++k) { tv[k] = 0.0; Fv[k] = 0.0; }
+            continue;
+        }
+        const double *xm = chain + (v - 1) * L, *x0 = chain + v * L, *xp = chain + (v + 1) * L;
+        /* Reading: the tangent rule the paper cites (Henkelman and Jonsson's
+         * improved tangent) is not printed; its published form is used: the
+         * difference towards the higher-energy neighbour, and at an energy
+         * extremum an energy-weighted mix of both differences. */
+        const double Ep = E[v + 1], E0 = E[v], Em = E[v - 1];
+        double wp, wm;
+        if (Ep > E0 && E0 > Em) {
+            wp = 1.0; wm = 0.0;
+        } else if (Ep < E0 && E0 < Em) {
+            wp = 0.0; wm = 1.0;
+        } else {
+            double d1 = fabs(Ep - E0), d2 = fabs(Em - E0);
+            double dmax = d1 > d2 ? d1 : d2, dmin = d1 > d2 ? d2 : d1;
+            if (Ep > Em) { wp = dmax; wm = dmin; } else { wp = dmin; wm = dmax; }
+        }
+        for (int64_t k = 0; k < L; ++k) tv[k] = wp * (xp[k] - x0[k]) + wm * (x0[k] - xm[k]);
+        /* project onto the tangent plane of each spin, then normalise in 3N
+         * (Appendix F) */
+        double nrm = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
+            double n[3], t[3];
+            load(x0, N, i, n);
+            load(tv, N, i, t);
+            double tn = dot3(t, n);
+            for (int c = 0; c < 3; ++c) tv[c * N + i] = t[c] - tn * n[c];
+        }
+        for (int64_t k = 0; k < L; ++k) nrm += tv[k] * tv[k];
+        nrm = sqrt(nrm);
+        if (nrm > 0.0)
+            for (int64_t k = 0; k < L; ++k) tv[k] /= nrm;
+        /* energy force -grad E + (grad E . tau) tau, per-spin projected, plus
+         * the spring force.  Reading: the printed spring force
+         * (l_{v-1,v} - l_{v,v+1}) tau carries no spring constant and the sign
+         * that would push images apart; the usual form
+         * k (l_{v,v+1} - l_{v-1,v}) tau, which equalises the distances, is used. */
+        ora_gradient(s, x0, g, NULL);
+        double gt = 0.0;
+        for (int64_t k = 0; k < L; ++k) gt += g[k] * tv[k];
+        const double fs = p->k_spring * (l[v] - l[v - 1]);
+        for (int64_t i = 0; i < N; ++i) {
+            double n[3], fe[3];
+            load(x0, N, i, n);
+            for (int c = 0; c < 3; ++c) fe[c] = -g[c * N + i] + gt * tv[c * N + i];
+            double fn = dot3(fe, n);
+            for (int c = 0; c < 3; ++c) Fv[c * N + i] = fe[c] - fn * n[c] + fs * tv[c * N + i];
+        }
+    }
+    free(g);
+}
+
+/* Velocity projection (Appendix D): Verlet steps of massive particles with
+ * force F, the velocity projected on the force (3N-dimensional over the
+ * whole chain; zeroed when it points against the force), spins renormalised
+ * after every position update. */
+void ora_gneb_vp(const ora_system *s, int M, double *chain, double *v, double *F_prev,
+                 const ora_gneb_params *p, int n_iter) {
+    const int64_t N = s->N, L = 3 * N;
+    const double dt = p->vp_dt, m = p->vp_mass;
+    double *E = (double *)malloc(sizeof(double) * (size_t)M);
+    double *l = (double *)malloc(sizeof(double) * (size_t)(M > 1 ? M - 1 : 1));
+    double *tau = (double *)malloc(sizeof(double) * (size_t)(M * L));
+    double *F = (double *)malloc(sizeof(double) * (size_t)(M * L));
+    for (int it = 0; it < n_iter; ++it) {
+        for (int im = 1; im + 1 < M; ++im) {
+            double *x = chain + im * L, *vv = v + im * L, *fp = F_prev + im * L;
+            for (int64_t k = 0; k < L; ++k) x[k] = x[k] + dt * vv[k] + dt * dt / (2.0 * m) * fp[k];
+            for (int64_t i = 0; i < N; ++i) {
+                double n[3];
+                load(x, N, i, n);
+                double r = norm3(n);
+                for (int c = 0; c < 3; ++c) x[c * N + i] = n[c] / r;
+            }
+        }
+        ora_gneb_forces(s, M, chain, p, E, tau, l, F);
+        double vf = 0.0, ff = 0.0;
+        for (int64_t k = 0; k < M * L; ++k) {
+            v[k] = v[k] + dt / (2.0 * m) * (F_prev[k] + F[k]);
+            vf += v[k] * F[k];
+            ff += F[k] * F[k];
+        }
+        const double scale = (vf > 0.0 && ff > 0.0) ? vf / ff : 0.0;
+        for (int64_t k = 0; k < M * L; ++k) {
+            v[k] = scale * F[k];
+            F_prev[k] = F[k];
+        }
+    }
+    free(E);
+    free(l);
+    free(tau);
+    free(F);
+}

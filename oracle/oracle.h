@@ -121,6 +121,26 @@ void ora_observe(const ora_system *s, const double *n, int64_t step, ora_observa
 int64_t ora_run(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step0,
                 int64_t n_steps, int64_t observe_every, ora_observation *obs);
 
+/* ------------------------------------------------------------------ GNEB
+ * Chain of M images (image-major: image v occupies chain[v*3N .. v*3N+3N),
+ * each SoA).  Images 0 and M-1 are fixed. */
+typedef struct {
+    double k_spring;   /* spring constant (meV per rad) */
+    double vp_dt;      /* velocity-projection time step */
+    double vp_mass;    /* velocity-projection mass */
+} ora_gneb_params;
+
+/* GNEB forces of every interior image (endpoints get zero force):
+ * energies E[M], tangents tau[M*3N] (normalised in 3N, per-spin projected),
+ * distances l[M-1] (geodesic, between images v and v+1), forces F[M*3N]. */
+void ora_gneb_forces(const ora_system *s, int M, const double *chain, const ora_gneb_params *p,
+                     double *E, double *tau, double *l, double *F);
+/* n_iter velocity-projection iterations of the whole chain.  v and F_prev
+ * (M*3N each) carry the minimiser state between calls; pass F_prev computed
+ * by ora_gneb_forces and v = 0 to start. */
+void ora_gneb_vp(const ora_system *s, int M, double *chain, double *v, double *F_prev,
+                 const ora_gneb_params *p, int n_iter);
+
 /* OpenMP threads the oracle's parallel loops use. */
 int ora_num_threads(void);
 

@@ -7,6 +7,7 @@ direct sum, and double-precision observables.
 """
 
 from .engine import (  # noqa: F401
+    Batch,
     Engine,
     SpError,
     engine_for,

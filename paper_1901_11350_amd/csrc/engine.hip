@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "sp_engine.h"
@@ -362,7 +363,7 @@ template <typename T, int TX, int TY, int R>
 void launch_fused2d(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     dim3 grid((unsigned)((e->geo.n[0] + TX - 1) / TX), (unsigned)((e->geo.n[1] + TY - 1) / TY));
     hipLaunchKernelGGL((sp::k_depondt_fused2d<T, TX, TY, R>), grid, dim3(256), 0, e->stream, make_stencil2d<T>(e),
-                       make_site2d<T>(e, p), make_llg<T>(p, step, 0), e->d_flag, static_cast<const T*>(nin),
+                       make_site2d<T>(e, p), make_llg<T>(p, step, p->replica), e->d_flag, static_cast<const T*>(nin),
                        static_cast<T*>(nout));
 }
 
@@ -422,7 +423,7 @@ void go_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* n
     const int ntiles = M.tiles_x * M.tiles_y;
     M.xcd_bands = (ntiles >= 8 && ntiles % 8 == 0) ? 1 : 0;
     hipLaunchKernelGGL((sp::k_fused2d_shape<T, S, NDMI, TX, TY, NT>), dim3((unsigned)ntiles), dim3(NT), 0, e->stream,
-                       shape_coef_for<T, S>(e), make_site2d<T>(e, p), make_llg<T>(p, step, 0), M, e->d_flag,
+                       shape_coef_for<T, S>(e), make_site2d<T>(e, p), make_llg<T>(p, step, p->replica), M, e->d_flag,
                        static_cast<const T*>(nin), static_cast<T*>(nout));
 }
 
@@ -479,7 +480,7 @@ int launch_step(sp_engine* e, const sp_llg_params* p, uint64_t step, const void*
     const sp::Lattice L = make_lattice(e);
     const sp::BondCoef<T> C = make_coef<T>(e);
     const sp::Phys<T> P = make_phys<T>(e, p);
-    const sp::LLGArgs<T> A = make_llg<T>(p, step, 0);
+    const sp::LLGArgs<T> A = make_llg<T>(p, step, p->replica);
     const void* gdd = nullptr;
     const void* gddp = nullptr;
     if (e->ham.ddi) {
@@ -870,7 +871,9 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
     // sit on the first shell only, and every DMI vector must be in-plane
     e->shape = -1;
     e->shape_ndmi = 0;
-    e->tile_cfg = 0;
+    // default tile: 64x16 sites, one site per thread (fastest measured on the
+    // 512^2 triangular workload); FP64 has a single configuration
+    e->tile_cfg = e->precision == SP_F64 ? 0 : 4;
     if (fused) {
         bool ok = true;
         for (const HostBond& b : all_bonds)
@@ -1153,6 +1156,442 @@ int sp_autotune(sp_engine* e, const sp_llg_params* p, int n_steps, double* ms_pe
     dfree(backup);
     e->step = keep_step;
     const int rc2 = sp_set_step_path(e, out == SP_OK ? best_name.c_str() : keep_label.c_str());
+    if (out == SP_OK && ms_per_step) *ms_per_step = best;
+    return out != SP_OK ? out : rc2;
+}
+
+}  // extern "C"
+
+// ====================================================================== batch
+namespace {
+
+constexpr TileCfg kBatchCfgs[] = {{"32x16x512", 32, 16, 512}, {"64x16x1024", 64, 16, 1024}};
+constexpr int kNumBatchCfgs = 2;
+
+struct BatchRep {
+    int na, nb, per_a, per_b;
+    sp_llg_params p;
+    int resident;        // 0 tiled, 32 or 64: resident replica side
+    size_t off;          // offset (floats) of buffer 0 in the arena; buffer 1 follows
+    std::vector<float> init;
+};
+
+}  // namespace
+
+struct sp_batch {
+    int device = 0;
+    hipStream_t stream = nullptr, side = nullptr;
+    bool own_stream = false;
+    std::string err;
+    bool has_template = false;
+    HostHam ham{};
+    std::vector<HostBond> all_bonds;
+    int n_shells = 0, shape = -1, shape_ndmi = 0;
+    sp::ShapeCoef<float> C{};
+    sp::Site2D<float> Q{};
+    std::vector<BatchRep> reps;
+    bool finalized = false;
+    float* arena = nullptr;
+    size_t arena_floats = 0;
+    sp::ReplicaDesc<float>* d_reps = nullptr;
+    int2* d_work = nullptr;
+    int n_work = 0;
+    int* d_res32 = nullptr;
+    int* d_res64 = nullptr;
+    int n_res32 = 0, n_res64 = 0;
+    unsigned long long* d_step = nullptr;
+    uint64_t step = 0;
+    int parity = 0;
+    int cfg = 0;
+    int chunk = 32;
+    hipGraphExec_t gexec = nullptr;
+    int g_parity = -1, g_cfg = -1, g_chunk = -1;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+};
+
+namespace {
+
+int bfail(sp_batch* b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                      \
+    do {                                                                                      \
+        hipError_t _s = (call);                                                               \
+        if (_s != hipSuccess)                                                                 \
+            return bfail((b), SP_E_HIP, std::string(#call) + ": " + hipGetErrorString(_s));   \
+    } while (0)
+
+bool same_ham(const HostHam& a, const HostHam& b) {
+    return std::memcmp(&a, &b, sizeof(HostHam)) == 0;
+}
+
+int batch_build_work(sp_batch* b) {
+    const TileCfg& tc = kBatchCfgs[b->cfg];
+    std::vector<sp::ReplicaDesc<float>> desc(b->reps.size());
+    std::vector<int2> work;
+    std::vector<int> r32, r64;
+    for (size_t r = 0; r < b->reps.size(); ++r) {
+        const BatchRep& R = b->reps[r];
+        sp::ReplicaDesc<float>& D = desc[r];
+        D.n[0] = b->arena + R.off;
+        D.n[1] = b->arena + R.off + 3 * (size_t)R.na * R.nb;
+        D.na = R.na;
+        D.nb = R.nb;
+        D.per_a = R.per_a;
+        D.per_b = R.per_b;
+        D.tiles_x = (R.na + tc.TX - 1) / tc.TX;
+        D.thermal = R.p.T_K > 0.0 ? 1 : 0;
+        const double mm = b->ham.mu[0] * kMuB;
+        D.sigma = R.p.T_K > 0.0 ? (float)std::sqrt(2.0 * R.p.alpha * kKB * R.p.T_K / (kGamma * mm * R.p.dt_ps)) : 0.0f;
+        D.gp = (float)(kGamma / (1.0 + R.p.alpha * R.p.alpha));
+        D.alpha = (float)R.p.alpha;
+        D.dt = (float)R.p.dt_ps;
+        D.seed_lo = (uint32_t)R.p.seed;
+        D.seed_hi = (uint32_t)(R.p.seed >> 32);
+        D.replica = R.p.replica;
+        if (R.resident == 32) {
+            r32.push_back((int)r);
+        } else if (R.resident == 64) {
+            r64.push_back((int)r);
+        } else {
+            const int tiles_y = (R.nb + tc.TY - 1) / tc.TY;
+            for (int t = 0; t < D.tiles_x * tiles_y; ++t) work.push_back(make_int2((int)r, t));
+        }
+    }
+    void* p = b->d_reps; dfree(p); b->d_reps = nullptr;
+    p = b->d_work; dfree(p); b->d_work = nullptr;
+    p = b->d_res32; dfree(p); b->d_res32 = nullptr;
+    p = b->d_res64; dfree(p); b->d_res64 = nullptr;
+    auto up = [&](auto*& dst, const void* src, size_t bytes) -> int {
+        void* q = nullptr;
+        if (bytes == 0) return SP_OK;
+        if (hipMalloc(&q, bytes) != hipSuccess) return bfail(b, SP_E_NOMEM, "batch table allocation failed");
+        if (hipMemcpy(q, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return bfail(b, SP_E_HIP, "batch table upload failed");
+        dst = static_cast<std::remove_reference_t<decltype(dst)>>(q);
+        return SP_OK;
+    };
+    int rc;
+    if ((rc = up(b->d_reps, desc.data(), desc.size() * sizeof(desc[0])))) return rc;
+    if ((rc = up(b->d_work, work.data(), work.size() * sizeof(int2)))) return rc;
+    if ((rc = up(b->d_res32, r32.data(), r32.size() * sizeof(int)))) return rc;
+    if ((rc = up(b->d_res64, r64.data(), r64.size() * sizeof(int)))) return rc;
+    b->n_work = (int)work.size();
+    b->n_res32 = (int)r32.size();
+    b->n_res64 = (int)r64.size();
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    return SP_OK;
+}
+
+int batch_finalize(sp_batch* b) {
+    if (b->finalized) return SP_OK;
+    if (b->reps.empty()) return bfail(b, SP_E_ORDER, "the batch has no replicas");
+    size_t total = 0;
+    for (BatchRep& R : b->reps) {
+        R.off = total;
+        total += 6 * (size_t)R.na * R.nb;
+    }
+    void* q = nullptr;
+    if (hipMalloc(&q, total * sizeof(float)) != hipSuccess) return bfail(b, SP_E_NOMEM, "batch arena allocation failed");
+    b->arena = static_cast<float*>(q);
+    b->arena_floats = total;
+    for (BatchRep& R : b->reps) {
+        BHIPCHK(b, hipMemcpy(b->arena + R.off, R.init.data(), R.init.size() * sizeof(float), hipMemcpyHostToDevice));
+        std::vector<float>().swap(R.init);
+    }
+    if (hipMalloc(&q, sizeof(unsigned long long)) != hipSuccess) return bfail(b, SP_E_NOMEM, "allocation failed");
+    b->d_step = static_cast<unsigned long long*>(q);
+    const unsigned long long s0 = b->step;
+    BHIPCHK(b, hipMemcpy(b->d_step, &s0, sizeof(s0), hipMemcpyHostToDevice));
+    int rc = batch_build_work(b);
+    if (rc) return rc;
+    b->finalized = true;
+    return SP_OK;
+}
+
+template <int S, int NDMI>
+void batch_launch_resident(sp_batch* b, hipStream_t s, int n_steps) {
+    if (b->n_res32)
+        hipLaunchKernelGGL((sp::k_batch_resident<float, S, NDMI, 32, 32, 1024>), dim3(b->n_res32), dim3(1024), 0, s,
+                           b->C, b->Q, b->d_reps, b->d_res32, b->d_step, n_steps);
+    if (b->n_res64)
+        hipLaunchKernelGGL((sp::k_batch_resident<float, S, NDMI, 64, 64, 1024>), dim3(b->n_res64), dim3(1024), 0, s,
+                           b->C, b->Q, b->d_reps, b->d_res64, b->d_step, n_steps);
+}
+
+template <int S, int NDMI>
+void batch_launch_tiled(sp_batch* b, hipStream_t s, int k, int parity) {
+    if (!b->n_work) return;
+    if (b->cfg == 1)
+        hipLaunchKernelGGL((sp::k_batch_tiled<float, S, NDMI, 64, 16, 1024>), dim3(b->n_work), dim3(1024), 0, s, b->C,
+                           b->Q, b->d_reps, b->d_work, b->d_step, k, parity);
+    else
+        hipLaunchKernelGGL((sp::k_batch_tiled<float, S, NDMI, 32, 16, 512>), dim3(b->n_work), dim3(512), 0, s, b->C,
+                           b->Q, b->d_reps, b->d_work, b->d_step, k, parity);
+}
+
+template <int S>
+void batch_chunk_shape(sp_batch* b, int n_steps, int parity) {
+    // resident replicas on the side stream, tiled steps on the main stream
+    (void)hipEventRecord(b->ev_fork, b->stream);
+    (void)hipStreamWaitEvent(b->side, b->ev_fork, 0);
+    if (b->shape_ndmi) batch_launch_resident<S, sp::ShapeTab<S>::NB0>(b, b->side, n_steps);
+    else batch_launch_resident<S, 0>(b, b->side, n_steps);
+    for (int k = 0; k < n_steps; ++k) {
+        if (b->shape_ndmi) batch_launch_tiled<S, sp::ShapeTab<S>::NB0>(b, b->stream, k, parity);
+        else batch_launch_tiled<S, 0>(b, b->stream, k, parity);
+    }
+    (void)hipEventRecord(b->ev_join, b->side);
+    (void)hipStreamWaitEvent(b->stream, b->ev_join, 0);
+    hipLaunchKernelGGL(sp::k_advance_step, dim3(1), dim3(64), 0, b->stream, b->d_step, n_steps);
+}
+
+// Enqueue one chunk of n_steps on b->stream (also used under graph capture).
+void batch_chunk(sp_batch* b, int n_steps, int parity) {
+    switch (b->shape) {
+        case sp::SH_SQ1: batch_chunk_shape<sp::SH_SQ1>(b, n_steps, parity); break;
+        case sp::SH_SQ2: batch_chunk_shape<sp::SH_SQ2>(b, n_steps, parity); break;
+        case sp::SH_SQ3: batch_chunk_shape<sp::SH_SQ3>(b, n_steps, parity); break;
+        case sp::SH_TRI1: batch_chunk_shape<sp::SH_TRI1>(b, n_steps, parity); break;
+        case sp::SH_TRI2: batch_chunk_shape<sp::SH_TRI2>(b, n_steps, parity); break;
+        default: batch_chunk_shape<sp::SH_TRI3>(b, n_steps, parity); break;
+    }
+}
+
+int batch_capture(sp_batch* b) {
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    batch_chunk(b, b->chunk, b->parity);
+    hipError_t s = hipStreamEndCapture(b->stream, &g);
+    if (s != hipSuccess) return bfail(b, SP_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(s));
+    s = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (s != hipSuccess) return bfail(b, SP_E_HIP, std::string("graph instantiation failed: ") + hipGetErrorString(s));
+    b->g_parity = b->parity;
+    b->g_cfg = b->cfg;
+    b->g_chunk = b->chunk;
+    return SP_OK;
+}
+
+int batch_advance(sp_batch* b, int64_t n_steps, bool use_graph) {
+    int64_t left = n_steps;
+    while (use_graph && left >= b->chunk) {
+        if (!b->gexec || b->g_parity != b->parity || b->g_cfg != b->cfg || b->g_chunk != b->chunk) {
+            int rc = batch_capture(b);
+            if (rc) return rc;
+        }
+        BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
+        left -= b->chunk;
+    }
+    while (left > 0) {
+        const int k = (int)std::min<int64_t>(left, 1024);
+        batch_chunk(b, k, b->parity);
+        BHIPCHK(b, hipGetLastError());
+        b->parity ^= (k & 1);
+        left -= k;
+    }
+    b->step += (uint64_t)n_steps;
+    return SP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sp_batch_create(sp_batch** out, int device, void* hip_stream) {
+    if (!out) return SP_E_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SP_E_HIP;
+    sp_batch* b = new (std::nothrow) sp_batch();
+    if (!b) return SP_E_NOMEM;
+    b->device = device;
+    if (hipSetDevice(device) != hipSuccess) { delete b; return SP_E_HIP; }
+    if (hip_stream) {
+        b->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) { delete b; return SP_E_HIP; }
+        b->own_stream = true;
+    }
+    if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess) {
+        sp_batch_destroy(b);
+        return SP_E_HIP;
+    }
+    *out = b;
+    return SP_OK;
+}
+
+void sp_batch_destroy(sp_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->side) (void)hipStreamSynchronize(b->side);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    void* p = b->arena; dfree(p);
+    p = b->d_reps; dfree(p);
+    p = b->d_work; dfree(p);
+    p = b->d_res32; dfree(p);
+    p = b->d_res64; dfree(p);
+    p = b->d_step; dfree(p);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+const char* sp_batch_last_error(const sp_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+int sp_batch_add(sp_batch* b, sp_engine* e, const sp_llg_params* p) {
+    if (!b || !e) return SP_E_ARG;
+    if (b->finalized) return bfail(b, SP_E_ORDER, "replicas cannot be added after the first sp_batch_run");
+    if (!e->has_geo || !e->has_ham || !e->has_spins) return bfail(b, SP_E_ORDER, "engine has no lattice or spins");
+    if (e->precision != SP_F32) return bfail(b, SP_E_UNSUPPORTED, "batches are FP32");
+    if (e->shape < 0) return bfail(b, SP_E_UNSUPPORTED, "replica lattice does not match a compile-time stencil");
+    if (check_llg(e, p)) return bfail(b, SP_E_ARG, e->err);
+    if (!b->has_template) {
+        b->ham = e->ham;
+        b->all_bonds = e->all_bonds;
+        b->n_shells = e->n_shells;
+        b->shape = e->shape;
+        b->shape_ndmi = e->shape_ndmi;
+        switch (e->shape) {
+            case sp::SH_SQ1: b->C = shape_coef_for<float, sp::SH_SQ1>(e); break;
+            case sp::SH_SQ2: b->C = shape_coef_for<float, sp::SH_SQ2>(e); break;
+            case sp::SH_SQ3: b->C = shape_coef_for<float, sp::SH_SQ3>(e); break;
+            case sp::SH_TRI1: b->C = shape_coef_for<float, sp::SH_TRI1>(e); break;
+            case sp::SH_TRI2: b->C = shape_coef_for<float, sp::SH_TRI2>(e); break;
+            default: b->C = shape_coef_for<float, sp::SH_TRI3>(e); break;
+        }
+        b->Q = make_site2d<float>(e, nullptr);
+        b->has_template = true;
+    } else if (!same_ham(b->ham, e->ham) || b->shape != e->shape || b->shape_ndmi != e->shape_ndmi) {
+        return bfail(b, SP_E_ARG, "every replica of a batch must have the same Hamiltonian and stencil");
+    }
+    BatchRep R{};
+    R.na = e->geo.n[0];
+    R.nb = e->geo.n[1];
+    R.per_a = e->geo.per[0];
+    R.per_b = e->geo.per[1];
+    R.p = *p;
+    R.resident = 0;
+    if (R.na == R.nb && (R.na == 32 || R.na == 64)) R.resident = R.na;
+    R.init.resize(6 * (size_t)e->N);
+    (void)hipSetDevice(e->device);
+    if (hipStreamSynchronize(e->stream) != hipSuccess ||
+        hipMemcpy(R.init.data(), e->d_n, 3 * (size_t)e->N * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return bfail(b, SP_E_HIP, "copying the replica's spins failed");
+    std::copy(R.init.begin(), R.init.begin() + 3 * (size_t)e->N, R.init.begin() + 3 * (size_t)e->N);
+    b->reps.push_back(std::move(R));
+    return (int)b->reps.size() - 1;
+}
+
+int sp_batch_run(sp_batch* b, int64_t n_steps) {
+    if (!b) return SP_E_ARG;
+    if (n_steps < 0) return bfail(b, SP_E_ARG, "n_steps must be >= 0");
+    (void)hipSetDevice(b->device);
+    int rc = batch_finalize(b);
+    if (rc) return rc;
+    return batch_advance(b, n_steps, true);
+}
+
+int sp_batch_get_spins(sp_batch* b, int slot, double* n_soa, int64_t N) {
+    if (!b) return SP_E_ARG;
+    if (slot < 0 || slot >= (int)b->reps.size()) return bfail(b, SP_E_ARG, "replica slot out of range");
+    const BatchRep& R = b->reps[slot];
+    const int64_t n = (int64_t)R.na * R.nb;
+    if (!n_soa || N != n) return bfail(b, SP_E_ARG, "spin array size differs from the replica's size");
+    std::vector<float> tmp(3 * (size_t)n);
+    if (!b->finalized) {
+        std::copy(R.init.begin(), R.init.begin() + 3 * n, tmp.begin());
+    } else {
+        (void)hipSetDevice(b->device);
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+        const int buf = R.resident ? 0 : b->parity;
+        BHIPCHK(b, hipMemcpy(tmp.data(), b->arena + R.off + (size_t)buf * 3 * n, 3 * n * sizeof(float),
+                             hipMemcpyDeviceToHost));
+    }
+    for (int64_t k = 0; k < 3 * n; ++k) n_soa[k] = tmp[k];
+    return SP_OK;
+}
+
+int sp_batch_replica_info(sp_batch* b, int slot, int64_t* n_sites, int* resident) {
+    if (!b) return SP_E_ARG;
+    if (slot < 0 || slot >= (int)b->reps.size()) return bfail(b, SP_E_ARG, "replica slot out of range");
+    if (n_sites) *n_sites = (int64_t)b->reps[slot].na * b->reps[slot].nb;
+    if (resident) *resident = b->reps[slot].resident ? 1 : 0;
+    return SP_OK;
+}
+
+int sp_batch_set_chunk(sp_batch* b, int steps) {
+    if (!b) return SP_E_ARG;
+    if (steps < 2 || steps > 1024 || (steps & 1)) return bfail(b, SP_E_ARG, "chunk must be even and in 2..1024");
+    b->chunk = steps;
+    return SP_OK;
+}
+
+uint64_t sp_batch_get_step(const sp_batch* b) { return b ? b->step : 0; }
+
+int sp_batch_autotune(sp_batch* b, int n_steps, double* ms_per_step) {
+    if (!b) return SP_E_ARG;
+    if (n_steps < 2 || n_steps > 1024 || (n_steps & 1)) return bfail(b, SP_E_ARG, "n_steps must be even, 2..1024");
+    (void)hipSetDevice(b->device);
+    int rc = batch_finalize(b);
+    if (rc) return rc;
+    void* backup = nullptr;
+    if (hipMalloc(&backup, b->arena_floats * sizeof(float)) != hipSuccess)
+        return bfail(b, SP_E_NOMEM, "autotune backup allocation failed");
+    const uint64_t keep_step = b->step;
+    const int keep_parity = b->parity;
+    double best = 1e300;
+    int best_cfg = b->cfg;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    int out = SP_OK;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess ||
+        hipMemcpy(backup, b->arena, b->arena_floats * sizeof(float), hipMemcpyDeviceToDevice) != hipSuccess)
+        out = bfail(b, SP_E_HIP, "autotune set-up failed");
+    for (int c = 0; out == SP_OK && c < kNumBatchCfgs; ++c) {
+        b->cfg = c;
+        if ((out = batch_build_work(b))) break;
+        float ms = 0.0f;
+        batch_chunk(b, 2, b->parity);  // warm-up
+        if (hipEventRecord(t0, b->stream) != hipSuccess) { out = SP_E_HIP; break; }
+        batch_chunk(b, n_steps, b->parity);
+        if (hipEventRecord(t1, b->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+            hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+            out = bfail(b, SP_E_HIP, "autotune timing failed");
+            break;
+        }
+        if (ms / n_steps < best) {
+            best = ms / n_steps;
+            best_cfg = c;
+        }
+        // restore replicas and the device step counter
+        const unsigned long long s0 = keep_step;
+        if (hipMemcpy(b->arena, backup, b->arena_floats * sizeof(float), hipMemcpyDeviceToDevice) != hipSuccess ||
+            hipMemcpy(b->d_step, &s0, sizeof(s0), hipMemcpyHostToDevice) != hipSuccess) {
+            out = bfail(b, SP_E_HIP, "autotune restore failed");
+            break;
+        }
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    (void)hipFree(backup);
+    b->step = keep_step;
+    b->parity = keep_parity;
+    b->cfg = best_cfg;
+    const int rc2 = batch_build_work(b);
     if (out == SP_OK && ms_per_step) *ms_per_step = best;
     return out != SP_OK ? out : rc2;
 }

@@ -167,25 +167,29 @@ __device__ __forceinline__ int wrap_once(int g, int n, int per, bool& in) {
     return g;
 }
 
-template <typename T, int S, int NDMI, int TX, int TY, int NT>
-__global__ void __launch_bounds__(NT) k_fused2d_shape(ShapeCoef<T> C, Site2D<T> Q, LLGArgs<T> A, TileMap M,
-                                                      const int* __restrict__ abort_flag, const T* __restrict__ n,
-                                                      T* __restrict__ nout) {
-    if (abort_flag && *abort_flag) return;
-    constexpr int R = ShapeTab<S>::R;
-    constexpr int WN = TX + 4 * R, HN = TY + 4 * R;
-    constexpr int WP = TX + 2 * R, HP = TY + 2 * R;
-    constexpr int PN = WN * HN, PP = WP * HP, PT = TX * TY;
-    __shared__ T sN[3 * PN];
-    __shared__ T sP[3 * PP];
-    __shared__ T sA[3 * PT];
-    __shared__ T sB[3 * PT];
+template <typename T, int S, int TX, int TY>
+struct TileLDS {
+    static constexpr int R = ShapeTab<S>::R;
+    static constexpr int WN = TX + 4 * R, HN = TY + 4 * R;
+    static constexpr int WP = TX + 2 * R, HP = TY + 2 * R;
+    static constexpr int PN = WN * HN, PP = WP * HP, PT = TX * TY;
+    T sN[3 * PN];
+    T sP[3 * PP];
+    T sA[3 * PT];
+    T sB[3 * PT];
+};
 
-    const int ntiles = M.tiles_x * M.tiles_y;
-    int tile = blockIdx.x;
-    if (M.xcd_bands) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
-    const int ty0 = tile / M.tiles_x;
-    const int x0 = (tile - ty0 * M.tiles_x) * TX, y0 = ty0 * TY;
+// One Depondt step of the TX x TY tile at (x0, y0) of one lattice.
+template <typename T, int S, int NDMI, int TX, int TY, int NT>
+__device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A,
+                                             int x0, int y0, const T* __restrict__ n, T* __restrict__ nout,
+                                             TileLDS<T, S, TX, TY>& L) {
+    using TL = TileLDS<T, S, TX, TY>;
+    constexpr int R = TL::R, WN = TL::WN, WP = TL::WP, PN = TL::PN, PP = TL::PP, PT = TL::PT;
+    T* sN = L.sN;
+    T* sP = L.sP;
+    T* sA = L.sA;
+    T* sB = L.sB;
     const int N = Q.na * Q.nb;
     const int tid = threadIdx.x;
 
@@ -261,6 +265,202 @@ __global__ void __launch_bounds__(NT) k_fused2d_shape(ShapeCoef<T> C, Site2D<T> 
         nout[N + gi] = o.y;
         nout[2 * N + gi] = o.z;
     }
+}
+
+template <typename T, int S, int NDMI, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_fused2d_shape(ShapeCoef<T> C, Site2D<T> Q, LLGArgs<T> A, TileMap M,
+                                                      const int* __restrict__ abort_flag, const T* __restrict__ n,
+                                                      T* __restrict__ nout) {
+    if (abort_flag && *abort_flag) return;
+    __shared__ TileLDS<T, S, TX, TY> L;
+    const int ntiles = M.tiles_x * M.tiles_y;
+    int tile = blockIdx.x;
+    if (M.xcd_bands) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+    const int ty0 = tile / M.tiles_x;
+    fused2d_tile<T, S, NDMI, TX, TY, NT>(C, Q, A, (tile - ty0 * M.tiles_x) * TX, ty0 * TY, n, nout, L);
+}
+
+// ------------------------------------------------------------ replica batch
+// Many independent replicas that share one Hamiltonian (same stencil and
+// coefficients) but differ in size, temperature, damping, time step and
+// Philox replica index.
+template <typename T>
+struct ReplicaDesc {
+    T* n[2];          // spin buffers (double-buffered for tiled replicas)
+    int na, nb, per_a, per_b;
+    int tiles_x;      // tiled replicas: tiles along a
+    int thermal;
+    T sigma, gp, alpha, dt;
+    uint32_t seed_lo, seed_hi, replica;
+};
+
+template <typename T>
+__device__ __forceinline__ void replica_args(const ReplicaDesc<T>& R, unsigned long long step, Site2D<T>& Q,
+                                             LLGArgs<T>& A) {
+    Q.na = R.na;
+    Q.nb = R.nb;
+    Q.per_a = R.per_a;
+    Q.per_b = R.per_b;
+    Q.sigma = R.sigma;
+    A.gp = R.gp;
+    A.alpha = R.alpha;
+    A.dt = R.dt;
+    A.thermal = R.thermal;
+    A.key.seed_lo = R.seed_lo;
+    A.key.seed_hi = R.seed_hi;
+    A.key.step_lo = (uint32_t)step;
+    A.key.step_hi = (uint32_t)(step >> 32);
+    A.key.replica = R.replica;
+}
+
+// One Depondt step of every tile of every tiled replica: work item
+// (replica, tile) per workgroup.  The step number is *step_base + k, so a
+// captured graph of k = 0..K-1 can be replayed after step_base advances.
+template <typename T, int S, int NDMI, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_batch_tiled(ShapeCoef<T> C, Site2D<T> Q, const ReplicaDesc<T>* __restrict__ reps,
+                                                    const int2* __restrict__ work,
+                                                    const unsigned long long* __restrict__ step_base, int k,
+                                                    int parity) {
+    __shared__ TileLDS<T, S, TX, TY> L;
+    const int2 wk = work[blockIdx.x];
+    const ReplicaDesc<T> R = reps[wk.x];
+    LLGArgs<T> A;
+    replica_args(R, *step_base + (unsigned long long)k, Q, A);
+    const int ty0 = wk.y / R.tiles_x;
+    const bool odd = (parity ^ (k & 1)) != 0;
+    T* const b0 = R.n[0];
+    T* const b1 = R.n[1];
+    fused2d_tile<T, S, NDMI, TX, TY, NT>(C, Q, A, (wk.y - ty0 * R.tiles_x) * TX, ty0 * TY, odd ? b1 : b0,
+                                         odd ? b0 : b1, L);
+}
+
+// Resident replicas: one workgroup holds a whole LX x LY replica (plus an R
+// halo of periodic images) in LDS and advances it n_steps Depondt steps
+// without touching HBM in between.  Each thread owns the sites
+// tid + j*NT and keeps their rotation vector A and thermal field in
+// registers from predictor to corrector; the halo is refreshed after each
+// phase instead of recomputed.
+template <typename T, int S, int NDMI, int LX, int LY, int NT>
+__global__ void __launch_bounds__(NT) k_batch_resident(ShapeCoef<T> C, Site2D<T> Q,
+                                                       const ReplicaDesc<T>* __restrict__ reps,
+                                                       const int* __restrict__ list,
+                                                       const unsigned long long* __restrict__ step_base,
+                                                       int n_steps) {
+    constexpr int R = ShapeTab<S>::R;
+    constexpr int W = LX + 2 * R, H = LY + 2 * R, P = W * H, N = LX * LY;
+    constexpr int PER = (N + NT - 1) / NT;
+    __shared__ T sN[3 * P];
+    __shared__ T sP[3 * P];
+    const ReplicaDesc<T> Rp = reps[list[blockIdx.x]];
+    LLGArgs<T> A;
+    const unsigned long long base = *step_base;
+    replica_args(Rp, base, Q, A);
+    const int tid = threadIdx.x;
+    const T* __restrict__ gin = Rp.n[0];
+    T* __restrict__ gout = Rp.n[0];
+
+    // padded cell -> source interior site (or -1 for an open-boundary pad)
+    auto source_of = [&](int idx) -> int {
+        const int ly = idx / W, lx = idx - ly * W;
+        bool in = true;
+        const int gx = wrap_once(lx - R, LX, Q.per_a, in);
+        const int gy = wrap_once(ly - R, LY, Q.per_b, in);
+        return in ? gx + gy * LX : -1;
+    };
+    for (int idx = tid; idx < P; idx += NT) {
+        const int s = source_of(idx);
+        sN[idx] = s >= 0 ? gin[s] : T(0);
+        sN[P + idx] = s >= 0 ? gin[N + s] : T(0);
+        sN[2 * P + idx] = s >= 0 ? gin[2 * N + s] : T(0);
+        sP[idx] = T(0);
+        sP[P + idx] = T(0);
+        sP[2 * P + idx] = T(0);
+    }
+    __syncthreads();
+
+    V3<T> keepA[PER], keepB[PER];
+    for (int k = 0; k < n_steps; ++k) {
+        A.key.step_lo = (uint32_t)(base + k);
+        A.key.step_hi = (uint32_t)((base + k) >> 32);
+        // predictor on the interior
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int s = tid + j * NT;
+            if (s < N) {
+                const int y = s / LX, x = s - y * LX;
+                const int c = (y + R) * W + (x + R);
+                const V3<T> ni{sN[c], sN[P + c], sN[2 * P + c]};
+                const V3<T> g = shape_field<T, S, NDMI, W>(C, Q, sN, sN + P, sN + 2 * P, c, ni);
+                V3<T> B = (-Q.inv_mumuB) * g;
+                V3<T> Bth{T(0), T(0), T(0)};
+                if (A.thermal) {
+                    Bth = Q.sigma * normals3(thermal_bits(A.key, (uint32_t)s), T(0));
+                    B = B + Bth;
+                }
+                const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
+                keepA[j] = Ai;
+                keepB[j] = Bth;
+                const V3<T> o = rotate_fast(ni, T(-1) * Ai, A.dt);
+                sP[c] = o.x;
+                sP[P + c] = o.y;
+                sP[2 * P + c] = o.z;
+            }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < P; idx += NT) {   // periodic images of n^p
+            const int ly = idx / W, lx = idx - ly * W;
+            if (lx >= R && lx < R + LX && ly >= R && ly < R + LY) continue;
+            const int s = source_of(idx);
+            if (s < 0) continue;
+            const int c = (s / LX + R) * W + (s % LX + R);
+            sP[idx] = sP[c];
+            sP[P + idx] = sP[P + c];
+            sP[2 * P + idx] = sP[2 * P + c];
+        }
+        __syncthreads();
+        // corrector on the interior (each thread rewrites only its own sites of n)
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int s = tid + j * NT;
+            if (s < N) {
+                const int y = s / LX, x = s - y * LX;
+                const int c = (y + R) * W + (x + R);
+                const V3<T> npi{sP[c], sP[P + c], sP[2 * P + c]};
+                const V3<T> g = shape_field<T, S, NDMI, W>(C, Q, sP, sP + P, sP + 2 * P, c, npi);
+                const V3<T> B = (-Q.inv_mumuB) * g + keepB[j];
+                const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
+                const V3<T> w{T(-0.5) * (keepA[j].x + Ap.x), T(-0.5) * (keepA[j].y + Ap.y),
+                              T(-0.5) * (keepA[j].z + Ap.z)};
+                const V3<T> ni{sN[c], sN[P + c], sN[2 * P + c]};
+                const V3<T> o = renorm_if_float(rotate_fast(ni, w, A.dt));
+                sN[c] = o.x;
+                sN[P + c] = o.y;
+                sN[2 * P + c] = o.z;
+            }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < P; idx += NT) {   // periodic images of n
+            const int ly = idx / W, lx = idx - ly * W;
+            if (lx >= R && lx < R + LX && ly >= R && ly < R + LY) continue;
+            const int s = source_of(idx);
+            if (s < 0) continue;
+            const int c = (s / LX + R) * W + (s % LX + R);
+            sN[idx] = sN[c];
+            sN[P + idx] = sN[P + c];
+            sN[2 * P + idx] = sN[2 * P + c];
+        }
+        __syncthreads();
+    }
+    for (int s = tid; s < N; s += NT) {
+        const int c = (s / LX + R) * W + (s % LX + R);
+        gout[s] = sN[c];
+        gout[N + s] = sN[P + c];
+        gout[2 * N + s] = sN[2 * P + c];
+    }
+}
+
+__global__ void k_advance_step(unsigned long long* step_base, int k) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += (unsigned long long)k;
 }
 
 }  // namespace sp

@@ -31,6 +31,9 @@ EXPORTS = [
     "sp_gradient_dev", "sp_energy", "sp_observe", "sp_llg_step", "sp_run", "sp_synchronize",
     "sp_dipole_gradient", "sp_dipole_gradient_dev", "sp_thermal_normals", "sp_step_path",
     "sp_set_step_path", "sp_autotune",
+    "sp_batch_create", "sp_batch_destroy", "sp_batch_last_error", "sp_batch_add", "sp_batch_run",
+    "sp_batch_get_spins", "sp_batch_replica_info", "sp_batch_set_chunk", "sp_batch_get_step",
+    "sp_batch_autotune",
 ]
 
 
@@ -56,7 +59,7 @@ class sp_hamiltonian(ctypes.Structure):
 
 class sp_llg_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("dt_ps", ctypes.c_double),
-                ("T_K", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("T_K", ctypes.c_double), ("seed", ctypes.c_uint64), ("replica", ctypes.c_uint32)]
 
 
 class sp_observation(ctypes.Structure):
@@ -107,6 +110,16 @@ def lib():
         "sp_step_path": (ctypes.c_char_p, [vp]),
         "sp_set_step_path": (ci, [vp, ctypes.c_char_p]),
         "sp_autotune": (ci, [vp, ctypes.POINTER(sp_llg_params), ci, dp]),
+        "sp_batch_create": (ci, [ctypes.POINTER(vp), ci, vp]),
+        "sp_batch_destroy": (None, [vp]),
+        "sp_batch_last_error": (ctypes.c_char_p, [vp]),
+        "sp_batch_add": (ci, [vp, vp, ctypes.POINTER(sp_llg_params)]),
+        "sp_batch_run": (ci, [vp, i64]),
+        "sp_batch_get_spins": (ci, [vp, ci, dp, i64]),
+        "sp_batch_replica_info": (ci, [vp, ci, ctypes.POINTER(i64), ctypes.POINTER(ci)]),
+        "sp_batch_set_chunk": (ci, [vp, ci]),
+        "sp_batch_get_step": (u64, [vp]),
+        "sp_batch_autotune": (ci, [vp, ci, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -260,13 +273,13 @@ class Engine:
         self._check(lib().sp_observe(self._h, ctypes.byref(o)))
         return obs_dict(o)
 
-    def llg_step(self, alpha: float, dt: float, T: float = 0.0, seed: int = 0):
-        p = sp_llg_params(alpha, dt, T, seed)
+    def llg_step(self, alpha: float, dt: float, T: float = 0.0, seed: int = 0, replica: int = 0):
+        p = sp_llg_params(alpha, dt, T, seed, replica)
         self._check(lib().sp_llg_step(self._h, ctypes.byref(p)))
 
     def run(self, alpha: float, dt: float, n_steps: int, T: float = 0.0, seed: int = 0,
-            observe_every: int = 0, check: bool = True):
-        p = sp_llg_params(alpha, dt, T, seed)
+            observe_every: int = 0, check: bool = True, replica: int = 0):
+        p = sp_llg_params(alpha, dt, T, seed, replica)
         n_obs = n_steps // observe_every if observe_every > 0 else 0
         obs = (sp_observation * max(n_obs, 1))()
         rc = lib().sp_run(self._h, ctypes.byref(p), n_steps, observe_every, obs if n_obs else None)
@@ -291,6 +304,69 @@ class Engine:
         raw = (ctypes.c_uint32 * (4 * n_sites))()
         self._check(lib().sp_thermal_normals(self._h, seed, step, replica, site0, n_sites, _dp(eta), raw))
         return eta.reshape(3, n_sites), np.frombuffer(raw, dtype=np.uint32).reshape(n_sites, 4).copy()
+
+
+class Batch:
+    """A replica batch (``sp_batch``): replicas sharing one Hamiltonian advance
+    together (LDS-resident small replicas, tiled large ones, HIP-graph chunks)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = lib()
+        self._h = ctypes.c_void_p()
+        s = None
+        if stream is not None:
+            s = ctypes.c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+        rc = L.sp_batch_create(ctypes.byref(self._h), device, s)
+        if rc != SP_OK:
+            raise SpError(rc, "sp_batch_create failed (no HIP device?)")
+        self.sizes = []
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.sp_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc: int):
+        if rc < 0:
+            raise SpError(rc, lib().sp_batch_last_error(self._h).decode())
+        return rc
+
+    def add(self, engine: "Engine", alpha: float, dt: float, T: float = 0.0, seed: int = 0,
+            replica: int = 0) -> int:
+        p = sp_llg_params(alpha, dt, T, seed, replica)
+        slot = self._check(lib().sp_batch_add(self._h, engine._h, ctypes.byref(p)))
+        self.sizes.append(engine.N)
+        return slot
+
+    def run(self, n_steps: int):
+        self._check(lib().sp_batch_run(self._h, n_steps))
+
+    def get_spins(self, slot: int) -> np.ndarray:
+        n = self.sizes[slot]
+        out = np.zeros(3 * n)
+        self._check(lib().sp_batch_get_spins(self._h, slot, _dp(out), n))
+        return out.reshape(3, n)
+
+    def info(self, slot: int):
+        n = ctypes.c_int64()
+        r = ctypes.c_int()
+        self._check(lib().sp_batch_replica_info(self._h, slot, ctypes.byref(n), ctypes.byref(r)))
+        return int(n.value), bool(r.value)
+
+    def set_chunk(self, steps: int):
+        self._check(lib().sp_batch_set_chunk(self._h, steps))
+
+    @property
+    def step(self) -> int:
+        return int(lib().sp_batch_get_step(self._h))
+
+    def autotune(self, n_steps: int = 20) -> float:
+        ms = ctypes.c_double()
+        self._check(lib().sp_batch_autotune(self._h, n_steps, ctypes.byref(ms)))
+        return ms.value
 
 
 def engine_for(workload, device: int = 0, precision: Optional[str] = None, stream=None) -> Engine:

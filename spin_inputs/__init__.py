@@ -26,6 +26,7 @@ from .generators import (  # noqa: F401
     conical_helix,
     skyrmion_ansatz,
     domain_walls,
+    geodesic_chain,
     ferromagnet,
     spin_spiral,
     site_coords,

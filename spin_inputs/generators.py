@@ -108,6 +108,36 @@ def skyrmion_ansatz(geometry, radius: float = 5.0, center=None, helicity: float 
     return _tilt(_normalise(n), noise_rad, _rng(seed))
 
 
+def geodesic_chain(a: np.ndarray, b: np.ndarray, n_images: int,
+                   fallback_axis=(0.0, 1.0, 0.0)) -> np.ndarray:
+    """Initial GNEB chain: per spin, great-circle interpolation from a to b at
+    n_images equally spaced parameters (endpoints included).  Antiparallel
+    spins rotate about fallback_axis (projected perpendicular to the spin).
+    Returns (n_images, 3, N)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    ax = np.cross(a.T, b.T).T
+    s = np.linalg.norm(ax, axis=0)
+    c = np.sum(a * b, axis=0)
+    theta = np.arctan2(s, c)
+    fb = np.asarray(fallback_axis, dtype=np.float64)[:, None]
+    fb = fb - np.sum(fb * a, axis=0, keepdims=True) * a
+    small = s < 1e-12
+    axis = np.where(small[None, :], fb, ax)
+    axis = axis / np.linalg.norm(axis, axis=0, keepdims=True)
+    perp = np.cross(axis.T, a.T).T   # unit vector in the rotation plane, 90 deg ahead of a
+    out = np.empty((n_images,) + a.shape)
+    for k in range(n_images):
+        t = k / (n_images - 1)
+        out[k] = np.cos(t * theta)[None, :] * a + np.sin(t * theta)[None, :] * perp
+    out[-1] = b
+    return _normalise_chain(out)
+
+
+def _normalise_chain(c: np.ndarray) -> np.ndarray:
+    return c / np.linalg.norm(c, axis=1, keepdims=True)
+
+
 def domain_walls(geometry, n_walls: int = 1, seed: int = 0, bloch: bool = True,
                  width_range=(2.0, 8.0)) -> np.ndarray:
     """Parallel tanh domain walls at random positions/orientation/width."""
