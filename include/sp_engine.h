@@ -235,6 +235,38 @@ uint64_t sp_batch_get_step(const sp_batch *b);
  * keeps the fastest, restores all replicas.  *ms_per_step may be NULL. */
 int sp_batch_autotune(sp_batch *b, int n_steps, double *ms_per_step);
 
+/* ------------------------------------------------------------------------
+ * Geodesic nudged elastic band (Sec. III.D; Appendix F for the tangents,
+ * geodesic distances and per-spin projections; Appendix D for the
+ * velocity-projection minimiser).  Per interior image v the force is
+ *   F = -g + (g.t)t (then projected per spin onto the tangent plane)
+ *       + k (l_{v,v+1} - l_{v-1,v}) t,
+ * t the improved tangent (difference towards the higher-energy neighbour,
+ * energy-weighted at extrema), projected per spin and normalised in 3N;
+ * l the geodesic distance sqrt(sum_i angle(n_i, n'_i)^2).  Images 0 and M-1
+ * stay fixed.  The velocity projection runs chain-wide: Verlet steps of
+ * mass vp_mass and step vp_dt, v <- (v.F/|F|^2) F when v.F > 0 else 0, spins
+ * renormalised after each move.  Energies and all dot products are reduced
+ * in double precision.
+ * ------------------------------------------------------------------------ */
+typedef struct sp_gneb sp_gneb;
+
+/* Chain of n_images (>= 3) images on engine e's lattice and Hamiltonian (no
+ * dipole term), in e's precision.  chain: n_images*3N doubles, image-major,
+ * each image SoA; spins are normalised on input.  The chain borrows e: e
+ * must outlive it and keep its geometry and Hamiltonian. */
+int sp_gneb_create(sp_gneb **out, sp_engine *e, int n_images, const double *chain, double k_spring,
+                   double vp_dt, double vp_mass);
+void sp_gneb_destroy(sp_gneb *c);
+const char *sp_gneb_last_error(const sp_gneb *c);
+/* n_iter velocity-projection iterations. */
+int sp_gneb_iterate(sp_gneb *c, int n_iter);
+/* Current chain (n_images*3N doubles). */
+int sp_gneb_get_chain(sp_gneb *c, double *chain);
+/* Of the last force evaluation: image energies E[n_images], geodesic
+ * distances l[n_images-1], forces F[n_images*3N] (any may be NULL). */
+int sp_gneb_get_forces(sp_gneb *c, double *E, double *l, double *F);
+
 #ifdef __cplusplus
 }
 #endif

@@ -126,6 +126,15 @@ def lib():
                                       dp, dp, dp, dp]
         L.ora_gneb_vp.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp, dp,
                                   ctypes.POINTER(GnebParams), ctypes.c_int]
+        L.ora_bf16.restype = ctypes.c_double
+        L.ora_bf16.argtypes = [ctypes.c_double]
+        L.ora_conv_set_exact.argtypes = [ctypes.c_int]
+        ci = ctypes.c_int
+        L.ora_conv3x3_fwd.argtypes = [ci, ci, ci, ci, ci, dp, dp, dp, dp]
+        L.ora_conv3x3_bwd.argtypes = [ci, ci, ci, ci, ci, dp, dp, dp, dp, dp, dp]
+        L.ora_silu.argtypes = [ctypes.c_int64, dp, dp, dp]
+        L.ora_adam.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, ci]
         L.ora_num_threads.restype = ctypes.c_int
         L.ora_num_threads.argtypes = []
         _lib = L
@@ -295,6 +304,96 @@ class Gneb:
     def iterate(self, n_iter: int):
         lib().ora_gneb_vp(self.s._p, self.M, _dp(self.chain), _dp(self.v), _dp(self.F_prev),
                           ctypes.byref(self.p), n_iter)
+
+
+def bf16(x) -> np.ndarray:
+    """Round to bfloat16 (nearest even), as doubles."""
+    a = np.asarray(x, dtype=np.float64)
+    f = np.vectorize(lib().ora_bf16, otypes=[np.float64])
+    return f(a) if a.size else a.copy()
+
+
+class conv_exact:
+    """Context manager: the conv layers skip their bfloat16 rounding."""
+
+    def __enter__(self):
+        lib().ora_conv_set_exact(1)
+
+    def __exit__(self, *a):
+        lib().ora_conv_set_exact(0)
+
+
+def conv3x3_fwd(x, w, b) -> np.ndarray:
+    """x (B,H,W,Cin), w (3,3,Cin,Cout), b (Cout,) -> pre-activation (B,H,W,Cout)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    B, H, W, Cin = x.shape
+    Cout = w.shape[3]
+    z = np.zeros((B, H, W, Cout))
+    lib().ora_conv3x3_fwd(B, H, W, Cin, Cout, _dp(x), _dp(w), _dp(b), _dp(z))
+    return z
+
+
+def conv3x3_bwd(x, w, dz, need_dx=True):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    dz = np.ascontiguousarray(dz, dtype=np.float64)
+    B, H, W, Cin = x.shape
+    Cout = w.shape[3]
+    dx = np.zeros_like(x) if need_dx else None
+    dw = np.zeros_like(w)
+    db = np.zeros(Cout)
+    lib().ora_conv3x3_bwd(B, H, W, Cin, Cout, _dp(x), _dp(w), _dp(dz), _dp(dx) if need_dx else None,
+                          _dp(dw), _dp(db))
+    return dx, dw, db
+
+
+def silu(z):
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    y = np.zeros_like(z)
+    d = np.zeros_like(z)
+    lib().ora_silu(z.size, _dp(z), _dp(y), _dp(d))
+    return y, d
+
+
+def adam(p, m, v, g, lr, b1=0.9, b2=0.999, eps=1e-8, t=1):
+    """In-place Adam step on float64 arrays p, m, v."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    lib().ora_adam(p.size, _dp(p), _dp(m), _dp(v), _dp(g), lr, b1, b2, eps, t)
+
+
+class SurrogateNet:
+    """The surrogate network on the oracle: 3x3 convolutions with SiLU between
+    them, forward with stored pre-activations, and the gradient of the
+    per-sample relative squared error sum_b |y_b - t_b|^2 / |t_b|^2."""
+
+    def __init__(self, weights, biases):
+        self.w = [np.asarray(w, dtype=np.float64) for w in weights]
+        self.b = [np.asarray(b, dtype=np.float64) for b in biases]
+
+    def forward(self, x):
+        acts, zs = [np.asarray(x, dtype=np.float64)], []
+        for k, (w, b) in enumerate(zip(self.w, self.b)):
+            z = conv3x3_fwd(acts[-1], w, b)
+            zs.append(z)
+            if k + 1 < len(self.w):
+                acts.append(silu(z)[0])
+        self.acts, self.zs = acts, zs
+        return zs[-1]
+
+    def loss_and_grads(self, x, target):
+        y = self.forward(x)
+        B = y.shape[0]
+        nt = np.array([np.sum(target[b] ** 2) for b in range(B)])
+        loss = sum(np.sum((y[b] - target[b]) ** 2) / nt[b] for b in range(B))
+        dz = np.stack([2.0 * (y[b] - target[b]) / nt[b] for b in range(B)])
+        gw, gb = [None] * len(self.w), [None] * len(self.w)
+        for k in range(len(self.w) - 1, -1, -1):
+            dx, gw[k], gb[k] = conv3x3_bwd(self.acts[k], self.w[k], dz, need_dx=k > 0)
+            if k > 0:
+                dz = dx * silu(self.zs[k - 1])[1]
+        return loss, gw, gb
 
 
 def _obs_dict(o: Observation) -> dict:

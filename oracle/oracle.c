@@ -719,3 +719,113 @@ void ora_gneb_vp(const ora_system *s, int M, double *chain, double *v, double *F
     free(tau);
     free(F);
 }
+
+/* ------------------------------------------------- convolutional surrogate
+ * Not in the paper: a learned stand-in for the dipolar field.  Plain loops
+ * over the definitions of a zero-padded 3x3 cross-correlation, SiLU, and the
+ * Adam update. */
+
+/* When non-zero the conv layers skip the bfloat16 rounding of their
+ * operands (exact arithmetic), for finite-difference checks of the chain rule. */
+static int g_conv_exact = 0;
+void ora_conv_set_exact(int on) { g_conv_exact = on; }
+
+static double q16(double x);
+
+/* Round to bfloat16, nearest-even (8 significant bits). */
+double ora_bf16(double x) {
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    double m = frexp(x, &e);          /* x = m 2^e, 0.5 <= |m| < 1 */
+    double s = ldexp(m, 8);           /* 8 significant bits -> integer part */
+    double r = nearbyint(s);          /* default rounding mode: ties to even */
+    return ldexp(r, e - 8);
+}
+
+static double q16(double x) { return g_conv_exact ? x : ora_bf16(x); }
+
+void ora_conv3x3_fwd(int B, int H, int W, int Cin, int Cout, const double *x, const double *w,
+                     const double *bias, double *z) {
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int b = 0; b < B; ++b)
+        for (int y = 0; y < H; ++y)
+            for (int xx = 0; xx < W; ++xx)
+                for (int co = 0; co < Cout; ++co) {
+                    double acc = bias[co];
+                    for (int ky = 0; ky < 3; ++ky)
+                        for (int kx = 0; kx < 3; ++kx) {
+                            int sy = y + ky - 1, sx = xx + kx - 1;
+                            if (sy < 0 || sy >= H || sx < 0 || sx >= W) continue;
+                            for (int ci = 0; ci < Cin; ++ci)
+                                acc += q16(x[(((int64_t)b * H + sy) * W + sx) * Cin + ci]) *
+                                       q16(w[((ky * 3 + kx) * Cin + ci) * Cout + co]);
+                        }
+                    z[(((int64_t)b * H + y) * W + xx) * Cout + co] = acc;
+                }
+}
+
+/* Chain rule of the forward definition:
+ *   dL/dx[b,sy,sx,ci] = sum over (y,x,ky,kx,co) with sy = y+ky-1, sx = x+kx-1 of dz[b,y,x,co] w[ky,kx,ci,co]
+ *   dL/dw[ky,kx,ci,co] = sum over (b,y,x) of x[b,y+ky-1,x+kx-1,ci] dz[b,y,x,co]
+ *   dL/db[co]          = sum over (b,y,x) of dz[b,y,x,co] */
+void ora_conv3x3_bwd(int B, int H, int W, int Cin, int Cout, const double *x, const double *w,
+                     const double *dz, double *dx, double *dw, double *db) {
+    if (dx) {
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int b = 0; b < B; ++b)
+            for (int sy = 0; sy < H; ++sy)
+                for (int sx = 0; sx < W; ++sx)
+                    for (int ci = 0; ci < Cin; ++ci) {
+                        double acc = 0.0;
+                        for (int ky = 0; ky < 3; ++ky)
+                            for (int kx = 0; kx < 3; ++kx) {
+                                int y = sy - ky + 1, xx = sx - kx + 1;
+                                if (y < 0 || y >= H || xx < 0 || xx >= W) continue;
+                                for (int co = 0; co < Cout; ++co)
+                                    acc += q16(dz[(((int64_t)b * H + y) * W + xx) * Cout + co]) *
+                                           q16(w[((ky * 3 + kx) * Cin + ci) * Cout + co]);
+                            }
+                        dx[(((int64_t)b * H + sy) * W + sx) * Cin + ci] = acc;
+                    }
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < 9; ++k)
+        for (int ci = 0; ci < Cin; ++ci)
+            for (int co = 0; co < Cout; ++co) {
+                int ky = k / 3, kx = k % 3;
+                double acc = 0.0;
+                for (int b = 0; b < B; ++b)
+                    for (int y = 0; y < H; ++y)
+                        for (int xx = 0; xx < W; ++xx) {
+                            int sy = y + ky - 1, sx = xx + kx - 1;
+                            if (sy < 0 || sy >= H || sx < 0 || sx >= W) continue;
+                            acc += q16(x[(((int64_t)b * H + sy) * W + sx) * Cin + ci]) *
+                                   q16(dz[(((int64_t)b * H + y) * W + xx) * Cout + co]);
+                        }
+                dw[(k * Cin + ci) * Cout + co] = acc;
+            }
+    for (int co = 0; co < Cout; ++co) {
+        double acc = 0.0;
+        for (int64_t q = 0; q < (int64_t)B * H * W; ++q) acc += dz[q * Cout + co];
+        db[co] = acc;
+    }
+}
+
+void ora_silu(int64_t n, const double *z, double *y, double *dydz) {
+    for (int64_t k = 0; k < n; ++k) {
+        double s = 1.0 / (1.0 + exp(-z[k]));
+        if (y) y[k] = z[k] * s;
+        if (dydz) dydz[k] = s * (1.0 + z[k] * (1.0 - s));
+    }
+}
+
+void ora_adam(int64_t n, double *p, double *m, double *v, const double *g, double lr, double b1, double b2,
+              double eps, int t) {
+    double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    for (int64_t k = 0; k < n; ++k) {
+        m[k] = b1 * m[k] + (1.0 - b1) * g[k];
+        v[k] = b2 * v[k] + (1.0 - b2) * g[k] * g[k];
+        double mh = m[k] / c1, vh = v[k] / c2;
+        p[k] -= lr * mh / (sqrt(vh) + eps);
+    }
+}

@@ -141,6 +141,26 @@ void ora_gneb_forces(const ora_system *s, int M, const double *chain, const ora_
 void ora_gneb_vp(const ora_system *s, int M, double *chain, double *v, double *F_prev,
                  const ora_gneb_params *p, int n_iter);
 
+/* ------------------------------------------------- convolutional surrogate
+ * Layers of a 3x3 convolution, zero padding, NHWC activations
+ * x[B][H][W][Cin], weights w[ky][kx][Cin][Cout], bias b[Cout].  The kernels'
+ * contract is reproduced: activations, weights and back-propagated
+ * gradients are rounded to bfloat16 (round to nearest even) before they are
+ * multiplied; sums are exact (double) here. */
+double ora_bf16(double x);
+/* on != 0: the conv layers skip the bfloat16 rounding (exact arithmetic). */
+void ora_conv_set_exact(int on);
+void ora_conv3x3_fwd(int B, int H, int W, int Cin, int Cout, const double *x, const double *w,
+                     const double *bias, double *z);
+/* dz -> dx (may be NULL), dw, db (accumulated over batch and pixels). */
+void ora_conv3x3_bwd(int B, int H, int W, int Cin, int Cout, const double *x, const double *w,
+                     const double *dz, double *dx, double *dw, double *db);
+/* SiLU y = z / (1 + exp(-z)) and its derivative dy/dz. */
+void ora_silu(int64_t n, const double *z, double *y, double *dydz);
+/* Adam (Kingma and Ba) step t >= 1 on n parameters. */
+void ora_adam(int64_t n, double *p, double *m, double *v, const double *g, double lr, double b1, double b2,
+              double eps, int t);
+
 /* OpenMP threads the oracle's parallel loops use. */
 int ora_num_threads(void);
 

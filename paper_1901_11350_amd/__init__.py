@@ -9,6 +9,7 @@ direct sum, and double-precision observables.
 from .engine import (  # noqa: F401
     Batch,
     Engine,
+    Gneb,
     SpError,
     engine_for,
     lib,

@@ -16,6 +16,7 @@
 #include "kernels_reduce.hpp"
 #include "kernels_dipole.hpp"
 #include "kernels_fused2d.hpp"
+#include "kernels_gneb.hpp"
 
 namespace {
 
@@ -1594,6 +1595,221 @@ int sp_batch_autotune(sp_batch* b, int n_steps, double* ms_per_step) {
     const int rc2 = batch_build_work(b);
     if (out == SP_OK && ms_per_step) *ms_per_step = best;
     return out != SP_OK ? out : rc2;
+}
+
+}  // extern "C"
+
+// ======================================================================= GNEB
+struct sp_gneb {
+    sp_engine* e = nullptr;
+    int M = 0, N = 0, nblk = 0;
+    double k = 1.0, dt = 0.1, m = 1.0;
+    void *x = nullptr, *v = nullptr, *F = nullptr, *Fp = nullptr, *g = nullptr, *tau = nullptr;
+    double* part = nullptr;
+    double* E = nullptr;    // [M]
+    double* s3 = nullptr;   // [3M]: |tau|^2, g.tau, l^2
+    double* vf = nullptr;   // [2]
+    int64_t iterations = 0;
+    std::string err;
+};
+
+namespace {
+
+int gfail(sp_gneb* G, int code, const std::string& msg) {
+    if (G) G->err = msg;
+    return code;
+}
+
+template <typename T>
+int gneb_forces(sp_gneb* G, bool update_v) {
+    sp_engine* e = G->e;
+    const sp::GnebDims d{G->M, G->N, G->nblk};
+    const sp::Lattice L = make_lattice(e);
+    const sp::BondCoef<T> C = make_coef<T>(e);
+    const sp::Phys<T> P = make_phys<T>(e, nullptr);
+    T* x = static_cast<T*>(G->x);
+    T* g = static_cast<T*>(G->g);
+    T* tau = static_cast<T*>(G->tau);
+    hipLaunchKernelGGL((sp::k_gneb_grad<T>), dim3(G->nblk, G->M), dim3(256), 0, e->stream, d, L, C, P, x, g, G->part);
+    hipLaunchKernelGGL((sp::k_gneb_sum<1>), dim3(G->M), dim3(256), 0, e->stream, G->part, G->nblk, G->E);
+    hipLaunchKernelGGL((sp::k_gneb_tangent<T>), dim3(G->nblk, G->M), dim3(256), 0, e->stream, d, x, g, G->E, tau,
+                       G->part);
+    hipLaunchKernelGGL((sp::k_gneb_sum<3>), dim3(G->M), dim3(256), 0, e->stream, G->part, G->nblk, G->s3);
+    hipLaunchKernelGGL((sp::k_gneb_force<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, e->stream, d, (T)G->k,
+                       (T)(G->dt / (2.0 * G->m)), update_v ? 1 : 0, x, g, tau, G->s3, static_cast<T*>(G->F),
+                       static_cast<const T*>(G->Fp), static_cast<T*>(G->v), G->part);
+    if (update_v)
+        hipLaunchKernelGGL((sp::k_gneb_sum<2>), dim3(1), dim3(256), 0, e->stream, G->part, (G->M - 2) * G->nblk,
+                           G->vf);
+    hipError_t s = hipGetLastError();
+    if (s != hipSuccess) return gfail(G, SP_E_HIP, hipGetErrorString(s));
+    return SP_OK;
+}
+
+template <typename T>
+int gneb_project(sp_gneb* G) {
+    const sp::GnebDims d{G->M, G->N, G->nblk};
+    hipLaunchKernelGGL((sp::k_gneb_project<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, G->e->stream, d, G->vf,
+                       static_cast<T*>(G->v), static_cast<const T*>(G->F), static_cast<T*>(G->Fp));
+    hipError_t s = hipGetLastError();
+    if (s != hipSuccess) return gfail(G, SP_E_HIP, hipGetErrorString(s));
+    return SP_OK;
+}
+
+template <typename T>
+int gneb_iterate(sp_gneb* G, int n_iter) {
+    const sp::GnebDims d{G->M, G->N, G->nblk};
+    for (int it = 0; it < n_iter; ++it) {
+        hipLaunchKernelGGL((sp::k_gneb_move<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, G->e->stream, d, (T)G->dt,
+                           (T)(G->dt * G->dt / (2.0 * G->m)), static_cast<T*>(G->x), static_cast<const T*>(G->v),
+                           static_cast<const T*>(G->Fp));
+        int rc = gneb_forces<T>(G, true);
+        if (rc) return rc;
+        if ((rc = gneb_project<T>(G))) return rc;
+        ++G->iterations;
+    }
+    return SP_OK;
+}
+
+template <typename T>
+int gneb_upload(sp_gneb* G, const double* chain) {
+    const size_t L = (size_t)3 * G->N;
+    std::vector<T> h((size_t)G->M * L);
+    for (int im = 0; im < G->M; ++im)
+        for (int i = 0; i < G->N; ++i) {
+            const double* c = chain + im * L;
+            const double x = c[i], y = c[G->N + i], z = c[2 * G->N + i];
+            const double r = std::sqrt(x * x + y * y + z * z);
+            if (!(r > 0.0) || !std::isfinite(r)) return gfail(G, SP_E_ARG, "chain has a zero or non-finite spin");
+            h[im * L + i] = (T)(x / r);
+            h[im * L + G->N + i] = (T)(y / r);
+            h[im * L + 2 * G->N + i] = (T)(z / r);
+        }
+    if (hipMemcpy(G->x, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return gfail(G, SP_E_HIP, "chain upload failed");
+    return SP_OK;
+}
+
+template <typename T>
+int gneb_download(sp_gneb* G, const void* src, double* out, size_t count) {
+    std::vector<T> h(count);
+    if (hipStreamSynchronize(G->e->stream) != hipSuccess ||
+        hipMemcpy(h.data(), src, count * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess)
+        return gfail(G, SP_E_HIP, "download failed");
+    for (size_t k = 0; k < count; ++k) out[k] = (double)h[k];
+    return SP_OK;
+}
+
+void gneb_free(sp_gneb* G) {
+    void* ps[] = {G->x, G->v, G->F, G->Fp, G->g, G->tau, G->part, G->E, G->s3, G->vf};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sp_gneb_create(sp_gneb** out, sp_engine* e, int n_images, const double* chain, double k_spring, double vp_dt,
+                   double vp_mass) {
+    if (!out) return SP_E_ARG;
+    *out = nullptr;
+    int rc = check_ready(e, false);
+    if (rc) return rc;
+    if (e->ham.ddi) return fail(e, SP_E_UNSUPPORTED, "GNEB chains do not support the dipole term");
+    if (n_images < 3 || n_images > 4096 || !chain) return fail(e, SP_E_ARG, "a chain needs 3..4096 images");
+    if (!(vp_dt > 0.0) || !(vp_mass > 0.0) || !std::isfinite(k_spring) || !std::isfinite(vp_dt) ||
+        !std::isfinite(vp_mass))
+        return fail(e, SP_E_ARG, "VP time step and mass must be finite and > 0, spring constant finite");
+    sp_gneb* G = new (std::nothrow) sp_gneb();
+    if (!G) return SP_E_NOMEM;
+    G->e = e;
+    G->M = n_images;
+    G->N = e->N;
+    G->nblk = (e->N + 255) / 256;
+    G->k = k_spring;
+    G->dt = vp_dt;
+    G->m = vp_mass;
+    (void)hipSetDevice(e->device);
+    const size_t vb = (size_t)G->M * 3 * G->N * e->esz();
+    const size_t parts = std::max<size_t>((size_t)G->M * G->nblk * 3, (size_t)(G->M - 2) * G->nblk * 2);
+    void** bufs[] = {&G->x, &G->v, &G->F, &G->Fp, &G->g, &G->tau};
+    for (void** b : bufs)
+        if (hipMalloc(b, vb) != hipSuccess) { gneb_free(G); delete G; return fail(e, SP_E_NOMEM, "GNEB allocation failed"); }
+    if (hipMalloc((void**)&G->part, parts * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&G->E, G->M * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&G->s3, 3 * G->M * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&G->vf, 2 * sizeof(double)) != hipSuccess) {
+        gneb_free(G);
+        delete G;
+        return fail(e, SP_E_NOMEM, "GNEB allocation failed");
+    }
+    if (hipMemset(G->v, 0, vb) != hipSuccess || hipMemset(G->F, 0, vb) != hipSuccess ||
+        hipMemset(G->Fp, 0, vb) != hipSuccess || hipMemset(G->tau, 0, vb) != hipSuccess ||
+        hipMemset(G->vf, 0, 2 * sizeof(double)) != hipSuccess) {
+        gneb_free(G);
+        delete G;
+        return fail(e, SP_E_HIP, "GNEB initialisation failed");
+    }
+    rc = e->precision == SP_F64 ? gneb_upload<double>(G, chain) : gneb_upload<float>(G, chain);
+    if (rc == SP_OK) rc = e->precision == SP_F64 ? gneb_forces<double>(G, false) : gneb_forces<float>(G, false);
+    // v = 0 (vf = 0 gives a zero projection) and F_prev = F
+    if (rc == SP_OK) rc = e->precision == SP_F64 ? gneb_project<double>(G) : gneb_project<float>(G);
+    if (rc == SP_OK && hipStreamSynchronize(e->stream) != hipSuccess) rc = SP_E_HIP;
+    if (rc) {
+        e->err = G->err;
+        gneb_free(G);
+        delete G;
+        return rc;
+    }
+    *out = G;
+    return SP_OK;
+}
+
+void sp_gneb_destroy(sp_gneb* G) {
+    if (!G) return;
+    (void)hipSetDevice(G->e->device);
+    (void)hipStreamSynchronize(G->e->stream);
+    gneb_free(G);
+    delete G;
+}
+
+const char* sp_gneb_last_error(const sp_gneb* G) { return G ? G->err.c_str() : "null chain"; }
+
+int sp_gneb_iterate(sp_gneb* G, int n_iter) {
+    if (!G) return SP_E_ARG;
+    if (n_iter < 0) return gfail(G, SP_E_ARG, "n_iter must be >= 0");
+    (void)hipSetDevice(G->e->device);
+    const int rc = G->e->precision == SP_F64 ? gneb_iterate<double>(G, n_iter) : gneb_iterate<float>(G, n_iter);
+    if (rc) return rc;
+    if (hipStreamSynchronize(G->e->stream) != hipSuccess) return gfail(G, SP_E_HIP, "synchronisation failed");
+    return SP_OK;
+}
+
+int sp_gneb_get_chain(sp_gneb* G, double* chain) {
+    if (!G || !chain) return SP_E_ARG;
+    (void)hipSetDevice(G->e->device);
+    const size_t n = (size_t)G->M * 3 * G->N;
+    return G->e->precision == SP_F64 ? gneb_download<double>(G, G->x, chain, n) : gneb_download<float>(G, G->x, chain, n);
+}
+
+int sp_gneb_get_forces(sp_gneb* G, double* E, double* l, double* F) {
+    if (!G) return SP_E_ARG;
+    (void)hipSetDevice(G->e->device);
+    if (hipStreamSynchronize(G->e->stream) != hipSuccess) return gfail(G, SP_E_HIP, "synchronisation failed");
+    if (E && hipMemcpy(E, G->E, G->M * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return gfail(G, SP_E_HIP, "download failed");
+    if (l) {
+        std::vector<double> s3(3 * (size_t)G->M);
+        if (hipMemcpy(s3.data(), G->s3, s3.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+            return gfail(G, SP_E_HIP, "download failed");
+        for (int v = 0; v + 1 < G->M; ++v) l[v] = std::sqrt(s3[3 * v + 2]);
+    }
+    if (F) {
+        const size_t n = (size_t)G->M * 3 * G->N;
+        return G->e->precision == SP_F64 ? gneb_download<double>(G, G->Fp, F, n) : gneb_download<float>(G, G->Fp, F, n);
+    }
+    return SP_OK;
 }
 
 }  // extern "C"

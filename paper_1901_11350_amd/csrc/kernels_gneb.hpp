@@ -1,0 +1,214 @@
+// kernels_gneb.hpp -- geodesic nudged elastic band on the GPU (Sec. III.D;
+// Appendix F for tangents, distances and projections; Appendix D for the
+// velocity-projection minimiser).
+//
+// The chain holds M images of N spins, image-major, each image SoA.  Images 0
+// and M-1 are fixed.  Per velocity-projection iteration:
+//   k_gneb_move       x <- normalise(x + dt v + dt^2/(2m) F_prev)    (interior)
+//   k_gneb_grad       g = dH/dn per image, energy partials per block
+//   k_gneb_sum        E[v]                                             (FP64)
+//   k_gneb_tangent    improved tangent, per-spin projection; partials of
+//                     |tau|^2, g.tau, and squared geodesic angles to image v+1
+//   k_gneb_sum        |tau|^2[v], g.tau[v], l^2[v]
+//   k_gneb_force      F = -g + (g.t)t, per-spin projected, + k (l_v - l_{v-1}) t
+//                     with t = tau/|tau|; v <- v + dt/(2m)(F_prev + F);
+//                     chain-wide partials of v.F and F.F
+//   k_gneb_sum        v.F, F.F
+//   k_gneb_project    v <- (v.F/F.F) F if v.F > 0 else 0;  F_prev <- F
+// Every reduction is a fixed-order FP64 tree (bit-reproducible).
+#pragma once
+
+#include "kernels_field.hpp"
+#include "kernels_reduce.hpp"
+
+namespace sp {
+
+template <int NV>
+__device__ __forceinline__ void block_sums(double* acc) {
+    __shared__ double red[4][NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+    }
+}
+
+struct GnebDims {
+    int M;         // images
+    int N;         // spins per image
+    int nblk;      // blocks per image in the per-site kernels
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gneb_move(GnebDims d, T dt, T half_dt2_m, T* __restrict__ x,
+                                                   const T* __restrict__ v, const T* __restrict__ Fp) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int im = blockIdx.y + 1;   // interior images only
+    if (i >= d.N) return;
+    const size_t base = (size_t)im * 3 * d.N;
+    T n[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const size_t q = base + (size_t)c * d.N + i;
+        n[c] = x[q] + dt * v[q] + half_dt2_m * Fp[q];
+    }
+    const T r = T(1) / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[base + (size_t)c * d.N + i] = n[c] * r;
+}
+
+// Gradient of every image and per-block energy partials (Zeeman linear,
+// the other local terms quadratic: e_i = n.(g_Z + (g_K + g_J + g_D)/2)).
+template <typename T>
+__global__ void __launch_bounds__(256) k_gneb_grad(GnebDims d, Lattice L, BondCoef<T> C, Phys<T> P,
+                                                   const T* __restrict__ x, T* __restrict__ g,
+                                                   double* __restrict__ part) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int im = blockIdx.y;
+    const T* xi = x + (size_t)im * 3 * d.N;
+    double acc[1] = {0.0};
+    if (i < d.N) {
+        const V3<T> ni = load3(xi, d.N, i);
+        const FieldTerms<T> f = site_terms(L, C, P, xi, i, ni);
+        store3(g + (size_t)im * 3 * d.N, d.N, i, total(f));
+        const double nx = ni.x, ny = ni.y, nz = ni.z;
+        acc[0] = nx * f.z.x + ny * f.z.y + nz * f.z.z +
+                 0.5 * (nx * (f.k.x + f.j.x + f.d.x) + ny * (f.k.y + f.j.y + f.d.y) + nz * (f.k.z + f.j.z + f.d.z));
+    }
+    block_sums<1>(acc);
+    if (threadIdx.x == 0) part[(size_t)im * d.nblk + blockIdx.x] = acc[0];
+}
+
+// Sum NV-value partials of each of `rows` rows (blocks per row = nblk) in a
+// fixed order: out[row*NV + k].
+template <int NV>
+__global__ void __launch_bounds__(256) k_gneb_sum(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+    const int row = blockIdx.x;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] += part[((size_t)row * nblk + b) * NV + k];
+    }
+    block_sums<NV>(acc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) out[row * NV + k] = acc[k];
+    }
+}
+
+// Tangent of interior images (unnormalised, per-spin projected) and partials
+// of |tau|^2, g.tau and the squared great-circle angle to image im+1.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gneb_tangent(GnebDims d, const T* __restrict__ x, const T* __restrict__ g,
+                                                      const double* __restrict__ E, T* __restrict__ tau,
+                                                      double* __restrict__ part) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int im = blockIdx.y;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (i < d.N) {
+        const size_t L3 = (size_t)3 * d.N;
+        const V3<T> n0 = load3(x + im * L3, d.N, i);
+        if (im + 1 < d.M) {
+            const V3<T> n1 = load3(x + (im + 1) * L3, d.N, i);
+            const V3<T> c = cross(n0, n1);
+            const double ang = atan2((double)sqrt(dot(c, c)), (double)dot(n0, n1));
+            acc[2] = ang * ang;
+        }
+        if (im > 0 && im + 1 < d.M) {
+            const V3<T> nm = load3(x + (im - 1) * L3, d.N, i);
+            const V3<T> np = load3(x + (im + 1) * L3, d.N, i);
+            const double Ep = E[im + 1], E0 = E[im], Em = E[im - 1];
+            double wp, wm;
+            if (Ep > E0 && E0 > Em) {
+                wp = 1.0; wm = 0.0;
+            } else if (Ep < E0 && E0 < Em) {
+                wp = 0.0; wm = 1.0;
+            } else {
+                const double d1 = fabs(Ep - E0), d2 = fabs(Em - E0);
+                const double dmax = d1 > d2 ? d1 : d2, dmin = d1 > d2 ? d2 : d1;
+                if (Ep > Em) { wp = dmax; wm = dmin; } else { wp = dmin; wm = dmax; }
+            }
+            V3<T> t = T(wp) * (np - n0) + T(wm) * (n0 - nm);
+            t = t - dot(t, n0) * n0;
+            store3(tau + im * L3, d.N, i, t);
+            const V3<T> gi = load3(g + im * L3, d.N, i);
+            acc[0] = (double)dot(t, t);
+            acc[1] = (double)dot(gi, t);
+        }
+    }
+    block_sums<3>(acc);
+    if (threadIdx.x == 0) {
+        double* o = part + ((size_t)im * d.nblk + blockIdx.x) * 3;
+        o[0] = acc[0];
+        o[1] = acc[1];
+        o[2] = acc[2];
+    }
+}
+
+// Forces of interior images, velocity update, chain-wide v.F and F.F partials.
+// s3[v] = (|tau|^2, g.tau, l^2) from k_gneb_sum<3>.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gneb_force(GnebDims d, T k_spring, T dt_2m, int update_v,
+                                                    const T* __restrict__ x, const T* __restrict__ g,
+                                                    const T* __restrict__ tau, const double* __restrict__ s3,
+                                                    T* __restrict__ F, const T* __restrict__ Fp, T* __restrict__ v,
+                                                    double* __restrict__ part) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int im = blockIdx.y + 1;
+    double acc[2] = {0.0, 0.0};
+    if (i < d.N) {
+        const size_t off = (size_t)im * 3 * d.N;
+        const double tn2 = s3[im * 3 + 0];
+        const double inv = tn2 > 0.0 ? 1.0 / sqrt(tn2) : 0.0;
+        const T gt = (T)(s3[im * 3 + 1] * inv);
+        const T fs = (T)(k_spring * (sqrt(s3[im * 3 + 2]) - sqrt(s3[(im - 1) * 3 + 2])));
+        const V3<T> n = load3(x + off, d.N, i);
+        const V3<T> t = T(inv) * load3(tau + off, d.N, i);
+        const V3<T> gi = load3(g + off, d.N, i);
+        V3<T> fe = gt * t - gi;
+        fe = fe - dot(fe, n) * n;
+        const V3<T> f = fe + fs * t;
+        store3(F + off, d.N, i, f);
+        if (update_v) {
+            const V3<T> vn = load3(v + off, d.N, i) + dt_2m * (load3(Fp + off, d.N, i) + f);
+            store3(v + off, d.N, i, vn);
+            acc[0] = (double)dot(vn, f);
+        }
+        acc[1] = (double)dot(f, f);
+    }
+    block_sums<2>(acc);
+    if (threadIdx.x == 0) {
+        double* o = part + ((size_t)(im - 1) * d.nblk + blockIdx.x) * 2;
+        o[0] = acc[0];
+        o[1] = acc[1];
+    }
+}
+
+// Velocity projection: v <- (v.F / F.F) F if v.F > 0, else 0; F_prev <- F.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gneb_project(GnebDims d, const double* __restrict__ vf_ff,
+                                                      T* __restrict__ v, const T* __restrict__ F,
+                                                      T* __restrict__ Fp) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int im = blockIdx.y + 1;
+    if (i >= d.N) return;
+    const double vf = vf_ff[0], ff = vf_ff[1];
+    const T scale = (vf > 0.0 && ff > 0.0) ? (T)(vf / ff) : T(0);
+    const size_t off = (size_t)im * 3 * d.N;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const size_t q = off + (size_t)c * d.N + i;
+        v[q] = scale * F[q];
+        Fp[q] = F[q];
+    }
+}
+
+}  // namespace sp

@@ -34,6 +34,8 @@ EXPORTS = [
     "sp_batch_create", "sp_batch_destroy", "sp_batch_last_error", "sp_batch_add", "sp_batch_run",
     "sp_batch_get_spins", "sp_batch_replica_info", "sp_batch_set_chunk", "sp_batch_get_step",
     "sp_batch_autotune",
+    "sp_gneb_create", "sp_gneb_destroy", "sp_gneb_last_error", "sp_gneb_iterate",
+    "sp_gneb_get_chain", "sp_gneb_get_forces",
 ]
 
 
@@ -120,6 +122,13 @@ def lib():
         "sp_batch_set_chunk": (ci, [vp, ci]),
         "sp_batch_get_step": (u64, [vp]),
         "sp_batch_autotune": (ci, [vp, ci, dp]),
+        "sp_gneb_create": (ci, [ctypes.POINTER(vp), vp, ci, dp, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double]),
+        "sp_gneb_destroy": (None, [vp]),
+        "sp_gneb_last_error": (ctypes.c_char_p, [vp]),
+        "sp_gneb_iterate": (ci, [vp, ci]),
+        "sp_gneb_get_chain": (ci, [vp, dp]),
+        "sp_gneb_get_forces": (ci, [vp, dp, dp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -367,6 +376,50 @@ class Batch:
         ms = ctypes.c_double()
         self._check(lib().sp_batch_autotune(self._h, n_steps, ctypes.byref(ms)))
         return ms.value
+
+
+class Gneb:
+    """GNEB chain (``sp_gneb``) on an engine's lattice and Hamiltonian; the
+    engine must stay alive while the chain is used."""
+
+    def __init__(self, engine: "Engine", chain, k_spring: float = 1.0, vp_dt: float = 0.1,
+                 vp_mass: float = 1.0):
+        c = np.ascontiguousarray(np.asarray(chain, dtype=np.float64))
+        self.M = c.shape[0]
+        self.N = engine.N
+        assert c.size == self.M * 3 * self.N
+        self.engine = engine
+        self._h = ctypes.c_void_p()
+        rc = lib().sp_gneb_create(ctypes.byref(self._h), engine._h, self.M, _dp(c), k_spring, vp_dt,
+                                  vp_mass)
+        engine._check(rc)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.sp_gneb_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc: int):
+        if rc != SP_OK:
+            raise SpError(rc, lib().sp_gneb_last_error(self._h).decode())
+
+    def iterate(self, n_iter: int):
+        self._check(lib().sp_gneb_iterate(self._h, n_iter))
+
+    def chain(self) -> np.ndarray:
+        out = np.zeros(self.M * 3 * self.N)
+        self._check(lib().sp_gneb_get_chain(self._h, _dp(out)))
+        return out.reshape(self.M, 3, self.N)
+
+    def forces(self) -> dict:
+        E = np.zeros(self.M)
+        l = np.zeros(self.M - 1)
+        F = np.zeros(self.M * 3 * self.N)
+        self._check(lib().sp_gneb_get_forces(self._h, _dp(E), _dp(l), _dp(F)))
+        return {"E": E, "l": l, "F": F.reshape(self.M, 3, self.N)}
 
 
 def engine_for(workload, device: int = 0, precision: Optional[str] = None, stream=None) -> Engine:

@@ -1,0 +1,125 @@
+"""Pins of the oracle's convolutional-surrogate pieces (not part of the paper;
+the learned stand-in for the dipolar field): 3x3 convolution forward and
+backward, SiLU, Adam and bfloat16 rounding, against CPU library routines
+(torch), finite differences and closed forms."""
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+
+def _bf16_exact(rng, shape, scale=64):
+    """Random values exactly representable in bfloat16 (k/scale, |k| <= 127)."""
+    return rng.integers(-127, 128, size=shape).astype(np.float64) / scale
+
+
+def test_bf16_rounding_matches_torch(ora):
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(20000) * 10.0 ** rng.integers(-6, 6, 20000)
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    # float32 intermediate in torch: compare only where x is exactly a float32
+    x32 = x.astype(np.float32).astype(np.float64)
+    ref32 = torch.tensor(x32, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ora.bf16(x32), ref32)
+    assert np.abs(ora.bf16(x) - x).max() <= np.abs(x).max() * 2.0 ** -8
+    # ties to even: 1 + 2^-8 is halfway between 1 and 1 + 2^-7
+    assert ora.bf16(1.0 + 2.0 ** -8) == 1.0
+    assert ora.bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6
+    del ref
+
+
+@pytest.mark.parametrize("B,H,W,Cin,Cout", [(2, 7, 5, 3, 4), (1, 9, 11, 12, 32), (2, 6, 6, 32, 12)])
+def test_conv_forward_matches_torch(ora, B, H, W, Cin, Cout):
+    rng = np.random.default_rng(B * 100 + Cin)
+    x = _bf16_exact(rng, (B, H, W, Cin))
+    w = _bf16_exact(rng, (3, 3, Cin, Cout), scale=256)
+    b = rng.standard_normal(Cout)
+    z = ora.conv3x3_fwd(x, w, b)
+    xt = torch.tensor(x).permute(0, 3, 1, 2)
+    wt = torch.tensor(w).permute(3, 2, 0, 1)   # (Cout, Cin, ky, kx)
+    ref = F.conv2d(xt, wt, torch.tensor(b), padding=1).permute(0, 2, 3, 1).numpy()
+    assert np.abs(z - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_conv_backward_matches_torch_autograd(ora):
+    rng = np.random.default_rng(3)
+    B, H, W, Cin, Cout = 2, 6, 7, 5, 6
+    x = _bf16_exact(rng, (B, H, W, Cin))
+    w = _bf16_exact(rng, (3, 3, Cin, Cout), scale=256)
+    b = np.zeros(Cout)
+    dz = _bf16_exact(rng, (B, H, W, Cout))
+    dx, dw, db = ora.conv3x3_bwd(x, w, dz)
+    xt = torch.tensor(x).permute(0, 3, 1, 2).requires_grad_()
+    wt = torch.tensor(w).permute(3, 2, 0, 1).contiguous().requires_grad_()
+    bt = torch.tensor(b).requires_grad_()
+    out = F.conv2d(xt, wt, bt, padding=1)
+    out.backward(torch.tensor(dz).permute(0, 3, 1, 2))
+    assert np.allclose(dx, xt.grad.permute(0, 2, 3, 1).numpy(), atol=1e-12)
+    assert np.allclose(dw, wt.grad.permute(2, 3, 1, 0).numpy(), atol=1e-12)
+    assert np.allclose(db, bt.grad.numpy(), atol=1e-12)
+
+
+def test_network_gradient_matches_finite_differences(ora):
+    """Tiny 8x8 network 2 -> 3 -> 3 -> 2 channels with SiLU: the loss gradient of
+    weights and biases of every layer against central differences of the loss,
+    in the oracle's exact mode (no bfloat16 rounding, which would make the
+    loss piecewise constant on the scale of a finite-difference step)."""
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((2, 8, 8, 2))
+    ws = [rng.standard_normal((3, 3, 2, 3)) * 0.4, rng.standard_normal((3, 3, 3, 3)) * 0.4,
+          rng.standard_normal((3, 3, 3, 2)) * 0.4]
+    bs = [rng.standard_normal(3) * 0.1, rng.standard_normal(3) * 0.1, rng.standard_normal(2) * 0.1]
+    t = rng.standard_normal((2, 8, 8, 2))
+    h = 1e-6
+    with ora.conv_exact():
+        loss, gw, gb = ora.SurrogateNet(ws, bs).loss_and_grads(x, t)
+        for layer in range(3):
+            for idx in [(0, 0, 0, 0), (1, 1, 1, 1), (2, 1, 0, 1)]:
+                wp = [w.copy() for w in ws]
+                wm = [w.copy() for w in ws]
+                wp[layer][idx] += h
+                wm[layer][idx] -= h
+                lp, _, _ = ora.SurrogateNet(wp, bs).loss_and_grads(x, t)
+                lm, _, _ = ora.SurrogateNet(wm, bs).loss_and_grads(x, t)
+                assert gw[layer][idx] == pytest.approx((lp - lm) / (2 * h), rel=1e-6, abs=1e-9)
+            bp = [b.copy() for b in bs]
+            bm = [b.copy() for b in bs]
+            bp[layer][1] += h
+            bm[layer][1] -= h
+            lp, _, _ = ora.SurrogateNet(ws, bp).loss_and_grads(x, t)
+            lm, _, _ = ora.SurrogateNet(ws, bm).loss_and_grads(x, t)
+            assert gb[layer][1] == pytest.approx((lp - lm) / (2 * h), rel=1e-6, abs=1e-9)
+
+
+def test_silu_derivative(ora):
+    z = np.linspace(-8, 8, 1001)
+    y, d = ora.silu(z)
+    assert np.allclose(y, z / (1 + np.exp(-z)), atol=1e-15)
+    h = 1e-6
+    fd = (ora.silu(z + h)[0] - ora.silu(z - h)[0]) / (2 * h)
+    assert np.abs(d - fd).max() < 1e-8
+
+
+def test_adam_first_step_closed_form_and_torch(ora):
+    rng = np.random.default_rng(11)
+    p0 = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    lr, eps = 1e-3, 1e-8
+    p = p0.copy()
+    m = np.zeros(50)
+    v = np.zeros(50)
+    ora.adam(p, m, v, g, lr, eps=eps, t=1)
+    # first step: m_hat = g, v_hat = g^2 -> step lr * g / (|g| + eps)
+    assert np.allclose(p, p0 - lr * g / (np.abs(g) + eps), atol=1e-15)
+    pt = torch.tensor(p0, requires_grad=True)
+    opt = torch.optim.Adam([pt], lr=lr, eps=eps)
+    p = p0.copy()
+    m[:] = 0
+    v[:] = 0
+    for step in range(1, 6):
+        gs = rng.standard_normal(50)
+        pt.grad = torch.tensor(gs)
+        opt.step()
+        ora.adam(p, m, v, gs, lr, eps=eps, t=step)
+    assert np.allclose(p, pt.detach().numpy(), atol=1e-12)
