@@ -22,6 +22,58 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_UPDATE = {"f32": 24.0, "f64": 48.0}   # read n, write n(t+dt): 3 components each
+# MI355X vector FP32 peak without packed-FP32 instructions (which this build
+# keeps out of its code): 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz.
+VALU_FP32_PEAK_TFLOPS = 78.6
+
+
+KERNEL_SOURCES = ["paper_1901_11350_amd/csrc/kernels_fused2d.hpp",
+                  "paper_1901_11350_amd/csrc/kernels_field.hpp",
+                  "paper_1901_11350_amd/csrc/device_common.hpp"]
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary of this kernel and workload, or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def flops_per_update(workload) -> float:
+    """Algorithmic FP32 flops of one Depondt spin-update (FMA = 2 flops):
+    two field evaluations (neighbour sums 3 per bond, 6 per shell for J,
+    8 per in-plane DMI bond, 9 anisotropy, 3 Zeeman) plus 163 for the two
+    A vectors, their average, two Rodrigues rotations and the
+    renormalisation, plus 15 for Box-Muller at T > 0 (integer Philox
+    operations and transcendentals are not counted)."""
+    import math
+
+    h = workload.hamiltonian
+    lat = "tri" if abs(workload.geometry.bravais[1][0] - 0.5) < 1e-12 else "sq"
+    per_shell = {"tri": [6, 6, 6], "sq": [4, 4, 4]} if workload.geometry.n_cells[2] == 1 else \
+        {"tri": [6, 6, 6], "sq": [6, 12, 8]}
+    shells = max(len(h.J), len(h.D))
+    nb = sum(per_shell[lat][:shells])
+    ndmi = sum(per_shell[lat][:len(h.D)]) if any(h.D) else 0
+    field = 3 * nb + 6 * len(h.J) + 8 * ndmi + 9 + 3
+    return 2 * field + 163 + (15 if workload.dynamics.T > 0 else 0) + 0 * math.pi
 
 
 def cpu_baseline(workload, budget_s: float = 12.0) -> dict:
@@ -138,8 +190,126 @@ def bench_batch(args) -> dict:
             "batch_gain": (total * K / ms) / (total * Ks / ms_sep), "autotune_ms_per_step": tuned}
 
 
+def film_textures(geo, count: int, seed: int):
+    """Seeded training/test textures of the dipolar film: a third uniform
+    random, a third 1-3 tanh domain walls (Bloch or Neel, random position,
+    orientation and width 2-8 a), a third skyrmion/bubble ansatz (radius
+    5-20 a, random centre and helicity, small tilt noise)."""
+    import numpy as np
+
+    import spin_inputs as si
+
+    rng = np.random.default_rng(seed)
+    out = np.empty((count, 3, geo.n_sites), dtype=np.float32)
+    W, H, _ = geo.n_cells
+    for k in range(count):
+        kind = k % 3
+        s = int(rng.integers(1 << 30))
+        if kind == 0:
+            n = si.uniform_sphere(geo.n_sites, s)
+        elif kind == 1:
+            n = si.domain_walls(geo, n_walls=int(rng.integers(1, 4)), seed=s, bloch=bool(rng.integers(2)))
+        else:
+            n = si.skyrmion_ansatz(geo, radius=float(rng.uniform(5, 20)),
+                                   center=(float(rng.uniform(0.25, 0.75) * W), float(rng.uniform(0.25, 0.75) * H)),
+                                   helicity=float(rng.uniform(0, 6.283)), width=float(rng.uniform(1.5, 4.0)),
+                                   noise_rad=0.05, seed=s)
+        out[k] = n
+    return out
+
+
+def bench_surrogate(args) -> dict:
+    """Learned dipole field on the 128x128x4 film: training on textures
+    labelled by the direct sum, held-out error, and the LLG step with the
+    direct sum against the step with the surrogate (+ residual check and
+    fallback)."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import paper_1901_11350_amd as pk
+    import spin_inputs as si
+
+    w = si.WORKLOADS["film128x4_dipolar"]
+    geo = w.geometry
+    stream = work_stream()
+    e = pk.Engine(0, "f32", stream=stream)
+    e.set_geometry(geo)
+    e.set_hamiltonian(w.hamiltonian)
+    N = e.N
+    ntr, nte = args.sur_train, args.sur_test
+    tex = torch.tensor(film_textures(geo, ntr + nte, 11354), device="cuda").contiguous()
+    lab = torch.zeros_like(tex)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    e.ddi_label_dev(ntr + nte, tex, lab)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_direct = ev0.elapsed_time(ev1) / (ntr + nte)
+    e.ddi_init([12, 32, 32, 32, 12], seed=11354)
+    t0 = time.perf_counter()
+    losses = e.ddi_train_dev(ntr, tex[:ntr], lab[:ntr], epochs=args.sur_epochs, batch=8, lr=args.sur_lr, seed=1)
+    train_s = time.perf_counter() - t0
+    # held-out per-field relative error against the FP32 direct sum
+    pred = torch.zeros_like(tex[ntr:])
+    e.ddi_forward_dev(nte, tex[ntr:].contiguous(), pred)
+    torch.cuda.synchronize()
+    err = (torch.linalg.vector_norm((pred - lab[ntr:]).reshape(nte, -1), dim=1) /
+           torch.linalg.vector_norm(lab[ntr:].reshape(nte, -1), dim=1)).cpu().numpy()
+    # surrogate evaluation time (network only) for one field
+    ev0.record(stream)
+    for _ in range(20):
+        e.ddi_forward_dev(1, tex[ntr:ntr + 1], pred[:1])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_net = ev0.elapsed_time(ev1) / 20
+    # LLG steps: direct sum vs surrogate with residual check (tol 1e-3, 256 sites)
+    steps = args.sur_steps
+    n0 = tex[ntr].double().cpu().numpy()
+    e.set_spins(n0)
+    e.run(0.3, 0.001, 2)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    e.run(0.3, 0.001, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_step_direct = ev0.elapsed_time(ev1) / steps
+    e.set_hamiltonian(dataclasses.replace(w.hamiltonian, ddi=2))
+    e.ddi_configure(1e-3, 256)
+    e.set_spins(n0)
+    e.run(0.3, 0.001, 2)
+    before = e.ddi_stats()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    e.run(0.3, 0.001, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_step_sur = ev0.elapsed_time(ev1) / steps
+    st = e.ddi_stats()
+    evals = st["evaluations"] - before["evaluations"]
+    falls = st["fallbacks"] - before["fallbacks"]
+    return {"workload": "film128x4_dipolar", "n_sites": N, "train_textures": ntr, "test_textures": nte,
+            "epochs": args.sur_epochs, "train_s": train_s, "loss_first_last": [float(losses[0]), float(losses[-1])],
+            "heldout_rel_err_mean": float(err.mean()), "heldout_rel_err_max": float(err.max()),
+            "ms_direct_sum_field": ms_direct, "ms_network_field": ms_net,
+            "field_speedup_network_only": ms_direct / ms_net,
+            "direct_pairs_per_s": N * (N - 1) / (ms_direct * 1e-3),
+            "ms_llg_step_direct": ms_step_direct, "ms_llg_step_surrogate": ms_step_sur,
+            "step_speedup": ms_step_direct / ms_step_sur, "check_tol": 1e-3, "check_sites": 256,
+            "fallback_rate": falls / max(evals, 1), "sampled_err_last": st["last_error"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--surrogate", action="store_true",
+                    help="also train and time the learned dipole field (reported under 'surrogate')")
+    ap.add_argument("--sur-train", type=int, default=384)
+    ap.add_argument("--sur-test", type=int, default=16)
+    ap.add_argument("--sur-epochs", type=int, default=20)
+    ap.add_argument("--sur-lr", type=float, default=2e-3)
+    ap.add_argument("--sur-steps", type=int, default=20)
     ap.add_argument("--batch", action="store_true",
                     help="also time the 96-replica batch (reported under 'batch')")
     ap.add_argument("--batch-steps", type=int, default=256)
@@ -216,6 +386,11 @@ def main():
     t_launch = k_ev0.elapsed_time(k_ev1) * 1e-3 / (K2 * launches_per_step)
     bytes_per_launch = BYTES_PER_UPDATE[w.precision] * e.N / launches_per_step
     achieved = bytes_per_launch / t_launch / 1e9
+    fpu = flops_per_update(w)
+    tflops = fpu * e.N / launches_per_step / t_launch / 1e12
+    kernel_name = {"fused2d": "k_depondt_fused2d", "twopass": "k_predict+k_correct"}.get(
+        e.step_path, "k_fused2d_shape")
+    traffic = measured_traffic(kernel_name, w.name)
 
     last = obs[-1] if obs else e.observe()
     line = {
@@ -235,16 +410,19 @@ def main():
                    "alpha": d.alpha, "dt_ps": d.dt, "T_K": d.T, "observe_every": oe,
                    "step_path": e.step_path},
         "hbm_gbps_algorithmic": value * BYTES_PER_UPDATE[w.precision] / 1e9,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": {"fused2d": "k_depondt_fused2d", "twopass": "k_predict+k_correct"}.get(
-                         e.step_path, "k_fused2d_shape"),
-                     "bytes_per_launch": bytes_per_launch, "us_per_launch": t_launch * 1e6},
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / VALU_FP32_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": kernel_name, "flops_per_update": fpu,
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "us_per_launch": t_launch * 1e6,
+                     "hbm_achieved_GBps": achieved, "hbm_peak_GBps": HBM_PEAK_GBPS,
+                     "hbm_frac": achieved / HBM_PEAK_GBPS},
         "wall_s": wall,
         "final_observation": {"E_per_spin": last["E"] / e.N, "max_norm_dev": last["max_norm_dev"]},
     }
     if args.batch:
         line["batch"] = bench_batch(args)
+    if args.surrogate:
+        line["surrogate"] = bench_surrogate(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -52,7 +52,7 @@ enum sp_status {
 
 enum sp_precision { SP_F32 = 0, SP_F64 = 1 };
 enum sp_dmi_kind { SP_DMI_BULK = 1, SP_DMI_INTERFACIAL = 2 };
-enum sp_ddi_mode { SP_DDI_OFF = 0, SP_DDI_DIRECT = 1 };
+enum sp_ddi_mode { SP_DDI_OFF = 0, SP_DDI_DIRECT = 1, SP_DDI_SURROGATE = 2 };
 
 #define SP_MAX_BASIS 8
 #define SP_MAX_SHELLS 8
@@ -77,7 +77,9 @@ typedef struct {
     int n_dmi_shells;        /* 0..SP_MAX_SHELLS */
     const double *D;         /* [n_dmi_shells], meV */
     int dmi_kind;            /* SP_DMI_BULK or SP_DMI_INTERFACIAL */
-    int ddi_mode;            /* SP_DDI_OFF or SP_DDI_DIRECT */
+    int ddi_mode;            /* SP_DDI_OFF, SP_DDI_DIRECT, or SP_DDI_SURROGATE (learned
+                                field with residual check and direct-sum fallback,
+                                see sp_ddi_*) */
 } sp_hamiltonian;
 
 /* LLG parameters (Sec. III.C).  T > 0 adds the stochastic thermal field
@@ -266,6 +268,48 @@ int sp_gneb_get_chain(sp_gneb *c, double *chain);
 /* Of the last force evaluation: image energies E[n_images], geodesic
  * distances l[n_images-1], forces F[n_images*3N] (any may be NULL). */
 int sp_gneb_get_forces(sp_gneb *c, double *E, double *l, double *F);
+
+/* ------------------------------------------------------------------------
+ * Learned dipole field (not in the paper; a stand-in for its costliest term,
+ * the dipolar direct sum of Sec. III.A).  A stack of zero-padded 3x3
+ * convolutions with SiLU between layers maps the spins of a one-atom film
+ * (channels 3 x number of layers, c = 3*layer + component, pixels = the
+ * in-plane cells) to the dipole gradient divided by C_dd mu^2.  Matrix-core
+ * kernels: bf16 operands, FP32 accumulation (v_mfma_f32_16x16x32_bf16),
+ * trained by the library's own forward/backward kernels and Adam on FP32
+ * master weights.  With ddi_mode SP_DDI_SURROGATE every dipole evaluation of
+ * the LLG step uses the network, then computes the exact direct sum at
+ * n_check sampled sites; when the relative error there exceeds tol the full
+ * direct sum replaces the network's field (decided on the device).
+ * Requirements: FP32 engine, n_basis 1, Na and Nb multiples of 16,
+ * 3*Nc <= 32, a Hamiltonian with a dipole term (any ddi_mode but OFF).
+ * Device arrays hold `batch` samples of 3N floats each (SoA per sample).
+ * ------------------------------------------------------------------------ */
+/* (Re)create the network: channels[0..n_layers] with channels[0] and
+ * channels[n_layers] = 3*Nc, each <= 32; He-normal weights from seed. */
+int sp_ddi_init(sp_engine *e, int n_layers, const int *channels, uint64_t seed);
+/* Parameter count and host copies (per layer: w[ky][kx][ci][co] then b[co]). */
+int64_t sp_ddi_num_params(sp_engine *e);
+int sp_ddi_set_params(sp_engine *e, const double *params, int64_t n);
+int sp_ddi_get_params(sp_engine *e, double *params, int64_t n);
+/* Training labels: the direct-sum dipole gradient (meV) of each sample. */
+int sp_ddi_label_dev(sp_engine *e, int batch, const void *spins_dev, void *labels_dev);
+/* Network field (meV) of each sample. */
+int sp_ddi_forward_dev(sp_engine *e, int batch, const void *spins_dev, void *field_dev);
+/* Loss sum_b |net_b - labels_b/(C_dd mu^2)|^2 / |labels_b/(C_dd mu^2)|^2 and
+ * its gradient (host, parameter layout; may be NULL). */
+int sp_ddi_loss_grad_dev(sp_engine *e, int batch, const void *spins_dev, const void *labels_dev, double *loss,
+                         double *grad);
+/* Adam (lr, beta 0.9/0.999, eps 1e-8) over `epochs` shuffled passes of
+ * minibatches of `batch` samples; epoch_loss[epochs] (may be NULL) receives
+ * the mean loss per sample of each epoch. */
+int sp_ddi_train_dev(sp_engine *e, int n_samples, const void *spins_dev, const void *labels_dev, int epochs,
+                     int batch, double lr, uint64_t seed, double *epoch_loss);
+/* Residual check: tolerance on the sampled relative error, number of
+ * sampled sites (0..4096; 0 disables check and fallback). Default 1e-3, 256. */
+int sp_ddi_configure(sp_engine *e, double tol, int n_check_sites);
+/* out[4] = evaluations, fallbacks, last sampled error, max sampled error. */
+int sp_ddi_stats(sp_engine *e, double out[4]);
 
 #ifdef __cplusplus
 }

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <random>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -17,6 +18,7 @@
 #include "kernels_dipole.hpp"
 #include "kernels_fused2d.hpp"
 #include "kernels_gneb.hpp"
+#include "kernels_conv.hpp"
 
 namespace {
 
@@ -55,6 +57,9 @@ struct HostBond {
 const char* kVersion = "sp_engine 0.1 (gfx950)";
 
 }  // namespace
+
+struct SurrogateState;
+void surrogate_free(SurrogateState* s);
 
 struct sp_engine {
     int device = 0;
@@ -105,6 +110,7 @@ struct sp_engine {
     int* d_flag = nullptr;            // abort flag (non-finite torque)
     long long* d_abort_step = nullptr;
     double* h_pin = nullptr;          // pinned staging for small results
+    SurrogateState* sur = nullptr;    // learned dipole field (sp_ddi_*)
 };
 
 namespace {
@@ -274,7 +280,7 @@ inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + b
 
 // ----------------------------------------------------------------- dipole
 template <typename T>
-int launch_dipole(sp_engine* e, const void* n, void* gdd) {
+int launch_direct_sum(sp_engine* e, const void* n, void* gdd, const int* gate = nullptr) {
     sp::DipoleArgs<T> a{};
     a.N = e->N;
     a.cells = e->geo.n[0] * e->geo.n[1] * e->geo.n[2];
@@ -285,11 +291,22 @@ int launch_dipole(sp_engine* e, const void* n, void* gdd) {
     constexpr int IPT = 2;
     dim3 grid((unsigned)((e->N + 256 * IPT - 1) / (256 * IPT)), (unsigned)a.slices);
     hipLaunchKernelGGL((sp::k_dipole_partial<T, IPT>), grid, dim3(256), 0, e->stream, a,
-                       static_cast<const T*>(e->d_pos), static_cast<const T*>(n), static_cast<T*>(e->d_ddpart));
+                       static_cast<const T*>(e->d_pos), static_cast<const T*>(n), static_cast<T*>(e->d_ddpart), gate);
     hipLaunchKernelGGL((sp::k_dipole_finish<T>), dim3(blocks_for(3LL * e->N)), dim3(256), 0, e->stream, a,
-                       (T)kCdd, static_cast<const T*>(e->d_ddpart), static_cast<T*>(gdd));
+                       (T)kCdd, static_cast<const T*>(e->d_ddpart), static_cast<T*>(gdd), gate);
     HIPCHK(e, hipGetLastError());
     return SP_OK;
+}
+
+template <typename T>
+int surrogate_field(sp_engine* e, const void* n, void* gdd);
+
+// Dipole gradient for the step/gradient/observe paths: the direct sum, or
+// the learned surrogate with its residual check and direct-sum fallback.
+template <typename T>
+int launch_dipole(sp_engine* e, const void* n, void* gdd) {
+    if (e->ham.ddi == 2) return surrogate_field<T>(e, n, gdd);
+    return launch_direct_sum<T>(e, n, gdd);
 }
 
 // --------------------------------------------------------------- observe
@@ -703,13 +720,15 @@ int sp_create(sp_engine** out, int device, int precision, void* hip_stream) {
 void sp_destroy(sp_engine* e) {
     if (!e) return;
     (void)hipSetDevice(e->device);
-    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    // a borrowed stream may already be destroyed by its owner: wait on the device
+    (void)hipDeviceSynchronize();
     free_state_buffers(e);
     dfree(*reinterpret_cast<void**>(&e->d_partials));
     dfree(*reinterpret_cast<void**>(&e->d_obs));
     dfree(*reinterpret_cast<void**>(&e->d_flag));
     dfree(*reinterpret_cast<void**>(&e->d_abort_step));
     if (e->h_pin) (void)hipHostFree(e->h_pin);
+    surrogate_free(e->sur);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
 }
@@ -773,8 +792,8 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
         return fail(e, SP_E_ARG, "J or D array is NULL");
     if (h->n_dmi_shells > 0 && h->dmi_kind != SP_DMI_BULK && h->dmi_kind != SP_DMI_INTERFACIAL)
         return fail(e, SP_E_ARG, "dmi_kind must be SP_DMI_BULK or SP_DMI_INTERFACIAL");
-    if (h->ddi_mode != SP_DDI_OFF && h->ddi_mode != SP_DDI_DIRECT)
-        return fail(e, SP_E_UNSUPPORTED, "ddi_mode must be SP_DDI_OFF or SP_DDI_DIRECT");
+    if (h->ddi_mode != SP_DDI_OFF && h->ddi_mode != SP_DDI_DIRECT && h->ddi_mode != SP_DDI_SURROGATE)
+        return fail(e, SP_E_UNSUPPORTED, "ddi_mode must be SP_DDI_OFF, SP_DDI_DIRECT or SP_DDI_SURROGATE");
     HostHam H{};
     for (int b = 0; b < e->geo.nb; ++b) {
         if (!(h->mu[b] > 0.0) || !std::isfinite(h->mu[b])) return fail(e, SP_E_ARG, "mu must be finite and > 0");
@@ -800,7 +819,7 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
     for (int s = 0; s < H.n_exch; ++s) H.J[s] = h->J[s];
     for (int s = 0; s < H.n_dmi; ++s) H.D[s] = h->D[s];
     H.dmi_kind = h->n_dmi_shells > 0 ? h->dmi_kind : SP_DMI_INTERFACIAL;
-    H.ddi = h->ddi_mode == SP_DDI_DIRECT ? 1 : 0;
+    H.ddi = h->ddi_mode;   // 0 off, 1 direct sum, 2 surrogate (with direct-sum fallback)
 
     std::vector<HostBond> bonds, all_bonds;
     std::vector<int> bstart;
@@ -1436,8 +1455,7 @@ int sp_batch_create(sp_batch** out, int device, void* hip_stream) {
 void sp_batch_destroy(sp_batch* b) {
     if (!b) return;
     (void)hipSetDevice(b->device);
-    if (b->stream) (void)hipStreamSynchronize(b->stream);
-    if (b->side) (void)hipStreamSynchronize(b->side);
+    (void)hipDeviceSynchronize();   // the main stream may be borrowed and already gone
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     void* p = b->arena; dfree(p);
     p = b->d_reps; dfree(p);
@@ -1602,6 +1620,7 @@ int sp_batch_autotune(sp_batch* b, int n_steps, double* ms_per_step) {
 // ======================================================================= GNEB
 struct sp_gneb {
     sp_engine* e = nullptr;
+    int device = 0;
     int M = 0, N = 0, nblk = 0;
     double k = 1.0, dt = 0.1, m = 1.0;
     void *x = nullptr, *v = nullptr, *F = nullptr, *Fp = nullptr, *g = nullptr, *tau = nullptr;
@@ -1724,6 +1743,7 @@ int sp_gneb_create(sp_gneb** out, sp_engine* e, int n_images, const double* chai
     sp_gneb* G = new (std::nothrow) sp_gneb();
     if (!G) return SP_E_NOMEM;
     G->e = e;
+    G->device = e->device;
     G->M = n_images;
     G->N = e->N;
     G->nblk = (e->N + 255) / 256;
@@ -1768,8 +1788,9 @@ int sp_gneb_create(sp_gneb** out, sp_engine* e, int n_images, const double* chai
 
 void sp_gneb_destroy(sp_gneb* G) {
     if (!G) return;
-    (void)hipSetDevice(G->e->device);
-    (void)hipStreamSynchronize(G->e->stream);
+    // The engine may already be gone (its stream too): only the device is used.
+    (void)hipSetDevice(G->device);
+    (void)hipDeviceSynchronize();
     gneb_free(G);
     delete G;
 }
@@ -1813,3 +1834,6 @@ int sp_gneb_get_forces(sp_gneb* G, double* E, double* l, double* F) {
 }
 
 }  // extern "C"
+
+// ================================================================= surrogate
+#include "surrogate_host.inc"

@@ -25,9 +25,14 @@ struct DipoleArgs {
     T mu[kMaxBasis];
 };
 
+// gate: when non-null and *gate == 0 the kernel does nothing (the surrogate's
+// fallback launches the direct sum unconditionally and lets the device-side
+// residual check decide).
 template <typename T, int IPT>
 __global__ void __launch_bounds__(256) k_dipole_partial(DipoleArgs<T> a, const T* __restrict__ pos,
-                                                        const T* __restrict__ n, T* __restrict__ part) {
+                                                        const T* __restrict__ n, T* __restrict__ part,
+                                                        const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     __shared__ T sp_[6][256];
     const int N = a.N;
     const int i0 = blockIdx.x * (256 * IPT) + threadIdx.x;
@@ -112,7 +117,8 @@ __global__ void __launch_bounds__(256) k_dipole_partial(DipoleArgs<T> a, const T
 // Sum the S slices in order and scale by C_dd mu_i.
 template <typename T>
 __global__ void __launch_bounds__(256) k_dipole_finish(DipoleArgs<T> a, T Cdd, const T* __restrict__ part,
-                                                       T* __restrict__ gdd) {
+                                                       T* __restrict__ gdd, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = a.N;
     if (t >= 3 * N) return;

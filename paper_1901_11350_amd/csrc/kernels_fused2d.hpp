@@ -156,15 +156,17 @@ struct TileMap {
     int xcd_bands;   // 1: XCD-banded mapping (tile count divisible by 8), 0: identity
 };
 
+// Periodic wrap (or open-boundary rejection) of a staged coordinate.  A tile
+// plus halo can be more than twice as wide as a small lattice, so the wrap
+// is a full modulo, not a single +-n.
 __device__ __forceinline__ int wrap_once(int g, int n, int per, bool& in) {
-    if (g < 0) {
-        if (per) return g + n;
+    if (g >= 0 && g < n) return g;
+    if (!per) {
         in = false;
-    } else if (g >= n) {
-        if (per) return g - n;
-        in = false;
+        return 0;
     }
-    return g;
+    g %= n;
+    return g < 0 ? g + n : g;
 }
 
 template <typename T, int S, int TX, int TY>

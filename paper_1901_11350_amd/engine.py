@@ -36,6 +36,8 @@ EXPORTS = [
     "sp_batch_autotune",
     "sp_gneb_create", "sp_gneb_destroy", "sp_gneb_last_error", "sp_gneb_iterate",
     "sp_gneb_get_chain", "sp_gneb_get_forces",
+    "sp_ddi_init", "sp_ddi_num_params", "sp_ddi_set_params", "sp_ddi_get_params", "sp_ddi_label_dev",
+    "sp_ddi_forward_dev", "sp_ddi_loss_grad_dev", "sp_ddi_train_dev", "sp_ddi_configure", "sp_ddi_stats",
 ]
 
 
@@ -129,6 +131,16 @@ def lib():
         "sp_gneb_iterate": (ci, [vp, ci]),
         "sp_gneb_get_chain": (ci, [vp, dp]),
         "sp_gneb_get_forces": (ci, [vp, dp, dp, dp]),
+        "sp_ddi_init": (ci, [vp, ci, ctypes.POINTER(ci), u64]),
+        "sp_ddi_num_params": (i64, [vp]),
+        "sp_ddi_set_params": (ci, [vp, dp, i64]),
+        "sp_ddi_get_params": (ci, [vp, dp, i64]),
+        "sp_ddi_label_dev": (ci, [vp, ci, vp, vp]),
+        "sp_ddi_forward_dev": (ci, [vp, ci, vp, vp]),
+        "sp_ddi_loss_grad_dev": (ci, [vp, ci, vp, vp, dp, dp]),
+        "sp_ddi_train_dev": (ci, [vp, ci, vp, vp, ci, ci, ctypes.c_double, u64, dp]),
+        "sp_ddi_configure": (ci, [vp, ctypes.c_double, ci]),
+        "sp_ddi_stats": (ci, [vp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -210,7 +222,8 @@ class Engine:
         h.n_dmi_shells = len(ham.D)
         h.D = _dp(arrs["D"])
         h.dmi_kind = ham.dmi_kind
-        h.ddi_mode = SP_DDI_DIRECT if ham.ddi else SP_DDI_OFF
+        # ddi: False/True (off / direct sum) or an sp_ddi_mode value
+        h.ddi_mode = int(ham.ddi)
         self._check(lib().sp_set_hamiltonian(self._h, ctypes.byref(h)))
 
     def bonds(self, beta: int = 0):
@@ -307,6 +320,55 @@ class Engine:
 
     def synchronize(self):
         self._check(lib().sp_synchronize(self._h))
+
+    # ------------------------------------------- learned dipole surrogate
+    def ddi_init(self, channels, seed: int = 0):
+        ch = (ctypes.c_int * len(channels))(*channels)
+        self._check(lib().sp_ddi_init(self._h, len(channels) - 1, ch, seed))
+
+    def ddi_num_params(self) -> int:
+        return int(lib().sp_ddi_num_params(self._h))
+
+    def ddi_set_params(self, params):
+        p = _f64(params, self.ddi_num_params())
+        self._check(lib().sp_ddi_set_params(self._h, _dp(p), p.size))
+
+    def ddi_get_params(self) -> np.ndarray:
+        p = np.zeros(self.ddi_num_params())
+        self._check(lib().sp_ddi_get_params(self._h, _dp(p), p.size))
+        return p
+
+    def ddi_label_dev(self, batch: int, spins_t, labels_t):
+        self._check(lib().sp_ddi_label_dev(self._h, batch, ctypes.c_void_p(spins_t.data_ptr()),
+                                           ctypes.c_void_p(labels_t.data_ptr())))
+
+    def ddi_forward_dev(self, batch: int, spins_t, field_t):
+        self._check(lib().sp_ddi_forward_dev(self._h, batch, ctypes.c_void_p(spins_t.data_ptr()),
+                                             ctypes.c_void_p(field_t.data_ptr())))
+
+    def ddi_loss_grad_dev(self, batch: int, spins_t, labels_t):
+        loss = ctypes.c_double()
+        g = np.zeros(self.ddi_num_params())
+        self._check(lib().sp_ddi_loss_grad_dev(self._h, batch, ctypes.c_void_p(spins_t.data_ptr()),
+                                               ctypes.c_void_p(labels_t.data_ptr()), ctypes.byref(loss),
+                                               _dp(g)))
+        return loss.value, g
+
+    def ddi_train_dev(self, n: int, spins_t, labels_t, epochs: int, batch: int, lr: float,
+                      seed: int = 0) -> np.ndarray:
+        out = np.zeros(max(epochs, 1))
+        self._check(lib().sp_ddi_train_dev(self._h, n, ctypes.c_void_p(spins_t.data_ptr()),
+                                           ctypes.c_void_p(labels_t.data_ptr()), epochs, batch, lr, seed,
+                                           _dp(out)))
+        return out[:epochs]
+
+    def ddi_configure(self, tol: float, n_check: int):
+        self._check(lib().sp_ddi_configure(self._h, tol, n_check))
+
+    def ddi_stats(self) -> dict:
+        s = np.zeros(4)
+        self._check(lib().sp_ddi_stats(self._h, _dp(s)))
+        return {"evaluations": int(s[0]), "fallbacks": int(s[1]), "last_error": s[2], "max_error": s[3]}
 
     def thermal_normals(self, seed: int, step: int, site0: int, n_sites: int, replica: int = 0):
         eta = np.zeros(3 * n_sites)

@@ -124,6 +124,10 @@ PATH_CASES = {
     "tri50x20_1shell": (si.triangular(50, 20), dataclasses.replace(HAM1, J=(1.0,), D=(0.2,))),
     "tri66x34_2shell_bulk": (si.triangular(66, 34), dataclasses.replace(HAM1, J=(1.0, -0.3), D=(0.25,),
                                                                         dmi_kind=si.DMI_BULK)),
+    # periodic lattices narrower than half a 64-wide tile plus halo: the
+    # staged coordinates wrap more than once
+    "sq20x12_small": (si.square(20, 12), HAM0),
+    "tri24x20_small": (si.triangular(24, 20), HAM1),
 }
 SHAPE_CFGS = {"f32": ["32x16x256", "64x16x512", "32x16x512", "32x32x1024", "64x16x1024"],
               "f64": ["32x16x256"]}
