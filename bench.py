@@ -63,8 +63,6 @@ def flops_per_update(workload) -> float:
     A vectors, their average, two Rodrigues rotations and the
     renormalisation, plus 15 for Box-Muller at T > 0 (integer Philox
     operations and transcendentals are not counted)."""
-    import math
-
     h = workload.hamiltonian
     lat = "tri" if abs(workload.geometry.bravais[1][0] - 0.5) < 1e-12 else "sq"
     per_shell = {"tri": [6, 6, 6], "sq": [4, 4, 4]} if workload.geometry.n_cells[2] == 1 else \
@@ -73,7 +71,7 @@ def flops_per_update(workload) -> float:
     nb = sum(per_shell[lat][:shells])
     ndmi = sum(per_shell[lat][:len(h.D)]) if any(h.D) else 0
     field = 3 * nb + 6 * len(h.J) + 8 * ndmi + 9 + 3
-    return 2 * field + 163 + (15 if workload.dynamics.T > 0 else 0) + 0 * math.pi
+    return 2 * field + 163 + (15 if workload.dynamics.T > 0 else 0)
 
 
 def cpu_baseline(workload, budget_s: float = 12.0) -> dict:
@@ -317,7 +315,7 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="only run a device copy of this size (counter calibration)")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="triangular512_sllg")
     ap.add_argument("--observe-every", type=int, default=100)

@@ -71,8 +71,9 @@ __device__ __forceinline__ V3<float> normals3(U4 b, float) {
     const float u0 = fmaf((float)b.x, s, h), u1 = fmaf((float)b.y, s, h);
     const float u2 = fmaf((float)b.z, s, h), u3 = fmaf((float)b.w, s, h);
     // -2 ln u = -2 ln2 * log2(u); v_log_f32 is log2, v_sin/v_cos take revolutions.
-    const float r0 = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
-    const float r1 = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u2));
+    // Raw v_sqrt_f32: its argument is zero or a normal number (2^-33 <= u <= 1).
+    const float r0 = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
+    const float r1 = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u2));
     return V3<float>{r0 * __builtin_amdgcn_cosf(u1), r0 * __builtin_amdgcn_sinf(u1),
                      r1 * __builtin_amdgcn_cosf(u3)};
 }

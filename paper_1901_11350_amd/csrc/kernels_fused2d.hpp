@@ -10,11 +10,13 @@
 // so n_j x D costs four FMAs.
 //
 // Per workgroup (NT threads, TX x TY output tile):
-//   1. stage n(t) on the tile plus a 2R halo into LDS (periodic axes wrap,
-//      open axes pad with zero spins, which drop out of every bond sum);
+//   1. stage n(t) on the tile plus a 2R halo into LDS, one 16-byte cell per
+//      site (periodic axes wrap, open axes pad with zero spins, which drop
+//      out of every bond sum);
 //   2. predictor on the tile plus an R halo: field, thermal normals
 //      (Philox, counter = global site), A = -gp (B + alpha n x B),
-//      n^p = R(A) n into LDS; A and the thermal field of tile sites kept;
+//      n^p = R(A) n into LDS; A and the thermal field of the tile sites stay
+//      in the registers of the thread that owns the site;
 //   3. corrector on the tile: A^p from n^p, n(t+dt) = R((A + A^p)/2) n(t),
 //      written once to HBM.
 // Workgroups are mapped to tiles so that each XCD (workgroups are dealt to
@@ -118,9 +120,17 @@ __device__ __forceinline__ V3<T> rotate_fast(V3<T> n, V3<T> w, T dt) {
                  n.z + s1 * wxn.z + s2 * (w.z * wn - w2 * n.z)};
 }
 
-template <typename T, int S, int NDMI, int W>
-__device__ __forceinline__ V3<T> shape_field(const ShapeCoef<T>& C, const Site2D<T>& Q, const T* __restrict__ sx,
-                                             const T* __restrict__ sy, const T* __restrict__ sz, int c, V3<T> ni) {
+// Site spin padded to 16 (FP32) or 32 (FP64) bytes, so that one LDS read
+// with an immediate offset fetches a neighbour.
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+    T x, y, z, w;
+};
+
+// Exchange + DMI + anisotropy + Zeeman gradient of the site at LDS cell c;
+// get(o) returns the spin at LDS cell o, W is the LDS row pitch.
+template <typename T, int S, int NDMI, int W, typename Get>
+__device__ __forceinline__ V3<T> shape_field(const ShapeCoef<T>& C, const Site2D<T>& Q, Get get, int c, V3<T> ni) {
     using SH = ShapeTab<S>;
     V3<T> acc[SH::NS];
 #pragma unroll
@@ -128,16 +138,15 @@ __device__ __forceinline__ V3<T> shape_field(const ShapeCoef<T>& C, const Site2D
     T dx = T(0), dy = T(0), dz = T(0);
 #pragma unroll
     for (int q = 0; q < SH::NB; ++q) {
-        const int o = c + SH::da[q] + SH::db[q] * W;
-        const T jx = sx[o], jy = sy[o], jz = sz[o];
-        acc[SH::sh[q]].x += jx;
-        acc[SH::sh[q]].y += jy;
-        acc[SH::sh[q]].z += jz;
+        const V3<T> nj = get(c + SH::da[q] + SH::db[q] * W);
+        acc[SH::sh[q]].x += nj.x;
+        acc[SH::sh[q]].y += nj.y;
+        acc[SH::sh[q]].z += nj.z;
         if (q < NDMI) {
             // n_j x D with D = (Dx, Dy, 0)
-            dx -= jz * C.Dy[q];
-            dy += jz * C.Dx[q];
-            dz += jx * C.Dy[q] - jy * C.Dx[q];
+            dx -= nj.z * C.Dy[q];
+            dy += nj.z * C.Dx[q];
+            dz += nj.x * C.Dy[q] - nj.y * C.Dx[q];
         }
     }
     const T kn = Q.K2 * (Q.Kax[0] * ni.x + Q.Kax[1] * ni.y + Q.Kax[2] * ni.z);
@@ -149,6 +158,25 @@ __device__ __forceinline__ V3<T> shape_field(const ShapeCoef<T>& C, const Site2D
         g.z -= C.J[s] * acc[s].z;
     }
     return g;
+}
+
+template <typename T, int S, int NDMI, int W>
+__device__ __forceinline__ V3<T> shape_field_soa(const ShapeCoef<T>& C, const Site2D<T>& Q, const T* __restrict__ sx,
+                                                 const T* __restrict__ sy, const T* __restrict__ sz, int c, V3<T> ni) {
+    return shape_field<T, S, NDMI, W>(
+        C, Q, [&](int o) { return V3<T>{sx[o], sy[o], sz[o]}; }, c, ni);
+}
+
+template <typename T, int S, int NDMI, int W>
+__device__ __forceinline__ V3<T> shape_field_aos(const ShapeCoef<T>& C, const Site2D<T>& Q,
+                                                 const V4<T>* __restrict__ sv, int c, V3<T> ni) {
+    return shape_field<T, S, NDMI, W>(
+        C, Q,
+        [&](int o) {
+            const V4<T> v = sv[o];
+            return V3<T>{v.x, v.y, v.z};
+        },
+        c, ni);
 }
 
 struct TileMap {
@@ -175,23 +203,57 @@ struct TileLDS {
     static constexpr int WN = TX + 4 * R, HN = TY + 4 * R;
     static constexpr int WP = TX + 2 * R, HP = TY + 2 * R;
     static constexpr int PN = WN * HN, PP = WP * HP, PT = TX * TY;
-    T sN[3 * PN];
-    T sP[3 * PP];
-    T sA[3 * PT];
-    T sB[3 * PT];
+    V4<T> sN[PN];
+    V4<T> sP[PP];
 };
 
-// One Depondt step of the TX x TY tile at (x0, y0) of one lattice.
+// Predictor of one LDS cell (px, py) of the R-haloed predictor frame:
+// rotation vector A and thermal field of the site, n^p written to sP.
+// Cells that fall outside an open lattice hold a zero spin.
+template <typename T, int S, int NDMI, int TX, int TY>
+__device__ __forceinline__ void predict_cell(const ShapeCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int x0,
+                                             int y0, int px, int py, TileLDS<T, S, TX, TY>& L, V3<T>& Ai,
+                                             V3<T>& Bth) {
+    using TL = TileLDS<T, S, TX, TY>;
+    constexpr int R = TL::R, WN = TL::WN, WP = TL::WP;
+    bool in = true;
+    const int gx = wrap_once(x0 - R + px, Q.na, Q.per_a, in);
+    const int gy = wrap_once(y0 - R + py, Q.nb, Q.per_b, in);
+    V4<T> out{T(0), T(0), T(0), T(0)};
+    Ai = V3<T>{T(0), T(0), T(0)};
+    Bth = V3<T>{T(0), T(0), T(0)};
+    if (in) {
+        const int c = (py + R) * WN + (px + R);
+        const V4<T> n4 = L.sN[c];
+        const V3<T> ni{n4.x, n4.y, n4.z};
+        const V3<T> g = shape_field_aos<T, S, NDMI, WN>(C, Q, L.sN, c, ni);
+        V3<T> B = (-Q.inv_mumuB) * g;
+        if (A.thermal) {
+            Bth = Q.sigma * normals3(thermal_bits(A.key, (uint32_t)(gx + gy * Q.na)), T(0));
+            B = B + Bth;
+        }
+        Ai = llg_A(ni, B, A.gp, A.alpha);
+        // n^p only feeds the corrector's field; its FP32 length error
+        // (~1 ulp) is left in place, only n(t+dt) is renormalised.
+        const V3<T> o = rotate_fast(ni, T(-1) * Ai, A.dt);
+        out = V4<T>{o.x, o.y, o.z, T(0)};
+    }
+    L.sP[py * WP + px] = out;
+}
+
+// One Depondt step of the TX x TY tile at (x0, y0) of one lattice.  Thread
+// t owns tile sites t + j NT: it computes their predictor, keeps A and the
+// thermal field in registers, and computes their corrector; the ring of
+// predictor cells around the tile is shared out over the threads between.
 template <typename T, int S, int NDMI, int TX, int TY, int NT>
 __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A,
                                              int x0, int y0, const T* __restrict__ n, T* __restrict__ nout,
                                              TileLDS<T, S, TX, TY>& L) {
     using TL = TileLDS<T, S, TX, TY>;
     constexpr int R = TL::R, WN = TL::WN, WP = TL::WP, PN = TL::PN, PP = TL::PP, PT = TL::PT;
-    T* sN = L.sN;
-    T* sP = L.sP;
-    T* sA = L.sA;
-    T* sB = L.sB;
+    static_assert(PT % NT == 0, "tile sites must divide evenly over the threads");
+    constexpr int KPT = PT / NT;
+    constexpr int RING = PP - PT;
     const int N = Q.na * Q.nb;
     const int tid = threadIdx.x;
 
@@ -201,67 +263,59 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
         bool in = true;
         const int gx = wrap_once(x0 - 2 * R + lx, Q.na, Q.per_a, in);
         const int gy = wrap_once(y0 - 2 * R + ly, Q.nb, Q.per_b, in);
-        T vx = T(0), vy = T(0), vz = T(0);
+        V4<T> v{T(0), T(0), T(0), T(0)};
         if (in) {
             const int g = gx + gy * Q.na;
-            vx = n[g];
-            vy = n[N + g];
-            vz = n[2 * N + g];
+            v.x = n[g];
+            v.y = n[N + g];
+            v.z = n[2 * N + g];
         }
-        sN[idx] = vx;
-        sN[PN + idx] = vy;
-        sN[2 * PN + idx] = vz;
+        L.sN[idx] = v;
     }
     __syncthreads();
 
-    // 2) predictor on the tile plus R halo
-    for (int idx = tid; idx < PP; idx += NT) {
-        const int py = idx / WP, px = idx - py * WP;
-        bool in = true;
-        const int gx = wrap_once(x0 - R + px, Q.na, Q.per_a, in);
-        const int gy = wrap_once(y0 - R + py, Q.nb, Q.per_b, in);
-        V3<T> out{T(0), T(0), T(0)};
-        if (in) {
-            const int c = (py + R) * WN + (px + R);
-            const V3<T> ni{sN[c], sN[PN + c], sN[2 * PN + c]};
-            const V3<T> g = shape_field<T, S, NDMI, WN>(C, Q, sN, sN + PN, sN + 2 * PN, c, ni);
-            V3<T> B = (-Q.inv_mumuB) * g;
-            V3<T> Bth{T(0), T(0), T(0)};
-            if (A.thermal) {
-                Bth = Q.sigma * normals3(thermal_bits(A.key, (uint32_t)(gx + gy * Q.na)), T(0));
-                B = B + Bth;
-            }
-            const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
-            // n^p only feeds the corrector's field; its FP32 length error
-            // (~1 ulp) is left in place, only n(t+dt) is renormalised.
-            out = rotate_fast(ni, T(-1) * Ai, A.dt);
-            const int tx = px - R, ty = py - R;
-            if (tx >= 0 && tx < TX && ty >= 0 && ty < TY) {
-                const int t = ty * TX + tx;
-                sA[t] = Ai.x; sA[PT + t] = Ai.y; sA[2 * PT + t] = Ai.z;
-                sB[t] = Bth.x; sB[PT + t] = Bth.y; sB[2 * PT + t] = Bth.z;
-            }
+    // 2) predictor: owned tile sites, then the ring of width R around the tile
+    V3<T> keepA[KPT], keepB[KPT];
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const int t = tid + j * NT;
+        const int ty = t / TX, tx = t - ty * TX;
+        predict_cell<T, S, NDMI, TX, TY>(C, Q, A, x0, y0, tx + R, ty + R, L, keepA[j], keepB[j]);
+    }
+    for (int h = tid; h < RING; h += NT) {
+        int px, py;
+        if (h < 2 * R * WP) {                 // R rows above and R rows below the tile
+            const int r = h / WP;
+            px = h - r * WP;
+            py = r < R ? r : TY + r;
+        } else {                              // R columns left and right of each tile row
+            const int k = h - 2 * R * WP;
+            const int r = k / (2 * R), q = k - r * (2 * R);
+            py = R + r;
+            px = q < R ? q : TX + q;
         }
-        sP[idx] = out.x;
-        sP[PP + idx] = out.y;
-        sP[2 * PP + idx] = out.z;
+        V3<T> a, b;
+        predict_cell<T, S, NDMI, TX, TY>(C, Q, A, x0, y0, px, py, L, a, b);
     }
     __syncthreads();
 
-    // 3) corrector on the tile
-    for (int t = tid; t < PT; t += NT) {
+    // 3) corrector on the owned tile sites
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const int t = tid + j * NT;
         const int ty = t / TX, tx = t - ty * TX;
         const int gx = x0 + tx, gy = y0 + ty;
         if (gx >= Q.na || gy >= Q.nb) continue;
         const int c = (ty + R) * WP + (tx + R);
-        const V3<T> npi{sP[c], sP[PP + c], sP[2 * PP + c]};
-        const V3<T> g = shape_field<T, S, NDMI, WP>(C, Q, sP, sP + PP, sP + 2 * PP, c, npi);
-        const V3<T> B = (-Q.inv_mumuB) * g + V3<T>{sB[t], sB[PT + t], sB[2 * PT + t]};
+        const V4<T> p4 = L.sP[c];
+        const V3<T> npi{p4.x, p4.y, p4.z};
+        const V3<T> g = shape_field_aos<T, S, NDMI, WP>(C, Q, L.sP, c, npi);
+        const V3<T> B = (-Q.inv_mumuB) * g + keepB[j];
         const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
-        const V3<T> w{T(-0.5) * (sA[t] + Ap.x), T(-0.5) * (sA[PT + t] + Ap.y), T(-0.5) * (sA[2 * PT + t] + Ap.z)};
-        const int cn = (ty + 2 * R) * WN + (tx + 2 * R);
-        const V3<T> ni{sN[cn], sN[PN + cn], sN[2 * PN + cn]};
-        const V3<T> o = renorm_if_float(rotate_fast(ni, w, A.dt));
+        const V3<T> w{T(-0.5) * (keepA[j].x + Ap.x), T(-0.5) * (keepA[j].y + Ap.y),
+                      T(-0.5) * (keepA[j].z + Ap.z)};
+        const V4<T> n4 = L.sN[(ty + 2 * R) * WN + (tx + 2 * R)];
+        const V3<T> o = renorm_if_float(rotate_fast(V3<T>{n4.x, n4.y, n4.z}, w, A.dt));
         const int gi = gx + gy * Q.na;
         nout[gi] = o.x;
         nout[N + gi] = o.y;
@@ -392,7 +446,7 @@ __global__ void __launch_bounds__(NT) k_batch_resident(ShapeCoef<T> C, Site2D<T>
                 const int y = s / LX, x = s - y * LX;
                 const int c = (y + R) * W + (x + R);
                 const V3<T> ni{sN[c], sN[P + c], sN[2 * P + c]};
-                const V3<T> g = shape_field<T, S, NDMI, W>(C, Q, sN, sN + P, sN + 2 * P, c, ni);
+                const V3<T> g = shape_field_soa<T, S, NDMI, W>(C, Q, sN, sN + P, sN + 2 * P, c, ni);
                 V3<T> B = (-Q.inv_mumuB) * g;
                 V3<T> Bth{T(0), T(0), T(0)};
                 if (A.thermal) {
@@ -428,7 +482,7 @@ __global__ void __launch_bounds__(NT) k_batch_resident(ShapeCoef<T> C, Site2D<T>
                 const int y = s / LX, x = s - y * LX;
                 const int c = (y + R) * W + (x + R);
                 const V3<T> npi{sP[c], sP[P + c], sP[2 * P + c]};
-                const V3<T> g = shape_field<T, S, NDMI, W>(C, Q, sP, sP + P, sP + 2 * P, c, npi);
+                const V3<T> g = shape_field_soa<T, S, NDMI, W>(C, Q, sP, sP + P, sP + 2 * P, c, npi);
                 const V3<T> B = (-Q.inv_mumuB) * g + keepB[j];
                 const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
                 const V3<T> w{T(-0.5) * (keepA[j].x + Ap.x), T(-0.5) * (keepA[j].y + Ap.y),
