@@ -52,7 +52,7 @@ enum sp_status {
 
 enum sp_precision { SP_F32 = 0, SP_F64 = 1 };
 enum sp_dmi_kind { SP_DMI_BULK = 1, SP_DMI_INTERFACIAL = 2 };
-enum sp_ddi_mode { SP_DDI_OFF = 0, SP_DDI_DIRECT = 1, SP_DDI_SURROGATE = 2 };
+enum sp_ddi_mode { SP_DDI_OFF = 0, SP_DDI_DIRECT = 1, SP_DDI_SURROGATE = 2, SP_DDI_FFT = 3 };
 
 #define SP_MAX_BASIS 8
 #define SP_MAX_SHELLS 8
@@ -77,9 +77,14 @@ typedef struct {
     int n_dmi_shells;        /* 0..SP_MAX_SHELLS */
     const double *D;         /* [n_dmi_shells], meV */
     int dmi_kind;            /* SP_DMI_BULK or SP_DMI_INTERFACIAL */
-    int ddi_mode;            /* SP_DDI_OFF, SP_DDI_DIRECT, or SP_DDI_SURROGATE (learned
+    int ddi_mode;            /* SP_DDI_OFF, SP_DDI_DIRECT, SP_DDI_SURROGATE (learned
                                 field with residual check and direct-sum fallback,
-                                see sp_ddi_*) */
+                                see sp_ddi_*), or SP_DDI_FFT: the same pair sum
+                                (all pairs inside the sample, Sec. III.A) as a 2D
+                                convolution per plane pair, zero-padded FFTs along
+                                a and b; needs n_cells[0], n_cells[1] <= 512 and
+                                n_cells[2] * n_basis <= 64, else
+                                SP_E_UNSUPPORTED from sp_set_hamiltonian */
 } sp_hamiltonian;
 
 /* LLG parameters (Sec. III.C).  T > 0 adds the stochastic thermal field

@@ -19,6 +19,7 @@
 #include "kernels_fused2d.hpp"
 #include "kernels_gneb.hpp"
 #include "kernels_conv.hpp"
+#include "kernels_fft.hpp"
 
 namespace {
 
@@ -60,6 +61,8 @@ const char* kVersion = "sp_engine 0.1 (gfx950)";
 
 struct SurrogateState;
 void surrogate_free(SurrogateState* s);
+struct FftState;
+void fft_free(FftState* s);
 
 struct sp_engine {
     int device = 0;
@@ -111,6 +114,7 @@ struct sp_engine {
     long long* d_abort_step = nullptr;
     double* h_pin = nullptr;          // pinned staging for small results
     SurrogateState* sur = nullptr;    // learned dipole field (sp_ddi_*)
+    FftState* fft = nullptr;          // FFT-convolution dipole field (SP_DDI_FFT)
 };
 
 namespace {
@@ -155,6 +159,8 @@ void free_state_buffers(sp_engine* e) {
     void* p = e->d_bond; dfree(p); e->d_bond = nullptr;
     p = e->d_bstart; dfree(p); e->d_bstart = nullptr;
     dfree(e->d_J); dfree(e->d_D);
+    fft_free(e->fft);
+    e->fft = nullptr;
 }
 
 // ------------------------------------------------------------ bond table
@@ -300,12 +306,18 @@ int launch_direct_sum(sp_engine* e, const void* n, void* gdd, const int* gate = 
 
 template <typename T>
 int surrogate_field(sp_engine* e, const void* n, void* gdd);
+template <typename T>
+int fft_field(sp_engine* e, const void* n, void* gdd);
+template <typename T>
+int fft_setup(sp_engine* e);
 
-// Dipole gradient for the step/gradient/observe paths: the direct sum, or
-// the learned surrogate with its residual check and direct-sum fallback.
+// Dipole gradient for the step/gradient/observe paths: the direct sum, the
+// FFT convolution, or the learned surrogate with its residual check and
+// direct-sum fallback.
 template <typename T>
 int launch_dipole(sp_engine* e, const void* n, void* gdd) {
-    if (e->ham.ddi == 2) return surrogate_field<T>(e, n, gdd);
+    if (e->ham.ddi == SP_DDI_SURROGATE) return surrogate_field<T>(e, n, gdd);
+    if (e->ham.ddi == SP_DDI_FFT) return fft_field<T>(e, n, gdd);
     return launch_direct_sum<T>(e, n, gdd);
 }
 
@@ -792,8 +804,9 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
         return fail(e, SP_E_ARG, "J or D array is NULL");
     if (h->n_dmi_shells > 0 && h->dmi_kind != SP_DMI_BULK && h->dmi_kind != SP_DMI_INTERFACIAL)
         return fail(e, SP_E_ARG, "dmi_kind must be SP_DMI_BULK or SP_DMI_INTERFACIAL");
-    if (h->ddi_mode != SP_DDI_OFF && h->ddi_mode != SP_DDI_DIRECT && h->ddi_mode != SP_DDI_SURROGATE)
-        return fail(e, SP_E_UNSUPPORTED, "ddi_mode must be SP_DDI_OFF, SP_DDI_DIRECT or SP_DDI_SURROGATE");
+    if (h->ddi_mode != SP_DDI_OFF && h->ddi_mode != SP_DDI_DIRECT && h->ddi_mode != SP_DDI_SURROGATE &&
+        h->ddi_mode != SP_DDI_FFT)
+        return fail(e, SP_E_UNSUPPORTED, "ddi_mode must be SP_DDI_OFF, SP_DDI_DIRECT, SP_DDI_SURROGATE or SP_DDI_FFT");
     HostHam H{};
     for (int b = 0; b < e->geo.nb; ++b) {
         if (!(h->mu[b] > 0.0) || !std::isfinite(h->mu[b])) return fail(e, SP_E_ARG, "mu must be finite and > 0");
@@ -819,7 +832,7 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
     for (int s = 0; s < H.n_exch; ++s) H.J[s] = h->J[s];
     for (int s = 0; s < H.n_dmi; ++s) H.D[s] = h->D[s];
     H.dmi_kind = h->n_dmi_shells > 0 ? h->dmi_kind : SP_DMI_INTERFACIAL;
-    H.ddi = h->ddi_mode;   // 0 off, 1 direct sum, 2 surrogate (with direct-sum fallback)
+    H.ddi = h->ddi_mode;   // off, direct sum, surrogate (with direct-sum fallback), FFT convolution
 
     std::vector<HostBond> bonds, all_bonds;
     std::vector<int> bstart;
@@ -866,7 +879,7 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
             return rc;
         }
     }
-    if ((rc = DISPATCH(e, upload_ham, e))) {
+    if ((rc = DISPATCH(e, upload_ham, e)) || (H.ddi == SP_DDI_FFT && (rc = DISPATCH(e, fft_setup, e)))) {
         free_state_buffers(e);
         e->has_ham = false;
         e->has_spins = false;
@@ -1837,3 +1850,6 @@ int sp_gneb_get_forces(sp_gneb* G, double* E, double* l, double* F) {
 
 // ================================================================= surrogate
 #include "surrogate_host.inc"
+
+// ====================================================================== FFT dipole
+#include "fft_host.inc"

@@ -12,9 +12,10 @@
 // Per workgroup (NT threads, TX x TY output tile):
 //   1. stage n(t) on the tile plus a 2R halo into LDS, one 16-byte cell per
 //      site (periodic axes wrap, open axes pad with zero spins, which drop
-//      out of every bond sum);
-//   2. predictor on the tile plus an R halo: field, thermal normals
-//      (Philox, counter = global site), A = -gp (B + alpha n x B),
+//      out of every bond sum); the thermal fields of the cells a thread
+//      will predict (Philox, counter = global site) are formed while these
+//      loads are in flight;
+//   2. predictor on the tile plus an R halo: field, A = -gp (B + alpha n x B),
 //      n^p = R(A) n into LDS; A and the thermal field of the tile sites stay
 //      in the registers of the thread that owns the site;
 //   3. corrector on the tile: A^p from n^p, n(t+dt) = R((A + A^p)/2) n(t),
@@ -207,31 +208,63 @@ struct TileLDS {
     V4<T> sP[PP];
 };
 
-// Predictor of one LDS cell (px, py) of the R-haloed predictor frame:
-// rotation vector A and thermal field of the site, n^p written to sP.
-// Cells that fall outside an open lattice hold a zero spin.
-template <typename T, int S, int NDMI, int TX, int TY>
-__device__ __forceinline__ void predict_cell(const ShapeCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int x0,
-                                             int y0, int px, int py, TileLDS<T, S, TX, TY>& L, V3<T>& Ai,
-                                             V3<T>& Bth) {
-    using TL = TileLDS<T, S, TX, TY>;
-    constexpr int R = TL::R, WN = TL::WN, WP = TL::WP;
-    bool in = true;
+// Global site of the predictor-frame cell (px, py), or in = false for a
+// cell outside an open lattice.
+template <typename T, int S, int TX, int TY>
+__device__ __forceinline__ int cell_site(const Site2D<T>& Q, int x0, int y0, int px, int py, bool& in) {
+    constexpr int R = ShapeTab<S>::R;
+    in = true;
     const int gx = wrap_once(x0 - R + px, Q.na, Q.per_a, in);
     const int gy = wrap_once(y0 - R + py, Q.nb, Q.per_b, in);
+    return gx + gy * Q.na;
+}
+
+// Thermal field of a predictor-frame cell: depends only on the site, the
+// step and the seed, so it is formed while the spins are still in flight.
+template <typename T, int S, int TX, int TY>
+__device__ __forceinline__ V3<T> cell_thermal(const Site2D<T>& Q, const LLGArgs<T>& A, int x0, int y0, int px,
+                                              int py) {
+    bool in;
+    const int site = cell_site<T, S, TX, TY>(Q, x0, y0, px, py, in);
+    if (!A.thermal || !in) return V3<T>{T(0), T(0), T(0)};
+    return Q.sigma * normals3(thermal_bits(A.key, (uint32_t)site), T(0));
+}
+
+// Ring cell h (0 <= h < ring size) of the predictor frame: R rows above and
+// below the tile, then R columns left and right of each tile row.
+template <int R, int TX, int TY>
+__device__ __forceinline__ void ring_cell(int h, int& px, int& py) {
+    constexpr int WP = TX + 2 * R;
+    if (h < 2 * R * WP) {
+        const int r = h / WP;
+        px = h - r * WP;
+        py = r < R ? r : TY + r;
+    } else {
+        const int k = h - 2 * R * WP;
+        const int r = k / (2 * R), q = k - r * (2 * R);
+        py = R + r;
+        px = q < R ? q : TX + q;
+    }
+}
+
+// Predictor of one predictor-frame cell (px, py) with its thermal field
+// Bth: rotation vector A of the site, n^p written to sP.  Cells that fall
+// outside an open lattice hold a zero spin.
+template <typename T, int S, int NDMI, int TX, int TY>
+__device__ __forceinline__ V3<T> predict_cell(const ShapeCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int x0,
+                                              int y0, int px, int py, TileLDS<T, S, TX, TY>& L, V3<T> Bth) {
+    using TL = TileLDS<T, S, TX, TY>;
+    constexpr int R = TL::R, WN = TL::WN, WP = TL::WP;
+    bool in;
+    cell_site<T, S, TX, TY>(Q, x0, y0, px, py, in);
     V4<T> out{T(0), T(0), T(0), T(0)};
-    Ai = V3<T>{T(0), T(0), T(0)};
-    Bth = V3<T>{T(0), T(0), T(0)};
+    V3<T> Ai{T(0), T(0), T(0)};
     if (in) {
         const int c = (py + R) * WN + (px + R);
         const V4<T> n4 = L.sN[c];
         const V3<T> ni{n4.x, n4.y, n4.z};
         const V3<T> g = shape_field_aos<T, S, NDMI, WN>(C, Q, L.sN, c, ni);
-        V3<T> B = (-Q.inv_mumuB) * g;
-        if (A.thermal) {
-            Bth = Q.sigma * normals3(thermal_bits(A.key, (uint32_t)(gx + gy * Q.na)), T(0));
-            B = B + Bth;
-        }
+        const V3<T> B = (-Q.inv_mumuB) * g + Bth;
         Ai = llg_A(ni, B, A.gp, A.alpha);
         // n^p only feeds the corrector's field; its FP32 length error
         // (~1 ulp) is left in place, only n(t+dt) is renormalised.
@@ -239,6 +272,7 @@ __device__ __forceinline__ void predict_cell(const ShapeCoef<T>& C, const Site2D
         out = V4<T>{o.x, o.y, o.z, T(0)};
     }
     L.sP[py * WP + px] = out;
+    return Ai;
 }
 
 // One Depondt step of the TX x TY tile at (x0, y0) of one lattice.  Thread
@@ -254,52 +288,73 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
     static_assert(PT % NT == 0, "tile sites must divide evenly over the threads");
     constexpr int KPT = PT / NT;
     constexpr int RING = PP - PT;
+    constexpr int KST = (PN + NT - 1) / NT;     // staged cells per thread
+    constexpr int KRG = (RING + NT - 1) / NT;   // ring cells per thread
     const int N = Q.na * Q.nb;
     const int tid = threadIdx.x;
 
-    // 1) stage n(t) on the tile plus 2R halo
-    for (int idx = tid; idx < PN; idx += NT) {
-        const int ly = idx / WN, lx = idx - ly * WN;
-        bool in = true;
-        const int gx = wrap_once(x0 - 2 * R + lx, Q.na, Q.per_a, in);
-        const int gy = wrap_once(y0 - 2 * R + ly, Q.nb, Q.per_b, in);
-        V4<T> v{T(0), T(0), T(0), T(0)};
-        if (in) {
-            const int g = gx + gy * Q.na;
-            v.x = n[g];
-            v.y = n[N + g];
-            v.z = n[2 * N + g];
+    // 1) load n(t) on the tile plus 2R halo into registers
+    V3<T> st[KST];
+#pragma unroll
+    for (int k = 0; k < KST; ++k) {
+        const int idx = tid + k * NT;
+        st[k] = V3<T>{T(0), T(0), T(0)};
+        if (idx < PN) {
+            const int ly = idx / WN, lx = idx - ly * WN;
+            bool in = true;
+            const int gx = wrap_once(x0 - 2 * R + lx, Q.na, Q.per_a, in);
+            const int gy = wrap_once(y0 - 2 * R + ly, Q.nb, Q.per_b, in);
+            if (in) {
+                const int g = gx + gy * Q.na;
+                st[k] = V3<T>{n[g], n[N + g], n[2 * N + g]};
+            }
         }
-        L.sN[idx] = v;
     }
-    __syncthreads();
-
-    // 2) predictor: owned tile sites, then the ring of width R around the tile
-    V3<T> keepA[KPT], keepB[KPT];
+    // 2) thermal fields of the owned cells while the loads are in flight
+    V3<T> keepB[KPT], ringB[KRG];
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
         const int t = tid + j * NT;
         const int ty = t / TX, tx = t - ty * TX;
-        predict_cell<T, S, NDMI, TX, TY>(C, Q, A, x0, y0, tx + R, ty + R, L, keepA[j], keepB[j]);
+        keepB[j] = cell_thermal<T, S, TX, TY>(Q, A, x0, y0, tx + R, ty + R);
     }
-    for (int h = tid; h < RING; h += NT) {
-        int px, py;
-        if (h < 2 * R * WP) {                 // R rows above and R rows below the tile
-            const int r = h / WP;
-            px = h - r * WP;
-            py = r < R ? r : TY + r;
-        } else {                              // R columns left and right of each tile row
-            const int k = h - 2 * R * WP;
-            const int r = k / (2 * R), q = k - r * (2 * R);
-            py = R + r;
-            px = q < R ? q : TX + q;
+#pragma unroll
+    for (int k = 0; k < KRG; ++k) {
+        const int h = tid + k * NT;
+        ringB[k] = V3<T>{T(0), T(0), T(0)};
+        if (h < RING) {
+            int px, py;
+            ring_cell<R, TX, TY>(h, px, py);
+            ringB[k] = cell_thermal<T, S, TX, TY>(Q, A, x0, y0, px, py);
         }
-        V3<T> a, b;
-        predict_cell<T, S, NDMI, TX, TY>(C, Q, A, x0, y0, px, py, L, a, b);
+    }
+#pragma unroll
+    for (int k = 0; k < KST; ++k) {
+        const int idx = tid + k * NT;
+        if (idx < PN) L.sN[idx] = V4<T>{st[k].x, st[k].y, st[k].z, T(0)};
     }
     __syncthreads();
 
-    // 3) corrector on the owned tile sites
+    // 3) predictor: owned tile sites, then the ring of width R around the tile
+    V3<T> keepA[KPT];
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const int t = tid + j * NT;
+        const int ty = t / TX, tx = t - ty * TX;
+        keepA[j] = predict_cell<T, S, NDMI, TX, TY>(C, Q, A, x0, y0, tx + R, ty + R, L, keepB[j]);
+    }
+#pragma unroll
+    for (int k = 0; k < KRG; ++k) {
+        const int h = tid + k * NT;
+        if (h < RING) {
+            int px, py;
+            ring_cell<R, TX, TY>(h, px, py);
+            predict_cell<T, S, NDMI, TX, TY>(C, Q, A, x0, y0, px, py, L, ringB[k]);
+        }
+    }
+    __syncthreads();
+
+    // 4) corrector on the owned tile sites
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
         const int t = tid + j * NT;

@@ -58,7 +58,10 @@ class Hamiltonian:
     J: Tuple[float, ...] = ()
     D: Tuple[float, ...] = ()
     dmi_kind: int = DMI_INTERFACIAL
-    ddi: bool = False
+    # dipole-dipole term: False/0 off; True/1 direct pair sum; the engine also
+    # takes 2 (learned surrogate with residual check) and 3 (FFT convolution),
+    # which define the same field
+    ddi: int = False
 
 
 @dataclasses.dataclass(frozen=True)

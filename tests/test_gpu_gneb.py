@@ -93,9 +93,11 @@ def test_gneb_fp64_iterations_match_oracle(ora, case, iters):
     fg, fo = g.forces(), o.forces()
     assert np.allclose(fg["E"], fo["E"], rtol=tol, atol=tol * np.abs(fo["E"]).max())
     # forces shrink as the chain converges: measure their difference on the
-    # scale of the initial forces
+    # scale of the initial forces.  They are recomputed from chains that agree
+    # to `tol`; the force map (curvature of the energy, spring and projection
+    # terms) amplifies that difference by up to ~1e2.
     dF = np.linalg.norm(fg["F"] - fo["F"]) / np.linalg.norm(f0["F"])
-    assert dF <= 1e-9, f"forces: difference {dF:.3e} of the initial force norm"
+    assert dF <= 100 * tol, f"forces: difference {dF:.3e} of the initial force norm"
 
 
 @pytest.mark.parametrize("case", ["single_spin", "square12x10", "chain32x128x128"])
