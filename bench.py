@@ -22,9 +22,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_UPDATE = {"f32": 24.0, "f64": 48.0}   # read n, write n(t+dt): 3 components each
-# MI355X vector FP32 peak without packed-FP32 instructions (which this build
-# keeps out of its code): 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz.
-VALU_FP32_PEAK_TFLOPS = 78.6
+# MI355X published vector FP32 peak: 256 CUs x 128 FMA lanes x 2 flops x
+# 2.4 GHz.  This build emits no packed-FP32 instructions, so one wave issues
+# at most 64 FMA lanes per CU per clock (78.6 TFLOP/s); the published figure
+# is still the peak the fraction is taken against.
+VALU_FP32_PEAK_TFLOPS = 157.3
 
 
 KERNEL_SOURCES = ["paper_1901_11350_amd/csrc/kernels_fused2d.hpp",

@@ -404,8 +404,9 @@ struct TileCfg {
 };
 constexpr TileCfg kTileCfgs[] = {{"32x16x256", 32, 16, 256},  {"64x16x512", 64, 16, 512},
                                  {"32x16x512", 32, 16, 512},  {"32x32x1024", 32, 32, 1024},
-                                 {"64x16x1024", 64, 16, 1024}};
-constexpr int kNumTileCfgs = 5;
+                                 {"64x16x1024", 64, 16, 1024}, {"32x32x512", 32, 32, 512},
+                                 {"64x16x256", 64, 16, 256}};
+constexpr int kNumTileCfgs = 7;
 constexpr int kNumTileCfgsF64 = 1;
 
 template <int S>
@@ -487,6 +488,8 @@ void launch_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const voi
             case 2: go_tile<T, 32, 16, 512>(e, p, step, nin, nout); break;
             case 3: go_tile<T, 32, 32, 1024>(e, p, step, nin, nout); break;
             case 4: go_tile<T, 64, 16, 1024>(e, p, step, nin, nout); break;
+            case 5: go_tile<T, 32, 32, 512>(e, p, step, nin, nout); break;
+            case 6: go_tile<T, 64, 16, 256>(e, p, step, nin, nout); break;
             default: go_tile<T, 32, 16, 256>(e, p, step, nin, nout); break;
         }
     }

@@ -129,7 +129,8 @@ PATH_CASES = {
     "sq20x12_small": (si.square(20, 12), HAM0),
     "tri24x20_small": (si.triangular(24, 20), HAM1),
 }
-SHAPE_CFGS = {"f32": ["32x16x256", "64x16x512", "32x16x512", "32x32x1024", "64x16x1024"],
+SHAPE_CFGS = {"f32": ["32x16x256", "64x16x512", "32x16x512", "32x32x1024", "64x16x1024", "32x32x512",
+                      "64x16x256"],
               "f64": ["32x16x256"]}
 
 
