@@ -65,7 +65,10 @@ class Bond(ctypes.Structure):
 
 class LLGParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("dt", ctypes.c_double), ("T", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("replica", ctypes.c_uint32)]
+                ("seed", ctypes.c_uint64), ("replica", ctypes.c_uint32), ("solver", ctypes.c_int32)]
+
+
+SOLVERS = {"depondt": 0, "heun": 1, "sib": 2}
 
 
 class GnebParams(ctypes.Structure):
@@ -112,8 +115,8 @@ def lib():
                                         ctypes.POINTER(ctypes.c_uint32)]
         L.ora_thermal_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                           ctypes.c_uint32, dp]
-        L.ora_depondt_step.argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(LLGParams),
-                                       ctypes.c_uint64]
+        for name in ("ora_depondt_step", "ora_heun_step", "ora_sib_step", "ora_llg_step"):
+            getattr(L, name).argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(LLGParams), ctypes.c_uint64]
         L.ora_rotate.argtypes = [dp, dp, ctypes.c_double, dp]
         L.ora_observe.argtypes = [ctypes.c_void_p, dp, ctypes.c_int64,
                                   ctypes.POINTER(Observation)]
@@ -256,9 +259,12 @@ class System:
         return (E, pt) if per_term else E
 
     def depondt_step(self, n, alpha, dt, T=0.0, seed=0, step=0, replica=0) -> np.ndarray:
+        return self.llg_step(n, alpha, dt, T, seed, step, replica, "depondt")
+
+    def llg_step(self, n, alpha, dt, T=0.0, seed=0, step=0, replica=0, solver="depondt") -> np.ndarray:
         n = self._spins(n).copy()
-        p = LLGParams(alpha, dt, T, seed, replica)
-        lib().ora_depondt_step(self._p, _dp(n), ctypes.byref(p), step)
+        p = LLGParams(alpha, dt, T, seed, replica, SOLVERS[solver])
+        lib().ora_llg_step(self._p, _dp(n), ctypes.byref(p), step)
         return n
 
     def observe(self, n, step=0) -> dict:
@@ -268,9 +274,9 @@ class System:
         return _obs_dict(o)
 
     def run(self, n, alpha, dt, n_steps, T=0.0, seed=0, step0=0, replica=0,
-            observe_every=0):
+            observe_every=0, solver="depondt"):
         n = self._spins(n).copy()
-        p = LLGParams(alpha, dt, T, seed, replica)
+        p = LLGParams(alpha, dt, T, seed, replica, SOLVERS[solver])
         n_obs = n_steps // observe_every if observe_every > 0 else 0
         obs = (Observation * max(n_obs, 1))()
         k = lib().ora_run(self._p, _dp(n), ctypes.byref(p), step0, n_steps, observe_every, obs)

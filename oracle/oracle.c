@@ -556,6 +556,146 @@ void ora_depondt_step(const ora_system *s, double *n, const ora_llg_params *p, u
     free(Bth);
 }
 
+/* Effective field in Tesla of every site with its thermal part:
+ * Bt_i = -g_i / (mu_i mu_B) + sigma_i eta_i (eta drawn at `step`). */
+static void field_tesla(const ora_system *s, const double *n, const ora_llg_params *p, uint64_t step,
+                        double *g, double *Bt) {
+    const int64_t N = s->N;
+    const double muB = ora_const_mu_B();
+    ora_gradient(s, n, g, NULL);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double mu = s->ham.mu[basis_of(s, i)];
+        double sigma = thermal_sigma(p->alpha, p->T, mu, p->dt);
+        double eta[3] = {0.0, 0.0, 0.0};
+        if (sigma > 0.0) ora_thermal_normals(p->seed, step, (uint32_t)i, p->replica, eta);
+        for (int k = 0; k < 3; ++k) Bt[k * N + i] = -g[k * N + i] / (mu * muB) + sigma * eta[k];
+    }
+}
+
+/* Heun's method (Appendix B, first part) for dn/dt = f(n) = n x A(n):
+ *   n^p = n + dt f(n);   n(t+dt) = n + dt (f(n) + f(n^p)) / 2.
+ * Readings: the same thermal normals in both stages; the scheme does not
+ * keep |n|, and both n^p and n(t+dt) are renormalised at every step (with
+ * this choice the single-spin precession of Sec. III.C, B = 1 T, alpha = 0.1,
+ * dt = 10 fs, stays within the 1e-6 of the exact solution the paper quotes
+ * for Heun's method; without renormalising n^p it does not). */
+void ora_heun_step(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step) {
+    const int64_t N = s->N;
+    double *g = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    double *Bt = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    double *np_ = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    double *f0 = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    field_tesla(s, n, p, step, g, Bt);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double ni[3], Bi[3], Ai[3], fi[3];
+        load(n, N, i, ni);
+        load(Bt, N, i, Bi);
+        llg_A(ni, Bi, p->alpha, Ai);
+        cross3(ni, Ai, fi);
+        double pi[3];
+        for (int k = 0; k < 3; ++k) {
+            f0[k * N + i] = fi[k];
+            pi[k] = ni[k] + p->dt * fi[k];
+        }
+        const double r = norm3(pi);
+        for (int k = 0; k < 3; ++k) np_[k * N + i] = pi[k] / r;
+    }
+    field_tesla(s, np_, p, step, g, Bt);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double ni[3], npi[3], Bi[3], Ap[3], fp[3], out[3];
+        load(n, N, i, ni);
+        load(np_, N, i, npi);
+        load(Bt, N, i, Bi);
+        llg_A(npi, Bi, p->alpha, Ap);
+        cross3(npi, Ap, fp);
+        for (int k = 0; k < 3; ++k) out[k] = ni[k] + 0.5 * p->dt * (f0[k * N + i] + fp[k]);
+        const double r = norm3(out);
+        for (int k = 0; k < 3; ++k) n[k * N + i] = out[k] / r;
+    }
+    free(g);
+    free(Bt);
+    free(np_);
+    free(f0);
+}
+
+/* Solution x of (I + skew(w)) x = a by Cramer's rule (Appendix C):
+ * M = [[1, -wz, wy], [wz, 1, -wx], [-wy, wx, 1]], x_k = det(M^k) / det(M),
+ * M^k = M with column k replaced by a. */
+static double det3(const double m[9]) {
+    return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+           m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+static void sib_solve(const double w[3], const double a[3], double x[3]) {
+    const double M[9] = {1.0, -w[2], w[1], w[2], 1.0, -w[0], -w[1], w[0], 1.0};
+    const double d = det3(M);
+    for (int k = 0; k < 3; ++k) {
+        double Mk[9];
+        for (int q = 0; q < 9; ++q) Mk[q] = M[q];
+        for (int r = 0; r < 3; ++r) Mk[3 * r + k] = a[r];
+        x[k] = det3(Mk) / d;
+    }
+}
+
+/* One implicit-midpoint stage with a frozen field: the x solving
+ * x = n + dt (n + x)/2 x A, i.e. (I + skew(w)) x = n + n x w, w = dt A / 2.
+ * Reading: the printed matrix M carries A; consistency with the midpoint
+ * equation it solves requires A dt / 2. */
+static void sib_stage(const double n[3], const double A[3], double dt, double x[3]) {
+    double w[3], nxw[3], a[3];
+    for (int k = 0; k < 3; ++k) w[k] = 0.5 * dt * A[k];
+    cross3(n, w, nxw);
+    for (int k = 0; k < 3; ++k) a[k] = n[k] + nxw[k];
+    sib_solve(w, a, x);
+}
+
+/* Semi-implicit scheme B (Appendix C): predictor with A(t, {n}), corrector
+ * with A at the midpoint spins m = (n + n^p)/2 (also in the damping term of
+ * site i).  Readings: the same thermal normals in both stages; m is not
+ * renormalised; the midpoint structure keeps |n|, no renormalisation. */
+void ora_sib_step(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step) {
+    const int64_t N = s->N;
+    double *g = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    double *Bt = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    double *m = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    field_tesla(s, n, p, step, g, Bt);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double ni[3], Bi[3], Ai[3], npi[3];
+        load(n, N, i, ni);
+        load(Bt, N, i, Bi);
+        llg_A(ni, Bi, p->alpha, Ai);
+        sib_stage(ni, Ai, p->dt, npi);
+        for (int k = 0; k < 3; ++k) m[k * N + i] = 0.5 * (ni[k] + npi[k]);
+    }
+    field_tesla(s, m, p, step, g, Bt);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double ni[3], mi[3], Bi[3], Am[3], out[3];
+        load(n, N, i, ni);
+        load(m, N, i, mi);
+        load(Bt, N, i, Bi);
+        llg_A(mi, Bi, p->alpha, Am);
+        sib_stage(ni, Am, p->dt, out);
+        for (int k = 0; k < 3; ++k) n[k * N + i] = out[k];
+    }
+    free(g);
+    free(Bt);
+    free(m);
+}
+
+void ora_llg_step(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step) {
+    if (p->solver == ORA_SOLVER_HEUN)
+        ora_heun_step(s, n, p, step);
+    else if (p->solver == ORA_SOLVER_SIB)
+        ora_sib_step(s, n, p, step);
+    else
+        ora_depondt_step(s, n, p, step);
+}
+
 /* Observables: energy with per-term split, maximum torque |n x dH/dn|,
  * mean spin, maximum deviation of |n| from 1. */
 void ora_observe(const ora_system *s, const double *n, int64_t step, ora_observation *obs) {
@@ -586,7 +726,7 @@ int64_t ora_run(const ora_system *s, double *n, const ora_llg_params *p, uint64_
                 int64_t n_steps, int64_t observe_every, ora_observation *obs) {
     int64_t n_obs = 0;
     for (int64_t t = 0; t < n_steps; ++t) {
-        ora_depondt_step(s, n, p, step0 + (uint64_t)t);
+        ora_llg_step(s, n, p, step0 + (uint64_t)t);
         if (observe_every > 0 && (t + 1) % observe_every == 0 && obs)
             ora_observe(s, n, (int64_t)step0 + t + 1, &obs[n_obs++]);
     }

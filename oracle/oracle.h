@@ -91,17 +91,26 @@ void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 void ora_thermal_normals(uint64_t seed, uint64_t step, uint32_t site, uint32_t replica,
                          double eta[3]);
 
+enum { ORA_SOLVER_DEPONDT = 0, ORA_SOLVER_HEUN = 1, ORA_SOLVER_SIB = 2 };
+
 typedef struct {
     double alpha;
     double dt;       /* ps */
     double T;        /* K */
     uint64_t seed;
     uint32_t replica;
+    int32_t solver;  /* ORA_SOLVER_* */
 } ora_llg_params;
 
 /* One Depondt step at step counter `step` (used as the Philox counter). n is
  * updated in place. */
 void ora_depondt_step(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step);
+/* One step of Heun's method with renormalisation (Appendix B, first part). */
+void ora_heun_step(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step);
+/* One step of the semi-implicit midpoint scheme SIB (Appendix C). */
+void ora_sib_step(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step);
+/* One step of the solver p->solver. */
+void ora_llg_step(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step);
 /* Rotation of one vector about omega by |omega|*dt (exposed for tests). */
 void ora_rotate(const double n[3], const double omega[3], double dt, double out[3]);
 
@@ -115,7 +124,7 @@ typedef struct {
 } ora_observation;
 
 void ora_observe(const ora_system *s, const double *n, int64_t step, ora_observation *obs);
-/* n_steps Depondt steps starting at step counter step0; an observation is
+/* n_steps steps of p->solver starting at step counter step0; an observation is
  * recorded after every observe_every steps (if > 0).  Returns the number of
  * observations written. */
 int64_t ora_run(const ora_system *s, double *n, const ora_llg_params *p, uint64_t step0,
