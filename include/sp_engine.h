@@ -87,6 +87,18 @@ typedef struct {
                                 SP_E_UNSUPPORTED from sp_set_hamiltonian */
 } sp_hamiltonian;
 
+/* Integrators of dn/dt = n x A (Sec. III.C):
+ * SP_SOLVER_DEPONDT  Depondt's rotation form of Heun's scheme (Appendix B):
+ *                    n^p = R(A(n)) n, n' = R((A(n) + A(n^p))/2) n;
+ * SP_SOLVER_HEUN     Heun's method (Appendix B): n^p = n + dt n x A(n) and
+ *                    n' = n + dt (n x A(n) + n^p x A(n^p))/2, both stages
+ *                    renormalised;
+ * SP_SOLVER_SIB      the semi-implicit midpoint scheme B (Appendix C): each
+ *                    stage solves x = n + dt (n + x)/2 x A with A frozen,
+ *                    first at n, then at the midpoint (n + n^p)/2.
+ * All three use the same thermal normals in both stages. */
+enum sp_solver { SP_SOLVER_DEPONDT = 0, SP_SOLVER_HEUN = 1, SP_SOLVER_SIB = 2 };
+
 /* LLG parameters (Sec. III.C).  T > 0 adds the stochastic thermal field
  * sqrt(2 alpha k_B T / (gamma mu_i mu_B dt)) eta_i, eta_i three standard
  * normals per site and step from Philox4x32-10 with counter
@@ -98,6 +110,7 @@ typedef struct {
     double T_K;              /* temperature, >= 0 */
     uint64_t seed;           /* Philox key */
     uint32_t replica;        /* Philox counter word 3 (replica index) */
+    int32_t solver;          /* sp_solver; replica batches take SP_SOLVER_DEPONDT only */
 } sp_llg_params;
 
 /* Observables of one spin state.  per_term: Zeeman, anisotropy, exchange,

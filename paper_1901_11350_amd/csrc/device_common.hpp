@@ -126,6 +126,35 @@ __device__ __forceinline__ V3<T> llg_A(V3<T> n, V3<T> B, T gp, T alpha) {
     return V3<T>{-gp * (B.x + alpha * nxB.x), -gp * (B.y + alpha * nxB.y), -gp * (B.z + alpha * nxB.z)};
 }
 
+// Integrators of the LLG equation dn/dt = n x A (Sec. III.C; Appendices B, C).
+enum Solver { SOLVER_DEPONDT = 0, SOLVER_HEUN = 1, SOLVER_SIB = 2 };
+
+template <typename T>
+__device__ __forceinline__ V3<T> normalize3(V3<T> v) {
+    const T r2 = v.x * v.x + v.y * v.y + v.z * v.z;
+    T r;
+    if constexpr (sizeof(T) == 4) {
+        r = __builtin_amdgcn_rsqf(r2);
+    } else {
+        r = T(1) / sqrt(r2);
+    }
+    return V3<T>{v.x * r, v.y * r, v.z * r};
+}
+
+// Implicit-midpoint stage with the rotation vector A frozen: the x solving
+// x = n + dt (n + x)/2 x A, i.e. (I + [w]x) x = n + n x w with w = A dt/2
+// (Appendix C).  The 3x3 system is the Cayley transform of w; its inverse is
+// (I - [w]x + w w^T) / (1 + |w|^2).
+template <typename T>
+__device__ __forceinline__ V3<T> sib_stage(V3<T> n, V3<T> A, T dt) {
+    const V3<T> w = (T(0.5) * dt) * A;
+    const V3<T> a = n + cross(n, w);
+    const V3<T> wxa = cross(w, a);
+    const T wa = dot(w, a);
+    const T inv = T(1) / (T(1) + dot(w, w));
+    return V3<T>{(a.x - wxa.x + w.x * wa) * inv, (a.y - wxa.y + w.y * wa) * inv, (a.z - wxa.z + w.z * wa) * inv};
+}
+
 template <typename T>
 __device__ __forceinline__ V3<T> renorm_if_float(V3<T> n) {
     if constexpr (sizeof(T) == 4) {

@@ -446,40 +446,58 @@ sp::ShapeCoef<T> shape_coef_for(const sp_engine* e) {
     return C;
 }
 
-template <typename T, int S, int NDMI, int TX, int TY, int NT>
+template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER>
 void go_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     sp::TileMap M{};
     M.tiles_x = (e->geo.n[0] + TX - 1) / TX;
     M.tiles_y = (e->geo.n[1] + TY - 1) / TY;
     const int ntiles = M.tiles_x * M.tiles_y;
     M.xcd_bands = (ntiles >= 8 && ntiles % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL((sp::k_fused2d_shape<T, S, NDMI, TX, TY, NT>), dim3((unsigned)ntiles), dim3(NT), 0, e->stream,
+    hipLaunchKernelGGL((sp::k_fused2d_shape<T, S, NDMI, TX, TY, NT, SOLVER>), dim3((unsigned)ntiles), dim3(NT), 0, e->stream,
                        shape_coef_for<T, S>(e), make_site2d<T>(e, p), make_llg<T>(p, step, p->replica), M, e->d_flag,
                        static_cast<const T*>(nin), static_cast<T*>(nout));
 }
 
-template <typename T, int S, int TX, int TY, int NT>
+template <typename T, int S, int TX, int TY, int NT, int SOLVER>
 void go_ndmi(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     if (e->shape_ndmi)
-        go_shape<T, S, sp::ShapeTab<S>::NB0, TX, TY, NT>(e, p, step, nin, nout);
+        go_shape<T, S, sp::ShapeTab<S>::NB0, TX, TY, NT, SOLVER>(e, p, step, nin, nout);
     else
-        go_shape<T, S, 0, TX, TY, NT>(e, p, step, nin, nout);
+        go_shape<T, S, 0, TX, TY, NT, SOLVER>(e, p, step, nin, nout);
 }
 
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, int SOLVER = sp::SOLVER_DEPONDT>
 void go_tile(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     switch (e->shape) {
-        case sp::SH_SQ1: go_ndmi<T, sp::SH_SQ1, TX, TY, NT>(e, p, step, nin, nout); break;
-        case sp::SH_SQ2: go_ndmi<T, sp::SH_SQ2, TX, TY, NT>(e, p, step, nin, nout); break;
-        case sp::SH_SQ3: go_ndmi<T, sp::SH_SQ3, TX, TY, NT>(e, p, step, nin, nout); break;
-        case sp::SH_TRI1: go_ndmi<T, sp::SH_TRI1, TX, TY, NT>(e, p, step, nin, nout); break;
-        case sp::SH_TRI2: go_ndmi<T, sp::SH_TRI2, TX, TY, NT>(e, p, step, nin, nout); break;
-        default: go_ndmi<T, sp::SH_TRI3, TX, TY, NT>(e, p, step, nin, nout); break;
+        case sp::SH_SQ1: go_ndmi<T, sp::SH_SQ1, TX, TY, NT, SOLVER>(e, p, step, nin, nout); break;
+        case sp::SH_SQ2: go_ndmi<T, sp::SH_SQ2, TX, TY, NT, SOLVER>(e, p, step, nin, nout); break;
+        case sp::SH_SQ3: go_ndmi<T, sp::SH_SQ3, TX, TY, NT, SOLVER>(e, p, step, nin, nout); break;
+        case sp::SH_TRI1: go_ndmi<T, sp::SH_TRI1, TX, TY, NT, SOLVER>(e, p, step, nin, nout); break;
+        case sp::SH_TRI2: go_ndmi<T, sp::SH_TRI2, TX, TY, NT, SOLVER>(e, p, step, nin, nout); break;
+        default: go_ndmi<T, sp::SH_TRI3, TX, TY, NT, SOLVER>(e, p, step, nin, nout); break;
     }
 }
 
+// Heun and SIB run on one tile configuration per precision.
+constexpr const char* kSolverTileF32 = "64x16x1024";
+constexpr const char* kSolverTileF64 = "32x16x256";
+
 template <typename T>
 void launch_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    if (p->solver == SP_SOLVER_HEUN) {
+        if constexpr (sizeof(T) == 8)
+            go_tile<T, 32, 16, 256, sp::SOLVER_HEUN>(e, p, step, nin, nout);
+        else
+            go_tile<T, 64, 16, 1024, sp::SOLVER_HEUN>(e, p, step, nin, nout);
+        return;
+    }
+    if (p->solver == SP_SOLVER_SIB) {
+        if constexpr (sizeof(T) == 8)
+            go_tile<T, 32, 16, 256, sp::SOLVER_SIB>(e, p, step, nin, nout);
+        else
+            go_tile<T, 64, 16, 1024, sp::SOLVER_SIB>(e, p, step, nin, nout);
+        return;
+    }
     if constexpr (sizeof(T) == 8) {
         go_tile<T, 32, 16, 256>(e, p, step, nin, nout);
     } else {
@@ -502,7 +520,7 @@ int launch_step(sp_engine* e, const sp_llg_params* p, uint64_t step, const void*
         HIPCHK(e, hipGetLastError());
         return SP_OK;
     }
-    if (std::strcmp(e->path, "fused2d") == 0) {
+    if (std::strcmp(e->path, "fused2d") == 0 && p->solver == SP_SOLVER_DEPONDT) {
         if (e->R <= 1)
             launch_fused2d<T, 32, 16, 1>(e, p, step, nin, nout);
         else
@@ -521,17 +539,38 @@ int launch_step(sp_engine* e, const sp_llg_params* p, uint64_t step, const void*
         if (rc) return rc;
         gdd = e->d_gdd;
     }
-    hipLaunchKernelGGL((sp::k_predict<T>), dim3(blocks_for(e->N)), dim3(256), 0, e->stream, L, C, P, A, e->d_flag,
-                       static_cast<const T*>(nin), static_cast<const T*>(gdd), static_cast<T*>(e->d_np),
-                       static_cast<T*>(e->d_A));
+    const dim3 grid(blocks_for(e->N)), block(256);
+    if (p->solver == SP_SOLVER_HEUN)
+        hipLaunchKernelGGL((sp::k_predict<T, sp::SOLVER_HEUN>), grid, block, 0, e->stream, L, C, P, A, e->d_flag,
+                           static_cast<const T*>(nin), static_cast<const T*>(gdd), static_cast<T*>(e->d_np),
+                           static_cast<T*>(e->d_A));
+    else if (p->solver == SP_SOLVER_SIB)
+        hipLaunchKernelGGL((sp::k_predict<T, sp::SOLVER_SIB>), grid, block, 0, e->stream, L, C, P, A, e->d_flag,
+                           static_cast<const T*>(nin), static_cast<const T*>(gdd), static_cast<T*>(e->d_np),
+                           static_cast<T*>(e->d_A));
+    else
+        hipLaunchKernelGGL((sp::k_predict<T, sp::SOLVER_DEPONDT>), grid, block, 0, e->stream, L, C, P, A, e->d_flag,
+                           static_cast<const T*>(nin), static_cast<const T*>(gdd), static_cast<T*>(e->d_np),
+                           static_cast<T*>(e->d_A));
     if (e->ham.ddi) {
+        // the corrector's dipole field is evaluated on what the predictor
+        // stored: n^p (Depondt, Heun) or the midpoint (SIB)
         int rc = launch_dipole<T>(e, e->d_np, e->d_gddp);
         if (rc) return rc;
         gddp = e->d_gddp;
     }
-    hipLaunchKernelGGL((sp::k_correct<T>), dim3(blocks_for(e->N)), dim3(256), 0, e->stream, L, C, P, A, e->d_flag,
-                       static_cast<const T*>(nin), static_cast<const T*>(e->d_np), static_cast<const T*>(gddp),
-                       static_cast<const T*>(e->d_A), static_cast<T*>(nout));
+    if (p->solver == SP_SOLVER_HEUN)
+        hipLaunchKernelGGL((sp::k_correct<T, sp::SOLVER_HEUN>), grid, block, 0, e->stream, L, C, P, A, e->d_flag,
+                           static_cast<const T*>(nin), static_cast<const T*>(e->d_np), static_cast<const T*>(gddp),
+                           static_cast<const T*>(e->d_A), static_cast<T*>(nout));
+    else if (p->solver == SP_SOLVER_SIB)
+        hipLaunchKernelGGL((sp::k_correct<T, sp::SOLVER_SIB>), grid, block, 0, e->stream, L, C, P, A, e->d_flag,
+                           static_cast<const T*>(nin), static_cast<const T*>(e->d_np), static_cast<const T*>(gddp),
+                           static_cast<const T*>(e->d_A), static_cast<T*>(nout));
+    else
+        hipLaunchKernelGGL((sp::k_correct<T, sp::SOLVER_DEPONDT>), grid, block, 0, e->stream, L, C, P, A, e->d_flag,
+                           static_cast<const T*>(nin), static_cast<const T*>(e->d_np), static_cast<const T*>(gddp),
+                           static_cast<const T*>(e->d_A), static_cast<T*>(nout));
     HIPCHK(e, hipGetLastError());
     return SP_OK;
 }
@@ -549,6 +588,8 @@ int check_llg(sp_engine* e, const sp_llg_params* p) {
     if (!(p->alpha >= 0.0) || !std::isfinite(p->alpha)) return fail(e, SP_E_ARG, "alpha must be finite and >= 0");
     if (!(p->dt_ps > 0.0) || !std::isfinite(p->dt_ps)) return fail(e, SP_E_ARG, "dt must be finite and > 0");
     if (!(p->T_K >= 0.0) || !std::isfinite(p->T_K)) return fail(e, SP_E_ARG, "T must be finite and >= 0");
+    if (p->solver != SP_SOLVER_DEPONDT && p->solver != SP_SOLVER_HEUN && p->solver != SP_SOLVER_SIB)
+        return fail(e, SP_E_ARG, "solver must be SP_SOLVER_DEPONDT, SP_SOLVER_HEUN or SP_SOLVER_SIB");
     return SP_OK;
 }
 
@@ -1148,10 +1189,16 @@ int sp_autotune(sp_engine* e, const sp_llg_params* p, int n_steps, double* ms_pe
     if (n_steps < 1 || n_steps > 100000) return fail(e, SP_E_ARG, "n_steps must be in 1..100000");
     (void)hipSetDevice(e->device);
     std::vector<std::string> cands{"twopass"};
-    if (e->fused_ok) cands.push_back("fused2d");
-    if (e->shape >= 0) {
-        const int ncfg = e->precision == SP_F64 ? kNumTileCfgsF64 : kNumTileCfgs;
-        for (int k = 0; k < ncfg; ++k) cands.push_back(std::string("shape2d/") + kTileCfgs[k].name);
+    if (p->solver != SP_SOLVER_DEPONDT) {
+        // Heun and SIB: the two-pass kernels or the one tile shape they are built for
+        if (e->shape >= 0)
+            cands.push_back(std::string("shape2d/") + (e->precision == SP_F64 ? kSolverTileF64 : kSolverTileF32));
+    } else {
+        if (e->fused_ok) cands.push_back("fused2d");
+        if (e->shape >= 0) {
+            const int ncfg = e->precision == SP_F64 ? kNumTileCfgsF64 : kNumTileCfgs;
+            for (int k = 0; k < ncfg; ++k) cands.push_back(std::string("shape2d/") + kTileCfgs[k].name);
+        }
     }
     const std::string keep_label = e->path_label;
     const uint64_t keep_step = e->step;
@@ -1495,6 +1542,7 @@ int sp_batch_add(sp_batch* b, sp_engine* e, const sp_llg_params* p) {
     if (e->precision != SP_F32) return bfail(b, SP_E_UNSUPPORTED, "batches are FP32");
     if (e->shape < 0) return bfail(b, SP_E_UNSUPPORTED, "replica lattice does not match a compile-time stencil");
     if (check_llg(e, p)) return bfail(b, SP_E_ARG, e->err);
+    if (p->solver != SP_SOLVER_DEPONDT) return bfail(b, SP_E_UNSUPPORTED, "batches run Depondt's scheme only");
     if (!b->has_template) {
         b->ham = e->ham;
         b->all_bonds = e->all_bonds;

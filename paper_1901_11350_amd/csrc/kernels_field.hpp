@@ -147,9 +147,13 @@ __global__ void __launch_bounds__(256) k_gradient(Lattice L, BondCoef<T> C, Phys
 }
 
 // ----------------------------------------------------------- two-pass path
-// Predictor: n^p_i = R(A_i(n)) n_i with A_i = -gp (B_i + alpha n_i x B_i),
-// B_i = -g_i/(mu_i mu_B) + sigma_i eta_i.  Stores n^p and A.
-template <typename T>
+// Predictor, with A_i = -gp (B_i + alpha n_i x B_i), B_i = -g_i/(mu_i mu_B)
+// + sigma_i eta_i:
+//   Depondt: np = R(A_i(n)) n_i, Aout = A_i;
+//   Heun:    np = normalised n_i + dt n_i x A_i, Aout = n_i x A_i;
+//   SIB:     np = midpoint (n_i + x_i)/2 with x_i the implicit-midpoint
+//            stage with A_i frozen (Appendix C); Aout unused.
+template <typename T, int SOLVER>
 __global__ void __launch_bounds__(256) k_predict(Lattice L, BondCoef<T> C, Phys<T> P, LLGArgs<T> A,
                                                  const int* __restrict__ abort_flag,
                                                  const T* __restrict__ n, const T* __restrict__ gdd,
@@ -165,12 +169,23 @@ __global__ void __launch_bounds__(256) k_predict(Lattice L, BondCoef<T> C, Phys<
     V3<T> B = (-inv_m) * g;
     if (A.thermal) B = B + P.sigma[beta] * normals3(thermal_bits(A.key, (uint32_t)i), T(0));
     const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
-    store3(Aout, L.N, i, Ai);
-    store3(np, L.N, i, renorm_if_float(rotate(ni, (T(-1)) * Ai, A.dt)));
+    if constexpr (SOLVER == SOLVER_HEUN) {
+        const V3<T> f = cross(ni, Ai);
+        store3(Aout, L.N, i, f);
+        store3(np, L.N, i, normalize3(ni + A.dt * f));
+    } else if constexpr (SOLVER == SOLVER_SIB) {
+        store3(np, L.N, i, T(0.5) * (ni + sib_stage(ni, Ai, A.dt)));
+    } else {
+        store3(Aout, L.N, i, Ai);
+        store3(np, L.N, i, renorm_if_float(rotate(ni, (T(-1)) * Ai, A.dt)));
+    }
 }
 
-// Corrector: A^p from (n^p, g(n^p), same eta); n(t+dt) = R((A + A^p)/2) n.
-template <typename T>
+// Corrector: A^p from (np, g(np), same eta), then
+//   Depondt: n(t+dt) = R((A + A^p)/2) n;
+//   Heun:    n(t+dt) = normalised n + dt (f + np x A^p)/2;
+//   SIB:     n(t+dt) = midpoint stage of n with A(m) frozen (np holds m).
+template <typename T, int SOLVER>
 __global__ void __launch_bounds__(256) k_correct(Lattice L, BondCoef<T> C, Phys<T> P, LLGArgs<T> A,
                                                  const int* __restrict__ abort_flag,
                                                  const T* __restrict__ n, const T* __restrict__ np,
@@ -187,9 +202,17 @@ __global__ void __launch_bounds__(256) k_correct(Lattice L, BondCoef<T> C, Phys<
     V3<T> B = (-inv_m) * g;
     if (A.thermal) B = B + P.sigma[beta] * normals3(thermal_bits(A.key, (uint32_t)i), T(0));
     const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
-    const V3<T> A0 = load3(Ain, L.N, i);
-    const V3<T> w = (T(-0.5)) * (A0 + Ap);
-    store3(nout, L.N, i, renorm_if_float(rotate(load3(n, L.N, i), w, A.dt)));
+    const V3<T> ni = load3(n, L.N, i);
+    if constexpr (SOLVER == SOLVER_HEUN) {
+        const V3<T> f0 = load3(Ain, L.N, i);
+        store3(nout, L.N, i, normalize3(ni + (T(0.5) * A.dt) * (f0 + cross(npi, Ap))));
+    } else if constexpr (SOLVER == SOLVER_SIB) {
+        store3(nout, L.N, i, renorm_if_float(sib_stage(ni, Ap, A.dt)));
+    } else {
+        const V3<T> A0 = load3(Ain, L.N, i);
+        const V3<T> w = (T(-0.5)) * (A0 + Ap);
+        store3(nout, L.N, i, renorm_if_float(rotate(ni, w, A.dt)));
+    }
 }
 
 // ------------------------------------------------------------ fused 2D path

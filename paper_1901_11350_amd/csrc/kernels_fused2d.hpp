@@ -248,9 +248,14 @@ __device__ __forceinline__ void ring_cell(int h, int& px, int& py) {
 }
 
 // Predictor of one predictor-frame cell (px, py) with its thermal field
-// Bth: rotation vector A of the site, n^p written to sP.  Cells that fall
-// outside an open lattice hold a zero spin.
-template <typename T, int S, int NDMI, int TX, int TY>
+// Bth.  Writes to sP what the corrector's field is evaluated on and returns
+// what the corrector needs of the site itself:
+//   Depondt: n^p = R(A) n, returns A;
+//   Heun:    n^p = (n + dt n x A) / |...|, returns f = n x A;
+//   SIB:     x solves the midpoint stage with A frozen; sP holds the
+//            midpoint m = (n + x)/2 (Appendix C), returns nothing.
+// Cells that fall outside an open lattice hold a zero spin.
+template <typename T, int S, int NDMI, int TX, int TY, int SOLVER>
 __device__ __forceinline__ V3<T> predict_cell(const ShapeCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int x0,
                                               int y0, int px, int py, TileLDS<T, S, TX, TY>& L, V3<T> Bth) {
     using TL = TileLDS<T, S, TX, TY>;
@@ -258,28 +263,37 @@ __device__ __forceinline__ V3<T> predict_cell(const ShapeCoef<T>& C, const Site2
     bool in;
     cell_site<T, S, TX, TY>(Q, x0, y0, px, py, in);
     V4<T> out{T(0), T(0), T(0), T(0)};
-    V3<T> Ai{T(0), T(0), T(0)};
+    V3<T> keep{T(0), T(0), T(0)};
     if (in) {
         const int c = (py + R) * WN + (px + R);
         const V4<T> n4 = L.sN[c];
         const V3<T> ni{n4.x, n4.y, n4.z};
         const V3<T> g = shape_field_aos<T, S, NDMI, WN>(C, Q, L.sN, c, ni);
         const V3<T> B = (-Q.inv_mumuB) * g + Bth;
-        Ai = llg_A(ni, B, A.gp, A.alpha);
-        // n^p only feeds the corrector's field; its FP32 length error
-        // (~1 ulp) is left in place, only n(t+dt) is renormalised.
-        const V3<T> o = rotate_fast(ni, T(-1) * Ai, A.dt);
+        const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
+        V3<T> o;
+        if constexpr (SOLVER == SOLVER_HEUN) {
+            keep = cross(ni, Ai);
+            o = normalize3(ni + A.dt * keep);
+        } else if constexpr (SOLVER == SOLVER_SIB) {
+            o = T(0.5) * (ni + sib_stage(ni, Ai, A.dt));
+        } else {
+            keep = Ai;
+            // n^p only feeds the corrector's field; its FP32 length error
+            // (~1 ulp) is left in place, only n(t+dt) is renormalised.
+            o = rotate_fast(ni, T(-1) * Ai, A.dt);
+        }
         out = V4<T>{o.x, o.y, o.z, T(0)};
     }
     L.sP[py * WP + px] = out;
-    return Ai;
+    return keep;
 }
 
 // One Depondt step of the TX x TY tile at (x0, y0) of one lattice.  Thread
 // t owns tile sites t + j NT: it computes their predictor, keeps A and the
 // thermal field in registers, and computes their corrector; the ring of
 // predictor cells around the tile is shared out over the threads between.
-template <typename T, int S, int NDMI, int TX, int TY, int NT>
+template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER = SOLVER_DEPONDT>
 __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A,
                                              int x0, int y0, const T* __restrict__ n, T* __restrict__ nout,
                                              TileLDS<T, S, TX, TY>& L) {
@@ -341,7 +355,7 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
     for (int j = 0; j < KPT; ++j) {
         const int t = tid + j * NT;
         const int ty = t / TX, tx = t - ty * TX;
-        keepA[j] = predict_cell<T, S, NDMI, TX, TY>(C, Q, A, x0, y0, tx + R, ty + R, L, keepB[j]);
+        keepA[j] = predict_cell<T, S, NDMI, TX, TY, SOLVER>(C, Q, A, x0, y0, tx + R, ty + R, L, keepB[j]);
     }
 #pragma unroll
     for (int k = 0; k < KRG; ++k) {
@@ -349,7 +363,7 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
         if (h < RING) {
             int px, py;
             ring_cell<R, TX, TY>(h, px, py);
-            predict_cell<T, S, NDMI, TX, TY>(C, Q, A, x0, y0, px, py, L, ringB[k]);
+            predict_cell<T, S, NDMI, TX, TY, SOLVER>(C, Q, A, x0, y0, px, py, L, ringB[k]);
         }
     }
     __syncthreads();
@@ -367,10 +381,20 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
         const V3<T> g = shape_field_aos<T, S, NDMI, WP>(C, Q, L.sP, c, npi);
         const V3<T> B = (-Q.inv_mumuB) * g + keepB[j];
         const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
-        const V3<T> w{T(-0.5) * (keepA[j].x + Ap.x), T(-0.5) * (keepA[j].y + Ap.y),
-                      T(-0.5) * (keepA[j].z + Ap.z)};
         const V4<T> n4 = L.sN[(ty + 2 * R) * WN + (tx + 2 * R)];
-        const V3<T> o = renorm_if_float(rotate_fast(V3<T>{n4.x, n4.y, n4.z}, w, A.dt));
+        const V3<T> ni{n4.x, n4.y, n4.z};
+        V3<T> o;
+        if constexpr (SOLVER == SOLVER_HEUN) {
+            // n + dt (f(n) + f(n^p)) / 2, renormalised
+            o = normalize3(ni + (T(0.5) * A.dt) * (keepA[j] + cross(npi, Ap)));
+        } else if constexpr (SOLVER == SOLVER_SIB) {
+            // npi is the midpoint m; A(m) drives the second midpoint stage
+            o = renorm_if_float(sib_stage(ni, Ap, A.dt));
+        } else {
+            const V3<T> w{T(-0.5) * (keepA[j].x + Ap.x), T(-0.5) * (keepA[j].y + Ap.y),
+                          T(-0.5) * (keepA[j].z + Ap.z)};
+            o = renorm_if_float(rotate_fast(ni, w, A.dt));
+        }
         const int gi = gx + gy * Q.na;
         nout[gi] = o.x;
         nout[N + gi] = o.y;
@@ -378,7 +402,7 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
     }
 }
 
-template <typename T, int S, int NDMI, int TX, int TY, int NT>
+template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER = SOLVER_DEPONDT>
 __global__ void __launch_bounds__(NT) k_fused2d_shape(ShapeCoef<T> C, Site2D<T> Q, LLGArgs<T> A, TileMap M,
                                                       const int* __restrict__ abort_flag, const T* __restrict__ n,
                                                       T* __restrict__ nout) {
@@ -388,7 +412,7 @@ __global__ void __launch_bounds__(NT) k_fused2d_shape(ShapeCoef<T> C, Site2D<T> 
     int tile = blockIdx.x;
     if (M.xcd_bands) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
     const int ty0 = tile / M.tiles_x;
-    fused2d_tile<T, S, NDMI, TX, TY, NT>(C, Q, A, (tile - ty0 * M.tiles_x) * TX, ty0 * TY, n, nout, L);
+    fused2d_tile<T, S, NDMI, TX, TY, NT, SOLVER>(C, Q, A, (tile - ty0 * M.tiles_x) * TX, ty0 * TY, n, nout, L);
 }
 
 // ------------------------------------------------------------ replica batch

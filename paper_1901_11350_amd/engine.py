@@ -63,7 +63,11 @@ class sp_hamiltonian(ctypes.Structure):
 
 class sp_llg_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("dt_ps", ctypes.c_double),
-                ("T_K", ctypes.c_double), ("seed", ctypes.c_uint64), ("replica", ctypes.c_uint32)]
+                ("T_K", ctypes.c_double), ("seed", ctypes.c_uint64), ("replica", ctypes.c_uint32),
+                ("solver", ctypes.c_int32)]
+
+
+SOLVERS = {"depondt": 0, "heun": 1, "sib": 2}   # sp_solver
 
 
 class sp_observation(ctypes.Structure):
@@ -295,13 +299,14 @@ class Engine:
         self._check(lib().sp_observe(self._h, ctypes.byref(o)))
         return obs_dict(o)
 
-    def llg_step(self, alpha: float, dt: float, T: float = 0.0, seed: int = 0, replica: int = 0):
-        p = sp_llg_params(alpha, dt, T, seed, replica)
+    def llg_step(self, alpha: float, dt: float, T: float = 0.0, seed: int = 0, replica: int = 0,
+                 solver: str = "depondt"):
+        p = sp_llg_params(alpha, dt, T, seed, replica, SOLVERS[solver])
         self._check(lib().sp_llg_step(self._h, ctypes.byref(p)))
 
     def run(self, alpha: float, dt: float, n_steps: int, T: float = 0.0, seed: int = 0,
-            observe_every: int = 0, check: bool = True, replica: int = 0):
-        p = sp_llg_params(alpha, dt, T, seed, replica)
+            observe_every: int = 0, check: bool = True, replica: int = 0, solver: str = "depondt"):
+        p = sp_llg_params(alpha, dt, T, seed, replica, SOLVERS[solver])
         n_obs = n_steps // observe_every if observe_every > 0 else 0
         obs = (sp_observation * max(n_obs, 1))()
         rc = lib().sp_run(self._h, ctypes.byref(p), n_steps, observe_every, obs if n_obs else None)
@@ -310,10 +315,11 @@ class Engine:
         res = [obs_dict(o) for o in obs[:n_obs]]
         return (res, rc) if not check else res
 
-    def autotune(self, alpha: float, dt: float, T: float = 0.0, seed: int = 0, n_steps: int = 50) -> float:
+    def autotune(self, alpha: float, dt: float, T: float = 0.0, seed: int = 0, n_steps: int = 50,
+                 solver: str = "depondt") -> float:
         """Time every allowed step path / tile configuration, keep the fastest;
         returns its milliseconds per step."""
-        p = sp_llg_params(alpha, dt, T, seed)
+        p = sp_llg_params(alpha, dt, T, seed, 0, SOLVERS[solver])
         ms = ctypes.c_double()
         self._check(lib().sp_autotune(self._h, ctypes.byref(p), n_steps, ctypes.byref(ms)))
         return ms.value
