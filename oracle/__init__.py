@@ -21,6 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 MAX_BASIS = 8
 MAX_SHELLS = 8
+MAX_GAUSS = 16
 MAX_BONDS = MAX_BASIS * 256
 
 
@@ -54,7 +55,11 @@ class Hamiltonian(ctypes.Structure):
                 ("n_dmi", ctypes.c_int),
                 ("D", ctypes.c_double * MAX_SHELLS),
                 ("dmi_kind", ctypes.c_int),
-                ("ddi", ctypes.c_int)]
+                ("ddi", ctypes.c_int),
+                ("n_gauss", ctypes.c_int),
+                ("gauss_a", ctypes.c_double * MAX_GAUSS),
+                ("gauss_sigma", ctypes.c_double * MAX_GAUSS),
+                ("gauss_c", ctypes.c_double * (3 * MAX_GAUSS))]
 
 
 class Bond(ctypes.Structure):
@@ -73,7 +78,10 @@ SOLVERS = {"depondt": 0, "heun": 1, "sib": 2}
 
 class GnebParams(ctypes.Structure):
     _fields_ = [("k_spring", ctypes.c_double), ("vp_dt", ctypes.c_double),
-                ("vp_mass", ctypes.c_double)]
+                ("vp_mass", ctypes.c_double), ("image_type", ctypes.POINTER(ctypes.c_int))]
+
+
+IMAGE_TYPES = {"normal": 0, "climbing": 1, "falling": 2}
 
 
 class Observation(ctypes.Structure):
@@ -193,6 +201,13 @@ def _hamiltonian(ham) -> Hamiltonian:
         h.D[s] = d
     h.dmi_kind = ham.dmi_kind
     h.ddi = 1 if ham.ddi else 0
+    gauss = getattr(ham, "gauss", ())
+    h.n_gauss = len(gauss)
+    for k, (a, sg, c) in enumerate(gauss):
+        h.gauss_a[k] = a
+        h.gauss_sigma[k] = sg
+        for q in range(3):
+            h.gauss_c[3 * k + q] = c[q]
     return h
 
 
@@ -291,7 +306,8 @@ class Gneb:
         self.s = system
         self.chain = np.ascontiguousarray(chain, dtype=np.float64).reshape(-1, 3, system.N).copy()
         self.M = self.chain.shape[0]
-        self.p = GnebParams(k_spring, vp_dt, vp_mass)
+        self.p = GnebParams(k_spring, vp_dt, vp_mass, None)
+        self._types = None
         self.v = np.zeros_like(self.chain)
         f = self.forces()
         self.F_prev = f["F"].copy()
@@ -306,6 +322,12 @@ class Gneb:
         lib().ora_gneb_forces(self.s._p, M, _dp(c), ctypes.byref(self.p), _dp(E), _dp(tau),
                               _dp(l), _dp(F))
         return {"E": E, "tau": tau, "l": l[: M - 1], "F": F}
+
+    def set_image_types(self, types):
+        """types: M entries of "normal", "climbing", "falling" (endpoints ignored)."""
+        arr = (ctypes.c_int * self.M)(*[IMAGE_TYPES[t] for t in types])
+        self._types = arr
+        self.p.image_type = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int))
 
     def iterate(self, n_iter: int):
         lib().ora_gneb_vp(self.s._p, self.M, _dp(self.chain), _dp(self.v), _dp(self.F_prev),

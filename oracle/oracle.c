@@ -229,6 +229,9 @@ static int build_neighbours(ora_system *s) {
 ora_system *ora_create(const ora_geometry *g, const ora_hamiltonian *h) {
     if (g->n_basis < 1 || g->n_basis > ORA_MAX_BASIS) return NULL;
     if (h->n_exch < 0 || h->n_exch > ORA_MAX_SHELLS || h->n_dmi < 0 || h->n_dmi > ORA_MAX_SHELLS) return NULL;
+    if (h->n_gauss < 0 || h->n_gauss > ORA_MAX_GAUSS) return NULL;
+    for (int k = 0; k < h->n_gauss; ++k)
+        if (!(h->gauss_sigma[k] > 0.0) || !(norm3(&h->gauss_c[3 * k]) > 0.0)) return NULL;
     for (int k = 0; k < 3; ++k)
         if (g->n_cells[k] < 1) return NULL;
     ora_system *s = (ora_system *)calloc(1, sizeof(ora_system));
@@ -328,6 +331,37 @@ void ora_dipole_gradient_sites(const ora_system *s, const double *n, const int64
     for (int64_t q = 0; q < n_req; ++q) dipole_gradient_at(s, n, sites[q], g_out + 3 * q);
 }
 
+/* Gaussian on-site potentials (Appendix G): energy of one spin and its
+ * gradient  d/dn a exp(-(1 - n.c)^2 / (2 s^2)) = a exp(...) (1 - n.c) / s^2 c.
+ * Reading: the centres c_k are directions (normalised here); the printed
+ * table lists them unnormalised. */
+static void gauss_centre(const ora_system *s, int k, double c[3]) {
+    const double *ck = &s->ham.gauss_c[3 * k];
+    const double r = norm3(ck);
+    for (int q = 0; q < 3; ++q) c[q] = ck[q] / r;
+}
+
+static double gauss_energy(const ora_system *s, const double n[3]) {
+    double e = 0.0;
+    for (int k = 0; k < s->ham.n_gauss; ++k) {
+        double c[3];
+        gauss_centre(s, k, c);
+        const double d = 1.0 - dot3(n, c), sg = s->ham.gauss_sigma[k];
+        e += s->ham.gauss_a[k] * exp(-d * d / (2.0 * sg * sg));
+    }
+    return e;
+}
+
+static void gauss_gradient_add(const ora_system *s, const double n[3], double g[3]) {
+    for (int k = 0; k < s->ham.n_gauss; ++k) {
+        double c[3];
+        gauss_centre(s, k, c);
+        const double d = 1.0 - dot3(n, c), sg = s->ham.gauss_sigma[k];
+        const double f = s->ham.gauss_a[k] * exp(-d * d / (2.0 * sg * sg)) * d / (sg * sg);
+        for (int q = 0; q < 3; ++q) g[q] += f * c[q];
+    }
+}
+
 /* Gradient dH/dn_i of the Hamiltonian (Sec. III.A) in the embedding space:
  *   Zeeman      -mu_i mu_B B
  *   anisotropy  -2 K (K_hat . n_i) K_hat
@@ -347,6 +381,7 @@ void ora_gradient(const ora_system *s, const double *n, double *g, double *terms
         const double *ax = &s->ham.K_axis[3 * beta];
         double kn = dot3(ax, ni);
         for (int k = 0; k < 3; ++k) gk[k] = -2.0 * s->ham.K[beta] * kn * ax[k];
+        gauss_gradient_add(s, ni, gk);
         for (int64_t q = s->nb_start[i]; q < s->nb_start[i + 1]; ++q) {
             const ora_bond *bd = &s->bonds[s->nb_bond[q]];
             double nj[3], c[3];
@@ -386,7 +421,7 @@ double ora_energy(const ora_system *s, const double *n, double *per_term) {
         load(n, N, i, ni);
         ez += -s->ham.mu[beta] * muB * dot3(s->ham.B, ni);
         double kn = dot3(&s->ham.K_axis[3 * beta], ni);
-        ek += -s->ham.K[beta] * kn * kn;
+        ek += -s->ham.K[beta] * kn * kn + gauss_energy(s, ni);
         for (int64_t q = s->nb_start[i]; q < s->nb_start[i + 1]; ++q) {
             const ora_bond *bd = &s->bonds[s->nb_bond[q]];
             double nj[3], c[3];
@@ -806,11 +841,19 @@ void ora_gneb_forces(const ora_system *s, int M, const double *chain, const ora_
         ora_gradient(s, x0, g, NULL);
         double gt = 0.0;
         for (int64_t k = 0; k < L; ++k) gt += g[k] * tv[k];
-        const double fs = p->k_spring * (l[v] - l[v - 1]);
+        /* climbing image (Sec. III.D): no spring, the gradient component
+         * along the path inverted, F = -grad E + 2 (grad E . tau) tau.
+         * Falling image: no spring, F = -grad E, so it relaxes into the
+         * nearest minimum.  Reading: the paper names the falling image but
+         * prints no force for it; the full energy force is its natural
+         * counterpart. */
+        const int type = p->image_type ? p->image_type[v] : ORA_IMAGE_NORMAL;
+        const double cpar = type == ORA_IMAGE_CLIMBING ? 2.0 : (type == ORA_IMAGE_FALLING ? 0.0 : 1.0);
+        const double fs = type == ORA_IMAGE_NORMAL ? p->k_spring * (l[v] - l[v - 1]) : 0.0;
         for (int64_t i = 0; i < N; ++i) {
             double n[3], fe[3];
             load(x0, N, i, n);
-            for (int c = 0; c < 3; ++c) fe[c] = -g[c * N + i] + gt * tv[c * N + i];
+            for (int c = 0; c < 3; ++c) fe[c] = -g[c * N + i] + cpar * gt * tv[c * N + i];
             double fn = dot3(fe, n);
             for (int c = 0; c < 3; ++c) Fv[c * N + i] = fe[c] - fn * n[c] + fs * tv[c * N + i];
         }

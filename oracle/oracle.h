@@ -29,6 +29,7 @@ extern "C" {
 #define ORA_MAX_BONDS_PER_BASIS 256
 
 enum { ORA_DMI_BULK = 1, ORA_DMI_INTERFACIAL = 2 };
+#define ORA_MAX_GAUSS 16
 
 typedef struct {
     double bravais[9];                 /* rows a1, a2, a3 (units of the lattice constant) */
@@ -50,6 +51,13 @@ typedef struct {
     double D[ORA_MAX_SHELLS];          /* meV per shell */
     int dmi_kind;                      /* ORA_DMI_BULK or ORA_DMI_INTERFACIAL */
     int ddi;                           /* 1: include dipole-dipole direct sum */
+    /* on-site Gaussian potentials sum_k a_k exp(-(1 - n.c_k)^2 / (2 sigma_k^2))
+     * on every site (the single-spin landscape of Appendix G); c_k are
+     * normalised internally; reported with the anisotropy energy */
+    int n_gauss;
+    double gauss_a[ORA_MAX_GAUSS];     /* meV */
+    double gauss_sigma[ORA_MAX_GAUSS];
+    double gauss_c[3 * ORA_MAX_GAUSS];
 } ora_hamiltonian;
 
 /* One directed bond of a basis atom: from basis atom `bi` in cell x to basis
@@ -133,10 +141,13 @@ int64_t ora_run(const ora_system *s, double *n, const ora_llg_params *p, uint64_
 /* ------------------------------------------------------------------ GNEB
  * Chain of M images (image-major: image v occupies chain[v*3N .. v*3N+3N),
  * each SoA).  Images 0 and M-1 are fixed. */
+enum { ORA_IMAGE_NORMAL = 0, ORA_IMAGE_CLIMBING = 1, ORA_IMAGE_FALLING = 2 };
+
 typedef struct {
     double k_spring;   /* spring constant (meV per rad) */
     double vp_dt;      /* velocity-projection time step */
     double vp_mass;    /* velocity-projection mass */
+    const int *image_type;  /* M entries of ORA_IMAGE_*, or NULL (all normal) */
 } ora_gneb_params;
 
 /* GNEB forces of every interior image (endpoints get zero force):

@@ -190,6 +190,20 @@ __global__ void __launch_bounds__(256) k_conv3x3_wgrad(int H, int W, const __bf1
 }
 
 // Fixed-order sum of per-tile partials: out[k] = sum_p part[p][k].
+// Sum of n_parts rows of length len, in two fixed-order stages: group g
+// (blockIdx.y) of k_sum_partials_stage adds rows [g*chunk, (g+1)*chunk) into
+// stage[g]; k_sum_partials then adds the groups in order.
+__global__ void __launch_bounds__(256) k_sum_partials_stage(int n_parts, int len, int chunk,
+                                                            const float* __restrict__ part,
+                                                            float* __restrict__ stage) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= len) return;
+    const int p0 = blockIdx.y * chunk, p1 = min(n_parts, p0 + chunk);
+    float s = 0.0f;
+    for (int p = p0; p < p1; ++p) s += part[(size_t)p * len + k];
+    stage[(size_t)blockIdx.y * len + k] = s;
+}
+
 __global__ void __launch_bounds__(256) k_sum_partials(int n_parts, int len, const float* __restrict__ part,
                                                       float* __restrict__ out) {
     const int k = blockIdx.x * 256 + threadIdx.x;
@@ -316,11 +330,17 @@ __global__ void __launch_bounds__(256) k_field_to_target(int H, int W, int L, co
 }
 
 // |t_b|^2 of each sample (one workgroup per sample, FP64 tree).
+// Squared norm of each sample (blockIdx.y) of length len: block x of
+// kNormChunks adds its contiguous chunk (FP64, fixed-order tree) into
+// part[sample * kNormChunks + x]; k_sample_norm2_final adds the chunks in order.
+constexpr int kNormChunks = 64;
 __global__ void __launch_bounds__(256) k_sample_norm2(int64_t len, const float* __restrict__ t,
-                                                      double* __restrict__ out) {
-    const float* tb = t + (size_t)blockIdx.x * len;
+                                                      double* __restrict__ part) {
+    const int64_t chunk = (len + kNormChunks - 1) / kNormChunks;
+    const int64_t k0 = (int64_t)blockIdx.x * chunk, k1 = k0 + chunk < len ? k0 + chunk : len;
+    const float* tb = t + (size_t)blockIdx.y * len;
     double s = 0.0;
-    for (int64_t k = threadIdx.x; k < len; k += 256) s += (double)tb[k] * tb[k];
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) s += (double)tb[k] * tb[k];
     __shared__ double red[256];
     red[threadIdx.x] = s;
     __syncthreads();
@@ -328,20 +348,30 @@ __global__ void __launch_bounds__(256) k_sample_norm2(int64_t len, const float* 
         if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * kNormChunks + blockIdx.x] = red[0];
+}
+
+__global__ void k_sample_norm2_final(int B, const double* __restrict__ part, double* __restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double s = 0.0;
+    for (int k = 0; k < kNormChunks; ++k) s += part[(size_t)b * kNormChunks + k];
+    out[b] = s;
 }
 
 // Residual check of a surrogate field at sampled sites: relative error
 // |g_s - exact_s| / |exact_s| over the samples; *need = (error > tol).
 // stats: [evaluations, fallbacks, last error, max error].
 // Sampled sites are offset + s * stride, s < n_sites.
+// One workgroup of 256 threads; thread t covers samples t, t + 256, ...; the
+// sums are reduced in a fixed-order tree.
 template <typename T>
-__global__ void k_surrogate_check(int N, int n_sites, int offset, int stride, const double* __restrict__ exact,
-                                  const T* __restrict__ g, double tol, int* __restrict__ need,
-                                  double* __restrict__ stats) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void __launch_bounds__(256) k_surrogate_check(int N, int n_sites, int offset, int stride,
+                                                         const double* __restrict__ exact,
+                                                         const T* __restrict__ g, double tol,
+                                                         int* __restrict__ need, double* __restrict__ stats) {
     double num = 0.0, den = 0.0;
-    for (int s = 0; s < n_sites; ++s) {
+    for (int s = threadIdx.x; s < n_sites; s += 256) {
         const int i = offset + s * stride;
         for (int c = 0; c < 3; ++c) {
             const double d = (double)g[(size_t)c * N + i] - exact[3 * s + c];
@@ -349,6 +379,20 @@ __global__ void k_surrogate_check(int N, int n_sites, int offset, int stride, co
             den += exact[3 * s + c] * exact[3 * s + c];
         }
     }
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = num;
+    red[1][threadIdx.x] = den;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + st];
+            red[1][threadIdx.x] += red[1][threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    num = red[0][0];
+    den = red[1][0];
     const double err = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? 1e300 : 0.0);
     const int f = (err > tol || !(err == err)) ? 1 : 0;
     *need = f;
@@ -358,34 +402,39 @@ __global__ void k_surrogate_check(int N, int n_sites, int offset, int stride, co
     stats[3] = fmax(stats[3], err);
 }
 
-// Exact dipole gradient (direct sum over all sources, FP32 two-level
-// accumulation) at a list of target sites, for the surrogate's residual check.
-// Target sites offset + s * stride, one workgroup per site.
+// Exact dipole gradient (direct sum over all sources) at a list of target
+// sites, for the surrogate's residual check.  Target sites offset + s *
+// stride, one 1024-thread workgroup per site; each thread accumulates its
+// sources in FP32, the per-thread sums are added in FP64 (fixed-order tree).
 template <typename T>
-__global__ void __launch_bounds__(256) k_dipole_at_sites(int N, const T* __restrict__ pos, const T* __restrict__ n,
-                                                         int offset, int stride, int n_sites, T mu, T Cdd,
-                                                         double* __restrict__ out) {
+__global__ void __launch_bounds__(1024) k_dipole_at_sites(int N, const T* __restrict__ pos, const T* __restrict__ n,
+                                                          int offset, int stride, int n_sites, T mu, T Cdd,
+                                                          double* __restrict__ out) {
     const int s = blockIdx.x;
     if (s >= n_sites) return;
     const int i = offset + s * stride;
     const T px = pos[i], py = pos[N + i], pz = pos[2 * N + i];
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int j = threadIdx.x; j < N; j += 256) {
+    T acc[3] = {T(0), T(0), T(0)};
+    for (int j = threadIdx.x; j < N; j += 1024) {
         const T rx = pos[j] - px, ry = pos[N + j] - py, rz = pos[2 * N + j] - pz;
         const T d2 = rx * rx + ry * ry + rz * rz;
-        if (!(d2 > T(0))) continue;
-        const T inv = T(1) / sqrt(d2);
+        T inv;
+        if constexpr (sizeof(T) == 4) {
+            inv = d2 > T(0) ? __builtin_amdgcn_rsqf(d2) : T(0);
+        } else {
+            inv = d2 > T(0) ? T(1) / sqrt(d2) : T(0);
+        }
         const T inv3 = inv * inv * inv;
         const T mx = n[j], my = n[N + j], mz = n[2 * N + j];
         const T sdot = T(3) * (mx * rx + my * ry + mz * rz) * inv * inv;
-        acc[0] += (double)((mx - sdot * rx) * inv3);
-        acc[1] += (double)((my - sdot * ry) * inv3);
-        acc[2] += (double)((mz - sdot * rz) * inv3);
+        acc[0] += (mx - sdot * rx) * inv3;
+        acc[1] += (my - sdot * ry) * inv3;
+        acc[2] += (mz - sdot * rz) * inv3;
     }
-    __shared__ double red[3][256];
-    for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = acc[c];
+    __shared__ double red[3][1024];
+    for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = (double)acc[c];
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
+    for (int st = 512; st > 0; st >>= 1) {
         if ((int)threadIdx.x < st)
             for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
         __syncthreads();

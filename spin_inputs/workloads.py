@@ -62,6 +62,8 @@ class Hamiltonian:
     # takes 2 (learned surrogate with residual check) and 3 (FFT convolution),
     # which define the same field
     ddi: int = False
+    # on-site Gaussian potentials ((a, sigma, (cx, cy, cz)), ...) on every site
+    gauss: Tuple[Tuple[float, float, Tuple[float, float, float]], ...] = ()
 
 
 @dataclasses.dataclass(frozen=True)
