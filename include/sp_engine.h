@@ -56,6 +56,7 @@ enum sp_ddi_mode { SP_DDI_OFF = 0, SP_DDI_DIRECT = 1, SP_DDI_SURROGATE = 2, SP_D
 
 #define SP_MAX_BASIS 8
 #define SP_MAX_SHELLS 8
+#define SP_MAX_GAUSS 16
 
 /* Hamiltonian parameters (Sec. III.A, extended Heisenberg Hamiltonian):
  *   H = - sum_i mu_i mu_B B . n_i - sum_i K_i (K_hat_i . n_i)^2
@@ -85,6 +86,14 @@ typedef struct {
                                 a and b; needs n_cells[0], n_cells[1] <= 512 and
                                 n_cells[2] * n_basis <= 64, else
                                 SP_E_UNSUPPORTED from sp_set_hamiltonian */
+    int n_gauss;             /* 0..SP_MAX_GAUSS on-site Gaussian potentials, the same on
+                                every site: sum_k a_k exp(-(1 - n.c_k)^2 / (2 sigma_k^2))
+                                (the single-spin landscape of Appendix G; c_k are
+                                normalised internally; reported with the anisotropy
+                                energy; runs on the two-pass step path) */
+    const double *gauss_a;       /* [n_gauss], meV */
+    const double *gauss_sigma;   /* [n_gauss], > 0 */
+    const double *gauss_c;       /* [3*n_gauss], non-zero centre vectors */
 } sp_hamiltonian;
 
 /* Integrators of dn/dt = n x A (Sec. III.C):
@@ -279,6 +288,14 @@ int sp_gneb_create(sp_gneb **out, sp_engine *e, int n_images, const double *chai
                    double vp_dt, double vp_mass);
 void sp_gneb_destroy(sp_gneb *c);
 const char *sp_gneb_last_error(const sp_gneb *c);
+/* Image types (Sec. III.D): SP_IMAGE_CLIMBING drops the spring force and
+ * inverts the energy gradient along the path (F = -grad E + 2 (grad E . tau)
+ * tau); SP_IMAGE_FALLING drops the spring force and keeps the full energy
+ * force (F = -grad E), so the image relaxes into a minimum; both per-spin
+ * projected.  image in 1..n_images-2; SP_E_ARG otherwise.  Takes effect at
+ * the next iteration (the minimiser's previous force is kept). */
+enum sp_image_type { SP_IMAGE_NORMAL = 0, SP_IMAGE_CLIMBING = 1, SP_IMAGE_FALLING = 2 };
+int sp_gneb_set_image_type(sp_gneb *c, int image, int type);
 /* n_iter velocity-projection iterations. */
 int sp_gneb_iterate(sp_gneb *c, int n_iter);
 /* Current chain (n_images*3N doubles). */

@@ -48,6 +48,8 @@ struct HostHam {
     double J[SP_MAX_SHELLS], D[SP_MAX_SHELLS];
     int dmi_kind;
     int ddi;
+    int n_gauss;
+    double ga[SP_MAX_GAUSS], gsigma[SP_MAX_GAUSS], gc[3 * SP_MAX_GAUSS];   // centres normalised
 };
 
 struct HostBond {
@@ -245,6 +247,12 @@ sp::Phys<T> make_phys(const sp_engine* e, const sp_llg_params* p) {
         P.sigma[b] = T(0);
         if (p && p->T_K > 0.0)
             P.sigma[b] = (T)std::sqrt(2.0 * p->alpha * kKB * p->T_K / (kGamma * mm * p->dt_ps));
+    }
+    P.ng = e->ham.n_gauss;
+    for (int k = 0; k < P.ng; ++k) {
+        P.ga[k] = (T)e->ham.ga[k];
+        P.gis2[k] = (T)(1.0 / (e->ham.gsigma[k] * e->ham.gsigma[k]));
+        for (int q = 0; q < 3; ++q) P.gc[k][q] = (T)e->ham.gc[3 * k + q];
     }
     return P;
 }
@@ -848,6 +856,9 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
         return fail(e, SP_E_ARG, "J or D array is NULL");
     if (h->n_dmi_shells > 0 && h->dmi_kind != SP_DMI_BULK && h->dmi_kind != SP_DMI_INTERFACIAL)
         return fail(e, SP_E_ARG, "dmi_kind must be SP_DMI_BULK or SP_DMI_INTERFACIAL");
+    if (h->n_gauss < 0 || h->n_gauss > SP_MAX_GAUSS) return fail(e, SP_E_ARG, "n_gauss must be in 0..16");
+    if (h->n_gauss > 0 && (!h->gauss_a || !h->gauss_sigma || !h->gauss_c))
+        return fail(e, SP_E_ARG, "Gaussian parameter arrays are NULL");
     if (h->ddi_mode != SP_DDI_OFF && h->ddi_mode != SP_DDI_DIRECT && h->ddi_mode != SP_DDI_SURROGATE &&
         h->ddi_mode != SP_DDI_FFT)
         return fail(e, SP_E_UNSUPPORTED, "ddi_mode must be SP_DDI_OFF, SP_DDI_DIRECT, SP_DDI_SURROGATE or SP_DDI_FFT");
@@ -877,6 +888,17 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
     for (int s = 0; s < H.n_dmi; ++s) H.D[s] = h->D[s];
     H.dmi_kind = h->n_dmi_shells > 0 ? h->dmi_kind : SP_DMI_INTERFACIAL;
     H.ddi = h->ddi_mode;   // off, direct sum, surrogate (with direct-sum fallback), FFT convolution
+    H.n_gauss = h->n_gauss;
+    for (int k = 0; k < H.n_gauss; ++k) {
+        const double* c = h->gauss_c + 3 * k;
+        const double r = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        if (!(h->gauss_sigma[k] > 0.0) || !std::isfinite(h->gauss_sigma[k]) || !std::isfinite(h->gauss_a[k]) ||
+            !(r > 0.0) || !std::isfinite(r))
+            return fail(e, SP_E_ARG, "Gaussian potentials need sigma > 0, finite a and a non-zero centre");
+        H.ga[k] = h->gauss_a[k];
+        H.gsigma[k] = h->gauss_sigma[k];
+        for (int q = 0; q < 3; ++q) H.gc[3 * k + q] = c[q] / r;
+    }
 
     std::vector<HostBond> bonds, all_bonds;
     std::vector<int> bstart;
@@ -938,7 +960,7 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
 
     // step path
     const HostGeo& g = e->geo;
-    bool fused = g.nb == 1 && g.n[2] == 1 && e->planar && !H.ddi && e->R <= 2 &&
+    bool fused = g.nb == 1 && g.n[2] == 1 && e->planar && !H.ddi && H.n_gauss == 0 && e->R <= 2 &&
                  (int)bonds.size() <= sp::kMaxStencil;
     if (g.per[0] && g.n[0] <= 2 * e->R) fused = false;
     if (g.per[1] && g.n[1] <= 2 * e->R) fused = false;
@@ -1692,6 +1714,7 @@ struct sp_gneb {
     double* E = nullptr;    // [M]
     double* s3 = nullptr;   // [3M]: |tau|^2, g.tau, l^2
     double* vf = nullptr;   // [2]
+    int* types = nullptr;   // [M] image types (0 normal, 1 climbing, 2 falling)
     int64_t iterations = 0;
     std::string err;
 };
@@ -1719,7 +1742,7 @@ int gneb_forces(sp_gneb* G, bool update_v) {
                        G->part);
     hipLaunchKernelGGL((sp::k_gneb_sum<3>), dim3(G->M), dim3(256), 0, e->stream, G->part, G->nblk, G->s3);
     hipLaunchKernelGGL((sp::k_gneb_force<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, e->stream, d, (T)G->k,
-                       (T)(G->dt / (2.0 * G->m)), update_v ? 1 : 0, x, g, tau, G->s3, static_cast<T*>(G->F),
+                       (T)(G->dt / (2.0 * G->m)), update_v ? 1 : 0, x, g, tau, G->s3, G->types, static_cast<T*>(G->F),
                        static_cast<const T*>(G->Fp), static_cast<T*>(G->v), G->part);
     if (update_v)
         hipLaunchKernelGGL((sp::k_gneb_sum<2>), dim3(1), dim3(256), 0, e->stream, G->part, (G->M - 2) * G->nblk,
@@ -1784,7 +1807,7 @@ int gneb_download(sp_gneb* G, const void* src, double* out, size_t count) {
 }
 
 void gneb_free(sp_gneb* G) {
-    void* ps[] = {G->x, G->v, G->F, G->Fp, G->g, G->tau, G->part, G->E, G->s3, G->vf};
+    void* ps[] = {G->x, G->v, G->F, G->Fp, G->g, G->tau, G->part, G->E, G->s3, G->vf, G->types};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }
@@ -1823,14 +1846,15 @@ int sp_gneb_create(sp_gneb** out, sp_engine* e, int n_images, const double* chai
     if (hipMalloc((void**)&G->part, parts * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&G->E, G->M * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&G->s3, 3 * G->M * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&G->vf, 2 * sizeof(double)) != hipSuccess) {
+        hipMalloc((void**)&G->vf, 2 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&G->types, G->M * sizeof(int)) != hipSuccess) {
         gneb_free(G);
         delete G;
         return fail(e, SP_E_NOMEM, "GNEB allocation failed");
     }
     if (hipMemset(G->v, 0, vb) != hipSuccess || hipMemset(G->F, 0, vb) != hipSuccess ||
         hipMemset(G->Fp, 0, vb) != hipSuccess || hipMemset(G->tau, 0, vb) != hipSuccess ||
-        hipMemset(G->vf, 0, 2 * sizeof(double)) != hipSuccess) {
+        hipMemset(G->vf, 0, 2 * sizeof(double)) != hipSuccess || hipMemset(G->types, 0, G->M * sizeof(int)) != hipSuccess) {
         gneb_free(G);
         delete G;
         return fail(e, SP_E_HIP, "GNEB initialisation failed");
@@ -1860,6 +1884,20 @@ void sp_gneb_destroy(sp_gneb* G) {
 }
 
 const char* sp_gneb_last_error(const sp_gneb* G) { return G ? G->err.c_str() : "null chain"; }
+
+int sp_gneb_set_image_type(sp_gneb* G, int image, int type) {
+    if (!G) return SP_E_ARG;
+    if (image < 1 || image > G->M - 2) return gfail(G, SP_E_ARG, "only interior images have a type");
+    if (type != SP_IMAGE_NORMAL && type != SP_IMAGE_CLIMBING && type != SP_IMAGE_FALLING)
+        return gfail(G, SP_E_ARG, "type must be SP_IMAGE_NORMAL, SP_IMAGE_CLIMBING or SP_IMAGE_FALLING");
+    (void)hipSetDevice(G->e->device);
+    if (hipMemcpyAsync(G->types + image, &type, sizeof(int), hipMemcpyHostToDevice, G->e->stream) != hipSuccess ||
+        hipStreamSynchronize(G->e->stream) != hipSuccess)
+        return gfail(G, SP_E_HIP, "image type upload failed");
+    // the previous force kept by the minimiser is left as it is; the next
+    // iteration forms the new force with the new type
+    return SP_OK;
+}
 
 int sp_gneb_iterate(sp_gneb* G, int n_iter) {
     if (!G) return SP_E_ARG;

@@ -25,10 +25,16 @@
 
 namespace sp {
 
+constexpr int kMaxGauss = 16;
+
 // Per-basis physical constants in engine precision.
 template <typename T>
 struct Phys {
     int nb;
+    int ng;                 // on-site Gaussian potentials (same on every site)
+    T ga[kMaxGauss];        // amplitude a_k (meV)
+    T gis2[kMaxGauss];      // 1 / sigma_k^2
+    T gc[kMaxGauss][3];     // unit centre directions
     T mumuB[kMaxBasis];     // mu_b mu_B (meV/T)
     T gZ[kMaxBasis][3];     // Zeeman gradient -mu_b mu_B B
     T K2[kMaxBasis];        // 2 K_b
@@ -64,6 +70,7 @@ struct BondCoef {
 template <typename T>
 struct FieldTerms {
     V3<T> z, k, j, d;
+    V3<T> q;   // on-site Gaussian potentials (not quadratic: energy formed separately)
 };
 
 __device__ __forceinline__ int wrap_coord(int t, int n, int per, bool& ok) {
@@ -103,6 +110,7 @@ __device__ FieldTerms<T> site_terms(const Lattice& L, const BondCoef<T>& C, cons
     f.z = V3<T>{P.gZ[beta][0], P.gZ[beta][1], P.gZ[beta][2]};
     const V3<T> ax{P.Kax[beta][0], P.Kax[beta][1], P.Kax[beta][2]};
     f.k = (-P.K2[beta] * dot(ax, ni)) * ax;
+    f.q = gauss_gradient(P, ni);
     V3<T> gj{T(0), T(0), T(0)}, gd{T(0), T(0), T(0)};
     for (int q = L.bstart[beta]; q < L.bstart[beta + 1]; ++q) {
         const int4 bd = L.bond[q];
@@ -126,7 +134,33 @@ __device__ FieldTerms<T> site_terms(const Lattice& L, const BondCoef<T>& C, cons
 
 template <typename T>
 __device__ __forceinline__ V3<T> total(const FieldTerms<T>& f) {
-    return f.z + f.k + f.j + f.d;
+    return f.z + f.k + f.j + f.d + f.q;
+}
+
+// On-site Gaussian potentials (the single-spin landscape of Appendix G):
+// E = sum_k a_k exp(-(1 - n.c_k)^2 / (2 sigma_k^2)), gradient
+// sum_k a_k exp(...) (1 - n.c_k) / sigma_k^2 c_k.
+template <typename T>
+__device__ __forceinline__ V3<T> gauss_gradient(const Phys<T>& P, V3<T> n) {
+    V3<T> g{T(0), T(0), T(0)};
+    for (int k = 0; k < P.ng; ++k) {
+        const V3<T> c{P.gc[k][0], P.gc[k][1], P.gc[k][2]};
+        const T d = T(1) - dot(n, c);
+        const T f = P.ga[k] * exp(T(-0.5) * d * d * P.gis2[k]) * d * P.gis2[k];
+        g = g + f * c;
+    }
+    return g;
+}
+
+template <typename T>
+__device__ __forceinline__ double gauss_energy(const Phys<T>& P, V3<T> n) {
+    double e = 0.0;
+    for (int k = 0; k < P.ng; ++k) {
+        const V3<T> c{P.gc[k][0], P.gc[k][1], P.gc[k][2]};
+        const T d = T(1) - dot(n, c);
+        e += (double)(P.ga[k] * exp(T(-0.5) * d * d * P.gis2[k]));
+    }
+    return e;
 }
 
 __device__ __forceinline__ int basis_of(const Lattice& L, int i) {

@@ -11,6 +11,7 @@
 //                     |tau|^2, g.tau, and squared geodesic angles to image v+1
 //   k_gneb_sum        |tau|^2[v], g.tau[v], l^2[v]
 //   k_gneb_force      F = -g + (g.t)t, per-spin projected, + k (l_v - l_{v-1}) t
+//                     (climbing images: -g + 2 (g.t)t, falling: -g, no spring)
 //                     with t = tau/|tau|; v <- v + dt/(2m)(F_prev + F);
 //                     chain-wide partials of v.F and F.F
 //   k_gneb_sum        v.F, F.F
@@ -79,7 +80,8 @@ __global__ void __launch_bounds__(256) k_gneb_grad(GnebDims d, Lattice L, BondCo
         store3(g + (size_t)im * 3 * d.N, d.N, i, total(f));
         const double nx = ni.x, ny = ni.y, nz = ni.z;
         acc[0] = nx * f.z.x + ny * f.z.y + nz * f.z.z +
-                 0.5 * (nx * (f.k.x + f.j.x + f.d.x) + ny * (f.k.y + f.j.y + f.d.y) + nz * (f.k.z + f.j.z + f.d.z));
+                 0.5 * (nx * (f.k.x + f.j.x + f.d.x) + ny * (f.k.y + f.j.y + f.d.y) + nz * (f.k.z + f.j.z + f.d.z)) +
+                 gauss_energy(P, ni);
     }
     block_sums<1>(acc);
     if (threadIdx.x == 0) part[(size_t)im * d.nblk + blockIdx.x] = acc[0];
@@ -155,10 +157,13 @@ __global__ void __launch_bounds__(256) k_gneb_tangent(GnebDims d, const T* __res
 
 // Forces of interior images, velocity update, chain-wide v.F and F.F partials.
 // s3[v] = (|tau|^2, g.tau, l^2) from k_gneb_sum<3>.
+// Image types: 0 normal, 1 climbing (no spring, F = -g + 2 (g.t) t),
+// 2 falling (no spring, F = -g); all per-spin projected.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gneb_force(GnebDims d, T k_spring, T dt_2m, int update_v,
                                                     const T* __restrict__ x, const T* __restrict__ g,
                                                     const T* __restrict__ tau, const double* __restrict__ s3,
+                                                    const int* __restrict__ types,
                                                     T* __restrict__ F, const T* __restrict__ Fp, T* __restrict__ v,
                                                     double* __restrict__ part) {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -168,8 +173,10 @@ __global__ void __launch_bounds__(256) k_gneb_force(GnebDims d, T k_spring, T dt
         const size_t off = (size_t)im * 3 * d.N;
         const double tn2 = s3[im * 3 + 0];
         const double inv = tn2 > 0.0 ? 1.0 / sqrt(tn2) : 0.0;
-        const T gt = (T)(s3[im * 3 + 1] * inv);
-        const T fs = (T)(k_spring * (sqrt(s3[im * 3 + 2]) - sqrt(s3[(im - 1) * 3 + 2])));
+        const int type = types[im];
+        const T cpar = type == 1 ? T(2) : (type == 2 ? T(0) : T(1));
+        const T gt = cpar * (T)(s3[im * 3 + 1] * inv);
+        const T fs = type == 0 ? (T)(k_spring * (sqrt(s3[im * 3 + 2]) - sqrt(s3[(im - 1) * 3 + 2]))) : T(0);
         const V3<T> n = load3(x + off, d.N, i);
         const V3<T> t = T(inv) * load3(tau + off, d.N, i);
         const V3<T> gi = load3(g + off, d.N, i);

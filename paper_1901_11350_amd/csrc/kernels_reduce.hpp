@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(256) k_observe_partial(Lattice L, BondCoef<T> 
         }
         const double nx = ni.x, ny = ni.y, nz = ni.z;
         acc[OBS_EZ] += nx * f.z.x + ny * f.z.y + nz * f.z.z;
-        acc[OBS_EK] += 0.5 * (nx * f.k.x + ny * f.k.y + nz * f.k.z);
+        acc[OBS_EK] += 0.5 * (nx * f.k.x + ny * f.k.y + nz * f.k.z) + gauss_energy(P, ni);
         acc[OBS_EJ] += 0.5 * (nx * f.j.x + ny * f.j.y + nz * f.j.z);
         acc[OBS_ED] += 0.5 * (nx * f.d.x + ny * f.d.y + nz * f.d.z);
         acc[OBS_EDD] += edd;

@@ -34,7 +34,7 @@ EXPORTS = [
     "sp_batch_create", "sp_batch_destroy", "sp_batch_last_error", "sp_batch_add", "sp_batch_run",
     "sp_batch_get_spins", "sp_batch_replica_info", "sp_batch_set_chunk", "sp_batch_get_step",
     "sp_batch_autotune",
-    "sp_gneb_create", "sp_gneb_destroy", "sp_gneb_last_error", "sp_gneb_iterate",
+    "sp_gneb_create", "sp_gneb_destroy", "sp_gneb_last_error", "sp_gneb_set_image_type", "sp_gneb_iterate",
     "sp_gneb_get_chain", "sp_gneb_get_forces",
     "sp_ddi_init", "sp_ddi_num_params", "sp_ddi_set_params", "sp_ddi_get_params", "sp_ddi_label_dev",
     "sp_ddi_forward_dev", "sp_ddi_loss_grad_dev", "sp_ddi_train_dev", "sp_ddi_configure", "sp_ddi_stats",
@@ -58,7 +58,11 @@ class sp_hamiltonian(ctypes.Structure):
                 ("n_dmi_shells", ctypes.c_int),
                 ("D", ctypes.POINTER(ctypes.c_double)),
                 ("dmi_kind", ctypes.c_int),
-                ("ddi_mode", ctypes.c_int)]
+                ("ddi_mode", ctypes.c_int),
+                ("n_gauss", ctypes.c_int),
+                ("gauss_a", ctypes.POINTER(ctypes.c_double)),
+                ("gauss_sigma", ctypes.POINTER(ctypes.c_double)),
+                ("gauss_c", ctypes.POINTER(ctypes.c_double))]
 
 
 class sp_llg_params(ctypes.Structure):
@@ -132,6 +136,7 @@ def lib():
                                 ctypes.c_double]),
         "sp_gneb_destroy": (None, [vp]),
         "sp_gneb_last_error": (ctypes.c_char_p, [vp]),
+        "sp_gneb_set_image_type": (ci, [vp, ci, ci]),
         "sp_gneb_iterate": (ci, [vp, ci]),
         "sp_gneb_get_chain": (ci, [vp, dp]),
         "sp_gneb_get_forces": (ci, [vp, dp, dp, dp]),
@@ -228,6 +233,13 @@ class Engine:
         h.dmi_kind = ham.dmi_kind
         # ddi: False/True (off / direct sum) or an sp_ddi_mode value
         h.ddi_mode = int(ham.ddi)
+        gauss = getattr(ham, "gauss", ())
+        h.n_gauss = len(gauss)
+        if gauss:
+            arrs["ga"] = _f64([a for a, _, _ in gauss])
+            arrs["gs"] = _f64([sg for _, sg, _ in gauss])
+            arrs["gc"] = _f64([x for _, _, c in gauss for x in c])
+            h.gauss_a, h.gauss_sigma, h.gauss_c = _dp(arrs["ga"]), _dp(arrs["gs"]), _dp(arrs["gc"])
         self._check(lib().sp_set_hamiltonian(self._h, ctypes.byref(h)))
 
     def bonds(self, beta: int = 0):
@@ -473,6 +485,13 @@ class Gneb:
     def _check(self, rc: int):
         if rc != SP_OK:
             raise SpError(rc, lib().sp_gneb_last_error(self._h).decode())
+
+    def set_image_types(self, types):
+        """types: one of "normal", "climbing", "falling" per image (endpoints ignored)."""
+        codes = {"normal": 0, "climbing": 1, "falling": 2}
+        for v, t in enumerate(types):
+            if 0 < v < len(types) - 1:
+                self._check(lib().sp_gneb_set_image_type(self._h, v, codes[t]))
 
     def iterate(self, n_iter: int):
         self._check(lib().sp_gneb_iterate(self._h, n_iter))

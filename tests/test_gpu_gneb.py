@@ -145,3 +145,104 @@ def test_gneb_stoner_wohlfarth_barrier_fp32():
     exact = K * (1 - h) ** 2
     bound = K * (1 - h * h) * (math.pi / (M - 1) / 2) ** 2
     assert -1e-6 <= exact - barrier <= bound + 1e-6
+
+
+# ------------------------------------------- climbing and falling images
+
+from test_oracle_gneb import _descend, gaussian_landscape, gaussian_system, geodesic  # noqa: E402
+
+
+def _gauss_ham():
+    return si.Hamiltonian(mu=(1.0,), B=(0, 0, 0), K=(0.0,), K_axis=((0, 0, 1),), gauss=gaussian_landscape())
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_gaussian_landscape_gradient_and_energy_match_oracle(ora, precision):
+    """The on-site Gaussian potentials on a 9 x 7 lattice with exchange."""
+    from gpu_util import make_pair
+
+    announce(f"gaussian landscape field {precision}")
+    geo = si.square(9, 7)
+    ham = dataclasses_replace(_gauss_ham(), J=(0.3,))
+    e, s = make_pair(ora, geo, ham, precision)
+    n = si.uniform_sphere(geo.n_sites, 12)
+    e.set_spins(n)
+    assert_close(e.gradient(), s.gradient(n), precision, what="gradient with Gaussians")
+    E, pt = e.energy(per_term=True)
+    Eo, pto = s.energy(n, per_term=True)
+    tol = 1e-12 if precision == "f64" else 1e-5
+    assert abs(E - Eo) <= tol * np.abs(pto).sum()
+    assert abs(pt[1] - pto[1]) <= tol * np.abs(pto).sum()
+
+
+def _relaxed_gaussian_chain(ora):
+    """Oracle chain between the minima of rows 6 and 7 of the Appendix G
+    landscape, relaxed without special images, and the image types: the two
+    interior energy maxima climb, the interior minimum falls.  The early
+    iterations from a geodesic guess amplify rounding differences ~100x per
+    ten iterations (tangent branches switch where neighbouring energies are
+    nearly equal), so both engines start from this relaxed chain."""
+    s = gaussian_system(ora)
+    gl = gaussian_landscape()
+    a, b = _descend(s, np.array(gl[5][2])), _descend(s, np.array(gl[6][2]))
+    o = ora.Gneb(s, geodesic(a, b, 40), k_spring=1.0, vp_dt=0.1)
+    o.iterate(3000)
+    E = o.forces()["E"]
+    M = len(E)
+    maxima = [k for k in range(1, M - 1) if E[k] > E[k - 1] and E[k] > E[k + 1]]
+    minima = [k for k in range(1, M - 1) if E[k] < E[k - 1] and E[k] < E[k + 1]]
+    assert len(maxima) == 2 and len(minima) == 1
+    types = ["normal"] * M
+    types[maxima[0]] = types[maxima[1]] = "climbing"
+    types[minima[0]] = "falling"
+    return s, o.chain.copy(), types, maxima + minima
+
+
+def _ci_pair(ora, precision, s, chain, types):
+    import paper_1901_11350_amd as pk
+
+    geo = si.Geometry(((1, 0, 0), (0, 1, 0), (0, 0, 1)), ((0, 0, 0),), (1, 1, 1), (0, 0, 0))
+    e = pk.Engine(0, precision)
+    e.set_geometry(geo)
+    e.set_hamiltonian(_gauss_ham())
+    g = pk.Gneb(e, chain, k_spring=1.0, vp_dt=0.1)
+    o = ora.Gneb(s, chain, k_spring=1.0, vp_dt=0.1)
+    g.set_image_types(types)
+    o.set_image_types(types)
+    return e, g, o
+
+
+def test_climbing_falling_fp64_iterations_match_oracle(ora):
+    announce("gneb climbing/falling fp64")
+    s, chain, types, special = _relaxed_gaussian_chain(ora)
+    e, g, o = _ci_pair(ora, "f64", s, chain, types)
+    g.iterate(20)
+    o.iterate(20)
+    assert_close(g.chain(), o.chain, "f64", 1e-10, what="20 iterations with climbing and falling images")
+    g.iterate(12000)
+    o.iterate(12000)
+    assert np.abs(o.forces()["F"]).max() < 1e-10
+    assert_close(g.chain()[special], o.chain[special], "f64", 1e-9, what="converged critical points")
+
+
+def test_climbing_falling_fp32_converge_to_the_oracle_critical_points(ora):
+    """FP32 chain with two climbing and one falling image: the special images
+    land on the oracle's converged saddles and minimum."""
+    announce("gneb climbing/falling fp32")
+    s, chain, types, special = _relaxed_gaussian_chain(ora)
+    e, g, o = _ci_pair(ora, "f32", s, chain, types)
+    g.iterate(12000)
+    o.iterate(12000)
+    fo = o.forces()
+    assert np.abs(fo["F"]).max() < 1e-10
+    cg, co = g.chain(), o.chain
+    fg = g.forces()
+    for k in special:
+        assert np.abs(cg[k] - co[k]).max() < 2e-4, k
+        assert fg["E"][k] == pytest.approx(fo["E"][k], abs=2e-6)
+
+
+def dataclasses_replace(obj, **kw):
+    import dataclasses
+
+    return dataclasses.replace(obj, **kw)
