@@ -135,6 +135,14 @@ typedef struct {
     double max_norm_dev;
 } sp_observation;
 
+/* Metropolis Monte Carlo parameters (Sec. III.B). */
+typedef struct {
+    double T_K;              /* temperature, > 0 */
+    double cone_deg;         /* opening angle of the trial cone, (0, 180] degrees */
+    uint64_t seed;           /* Philox key */
+    uint32_t replica;        /* Philox counter word 3 */
+} sp_mc_params;
+
 /* Create an engine on HIP device `device` computing in `precision`.
  * hip_stream: a hipStream_t to order all work on, or NULL for an engine-owned
  * stream.  *out receives the engine (NULL on failure). */
@@ -143,6 +151,22 @@ int sp_create(sp_engine **out, int device, int precision, void *hip_stream);
 void sp_destroy(sp_engine *e);
 /* Message of the last failing call on this engine (never NULL). */
 const char *sp_last_error(const sp_engine *e);
+
+/* Metropolis sweeps with cone trial moves (Sec. III.B): each sweep tries
+ * every site once, first the sites with a + b + c even, then the odd ones
+ * (sites of one colour share no bond, so a colour updates in parallel).
+ * Trial at site i of sweep s: Philox block of counter (i, s_lo, s_hi,
+ * replica) and key (seed_lo, seed_hi), u_k = (x_k + 1/2) 2^-32; phi = 2 pi u0,
+ * cos(theta) = 1 - u1 (1 - cos(cone)); new spin cos(theta) n +
+ * sin(theta) (cos(phi) e1 + sin(phi) e2), e1 = unit(n x r) with r = z if
+ * |n_z| < 0.9 else x, e2 = n x e1; accepted if u2 < exp(-dE / (k_B T)).
+ * The sweep number is the engine's step counter (advanced by n_sweeps).
+ * Needs a one-atom basis, bonds that join the two colours, even lengths on
+ * periodic axes and no dipole term (SP_E_UNSUPPORTED otherwise).  obs
+ * receives n_sweeps / observe_every observations (observe_every = 0: none);
+ * *accepted (may be NULL) the accepted trials of the run. */
+int sp_mc_run(sp_engine *e, const sp_mc_params *p, int64_t n_sweeps, int64_t observe_every,
+              sp_observation *obs, int64_t *accepted);
 /* Version string of the library. */
 const char *sp_version(void);
 

@@ -76,6 +76,11 @@ class LLGParams(ctypes.Structure):
 SOLVERS = {"depondt": 0, "heun": 1, "sib": 2}
 
 
+class McParams(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("cone_deg", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("replica", ctypes.c_uint32)]
+
+
 class GnebParams(ctypes.Structure):
     _fields_ = [("k_spring", ctypes.c_double), ("vp_dt", ctypes.c_double),
                 ("vp_mass", ctypes.c_double), ("image_type", ctypes.POINTER(ctypes.c_int))]
@@ -123,6 +128,13 @@ def lib():
                                         ctypes.POINTER(ctypes.c_uint32)]
         L.ora_thermal_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                           ctypes.c_uint32, dp]
+        L.ora_mc_delta_energy.restype = ctypes.c_double
+        L.ora_mc_delta_energy.argtypes = [ctypes.c_void_p, dp, ctypes.c_int64, dp]
+        L.ora_mc_sweep.restype = ctypes.c_int64
+        L.ora_mc_sweep.argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(McParams), ctypes.c_uint64]
+        L.ora_mc_run.restype = ctypes.c_int64
+        L.ora_mc_run.argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(McParams), ctypes.c_uint64, ctypes.c_int64,
+                                 ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
         for name in ("ora_depondt_step", "ora_heun_step", "ora_sib_step", "ora_llg_step"):
             getattr(L, name).argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(LLGParams), ctypes.c_uint64]
         L.ora_rotate.argtypes = [dp, dp, ctypes.c_double, dp]
@@ -281,6 +293,23 @@ class System:
         p = LLGParams(alpha, dt, T, seed, replica, SOLVERS[solver])
         lib().ora_llg_step(self._p, _dp(n), ctypes.byref(p), step)
         return n
+
+    def mc_delta_energy(self, n, i, n_new) -> float:
+        n = self._spins(n)
+        return lib().ora_mc_delta_energy(self._p, _dp(n), int(i), _dp(np.ascontiguousarray(n_new, dtype=np.float64)))
+
+    def mc_run(self, n, T, cone_deg, n_sweeps, seed=0, sweep0=0, replica=0, observe_every=0):
+        """Metropolis sweeps; returns (spins, observations, accepted trials)."""
+        n = self._spins(n).copy()
+        p = McParams(T, cone_deg, seed, replica)
+        n_obs = n_sweeps // observe_every if observe_every > 0 else 0
+        obs = (Observation * max(n_obs, 1))()
+        acc = ctypes.c_int64()
+        k = lib().ora_mc_run(self._p, _dp(n), ctypes.byref(p), sweep0, n_sweeps, observe_every,
+                             ctypes.cast(obs, ctypes.c_void_p), ctypes.byref(acc))
+        if k < 0:
+            raise ValueError("lattice does not admit the two-colour Monte Carlo sweep")
+        return n, [_obs_dict(o) for o in obs[:k]], acc.value
 
     def observe(self, n, step=0) -> dict:
         n = self._spins(n)

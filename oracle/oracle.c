@@ -768,6 +768,101 @@ int64_t ora_run(const ora_system *s, double *n, const ora_llg_params *p, uint64_
     return n_obs;
 }
 
+/* ----------------------------------------------------------- Monte Carlo */
+
+double ora_mc_delta_energy(const ora_system *s, const double *n, int64_t i, const double n_new[3]) {
+    const int64_t N = s->N;
+    const int beta = basis_of(s, i);
+    const double muB = ora_const_mu_B();
+    double ni[3], dn[3];
+    load(n, N, i, ni);
+    for (int k = 0; k < 3; ++k) dn[k] = n_new[k] - ni[k];
+    /* Zeeman and the pair terms are linear in n_i: their change is
+     * dn . (coefficient of n_i) */
+    double lin[3];
+    for (int k = 0; k < 3; ++k) lin[k] = -s->ham.mu[beta] * muB * s->ham.B[k];
+    for (int64_t q = s->nb_start[i]; q < s->nb_start[i + 1]; ++q) {
+        const ora_bond *bd = &s->bonds[s->nb_bond[q]];
+        double nj[3], c[3];
+        load(n, N, s->nb_j[q], nj);
+        cross3(nj, bd->D, c);
+        for (int k = 0; k < 3; ++k) lin[k] -= bd->J * nj[k] + c[k];
+    }
+    const double *ax = &s->ham.K_axis[3 * beta];
+    const double k_old = dot3(ax, ni), k_new = dot3(ax, n_new);
+    return dot3(dn, lin) - s->ham.K[beta] * (k_new * k_new - k_old * k_old) + gauss_energy(s, n_new) -
+           gauss_energy(s, ni);
+}
+
+static int mc_admissible(const ora_system *s) {
+    if (s->geo.n_basis != 1 || s->ham.ddi) return 0;
+    for (int k = 0; k < 3; ++k)
+        if (s->geo.periodic[k] && s->geo.n_cells[k] > 1 && (s->geo.n_cells[k] % 2)) return 0;
+    for (int64_t b = 0; b < s->n_bonds; ++b) {
+        const ora_bond *bd = &s->bonds[b];
+        if (((bd->da + bd->db + bd->dc) % 2 + 2) % 2 != 1) return 0;
+    }
+    return 1;
+}
+
+static void mc_trial(const double n[3], const double u[4], double cos_cone, double out[3]) {
+    double r[3] = {0.0, 0.0, 0.0}, e1[3], e2[3];
+    if (fabs(n[2]) < 0.9) r[2] = 1.0; else r[0] = 1.0;
+    cross3(n, r, e1);
+    const double l = norm3(e1);
+    for (int k = 0; k < 3; ++k) e1[k] /= l;
+    cross3(n, e1, e2);
+    const double phi = 2.0 * PI * u[0];
+    const double ct = 1.0 - u[1] * (1.0 - cos_cone);
+    const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    for (int k = 0; k < 3; ++k) out[k] = ct * n[k] + st * (cos(phi) * e1[k] + sin(phi) * e2[k]);
+}
+
+int64_t ora_mc_sweep(const ora_system *s, double *n, const ora_mc_params *p, uint64_t sweep) {
+    if (!mc_admissible(s)) return -1;
+    const int64_t N = s->N;
+    const double kT = ora_const_k_B() * p->T;
+    const double cos_cone = cos(p->cone_deg * PI / 180.0);
+    const int na = s->geo.n_cells[0], nb = s->geo.n_cells[1];
+    int64_t accepted = 0;
+    for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(static) reduction(+ : accepted)
+        for (int64_t i = 0; i < N; ++i) {
+            const int64_t a = i % na, b = (i / na) % nb, c = i / ((int64_t)na * nb);
+            if ((int)((a + b + c) % 2) != colour) continue;
+            uint32_t ctr[4] = {(uint32_t)i, (uint32_t)sweep, (uint32_t)(sweep >> 32), p->replica};
+            uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+            uint32_t x[4];
+            ora_philox4x32_10(ctr, key, x);
+            double u[4];
+            for (int k = 0; k < 4; ++k) u[k] = ((double)x[k] + 0.5) * (1.0 / 4294967296.0);
+            double ni[3], nn[3];
+            load(n, N, i, ni);
+            mc_trial(ni, u, cos_cone, nn);
+            const double dE = ora_mc_delta_energy(s, n, i, nn);
+            if (u[2] < exp(-dE / kT)) {
+                for (int k = 0; k < 3; ++k) n[k * N + i] = nn[k];
+                ++accepted;
+            }
+        }
+    }
+    return accepted;
+}
+
+int64_t ora_mc_run(const ora_system *s, double *n, const ora_mc_params *p, uint64_t sweep0, int64_t n_sweeps,
+                   int64_t observe_every, ora_observation *obs, int64_t *accepted) {
+    int64_t n_obs = 0, acc = 0;
+    for (int64_t t = 0; t < n_sweeps; ++t) {
+        const int64_t a = ora_mc_sweep(s, n, p, sweep0 + (uint64_t)t);
+        if (a < 0) return -1;
+        acc += a;
+        if (observe_every > 0 && (t + 1) % observe_every == 0 && obs)
+            ora_observe(s, n, (int64_t)sweep0 + t + 1, &obs[n_obs++]);
+    }
+    if (accepted) *accepted = acc;
+    return n_obs;
+}
+
 /* ------------------------------------------------------------------ GNEB
  * Geodesic nudged elastic band (Sec. III.D, Appendices D and F). */
 

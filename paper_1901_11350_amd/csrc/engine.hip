@@ -20,6 +20,7 @@
 #include "kernels_gneb.hpp"
 #include "kernels_conv.hpp"
 #include "kernels_fft.hpp"
+#include "kernels_mc.hpp"
 
 namespace {
 
@@ -746,6 +747,80 @@ int run_impl(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t obse
     return SP_OK;
 }
 
+// ------------------------------------------------------------ Monte Carlo
+int mc_admissible(sp_engine* e) {
+    const HostGeo& g = e->geo;
+    if (g.nb != 1) return fail(e, SP_E_UNSUPPORTED, "Monte Carlo sweeps need a one-atom basis");
+    if (e->ham.ddi) return fail(e, SP_E_UNSUPPORTED, "Monte Carlo sweeps do not support the dipole term");
+    for (int k = 0; k < 3; ++k)
+        if (g.per[k] && g.n[k] > 1 && (g.n[k] % 2))
+            return fail(e, SP_E_UNSUPPORTED, "Monte Carlo sweeps need even lengths on periodic axes");
+    for (const HostBond& b : e->all_bonds)
+        if ((((b.d[0] + b.d[1] + b.d[2]) % 2) + 2) % 2 != 1)
+            return fail(e, SP_E_UNSUPPORTED, "a bond joins two sites of the same checkerboard colour");
+    return SP_OK;
+}
+
+template <typename T>
+int mc_run_impl(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t observe_every, sp_observation* obs,
+                int64_t* accepted) {
+    const int64_t n_obs = observe_every > 0 ? n_sweeps / observe_every : 0;
+    int rc;
+    if (n_obs > e->obs_cap) {
+        if ((rc = dalloc(e, e->d_obs, (size_t)n_obs * sp::OBS_NVALS * sizeof(double)))) return rc;
+        e->obs_cap = n_obs;
+    }
+    const unsigned blocks = blocks_for(e->N);
+    unsigned int* acc = nullptr;
+    if ((rc = dalloc(e, acc, blocks * sizeof(unsigned int)))) return rc;
+    HIPCHK(e, hipMemsetAsync(acc, 0, blocks * sizeof(unsigned int), e->stream));
+    const sp::Lattice L = make_lattice(e);
+    const sp::BondCoef<T> C = make_coef<T>(e);
+    const sp::Phys<T> P = make_phys<T>(e, nullptr);
+    sp::McArgs<T> M{};
+    M.kT = (T)(kKB * p->T_K);
+    M.cos_cone = (T)std::cos(p->cone_deg * M_PI / 180.0);
+    M.key.seed_lo = (uint32_t)p->seed;
+    M.key.seed_hi = (uint32_t)(p->seed >> 32);
+    M.key.replica = p->replica;
+    int64_t k = 0;
+    for (int64_t t = 0; t < n_sweeps; ++t) {
+        M.key.step_lo = (uint32_t)e->step;
+        M.key.step_hi = (uint32_t)(e->step >> 32);
+        for (int colour = 0; colour < 2; ++colour) {
+            M.colour = colour;
+            hipLaunchKernelGGL((sp::k_mc_colour<T>), dim3(blocks), dim3(256), 0, e->stream, L, C, P, M,
+                               static_cast<T*>(e->d_n), acc);
+        }
+        ++e->step;
+        if (observe_every > 0 && (t + 1) % observe_every == 0) {
+            rc = launch_observe<T>(e, e->d_n, e->d_obs + k * sp::OBS_NVALS, (long long)e->step, false);
+            if (rc) { dfree(*reinterpret_cast<void**>(&acc)); return rc; }
+            ++k;
+        }
+    }
+    hipError_t st = hipGetLastError();
+    std::vector<unsigned int> h(blocks);
+    if (st == hipSuccess) st = hipMemcpyAsync(h.data(), acc, blocks * sizeof(unsigned int), hipMemcpyDeviceToHost, e->stream);
+    std::vector<double> ho((size_t)n_obs * sp::OBS_NVALS);
+    if (st == hipSuccess && n_obs > 0 && obs)
+        st = hipMemcpyAsync(ho.data(), e->d_obs, ho.size() * sizeof(double), hipMemcpyDeviceToHost, e->stream);
+    if (st == hipSuccess) st = hipStreamSynchronize(e->stream);
+    dfree(*reinterpret_cast<void**>(&acc));
+    if (st != hipSuccess) return fail(e, SP_E_HIP, std::string("Monte Carlo run: ") + hipGetErrorString(st));
+    if (accepted) {
+        int64_t s = 0;
+        for (unsigned int v : h) s += v;
+        *accepted = s;
+    }
+    if (n_obs > 0 && obs) {
+        const int64_t step0 = (int64_t)e->step - n_sweeps;
+        for (int64_t q = 0; q < n_obs; ++q)
+            obs_from(&ho[(size_t)q * sp::OBS_NVALS], step0 + (q + 1) * observe_every, e->N, &obs[q]);
+    }
+    return SP_OK;
+}
+
 }  // namespace
 
 #define DISPATCH(e, fn, ...) ((e)->precision == SP_F64 ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__))
@@ -798,6 +873,20 @@ void sp_destroy(sp_engine* e) {
 }
 
 const char* sp_last_error(const sp_engine* e) { return e ? e->err.c_str() : "null engine"; }
+
+int sp_mc_run(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t observe_every, sp_observation* obs,
+              int64_t* accepted) {
+    int rc = check_ready(e, true);
+    if (rc) return rc;
+    if (!p) return fail(e, SP_E_ARG, "Monte Carlo params are NULL");
+    if (!(p->T_K > 0.0) || !std::isfinite(p->T_K)) return fail(e, SP_E_ARG, "T must be finite and > 0");
+    if (!(p->cone_deg > 0.0) || !(p->cone_deg <= 180.0)) return fail(e, SP_E_ARG, "cone angle must be in (0, 180]");
+    if (n_sweeps < 0 || observe_every < 0) return fail(e, SP_E_ARG, "n_sweeps and observe_every must be >= 0");
+    if (observe_every > 0 && n_sweeps / observe_every > 0 && !obs) return fail(e, SP_E_ARG, "obs is NULL");
+    if ((rc = mc_admissible(e))) return rc;
+    (void)hipSetDevice(e->device);
+    return DISPATCH(e, mc_run_impl, e, p, n_sweeps, observe_every, obs, accepted);
+}
 
 int sp_set_geometry(sp_engine* e, const double bravais[9], int n_basis, const double* basis, const int n_cells[3],
                     const int periodic[3], double lattice_constant) {

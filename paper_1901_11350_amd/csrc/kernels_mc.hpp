@@ -1,0 +1,93 @@
+// kernels_mc.hpp -- Metropolis Monte Carlo with cone trial moves (Sec. III.B)
+// as a two-colour (checkerboard) sweep: sites with a + b + c of one parity
+// share no bond, so one launch updates a whole colour in parallel.
+//
+// Trial at site i of sweep s: Philox block of counter (i, s_lo, s_hi,
+// replica), u_k = (x_k + 1/2) 2^-32; phi = 2 pi u0, cos(theta) = 1 - u1 (1 -
+// cos(cone)); new spin cos(theta) n + sin(theta) (cos(phi) e1 + sin(phi) e2),
+// e1 = unit(n x r) with r = z if |n_z| < 0.9 else x, e2 = n x e1; accepted
+// if u2 < exp(-dE / k_B T).  dE needs only the terms containing site i:
+// Zeeman and the pair terms are linear in n_i (dn . coefficient), the
+// anisotropy and the on-site Gaussians are evaluated at both spins.
+#pragma once
+
+#include "kernels_field.hpp"
+
+namespace sp {
+
+template <typename T>
+struct McArgs {
+    T kT;            // k_B T (meV)
+    T cos_cone;
+    ThermalKey key;  // seed, sweep number (step words), replica
+    int colour;
+};
+
+template <typename T>
+__device__ __forceinline__ void mc_uniforms(const U4& x, T u[3]) {
+    if constexpr (sizeof(T) == 4) {
+        u[0] = fmaf((float)x.x, 0x1p-32f, 0x1p-33f);
+        u[1] = fmaf((float)x.y, 0x1p-32f, 0x1p-33f);
+        u[2] = fmaf((float)x.z, 0x1p-32f, 0x1p-33f);
+    } else {
+        u[0] = ((double)x.x + 0.5) * 0x1p-32;
+        u[1] = ((double)x.y + 0.5) * 0x1p-32;
+        u[2] = ((double)x.z + 0.5) * 0x1p-32;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ V3<T> mc_trial(V3<T> n, const T u[3], T cos_cone) {
+    const V3<T> r = fabs(n.z) < T(0.9) ? V3<T>{T(0), T(0), T(1)} : V3<T>{T(1), T(0), T(0)};
+    const V3<T> e1 = normalize3(cross(n, r));
+    const V3<T> e2 = cross(n, e1);
+    T sp, cp;
+    if constexpr (sizeof(T) == 4) {
+        sp = __builtin_amdgcn_sinf(u[0]);   // argument in revolutions
+        cp = __builtin_amdgcn_cosf(u[0]);
+    } else {
+        sincospi(T(2) * u[0], &sp, &cp);
+    }
+    const T ct = T(1) - u[1] * (T(1) - cos_cone);
+    const T st = sqrt(fmax(T(0), T(1) - ct * ct));
+    return V3<T>{ct * n.x + st * (cp * e1.x + sp * e2.x), ct * n.y + st * (cp * e1.y + sp * e2.y),
+                 ct * n.z + st * (cp * e1.z + sp * e2.z)};
+}
+
+// One colour of one sweep (one-atom basis).  acc_part[block] accumulates the
+// accepted trials of this workgroup's sites over the launches of a run.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mc_colour(Lattice L, BondCoef<T> C, Phys<T> P, McArgs<T> M,
+                                                   T* __restrict__ n, unsigned int* __restrict__ acc_part) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    bool accepted = false;
+    if (i < L.N) {
+        const int a = i % L.n[0];
+        const int rem = i / L.n[0];
+        const int b = rem % L.n[1];
+        const int c = rem / L.n[1];
+        if (((a + b + c) & 1) == M.colour) {
+            const V3<T> ni = load3(n, L.N, i);
+            T u[3];
+            mc_uniforms<T>(thermal_bits(M.key, (uint32_t)i), u);
+            const V3<T> nn = renorm_if_float(mc_trial(ni, u, M.cos_cone));
+            const FieldTerms<T> f = site_terms(L, C, P, n, i, ni);
+            const V3<T> lin = f.z + f.j + f.d;
+            const V3<T> ax{P.Kax[0][0], P.Kax[0][1], P.Kax[0][2]};
+            const T k0 = dot(ax, ni), k1 = dot(ax, nn);
+            const T dE = dot(nn - ni, lin) - T(0.5) * P.K2[0] * (k1 * k1 - k0 * k0) +
+                         (T)(gauss_energy(P, nn) - gauss_energy(P, ni));
+            if (u[2] < exp(-dE / M.kT)) {
+                store3(n, L.N, i, nn);
+                accepted = true;
+            }
+        }
+    }
+    const unsigned long long mask = __ballot(accepted);
+    __shared__ unsigned int cnt[4];
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = (unsigned int)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) acc_part[blockIdx.x] += cnt[0] + cnt[1] + cnt[2] + cnt[3];
+}
+
+}  // namespace sp

@@ -30,7 +30,7 @@ EXPORTS = [
     "sp_set_spins_dev", "sp_get_spins_dev", "sp_set_step", "sp_get_step", "sp_gradient",
     "sp_gradient_dev", "sp_energy", "sp_observe", "sp_llg_step", "sp_run", "sp_synchronize",
     "sp_dipole_gradient", "sp_dipole_gradient_dev", "sp_thermal_normals", "sp_step_path",
-    "sp_set_step_path", "sp_autotune",
+    "sp_set_step_path", "sp_autotune", "sp_mc_run",
     "sp_batch_create", "sp_batch_destroy", "sp_batch_last_error", "sp_batch_add", "sp_batch_run",
     "sp_batch_get_spins", "sp_batch_replica_info", "sp_batch_set_chunk", "sp_batch_get_step",
     "sp_batch_autotune",
@@ -72,6 +72,11 @@ class sp_llg_params(ctypes.Structure):
 
 
 SOLVERS = {"depondt": 0, "heun": 1, "sib": 2}   # sp_solver
+
+
+class sp_mc_params(ctypes.Structure):
+    _fields_ = [("T_K", ctypes.c_double), ("cone_deg", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("replica", ctypes.c_uint32)]
 
 
 class sp_observation(ctypes.Structure):
@@ -122,6 +127,8 @@ def lib():
         "sp_step_path": (ctypes.c_char_p, [vp]),
         "sp_set_step_path": (ci, [vp, ctypes.c_char_p]),
         "sp_autotune": (ci, [vp, ctypes.POINTER(sp_llg_params), ci, dp]),
+        "sp_mc_run": (ci, [vp, ctypes.POINTER(sp_mc_params), i64, i64, ctypes.POINTER(sp_observation),
+                           ctypes.POINTER(i64)]),
         "sp_batch_create": (ci, [ctypes.POINTER(vp), ci, vp]),
         "sp_batch_destroy": (None, [vp]),
         "sp_batch_last_error": (ctypes.c_char_p, [vp]),
@@ -326,6 +333,17 @@ class Engine:
             self._check(rc)
         res = [obs_dict(o) for o in obs[:n_obs]]
         return (res, rc) if not check else res
+
+    def mc_run(self, T: float, cone_deg: float, n_sweeps: int, seed: int = 0, replica: int = 0,
+               observe_every: int = 0):
+        """Metropolis sweeps; returns (observations, accepted trials)."""
+        p = sp_mc_params(T, cone_deg, seed, replica)
+        n_obs = n_sweeps // observe_every if observe_every > 0 else 0
+        obs = (sp_observation * max(n_obs, 1))()
+        acc = ctypes.c_int64()
+        self._check(lib().sp_mc_run(self._h, ctypes.byref(p), n_sweeps, observe_every, obs if n_obs else None,
+                                    ctypes.byref(acc)))
+        return [obs_dict(o) for o in obs[:n_obs]], acc.value
 
     def autotune(self, alpha: float, dt: float, T: float = 0.0, seed: int = 0, n_steps: int = 50,
                  solver: str = "depondt") -> float:
