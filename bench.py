@@ -327,6 +327,66 @@ def bench_surrogate(args) -> dict:
             "step_speedup_fft": ms_step_direct / ms_step_fft}
 
 
+def binder_table(precision, sizes, temps, therm, samples, method, seed=5):
+    """U4 = 1 - <m^4>/(3 <m^2>^2) (m = |mean spin|) of the simple-cubic
+    ferromagnet J = 1 meV, mu = 2, periodic L^3, from Metropolis sweeps
+    (cone 60 deg) or stochastic Depondt LLG (alpha = 1, dt = 1 fs, one sample
+    per 10 steps)."""
+    import numpy as np
+
+    import paper_1901_11350_amd as pk
+    import spin_inputs as si
+
+    ham = si.Hamiltonian(mu=(2.0,), B=(0, 0, 0), K=(0.0,), K_axis=((0, 0, 1),), J=(1.0,))
+    out = {}
+    for L in sizes:
+        e = pk.Engine(0, precision, stream=work_stream())
+        e.set_geometry(si.simple_cubic(L, L, L))
+        e.set_hamiltonian(ham)
+        for T in temps:
+            e.set_spins(si.ferromagnet(e.N, (0, 0, 1)))
+            if method == "mc":
+                e.mc_run(T, 60.0, therm, seed=seed)
+                obs, _ = e.mc_run(T, 60.0, samples, seed=seed, observe_every=1)
+            else:
+                e.run(1.0, 0.001, therm, T=T, seed=seed)
+                obs = e.run(1.0, 0.001, 10 * samples, T=T, seed=seed, observe_every=10)
+            m = np.array([np.linalg.norm(o["M"]) for o in obs])
+            out[(L, T)] = float(1 - np.mean(m ** 4) / (3 * np.mean(m ** 2) ** 2))
+    return out
+
+
+def binder_crossing(u, L1, L2, temps):
+    d = [u[(L1, T)] - u[(L2, T)] for T in temps]
+    for k in range(len(temps) - 1):
+        if d[k] < 0 <= d[k + 1]:
+            return temps[k] + (temps[k + 1] - temps[k]) * (-d[k]) / (d[k + 1] - d[k])
+    return None
+
+
+def bench_tc(args) -> dict:
+    """Critical temperature of the simple-cubic ferromagnet (J = 1 meV,
+    expected 1.44 J/k_B = 16.71 K) from Binder-cumulant crossings: Metropolis
+    with the paper's sampling (10k thermalisation + 100k samples per T) on
+    L = 10, 16, 20, 30, and stochastic LLG on L = 8, 12 (shorter runs)."""
+    temps = [15.5, 16.0, 16.5, 17.0, 17.5]
+    t0 = time.perf_counter()
+    mc = binder_table("f32", (10, 16, 20, 30), temps, args.tc_therm, args.tc_samples, "mc")
+    t_mc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    llg = binder_table("f32", (8, 12), temps, args.tc_llg_therm, args.tc_llg_samples, "llg")
+    t_llg = time.perf_counter() - t0
+    pairs = [(10, 16), (16, 20), (20, 30)]
+    return {"workload": "simple_cubic_ferromagnet_J1meV", "expected_K": 16.71, "temps_K": temps,
+            "mc": {"sizes": [10, 16, 20, 30], "thermalisation_sweeps": args.tc_therm, "samples": args.tc_samples,
+                   "U4": {f"L{L}_T{T}": v for (L, T), v in mc.items()},
+                   "crossings_K": {f"{a}/{b}": binder_crossing(mc, a, b, temps) for a, b in pairs}, "s": t_mc},
+            "llg": {"sizes": [8, 12], "thermalisation_steps": args.tc_llg_therm,
+                    "samples_every_10_steps": args.tc_llg_samples,
+                    "U4": {f"L{L}_T{T}": v for (L, T), v in llg.items()},
+                    "crossing_K": binder_crossing(llg, 8, 12, temps), "s": t_llg}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--surrogate", action="store_true",
@@ -340,6 +400,12 @@ def main():
                     help="also time the 96-replica batch (reported under 'batch')")
     ap.add_argument("--batch-steps", type=int, default=256)
     ap.add_argument("--batch-chunk", type=int, default=32)
+    ap.add_argument("--tc", action="store_true",
+                    help="also estimate the ferromagnet's Tc from Binder crossings (reported under 'tc')")
+    ap.add_argument("--tc-therm", type=int, default=10000)
+    ap.add_argument("--tc-samples", type=int, default=100000)
+    ap.add_argument("--tc-llg-therm", type=int, default=20000)
+    ap.add_argument("--tc-llg-samples", type=int, default=20000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="only run a device copy of this size (counter calibration)")
     ap.add_argument("--gpus", type=int, default=1)
@@ -449,6 +515,8 @@ def main():
         line["batch"] = bench_batch(args)
     if args.surrogate:
         line["surrogate"] = bench_surrogate(args)
+    if args.tc:
+        line["tc"] = bench_tc(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(line), flush=True)

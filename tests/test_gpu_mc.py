@@ -1,0 +1,119 @@
+"""GPU Metropolis Monte Carlo (sp_mc_run) against the FP64 oracle: the same
+cone trials and accept/reject decisions sweep by sweep (FP64 engine exactly,
+FP32 engine to its tolerance), observations, rejected lattices, and the
+Binder-cumulant crossing of the simple-cubic ferromagnet at Tc = 1.44 J/k_B."""
+
+import numpy as np
+import pytest
+
+import spin_inputs as si
+from gpu_util import announce, assert_close, make_pair, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+GAUSS = ((-0.5, 0.2, (0.3, 0.1, 0.9)), (0.4, 0.3, (-1.0, 0.5, 0.0)))
+CASES = {
+    "cubic8x6x4_all_terms": (si.simple_cubic(8, 6, 4, periodic=(1, 1, 0)),
+                             si.Hamiltonian(mu=(2.0,), B=(0.3, -0.2, 0.5), K=(0.2,), K_axis=((0.6, 0, 0.8),),
+                                            J=(1.0,), D=(0.3,), dmi_kind=si.DMI_BULK, gauss=GAUSS)),
+    "square16x12_interfacial": (si.square(16, 12),
+                                si.Hamiltonian(mu=(2.0,), B=(0, 0, 1.0), K=(0.1,), K_axis=((0, 0, 1),), J=(1.0,),
+                                               D=(0.3,))),
+    "cubic7x6x5_open": (si.simple_cubic(7, 6, 5, periodic=(0, 1, 0)),
+                        si.Hamiltonian(mu=(2.0,), B=(0, 0, 0.5), K=(0.0,), K_axis=((0, 0, 1),), J=(1.0,))),
+}
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("precision,sweeps", [("f64", 12), ("f32", 3)])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_mc_sweeps_match_oracle(ora, case, precision, sweeps):
+    announce(f"mc {case} {precision}")
+    geo, ham = CASES[case]
+    e, s = make_pair(ora, geo, ham, precision)
+    n0 = si.uniform_sphere(s.N, 8)
+    e.set_spins(n0)
+    e.step = 40
+    obs, acc = e.mc_run(12.0, 50.0, sweeps, seed=77, observe_every=1)
+    n_ora, obs_ora, acc_ora = s.mc_run(n0, 12.0, 50.0, sweeps, seed=77, sweep0=40, observe_every=1)
+    assert acc == acc_ora
+    assert 0 < acc < sweeps * s.N
+    assert_close(e.get_spins(), n_ora, precision, what=f"mc {case}")
+    tol = 1e-11 if precision == "f64" else 1e-5
+    for a, b in zip(obs, obs_ora):
+        assert a["E"] == pytest.approx(b["E"], rel=tol, abs=tol)
+        assert np.allclose(a["M"], b["M"], atol=tol)
+    assert e.step == 40 + sweeps
+
+
+def test_mc_rejects_lattices_without_two_colours():
+    import paper_1901_11350_amd as pk
+    from paper_1901_11350_amd.engine import SpError
+
+    e = pk.Engine(0, "f32")
+    e.set_geometry(si.triangular(8, 8))
+    e.set_hamiltonian(si.Hamiltonian(mu=(2.0,), B=(0, 0, 1.0), K=(0.0,), K_axis=((0, 0, 1),), J=(1.0,)))
+    e.set_spins(si.uniform_sphere(e.N, 1))
+    with pytest.raises(SpError):
+        e.mc_run(10.0, 30.0, 1)
+
+
+def binder_scan(precision, sizes, temps, therm, samples, cone=60.0, seed=5):
+    """U4 = 1 - <m^4>/(3 <m^2>^2), m = |mean spin|, per size and temperature."""
+    import paper_1901_11350_amd as pk
+
+    out = {}
+    ham = si.Hamiltonian(mu=(2.0,), B=(0, 0, 0), K=(0.0,), K_axis=((0, 0, 1),), J=(1.0,))
+    for L in sizes:
+        e = pk.Engine(0, precision)
+        e.set_geometry(si.simple_cubic(L, L, L))
+        e.set_hamiltonian(ham)
+        for T in temps:
+            e.set_spins(si.ferromagnet(e.N, (0, 0, 1)))
+            e.mc_run(T, cone, therm, seed=seed)
+            obs, _ = e.mc_run(T, cone, samples, seed=seed, observe_every=1)
+            m = np.array([np.linalg.norm(o["M"]) for o in obs])
+            out[(L, T)] = 1 - np.mean(m ** 4) / (3 * np.mean(m ** 2) ** 2)
+    return out
+
+
+def crossing(u, L1, L2, temps):
+    """Temperature where U4(L1) - U4(L2) changes sign (the larger lattice has
+    the larger cumulant below Tc and the smaller above), linearly
+    interpolated; None if it does not."""
+    d = [u[(L1, T)] - u[(L2, T)] for T in temps]
+    for k in range(len(temps) - 1):
+        if d[k] < 0 <= d[k + 1]:
+            return temps[k] + (temps[k + 1] - temps[k]) * (-d[k]) / (d[k + 1] - d[k])
+    return None
+
+
+def test_binder_crossing_near_the_known_tc():
+    """Binder cumulants of L = 8 and 12 cross near Tc = 1.44 J/k_B = 16.71 K
+    for J = 1 meV (finite-size shifts and sampling noise allow +-4 %)."""
+    announce("mc binder crossing")
+    temps = [15.5, 16.0, 16.5, 17.0, 17.5]
+    u = binder_scan("f32", (8, 12), temps, 4000, 40000)
+    tc = crossing(u, 8, 12, temps)
+    table = {f"{L}@{T}": round(v, 4) for (L, T), v in u.items()}
+    assert tc is not None, table
+    assert abs(tc - 16.71) < 0.04 * 16.71, (tc, table)
+
+
+def test_stochastic_llg_binder_crossing_near_the_known_tc():
+    """The thermal field of the LLG equation samples the same phase
+    transition: stochastic Depondt LLG (alpha = 1, dt = 1 fs, 20k steps to
+    thermalise, 20k samples one per 10 steps) on L = 8 and 12."""
+    import bench
+
+    announce("llg binder crossing")
+    temps = [15.5, 16.0, 16.5, 17.0, 17.5]
+    u = bench.binder_table("f32", (8, 12), temps, 20000, 20000, "llg")
+    tc = bench.binder_crossing(u, 8, 12, temps)
+    table = {f"{L}@{T}": round(v, 4) for (L, T), v in u.items()}
+    assert tc is not None, table
+    assert abs(tc - 16.71) < 0.05 * 16.71, (tc, table)
