@@ -183,7 +183,24 @@ def bench_batch(args) -> dict:
     torch.cuda.synchronize()
     ms_sep = ev0.elapsed_time(ev1)
     n_res = sum(1 for r in range(len(table)) if b.info(r)[1])
-    return {"workload": "batch96_square", "replicas": len(table), "resident_replicas": n_res,
+    # the 32-image GNEB chain on a 128x128 lattice (same Hamiltonian), FP32
+    geo = si.square(128, 128)
+    ge = pk.Engine(0, "f32", stream=stream)
+    ge.set_geometry(geo)
+    ge.set_hamiltonian(ham)
+    a = si.skyrmion_ansatz(geo, radius=5.0, width=1.5)
+    chain = si.geodesic_chain(a, si.ferromagnet(geo.n_sites, (0, 0, 1)), 32, fallback_axis=(1, 0, 0))
+    g = pk.Gneb(ge, chain, k_spring=1.0, vp_dt=0.1)
+    g.iterate(20)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    g.iterate(args.gneb_iters)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_gneb = ev0.elapsed_time(ev1) / args.gneb_iters
+    gneb = {"images": 32, "spins_per_image": geo.n_sites, "ms_per_iteration": ms_gneb,
+            "image_spin_updates_per_s": 32 * geo.n_sites / (ms_gneb * 1e-3)}
+    return {"workload": "batch96_square", "replicas": len(table), "resident_replicas": n_res, "gneb": gneb,
             "total_spins": total, "steps": K, "chunk": args.batch_chunk,
             "spin_updates_per_s": total * K / (ms * 1e-3), "ms_per_step": ms / K,
             "separate_engines_spin_updates_per_s": total * Ks / (ms_sep * 1e-3),
@@ -400,6 +417,7 @@ def main():
                     help="also time the 96-replica batch (reported under 'batch')")
     ap.add_argument("--batch-steps", type=int, default=256)
     ap.add_argument("--batch-chunk", type=int, default=32)
+    ap.add_argument("--gneb-iters", type=int, default=200)
     ap.add_argument("--tc", action="store_true",
                     help="also estimate the ferromagnet's Tc from Binder crossings (reported under 'tc')")
     ap.add_argument("--tc-therm", type=int, default=10000)

@@ -21,6 +21,7 @@
 #include "kernels_conv.hpp"
 #include "kernels_fft.hpp"
 #include "kernels_mc.hpp"
+#include "kernels_fused3d.hpp"
 
 namespace {
 
@@ -90,6 +91,9 @@ struct sp_engine {
     int shape = -1;                   // sp::Shape2D matched by the bond table, or -1
     int shape_ndmi = 0;               // 0: no DMI, 1: DMI on the first shell only
     int tile_cfg = 0;                 // index into the shape-path tile configurations
+    int shape3 = -1;                  // sp::Shape3D matched by a 3D one-atom bond table, or -1
+    int shape3_ndmi = 0;              // DMI on the first shell
+    int tile3_cfg = 0;                // index into the 3D tile configurations
     std::string path_label;
 
     size_t esz() const { return precision == SP_F64 ? 8 : 4; }
@@ -522,10 +526,122 @@ void launch_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const voi
     }
 }
 
+// ------------------------------------------------ 3D streamed fused path
+// `blocks`: workgroups to aim for (the plane chunk length follows); tiles
+// whose LDS rings leave room for several workgroups per CU aim higher.
+struct Tile3Cfg {
+    const char* name;
+    int TX, TY, blocks;
+};
+constexpr Tile3Cfg kTile3Cfgs[] = {{"32x16", 32, 16, 256}, {"16x16", 16, 16, 768}, {"32x8", 32, 8, 768},
+                                   {"16x16z", 16, 16, 256}, {"32x16b", 32, 16, 512}};
+constexpr int kNumTile3Cfgs = 5;      // FP64 takes the 16x16 tiles only (LDS)
+
+template <int S>
+bool match_shape3(const sp_engine* e) {
+    using SH = sp::ShapeTab3<S>;
+    if (e->n_shells != SH::NS || (int)e->all_bonds.size() != SH::NB) return false;
+    for (int q = 0; q < SH::NB; ++q) {
+        bool found = false;
+        for (const HostBond& b : e->all_bonds)
+            if (b.d[0] == SH::da[q] && b.d[1] == SH::db[q] && b.d[2] == SH::dc[q] && b.shell == SH::sh[q]) found = true;
+        if (!found) return false;
+    }
+    return true;
+}
+
+int detect_shape3(const sp_engine* e) {
+    if (match_shape3<sp::SH3_SC1>(e)) return sp::SH3_SC1;
+    if (match_shape3<sp::SH3_SC2>(e)) return sp::SH3_SC2;
+    if (match_shape3<sp::SH3_SC3>(e)) return sp::SH3_SC3;
+    return -1;
+}
+
+template <typename T, int S>
+sp::ShapeCoef3<T> shape_coef3_for(const sp_engine* e) {
+    using SH = sp::ShapeTab3<S>;
+    sp::ShapeCoef3<T> C{};
+    for (int s = 0; s < SH::NS; ++s) C.J[s] = (T)(s < e->ham.n_exch ? e->ham.J[s] : 0.0);
+    for (int q = 0; q < SH::NB0; ++q)
+        for (const HostBond& b : e->all_bonds)
+            if (b.d[0] == SH::da[q] && b.d[1] == SH::db[q] && b.d[2] == SH::dc[q] && b.shell == 0) {
+                C.Dx[q] = (T)b.D[0];
+                C.Dy[q] = (T)b.D[1];
+                C.Dz[q] = (T)b.D[2];
+            }
+    return C;
+}
+
+template <typename T, int S, int NDMI, int TX, int TY, int SOLVER>
+void go_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    const int target = kTile3Cfgs[e->tile3_cfg].blocks;
+    sp::Site3D Z{};
+    Z.nc = e->geo.n[2];
+    Z.per_c = e->geo.per[2];
+    Z.tiles_x = (e->geo.n[0] + TX - 1) / TX;
+    Z.tiles_y = (e->geo.n[1] + TY - 1) / TY;
+    const int txy = Z.tiles_x * Z.tiles_y;
+    const int chunks = std::max(1, std::min(Z.nc, (target + txy - 1) / txy));
+    Z.zc = (Z.nc + chunks - 1) / chunks;
+    const int nchunks = (Z.nc + Z.zc - 1) / Z.zc;
+    hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, NDMI, TX, TY, SOLVER>), dim3((unsigned)(txy * nchunks)),
+                       dim3(TX * TY), 0, e->stream, shape_coef3_for<T, S>(e), make_site2d<T>(e, p), Z,
+                       make_llg<T>(p, step, p->replica), e->d_flag, static_cast<const T*>(nin), static_cast<T*>(nout));
+}
+
+template <typename T, int TX, int TY, int SOLVER>
+void go_tile3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    const bool dmi = e->shape3_ndmi != 0;
+    switch (e->shape3) {
+        case sp::SH3_SC1:
+            dmi ? go_shape3<T, sp::SH3_SC1, 6, TX, TY, SOLVER>(e, p, step, nin, nout)
+                : go_shape3<T, sp::SH3_SC1, 0, TX, TY, SOLVER>(e, p, step, nin, nout);
+            break;
+        case sp::SH3_SC2:
+            dmi ? go_shape3<T, sp::SH3_SC2, 6, TX, TY, SOLVER>(e, p, step, nin, nout)
+                : go_shape3<T, sp::SH3_SC2, 0, TX, TY, SOLVER>(e, p, step, nin, nout);
+            break;
+        default:
+            dmi ? go_shape3<T, sp::SH3_SC3, 6, TX, TY, SOLVER>(e, p, step, nin, nout)
+                : go_shape3<T, sp::SH3_SC3, 0, TX, TY, SOLVER>(e, p, step, nin, nout);
+            break;
+    }
+}
+
+template <typename T, int SOLVER>
+void go_cfg3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    if constexpr (sizeof(T) == 8) {
+        go_tile3<T, 16, 16, SOLVER>(e, p, step, nin, nout);
+    } else {
+        if (e->tile3_cfg == 1 || e->tile3_cfg == 3)
+            go_tile3<T, 16, 16, SOLVER>(e, p, step, nin, nout);
+        else if (e->tile3_cfg == 2)
+            go_tile3<T, 32, 8, SOLVER>(e, p, step, nin, nout);
+        // configurations 0 and 4 share the 32x16 kernel (different chunking)
+        else
+            go_tile3<T, 32, 16, SOLVER>(e, p, step, nin, nout);
+    }
+}
+
+template <typename T>
+void launch_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    if (p->solver == SP_SOLVER_HEUN)
+        go_cfg3<T, sp::SOLVER_HEUN>(e, p, step, nin, nout);
+    else if (p->solver == SP_SOLVER_SIB)
+        go_cfg3<T, sp::SOLVER_SIB>(e, p, step, nin, nout);
+    else
+        go_cfg3<T, sp::SOLVER_DEPONDT>(e, p, step, nin, nout);
+}
+
 template <typename T>
 int launch_step(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     if (std::strcmp(e->path, "shape2d") == 0) {
         launch_shape<T>(e, p, step, nin, nout);
+        HIPCHK(e, hipGetLastError());
+        return SP_OK;
+    }
+    if (std::strcmp(e->path, "shape3d") == 0) {
+        launch_shape3<T>(e, p, step, nin, nout);
         HIPCHK(e, hipGetLastError());
         return SP_OK;
     }
@@ -1074,8 +1190,28 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
             e->path = "shape2d";
         }
     }
+    // 3D one-atom lattices: streamed fused path when the bond table matches a
+    // compile-time simple-cubic stencil (DMI on the first shell only)
+    e->shape3 = -1;
+    e->shape3_ndmi = 0;
+    // default 3D tile: 32x16 columns, two workgroups per CU (fastest measured
+    // on the 128^3 workload); FP64 takes 16x16 (LDS)
+    e->tile3_cfg = e->precision == SP_F64 ? 1 : 4;
+    if (g.nb == 1 && g.n[2] > 1 && !H.ddi && H.n_gauss == 0) {
+        bool ok = true;
+        for (const HostBond& b : all_bonds)
+            if (b.shell > 0 && (b.D[0] != 0.0 || b.D[1] != 0.0 || b.D[2] != 0.0)) ok = false;
+        const int shp = ok ? detect_shape3(e) : -1;
+        if (shp >= 0) {
+            e->shape3 = shp;
+            for (const HostBond& b : all_bonds)
+                if (b.shell == 0 && (b.D[0] != 0.0 || b.D[1] != 0.0 || b.D[2] != 0.0)) e->shape3_ndmi = 1;
+            e->path = "shape3d";
+        }
+    }
     e->path_label = e->path;
     if (e->shape >= 0) e->path_label += std::string("/") + kTileCfgs[e->tile_cfg].name;
+    if (e->shape3 >= 0) e->path_label += std::string("/") + kTile3Cfgs[e->tile3_cfg].name;
 
     if (had_spins) {
         if ((rc = DISPATCH(e, copy_in_soa, e, e->d_n, saved.data(), 3LL * e->N))) return rc;
@@ -1285,11 +1421,25 @@ int sp_set_step_path(sp_engine* e, const char* name) {
         }
         e->path = "shape2d";
         e->tile_cfg = cfg;
+    } else if (s.rfind("shape3d", 0) == 0) {
+        if (e->shape3 < 0)
+            return fail(e, SP_E_UNSUPPORTED, "shape3d needs a 3D one-atom bond table matching a compile-time stencil");
+        int cfg = e->precision == SP_F64 ? 1 : 4;
+        if (s.size() > 7) {
+            if (s[7] != '/') return fail(e, SP_E_ARG, "unknown step path " + s);
+            cfg = -1;
+            for (int k = 0; k < kNumTile3Cfgs; ++k)
+                if (s.substr(8) == kTile3Cfgs[k].name && (e->precision != SP_F64 || k == 1 || k == 3)) cfg = k;
+            if (cfg < 0) return fail(e, SP_E_ARG, "unknown tile configuration in " + s);
+        }
+        e->path = "shape3d";
+        e->tile3_cfg = cfg;
     } else {
         return fail(e, SP_E_ARG, "unknown step path " + s);
     }
     e->path_label = e->path;
     if (std::strcmp(e->path, "shape2d") == 0) e->path_label += std::string("/") + kTileCfgs[e->tile_cfg].name;
+    if (std::strcmp(e->path, "shape3d") == 0) e->path_label += std::string("/") + kTile3Cfgs[e->tile3_cfg].name;
     return SP_OK;
 }
 
@@ -1300,6 +1450,9 @@ int sp_autotune(sp_engine* e, const sp_llg_params* p, int n_steps, double* ms_pe
     if (n_steps < 1 || n_steps > 100000) return fail(e, SP_E_ARG, "n_steps must be in 1..100000");
     (void)hipSetDevice(e->device);
     std::vector<std::string> cands{"twopass"};
+    if (e->shape3 >= 0)
+        for (int k = 0; k < kNumTile3Cfgs; ++k)
+            if (e->precision != SP_F64 || k == 1 || k == 3) cands.push_back(std::string("shape3d/") + kTile3Cfgs[k].name);
     if (p->solver != SP_SOLVER_DEPONDT) {
         // Heun and SIB: the two-pass kernels or the one tile shape they are built for
         if (e->shape >= 0)

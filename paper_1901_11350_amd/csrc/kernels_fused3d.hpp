@@ -1,0 +1,290 @@
+// kernels_fused3d.hpp -- fused LLG step (Depondt, Heun or SIB) for one-atom
+// simple-cubic lattices with a compile-time neighbour stencil, streamed
+// plane by plane along c (2.5D blocking).
+//
+// A workgroup owns a TX x TY column of the lattice over ZC consecutive
+// planes.  It marches along c keeping rings of four planes in LDS: n(t) with
+// a 2R halo in a and b, and three planes of predictor output with an R halo.  Iteration
+// k stores n(t) plane k+1 (loaded into registers one iteration earlier) and
+// issues the loads of plane k+2, computes the predictor of plane k (tile + R
+// halo; needs n(t) planes k-1..k+1) and the corrector of plane k-1 (needs
+// predictor planes k-2..k), which is written once to HBM.  Only two extra
+// predictor planes per column are recomputed (instead of a full 3D halo),
+// and each thread keeps the rotation vector / Heun slope and the thermal
+// field of its own site from the predictor of a plane to its corrector one
+// iteration later.
+#pragma once
+
+#include "kernels_fused2d.hpp"
+
+namespace sp {
+
+enum Shape3D { SH3_SC1 = 0, SH3_SC2, SH3_SC3, SH3_COUNT };
+
+template <int S>
+struct ShapeTab3;
+
+// simple cubic: shells at 1, sqrt2, sqrt3 lattice constants
+template <>
+struct ShapeTab3<SH3_SC1> {
+    static constexpr int NB = 6, NS = 1, R = 1, NB0 = 6;
+    static constexpr int da[NB] = {1, -1, 0, 0, 0, 0};
+    static constexpr int db[NB] = {0, 0, 1, -1, 0, 0};
+    static constexpr int dc[NB] = {0, 0, 0, 0, 1, -1};
+    static constexpr int sh[NB] = {0, 0, 0, 0, 0, 0};
+};
+template <>
+struct ShapeTab3<SH3_SC2> {
+    static constexpr int NB = 18, NS = 2, R = 1, NB0 = 6;
+    static constexpr int da[NB] = {1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int db[NB] = {0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int dc[NB] = {0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr int sh[NB] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+};
+template <>
+struct ShapeTab3<SH3_SC3> {
+    static constexpr int NB = 26, NS = 3, R = 1, NB0 = 6;
+    static constexpr int da[NB] = {1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                                   1, -1, 1, -1, 1, -1, -1, 1};
+    static constexpr int db[NB] = {0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                                   1, -1, 1, -1, -1, 1, 1, -1};
+    static constexpr int dc[NB] = {0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                                   1, -1, -1, 1, 1, -1, 1, -1};
+    static constexpr int sh[NB] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
+                                   2, 2, 2, 2, 2, 2, 2, 2};
+};
+
+// Run-time coefficients in shape order (DMI vectors may point anywhere).
+template <typename T>
+struct ShapeCoef3 {
+    T J[4];
+    T Dx[8], Dy[8], Dz[8];   // first-shell bonds only
+};
+
+struct Site3D {
+    int nc, per_c;
+    int zc;                  // planes per workgroup
+    int tiles_x, tiles_y;
+};
+
+template <typename T, int S, int TX, int TY>
+struct PlaneLDS {
+    static constexpr int R = ShapeTab3<S>::R;
+    static constexpr int WN = TX + 4 * R, HN = TY + 4 * R, PN = WN * HN;   // n(t) plane + 2R halo
+    static constexpr int WP = TX + 2 * R, HP = TY + 2 * R, PP = WP * HP;   // predictor plane + R halo
+    V4<T> sN[4][PN];
+    V4<T> sP[3][PP];   // predictor plane k lives in slot k mod 3
+};
+
+// Field of a site whose own plane sits in ring slot s0 at LDS cell c (pitch
+// W); neighbours in planes c +- 1 sit in slots sm, sp.
+template <typename T, int S, int NDMI, int W, int PL>
+__device__ __forceinline__ V3<T> shape_field3(const ShapeCoef3<T>& C, const Site2D<T>& Q,
+                                              const V4<T> (*rings)[PL], int sm, int s0, int sp, int c, V3<T> ni) {
+    using SH = ShapeTab3<S>;
+    V3<T> acc[SH::NS];
+#pragma unroll
+    for (int s = 0; s < SH::NS; ++s) acc[s] = V3<T>{T(0), T(0), T(0)};
+    V3<T> dm{T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < SH::NB; ++q) {
+        const int slot = SH::dc[q] < 0 ? sm : (SH::dc[q] > 0 ? sp : s0);
+        const V4<T> v = rings[slot][c + SH::da[q] + SH::db[q] * W];
+        acc[SH::sh[q]].x += v.x;
+        acc[SH::sh[q]].y += v.y;
+        acc[SH::sh[q]].z += v.z;
+        if (q < NDMI) {
+            // n_j x D
+            dm.x += v.y * C.Dz[q] - v.z * C.Dy[q];
+            dm.y += v.z * C.Dx[q] - v.x * C.Dz[q];
+            dm.z += v.x * C.Dy[q] - v.y * C.Dx[q];
+        }
+    }
+    const T kn = Q.K2 * (Q.Kax[0] * ni.x + Q.Kax[1] * ni.y + Q.Kax[2] * ni.z);
+    V3<T> g{Q.gZ[0] - kn * Q.Kax[0] - dm.x, Q.gZ[1] - kn * Q.Kax[1] - dm.y, Q.gZ[2] - kn * Q.Kax[2] - dm.z};
+#pragma unroll
+    for (int s = 0; s < SH::NS; ++s) {
+        g.x -= C.J[s] * acc[s].x;
+        g.y -= C.J[s] * acc[s].y;
+        g.z -= C.J[s] * acc[s].z;
+    }
+    return g;
+}
+
+// Plane index with periodic wrap, or in = false outside an open lattice.
+__device__ __forceinline__ int wrap_plane(int z, int nc, int per, bool& in) {
+    if (z >= 0 && z < nc) return z;
+    if (!per) {
+        in = false;
+        return 0;
+    }
+    z %= nc;
+    return z < 0 ? z + nc : z;
+}
+
+template <typename T, int S, int NDMI, int TX, int TY, int SOLVER>
+__global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site2D<T> Q, Site3D Z, LLGArgs<T> A,
+                                                            const int* __restrict__ abort_flag,
+                                                            const T* __restrict__ n, T* __restrict__ nout) {
+    if (abort_flag && *abort_flag) return;
+    using PL = PlaneLDS<T, S, TX, TY>;
+    constexpr int R = PL::R, WN = PL::WN, PN = PL::PN, WP = PL::WP, PP = PL::PP;
+    constexpr int NT = TX * TY;
+    constexpr int RING = PP - TX * TY;
+    constexpr int KST = (PN + NT - 1) / NT;
+    constexpr int KRG = (RING + NT - 1) / NT;
+    __shared__ PL L;
+    const int tid = threadIdx.x;
+    const int tiles_xy = Z.tiles_x * Z.tiles_y;
+    const int zchunk = blockIdx.x / tiles_xy;
+    const int txy = blockIdx.x - zchunk * tiles_xy;
+    const int ty0 = txy / Z.tiles_x;
+    const int x0 = (txy - ty0 * Z.tiles_x) * TX, y0 = ty0 * TY;
+    const int z0 = zchunk * Z.zc;
+    const int z1 = min(z0 + Z.zc, Z.nc);
+    const int NA = Q.na, NBB = Q.nb;
+    const long long plane = (long long)NA * NBB;
+    const long long N = plane * Z.nc;
+    const int tx = tid % TX, tyy = tid / TX;
+    // predictor ring slot of plane z (z >= -2)
+    auto pslot = [](int z) { return (z + 3) % 3; };
+
+    // n(t) of plane z (tile + 2R halo): load into registers, later store into
+    // ring slot z & 3 (the loads of plane k+2 fly while planes k and k-1 are
+    // computed)
+    auto load_plane = [&](int z, V3<T>* st) {
+        bool zin = true;
+        const int gz = wrap_plane(z, Z.nc, Z.per_c, zin);
+#pragma unroll
+        for (int k = 0; k < KST; ++k) {
+            const int idx = tid + k * NT;
+            st[k] = V3<T>{T(0), T(0), T(0)};
+            if (idx < PN) {
+                const int ly = idx / WN, lx = idx - ly * WN;
+                bool in = zin;
+                const int gx = wrap_once(x0 - 2 * R + lx, NA, Q.per_a, in);
+                const int gy = wrap_once(y0 - 2 * R + ly, NBB, Q.per_b, in);
+                if (in) {
+                    const long long g = gx + (long long)NA * gy + plane * gz;
+                    st[k] = V3<T>{n[g], n[N + g], n[2 * N + g]};
+                }
+            }
+        }
+    };
+    auto store_plane = [&](int z, const V3<T>* st) {
+        V4<T>* dst = L.sN[z & 3];
+#pragma unroll
+        for (int k = 0; k < KST; ++k) {
+            const int idx = tid + k * NT;
+            if (idx < PN) dst[idx] = V4<T>{st[k].x, st[k].y, st[k].z, T(0)};
+        }
+    };
+    // thermal field of predictor-frame cell (px, py) of plane z
+    auto thermal = [&](int px, int py, int z) -> V3<T> {
+        bool in = true;
+        const int gz = wrap_plane(z, Z.nc, Z.per_c, in);
+        const int gx = wrap_once(x0 - R + px, NA, Q.per_a, in);
+        const int gy = wrap_once(y0 - R + py, NBB, Q.per_b, in);
+        if (!A.thermal || !in) return V3<T>{T(0), T(0), T(0)};
+        const long long site = gx + (long long)NA * gy + plane * gz;
+        return Q.sigma * normals3(thermal_bits(A.key, (uint32_t)site), T(0));
+    };
+    // predictor of cell (px, py) of plane z into predictor slot z & 3
+    auto predict = [&](int px, int py, int z, V3<T> Bth) -> V3<T> {
+        bool in = true;
+        wrap_plane(z, Z.nc, Z.per_c, in);
+        wrap_once(x0 - R + px, NA, Q.per_a, in);
+        wrap_once(y0 - R + py, NBB, Q.per_b, in);
+        V4<T> out{T(0), T(0), T(0), T(0)};
+        V3<T> keep{T(0), T(0), T(0)};
+        if (in) {
+            const int c = (py + R) * WN + (px + R);
+            const V4<T> n4 = L.sN[z & 3][c];
+            const V3<T> ni{n4.x, n4.y, n4.z};
+            const V3<T> g = shape_field3<T, S, NDMI, WN, PN>(C, Q, L.sN, (z - 1) & 3, z & 3, (z + 1) & 3, c, ni);
+            const V3<T> B = (-Q.inv_mumuB) * g + Bth;
+            const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
+            V3<T> o;
+            if constexpr (SOLVER == SOLVER_HEUN) {
+                keep = cross(ni, Ai);
+                o = normalize3(ni + A.dt * keep);
+            } else if constexpr (SOLVER == SOLVER_SIB) {
+                o = T(0.5) * (ni + sib_stage(ni, Ai, A.dt));
+            } else {
+                keep = Ai;
+                o = rotate_fast(ni, T(-1) * Ai, A.dt);
+            }
+            out = V4<T>{o.x, o.y, o.z, T(0)};
+        }
+        L.sP[pslot(z)][py * WP + px] = out;
+        return keep;
+    };
+
+    // pipeline: predictor planes z0-1 .. z1, corrector planes z0 .. z1-1
+    V3<T> st[KST];
+    load_plane(z0 - 2, st);
+    store_plane(z0 - 2, st);
+    load_plane(z0 - 1, st);
+    store_plane(z0 - 1, st);
+    load_plane(z0, st);
+    V3<T> keepA{T(0), T(0), T(0)}, keepB{T(0), T(0), T(0)};   // of the previous plane
+    for (int k = z0 - 1; k <= z1; ++k) {
+        // thermal fields of this thread's cells of plane k, then stage n(t) plane k+1
+        const V3<T> bI = thermal(tx + R, tyy + R, k);
+        V3<T> bR[KRG];
+#pragma unroll
+        for (int q = 0; q < KRG; ++q) {
+            const int h = tid + q * NT;
+            bR[q] = V3<T>{T(0), T(0), T(0)};
+            if (h < RING) {
+                int px, py;
+                ring_cell<R, TX, TY>(h, px, py);
+                bR[q] = thermal(px, py, k);
+            }
+        }
+        store_plane(k + 1, st);
+        if (k + 2 <= z1 + 1) load_plane(k + 2, st);
+        __syncthreads();
+        const V3<T> aI = predict(tx + R, tyy + R, k, bI);
+#pragma unroll
+        for (int q = 0; q < KRG; ++q) {
+            const int h = tid + q * NT;
+            if (h < RING) {
+                int px, py;
+                ring_cell<R, TX, TY>(h, px, py);
+                predict(px, py, k, bR[q]);
+            }
+        }
+        __syncthreads();
+        // corrector of plane k-1
+        const int zc = k - 1;
+        const int gx = x0 + tx, gy = y0 + tyy;
+        if (zc >= z0 && zc < z1 && gx < NA && gy < NBB) {
+            const int c = (tyy + R) * WP + (tx + R);
+            const V4<T> p4 = L.sP[pslot(zc)][c];
+            const V3<T> npi{p4.x, p4.y, p4.z};
+            const V3<T> g = shape_field3<T, S, NDMI, WP, PP>(C, Q, L.sP, pslot(zc - 1), pslot(zc), pslot(zc + 1), c, npi);
+            const V3<T> B = (-Q.inv_mumuB) * g + keepB;
+            const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
+            const V4<T> n4 = L.sN[zc & 3][(tyy + 2 * R) * WN + (tx + 2 * R)];
+            const V3<T> ni{n4.x, n4.y, n4.z};
+            V3<T> o;
+            if constexpr (SOLVER == SOLVER_HEUN) {
+                o = normalize3(ni + (T(0.5) * A.dt) * (keepA + cross(npi, Ap)));
+            } else if constexpr (SOLVER == SOLVER_SIB) {
+                o = renorm_if_float(sib_stage(ni, Ap, A.dt));
+            } else {
+                const V3<T> w{T(-0.5) * (keepA.x + Ap.x), T(-0.5) * (keepA.y + Ap.y), T(-0.5) * (keepA.z + Ap.z)};
+                o = renorm_if_float(rotate_fast(ni, w, A.dt));
+            }
+            const long long gi = gx + (long long)NA * gy + plane * zc;
+            nout[gi] = o.x;
+            nout[N + gi] = o.y;
+            nout[2 * N + gi] = o.z;
+        }
+        keepA = aI;
+        keepB = bI;
+    }
+}
+
+}  // namespace sp

@@ -1,0 +1,71 @@
+"""GPU parity of the streamed 3D fused step (compile-time simple-cubic
+stencils, one to three shells, DMI on the first shell) against the FP64
+oracle, for every tile configuration and integrator, ragged tiles, open and
+periodic axes, thin lattices, and the full 128^3 workload on sampled sites."""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import spin_inputs as si
+from gpu_util import TOL, announce, assert_close, make_pair, need_gpu, rel_err
+
+pytestmark = pytest.mark.gpu
+
+HAM2 = si.WORKLOADS["cubic128_bulkdmi"].hamiltonian
+CASES = {
+    "sc2_bulk_12x10x8": (si.simple_cubic(12, 10, 8), HAM2),
+    "sc2_bulk_ragged_37x21x11_openz": (si.simple_cubic(37, 21, 11, periodic=(1, 1, 0)), HAM2),
+    "sc1_interfacial_20x18x6_open": (si.simple_cubic(20, 18, 6, periodic=(0, 0, 0)),
+                                     dataclasses.replace(HAM2, J=(1.0,), D=(0.2,), dmi_kind=si.DMI_INTERFACIAL,
+                                                         K=(0.1,), K_axis=((0.0, 0.6, 0.8),))),
+    "sc3_nodmi_17x16x5": (si.simple_cubic(17, 16, 5), dataclasses.replace(HAM2, J=(1.0, 0.2, -0.05), D=())),
+    "sc2_thin_9x9x2": (si.simple_cubic(9, 9, 2), HAM2),
+    "sc1_40x4x3_periodic_small": (si.simple_cubic(40, 4, 3), dataclasses.replace(HAM2, J=(1.0,), D=(0.15,))),
+}
+CFGS = {"f32": ["32x16", "16x16", "32x8", "16x16z", "32x16b"], "f64": ["16x16", "16x16z"]}
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("solver", ["depondt", "heun", "sib"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_fused3d_matches_oracle(ora, case, precision, solver):
+    geo, ham = CASES[case]
+    announce(f"fused3d {case} {precision} {solver}")
+    e, s = make_pair(ora, geo, ham, precision)
+    assert e.step_path.startswith("shape3d"), e.step_path
+    n0 = si.uniform_sphere(s.N, 19)
+    n_ora, _ = s.run(n0, 0.5, 0.001, 3, T=30.0, seed=4, step0=7, solver=solver)
+    res = {}
+    for path in ["twopass"] + ["shape3d/" + c for c in CFGS[precision]]:
+        e.step_path = path
+        assert e.step_path == path
+        e.set_spins(n0)
+        e.step = 7
+        e.run(0.5, 0.001, 3, T=30.0, seed=4, solver=solver)
+        res[path] = e.get_spins()
+        assert_close(res[path], n_ora, precision, what=f"{path} {case} {solver}")
+    for path in res:
+        assert rel_err(res[path], res["twopass"]) <= 2 * TOL[precision]
+
+
+def test_fused3d_full_cubic128_thermal(ora):
+    """The 128^3 lattice (2,097,152 spins) on the streamed path: two steps with
+    the thermal field on (T = 20 K, global site index as Philox counter)
+    against the oracle over the whole lattice."""
+    w = si.WORKLOADS["cubic128_bulkdmi"]
+    announce("fused3d cubic128 full")
+    e, s = make_pair(ora, w.geometry, w.hamiltonian, "f32")
+    assert e.step_path.startswith("shape3d")
+    n0 = si.conical_helix(w.geometry, seed=w.init_seed)
+    e.set_spins(n0)
+    d = w.dynamics
+    e.run(d.alpha, d.dt, 2, T=20.0, seed=d.seed)
+    n_ora, _ = s.run(n0, d.alpha, d.dt, 2, T=20.0, seed=d.seed)
+    assert_close(e.get_spins(), n_ora, "f32", what="cubic128 two thermal steps")
