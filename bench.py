@@ -44,16 +44,16 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(kernel: str, workload: str, step_path: str):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary of this kernel and workload, or None when there is none or the
-    kernel sources changed since the counters were taken."""
+    summary of this kernel, workload and step path (tile shape), or None when
+    there is none or the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_sha256") != kernel_source_digest():
+    if rec.get("kernel_source_sha256") != kernel_source_digest() or rec.get("step_path") != step_path:
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
@@ -61,7 +61,8 @@ def measured_traffic(kernel: str, workload: str):
 def flops_per_update(workload) -> float:
     """Algorithmic FP32 flops of one Depondt spin-update (FMA = 2 flops):
     two field evaluations (neighbour sums 3 per bond, 6 per shell for J,
-    8 per in-plane DMI bond, 9 anisotropy, 3 Zeeman) plus 163 for the two
+    8 per in-plane DMI bond or 12 per 3D DMI bond, 9 anisotropy, 3 Zeeman)
+    plus 163 for the two
     A vectors, their average, two Rodrigues rotations and the
     renormalisation, plus 15 for Box-Muller at T > 0 (integer Philox
     operations and transcendentals are not counted)."""
@@ -72,7 +73,8 @@ def flops_per_update(workload) -> float:
     shells = max(len(h.J), len(h.D))
     nb = sum(per_shell[lat][:shells])
     ndmi = sum(per_shell[lat][:len(h.D)]) if any(h.D) else 0
-    field = 3 * nb + 6 * len(h.J) + 8 * ndmi + 9 + 3
+    per_dmi = 8 if workload.geometry.n_cells[2] == 1 else 12
+    field = 3 * nb + 6 * len(h.J) + per_dmi * ndmi + 9 + 3
     return 2 * field + 163 + (15 if workload.dynamics.T > 0 else 0)
 
 
@@ -432,7 +434,10 @@ def main():
     ap.add_argument("--workload", default="triangular512_sllg")
     ap.add_argument("--observe-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every step path / tile shape first and keep the fastest (default: the engine's "
+                         "default path, chosen from such sweeps)")
+    ap.add_argument("--no-autotune", action="store_true", help="(default; kept for old command lines)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
     if args.calibrate_copy:
@@ -460,7 +465,7 @@ def main():
         n0 = si.uniform_sphere(e.N, w.init_seed)
     e.set_spins(n0)
     tuned_ms = None
-    if not args.no_autotune:
+    if args.autotune and not args.no_autotune:
         tuned_ms = e.autotune(d.alpha, d.dt, d.T, d.seed, n_steps=50)
     print(f"[bench] workload={w.name} N={e.N} path={e.step_path} precision={w.precision} "
           f"autotune_ms={tuned_ms}", file=sys.stderr, flush=True)
@@ -500,7 +505,7 @@ def main():
     tflops = fpu * e.N / launches_per_step / t_launch / 1e12
     kernel_name = {"fused2d": "k_depondt_fused2d", "twopass": "k_predict+k_correct"}.get(
         e.step_path, "k_fused2d_shape")
-    traffic = measured_traffic(kernel_name, w.name)
+    traffic = measured_traffic(kernel_name, w.name, e.step_path)
 
     last = obs[-1] if obs else e.observe()
     line = {
