@@ -17,8 +17,18 @@
  *   - Depondt's rotation-based Heun scheme: Appendix B (predictor rotates
  *     n(t) by R(A(t)); corrector rotates n(t) by R of the averaged field).
  *   - Energy from fields: Appendix H (linear + quadratic decomposition of H).
+ *   - Heun's method and the semi-implicit midpoint scheme SIB: Appendices B
+ *     and C (Cramer's rule for each midpoint stage).
+ *   - Metropolis Monte Carlo with cone trial moves: Sec. III.B.
+ *   - GNEB (improved tangent, geodesic distances, springs, per-spin
+ *     projection, velocity projection, climbing and falling images):
+ *     Sec. III.D, Appendices D and F; the single-spin Gaussian landscape of
+ *     Appendix G as an on-site potential.
+ *   - The convolution, SiLU and Adam steps of the learned dipole field (not
+ *     in the paper) with the bf16 rounding contract of the GPU kernels.
  * Readings where the paper is silent, garbled or ambiguous are marked
- * "Reading:" next to the code that takes them.
+ * "Reading:" next to the code that takes them.  Every function is pinned
+ * by a test that does not re-type its formula (tests/test_oracle_*.py).
  */
 #include "oracle.h"
 
