@@ -1952,7 +1952,9 @@ struct sp_gneb {
     int M = 0, N = 0, nblk = 0;
     double k = 1.0, dt = 0.1, m = 1.0;
     void *x = nullptr, *v = nullptr, *F = nullptr, *Fp = nullptr, *g = nullptr, *tau = nullptr;
-    double* part = nullptr;
+    double* part = nullptr;  // force partials (v.F, F.F)
+    double* epart = nullptr; // energy partials [M][nblk]
+    double* tpart = nullptr; // tangent partials [M][nblk][3]
     double* E = nullptr;    // [M]
     double* s3 = nullptr;   // [3M]: |tau|^2, g.tau, l^2
     double* vf = nullptr;   // [2]
@@ -1978,14 +1980,12 @@ int gneb_forces(sp_gneb* G, bool update_v) {
     T* x = static_cast<T*>(G->x);
     T* g = static_cast<T*>(G->g);
     T* tau = static_cast<T*>(G->tau);
-    hipLaunchKernelGGL((sp::k_gneb_grad<T>), dim3(G->nblk, G->M), dim3(256), 0, e->stream, d, L, C, P, x, g, G->part);
-    hipLaunchKernelGGL((sp::k_gneb_sum<1>), dim3(G->M), dim3(256), 0, e->stream, G->part, G->nblk, G->E);
-    hipLaunchKernelGGL((sp::k_gneb_tangent<T>), dim3(G->nblk, G->M), dim3(256), 0, e->stream, d, x, g, G->E, tau,
-                       G->part);
-    hipLaunchKernelGGL((sp::k_gneb_sum<3>), dim3(G->M), dim3(256), 0, e->stream, G->part, G->nblk, G->s3);
+    hipLaunchKernelGGL((sp::k_gneb_grad<T>), dim3(G->nblk, G->M), dim3(256), 0, e->stream, d, L, C, P, x, g, G->epart);
+    hipLaunchKernelGGL((sp::k_gneb_tangent<T>), dim3(G->nblk, G->M), dim3(256), 0, e->stream, d, x, g, G->epart, G->E,
+                       tau, G->tpart);
     hipLaunchKernelGGL((sp::k_gneb_force<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, e->stream, d, (T)G->k,
-                       (T)(G->dt / (2.0 * G->m)), update_v ? 1 : 0, x, g, tau, G->s3, G->types, static_cast<T*>(G->F),
-                       static_cast<const T*>(G->Fp), static_cast<T*>(G->v), G->part);
+                       (T)(G->dt / (2.0 * G->m)), update_v ? 1 : 0, x, g, tau, G->tpart, G->s3, G->types,
+                       static_cast<T*>(G->F), static_cast<const T*>(G->Fp), static_cast<T*>(G->v), G->part);
     if (update_v)
         hipLaunchKernelGGL((sp::k_gneb_sum<2>), dim3(1), dim3(256), 0, e->stream, G->part, (G->M - 2) * G->nblk,
                            G->vf);
@@ -2007,15 +2007,17 @@ int gneb_project(sp_gneb* G) {
 template <typename T>
 int gneb_iterate(sp_gneb* G, int n_iter) {
     const sp::GnebDims d{G->M, G->N, G->nblk};
+    // the projection of each iteration is applied by the next move; the
+    // state between calls is always projected (v, F_prev final)
     for (int it = 0; it < n_iter; ++it) {
         hipLaunchKernelGGL((sp::k_gneb_move<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, G->e->stream, d, (T)G->dt,
-                           (T)(G->dt * G->dt / (2.0 * G->m)), static_cast<T*>(G->x), static_cast<const T*>(G->v),
-                           static_cast<const T*>(G->Fp));
+                           (T)(G->dt * G->dt / (2.0 * G->m)), it > 0 ? 1 : 0, G->vf, static_cast<const T*>(G->F),
+                           static_cast<T*>(G->x), static_cast<T*>(G->v), static_cast<T*>(G->Fp));
         int rc = gneb_forces<T>(G, true);
         if (rc) return rc;
-        if ((rc = gneb_project<T>(G))) return rc;
         ++G->iterations;
     }
+    if (n_iter > 0) return gneb_project<T>(G);
     return SP_OK;
 }
 
@@ -2049,7 +2051,7 @@ int gneb_download(sp_gneb* G, const void* src, double* out, size_t count) {
 }
 
 void gneb_free(sp_gneb* G) {
-    void* ps[] = {G->x, G->v, G->F, G->Fp, G->g, G->tau, G->part, G->E, G->s3, G->vf, G->types};
+    void* ps[] = {G->x, G->v, G->F, G->Fp, G->g, G->tau, G->part, G->epart, G->tpart, G->E, G->s3, G->vf, G->types};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }
@@ -2081,11 +2083,13 @@ int sp_gneb_create(sp_gneb** out, sp_engine* e, int n_images, const double* chai
     G->m = vp_mass;
     (void)hipSetDevice(e->device);
     const size_t vb = (size_t)G->M * 3 * G->N * e->esz();
-    const size_t parts = std::max<size_t>((size_t)G->M * G->nblk * 3, (size_t)(G->M - 2) * G->nblk * 2);
+    const size_t parts = (size_t)(G->M - 2) * G->nblk * 2;
     void** bufs[] = {&G->x, &G->v, &G->F, &G->Fp, &G->g, &G->tau};
     for (void** b : bufs)
         if (hipMalloc(b, vb) != hipSuccess) { gneb_free(G); delete G; return fail(e, SP_E_NOMEM, "GNEB allocation failed"); }
     if (hipMalloc((void**)&G->part, parts * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&G->epart, (size_t)G->M * G->nblk * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&G->tpart, (size_t)G->M * G->nblk * 3 * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&G->E, G->M * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&G->s3, 3 * G->M * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&G->vf, 2 * sizeof(double)) != hipSuccess ||

@@ -3,20 +3,24 @@
 // velocity-projection minimiser).
 //
 // The chain holds M images of N spins, image-major, each image SoA.  Images 0
-// and M-1 are fixed.  Per velocity-projection iteration:
-//   k_gneb_move       x <- normalise(x + dt v + dt^2/(2m) F_prev)    (interior)
+// and M-1 are fixed.  Per velocity-projection iteration (five launches):
+//   k_gneb_move       [projection of the previous iteration: v <- (v.F/F.F) F
+//                     if v.F > 0 else 0, F_prev <- F]  then
+//                     x <- normalise(x + dt v + dt^2/(2m) F_prev)    (interior)
 //   k_gneb_grad       g = dH/dn per image, energy partials per block
-//   k_gneb_sum        E[v]                                             (FP64)
-//   k_gneb_tangent    improved tangent, per-spin projection; partials of
+//   k_gneb_tangent    E of the image and its neighbours from the partials;
+//                     improved tangent, per-spin projection; partials of
 //                     |tau|^2, g.tau, and squared geodesic angles to image v+1
-//   k_gneb_sum        |tau|^2[v], g.tau[v], l^2[v]
-//   k_gneb_force      F = -g + (g.t)t, per-spin projected, + k (l_v - l_{v-1}) t
+//   k_gneb_force      |tau|^2, g.tau, l^2 from the partials;
+//                     F = -g + (g.t)t, per-spin projected, + k (l_v - l_{v-1}) t
 //                     (climbing images: -g + 2 (g.t)t, falling: -g, no spring)
 //                     with t = tau/|tau|; v <- v + dt/(2m)(F_prev + F);
 //                     chain-wide partials of v.F and F.F
 //   k_gneb_sum        v.F, F.F
-//   k_gneb_project    v <- (v.F/F.F) F if v.F > 0 else 0;  F_prev <- F
-// Every reduction is a fixed-order FP64 tree (bit-reproducible).
+// k_gneb_project applies the last projection when a run of iterations ends.
+// Every reduction is a fixed-order FP64 tree: a row of partials is summed by
+// the same thread-strided loop and tree in every workgroup that needs it
+// (bit-reproducible, identical everywhere).
 #pragma once
 
 #include "kernels_field.hpp"
@@ -40,6 +44,29 @@ __device__ __forceinline__ void block_sums(double* acc) {
     }
 }
 
+// Sum of row `row` of NV-value partials (nblk per row), fixed order; every
+// thread receives the result.
+template <int NV>
+__device__ __forceinline__ void row_sum(const double* __restrict__ part, int nblk, int row, double* out) {
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] += part[((size_t)row * nblk + b) * NV + k];
+    }
+    block_sums<NV>(acc);
+    __shared__ double bc[NV];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) bc[k] = acc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = bc[k];
+    __syncthreads();
+}
+
 struct GnebDims {
     int M;         // images
     int N;         // spins per image
@@ -47,17 +74,33 @@ struct GnebDims {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_gneb_move(GnebDims d, T dt, T half_dt2_m, T* __restrict__ x,
-                                                   const T* __restrict__ v, const T* __restrict__ Fp) {
+__global__ void __launch_bounds__(256) k_gneb_move(GnebDims d, T dt, T half_dt2_m, int project,
+                                                   const double* __restrict__ vf_ff, const T* __restrict__ F,
+                                                   T* __restrict__ x, T* __restrict__ v, T* __restrict__ Fp) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int im = blockIdx.y + 1;   // interior images only
     if (i >= d.N) return;
     const size_t base = (size_t)im * 3 * d.N;
+    T scale = T(0);
+    if (project) {
+        const double vf = vf_ff[0], ff = vf_ff[1];
+        scale = (vf > 0.0 && ff > 0.0) ? (T)(vf / ff) : T(0);
+    }
     T n[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const size_t q = base + (size_t)c * d.N + i;
-        n[c] = x[q] + dt * v[q] + half_dt2_m * Fp[q];
+        T vq, fq;
+        if (project) {
+            fq = F[q];
+            vq = scale * fq;
+            v[q] = vq;
+            Fp[q] = fq;
+        } else {
+            vq = v[q];
+            fq = Fp[q];
+        }
+        n[c] = x[q] + dt * vq + half_dt2_m * fq;
     }
     const T r = T(1) / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
 #pragma unroll
@@ -110,10 +153,18 @@ __global__ void __launch_bounds__(256) k_gneb_sum(const double* __restrict__ par
 // of |tau|^2, g.tau and the squared great-circle angle to image im+1.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gneb_tangent(GnebDims d, const T* __restrict__ x, const T* __restrict__ g,
-                                                      const double* __restrict__ E, T* __restrict__ tau,
-                                                      double* __restrict__ part) {
+                                                      const double* __restrict__ epart, double* __restrict__ E,
+                                                      T* __restrict__ tau, double* __restrict__ part) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int im = blockIdx.y;
+    // energies of this image and its neighbours
+    double Em = 0.0, E0 = 0.0, Ep = 0.0;
+    row_sum<1>(epart, d.nblk, im, &E0);
+    if (im > 0 && im + 1 < d.M) {
+        row_sum<1>(epart, d.nblk, im - 1, &Em);
+        row_sum<1>(epart, d.nblk, im + 1, &Ep);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) E[im] = E0;
     double acc[3] = {0.0, 0.0, 0.0};
     if (i < d.N) {
         const size_t L3 = (size_t)3 * d.N;
@@ -127,7 +178,6 @@ __global__ void __launch_bounds__(256) k_gneb_tangent(GnebDims d, const T* __res
         if (im > 0 && im + 1 < d.M) {
             const V3<T> nm = load3(x + (im - 1) * L3, d.N, i);
             const V3<T> np = load3(x + (im + 1) * L3, d.N, i);
-            const double Ep = E[im + 1], E0 = E[im], Em = E[im - 1];
             double wp, wm;
             if (Ep > E0 && E0 > Em) {
                 wp = 1.0; wm = 0.0;
@@ -162,21 +212,30 @@ __global__ void __launch_bounds__(256) k_gneb_tangent(GnebDims d, const T* __res
 template <typename T>
 __global__ void __launch_bounds__(256) k_gneb_force(GnebDims d, T k_spring, T dt_2m, int update_v,
                                                     const T* __restrict__ x, const T* __restrict__ g,
-                                                    const T* __restrict__ tau, const double* __restrict__ s3,
-                                                    const int* __restrict__ types,
+                                                    const T* __restrict__ tau, const double* __restrict__ tpart,
+                                                    double* __restrict__ s3, const int* __restrict__ types,
                                                     T* __restrict__ F, const T* __restrict__ Fp, T* __restrict__ v,
                                                     double* __restrict__ part) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int im = blockIdx.y + 1;
+    // |tau|^2, g.tau, l^2 of this image and of the one before
+    double s_im[3], s_prev[3];
+    row_sum<3>(tpart, d.nblk, im, s_im);
+    row_sum<3>(tpart, d.nblk, im - 1, s_prev);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < 3; ++k) s3[im * 3 + k] = s_im[k];
+        if (im == 1)
+            for (int k = 0; k < 3; ++k) s3[k] = s_prev[k];
+    }
     double acc[2] = {0.0, 0.0};
     if (i < d.N) {
         const size_t off = (size_t)im * 3 * d.N;
-        const double tn2 = s3[im * 3 + 0];
+        const double tn2 = s_im[0];
         const double inv = tn2 > 0.0 ? 1.0 / sqrt(tn2) : 0.0;
         const int type = types[im];
         const T cpar = type == 1 ? T(2) : (type == 2 ? T(0) : T(1));
-        const T gt = cpar * (T)(s3[im * 3 + 1] * inv);
-        const T fs = type == 0 ? (T)(k_spring * (sqrt(s3[im * 3 + 2]) - sqrt(s3[(im - 1) * 3 + 2]))) : T(0);
+        const T gt = cpar * (T)(s_im[1] * inv);
+        const T fs = type == 0 ? (T)(k_spring * (sqrt(s_im[2]) - sqrt(s_prev[2]))) : T(0);
         const V3<T> n = load3(x + off, d.N, i);
         const V3<T> t = T(inv) * load3(tau + off, d.N, i);
         const V3<T> gi = load3(g + off, d.N, i);
