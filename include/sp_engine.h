@@ -238,11 +238,22 @@ int sp_thermal_normals(sp_engine *e, uint64_t seed, uint64_t step, uint32_t repl
  * ("fused2d", "twopass", ...), for diagnostics. */
 const char *sp_step_path(const sp_engine *e);
 /* Force the step path: "twopass" (any lattice), "fused2d" (one-atom 2D
- * lattice, runtime bond loop) or "shape2d[/TXxTYxNT]" (one-atom 2D lattice
+ * lattice, runtime bond loop), "shape2d[/TXxTYxNT]" (one-atom 2D lattice
  * whose bond table matches a compile-time stencil; optional tile
- * configuration such as "shape2d/32x16x256").  A path the current lattice
- * does not allow gives SP_E_UNSUPPORTED, an unknown name SP_E_ARG.  Reset by
- * sp_set_hamiltonian (which picks the fastest allowed path by default). */
+ * configuration such as "shape2d/32x16x256"), "shape3d[/cfg]" (one-atom
+ * simple-cubic lattice with a compile-time stencil) or "persist2d[/TXxTY]"
+ * (as shape2d; tiles "64x16", "32x32", "32x16" in FP32, "32x16" in FP64;
+ * lattice sides must be multiples of the tile and every tile must fit on
+ * the device at once).  On persist2d, sp_run advances the Depondt solver
+ * many steps per launch (one launch per observation interval): tiles stay
+ * resident and exchange halos through per-tile flags with agent-scope
+ * release/acquire; a tile that waits for its neighbours beyond a bound
+ * (about a second; environment variable SP_PERSIST_SPIN_LIMIT lowers it)
+ * makes sp_run return SP_E_HIP with the spins invalid.  sp_llg_step and the
+ * other solvers use the one-step kernel of the same tile on that path.
+ * A path the current lattice does not allow gives SP_E_UNSUPPORTED, an
+ * unknown name SP_E_ARG.  Reset by sp_set_hamiltonian (which picks the
+ * default path of the lattice). */
 int sp_set_step_path(sp_engine *e, const char *name);
 /* Autotuner: times every step path and tile configuration the current
  * lattice allows (n_steps steps each, after one warm-up step, HIP events on

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <random>
 #include <string>
@@ -22,6 +23,7 @@
 #include "kernels_fft.hpp"
 #include "kernels_mc.hpp"
 #include "kernels_fused3d.hpp"
+#include "kernels_persist2d.hpp"
 
 namespace {
 
@@ -94,6 +96,7 @@ struct sp_engine {
     int shape3 = -1;                  // sp::Shape3D matched by a 3D one-atom bond table, or -1
     int shape3_ndmi = 0;              // DMI on the first shell
     int tile3_cfg = 0;                // index into the 3D tile configurations
+    int persist_cfg = 0;              // index into the persistent-path tile configurations
     std::string path_label;
 
     size_t esz() const { return precision == SP_F64 ? 8 : 4; }
@@ -119,6 +122,10 @@ struct sp_engine {
     int64_t obs_cap = 0;
     int* d_flag = nullptr;            // abort flag (non-finite torque)
     long long* d_abort_step = nullptr;
+    uint32_t* d_pflags = nullptr;     // persistent path: one flag line per tile
+    int pflag_tiles = 0;
+    uint32_t pgen = 0;                // every flag is <= pgen between launches
+    int* d_pstatus = nullptr;         // persistent path: nonzero after a failed wait
     double* h_pin = nullptr;          // pinned staging for small results
     SurrogateState* sur = nullptr;    // learned dipole field (sp_ddi_*)
     FftState* fft = nullptr;          // FFT-convolution dipole field (SP_DDI_FFT)
@@ -526,6 +533,103 @@ void launch_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const voi
     }
 }
 
+// ------------------------------------------------ persistent 2D path
+// Tiles of the persistent kernel (one thread per site); the matching
+// one-step configuration of kTileCfgs serves single steps and the other
+// solvers on this path.
+struct PersistCfg {
+    const char* name;
+    int TX, TY;
+    int tile_cfg;   // index of the same tile in kTileCfgs
+    bool f64;       // offered in FP64
+};
+constexpr PersistCfg kPersistCfgs[] = {{"64x16", 64, 16, 4, false}, {"32x32", 32, 32, 3, false},
+                                       {"32x16", 32, 16, 2, true}};
+constexpr int kNumPersistCfgs = 3;
+constexpr int kPersistSpinLimit = 1 << 21;   // polls per wait (~1 s) before a workgroup gives up
+constexpr int kPersistMaxChunk = 1 << 16;    // steps per launch
+
+template <typename T, int S, int NDMI, int TX, int TY>
+int go_persist(sp_engine* e, const sp_llg_params* p, int n_steps, bool check_only) {
+    const void* fn = reinterpret_cast<const void*>(&sp::k_persist2d<T, S, NDMI, TX, TY>);
+    sp::PersistMap M{};
+    M.tiles_x = e->geo.n[0] / TX;
+    M.tiles_y = e->geo.n[1] / TY;
+    const int ntiles = M.tiles_x * M.tiles_y;
+    int per_cu = 0, n_cu = 0;
+    HIPCHK(e, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, TX * TY, 0));
+    HIPCHK(e, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, e->device));
+    if ((long long)per_cu * n_cu < ntiles)
+        return fail(e, SP_E_UNSUPPORTED, "persist2d needs every tile resident at once: " + std::to_string(ntiles) +
+                                             " tiles, " + std::to_string((long long)per_cu * n_cu) + " slots");
+    if (check_only) return SP_OK;
+    if (ntiles > e->pflag_tiles || e->pgen > (1u << 30)) {
+        int rc;
+        if (ntiles > e->pflag_tiles) {
+            if ((rc = dalloc(e, e->d_pflags, (size_t)ntiles * sp::kFlagStride * sizeof(uint32_t)))) return rc;
+            e->pflag_tiles = ntiles;
+        }
+        HIPCHK(e, hipMemsetAsync(e->d_pflags, 0, (size_t)e->pflag_tiles * sp::kFlagStride * sizeof(uint32_t),
+                                 e->stream));
+        e->pgen = 0;
+    }
+    M.xcd_bands = (ntiles >= 8 && ntiles % 8 == 0) ? 1 : 0;
+    M.n_steps = n_steps;
+    M.gen = e->pgen;
+    // SP_PERSIST_SPIN_LIMIT lowers the bound (tests of the time-out path)
+    M.spin_limit = kPersistSpinLimit;
+    if (const char* lim = std::getenv("SP_PERSIST_SPIN_LIMIT")) M.spin_limit = std::max(0, std::atoi(lim));
+    sp::ShapeCoef<T> C = shape_coef_for<T, S>(e);
+    sp::Site2D<T> Q = make_site2d<T>(e, p);
+    sp::LLGArgs<T> A = make_llg<T>(p, e->step, p->replica);
+    const int* abort_flag = e->d_flag;
+    T* b0 = static_cast<T*>(e->d_n);
+    T* b1 = static_cast<T*>(e->d_n2);
+    uint32_t* flags = e->d_pflags;
+    int* status = e->d_pstatus;
+    void* args[] = {&C, &Q, &A, &M, &abort_flag, &b0, &b1, &flags, &status};
+    HIPCHK(e, hipLaunchCooperativeKernel(fn, dim3((unsigned)ntiles), dim3(TX * TY), args, 0, e->stream));
+    e->pgen += (uint32_t)n_steps;
+    if (n_steps & 1) std::swap(e->d_n, e->d_n2);
+    e->step += (uint64_t)n_steps;
+    return SP_OK;
+}
+
+template <typename T, int TX, int TY>
+int go_persist_shape(sp_engine* e, const sp_llg_params* p, int n_steps, bool check_only) {
+#define SP_PERSIST_CASE(SH)                                                                      \
+    case SH:                                                                                     \
+        return e->shape_ndmi ? go_persist<T, SH, sp::ShapeTab<SH>::NB0, TX, TY>(e, p, n_steps, check_only) \
+                             : go_persist<T, SH, 0, TX, TY>(e, p, n_steps, check_only);
+    switch (e->shape) {
+        SP_PERSIST_CASE(sp::SH_SQ1)
+        SP_PERSIST_CASE(sp::SH_SQ2)
+        SP_PERSIST_CASE(sp::SH_SQ3)
+        SP_PERSIST_CASE(sp::SH_TRI1)
+        SP_PERSIST_CASE(sp::SH_TRI2)
+        SP_PERSIST_CASE(sp::SH_TRI3)
+        default: return fail(e, SP_E_UNSUPPORTED, "persist2d needs a compile-time stencil");
+    }
+#undef SP_PERSIST_CASE
+}
+
+// n_steps Depondt steps of the whole lattice in one launch (check_only:
+// report whether the lattice and the tile fit the path, launch nothing).
+template <typename T>
+int launch_persist(sp_engine* e, const sp_llg_params* p, int n_steps, bool check_only = false) {
+    const PersistCfg& c = kPersistCfgs[e->persist_cfg];
+    if (e->shape < 0) return fail(e, SP_E_UNSUPPORTED, "persist2d needs a bond table matching a compile-time stencil");
+    if (e->geo.n[0] % c.TX || e->geo.n[1] % c.TY)
+        return fail(e, SP_E_UNSUPPORTED, std::string("persist2d/") + c.name + " needs lattice sides divisible by the tile");
+    if (c.TX < 2 * e->R || c.TY < 2 * e->R) return fail(e, SP_E_UNSUPPORTED, "persist2d tile narrower than the halo");
+    switch (e->persist_cfg) {
+        case 0: if constexpr (sizeof(T) == 4) return go_persist_shape<T, 64, 16>(e, p, n_steps, check_only); break;
+        case 1: if constexpr (sizeof(T) == 4) return go_persist_shape<T, 32, 32>(e, p, n_steps, check_only); break;
+        default: return go_persist_shape<T, 32, 16>(e, p, n_steps, check_only);
+    }
+    return fail(e, SP_E_UNSUPPORTED, "persist2d tile not offered in this precision");
+}
+
 // ------------------------------------------------ 3D streamed fused path
 // `blocks`: workgroups to aim for (the plane chunk length follows); tiles
 // whose LDS rings leave room for several workgroups per CU aim higher.
@@ -635,7 +739,7 @@ void launch_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const vo
 
 template <typename T>
 int launch_step(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
-    if (std::strcmp(e->path, "shape2d") == 0) {
+    if (std::strcmp(e->path, "shape2d") == 0 || std::strcmp(e->path, "persist2d") == 0) {
         launch_shape<T>(e, p, step, nin, nout);
         HIPCHK(e, hipGetLastError());
         return SP_OK;
@@ -833,7 +937,23 @@ int run_impl(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t obse
     HIPCHK(e, hipMemsetAsync(e->d_flag, 0, sizeof(int), e->stream));
     HIPCHK(e, hipMemsetAsync(e->d_abort_step, 0, sizeof(long long), e->stream));
     int64_t k = 0;
-    for (int64_t t = 0; t < n_steps; ++t) {
+    const bool persist = std::strcmp(e->path, "persist2d") == 0 && p->solver == SP_SOLVER_DEPONDT;
+    if (persist) {
+        HIPCHK(e, hipMemsetAsync(e->d_pstatus, 0, sizeof(int), e->stream));
+        // one launch per observation interval (or per kPersistMaxChunk steps)
+        for (int64_t t = 0; t < n_steps;) {
+            int64_t chunk = observe_every > 0 ? observe_every - t % observe_every : n_steps - t;
+            chunk = std::min<int64_t>(std::min<int64_t>(chunk, n_steps - t), kPersistMaxChunk);
+            if ((rc = launch_persist<T>(e, p, (int)chunk))) return rc;
+            t += chunk;
+            if (observe_every > 0 && t % observe_every == 0) {
+                rc = launch_observe<T>(e, e->d_n, e->d_obs + k * sp::OBS_NVALS, (long long)e->step, true);
+                if (rc) return rc;
+                ++k;
+            }
+        }
+    }
+    for (int64_t t = 0; !persist && t < n_steps; ++t) {
         rc = launch_step<T>(e, p, e->step, e->d_n, e->d_n2);
         if (rc) return rc;
         std::swap(e->d_n, e->d_n2);
@@ -857,6 +977,15 @@ int run_impl(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t obse
             obs_from(&h[(size_t)q * sp::OBS_NVALS], step0 + (q + 1) * observe_every, e->N, &obs[q]);
     }
     HIPCHK(e, hipStreamSynchronize(e->stream));
+    if (persist) {
+        int pst = 0;
+        HIPCHK(e, hipMemcpy(&pst, e->d_pstatus, sizeof(int), hipMemcpyDeviceToHost));
+        if (pst) {
+            // flags may have stopped anywhere: start the next launch from zero
+            e->pgen = (1u << 30) + 1;
+            return fail(e, SP_E_HIP, "persist2d: a tile timed out waiting for its neighbours; spins are invalid");
+        }
+    }
     if (flag)
         return fail(e, SP_E_NONFINITE, "non-finite torque observed after step " + std::to_string(astep) +
                                            "; later steps were skipped");
@@ -963,6 +1092,7 @@ int sp_create(sp_engine** out, int device, int precision, void* hip_stream) {
         e->own_stream = true;
     }
     if (dalloc(e, e->d_flag, sizeof(int)) || dalloc(e, e->d_abort_step, sizeof(long long)) ||
+        dalloc(e, e->d_pstatus, sizeof(int)) ||
         hipHostMalloc((void**)&e->h_pin, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         sp_destroy(e);
         return SP_E_NOMEM;
@@ -982,6 +1112,8 @@ void sp_destroy(sp_engine* e) {
     dfree(*reinterpret_cast<void**>(&e->d_obs));
     dfree(*reinterpret_cast<void**>(&e->d_flag));
     dfree(*reinterpret_cast<void**>(&e->d_abort_step));
+    dfree(*reinterpret_cast<void**>(&e->d_pflags));
+    dfree(*reinterpret_cast<void**>(&e->d_pstatus));
     if (e->h_pin) (void)hipHostFree(e->h_pin);
     surrogate_free(e->sur);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
@@ -1434,12 +1566,35 @@ int sp_set_step_path(sp_engine* e, const char* name) {
         }
         e->path = "shape3d";
         e->tile3_cfg = cfg;
+    } else if (s.rfind("persist2d", 0) == 0) {
+        int cfg = e->precision == SP_F64 ? 2 : 0;
+        if (s.size() > 9) {
+            if (s[9] != '/') return fail(e, SP_E_ARG, "unknown step path " + s);
+            cfg = -1;
+            for (int k = 0; k < kNumPersistCfgs; ++k)
+                if (s.substr(10) == kPersistCfgs[k].name && (e->precision != SP_F64 || kPersistCfgs[k].f64)) cfg = k;
+            if (cfg < 0) return fail(e, SP_E_ARG, "unknown tile configuration in " + s);
+        }
+        const int keep = e->persist_cfg;
+        e->persist_cfg = cfg;
+        sp_llg_params probe{};
+        probe.alpha = 0.1;
+        probe.dt_ps = 1e-3;
+        rc = e->precision == SP_F64 ? launch_persist<double>(e, &probe, 1, true)
+                                    : launch_persist<float>(e, &probe, 1, true);
+        if (rc) {
+            e->persist_cfg = keep;
+            return rc;
+        }
+        e->path = "persist2d";
+        e->tile_cfg = kPersistCfgs[cfg].tile_cfg;
     } else {
         return fail(e, SP_E_ARG, "unknown step path " + s);
     }
     e->path_label = e->path;
     if (std::strcmp(e->path, "shape2d") == 0) e->path_label += std::string("/") + kTileCfgs[e->tile_cfg].name;
     if (std::strcmp(e->path, "shape3d") == 0) e->path_label += std::string("/") + kTile3Cfgs[e->tile3_cfg].name;
+    if (std::strcmp(e->path, "persist2d") == 0) e->path_label += std::string("/") + kPersistCfgs[e->persist_cfg].name;
     return SP_OK;
 }
 
@@ -1462,6 +1617,17 @@ int sp_autotune(sp_engine* e, const sp_llg_params* p, int n_steps, double* ms_pe
         if (e->shape >= 0) {
             const int ncfg = e->precision == SP_F64 ? kNumTileCfgsF64 : kNumTileCfgs;
             for (int k = 0; k < ncfg; ++k) cands.push_back(std::string("shape2d/") + kTileCfgs[k].name);
+            const int keep_cfg = e->persist_cfg;
+            const std::string keep_err = e->err;
+            for (int k = 0; k < kNumPersistCfgs; ++k) {
+                if (e->precision == SP_F64 && !kPersistCfgs[k].f64) continue;
+                e->persist_cfg = k;
+                const int ok = e->precision == SP_F64 ? launch_persist<double>(e, p, 1, true)
+                                                      : launch_persist<float>(e, p, 1, true);
+                if (ok == SP_OK) cands.push_back(std::string("persist2d/") + kPersistCfgs[k].name);
+            }
+            e->persist_cfg = keep_cfg;
+            e->err = keep_err;
         }
     }
     const std::string keep_label = e->path_label;
@@ -1480,15 +1646,31 @@ int sp_autotune(sp_engine* e, const sp_llg_params* p, int n_steps, double* ms_pe
     for (size_t c = 0; out == SP_OK && c < cands.size(); ++c) {
         if ((rc = sp_set_step_path(e, cands[c].c_str()))) { out = rc; break; }
         float ms = 0.0f;
-        // warm-up (code load, caches), then the timed steps
-        rc = DISPATCH(e, launch_step, e, p, e->step, e->d_n, e->d_n2);
-        if (!rc && hipEventRecord(t0, e->stream) != hipSuccess) rc = SP_E_HIP;
-        for (int k = 0; !rc && k < n_steps; ++k) {
-            rc = DISPATCH(e, launch_step, e, p, keep_step + k, (k & 1) ? e->d_n2 : e->d_n, (k & 1) ? e->d_n : e->d_n2);
+        const bool pers = std::strcmp(e->path, "persist2d") == 0 && p->solver == SP_SOLVER_DEPONDT;
+        if (pers) {
+            // warm-up launch, then all n_steps in one launch
+            e->step = keep_step;
+            rc = hipMemsetAsync(e->d_pstatus, 0, sizeof(int), e->stream) == hipSuccess ? SP_OK : SP_E_HIP;
+            if (!rc) rc = DISPATCH(e, launch_persist, e, p, 1, false);
+            if (!rc && hipEventRecord(t0, e->stream) != hipSuccess) rc = SP_E_HIP;
+            if (!rc) rc = DISPATCH(e, launch_persist, e, p, n_steps, false);
+        } else {
+            // warm-up (code load, caches), then the timed steps
+            rc = DISPATCH(e, launch_step, e, p, e->step, e->d_n, e->d_n2);
+            if (!rc && hipEventRecord(t0, e->stream) != hipSuccess) rc = SP_E_HIP;
+            for (int k = 0; !rc && k < n_steps; ++k) {
+                rc = DISPATCH(e, launch_step, e, p, keep_step + k, (k & 1) ? e->d_n2 : e->d_n,
+                              (k & 1) ? e->d_n : e->d_n2);
+            }
         }
         if (!rc && (hipEventRecord(t1, e->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
                     hipEventElapsedTime(&ms, t0, t1) != hipSuccess))
             rc = SP_E_HIP;
+        if (!rc && pers) {
+            int pst = 0;
+            if (hipMemcpy(&pst, e->d_pstatus, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess || pst) rc = SP_E_HIP;
+            if (pst) e->pgen = (1u << 30) + 1;
+        }
         if (!rc && hipMemcpyAsync(e->d_n, backup, bytes, hipMemcpyDeviceToDevice, e->stream) != hipSuccess)
             rc = SP_E_HIP;
         if (rc) { out = rc == SP_E_HIP ? fail(e, SP_E_HIP, "autotune timing failed") : rc; break; }

@@ -289,6 +289,34 @@ __device__ __forceinline__ V3<T> predict_cell(const ShapeCoef<T>& C, const Site2
     return keep;
 }
 
+// Corrector of tile site (tx, ty) from the predictor cells in sP, the spin
+// n(t) in sN and what the predictor kept for the site (A or n x A, and the
+// thermal field): returns n(t+dt).
+template <typename T, int S, int NDMI, int TX, int TY, int SOLVER>
+__device__ __forceinline__ V3<T> correct_cell(const ShapeCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int tx,
+                                              int ty, const TileLDS<T, S, TX, TY>& L, V3<T> keepA, V3<T> keepB) {
+    using TL = TileLDS<T, S, TX, TY>;
+    constexpr int R = TL::R, WN = TL::WN, WP = TL::WP;
+    const int c = (ty + R) * WP + (tx + R);
+    const V4<T> p4 = L.sP[c];
+    const V3<T> npi{p4.x, p4.y, p4.z};
+    const V3<T> g = shape_field_aos<T, S, NDMI, WP>(C, Q, L.sP, c, npi);
+    const V3<T> B = (-Q.inv_mumuB) * g + keepB;
+    const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
+    const V4<T> n4 = L.sN[(ty + 2 * R) * WN + (tx + 2 * R)];
+    const V3<T> ni{n4.x, n4.y, n4.z};
+    if constexpr (SOLVER == SOLVER_HEUN) {
+        // n + dt (f(n) + f(n^p)) / 2, renormalised
+        return normalize3(ni + (T(0.5) * A.dt) * (keepA + cross(npi, Ap)));
+    } else if constexpr (SOLVER == SOLVER_SIB) {
+        // npi is the midpoint m; A(m) drives the second midpoint stage
+        return renorm_if_float(sib_stage(ni, Ap, A.dt));
+    } else {
+        const V3<T> w{T(-0.5) * (keepA.x + Ap.x), T(-0.5) * (keepA.y + Ap.y), T(-0.5) * (keepA.z + Ap.z)};
+        return renorm_if_float(rotate_fast(ni, w, A.dt));
+    }
+}
+
 // One Depondt step of the TX x TY tile at (x0, y0) of one lattice.  Thread
 // t owns tile sites t + j NT: it computes their predictor, keeps A and the
 // thermal field in registers, and computes their corrector; the ring of
@@ -375,26 +403,7 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
         const int ty = t / TX, tx = t - ty * TX;
         const int gx = x0 + tx, gy = y0 + ty;
         if (gx >= Q.na || gy >= Q.nb) continue;
-        const int c = (ty + R) * WP + (tx + R);
-        const V4<T> p4 = L.sP[c];
-        const V3<T> npi{p4.x, p4.y, p4.z};
-        const V3<T> g = shape_field_aos<T, S, NDMI, WP>(C, Q, L.sP, c, npi);
-        const V3<T> B = (-Q.inv_mumuB) * g + keepB[j];
-        const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
-        const V4<T> n4 = L.sN[(ty + 2 * R) * WN + (tx + 2 * R)];
-        const V3<T> ni{n4.x, n4.y, n4.z};
-        V3<T> o;
-        if constexpr (SOLVER == SOLVER_HEUN) {
-            // n + dt (f(n) + f(n^p)) / 2, renormalised
-            o = normalize3(ni + (T(0.5) * A.dt) * (keepA[j] + cross(npi, Ap)));
-        } else if constexpr (SOLVER == SOLVER_SIB) {
-            // npi is the midpoint m; A(m) drives the second midpoint stage
-            o = renorm_if_float(sib_stage(ni, Ap, A.dt));
-        } else {
-            const V3<T> w{T(-0.5) * (keepA[j].x + Ap.x), T(-0.5) * (keepA[j].y + Ap.y),
-                          T(-0.5) * (keepA[j].z + Ap.z)};
-            o = renorm_if_float(rotate_fast(ni, w, A.dt));
-        }
+        const V3<T> o = correct_cell<T, S, NDMI, TX, TY, SOLVER>(C, Q, A, tx, ty, L, keepA[j], keepB[j]);
         const int gi = gx + gy * Q.na;
         nout[gi] = o.x;
         nout[N + gi] = o.y;

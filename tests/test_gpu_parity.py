@@ -172,7 +172,8 @@ def test_autotune_restores_state_and_picks_a_path(ora):
     assert ms > 0
     assert e.step == 17
     assert np.array_equal(e.get_spins(), before)
-    assert e.step_path in ["twopass", "fused2d"] + ["shape2d/" + c for c in SHAPE_CFGS["f32"]]
+    assert e.step_path in (["twopass", "fused2d"] + ["shape2d/" + c for c in SHAPE_CFGS["f32"]] +
+                           ["persist2d/" + c for c in ("64x16", "32x32", "32x16")])
     announce(f"autotune picked {e.step_path} at {ms:.4f} ms/step")
 
 
