@@ -180,6 +180,28 @@ int sp_set_geometry(sp_engine *e, const double bravais[9], int n_basis, const do
 /* Hamiltonian; builds the neighbour-shell bond table.  Requires geometry.
  * SP_E_ARG if a requested shell does not exist within 4 cells. */
 int sp_set_hamiltonian(sp_engine *e, const sp_hamiltonian *h);
+
+/* Explicit pair interactions.  The exchange and DMI sums of the Hamiltonian
+ * (Sec. III.A, the extended Heisenberg Hamiltonian) run over unique pairs
+ * <ij>, with no limit on their number, distance or direction dependence.  Pair p couples basis atom
+ * bi[p] of every cell x with basis atom bj[p] of cell x + dcell[3p..3p+2]
+ * (cell offsets along a1, a2, a3) with energy
+ *   -J[p] n_i.n_j - D_p.(n_i x n_j),   D_p = D[3p..3p+2] in meV (D may be NULL).
+ * Periodic axes wrap the partner (also by more than one lattice length),
+ * open axes drop the pair where the partner leaves the lattice, and a pair
+ * that wraps onto its own site is dropped.  Replaces the shell-built
+ * exchange and DMI bonds of the current Hamiltonian (call after
+ * sp_set_hamiltonian, which discards the pairs again); every other term
+ * stays, spins are kept, and the step path is chosen again (the
+ * compile-time-stencil paths shape2d/shape3d/persist2d are not used with
+ * explicit pairs).  n_pairs = 0 removes exchange and DMI.  SP_E_ARG for: a
+ * pair given twice or together with its reverse (bj, bi, -dcell), a spin
+ * paired with itself (bi == bj, dcell = 0), basis indices out of range,
+ * |dcell| > 64 on an axis, non-finite J or D, or more than 256 bonds on
+ * one basis atom (both directions of every pair counted).  Arrays are read
+ * during the call only. */
+int sp_set_pairs(sp_engine *e, int64_t n_pairs, const int *bi, const int *bj, const int *dcell,
+                 const double *J, const double *D);
 /* Number of sites N (0 before sp_set_geometry). */
 int64_t sp_num_sites(const sp_engine *e);
 /* Directed bonds of basis atom beta in the bond table (bonds whose J and D

@@ -112,6 +112,10 @@ def lib():
         L.ora_num_sites.argtypes = [ctypes.c_void_p]
         L.ora_bonds.restype = ctypes.c_int
         L.ora_bonds.argtypes = [ctypes.c_void_p, ctypes.POINTER(Bond), ctypes.c_int]
+        ci_p = ctypes.POINTER(ctypes.c_int)
+        L.ora_set_pairs.restype = ctypes.c_int
+        L.ora_set_pairs.argtypes = [ctypes.c_void_p, ctypes.c_int, ci_p, ci_p, ci_p,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.ora_site_neighbours.restype = ctypes.c_int
         L.ora_site_neighbours.argtypes = [ctypes.c_void_p, ctypes.c_int64,
                                           ctypes.POINTER(ctypes.c_int64),
@@ -251,6 +255,22 @@ class System:
         buf = (Bond * MAX_BONDS)()
         k = lib().ora_bonds(self._p, buf, MAX_BONDS)
         return [(b.bi, b.bj, b.da, b.db, b.dc, b.shell, b.J, tuple(b.D)) for b in buf[:k]]
+
+    def set_pairs(self, pairs):
+        """Explicit unique pairs (bi, bj, (da, db, dc), J, (Dx, Dy, Dz)) in place
+        of the shell-built exchange and DMI bonds (``ora_set_pairs``)."""
+        pairs = list(pairs)
+        n = len(pairs)
+        bi = np.ascontiguousarray([p[0] for p in pairs] or [0], dtype=np.int32)
+        bj = np.ascontiguousarray([p[1] for p in pairs] or [0], dtype=np.int32)
+        dc = np.ascontiguousarray([list(p[2]) for p in pairs] or [[0, 0, 0]], dtype=np.int32).reshape(-1)
+        J = np.ascontiguousarray([p[3] for p in pairs] or [0.0], dtype=np.float64)
+        D = np.ascontiguousarray([list(p[4]) for p in pairs] or [[0.0, 0.0, 0.0]], dtype=np.float64).reshape(-1)
+        ip = ctypes.POINTER(ctypes.c_int)
+        rc = lib().ora_set_pairs(self._p, n, bi.ctypes.data_as(ip), bj.ctypes.data_as(ip), dc.ctypes.data_as(ip),
+                                 _dp(J), _dp(D))
+        if rc != 0:
+            raise ValueError(f"oracle rejected the pair list (code {rc})")
 
     def neighbours(self, i: int):
         js = (ctypes.c_int64 * 512)()

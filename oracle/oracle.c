@@ -10,7 +10,8 @@
  * Sources followed (the paper's text):
  *   - Hamiltonian: Sec. III.A, the extended Heisenberg Hamiltonian equation
  *     (Zeeman, uniaxial anisotropy, exchange and DMI over unique pairs,
- *     dipole-dipole), pairs of any distance.
+ *     dipole-dipole), pairs of any distance: from neighbour shells or as an
+ *     explicit list of unique pairs (ora_set_pairs).
  *   - LLG: Sec. III.C, LLG equation terms (i) precession and (ii) damping,
  *     stochastic thermal field with fluctuation-dissipation amplitude and the
  *     1/sqrt(dt) normalisation.
@@ -296,6 +297,54 @@ int ora_shell_distances(const ora_system *s, int beta, double *out, int max_out)
     int n = s->n_shell_dist[beta];
     for (int q = 0; q < n && q < max_out; ++q) out[q] = s->shell_dist[beta][q];
     return n;
+}
+
+/* Explicit pairs.  The Hamiltonian's exchange and DMI sums run over unique
+ * pairs <ij> of any number and range (Sec. III.A).  Pair p joins basis atom
+ * bi[p] of every cell x to basis atom bj[p] of cell x + dcell[p]; as a
+ * directed bond table it is kept in both directions, the reverse bond with
+ * -D (n_j x n_i = -(n_i x n_j)), so that each site sees its partners and
+ * the energy over directed bonds carries the factor 1/2.  The neighbour
+ * lists are rebuilt with the same wrap/drop rules as for shells. */
+int ora_set_pairs(ora_system *s, int n, const int *bi, const int *bj, const int *dcell, const double *J,
+                  const double *D) {
+    const int nb = s->geo.n_basis;
+    int count[ORA_MAX_BASIS] = {0};
+    if (n < 0 || 2 * n > ORA_MAX_BASIS * ORA_MAX_BONDS_PER_BASIS) return -1;
+    for (int p = 0; p < n; ++p) {
+        const int *d = dcell + 3 * p;
+        if (bi[p] < 0 || bi[p] >= nb || bj[p] < 0 || bj[p] >= nb) return -1;
+        if (bi[p] == bj[p] && d[0] == 0 && d[1] == 0 && d[2] == 0) return -1;
+        for (int q = 0; q < p; ++q) {
+            const int *e = dcell + 3 * q;
+            int same = bi[q] == bi[p] && bj[q] == bj[p] && e[0] == d[0] && e[1] == d[1] && e[2] == d[2];
+            int rev = bi[q] == bj[p] && bj[q] == bi[p] && e[0] == -d[0] && e[1] == -d[1] && e[2] == -d[2];
+            if (same || rev) return -1;
+        }
+        if (++count[bi[p]] > ORA_MAX_BONDS_PER_BASIS || ++count[bj[p]] > ORA_MAX_BONDS_PER_BASIS) return -1;
+    }
+    s->n_bonds = 0;
+    for (int p = 0; p < n; ++p) {
+        for (int dir = 0; dir < 2; ++dir) {
+            const double sgn = dir == 0 ? 1.0 : -1.0;
+            ora_bond *bd = &s->bonds[s->n_bonds++];
+            bd->bi = dir == 0 ? bi[p] : bj[p];
+            bd->bj = dir == 0 ? bj[p] : bi[p];
+            bd->da = (int)sgn * dcell[3 * p];
+            bd->db = (int)sgn * dcell[3 * p + 1];
+            bd->dc = (int)sgn * dcell[3 * p + 2];
+            bd->shell = -1;
+            bd->J = J[p];
+            for (int k = 0; k < 3; ++k) bd->D[k] = D ? sgn * D[3 * p + k] : 0.0;
+        }
+    }
+    free(s->nb_start);
+    free(s->nb_j);
+    free(s->nb_bond);
+    s->nb_start = NULL;
+    s->nb_j = NULL;
+    s->nb_bond = NULL;
+    return build_neighbours(s) == 0 ? 0 : -2;
 }
 
 static int basis_of(const ora_system *s, int64_t i) {

@@ -81,6 +81,13 @@ int ora_bonds(const ora_system *s, ora_bond *out, int max_bonds);
 int ora_site_neighbours(const ora_system *s, int64_t i, int64_t *j_out, int *bond_out, int max_out);
 /* Shell distances of basis atom beta (units of the lattice constant). */
 int ora_shell_distances(const ora_system *s, int beta, double *out, int max_out);
+/* Replace the shell-built exchange/DMI bonds by n explicit unique pairs:
+ * pair p joins basis atom bi[p] of every cell x with basis atom bj[p] of
+ * cell x + dcell[3p..3p+2], energy -J[p] n_i.n_j - D_p.(n_i x n_j) (D may
+ * be NULL).  Returns 0; -1 for an index out of range, a spin paired with
+ * itself, a pair given twice or with its reverse, or too many bonds. */
+int ora_set_pairs(ora_system *s, int n, const int *bi, const int *bj, const int *dcell, const double *J,
+                  const double *D);
 
 /* dH/dn per site (embedding space).  terms, if non-NULL, receives the five
  * contributions Zeeman, anisotropy, exchange, DMI, dipole as 5 blocks of 3N. */

@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <array>
+#include <set>
 #include <random>
 #include <string>
 #include <type_traits>
@@ -94,6 +96,7 @@ struct sp_engine {
     int shape_ndmi = 0;               // 0: no DMI, 1: DMI on the first shell only
     int tile_cfg = 0;                 // index into the shape-path tile configurations
     int shape3 = -1;                  // sp::Shape3D matched by a 3D one-atom bond table, or -1
+    bool explicit_pairs = false;      // bond table from sp_set_pairs (no compile-time stencil paths)
     int shape3_ndmi = 0;              // DMI on the first shell
     int tile3_cfg = 0;                // index into the 3D tile configurations
     int persist_cfg = 0;              // index into the persistent-path tile configurations
@@ -1068,6 +1071,11 @@ int mc_run_impl(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t o
 
 }  // namespace
 
+namespace {
+int install_ham(sp_engine* e, const HostHam& H, const std::vector<HostBond>& bonds, const std::vector<int>& bstart,
+                const std::vector<HostBond>& all_bonds, bool explicit_pairs);
+}  // namespace
+
 #define DISPATCH(e, fn, ...) ((e)->precision == SP_F64 ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__))
 
 extern "C" {
@@ -1241,7 +1249,18 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
     std::vector<int> bstart;
     int rc = build_bonds(e, e->geo, H, bonds, bstart, all_bonds);
     if (rc) return rc;
+    return install_ham(e, H, bonds, bstart, all_bonds, false);
+}
 
+}  // extern "C"
+
+namespace {
+
+// Installs a Hamiltonian and its bond table (shell-built or explicit pairs):
+// device buffers, bond upload, step-path selection; spins are kept.
+int install_ham(sp_engine* e, const HostHam& H, const std::vector<HostBond>& bonds, const std::vector<int>& bstart,
+                const std::vector<HostBond>& all_bonds, bool explicit_pairs) {
+    int rc;
     (void)hipSetDevice(e->device);
     // keep spins across a Hamiltonian change only if already uploaded
     const bool had_spins = e->has_spins;
@@ -1254,7 +1273,8 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
     e->ham = H;
     e->bonds = bonds;
     e->all_bonds = all_bonds;
-    e->n_shells = std::max(H.n_exch, H.n_dmi);
+    e->explicit_pairs = explicit_pairs;
+    e->n_shells = explicit_pairs ? 0 : std::max(H.n_exch, H.n_dmi);
     e->bstart = bstart;
     e->R = 0;
     e->planar = true;
@@ -1310,7 +1330,7 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
     // default tile: 64x16 sites, one site per thread (fastest measured on the
     // 512^2 triangular workload); FP64 has a single configuration
     e->tile_cfg = e->precision == SP_F64 ? 0 : 4;
-    if (fused) {
+    if (fused && !explicit_pairs) {
         bool ok = true;
         for (const HostBond& b : all_bonds)
             if (b.D[2] != 0.0 || (b.shell > 0 && (b.D[0] != 0.0 || b.D[1] != 0.0))) ok = false;
@@ -1329,7 +1349,7 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
     // default 3D tile: 32x16 columns, two workgroups per CU (fastest measured
     // on the 128^3 workload); FP64 takes 16x16 (LDS)
     e->tile3_cfg = e->precision == SP_F64 ? 1 : 4;
-    if (g.nb == 1 && g.n[2] > 1 && !H.ddi && H.n_gauss == 0) {
+    if (g.nb == 1 && g.n[2] > 1 && !H.ddi && H.n_gauss == 0 && !explicit_pairs) {
         bool ok = true;
         for (const HostBond& b : all_bonds)
             if (b.shell > 0 && (b.D[0] != 0.0 || b.D[1] != 0.0 || b.D[2] != 0.0)) ok = false;
@@ -1350,6 +1370,71 @@ int sp_set_hamiltonian(sp_engine* e, const sp_hamiltonian* h) {
         e->has_spins = true;
     }
     return SP_OK;
+}
+
+constexpr int kMaxPairOffset = 64;       // |dcell| per axis in sp_set_pairs
+constexpr int kMaxBondsPerBasis = 256;   // directed bonds per basis atom
+
+}  // namespace
+
+extern "C" {
+
+int sp_set_pairs(sp_engine* e, int64_t n_pairs, const int* bi, const int* bj, const int* dcell, const double* J,
+                 const double* D) {
+    int rc = check_ready(e, false);
+    if (rc) return rc;
+    if (n_pairs < 0) return fail(e, SP_E_ARG, "n_pairs must be >= 0");
+    if (n_pairs > 0 && (!bi || !bj || !dcell || !J)) return fail(e, SP_E_ARG, "pair arrays are NULL");
+    const int nb = e->geo.nb;
+    std::vector<std::vector<HostBond>> per(nb);
+    std::set<std::array<int, 5>> seen;
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const std::string at = "pair " + std::to_string(p) + ": ";
+        if (bi[p] < 0 || bi[p] >= nb || bj[p] < 0 || bj[p] >= nb) return fail(e, SP_E_ARG, at + "basis index out of range");
+        const int* d = dcell + 3 * p;
+        for (int k = 0; k < 3; ++k)
+            if (d[k] < -kMaxPairOffset || d[k] > kMaxPairOffset)
+                return fail(e, SP_E_ARG, at + "cell offset beyond +-" + std::to_string(kMaxPairOffset));
+        if (bi[p] == bj[p] && d[0] == 0 && d[1] == 0 && d[2] == 0) return fail(e, SP_E_ARG, at + "a spin paired with itself");
+        HostBond f{};
+        f.bi = bi[p];
+        f.bj = bj[p];
+        f.shell = -1;
+        f.J = J[p];
+        for (int k = 0; k < 3; ++k) {
+            f.d[k] = d[k];
+            f.D[k] = D ? D[3 * p + k] : 0.0;
+        }
+        if (!std::isfinite(f.J) || !std::isfinite(f.D[0]) || !std::isfinite(f.D[1]) || !std::isfinite(f.D[2]))
+            return fail(e, SP_E_ARG, at + "non-finite J or D");
+        const std::array<int, 5> key{f.bi, f.bj, d[0], d[1], d[2]}, rkey{f.bj, f.bi, -d[0], -d[1], -d[2]};
+        if (seen.count(key) || seen.count(rkey)) return fail(e, SP_E_ARG, at + "repeats an earlier pair or its reverse");
+        seen.insert(key);
+        // the same pair seen from j: n_j x n_i = -(n_i x n_j), so D changes sign
+        HostBond r = f;
+        r.bi = f.bj;
+        r.bj = f.bi;
+        for (int k = 0; k < 3; ++k) {
+            r.d[k] = -d[k];
+            r.D[k] = -f.D[k];
+        }
+        per[f.bi].push_back(f);
+        per[r.bi].push_back(r);
+        if ((int)per[f.bi].size() > kMaxBondsPerBasis || (int)per[r.bi].size() > kMaxBondsPerBasis)
+            return fail(e, SP_E_ARG, "more than " + std::to_string(kMaxBondsPerBasis) + " bonds on one basis atom");
+    }
+    std::vector<HostBond> bonds;
+    std::vector<int> bstart(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) {
+        bstart[b] = (int)bonds.size();
+        for (const HostBond& q : per[b])
+            if (q.J != 0.0 || q.D[0] != 0.0 || q.D[1] != 0.0 || q.D[2] != 0.0) bonds.push_back(q);
+    }
+    bstart[nb] = (int)bonds.size();
+    HostHam H = e->ham;
+    H.n_exch = 0;   // the shells no longer define the pair terms
+    H.n_dmi = 0;
+    return install_ham(e, H, bonds, bstart, bonds, true);
 }
 
 int64_t sp_num_sites(const sp_engine* e) { return e && e->has_geo ? e->N : 0; }

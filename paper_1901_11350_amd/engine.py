@@ -26,7 +26,7 @@ SP_DDI_OFF, SP_DDI_DIRECT = 0, 1
 # every symbol the header declares
 EXPORTS = [
     "sp_create", "sp_destroy", "sp_last_error", "sp_version", "sp_set_geometry",
-    "sp_set_hamiltonian", "sp_num_sites", "sp_get_bonds", "sp_set_spins", "sp_get_spins",
+    "sp_set_hamiltonian", "sp_set_pairs", "sp_num_sites", "sp_get_bonds", "sp_set_spins", "sp_get_spins",
     "sp_set_spins_dev", "sp_get_spins_dev", "sp_set_step", "sp_get_step", "sp_gradient",
     "sp_gradient_dev", "sp_energy", "sp_observe", "sp_llg_step", "sp_run", "sp_synchronize",
     "sp_dipole_gradient", "sp_dipole_gradient_dev", "sp_thermal_normals", "sp_step_path",
@@ -105,6 +105,7 @@ def lib():
         "sp_version": (ctypes.c_char_p, []),
         "sp_set_geometry": (ci, [vp, dp, ci, dp, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.c_double]),
         "sp_set_hamiltonian": (ci, [vp, ctypes.POINTER(sp_hamiltonian)]),
+        "sp_set_pairs": (ci, [vp, i64, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci), dp, dp]),
         "sp_num_sites": (i64, [vp]),
         "sp_get_bonds": (ci, [vp, ci, dp, ci]),
         "sp_set_spins": (ci, [vp, dp, i64]),
@@ -182,6 +183,23 @@ def obs_dict(o: sp_observation) -> dict:
             "max_torque": o.max_torque, "M": list(o.M), "max_norm_dev": o.max_norm_dev}
 
 
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _pair_arrays(pairs):
+    pairs = list(pairs)
+    bi = np.ascontiguousarray([p[0] for p in pairs], dtype=np.int32)
+    bj = np.ascontiguousarray([p[1] for p in pairs], dtype=np.int32)
+    dc = np.ascontiguousarray([list(p[2]) for p in pairs], dtype=np.int32).reshape(-1)
+    J = np.ascontiguousarray([p[3] for p in pairs], dtype=np.float64)
+    D = np.ascontiguousarray([list(p[4]) for p in pairs], dtype=np.float64).reshape(-1)
+    if not pairs:   # valid pointers for an empty list
+        bi, bj, dc = (np.zeros(3, np.int32) for _ in range(3))
+        J, D = np.zeros(1), np.zeros(3)
+    return len(pairs), bi, bj, dc, J, D
+
+
 class Engine:
     """One engine instance (``sp_engine``) on one HIP device."""
 
@@ -248,6 +266,12 @@ class Engine:
             arrs["gc"] = _f64([x for _, _, c in gauss for x in c])
             h.gauss_a, h.gauss_sigma, h.gauss_c = _dp(arrs["ga"]), _dp(arrs["gs"]), _dp(arrs["gc"])
         self._check(lib().sp_set_hamiltonian(self._h, ctypes.byref(h)))
+
+    def set_pairs(self, pairs):
+        """Explicit pair interactions: a sequence of (bi, bj, (da, db, dc), J,
+        (Dx, Dy, Dz)) replacing the shell-built exchange and DMI bonds."""
+        n, bi, bj, dc, J, D = _pair_arrays(pairs)
+        self._check(lib().sp_set_pairs(self._h, n, _ip(bi), _ip(bj), _ip(dc), _dp(J), _dp(D)))
 
     def bonds(self, beta: int = 0):
         k = lib().sp_get_bonds(self._h, beta, None, 0)
