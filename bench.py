@@ -434,6 +434,8 @@ def main():
     ap.add_argument("--workload", default="triangular512_sllg")
     ap.add_argument("--observe-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--step-path", default="",
+                    help="force a step path (e.g. persist2d/32x16) instead of the engine's default")
     ap.add_argument("--autotune", action="store_true",
                     help="time every step path / tile shape first and keep the fastest (default: the engine's "
                          "default path, chosen from such sweeps)")
@@ -467,6 +469,8 @@ def main():
     tuned_ms = None
     if args.autotune and not args.no_autotune:
         tuned_ms = e.autotune(d.alpha, d.dt, d.T, d.seed, n_steps=50)
+    if args.step_path:
+        e.step_path = args.step_path
     print(f"[bench] workload={w.name} N={e.N} path={e.step_path} precision={w.precision} "
           f"autotune_ms={tuned_ms}", file=sys.stderr, flush=True)
 
@@ -497,6 +501,8 @@ def main():
     e.run(d.alpha, d.dt, K2, T=d.T, seed=d.seed)
     k_ev1.record(stream)
     torch.cuda.synchronize()
+    # per launch; the persistent path runs all K2 steps in one launch, so
+    # its figures are per step of that launch
     launches_per_step = 2 if e.step_path == "twopass" else 1
     t_launch = k_ev0.elapsed_time(k_ev1) * 1e-3 / (K2 * launches_per_step)
     bytes_per_launch = BYTES_PER_UPDATE[w.precision] * e.N / launches_per_step
@@ -504,7 +510,8 @@ def main():
     fpu = flops_per_update(w)
     tflops = fpu * e.N / launches_per_step / t_launch / 1e12
     kernel_name = {"fused2d": "k_depondt_fused2d", "twopass": "k_predict+k_correct"}.get(
-        e.step_path, "k_fused2d_shape")
+        e.step_path.split("/")[0], {"shape3d": "k_fused3d_shape", "persist2d": "k_persist2d"}.get(
+            e.step_path.split("/")[0], "k_fused2d_shape"))
     traffic = measured_traffic(kernel_name, w.name, e.step_path)
 
     last = obs[-1] if obs else e.observe()
