@@ -37,48 +37,56 @@ __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
 }
 
 // Lines of length L = 2^logL: line l of batch q starts at q * batch_stride +
-// l * line_stride, element e sits e * elem_stride further.  blockDim =
-// C * L / 2; thread t handles butterfly j of line lo, with the line index
-// fastest (LINE_FAST, for lines adjacent in memory) or the butterfly index
-// fastest (for contiguous lines).  inverse: conjugated twiddles, no scaling.
+// l * line_stride, element e sits e * elem_stride further.  A workgroup
+// transforms C lines; its threads step through the C * L / 2 butterflies of
+// a stage.  LINE_FAST (lines adjacent in memory, e.g. the columns of a
+// row-major grid): the line index runs fastest over the threads, so a wave
+// reads C adjacent elements of each of 64 / C rows, and the LDS copy is
+// element-major (index e C + l), so the lanes of a wave touch consecutive
+// LDS words in every stage.  Otherwise (contiguous lines) the element index
+// runs fastest and the LDS copy is line-major.  inverse: conjugated
+// twiddles, no scaling.
 template <typename T, bool LINE_FAST>
 __global__ void __launch_bounds__(1024) k_fft_lines(Cx<T>* __restrict__ data, const Cx<T>* __restrict__ tw, int logL,
                                                     int C, int n_lines, long long line_stride, long long elem_stride,
                                                     long long batch_stride, int inverse) {
     extern __shared__ unsigned char fft_smem[];
-    Cx<T>* buf = reinterpret_cast<Cx<T>*>(fft_smem);
     const int L = 1 << logL, H = L >> 1;
-    const int t = threadIdx.x;
-    const int lo = LINE_FAST ? t % C : t / H;
-    const int j = LINE_FAST ? t / C : t % H;
-    const int line = blockIdx.x * C + lo;
-    const bool live = line < n_lines;
-    Cx<T>* base = data + (long long)blockIdx.y * batch_stride + (long long)line * line_stride;
-    Cx<T>* x = buf + lo * L;
-    Cx<T>* y = buf + (C + lo) * L;
-    if (live) {
-        x[j] = base[(long long)j * elem_stride];
-        x[j + H] = base[(long long)(j + H) * elem_stride];
+    Cx<T>* x = reinterpret_cast<Cx<T>*>(fft_smem);
+    Cx<T>* y = x + C * L;
+    const int nthr = blockDim.x;
+    auto at = [&](int lo, int e) { return LINE_FAST ? e * C + lo : lo * L + e; };
+    Cx<T>* base = data + (long long)blockIdx.y * batch_stride;
+    const int line0 = blockIdx.x * C;
+    for (int u = threadIdx.x; u < C * L; u += nthr) {
+        const int lo = LINE_FAST ? u % C : u / L;
+        const int e = LINE_FAST ? u / C : u % L;
+        if (line0 + lo < n_lines) x[at(lo, e)] = base[(long long)(line0 + lo) * line_stride + (long long)e * elem_stride];
     }
     __syncthreads();
     for (int s = 0; s < logL; ++s) {
         const int Ns = 1 << s;
-        const int k = j & (Ns - 1);
-        Cx<T> w = tw[k << (logL - 1 - s)];
-        if (inverse) w.im = -w.im;
-        const Cx<T> a = x[j];
-        const Cx<T> b = cmul(x[j + H], w);
-        const int o = ((j - k) << 1) + k;
-        y[o] = Cx<T>{a.re + b.re, a.im + b.im};
-        y[o + Ns] = Cx<T>{a.re - b.re, a.im - b.im};
+        for (int u = threadIdx.x; u < C * H; u += nthr) {
+            const int lo = LINE_FAST ? u % C : u / H;
+            const int j = LINE_FAST ? u / C : u % H;
+            const int k = j & (Ns - 1);
+            Cx<T> w = tw[k << (logL - 1 - s)];
+            if (inverse) w.im = -w.im;
+            const Cx<T> a = x[at(lo, j)];
+            const Cx<T> b = cmul(x[at(lo, j + H)], w);
+            const int o = ((j - k) << 1) + k;
+            y[at(lo, o)] = Cx<T>{a.re + b.re, a.im + b.im};
+            y[at(lo, o + Ns)] = Cx<T>{a.re - b.re, a.im - b.im};
+        }
         __syncthreads();
         Cx<T>* sw = x;
         x = y;
         y = sw;
     }
-    if (live) {
-        base[(long long)j * elem_stride] = x[j];
-        base[(long long)(j + H) * elem_stride] = x[j + H];
+    for (int u = threadIdx.x; u < C * L; u += nthr) {
+        const int lo = LINE_FAST ? u % C : u / L;
+        const int e = LINE_FAST ? u / C : u % L;
+        if (line0 + lo < n_lines) base[(long long)(line0 + lo) * line_stride + (long long)e * elem_stride] = x[at(lo, e)];
     }
 }
 
