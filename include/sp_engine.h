@@ -23,7 +23,10 @@
  * Errors: every int-returning call returns SP_OK (0) or a negative
  *        sp_status; no C++ exception crosses the ABI.  sp_last_error gives
  *        a message for the last failing call.  A failing set_* call leaves
- *        the previous state unchanged.
+ *        the previous state unchanged, except when device memory or a HIP
+ *        call fails while a new Hamiltonian is installed (SP_E_NOMEM,
+ *        SP_E_HIP from sp_set_hamiltonian / sp_set_pairs): the Hamiltonian
+ *        and the spins are then dropped and must be set again.
  * Call order: sp_set_geometry -> sp_set_hamiltonian -> sp_set_spins ->
  *        compute calls; out of order gives SP_E_ORDER.
  * Threads: one engine must not be used from two threads at once; separate
@@ -321,6 +324,20 @@ uint64_t sp_batch_get_step(const sp_batch *b);
  * keeps the fastest, restores all replicas.  *ms_per_step may be NULL. */
 int sp_batch_autotune(sp_batch *b, int n_steps, double *ms_per_step);
 
+typedef struct sp_gneb sp_gneb;
+/* Attach a GNEB chain (sp_gneb_create, below; FP32 engine, same device) to
+ * the batch: every sp_batch_run(b, n) then also performs n velocity-
+ * projection iterations of the chain (Sec. III.D), on a branch of the same
+ * chunk graph that runs beside the replicas, with the same kernels and
+ * results as sp_gneb_iterate(g, n).  While attached, sp_gneb_iterate on the
+ * chain returns SP_E_ORDER and the chain's readers (sp_gneb_get_chain,
+ * sp_gneb_get_forces, sp_gneb_set_image_type) wait for the batch's work.
+ * Destroying either object detaches the chain (it stays usable on its own).
+ * SP_E_ORDER if the batch already has a chain or the chain another batch;
+ * SP_E_ARG for an FP64 chain or another device.  sp_batch_autotune times
+ * the replicas only and leaves an attached chain as it is. */
+int sp_batch_add_gneb(sp_batch *b, sp_gneb *g);
+
 /* ------------------------------------------------------------------------
  * Geodesic nudged elastic band (Sec. III.D; Appendix F for the tangents,
  * geodesic distances and per-spin projections; Appendix D for the
@@ -335,7 +352,6 @@ int sp_batch_autotune(sp_batch *b, int n_steps, double *ms_per_step);
  * renormalised after each move.  Energies and all dot products are reduced
  * in double precision.
  * ------------------------------------------------------------------------ */
-typedef struct sp_gneb sp_gneb;
 
 /* Chain of n_images (>= 3) images on engine e's lattice and Hamiltonian (no
  * dipole term), in e's precision.  chain: n_images*3N doubles, image-major,

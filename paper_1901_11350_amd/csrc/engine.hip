@@ -333,6 +333,7 @@ template <typename T>
 int fft_field(sp_engine* e, const void* n, void* gdd);
 template <typename T>
 int fft_setup(sp_engine* e);
+int fft_check(sp_engine* e);
 
 // Dipole gradient for the step/gradient/observe paths: the direct sum, the
 // FFT convolution, or the learned surrogate with its residual check and
@@ -1261,6 +1262,8 @@ namespace {
 int install_ham(sp_engine* e, const HostHam& H, const std::vector<HostBond>& bonds, const std::vector<int>& bstart,
                 const std::vector<HostBond>& all_bonds, bool explicit_pairs) {
     int rc;
+    // checks that can fail without a device error come before any state is replaced
+    if (H.ddi == SP_DDI_FFT && (rc = fft_check(e))) return rc;
     (void)hipSetDevice(e->device);
     // keep spins across a Hamiltonian change only if already uploaded
     const bool had_spins = e->has_spins;
@@ -1792,6 +1795,24 @@ struct BatchRep {
 
 }  // namespace
 
+struct sp_gneb {
+    sp_engine* e = nullptr;
+    int device = 0;
+    int M = 0, N = 0, nblk = 0;
+    double k = 1.0, dt = 0.1, m = 1.0;
+    void *x = nullptr, *v = nullptr, *F = nullptr, *Fp = nullptr, *g = nullptr, *tau = nullptr;
+    double* part = nullptr;  // force partials (v.F, F.F)
+    double* epart = nullptr; // energy partials [M][nblk]
+    double* tpart = nullptr; // tangent partials [M][nblk][3]
+    double* E = nullptr;    // [M]
+    double* s3 = nullptr;   // [3M]: |tau|^2, g.tau, l^2
+    double* vf = nullptr;   // [2]
+    int* types = nullptr;   // [M] image types (0 normal, 1 climbing, 2 falling)
+    int64_t iterations = 0;
+    sp_batch* batch = nullptr;   // the batch that advances the chain, if attached
+    std::string err;
+};
+
 struct sp_batch {
     int device = 0;
     hipStream_t stream = nullptr, side = nullptr;
@@ -1821,9 +1842,15 @@ struct sp_batch {
     hipGraphExec_t gexec = nullptr;
     int g_parity = -1, g_cfg = -1, g_chunk = -1;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    sp_gneb* gneb = nullptr;                   // attached GNEB chain (FP32), advanced by every run
+    hipStream_t gside = nullptr;               // its branch of the chunk graph
+    hipEvent_t ev_gfork = nullptr, ev_gjoin = nullptr;
 };
 
 namespace {
+
+template <typename T>
+int gneb_enqueue(sp_gneb* G, int n_iter, hipStream_t st);
 
 int bfail(sp_batch* b, int code, const std::string& msg) {
     if (b) b->err = msg;
@@ -1956,12 +1983,22 @@ void batch_chunk_shape(sp_batch* b, int n_steps, int parity) {
     (void)hipStreamWaitEvent(b->side, b->ev_fork, 0);
     if (b->shape_ndmi) batch_launch_resident<S, sp::ShapeTab<S>::NB0>(b, b->side, n_steps);
     else batch_launch_resident<S, 0>(b, b->side, n_steps);
+    // an attached GNEB chain: n_steps iterations on a third branch
+    if (b->gneb) {
+        (void)hipEventRecord(b->ev_gfork, b->stream);
+        (void)hipStreamWaitEvent(b->gside, b->ev_gfork, 0);
+        (void)gneb_enqueue<float>(b->gneb, n_steps, b->gside);
+    }
     for (int k = 0; k < n_steps; ++k) {
         if (b->shape_ndmi) batch_launch_tiled<S, sp::ShapeTab<S>::NB0>(b, b->stream, k, parity);
         else batch_launch_tiled<S, 0>(b, b->stream, k, parity);
     }
     (void)hipEventRecord(b->ev_join, b->side);
     (void)hipStreamWaitEvent(b->stream, b->ev_join, 0);
+    if (b->gneb) {
+        (void)hipEventRecord(b->ev_gjoin, b->gside);
+        (void)hipStreamWaitEvent(b->stream, b->ev_gjoin, 0);
+    }
     hipLaunchKernelGGL(sp::k_advance_step, dim3(1), dim3(64), 0, b->stream, b->d_step, n_steps);
 }
 
@@ -2014,6 +2051,7 @@ int batch_advance(sp_batch* b, int64_t n_steps, bool use_graph) {
         left -= k;
     }
     b->step += (uint64_t)n_steps;
+    if (b->gneb) b->gneb->iterations += n_steps;
     return SP_OK;
 }
 
@@ -2060,6 +2098,10 @@ void sp_batch_destroy(sp_batch* b) {
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->gneb) b->gneb->batch = nullptr;   // the chain stays usable on its own
+    if (b->ev_gfork) (void)hipEventDestroy(b->ev_gfork);
+    if (b->ev_gjoin) (void)hipEventDestroy(b->ev_gjoin);
+    if (b->gside) (void)hipStreamDestroy(b->gside);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -2109,6 +2151,29 @@ int sp_batch_add(sp_batch* b, sp_engine* e, const sp_llg_params* p) {
     std::copy(R.init.begin(), R.init.begin() + 3 * (size_t)e->N, R.init.begin() + 3 * (size_t)e->N);
     b->reps.push_back(std::move(R));
     return (int)b->reps.size() - 1;
+}
+
+int sp_batch_add_gneb(sp_batch* b, sp_gneb* G) {
+    if (!b || !G) return SP_E_ARG;
+    if (b->gneb) return bfail(b, SP_E_ORDER, "the batch already advances a GNEB chain");
+    if (G->batch) return bfail(b, SP_E_ORDER, "the chain is attached to another batch");
+    if (G->e->precision != SP_F32) return bfail(b, SP_E_ARG, "batches run FP32: the chain's engine must be FP32");
+    if (G->device != b->device) return bfail(b, SP_E_ARG, "the chain lives on another device");
+    (void)hipSetDevice(b->device);
+    if (!b->gside && (hipStreamCreateWithFlags(&b->gside, hipStreamNonBlocking) != hipSuccess ||
+                      hipEventCreateWithFlags(&b->ev_gfork, hipEventDisableTiming) != hipSuccess ||
+                      hipEventCreateWithFlags(&b->ev_gjoin, hipEventDisableTiming) != hipSuccess))
+        return bfail(b, SP_E_HIP, "stream creation failed");
+    // the chain's own pending work ends before the batch takes it over
+    BHIPCHK(b, hipStreamSynchronize(G->e->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    if (b->gexec) {   // the captured chunk no longer matches
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    b->gneb = G;
+    G->batch = b;
+    return SP_OK;
 }
 
 int sp_batch_run(sp_batch* b, int64_t n_steps) {
@@ -2168,6 +2233,8 @@ int sp_batch_autotune(sp_batch* b, int n_steps, double* ms_per_step) {
         return bfail(b, SP_E_NOMEM, "autotune backup allocation failed");
     const uint64_t keep_step = b->step;
     const int keep_parity = b->parity;
+    sp_gneb* const keep_gneb = b->gneb;   // an attached chain is neither timed nor advanced
+    b->gneb = nullptr;
     double best = 1e300;
     int best_cfg = b->cfg;
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -2204,6 +2271,7 @@ int sp_batch_autotune(sp_batch* b, int n_steps, double* ms_per_step) {
     (void)hipFree(backup);
     b->step = keep_step;
     b->parity = keep_parity;
+    b->gneb = keep_gneb;
     b->cfg = best_cfg;
     const int rc2 = batch_build_work(b);
     if (out == SP_OK && ms_per_step) *ms_per_step = best;
@@ -2213,22 +2281,6 @@ int sp_batch_autotune(sp_batch* b, int n_steps, double* ms_per_step) {
 }  // extern "C"
 
 // ======================================================================= GNEB
-struct sp_gneb {
-    sp_engine* e = nullptr;
-    int device = 0;
-    int M = 0, N = 0, nblk = 0;
-    double k = 1.0, dt = 0.1, m = 1.0;
-    void *x = nullptr, *v = nullptr, *F = nullptr, *Fp = nullptr, *g = nullptr, *tau = nullptr;
-    double* part = nullptr;  // force partials (v.F, F.F)
-    double* epart = nullptr; // energy partials [M][nblk]
-    double* tpart = nullptr; // tangent partials [M][nblk][3]
-    double* E = nullptr;    // [M]
-    double* s3 = nullptr;   // [3M]: |tau|^2, g.tau, l^2
-    double* vf = nullptr;   // [2]
-    int* types = nullptr;   // [M] image types (0 normal, 1 climbing, 2 falling)
-    int64_t iterations = 0;
-    std::string err;
-};
 
 namespace {
 
@@ -2238,7 +2290,7 @@ int gfail(sp_gneb* G, int code, const std::string& msg) {
 }
 
 template <typename T>
-int gneb_forces(sp_gneb* G, bool update_v) {
+int gneb_forces(sp_gneb* G, bool update_v, hipStream_t st) {
     sp_engine* e = G->e;
     const sp::GnebDims d{G->M, G->N, G->nblk};
     const sp::Lattice L = make_lattice(e);
@@ -2247,46 +2299,56 @@ int gneb_forces(sp_gneb* G, bool update_v) {
     T* x = static_cast<T*>(G->x);
     T* g = static_cast<T*>(G->g);
     T* tau = static_cast<T*>(G->tau);
-    hipLaunchKernelGGL((sp::k_gneb_grad<T>), dim3(G->nblk, G->M), dim3(256), 0, e->stream, d, L, C, P, x, g, G->epart);
-    hipLaunchKernelGGL((sp::k_gneb_tangent<T>), dim3(G->nblk, G->M), dim3(256), 0, e->stream, d, x, g, G->epart, G->E,
-                       tau, G->tpart);
-    hipLaunchKernelGGL((sp::k_gneb_force<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, e->stream, d, (T)G->k,
+    hipLaunchKernelGGL((sp::k_gneb_grad<T>), dim3(G->nblk, G->M), dim3(256), 0, st, d, L, C, P, x, g, G->epart);
+    hipLaunchKernelGGL((sp::k_gneb_tangent<T>), dim3(G->nblk, G->M), dim3(256), 0, st, d, x, g, G->epart, G->E, tau,
+                       G->tpart);
+    hipLaunchKernelGGL((sp::k_gneb_force<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, st, d, (T)G->k,
                        (T)(G->dt / (2.0 * G->m)), update_v ? 1 : 0, x, g, tau, G->tpart, G->s3, G->types,
                        static_cast<T*>(G->F), static_cast<const T*>(G->Fp), static_cast<T*>(G->v), G->part);
     if (update_v)
-        hipLaunchKernelGGL((sp::k_gneb_sum<2>), dim3(1), dim3(256), 0, e->stream, G->part, (G->M - 2) * G->nblk,
-                           G->vf);
+        hipLaunchKernelGGL((sp::k_gneb_sum<2>), dim3(1), dim3(256), 0, st, G->part, (G->M - 2) * G->nblk, G->vf);
     hipError_t s = hipGetLastError();
     if (s != hipSuccess) return gfail(G, SP_E_HIP, hipGetErrorString(s));
     return SP_OK;
 }
 
 template <typename T>
-int gneb_project(sp_gneb* G) {
+int gneb_project(sp_gneb* G, hipStream_t st) {
     const sp::GnebDims d{G->M, G->N, G->nblk};
-    hipLaunchKernelGGL((sp::k_gneb_project<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, G->e->stream, d, G->vf,
+    hipLaunchKernelGGL((sp::k_gneb_project<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, st, d, G->vf,
                        static_cast<T*>(G->v), static_cast<const T*>(G->F), static_cast<T*>(G->Fp));
     hipError_t s = hipGetLastError();
     if (s != hipSuccess) return gfail(G, SP_E_HIP, hipGetErrorString(s));
     return SP_OK;
 }
 
+// n_iter velocity-projection iterations enqueued on st (also under graph
+// capture); the iteration counter is the caller's business.
 template <typename T>
-int gneb_iterate(sp_gneb* G, int n_iter) {
+int gneb_enqueue(sp_gneb* G, int n_iter, hipStream_t st) {
     const sp::GnebDims d{G->M, G->N, G->nblk};
     // the projection of each iteration is applied by the next move; the
     // state between calls is always projected (v, F_prev final)
     for (int it = 0; it < n_iter; ++it) {
-        hipLaunchKernelGGL((sp::k_gneb_move<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, G->e->stream, d, (T)G->dt,
+        hipLaunchKernelGGL((sp::k_gneb_move<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, st, d, (T)G->dt,
                            (T)(G->dt * G->dt / (2.0 * G->m)), it > 0 ? 1 : 0, G->vf, static_cast<const T*>(G->F),
                            static_cast<T*>(G->x), static_cast<T*>(G->v), static_cast<T*>(G->Fp));
-        int rc = gneb_forces<T>(G, true);
+        int rc = gneb_forces<T>(G, true, st);
         if (rc) return rc;
-        ++G->iterations;
     }
-    if (n_iter > 0) return gneb_project<T>(G);
+    if (n_iter > 0) return gneb_project<T>(G, st);
     return SP_OK;
 }
+
+template <typename T>
+int gneb_iterate(sp_gneb* G, int n_iter) {
+    int rc = gneb_enqueue<T>(G, n_iter, G->e->stream);
+    if (rc == SP_OK) G->iterations += n_iter;
+    return rc;
+}
+
+// The stream that orders the chain's work: the batch's when attached.
+hipStream_t gneb_stream(const sp_gneb* G) { return G->batch ? G->batch->stream : G->e->stream; }
 
 template <typename T>
 int gneb_upload(sp_gneb* G, const double* chain) {
@@ -2310,7 +2372,7 @@ int gneb_upload(sp_gneb* G, const double* chain) {
 template <typename T>
 int gneb_download(sp_gneb* G, const void* src, double* out, size_t count) {
     std::vector<T> h(count);
-    if (hipStreamSynchronize(G->e->stream) != hipSuccess ||
+    if (hipStreamSynchronize(gneb_stream(G)) != hipSuccess ||
         hipMemcpy(h.data(), src, count * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess)
         return gfail(G, SP_E_HIP, "download failed");
     for (size_t k = 0; k < count; ++k) out[k] = (double)h[k];
@@ -2373,9 +2435,11 @@ int sp_gneb_create(sp_gneb** out, sp_engine* e, int n_images, const double* chai
         return fail(e, SP_E_HIP, "GNEB initialisation failed");
     }
     rc = e->precision == SP_F64 ? gneb_upload<double>(G, chain) : gneb_upload<float>(G, chain);
-    if (rc == SP_OK) rc = e->precision == SP_F64 ? gneb_forces<double>(G, false) : gneb_forces<float>(G, false);
+    if (rc == SP_OK)
+        rc = e->precision == SP_F64 ? gneb_forces<double>(G, false, e->stream) : gneb_forces<float>(G, false, e->stream);
     // v = 0 (vf = 0 gives a zero projection) and F_prev = F
-    if (rc == SP_OK) rc = e->precision == SP_F64 ? gneb_project<double>(G) : gneb_project<float>(G);
+    if (rc == SP_OK)
+        rc = e->precision == SP_F64 ? gneb_project<double>(G, e->stream) : gneb_project<float>(G, e->stream);
     if (rc == SP_OK && hipStreamSynchronize(e->stream) != hipSuccess) rc = SP_E_HIP;
     if (rc) {
         e->err = G->err;
@@ -2392,6 +2456,14 @@ void sp_gneb_destroy(sp_gneb* G) {
     // The engine may already be gone (its stream too): only the device is used.
     (void)hipSetDevice(G->device);
     (void)hipDeviceSynchronize();
+    if (G->batch) {   // detach: the batch's captured chunk launches this chain's kernels
+        sp_batch* b = G->batch;
+        b->gneb = nullptr;
+        if (b->gexec) {
+            (void)hipGraphExecDestroy(b->gexec);
+            b->gexec = nullptr;
+        }
+    }
     gneb_free(G);
     delete G;
 }
@@ -2404,8 +2476,9 @@ int sp_gneb_set_image_type(sp_gneb* G, int image, int type) {
     if (type != SP_IMAGE_NORMAL && type != SP_IMAGE_CLIMBING && type != SP_IMAGE_FALLING)
         return gfail(G, SP_E_ARG, "type must be SP_IMAGE_NORMAL, SP_IMAGE_CLIMBING or SP_IMAGE_FALLING");
     (void)hipSetDevice(G->e->device);
-    if (hipMemcpyAsync(G->types + image, &type, sizeof(int), hipMemcpyHostToDevice, G->e->stream) != hipSuccess ||
-        hipStreamSynchronize(G->e->stream) != hipSuccess)
+    const hipStream_t st = gneb_stream(G);
+    if (hipMemcpyAsync(G->types + image, &type, sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
         return gfail(G, SP_E_HIP, "image type upload failed");
     // the previous force kept by the minimiser is left as it is; the next
     // iteration forms the new force with the new type
@@ -2415,6 +2488,7 @@ int sp_gneb_set_image_type(sp_gneb* G, int image, int type) {
 int sp_gneb_iterate(sp_gneb* G, int n_iter) {
     if (!G) return SP_E_ARG;
     if (n_iter < 0) return gfail(G, SP_E_ARG, "n_iter must be >= 0");
+    if (G->batch) return gfail(G, SP_E_ORDER, "the chain is attached to a batch: sp_batch_run advances it");
     (void)hipSetDevice(G->e->device);
     const int rc = G->e->precision == SP_F64 ? gneb_iterate<double>(G, n_iter) : gneb_iterate<float>(G, n_iter);
     if (rc) return rc;
@@ -2432,7 +2506,7 @@ int sp_gneb_get_chain(sp_gneb* G, double* chain) {
 int sp_gneb_get_forces(sp_gneb* G, double* E, double* l, double* F) {
     if (!G) return SP_E_ARG;
     (void)hipSetDevice(G->e->device);
-    if (hipStreamSynchronize(G->e->stream) != hipSuccess) return gfail(G, SP_E_HIP, "synchronisation failed");
+    if (hipStreamSynchronize(gneb_stream(G)) != hipSuccess) return gfail(G, SP_E_HIP, "synchronisation failed");
     if (E && hipMemcpy(E, G->E, G->M * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
         return gfail(G, SP_E_HIP, "download failed");
     if (l) {

@@ -33,7 +33,7 @@ EXPORTS = [
     "sp_set_step_path", "sp_autotune", "sp_mc_run",
     "sp_batch_create", "sp_batch_destroy", "sp_batch_last_error", "sp_batch_add", "sp_batch_run",
     "sp_batch_get_spins", "sp_batch_replica_info", "sp_batch_set_chunk", "sp_batch_get_step",
-    "sp_batch_autotune",
+    "sp_batch_autotune", "sp_batch_add_gneb",
     "sp_gneb_create", "sp_gneb_destroy", "sp_gneb_last_error", "sp_gneb_set_image_type", "sp_gneb_iterate",
     "sp_gneb_get_chain", "sp_gneb_get_forces",
     "sp_ddi_init", "sp_ddi_num_params", "sp_ddi_set_params", "sp_ddi_get_params", "sp_ddi_label_dev",
@@ -140,6 +140,7 @@ def lib():
         "sp_batch_set_chunk": (ci, [vp, ci]),
         "sp_batch_get_step": (u64, [vp]),
         "sp_batch_autotune": (ci, [vp, ci, dp]),
+        "sp_batch_add_gneb": (ci, [vp, vp]),
         "sp_gneb_create": (ci, [ctypes.POINTER(vp), vp, ci, dp, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double]),
         "sp_gneb_destroy": (None, [vp]),
@@ -498,6 +499,11 @@ class Batch:
         ms = ctypes.c_double()
         self._check(lib().sp_batch_autotune(self._h, n_steps, ctypes.byref(ms)))
         return ms.value
+
+    def add_gneb(self, chain: "Gneb"):
+        """Advance a GNEB chain (FP32) with every run, in the same chunk graph."""
+        self._check(lib().sp_batch_add_gneb(self._h, chain._h))
+        self._gneb = chain   # keep it alive while attached
 
 
 class Gneb:

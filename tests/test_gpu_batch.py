@@ -138,3 +138,74 @@ def test_batch_rejects_mixed_or_unsupported_replicas():
     assert ei.value.code == pk.SP_E_ORDER
     with pytest.raises(pk.SpError):
         b.set_chunk(3)
+
+
+def _chain(pk, L=48, M=10):
+    e = pk.Engine(0, "f32")
+    geo = si.square(L, L)
+    e.set_geometry(geo)
+    e.set_hamiltonian(HAM0)
+    a = si.skyrmion_ansatz(geo, radius=4.0, width=1.5)
+    c = si.geodesic_chain(a, si.ferromagnet(geo.n_sites, (0, 0, 1)), M, fallback_axis=(1, 0, 0))
+    return e, c
+
+
+def test_batch_advances_an_attached_gneb_chain():
+    """A chain attached to a batch (its iterations a branch of the chunk
+    graph) ends bit-identical to the same chain iterated on its own, through
+    graph replays, a re-capture and direct chunks; the replicas are the same
+    as in a batch without the chain."""
+    import paper_1901_11350_amd as pk
+    from paper_1901_11350_amd.engine import SpError
+
+    announce("batch + attached GNEB chain")
+    e1, c = _chain(pk)
+    g1 = pk.Gneb(e1, c, k_spring=1.0, vp_dt=0.1)
+    e2, _ = _chain(pk)
+    g2 = pk.Gneb(e2, c, k_spring=1.0, vp_dt=0.1)
+    b, _ = _make(pk, "square", HAM0, SPECS, chunk=4)
+    ref, _ = _make(pk, "square", HAM0, SPECS, chunk=4)
+    g1.iterate(3)                       # the chain may have a history before it is attached
+    g2.iterate(3)
+    b.add_gneb(g1)
+    with pytest.raises(SpError):
+        g1.iterate(1)                   # the batch advances it now
+    with pytest.raises(SpError):
+        b.add_gneb(g2)                  # one chain per batch
+    for n in (9, 6, 3):                 # replays + direct steps, a parity change, direct only
+        b.run(n)
+        ref.run(n)
+        g2.iterate(n)
+    assert np.array_equal(g1.chain(), g2.chain())
+    f1, f2 = g1.forces(), g2.forces()
+    assert np.array_equal(f1["E"], f2["E"]) and np.array_equal(f1["F"], f2["F"])
+    for r in range(len(SPECS)):
+        assert np.array_equal(b.get_spins(r), ref.get_spins(r))
+    # destroying the chain detaches it; the batch keeps running
+    g1.close()
+    b.run(4)
+    ref.run(4)
+    assert np.array_equal(b.get_spins(0), ref.get_spins(0))
+
+
+def test_attached_chain_survives_the_batch_and_fp64_is_refused():
+    import paper_1901_11350_amd as pk
+    from paper_1901_11350_amd.engine import SpError
+
+    announce("batch + GNEB detach and refusals")
+    e1, c = _chain(pk, L=32, M=6)
+    g1 = pk.Gneb(e1, c)
+    b, _ = _make(pk, "square", HAM0, SPECS[:2], chunk=2)
+    b.add_gneb(g1)
+    b.run(4)
+    x = g1.chain()
+    b.close()                           # detaches: the chain runs on its own again
+    g1.iterate(2)
+    assert not np.array_equal(g1.chain(), x)
+    e64 = pk.Engine(0, "f64")
+    e64.set_geometry(si.square(32, 32))
+    e64.set_hamiltonian(HAM0)
+    g64 = pk.Gneb(e64, c)
+    b2, _ = _make(pk, "square", HAM0, SPECS[:1], chunk=2)
+    with pytest.raises(SpError):
+        b2.add_gneb(g64)

@@ -93,11 +93,17 @@ def test_fft_dipole_llg_trajectory(ora, precision):
     assert_close(e.get_spins(), ref, precision, what="FFT dipole trajectory")
 
 
-def test_fft_mode_rejects_oversized_lattice():
+def test_fft_mode_rejects_oversized_lattice_and_keeps_the_state():
     import paper_1901_11350_amd as pk
     from paper_1901_11350_amd.engine import SpError
 
     e = pk.Engine(0, "f32")
     e.set_geometry(si.simple_cubic(600, 2, 1, periodic=(0, 0, 0)))
+    plain = dataclasses.replace(DIP, ddi=0, J=(1.0,))
+    e.set_hamiltonian(plain)
+    e.set_spins(si.uniform_sphere(e.N, 3))
+    E0, path0, n0 = e.energy(), e.step_path, e.get_spins()
     with pytest.raises(SpError):
         e.set_hamiltonian(DIP)
+    assert e.energy() == E0 and e.step_path == path0
+    assert np.array_equal(e.get_spins(), n0)
