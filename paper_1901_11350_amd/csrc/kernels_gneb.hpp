@@ -172,7 +172,8 @@ __global__ void __launch_bounds__(256) k_gneb_tangent(GnebDims d, const T* __res
         if (im + 1 < d.M) {
             const V3<T> n1 = load3(x + (im + 1) * L3, d.N, i);
             const V3<T> c = cross(n0, n1);
-            const double ang = atan2((double)sqrt(dot(c, c)), (double)dot(n0, n1));
+            // angle in working precision (its inputs are), squared sum in FP64
+            const double ang = (double)atan2(sqrt(dot(c, c)), dot(n0, n1));
             acc[2] = ang * ang;
         }
         if (im > 0 && im + 1 < d.M) {
