@@ -222,6 +222,58 @@ def bench_batch(args) -> dict:
             "batch_gain": (total * K / ms) / (total * Ks / ms_sep), "autotune_ms_per_step": tuned}
 
 
+def bench_stencil(args) -> dict:
+    """The stand-alone stencil field kernel (sp_gradient_dev: exchange, DMI,
+    anisotropy, Zeeman from LDS-staged tiles) on the 512^2 triangular
+    workload and on the 8192^2 probe lattice, whose working set exceeds the
+    last-level cache; algorithmic HBM bytes 24 per site (read n, write g)."""
+    import torch
+
+    import paper_1901_11350_amd as pk
+    import spin_inputs as si
+
+    out = {}
+    stream = work_stream()
+    for name in ("triangular512_sllg", "square8192_probe"):
+        w = si.WORKLOADS[name]
+        e = pk.engine_for(w, 0, "f32", stream=stream)
+        e.set_spins(si.uniform_sphere(e.N, w.init_seed))
+        g = torch.empty((3, e.N), dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            e.gradient_dev(g)
+        torch.cuda.synchronize()
+        K = args.stencil_launches
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(K):
+            e.gradient_dev(g)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t = ev0.elapsed_time(ev1) * 1e-3 / K
+        gbps = 24.0 * e.N / t / 1e9
+        out[name] = {"n_sites": e.N, "us_per_launch": t * 1e6, "hbm_gbps_algorithmic": gbps,
+                     "hbm_frac": gbps / HBM_PEAK_GBPS, "kernel": "k_gradient_shape", "launches": K}
+        if name == "square8192_probe":
+            # a device copy of the same bytes (read 12 B, write 12 B per site): the
+            # practical HBM ceiling the stencil is measured against
+            src = torch.empty((3, e.N), dtype=torch.float32, device="cuda")
+            with torch.cuda.stream(stream):
+                for _ in range(3):
+                    g.copy_(src)
+                ev0.record(stream)
+                for _ in range(K):
+                    g.copy_(src)
+                ev1.record(stream)
+            torch.cuda.synchronize()
+            tc = ev0.elapsed_time(ev1) * 1e-3 / K
+            out[name]["copy_same_bytes_gbps"] = 24.0 * e.N / tc / 1e9
+            out[name]["frac_of_copy"] = gbps / out[name]["copy_same_bytes_gbps"]
+            del src
+        del g, e
+        torch.cuda.empty_cache()
+    return out
+
+
 def film_textures(geo, count: int, seed: int):
     """Seeded training/test textures of the dipolar film: a third uniform
     random, a third 1-3 tanh domain walls (Bloch or Neel, random position,
@@ -433,6 +485,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=256)
     ap.add_argument("--batch-chunk", type=int, default=32)
     ap.add_argument("--gneb-iters", type=int, default=200)
+    ap.add_argument("--stencil", action="store_true",
+                    help="also time the stand-alone stencil field kernel (512^2 and the 8192^2 probe)")
+    ap.add_argument("--stencil-launches", type=int, default=200)
     ap.add_argument("--tc", action="store_true",
                     help="also estimate the ferromagnet's Tc from Binder crossings (reported under 'tc')")
     ap.add_argument("--tc-therm", type=int, default=10000)
@@ -560,6 +615,8 @@ def main():
         line["surrogate"] = bench_surrogate(args)
     if args.tc:
         line["tc"] = bench_tc(args)
+    if args.stencil:
+        line["stencil"] = bench_stencil(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -893,8 +893,53 @@ int upload_ham(sp_engine* e) {
     return SP_OK;
 }
 
+// Stencil gradient of a one-atom 2D lattice with a compile-time stencil:
+// 64 x 16 tiles with one site per thread, or, for FP32 lattices of at least
+// 512 such 64 x 64 tiles, 64 x 64 tiles with four sites per thread (more
+// loads in flight per CU, less halo).
+template <typename T, int S, int TX, int TY, int NT>
+void go_gradient_tile(sp_engine* e, const void* n, void* g) {
+    sp::TileMap M{};
+    M.tiles_x = (e->geo.n[0] + TX - 1) / TX;
+    M.tiles_y = (e->geo.n[1] + TY - 1) / TY;
+    const int ntiles = M.tiles_x * M.tiles_y;
+    M.xcd_bands = (ntiles >= 8 && ntiles % 8 == 0) ? 1 : 0;
+    const sp::ShapeCoef<T> C = shape_coef_for<T, S>(e);
+    const sp::Site2D<T> Q = make_site2d<T>(e, nullptr);
+    if (e->shape_ndmi)
+        hipLaunchKernelGGL((sp::k_gradient_shape<T, S, sp::ShapeTab<S>::NB0, TX, TY, NT>), dim3((unsigned)ntiles),
+                           dim3(NT), 0, e->stream, C, Q, M, static_cast<const T*>(n), static_cast<T*>(g));
+    else
+        hipLaunchKernelGGL((sp::k_gradient_shape<T, S, 0, TX, TY, NT>), dim3((unsigned)ntiles), dim3(NT), 0,
+                           e->stream, C, Q, M, static_cast<const T*>(n), static_cast<T*>(g));
+}
+
+template <typename T, int S>
+void go_gradient_shape(sp_engine* e, const void* n, void* g) {
+    const long long big_tiles = (long long)((e->geo.n[0] + 63) / 64) * ((e->geo.n[1] + 63) / 64);
+    if constexpr (sizeof(T) == 4) {
+        if (big_tiles >= 512) {
+            go_gradient_tile<T, S, 64, 64, 1024>(e, n, g);
+            return;
+        }
+    }
+    go_gradient_tile<T, S, 64, 16, 1024>(e, n, g);
+}
+
 template <typename T>
 int gradient_dev(sp_engine* e, const void* n, void* g) {
+    if (e->shape >= 0) {   // no dipole, no on-site potentials on this path
+        switch (e->shape) {
+            case sp::SH_SQ1: go_gradient_shape<T, sp::SH_SQ1>(e, n, g); break;
+            case sp::SH_SQ2: go_gradient_shape<T, sp::SH_SQ2>(e, n, g); break;
+            case sp::SH_SQ3: go_gradient_shape<T, sp::SH_SQ3>(e, n, g); break;
+            case sp::SH_TRI1: go_gradient_shape<T, sp::SH_TRI1>(e, n, g); break;
+            case sp::SH_TRI2: go_gradient_shape<T, sp::SH_TRI2>(e, n, g); break;
+            default: go_gradient_shape<T, sp::SH_TRI3>(e, n, g); break;
+        }
+        HIPCHK(e, hipGetLastError());
+        return SP_OK;
+    }
     const void* gdd = nullptr;
     if (e->ham.ddi) {
         int rc = launch_dipole<T>(e, n, e->d_gdd);

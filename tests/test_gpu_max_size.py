@@ -6,8 +6,8 @@ A 32768 x 16384 periodic triangular lattice (exactly 2^29 sites, the
 64 x 64 random patch.  At T = 0 the dynamics commute with lattice
 translations, so every site of the big lattice must follow the oracle's
 trajectory of the 64 x 64 periodic patch: checked on sampled sites after
-Depondt steps on the default fused path and on the two-pass path, and for
-the energy per spin.  The spins are built and read on the device (torch
+Depondt steps on the default fused path and on the two-pass path, for the
+energy per spin, and for the LDS-tiled stencil gradient.  The spins are built and read on the device (torch
 tensors through the *_dev entry points), so no 2^29-site array crosses to
 the host.  Also: 2^29 + 1 sites are rejected, the persistent path refuses a
 lattice whose tiles cannot all be resident, and the Philox normals of the
@@ -86,6 +86,35 @@ def test_max_size_lattice_follows_the_periodic_patch(ora, big_engine, path, step
     E_patch = s.energy(ref) / (P * P)
     assert E_big == pytest.approx(E_patch, rel=1e-5)
     del n
+    torch.cuda.empty_cache()
+
+
+def test_max_size_stencil_gradient_follows_the_periodic_patch(ora, big_engine):
+    """The LDS-tiled stencil gradient of the 2^29-site lattice on sampled
+    sites against the oracle's gradient of the 64 x 64 periodic patch."""
+    import torch
+
+    announce("max size stencil gradient")
+    w = W["triangular512_sllg"]
+    patch = si.uniform_sphere(P * P, 123)
+    s = ora.System(w.geometry.with_cells((P, P, 1)), w.hamiltonian)
+    ref = s.gradient(patch)
+    e = big_engine
+    n = _tiled(torch, patch)
+    g = torch.empty_like(n)
+    torch.cuda.synchronize()
+    e.set_spins_dev(n)
+    e.gradient_dev(g)
+    e.synchronize()
+    rng = np.random.default_rng(6)
+    xs = rng.integers(0, BIG[0], 8192)
+    ys = rng.integers(0, BIG[1], 8192)
+    xs[:4] = [0, BIG[0] - 1, 0, BIG[0] - 1]
+    ys[:4] = [0, 0, BIG[1] - 1, BIG[1] - 1]
+    idx = torch.tensor(xs + ys * BIG[0], device="cuda")
+    got = g[:, idx].double().cpu().numpy()
+    assert_close(got, ref[:, (xs % P) + (ys % P) * P], "f32", what="2^29-site stencil gradient")
+    del n, g
     torch.cuda.empty_cache()
 
 

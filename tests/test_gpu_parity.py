@@ -333,3 +333,19 @@ def test_call_order_errors(ora):
     assert ei.value.code == pk.SP_E_ORDER
     with pytest.raises(pk.SpError):
         e.step_path = "nonsense"
+
+
+@pytest.mark.parametrize("case", ["tri1540x1530", "sq1600x1536_open_2shell"])
+def test_stencil_gradient_large_tiles_match_oracle(ora, case):
+    """Lattices large enough for the 64 x 64 tiles of the stand-alone stencil
+    gradient (ragged tiles, open edges): every site against the oracle."""
+    announce(f"stencil gradient large tiles {case}")
+    if case == "tri1540x1530":
+        geo, ham = si.triangular(1540, 1530), HAM1
+    else:
+        geo, ham = si.square(1600, 1536, periodic=(0, 1, 0)), dataclasses.replace(HAM0, J=(1.0, 0.3))
+    e, s = make_pair(ora, geo, ham, "f32")
+    assert e.step_path.startswith("shape2d")
+    n = si.uniform_sphere(s.N, 77)
+    e.set_spins(n)
+    assert_close(e.gradient(), s.gradient(n), "f32", what=f"stencil gradient {case}")
