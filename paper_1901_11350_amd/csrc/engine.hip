@@ -26,6 +26,7 @@
 #include "kernels_mc.hpp"
 #include "kernels_fused3d.hpp"
 #include "kernels_persist2d.hpp"
+#include "kernels_stencil.hpp"
 
 namespace {
 
