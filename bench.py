@@ -97,9 +97,25 @@ def cpu_baseline(workload, budget_s: float = 12.0) -> dict:
         el = time.perf_counter() - t0
         if el >= budget_s or steps >= 2000:
             break
-    return {"value": s.N * steps / el, "unit": "spin-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} FP64 Depondt steps of the full {s.N}-spin workload ({el:.1f} s)"}
+    cores = oracle.num_threads()
+    out = {"value": s.N * steps / el, "unit": "spin-updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"{steps} FP64 Depondt steps of the full {s.N}-spin workload ({el:.1f} s)"}
+    # the same oracle on one core (the paper compares one thread with many)
+    oracle.set_num_threads(1)
+    try:
+        steps1 = 0
+        t0 = time.perf_counter()
+        while True:
+            n, _ = s.run(n, d.alpha, d.dt, 1, T=d.T, seed=d.seed, step0=steps + steps1)
+            steps1 += 1
+            el1 = time.perf_counter() - t0
+            if el1 >= budget_s / 2 or steps1 >= 2000:
+                break
+    finally:
+        oracle.set_num_threads(cores)
+    out["single_core"] = {"value": s.N * steps1 / el1, "cores": 1,
+                          "sample": f"{steps1} steps ({el1:.1f} s)"}
+    return out
 
 
 def calibrate_copy(mib: int, reps: int = 5) -> None:

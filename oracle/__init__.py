@@ -164,6 +164,8 @@ def lib():
                                ctypes.c_double, ctypes.c_double, ci]
         L.ora_num_threads.restype = ctypes.c_int
         L.ora_num_threads.argtypes = []
+        L.ora_set_num_threads.restype = None
+        L.ora_set_num_threads.argtypes = [ci]
         _lib = L
     return _lib
 
@@ -180,6 +182,10 @@ def constants() -> dict:
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().ora_set_num_threads(int(n))
 
 
 def _geometry(geo) -> Geometry:

@@ -50,8 +50,10 @@
 #ifdef _OPENMP
 #include <omp.h>
 int ora_num_threads(void) { return omp_get_max_threads(); }
+void ora_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 #else
 int ora_num_threads(void) { return 1; }
+void ora_set_num_threads(int n) { (void)n; }
 #endif
 
 double ora_const_mu_B(void) { return MU_B_J_PER_T / J_PER_MEV; }

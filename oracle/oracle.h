@@ -219,8 +219,10 @@ void ora_silu(int64_t n, const double *z, double *y, double *dydz);
 void ora_adam(int64_t n, double *p, double *m, double *v, const double *g, double lr, double b1, double b2,
               double eps, int t);
 
-/* OpenMP threads the oracle's parallel loops use. */
+/* OpenMP threads the oracle's parallel loops use, and a way to change them
+ * (timing on one core beside all cores). */
 int ora_num_threads(void);
+void ora_set_num_threads(int n);
 
 /* Physical constants used by the oracle. */
 double ora_const_mu_B(void);
