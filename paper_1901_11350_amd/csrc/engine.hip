@@ -693,6 +693,7 @@ void go_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* 
     const int chunks = std::max(1, std::min(Z.nc, (target + txy - 1) / txy));
     Z.zc = (Z.nc + chunks - 1) / chunks;
     const int nchunks = (Z.nc + Z.zc - 1) / Z.zc;
+    Z.xcd_bands = ((txy * nchunks) % 8 == 0) ? 1 : 0;
     hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, NDMI, TX, TY, SOLVER>), dim3((unsigned)(txy * nchunks)),
                        dim3(TX * TY), 0, e->stream, shape_coef3_for<T, S>(e), make_site2d<T>(e, p), Z,
                        make_llg<T>(p, step, p->replica), e->d_flag, static_cast<const T*>(nin), static_cast<T*>(nout));

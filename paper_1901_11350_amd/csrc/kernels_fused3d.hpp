@@ -65,6 +65,7 @@ struct Site3D {
     int nc, per_c;
     int zc;                  // planes per workgroup
     int tiles_x, tiles_y;
+    int xcd_bands;           // 1: each XCD gets a contiguous range of work items (count divisible by 8)
 };
 
 template <typename T, int S, int TX, int TY>
@@ -136,8 +137,13 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
     __shared__ PL L;
     const int tid = threadIdx.x;
     const int tiles_xy = Z.tiles_x * Z.tiles_y;
-    const int zchunk = blockIdx.x / tiles_xy;
-    const int txy = blockIdx.x - zchunk * tiles_xy;
+    // workgroups are dealt to the 8 XCDs round-robin: give each XCD a
+    // contiguous range of (chunk, tile) items, so that neighbouring columns,
+    // which stream through the planes in step, share one L2 for their halos
+    int item = blockIdx.x;
+    if (Z.xcd_bands) item = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const int zchunk = item / tiles_xy;
+    const int txy = item - zchunk * tiles_xy;
     const int ty0 = txy / Z.tiles_x;
     const int x0 = (txy - ty0 * Z.tiles_x) * TX, y0 = ty0 * TY;
     const int z0 = zchunk * Z.zc;
