@@ -349,3 +349,57 @@ def test_stencil_gradient_large_tiles_match_oracle(ora, case):
     n = si.uniform_sphere(s.N, 77)
     e.set_spins(n)
     assert_close(e.gradient(), s.gradient(n), "f32", what=f"stencil gradient {case}")
+
+
+@pytest.mark.parametrize("path", ["shape2d/64x16x1024", "persist2d/64x16", "twopass"])
+def test_zero_work_calls_change_nothing(ora, path):
+    """Empty runs: zero LLG steps, zero Monte Carlo sweeps, zero GNEB
+    iterations and zero batch steps return OK and leave spins and step
+    counters as they were; an observation interval longer than the run
+    yields no observation; negative counts are rejected."""
+    import paper_1901_11350_amd as pk
+
+    announce(f"zero work {path}")
+    e = pk.Engine(0, "f32")
+    geo = si.triangular(128, 64)
+    e.set_geometry(geo)
+    e.set_hamiltonian(HAM1)
+    e.step_path = path
+    n0 = si.uniform_sphere(e.N, 3)
+    e.set_spins(n0)
+    e.step = 7
+    before = e.get_spins()
+    assert e.run(0.1, 0.001, 0, T=10.0, seed=1) == []
+    assert e.run(0.1, 0.001, 0, T=10.0, seed=1, observe_every=5) == []
+    assert e.step == 7 and np.array_equal(e.get_spins(), before)
+    obs = e.run(0.1, 0.001, 3, T=10.0, seed=1, observe_every=5)   # interval longer than the run
+    assert obs == [] and e.step == 10
+    with pytest.raises(pk.SpError):
+        e.run(0.1, 0.001, -1)
+    m = pk.Engine(0, "f32")
+    m.set_geometry(si.square(16, 16))
+    m.set_hamiltonian(dataclasses.replace(HAM0, D=()))
+    m.set_spins(si.uniform_sphere(m.N, 4))
+    m0 = m.get_spins()
+    obs, acc = m.mc_run(10.0, 30.0, 0, observe_every=1)
+    assert obs == [] and acc == 0 and np.array_equal(m.get_spins(), m0)
+    g_eng = pk.Engine(0, "f32")
+    g_eng.set_geometry(si.square(16, 16))
+    g_eng.set_hamiltonian(HAM0)
+    chain = si.geodesic_chain(si.skyrmion_ansatz(si.square(16, 16), radius=3.0), si.ferromagnet(256, (0, 0, 1)), 5,
+                              fallback_axis=(1, 0, 0))
+    g = pk.Gneb(g_eng, chain)
+    c0 = g.chain()
+    g.iterate(0)
+    assert np.array_equal(g.chain(), c0)
+    with pytest.raises(pk.SpError):
+        g.iterate(-1)
+    b = pk.Batch(0)
+    r = pk.Engine(0, "f32")
+    r.set_geometry(si.square(32, 32))
+    r.set_hamiltonian(HAM0)
+    r.set_spins(si.uniform_sphere(r.N, 5))
+    b.add(r, 0.3, 0.001)
+    s0 = b.get_spins(0)
+    b.run(0)
+    assert b.step == 0 and np.array_equal(b.get_spins(0), s0)
