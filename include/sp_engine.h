@@ -163,7 +163,10 @@ const char *sp_last_error(const sp_engine *e);
  * cos(theta) = 1 - u1 (1 - cos(cone)); new spin cos(theta) n +
  * sin(theta) (cos(phi) e1 + sin(phi) e2), e1 = unit(n x r) with r = z if
  * |n_z| < 0.9 else x, e2 = n x e1; accepted if u2 < exp(-dE / (k_B T)).
- * The sweep number is the engine's step counter (advanced by n_sweeps).
+ * Trial, dE and the test are computed in FP64 in both engine precisions
+ * (an FP32 engine reads its FP32 spins and stores an accepted trial rounded
+ * to FP32).  The sweep number is the engine's step counter (advanced by
+ * n_sweeps).
  * Needs a one-atom basis, bonds that join the two colours, even lengths on
  * periodic axes and no dipole term (SP_E_UNSUPPORTED otherwise).  obs
  * receives n_sweeps / observe_every observations (observe_every = 0: none);

@@ -120,6 +120,8 @@ struct sp_engine {
     int* d_bstart = nullptr;
     void* d_J = nullptr;
     void* d_D = nullptr;
+    void* d_J64 = nullptr;              // FP64 copies for an FP32 engine's Monte Carlo decisions
+    void* d_D64 = nullptr;
     double* d_partials = nullptr;     // observe stage-1 rows
     int partial_rows = 0;
     double* d_obs = nullptr;          // observations of a run, OBS_NVALS each
@@ -176,7 +178,7 @@ void free_state_buffers(sp_engine* e) {
     dfree(e->d_gdd); dfree(e->d_gddp); dfree(e->d_pos); dfree(e->d_ddpart);
     void* p = e->d_bond; dfree(p); e->d_bond = nullptr;
     p = e->d_bstart; dfree(p); e->d_bstart = nullptr;
-    dfree(e->d_J); dfree(e->d_D);
+    dfree(e->d_J); dfree(e->d_D); dfree(e->d_J64); dfree(e->d_D64);
     fft_free(e->fft);
     e->fft = nullptr;
 }
@@ -876,6 +878,17 @@ int upload_ham(sp_engine* e) {
     HIPCHK(e, hipMemcpy(e->d_bstart, e->bstart.data(), e->bstart.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(e, hipMemcpy(e->d_J, J.data(), J.size() * sizeof(T), hipMemcpyHostToDevice));
     HIPCHK(e, hipMemcpy(e->d_D, D.data(), D.size() * sizeof(T), hipMemcpyHostToDevice));
+    if constexpr (sizeof(T) == 4) {
+        std::vector<double> J64(J.size()), D64(D.size());
+        for (size_t q = 0; q < nbond; ++q) {
+            J64[q] = e->bonds[q].J;
+            for (int k = 0; k < 3; ++k) D64[3 * q + k] = e->bonds[q].D[k];
+        }
+        if ((rc = dalloc(e, e->d_J64, J64.size() * sizeof(double)))) return rc;
+        if ((rc = dalloc(e, e->d_D64, D64.size() * sizeof(double)))) return rc;
+        HIPCHK(e, hipMemcpy(e->d_J64, J64.data(), J64.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(e, hipMemcpy(e->d_D64, D64.data(), D64.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     if (e->ham.ddi) {
         // site positions in Angstrom
         std::vector<T> pos(3 * (size_t)e->N);
@@ -1071,11 +1084,13 @@ int mc_run_impl(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t o
     if ((rc = dalloc(e, acc, blocks * sizeof(unsigned int)))) return rc;
     HIPCHK(e, hipMemsetAsync(acc, 0, blocks * sizeof(unsigned int), e->stream));
     const sp::Lattice L = make_lattice(e);
-    const sp::BondCoef<T> C = make_coef<T>(e);
-    const sp::Phys<T> P = make_phys<T>(e, nullptr);
-    sp::McArgs<T> M{};
-    M.kT = (T)(kKB * p->T_K);
-    M.cos_cone = (T)std::cos(p->cone_deg * M_PI / 180.0);
+    // decisions in FP64 for every engine precision: FP64 couplings
+    const sp::BondCoef<double> C{static_cast<const double*>(e->precision == SP_F64 ? e->d_J : e->d_J64),
+                                 static_cast<const double*>(e->precision == SP_F64 ? e->d_D : e->d_D64)};
+    const sp::Phys<double> P = make_phys<double>(e, nullptr);
+    sp::McArgs<double> M{};
+    M.kT = kKB * p->T_K;
+    M.cos_cone = std::cos(p->cone_deg * M_PI / 180.0);
     M.key.seed_lo = (uint32_t)p->seed;
     M.key.seed_hi = (uint32_t)(p->seed >> 32);
     M.key.replica = p->replica;

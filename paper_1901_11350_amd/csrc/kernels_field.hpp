@@ -95,10 +95,12 @@ __device__ __forceinline__ void store3(T* __restrict__ v, int N, int i, V3<T> a)
     v[2 * N + i] = a.z;
 }
 
-// Local field terms of site i from the bond table (generic lattice).
-template <typename T>
+// Local field terms of site i from the bond table (generic lattice), in
+// arithmetic type T from spins stored as S (S = T except where an FP32
+// engine takes a decision in FP64).
+template <typename T, typename S = T>
 __device__ FieldTerms<T> site_terms(const Lattice& L, const BondCoef<T>& C, const Phys<T>& P,
-                                    const T* __restrict__ n, int i, V3<T> ni) {
+                                    const S* __restrict__ n, int i, V3<T> ni) {
     const int na = L.n[0], nbc = L.n[1], nc = L.n[2];
     const int a = i % na;
     const int rem = i / na;
@@ -121,7 +123,7 @@ __device__ FieldTerms<T> site_terms(const Lattice& L, const BondCoef<T>& C, cons
         if (!ok) continue;
         const int j = ta + na * (tb + nbc * (tc + nc * bd.x));
         if (j == i) continue;
-        const V3<T> nj = load3(n, L.N, j);
+        const V3<T> nj{(T)n[j], (T)n[L.N + j], (T)n[2 * L.N + j]};
         const T J = C.J[q];
         const V3<T> D{C.D[3 * q], C.D[3 * q + 1], C.D[3 * q + 2]};
         gj = gj - J * nj;

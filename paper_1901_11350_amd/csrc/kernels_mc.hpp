@@ -56,9 +56,14 @@ __device__ __forceinline__ V3<T> mc_trial(V3<T> n, const T u[3], T cos_cone) {
 
 // One colour of one sweep (one-atom basis).  acc_part[block] accumulates the
 // accepted trials of this workgroup's sites over the launches of a run.
+// The accept/reject decision is taken in FP64 for every engine precision
+// (the precision of the FP64 reference): trial spin, energy difference and
+// Metropolis test from the stored spins (type T) with FP64 couplings; an
+// accepted trial is stored rounded to T.
 template <typename T>
-__global__ void __launch_bounds__(256) k_mc_colour(Lattice L, BondCoef<T> C, Phys<T> P, McArgs<T> M,
-                                                   T* __restrict__ n, unsigned int* __restrict__ acc_part) {
+__global__ void __launch_bounds__(256) k_mc_colour(Lattice L, BondCoef<double> C, Phys<double> P,
+                                                   McArgs<double> M, T* __restrict__ n,
+                                                   unsigned int* __restrict__ acc_part) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     bool accepted = false;
     if (i < L.N) {
@@ -67,18 +72,18 @@ __global__ void __launch_bounds__(256) k_mc_colour(Lattice L, BondCoef<T> C, Phy
         const int b = rem % L.n[1];
         const int c = rem / L.n[1];
         if (((a + b + c) & 1) == M.colour) {
-            const V3<T> ni = load3(n, L.N, i);
-            T u[3];
-            mc_uniforms<T>(thermal_bits(M.key, (uint32_t)i), u);
-            const V3<T> nn = renorm_if_float(mc_trial(ni, u, M.cos_cone));
-            const FieldTerms<T> f = site_terms(L, C, P, n, i, ni);
-            const V3<T> lin = f.z + f.j + f.d;
-            const V3<T> ax{P.Kax[0][0], P.Kax[0][1], P.Kax[0][2]};
-            const T k0 = dot(ax, ni), k1 = dot(ax, nn);
-            const T dE = dot(nn - ni, lin) - T(0.5) * P.K2[0] * (k1 * k1 - k0 * k0) +
-                         (T)(gauss_energy(P, nn) - gauss_energy(P, ni));
+            const V3<double> ni{(double)n[i], (double)n[L.N + i], (double)n[2 * L.N + i]};
+            double u[3];
+            mc_uniforms<double>(thermal_bits(M.key, (uint32_t)i), u);
+            const V3<double> nn = mc_trial(ni, u, M.cos_cone);
+            const FieldTerms<double> f = site_terms<double, T>(L, C, P, n, i, ni);
+            const V3<double> lin = f.z + f.j + f.d;
+            const V3<double> ax{P.Kax[0][0], P.Kax[0][1], P.Kax[0][2]};
+            const double k0 = dot(ax, ni), k1 = dot(ax, nn);
+            const double dE = dot(nn - ni, lin) - 0.5 * P.K2[0] * (k1 * k1 - k0 * k0) +
+                              (gauss_energy(P, nn) - gauss_energy(P, ni));
             if (u[2] < exp(-dE / M.kT)) {
-                store3(n, L.N, i, nn);
+                store3(n, L.N, i, V3<T>{(T)nn.x, (T)nn.y, (T)nn.z});
                 accepted = true;
             }
         }
