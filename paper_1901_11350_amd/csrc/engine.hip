@@ -308,6 +308,13 @@ sp::BondCoef<T> make_coef(const sp_engine* e) {
     return sp::BondCoef<T>{static_cast<const T*>(e->d_J), static_cast<const T*>(e->d_D)};
 }
 
+// FP64 couplings for every engine precision (an FP32 engine keeps FP64
+// copies for its FP64 decisions).
+sp::BondCoef<double> make_coef64(const sp_engine* e) {
+    return sp::BondCoef<double>{static_cast<const double*>(e->precision == SP_F64 ? e->d_J : e->d_J64),
+                                static_cast<const double*>(e->precision == SP_F64 ? e->d_D : e->d_D64)};
+}
+
 inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 // ----------------------------------------------------------------- dipole
@@ -1085,8 +1092,7 @@ int mc_run_impl(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t o
     HIPCHK(e, hipMemsetAsync(acc, 0, blocks * sizeof(unsigned int), e->stream));
     const sp::Lattice L = make_lattice(e);
     // decisions in FP64 for every engine precision: FP64 couplings
-    const sp::BondCoef<double> C{static_cast<const double*>(e->precision == SP_F64 ? e->d_J : e->d_J64),
-                                 static_cast<const double*>(e->precision == SP_F64 ? e->d_D : e->d_D64)};
+    const sp::BondCoef<double> C = make_coef64(e);
     const sp::Phys<double> P = make_phys<double>(e, nullptr);
     sp::McArgs<double> M{};
     M.kT = kKB * p->T_K;
@@ -2356,8 +2362,8 @@ int gneb_forces(sp_gneb* G, bool update_v, hipStream_t st) {
     sp_engine* e = G->e;
     const sp::GnebDims d{G->M, G->N, G->nblk};
     const sp::Lattice L = make_lattice(e);
-    const sp::BondCoef<T> C = make_coef<T>(e);
-    const sp::Phys<T> P = make_phys<T>(e, nullptr);
+    const sp::BondCoef<double> C = make_coef64(e);
+    const sp::Phys<double> P = make_phys<double>(e, nullptr);
     T* x = static_cast<T*>(G->x);
     T* g = static_cast<T*>(G->g);
     T* tau = static_cast<T*>(G->tau);

@@ -110,20 +110,24 @@ __global__ void __launch_bounds__(256) k_gneb_move(GnebDims d, T dt, T half_dt2_
 // Gradient of every image and per-block energy partials (Zeeman linear,
 // the other local terms quadratic: e_i = n.(g_Z + (g_K + g_J + g_D)/2)).
 template <typename T>
-__global__ void __launch_bounds__(256) k_gneb_grad(GnebDims d, Lattice L, BondCoef<T> C, Phys<T> P,
+__global__ void __launch_bounds__(256) k_gneb_grad(GnebDims d, Lattice L, BondCoef<double> C, Phys<double> P,
                                                    const T* __restrict__ x, T* __restrict__ g,
                                                    double* __restrict__ part) {
+    // field and energy in FP64 from the stored spins (type T): the image
+    // energies decide the tangent's branch, so they are formed in the
+    // reference's precision for both engine precisions; g is stored as T
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int im = blockIdx.y;
     const T* xi = x + (size_t)im * 3 * d.N;
     double acc[1] = {0.0};
     if (i < d.N) {
-        const V3<T> ni = load3(xi, d.N, i);
-        const FieldTerms<T> f = site_terms(L, C, P, xi, i, ni);
-        store3(g + (size_t)im * 3 * d.N, d.N, i, total(f));
-        const double nx = ni.x, ny = ni.y, nz = ni.z;
-        acc[0] = nx * f.z.x + ny * f.z.y + nz * f.z.z +
-                 0.5 * (nx * (f.k.x + f.j.x + f.d.x) + ny * (f.k.y + f.j.y + f.d.y) + nz * (f.k.z + f.j.z + f.d.z)) +
+        const V3<double> ni{(double)xi[i], (double)xi[d.N + i], (double)xi[2 * d.N + i]};
+        const FieldTerms<double> f = site_terms<double, T>(L, C, P, xi, i, ni);
+        const V3<double> gt = total(f);
+        store3(g + (size_t)im * 3 * d.N, d.N, i, V3<T>{(T)gt.x, (T)gt.y, (T)gt.z});
+        acc[0] = ni.x * f.z.x + ni.y * f.z.y + ni.z * f.z.z +
+                 0.5 * (ni.x * (f.k.x + f.j.x + f.d.x) + ni.y * (f.k.y + f.j.y + f.d.y) +
+                        ni.z * (f.k.z + f.j.z + f.d.z)) +
                  gauss_energy(P, ni);
     }
     block_sums<1>(acc);
