@@ -168,16 +168,23 @@ __device__ __forceinline__ V3<T> shape_field_soa(const ShapeCoef<T>& C, const Si
         C, Q, [&](int o) { return V3<T>{sx[o], sy[o], sz[o]}; }, c, ni);
 }
 
+// One FP32 LDS cell read as a whole 16-byte ds_read_b128.  Left to itself
+// the compiler drops the unused padding word and emits ds_read_b96, which
+// on gfx950 costs ~8.7 LDS cycles per wave against ~4.9 for b128 (a wave of
+// 16-byte-strided cells); the empty asm keeps the fourth word live, so the
+// full-width read is kept, at no arithmetic cost.
+template <typename T>
+__device__ __forceinline__ V3<T> lds_cell_xyz(const V4<T>* __restrict__ sv, int o) {
+    const V4<T> v = sv[o];
+    if constexpr (sizeof(T) == 4) asm volatile("" ::"v"(v.w));
+    return V3<T>{v.x, v.y, v.z};
+}
+
 template <typename T, int S, int NDMI, int W>
 __device__ __forceinline__ V3<T> shape_field_aos(const ShapeCoef<T>& C, const Site2D<T>& Q,
                                                  const V4<T>* __restrict__ sv, int c, V3<T> ni) {
     return shape_field<T, S, NDMI, W>(
-        C, Q,
-        [&](int o) {
-            const V4<T> v = sv[o];
-            return V3<T>{v.x, v.y, v.z};
-        },
-        c, ni);
+        C, Q, [&](int o) { return lds_cell_xyz(sv, o); }, c, ni);
 }
 
 struct TileMap {
@@ -266,8 +273,7 @@ __device__ __forceinline__ V3<T> predict_cell(const ShapeCoef<T>& C, const Site2
     V3<T> keep{T(0), T(0), T(0)};
     if (in) {
         const int c = (py + R) * WN + (px + R);
-        const V4<T> n4 = L.sN[c];
-        const V3<T> ni{n4.x, n4.y, n4.z};
+        const V3<T> ni = lds_cell_xyz(L.sN, c);
         const V3<T> g = shape_field_aos<T, S, NDMI, WN>(C, Q, L.sN, c, ni);
         const V3<T> B = (-Q.inv_mumuB) * g + Bth;
         const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
@@ -298,13 +304,11 @@ __device__ __forceinline__ V3<T> correct_cell(const ShapeCoef<T>& C, const Site2
     using TL = TileLDS<T, S, TX, TY>;
     constexpr int R = TL::R, WN = TL::WN, WP = TL::WP;
     const int c = (ty + R) * WP + (tx + R);
-    const V4<T> p4 = L.sP[c];
-    const V3<T> npi{p4.x, p4.y, p4.z};
+    const V3<T> npi = lds_cell_xyz(L.sP, c);
     const V3<T> g = shape_field_aos<T, S, NDMI, WP>(C, Q, L.sP, c, npi);
     const V3<T> B = (-Q.inv_mumuB) * g + keepB;
     const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
-    const V4<T> n4 = L.sN[(ty + 2 * R) * WN + (tx + 2 * R)];
-    const V3<T> ni{n4.x, n4.y, n4.z};
+    const V3<T> ni = lds_cell_xyz(L.sN, (ty + 2 * R) * WN + (tx + 2 * R));
     if constexpr (SOLVER == SOLVER_HEUN) {
         // n + dt (f(n) + f(n^p)) / 2, renormalised
         return normalize3(ni + (T(0.5) * A.dt) * (keepA + cross(npi, Ap)));

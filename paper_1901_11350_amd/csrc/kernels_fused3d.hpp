@@ -90,7 +90,7 @@ __device__ __forceinline__ V3<T> shape_field3(const ShapeCoef3<T>& C, const Site
 #pragma unroll
     for (int q = 0; q < SH::NB; ++q) {
         const int slot = SH::dc[q] < 0 ? sm : (SH::dc[q] > 0 ? sp : s0);
-        const V4<T> v = rings[slot][c + SH::da[q] + SH::db[q] * W];
+        const V3<T> v = lds_cell_xyz(rings[slot], c + SH::da[q] + SH::db[q] * W);
         acc[SH::sh[q]].x += v.x;
         acc[SH::sh[q]].y += v.y;
         acc[SH::sh[q]].z += v.z;
@@ -205,8 +205,7 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
         V3<T> keep{T(0), T(0), T(0)};
         if (in) {
             const int c = (py + R) * WN + (px + R);
-            const V4<T> n4 = L.sN[z & 3][c];
-            const V3<T> ni{n4.x, n4.y, n4.z};
+            const V3<T> ni = lds_cell_xyz(L.sN[z & 3], c);
             const V3<T> g = shape_field3<T, S, NDMI, WN, PN>(C, Q, L.sN, (z - 1) & 3, z & 3, (z + 1) & 3, c, ni);
             const V3<T> B = (-Q.inv_mumuB) * g + Bth;
             const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
@@ -267,13 +266,11 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
         const int gx = x0 + tx, gy = y0 + tyy;
         if (zc >= z0 && zc < z1 && gx < NA && gy < NBB) {
             const int c = (tyy + R) * WP + (tx + R);
-            const V4<T> p4 = L.sP[pslot(zc)][c];
-            const V3<T> npi{p4.x, p4.y, p4.z};
+            const V3<T> npi = lds_cell_xyz(L.sP[pslot(zc)], c);
             const V3<T> g = shape_field3<T, S, NDMI, WP, PP>(C, Q, L.sP, pslot(zc - 1), pslot(zc), pslot(zc + 1), c, npi);
             const V3<T> B = (-Q.inv_mumuB) * g + keepB;
             const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
-            const V4<T> n4 = L.sN[zc & 3][(tyy + 2 * R) * WN + (tx + 2 * R)];
-            const V3<T> ni{n4.x, n4.y, n4.z};
+            const V3<T> ni = lds_cell_xyz(L.sN[zc & 3], (tyy + 2 * R) * WN + (tx + 2 * R));
             V3<T> o;
             if constexpr (SOLVER == SOLVER_HEUN) {
                 o = normalize3(ni + (T(0.5) * A.dt) * (keepA + cross(npi, Ap)));

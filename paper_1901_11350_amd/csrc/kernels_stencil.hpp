@@ -57,8 +57,7 @@ __global__ void __launch_bounds__(NT) k_gradient_shape(ShapeCoef<T> C, Site2D<T>
         const int gx = x0 + tx, gy = y0 + ty;
         if (gx >= Q.na || gy >= Q.nb) continue;
         const int c = (ty + R) * W + (tx + R);
-        const V4<T> n4 = sN[c];
-        const V3<T> gv = shape_field_aos<T, S, NDMI, W>(C, Q, sN, c, V3<T>{n4.x, n4.y, n4.z});
+        const V3<T> gv = shape_field_aos<T, S, NDMI, W>(C, Q, sN, c, lds_cell_xyz(sN, c));
         const int gi = gx + gy * Q.na;
         g[gi] = gv.x;
         g[N + gi] = gv.y;
