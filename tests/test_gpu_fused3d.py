@@ -1,7 +1,8 @@
 """GPU parity of the streamed 3D fused step (compile-time simple-cubic
 stencils, one to three shells, DMI on the first shell) against the FP64
 oracle, for every tile configuration and integrator, ragged tiles, open and
-periodic axes, thin lattices, and the full 128^3 workload on sampled sites."""
+periodic axes, thin lattices, the full 128^3 workload, and the largest
+lattice the engine accepts (2^29 sites) on sampled sites."""
 
 import dataclasses
 
@@ -69,3 +70,55 @@ def test_fused3d_full_cubic128_thermal(ora):
     e.run(d.alpha, d.dt, 2, T=20.0, seed=d.seed)
     n_ora, _ = s.run(n0, d.alpha, d.dt, 2, T=20.0, seed=d.seed)
     assert_close(e.get_spins(), n_ora, "f32", what="cubic128 two thermal steps")
+
+
+def test_fused3d_max_size_lattice_follows_the_periodic_patch(ora):
+    """A 1024 x 1024 x 512 periodic simple-cubic lattice (exactly 2^29 sites,
+    the 128^3 workload's Hamiltonian, FP32) filled with a periodic tiling of a
+    random 16^3 patch.  At T = 0 the dynamics commute with lattice
+    translations, so after two steps on the streamed 3D path every sampled
+    site (the eight corners included) must hold the oracle's trajectory of the
+    16^3 periodic patch, and the energy per spin must be the patch's.  The
+    spins are built and read on the device."""
+    import torch
+
+    import paper_1901_11350_amd as pk
+
+    w = si.WORKLOADS["cubic128_bulkdmi"]
+    d = w.dynamics
+    P, BIG = 16, (1024, 1024, 512)
+    announce(f"fused3d max size {BIG}")
+    patch = si.uniform_sphere(P ** 3, 77)
+    s = ora.System(w.geometry.with_cells((P, P, P)), w.hamiltonian)
+    ref, _ = s.run(patch, d.alpha, d.dt, 2)            # T = 0
+    e = pk.Engine(0, "f32")
+    e.set_geometry(w.geometry.with_cells(BIG))
+    e.set_hamiltonian(w.hamiltonian)
+    assert e.N == 1 << 29
+    assert e.step_path.startswith("shape3d"), e.step_path
+    p = torch.tensor(patch.reshape(3, P, P, P), dtype=torch.float32, device="cuda")   # [3][c][b][a]
+    n = p.repeat(1, BIG[2] // P, BIG[1] // P, BIG[0] // P).reshape(3, -1).contiguous()
+    del p
+    torch.cuda.synchronize()
+    e.set_spins_dev(n)
+    e.step = 0
+    e.run(d.alpha, d.dt, 2)
+    e.get_spins_dev(n)
+    e.synchronize()
+    rng = np.random.default_rng(8)
+    xs = rng.integers(0, BIG[0], 8192)
+    ys = rng.integers(0, BIG[1], 8192)
+    zs = rng.integers(0, BIG[2], 8192)
+    for k in range(8):                                  # the eight corners
+        xs[k] = (BIG[0] - 1) * (k & 1)
+        ys[k] = (BIG[1] - 1) * ((k >> 1) & 1)
+        zs[k] = (BIG[2] - 1) * (k >> 2)
+    idx = torch.tensor(xs + BIG[0] * (ys + BIG[1] * zs), device="cuda")
+    got = n[:, idx].double().cpu().numpy()
+    want = ref[:, (xs % P) + P * ((ys % P) + P * (zs % P))]
+    assert_close(got, want, "f32", what="2^29-site 3D lattice")
+    E_big = e.energy() / e.N
+    E_patch = s.energy(ref) / P ** 3
+    assert E_big == pytest.approx(E_patch, rel=1e-5)
+    del n, e
+    torch.cuda.empty_cache()
