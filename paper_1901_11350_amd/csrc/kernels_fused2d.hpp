@@ -168,6 +168,16 @@ __device__ __forceinline__ V3<T> shape_field_soa(const ShapeCoef<T>& C, const Si
         C, Q, [&](int o) { return V3<T>{sx[o], sy[o], sz[o]}; }, c, ni);
 }
 
+// Store of a kernel's output spin or field.  An agent-scope store is written
+// through to the device coherence point instead of staying dirty in the
+// writing XCD's L2, so the L2 write-back that ends the kernel (it makes the
+// output visible to the next launch on every XCD) finds little to do.
+// Semantically a plain store: the kernel boundary orders it.
+template <typename T>
+__device__ __forceinline__ void store_out(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // One FP32 LDS cell read as a whole 16-byte ds_read_b128.  Left to itself
 // the compiler drops the unused padding word and emits ds_read_b96, which
 // on gfx950 costs ~8.7 LDS cycles per wave against ~4.9 for b128 (a wave of
@@ -409,9 +419,9 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
         if (gx >= Q.na || gy >= Q.nb) continue;
         const V3<T> o = correct_cell<T, S, NDMI, TX, TY, SOLVER>(C, Q, A, tx, ty, L, keepA[j], keepB[j]);
         const int gi = gx + gy * Q.na;
-        nout[gi] = o.x;
-        nout[N + gi] = o.y;
-        nout[2 * N + gi] = o.z;
+        store_out(nout + gi, o.x);
+        store_out(nout + N + gi, o.y);
+        store_out(nout + 2 * N + gi, o.z);
     }
 }
 

@@ -281,9 +281,9 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
                 o = renorm_if_float(rotate_fast(ni, w, A.dt));
             }
             const long long gi = gx + (long long)NA * gy + plane * zc;
-            nout[gi] = o.x;
-            nout[N + gi] = o.y;
-            nout[2 * N + gi] = o.z;
+            store_out(nout + gi, o.x);
+            store_out(nout + N + gi, o.y);
+            store_out(nout + 2 * N + gi, o.z);
         }
         keepA = aI;
         keepB = bI;

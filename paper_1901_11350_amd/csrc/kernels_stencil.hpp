@@ -59,9 +59,9 @@ __global__ void __launch_bounds__(NT) k_gradient_shape(ShapeCoef<T> C, Site2D<T>
         const int c = (ty + R) * W + (tx + R);
         const V3<T> gv = shape_field_aos<T, S, NDMI, W>(C, Q, sN, c, lds_cell_xyz(sN, c));
         const int gi = gx + gy * Q.na;
-        g[gi] = gv.x;
-        g[N + gi] = gv.y;
-        g[2 * N + gi] = gv.z;
+        store_out(g + gi, gv.x);
+        store_out(g + N + gi, gv.y);
+        store_out(g + 2 * N + gi, gv.z);
     }
 }
 
