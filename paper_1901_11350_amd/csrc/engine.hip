@@ -357,7 +357,48 @@ int launch_dipole(sp_engine* e, const void* n, void* gdd) {
 
 // --------------------------------------------------------------- observe
 template <typename T>
+sp::Site2D<T> make_site2d(const sp_engine* e, const sp_llg_params* p);
+template <typename T, int S>
+sp::ShapeCoef<T> shape_coef_for(const sp_engine* e);
+
+// Observables on the stencil path's tiles (64 x 16, four sites per thread):
+// one partial row per workgroup, at most partial_rows workgroups.  Returns
+// the number of rows.
+template <typename T, int S>
+int go_observe_shape(sp_engine* e, const void* n) {
+    constexpr int TX = 64, TY = 16, NT = 256;   // 1024 threads measured slower
+    sp::TileMap M{};
+    M.tiles_x = (e->geo.n[0] + TX - 1) / TX;
+    M.tiles_y = (e->geo.n[1] + TY - 1) / TY;
+    const int rows = std::min(M.tiles_x * M.tiles_y, e->partial_rows);
+    const sp::ShapeCoef<T> C = shape_coef_for<T, S>(e);
+    const sp::Site2D<T> Q = make_site2d<T>(e, nullptr);
+    if (e->shape_ndmi)
+        hipLaunchKernelGGL((sp::k_observe_shape<T, S, sp::ShapeTab<S>::NB0, TX, TY, NT>), dim3((unsigned)rows),
+                           dim3(NT), 0, e->stream, C, Q, M, static_cast<const T*>(n), e->d_partials);
+    else
+        hipLaunchKernelGGL((sp::k_observe_shape<T, S, 0, TX, TY, NT>), dim3((unsigned)rows), dim3(NT), 0, e->stream,
+                           C, Q, M, static_cast<const T*>(n), e->d_partials);
+    return rows;
+}
+
+template <typename T>
 int launch_observe(sp_engine* e, const void* n, double* out, long long step, bool with_flag) {
+    if (e->shape >= 0 && !e->ham.ddi && e->ham.n_gauss == 0) {
+        int rows;
+        switch (e->shape) {
+            case sp::SH_SQ1: rows = go_observe_shape<T, sp::SH_SQ1>(e, n); break;
+            case sp::SH_SQ2: rows = go_observe_shape<T, sp::SH_SQ2>(e, n); break;
+            case sp::SH_SQ3: rows = go_observe_shape<T, sp::SH_SQ3>(e, n); break;
+            case sp::SH_TRI1: rows = go_observe_shape<T, sp::SH_TRI1>(e, n); break;
+            case sp::SH_TRI2: rows = go_observe_shape<T, sp::SH_TRI2>(e, n); break;
+            default: rows = go_observe_shape<T, sp::SH_TRI3>(e, n); break;
+        }
+        hipLaunchKernelGGL(sp::k_observe_final, dim3(1), dim3(256), 0, e->stream, e->d_partials, rows, out,
+                           with_flag ? e->d_flag : nullptr, e->d_abort_step, step);
+        HIPCHK(e, hipGetLastError());
+        return SP_OK;
+    }
     const void* gdd = nullptr;
     if (e->ham.ddi) {
         int rc = launch_dipole<T>(e, n, e->d_gdd);

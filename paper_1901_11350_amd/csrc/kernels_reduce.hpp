@@ -33,9 +33,11 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Reduce acc[OBS_NVALS] across a 256-thread workgroup; thread 0 gets the result.
+// Reduce acc[OBS_NVALS] across a workgroup of NW wavefronts; thread 0 gets
+// the result.
+template <int NW = 4>
 __device__ __forceinline__ void block_reduce(double* acc) {
-    __shared__ double red[4][OBS_NVALS];
+    __shared__ double red[NW][OBS_NVALS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < OBS_NVALS; ++k) {
@@ -47,7 +49,7 @@ __device__ __forceinline__ void block_reduce(double* acc) {
 #pragma unroll
         for (int k = 0; k < OBS_NVALS; ++k) {
             double v = red[0][k];
-            for (int w = 1; w < 4; ++w) v = is_max_slot(k) ? fmax(v, red[w][k]) : v + red[w][k];
+            for (int w = 1; w < NW; ++w) v = is_max_slot(k) ? fmax(v, red[w][k]) : v + red[w][k];
             acc[k] = v;
         }
     }

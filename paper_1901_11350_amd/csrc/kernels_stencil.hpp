@@ -1,9 +1,10 @@
 // kernels_stencil.hpp -- the stand-alone stencil field kernel (sp_gradient on
 // one-atom 2D lattices with a compile-time stencil; the shapes and field
-// routine of kernels_fused2d.hpp).
+// routine of kernels_fused2d.hpp) and the observables on the same tiles.
 #pragma once
 
 #include "kernels_fused2d.hpp"
+#include "kernels_reduce.hpp"
 
 namespace sp {
 
@@ -62,6 +63,122 @@ __global__ void __launch_bounds__(NT) k_gradient_shape(ShapeCoef<T> C, Site2D<T>
         store_out(g + gi, gv.x);
         store_out(g + N + gi, gv.y);
         store_out(g + 2 * N + gi, gv.z);
+    }
+}
+
+// The four local terms of dH/dn at LDS cell c, kept apart for the energy
+// per term: the same sums as shape_field (Sec. III.A).
+template <typename T, int S, int NDMI, int W>
+__device__ __forceinline__ FieldTerms<T> shape_terms(const ShapeCoef<T>& C, const Site2D<T>& Q,
+                                                     const V4<T>* __restrict__ sv, int c, V3<T> ni) {
+    using SH = ShapeTab<S>;
+    V3<T> acc[SH::NS];
+#pragma unroll
+    for (int s = 0; s < SH::NS; ++s) acc[s] = V3<T>{T(0), T(0), T(0)};
+    V3<T> d{T(0), T(0), T(0)};   // sum of n_j x D over the DMI bonds, D = (Dx, Dy, 0)
+#pragma unroll
+    for (int q = 0; q < SH::NB; ++q) {
+        const V3<T> nj = lds_cell_xyz(sv, c + SH::da[q] + SH::db[q] * W);
+        acc[SH::sh[q]] = acc[SH::sh[q]] + nj;
+        if (q < NDMI) {
+            d.x -= nj.z * C.Dy[q];
+            d.y += nj.z * C.Dx[q];
+            d.z += nj.x * C.Dy[q] - nj.y * C.Dx[q];
+        }
+    }
+    FieldTerms<T> f;
+    f.z = V3<T>{Q.gZ[0], Q.gZ[1], Q.gZ[2]};
+    const V3<T> ax{Q.Kax[0], Q.Kax[1], Q.Kax[2]};
+    f.k = (-Q.K2 * dot(ax, ni)) * ax;
+    V3<T> j{T(0), T(0), T(0)};
+#pragma unroll
+    for (int s = 0; s < SH::NS; ++s) j = j - C.J[s] * acc[s];
+    f.j = j;
+    f.d = T(-1) * d;
+    f.q = V3<T>{T(0), T(0), T(0)};
+    return f;
+}
+
+// Stage 1 of the observables (kernels_reduce.hpp) on the tiles of the
+// stencil path: each workgroup stages TX x TY tiles plus an R halo in LDS, as
+// k_gradient_shape does, and folds the energy per term, torque, mean spin and
+// norm deviation of their sites into one row of partials.  Workgroups take
+// tiles blockIdx.x, blockIdx.x + gridDim.x, ...; k_observe_final reduces
+// the gridDim.x rows.  No dipole term and no on-site potentials on this
+// path.
+template <typename T, int S, int NDMI, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_observe_shape(ShapeCoef<T> C, Site2D<T> Q, TileMap M,
+                                                      const T* __restrict__ n, double* __restrict__ partials) {
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    constexpr int R = ShapeTab<S>::R, W = TX + 2 * R, H = TY + 2 * R, P = W * H, PT = TX * TY;
+    static_assert(PT % NT == 0, "tile sites must divide evenly over the threads");
+    constexpr int KPT = PT / NT, KST = (P + NT - 1) / NT;
+    __shared__ V4<T> sN[P];
+    const int ntiles = M.tiles_x * M.tiles_y;
+    const int N = Q.na * Q.nb;
+    const int tid = threadIdx.x;
+    double acc[OBS_NVALS];
+#pragma unroll
+    for (int k = 0; k < OBS_NVALS; ++k) acc[k] = 0.0;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tyi = tile / M.tiles_x;
+        const int x0 = (tile - tyi * M.tiles_x) * TX, y0 = tyi * TY;
+        V4<T> st[KST];
+#pragma unroll
+        for (int k = 0; k < KST; ++k) {
+            const int idx = tid + k * NT;
+            st[k] = V4<T>{T(0), T(0), T(0), T(0)};
+            if (idx < P) {
+                const int ly = idx / W, lx = idx - ly * W;
+                bool in = true;
+                const int gx = wrap_once(x0 - R + lx, Q.na, Q.per_a, in);
+                const int gy = wrap_once(y0 - R + ly, Q.nb, Q.per_b, in);
+                if (in) {
+                    const int q = gx + gy * Q.na;
+                    st[k] = V4<T>{n[q], n[N + q], n[2 * N + q], T(0)};
+                }
+            }
+        }
+        __syncthreads();   // the previous tile's cells are no longer read
+#pragma unroll
+        for (int k = 0; k < KST; ++k) {
+            const int idx = tid + k * NT;
+            if (idx < P) sN[idx] = st[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+            const int t = tid + j * NT;
+            const int ty = t / TX, tx = t - ty * TX;
+            if (x0 + tx >= Q.na || y0 + ty >= Q.nb) continue;
+            const int c = (ty + R) * W + (tx + R);
+            const V3<T> ni = lds_cell_xyz(sN, c);
+            const FieldTerms<T> f = shape_terms<T, S, NDMI, W>(C, Q, sN, c, ni);
+            const V3<T> g = f.z + f.k + f.j + f.d;
+            const double nx = ni.x, ny = ni.y, nz = ni.z;
+            acc[OBS_EZ] += nx * f.z.x + ny * f.z.y + nz * f.z.z;
+            acc[OBS_EK] += 0.5 * (nx * f.k.x + ny * f.k.y + nz * f.k.z);
+            acc[OBS_EJ] += 0.5 * (nx * f.j.x + ny * f.j.y + nz * f.j.z);
+            acc[OBS_ED] += 0.5 * (nx * f.d.x + ny * f.d.y + nz * f.d.z);
+            const double tx_ = ny * g.z - nz * g.y, ty_ = nz * g.x - nx * g.z, tz_ = nx * g.y - ny * g.x;
+            const double t2 = tx_ * tx_ + ty_ * ty_ + tz_ * tz_;
+            if (!isfinite(t2)) {
+                acc[OBS_NONFINITE] += 1.0;
+            } else {
+                acc[OBS_TMAX] = fmax(acc[OBS_TMAX], sqrt(t2));
+                acc[OBS_T2] += t2;
+            }
+            acc[OBS_MX] += nx;
+            acc[OBS_MY] += ny;
+            acc[OBS_MZ] += nz;
+            const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+            acc[OBS_NDEV] = fmax(acc[OBS_NDEV], fabs(nn - 1.0));
+        }
+    }
+    block_reduce<NT / 64>(acc);
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < OBS_NVALS; ++k) partials[blockIdx.x * OBS_NVALS + k] = acc[k];
     }
 }
 

@@ -92,6 +92,45 @@ def test_energy_parity(ora, case, precision):
     assert np.allclose(obs["M"], oo["M"], atol=10 * tol)
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("dims", [(200, 70), (2048, 1024)])
+def test_observation_on_stencil_tiles_matches_oracle(ora, dims, precision):
+    """Energy per term, largest torque, mean spin and norm deviation formed on
+    the stencil path's tiles: 4 x 5 tiles with ragged edges, and 2,048 tiles
+    (more than the partial rows, so each workgroup folds several tiles)
+    against the oracle, and against the generic observation kernel of the
+    same lattice with its bonds given as explicit pairs."""
+    announce(f"observation on tiles {dims} {precision}")
+    w = W["triangular512_sllg"]
+    geo = w.geometry.with_cells((dims[0], dims[1], 1))
+    e, s = make_pair(ora, geo, w.hamiltonian, precision)
+    assert e.step_path.startswith("shape2d")
+    n = si.uniform_sphere(s.N, 29)
+    e.set_spins(n)
+    obs = e.observe()
+    oo = s.observe(n)
+    tol = TOL[precision]
+    scale = np.abs(oo["per_term"]).sum()
+    assert np.abs(np.array(obs["per_term"]) - np.array(oo["per_term"])).max() <= tol * scale
+    assert obs["E"] == pytest.approx(oo["E"], rel=tol, abs=tol * scale)
+    assert obs["max_torque"] == pytest.approx(oo["max_torque"], rel=10 * tol)
+    assert np.allclose(obs["M"], oo["M"], atol=10 * tol)
+    if precision == "f64":
+        assert obs["max_norm_dev"] == pytest.approx(oo["max_norm_dev"], abs=1e-14)
+    else:
+        assert obs["max_norm_dev"] < 1e-6
+    table = {(b[0], b[1], b[2], b[3], b[4]): b for b in s.bonds()}
+    pairs = [(b[0], b[1], (b[2], b[3], b[4]), b[6], b[7]) for k, b in table.items()
+             if k < (b[1], b[0], -b[2], -b[3], -b[4])]
+    g, _ = make_pair(ora, geo, dataclasses.replace(w.hamiltonian, J=(), D=()), precision)
+    g.set_pairs(pairs)
+    assert g.step_path == "fused2d"
+    g.set_spins(n)
+    og = g.observe()
+    assert np.abs(np.array(obs["per_term"]) - np.array(og["per_term"])).max() <= 2 * tol * scale
+    assert obs["max_torque"] == pytest.approx(og["max_torque"], rel=10 * tol)
+
+
 def _step_case(ora, case, precision, T, steps, path=None, seed=99, alpha=0.3, dt=0.001):
     geo, ham = CASES[case]
     e, s = make_pair(ora, geo, ham, precision)
