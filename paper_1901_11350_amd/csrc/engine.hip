@@ -2398,17 +2398,51 @@ int gfail(sp_gneb* G, int code, const std::string& msg) {
     return code;
 }
 
+// Images on the stencil path whose sides divide into the 64 x 4 tiles of
+// k_gneb_grad_shape (then tiles and site blocks coincide in number).
+bool gneb_tiles(const sp_gneb* G) {
+    const sp_engine* e = G->e;
+    return e->shape >= 0 && !e->ham.ddi && e->ham.n_gauss == 0 && e->geo.n[0] % 64 == 0 && e->geo.n[1] % 4 == 0 &&
+           (long long)(e->geo.n[0] / 64) * (e->geo.n[1] / 4) == G->nblk;
+}
+
+template <typename T, int S>
+void gneb_grad_shape(sp_gneb* G, hipStream_t st) {
+    sp_engine* e = G->e;
+    const sp::GnebDims d{G->M, G->N, G->nblk};
+    const sp::ShapeCoef<double> C = shape_coef_for<double, S>(e);
+    const sp::Site2D<double> Q = make_site2d<double>(e, nullptr);
+    const int tiles_x = e->geo.n[0] / 64;
+    const T* x = static_cast<const T*>(G->x);
+    T* g = static_cast<T*>(G->g);
+    const dim3 grid((unsigned)G->nblk, (unsigned)G->M);
+    if (e->shape_ndmi)
+        hipLaunchKernelGGL((sp::k_gneb_grad_shape<T, S, sp::ShapeTab<S>::NB0>), grid, dim3(256), 0, st, d, C, Q,
+                           tiles_x, x, g, G->epart);
+    else
+        hipLaunchKernelGGL((sp::k_gneb_grad_shape<T, S, 0>), grid, dim3(256), 0, st, d, C, Q, tiles_x, x, g, G->epart);
+}
+
 template <typename T>
 int gneb_forces(sp_gneb* G, bool update_v, hipStream_t st) {
     sp_engine* e = G->e;
     const sp::GnebDims d{G->M, G->N, G->nblk};
-    const sp::Lattice L = make_lattice(e);
-    const sp::BondCoef<double> C = make_coef64(e);
-    const sp::Phys<double> P = make_phys<double>(e, nullptr);
     T* x = static_cast<T*>(G->x);
     T* g = static_cast<T*>(G->g);
     T* tau = static_cast<T*>(G->tau);
-    hipLaunchKernelGGL((sp::k_gneb_grad<T>), dim3(G->nblk, G->M), dim3(256), 0, st, d, L, C, P, x, g, G->epart);
+    if (gneb_tiles(G)) {
+        switch (e->shape) {
+            case sp::SH_SQ1: gneb_grad_shape<T, sp::SH_SQ1>(G, st); break;
+            case sp::SH_SQ2: gneb_grad_shape<T, sp::SH_SQ2>(G, st); break;
+            case sp::SH_SQ3: gneb_grad_shape<T, sp::SH_SQ3>(G, st); break;
+            case sp::SH_TRI1: gneb_grad_shape<T, sp::SH_TRI1>(G, st); break;
+            case sp::SH_TRI2: gneb_grad_shape<T, sp::SH_TRI2>(G, st); break;
+            default: gneb_grad_shape<T, sp::SH_TRI3>(G, st); break;
+        }
+    } else {
+        hipLaunchKernelGGL((sp::k_gneb_grad<T>), dim3(G->nblk, G->M), dim3(256), 0, st, d, make_lattice(e),
+                           make_coef64(e), make_phys<double>(e, nullptr), x, g, G->epart);
+    }
     hipLaunchKernelGGL((sp::k_gneb_tangent<T>), dim3(G->nblk, G->M), dim3(256), 0, st, d, x, g, G->epart, G->E, tau,
                        G->tpart);
     hipLaunchKernelGGL((sp::k_gneb_force<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, st, d, (T)G->k,

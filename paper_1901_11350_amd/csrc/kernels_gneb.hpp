@@ -8,6 +8,7 @@
 //                     if v.F > 0 else 0, F_prev <- F]  then
 //                     x <- normalise(x + dt v + dt^2/(2m) F_prev)    (interior)
 //   k_gneb_grad       g = dH/dn per image, energy partials per block
+//                     (k_gneb_grad_shape on the stencil path's tiles)
 //   k_gneb_tangent    E of the image and its neighbours from the partials;
 //                     improved tangent, per-spin projection; partials of
 //                     |tau|^2, g.tau, and squared geodesic angles to image v+1
@@ -25,6 +26,7 @@
 
 #include "kernels_field.hpp"
 #include "kernels_reduce.hpp"
+#include "kernels_stencil.hpp"
 
 namespace sp {
 
@@ -132,6 +134,59 @@ __global__ void __launch_bounds__(256) k_gneb_grad(GnebDims d, Lattice L, BondCo
     }
     block_sums<1>(acc);
     if (threadIdx.x == 0) part[(size_t)im * d.nblk + blockIdx.x] = acc[0];
+}
+
+// The same gradient and energy partials on the stencil path's tiles, for
+// one-atom 2D images with a compile-time stencil whose sides divide into
+// 64 x 4 tiles: tile t of an image (256 sites, one per thread) is partial t
+// of its row, as block t is in k_gneb_grad.  The image is staged in LDS with
+// an R halo as FP64 cells; the terms are those of shape_terms, in FP64 from
+// the stored spins.
+template <typename T, int S, int NDMI>
+__global__ void __launch_bounds__(256) k_gneb_grad_shape(GnebDims d, ShapeCoef<double> C, Site2D<double> Q,
+                                                         int tiles_x, const T* __restrict__ x, T* __restrict__ g,
+                                                         double* __restrict__ part) {
+    constexpr int TX = 64, TY = 4, NT = 256;
+    constexpr int R = ShapeTab<S>::R, W = TX + 2 * R, H = TY + 2 * R, P = W * H, KST = (P + NT - 1) / NT;
+    __shared__ V4<double> sN[P];
+    const int im = blockIdx.y, tile = blockIdx.x;
+    const int tyi = tile / tiles_x;
+    const int x0 = (tile - tyi * tiles_x) * TX, y0 = tyi * TY;
+    const int N = d.N, tid = threadIdx.x;
+    const T* xi = x + (size_t)im * 3 * N;
+    V4<double> st[KST];
+#pragma unroll
+    for (int k = 0; k < KST; ++k) {
+        const int idx = tid + k * NT;
+        st[k] = V4<double>{0.0, 0.0, 0.0, 0.0};
+        if (idx < P) {
+            const int ly = idx / W, lx = idx - ly * W;
+            bool in = true;
+            const int gx = wrap_once(x0 - R + lx, Q.na, Q.per_a, in);
+            const int gy = wrap_once(y0 - R + ly, Q.nb, Q.per_b, in);
+            if (in) {
+                const int q = gx + gy * Q.na;
+                st[k] = V4<double>{(double)xi[q], (double)xi[N + q], (double)xi[2 * N + q], 0.0};
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KST; ++k) {
+        const int idx = tid + k * NT;
+        if (idx < P) sN[idx] = st[k];
+    }
+    __syncthreads();
+    const int ty = tid / TX, tx = tid - ty * TX;
+    const int c = (ty + R) * W + (tx + R);
+    const V3<double> ni = lds_cell_xyz(sN, c);
+    const FieldTerms<double> f = shape_terms<double, S, NDMI, W>(C, Q, sN, c, ni);
+    const V3<double> gt = f.z + f.k + f.j + f.d;
+    store3(g + (size_t)im * 3 * N, N, (x0 + tx) + (y0 + ty) * Q.na, V3<T>{(T)gt.x, (T)gt.y, (T)gt.z});
+    double acc[1] = {ni.x * f.z.x + ni.y * f.z.y + ni.z * f.z.z +
+                     0.5 * (ni.x * (f.k.x + f.j.x + f.d.x) + ni.y * (f.k.y + f.j.y + f.d.y) +
+                            ni.z * (f.k.z + f.j.z + f.d.z))};
+    block_sums<1>(acc);
+    if (tid == 0) part[(size_t)im * d.nblk + tile] = acc[0];
 }
 
 // Sum NV-value partials of each of `rows` rows (blocks per row = nblk) in a

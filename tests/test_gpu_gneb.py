@@ -70,11 +70,18 @@ def _case(name):
     if name == "square12x10":
         geo = si.square(12, 10)
         return geo, HAM0, _skyrmion_chain(geo, 8, 3.0), dict(k_spring=1.0, vp_dt=0.1, vp_mass=1.0)
+    if name == "tri128x16_tiles":
+        # sides divide into the 64 x 4 tiles of the stencil-path gradient:
+        # three shells with interfacial DMI on the triangular stencil
+        geo = si.triangular(128, 16)
+        return (geo, si.WORKLOADS["triangular512_sllg"].hamiltonian, _skyrmion_chain(geo, 8, 3.0),
+                dict(k_spring=1.0, vp_dt=0.1, vp_mass=1.0))
     geo = si.square(128, 128)
     return geo, HAM0, _skyrmion_chain(geo, 32, 5.0), dict(k_spring=1.0, vp_dt=0.1, vp_mass=1.0)
 
 
-@pytest.mark.parametrize("case,iters", [("single_spin", 60), ("square12x10", 40), ("chain32x128x128", 20)])
+@pytest.mark.parametrize("case,iters", [("single_spin", 60), ("square12x10", 40), ("chain32x128x128", 20),
+                                        ("tri128x16_tiles", 20)])
 def test_gneb_fp64_iterations_match_oracle(ora, case, iters):
     announce(f"gneb fp64 {case}")
     geo, ham, chain, kw = _case(case)
@@ -100,7 +107,7 @@ def test_gneb_fp64_iterations_match_oracle(ora, case, iters):
     assert dF <= 100 * tol, f"forces: difference {dF:.3e} of the initial force norm"
 
 
-@pytest.mark.parametrize("case", ["single_spin", "square12x10", "chain32x128x128"])
+@pytest.mark.parametrize("case", ["single_spin", "square12x10", "chain32x128x128", "tri128x16_tiles"])
 def test_gneb_fp32_first_iterations_match_oracle(ora, case):
     announce(f"gneb fp32 first iterations {case}")
     geo, ham, chain, kw = _case(case)
