@@ -1949,6 +1949,7 @@ struct sp_batch {
     int cfg = 0;
     int chunk = 32;
     hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec_chain = nullptr;     // an attached chain's chunk, launched beside gexec
     int g_parity = -1, g_cfg = -1, g_chunk = -1;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     sp_gneb* gneb = nullptr;                   // attached GNEB chain (FP32), advanced by every run
@@ -1975,6 +1976,14 @@ int bfail(sp_batch* b, int code, const std::string& msg) {
 
 bool same_ham(const HostHam& a, const HostHam& b) {
     return std::memcmp(&a, &b, sizeof(HostHam)) == 0;
+}
+
+// Drop the captured chunk graphs (they no longer match the batch).
+void batch_drop_graphs(sp_batch* b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->gexec_chain) (void)hipGraphExecDestroy(b->gexec_chain);
+    b->gexec = nullptr;
+    b->gexec_chain = nullptr;
 }
 
 int batch_build_work(sp_batch* b) {
@@ -2031,10 +2040,7 @@ int batch_build_work(sp_batch* b) {
     b->n_work = (int)work.size();
     b->n_res32 = (int)r32.size();
     b->n_res64 = (int)r64.size();
-    if (b->gexec) {
-        (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-    }
+    batch_drop_graphs(b);
     return SP_OK;
 }
 
@@ -2086,14 +2092,16 @@ void batch_launch_tiled(sp_batch* b, hipStream_t s, int k, int parity) {
 }
 
 template <int S>
-void batch_chunk_shape(sp_batch* b, int n_steps, int parity) {
+void batch_chunk_shape(sp_batch* b, int n_steps, int parity, bool with_chain) {
     // resident replicas on the side stream, tiled steps on the main stream
     (void)hipEventRecord(b->ev_fork, b->stream);
     (void)hipStreamWaitEvent(b->side, b->ev_fork, 0);
     if (b->shape_ndmi) batch_launch_resident<S, sp::ShapeTab<S>::NB0>(b, b->side, n_steps);
     else batch_launch_resident<S, 0>(b, b->side, n_steps);
-    // an attached GNEB chain: n_steps iterations on a third branch
-    if (b->gneb) {
+    // an attached GNEB chain: n_steps iterations on a third branch (unless
+    // the caller launches the chain's own graph beside this chunk's)
+    const bool chain = with_chain && b->gneb;
+    if (chain) {
         (void)hipEventRecord(b->ev_gfork, b->stream);
         (void)hipStreamWaitEvent(b->gside, b->ev_gfork, 0);
         (void)gneb_enqueue<float>(b->gneb, n_steps, b->gside);
@@ -2104,7 +2112,7 @@ void batch_chunk_shape(sp_batch* b, int n_steps, int parity) {
     }
     (void)hipEventRecord(b->ev_join, b->side);
     (void)hipStreamWaitEvent(b->stream, b->ev_join, 0);
-    if (b->gneb) {
+    if (chain) {
         (void)hipEventRecord(b->ev_gjoin, b->gside);
         (void)hipStreamWaitEvent(b->stream, b->ev_gjoin, 0);
     }
@@ -2112,30 +2120,42 @@ void batch_chunk_shape(sp_batch* b, int n_steps, int parity) {
 }
 
 // Enqueue one chunk of n_steps on b->stream (also used under graph capture).
-void batch_chunk(sp_batch* b, int n_steps, int parity) {
+void batch_chunk(sp_batch* b, int n_steps, int parity, bool with_chain = true) {
     switch (b->shape) {
-        case sp::SH_SQ1: batch_chunk_shape<sp::SH_SQ1>(b, n_steps, parity); break;
-        case sp::SH_SQ2: batch_chunk_shape<sp::SH_SQ2>(b, n_steps, parity); break;
-        case sp::SH_SQ3: batch_chunk_shape<sp::SH_SQ3>(b, n_steps, parity); break;
-        case sp::SH_TRI1: batch_chunk_shape<sp::SH_TRI1>(b, n_steps, parity); break;
-        case sp::SH_TRI2: batch_chunk_shape<sp::SH_TRI2>(b, n_steps, parity); break;
-        default: batch_chunk_shape<sp::SH_TRI3>(b, n_steps, parity); break;
+        case sp::SH_SQ1: batch_chunk_shape<sp::SH_SQ1>(b, n_steps, parity, with_chain); break;
+        case sp::SH_SQ2: batch_chunk_shape<sp::SH_SQ2>(b, n_steps, parity, with_chain); break;
+        case sp::SH_SQ3: batch_chunk_shape<sp::SH_SQ3>(b, n_steps, parity, with_chain); break;
+        case sp::SH_TRI1: batch_chunk_shape<sp::SH_TRI1>(b, n_steps, parity, with_chain); break;
+        case sp::SH_TRI2: batch_chunk_shape<sp::SH_TRI2>(b, n_steps, parity, with_chain); break;
+        default: batch_chunk_shape<sp::SH_TRI3>(b, n_steps, parity, with_chain); break;
     }
 }
 
+// The chunk as graphs: the replicas' (resident and tiled branches, then the
+// step counter), and an attached chain's chunk of iterations as a graph of
+// its own.  Launched on two streams, the chain's graph runs beside the
+// replicas'; branches inside one graph were measured to run one after the
+// other.
 int batch_capture(sp_batch* b) {
-    if (b->gexec) {
-        (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-    }
+    batch_drop_graphs(b);
     hipGraph_t g = nullptr;
     BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    batch_chunk(b, b->chunk, b->parity);
+    batch_chunk(b, b->chunk, b->parity, false);
     hipError_t s = hipStreamEndCapture(b->stream, &g);
     if (s != hipSuccess) return bfail(b, SP_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(s));
     s = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (s != hipSuccess) return bfail(b, SP_E_HIP, std::string("graph instantiation failed: ") + hipGetErrorString(s));
+    if (b->gneb) {
+        BHIPCHK(b, hipStreamBeginCapture(b->gside, hipStreamCaptureModeThreadLocal));
+        (void)gneb_enqueue<float>(b->gneb, b->chunk, b->gside);
+        s = hipStreamEndCapture(b->gside, &g);
+        if (s != hipSuccess) return bfail(b, SP_E_HIP, std::string("chain graph capture failed: ") + hipGetErrorString(s));
+        s = hipGraphInstantiate(&b->gexec_chain, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (s != hipSuccess)
+            return bfail(b, SP_E_HIP, std::string("chain graph instantiation failed: ") + hipGetErrorString(s));
+    }
     b->g_parity = b->parity;
     b->g_cfg = b->cfg;
     b->g_chunk = b->chunk;
@@ -2145,11 +2165,21 @@ int batch_capture(sp_batch* b) {
 int batch_advance(sp_batch* b, int64_t n_steps, bool use_graph) {
     int64_t left = n_steps;
     while (use_graph && left >= b->chunk) {
-        if (!b->gexec || b->g_parity != b->parity || b->g_cfg != b->cfg || b->g_chunk != b->chunk) {
+        if (!b->gexec || b->g_parity != b->parity || b->g_cfg != b->cfg || b->g_chunk != b->chunk ||
+            (b->gneb != nullptr) != (b->gexec_chain != nullptr)) {
             int rc = batch_capture(b);
             if (rc) return rc;
         }
+        if (b->gexec_chain) {   // the chain's chunk beside the replicas', joined before the next chunk
+            BHIPCHK(b, hipEventRecord(b->ev_gfork, b->stream));
+            BHIPCHK(b, hipStreamWaitEvent(b->gside, b->ev_gfork, 0));
+            BHIPCHK(b, hipGraphLaunch(b->gexec_chain, b->gside));
+        }
         BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
+        if (b->gexec_chain) {
+            BHIPCHK(b, hipEventRecord(b->ev_gjoin, b->gside));
+            BHIPCHK(b, hipStreamWaitEvent(b->stream, b->ev_gjoin, 0));
+        }
         left -= b->chunk;
     }
     while (left > 0) {
@@ -2197,7 +2227,7 @@ void sp_batch_destroy(sp_batch* b) {
     if (!b) return;
     (void)hipSetDevice(b->device);
     (void)hipDeviceSynchronize();   // the main stream may be borrowed and already gone
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    batch_drop_graphs(b);
     void* p = b->arena; dfree(p);
     p = b->d_reps; dfree(p);
     p = b->d_work; dfree(p);
@@ -2276,10 +2306,7 @@ int sp_batch_add_gneb(sp_batch* b, sp_gneb* G) {
     // the chain's own pending work ends before the batch takes it over
     BHIPCHK(b, hipStreamSynchronize(G->e->stream));
     BHIPCHK(b, hipStreamSynchronize(b->stream));
-    if (b->gexec) {   // the captured chunk no longer matches
-        (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-    }
+    batch_drop_graphs(b);   // the captured chunk no longer matches
     b->gneb = G;
     G->batch = b;
     return SP_OK;
@@ -2602,10 +2629,7 @@ void sp_gneb_destroy(sp_gneb* G) {
     if (G->batch) {   // detach: the batch's captured chunk launches this chain's kernels
         sp_batch* b = G->batch;
         b->gneb = nullptr;
-        if (b->gexec) {
-            (void)hipGraphExecDestroy(b->gexec);
-            b->gexec = nullptr;
-        }
+        batch_drop_graphs(b);
     }
     gneb_free(G);
     delete G;
