@@ -218,8 +218,8 @@ def bench_batch(args) -> dict:
     ms_gneb = ev0.elapsed_time(ev1) / args.gneb_iters
     gneb = {"images": 32, "spins_per_image": geo.n_sites, "ms_per_iteration": ms_gneb,
             "image_spin_updates_per_s": 32 * geo.n_sites / (ms_gneb * 1e-3)}
-    # the chain attached to the batch: one VP iteration per batch step, on a
-    # branch of the same chunk graph as the replicas
+    # the chain attached to the batch: one VP iteration per batch step, its
+    # chunk graph launched beside the replicas' on the batch's side stream
     b.add_gneb(g)
     b.run(args.batch_chunk)
     torch.cuda.synchronize()
@@ -230,7 +230,7 @@ def bench_batch(args) -> dict:
     ms_both = ev0.elapsed_time(ev1)
     gneb["in_batch"] = {"ms_per_step": ms_both / K,
                         "updates_per_s": (total + 32 * geo.n_sites) * K / (ms_both * 1e-3),
-                        "note": "replica spin-updates + chain image-spin updates per second, one graph"}
+                        "note": "replica spin-updates + chain image-spin updates per second; the chain's graph runs beside the replicas' graph"}
     return {"workload": "batch96_square", "replicas": len(table), "resident_replicas": n_res, "gneb": gneb,
             "total_spins": total, "steps": K, "chunk": args.batch_chunk,
             "spin_updates_per_s": total * K / (ms * 1e-3), "ms_per_step": ms / K,
