@@ -360,6 +360,8 @@ template <typename T>
 sp::Site2D<T> make_site2d(const sp_engine* e, const sp_llg_params* p);
 template <typename T, int S>
 sp::ShapeCoef<T> shape_coef_for(const sp_engine* e);
+template <typename T, int S>
+sp::ShapeCoef3<T> shape_coef3_for(const sp_engine* e);
 
 // Observables on the stencil path's tiles (64 x 16, four sites per thread):
 // one partial row per workgroup, at most partial_rows workgroups.  Returns
@@ -382,8 +384,40 @@ int go_observe_shape(sp_engine* e, const void* n) {
     return rows;
 }
 
+// The same on the streamed 3D path's lattices: 32 x 8 tiles of one plane
+// (with the planes either side) per work item.
+template <typename T, int S>
+int go_observe_shape3(sp_engine* e, const void* n) {
+    constexpr int TX = 32, TY = 8;
+    const int tiles_x = (e->geo.n[0] + TX - 1) / TX, tiles_y = (e->geo.n[1] + TY - 1) / TY;
+    const long long items = (long long)tiles_x * tiles_y * e->geo.n[2];
+    const int rows = (int)std::min<long long>(items, e->partial_rows);
+    const sp::ShapeCoef3<T> C = shape_coef3_for<T, S>(e);
+    const sp::Site2D<T> Q = make_site2d<T>(e, nullptr);
+    if (e->shape3_ndmi)
+        hipLaunchKernelGGL((sp::k_observe_shape3<T, S, sp::ShapeTab3<S>::NB0, TX, TY>), dim3((unsigned)rows),
+                           dim3(TX * TY), 0, e->stream, C, Q, e->geo.n[2], e->geo.per[2], tiles_x, tiles_y,
+                           static_cast<const T*>(n), e->d_partials);
+    else
+        hipLaunchKernelGGL((sp::k_observe_shape3<T, S, 0, TX, TY>), dim3((unsigned)rows), dim3(TX * TY), 0, e->stream,
+                           C, Q, e->geo.n[2], e->geo.per[2], tiles_x, tiles_y, static_cast<const T*>(n), e->d_partials);
+    return rows;
+}
+
 template <typename T>
 int launch_observe(sp_engine* e, const void* n, double* out, long long step, bool with_flag) {
+    if (e->shape3 >= 0 && !e->ham.ddi && e->ham.n_gauss == 0) {
+        int rows;
+        switch (e->shape3) {
+            case sp::SH3_SC1: rows = go_observe_shape3<T, sp::SH3_SC1>(e, n); break;
+            case sp::SH3_SC2: rows = go_observe_shape3<T, sp::SH3_SC2>(e, n); break;
+            default: rows = go_observe_shape3<T, sp::SH3_SC3>(e, n); break;
+        }
+        hipLaunchKernelGGL(sp::k_observe_final, dim3(1), dim3(256), 0, e->stream, e->d_partials, rows, out,
+                           with_flag ? e->d_flag : nullptr, e->d_abort_step, step);
+        HIPCHK(e, hipGetLastError());
+        return SP_OK;
+    }
     if (e->shape >= 0 && !e->ham.ddi && e->ham.n_gauss == 0) {
         int rows;
         switch (e->shape) {

@@ -16,6 +16,7 @@
 #pragma once
 
 #include "kernels_fused2d.hpp"
+#include "kernels_reduce.hpp"
 
 namespace sp {
 
@@ -287,6 +288,125 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
         }
         keepA = aI;
         keepB = bI;
+    }
+}
+
+// The four local terms of dH/dn of a site whose own plane sits in slot 1 of
+// `planes` (slots 0 and 2: planes c - 1 and c + 1) at LDS cell c (pitch W),
+// kept apart for the energy per term: the sums of shape_field3 (Sec. III.A).
+template <typename T, int S, int NDMI, int W, int PL>
+__device__ __forceinline__ FieldTerms<T> shape_terms3(const ShapeCoef3<T>& C, const Site2D<T>& Q,
+                                                      const V4<T> (*planes)[PL], int c, V3<T> ni) {
+    using SH = ShapeTab3<S>;
+    V3<T> acc[SH::NS];
+#pragma unroll
+    for (int s = 0; s < SH::NS; ++s) acc[s] = V3<T>{T(0), T(0), T(0)};
+    V3<T> dm{T(0), T(0), T(0)};   // sum of n_j x D over the DMI bonds
+#pragma unroll
+    for (int q = 0; q < SH::NB; ++q) {
+        const V3<T> v = lds_cell_xyz(planes[1 + SH::dc[q]], c + SH::da[q] + SH::db[q] * W);
+        acc[SH::sh[q]] = acc[SH::sh[q]] + v;
+        if (q < NDMI) {
+            dm.x += v.y * C.Dz[q] - v.z * C.Dy[q];
+            dm.y += v.z * C.Dx[q] - v.x * C.Dz[q];
+            dm.z += v.x * C.Dy[q] - v.y * C.Dx[q];
+        }
+    }
+    FieldTerms<T> f;
+    f.z = V3<T>{Q.gZ[0], Q.gZ[1], Q.gZ[2]};
+    const V3<T> ax{Q.Kax[0], Q.Kax[1], Q.Kax[2]};
+    f.k = (-Q.K2 * dot(ax, ni)) * ax;
+    V3<T> j{T(0), T(0), T(0)};
+#pragma unroll
+    for (int s = 0; s < SH::NS; ++s) j = j - C.J[s] * acc[s];
+    f.j = j;
+    f.d = T(-1) * dm;
+    f.q = V3<T>{T(0), T(0), T(0)};
+    return f;
+}
+
+// Stage 1 of the observables (kernels_reduce.hpp) for one-atom simple-cubic
+// lattices with a compile-time stencil: a work item is a TX x TY tile of one
+// plane c, staged with planes c - 1 and c + 1 and a one-cell halo in LDS;
+// workgroups take items blockIdx.x, blockIdx.x + gridDim.x, ... and fold the
+// energy per term, torque, mean spin and norm deviation of their sites into
+// one row of partials.  No dipole term and no on-site potentials on this
+// path.
+template <typename T, int S, int NDMI, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k_observe_shape3(ShapeCoef3<T> C, Site2D<T> Q, int nc, int per_c,
+                                                             int tiles_x, int tiles_y, const T* __restrict__ n,
+                                                             double* __restrict__ partials) {
+    constexpr int NT = TX * TY;
+    static_assert(ShapeTab3<S>::R == 1, "one-cell halo");
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    constexpr int W = TX + 2, H = TY + 2, P = W * H, KST = (3 * P + NT - 1) / NT;
+    __shared__ V4<T> sN[3][P];
+    const int ntiles = tiles_x * tiles_y;
+    const long long items = (long long)ntiles * nc;
+    const long long plane = (long long)Q.na * Q.nb;
+    const long long N = plane * nc;
+    const int tid = threadIdx.x;
+    const int ty = tid / TX, tx = tid - ty * TX;
+    double acc[OBS_NVALS];
+#pragma unroll
+    for (int k = 0; k < OBS_NVALS; ++k) acc[k] = 0.0;
+    for (long long w = blockIdx.x; w < items; w += gridDim.x) {
+        const int z = (int)(w / ntiles), tile = (int)(w - (long long)z * ntiles);
+        const int tyi = tile / tiles_x;
+        const int x0 = (tile - tyi * tiles_x) * TX, y0 = tyi * TY;
+        V4<T> st[KST];
+#pragma unroll
+        for (int k = 0; k < KST; ++k) {
+            const int idx = tid + k * NT;
+            st[k] = V4<T>{T(0), T(0), T(0), T(0)};
+            if (idx < 3 * P) {
+                const int s = idx / P, r = idx - s * P;
+                const int ly = r / W, lx = r - ly * W;
+                bool in = true;
+                const int gz = wrap_plane(z - 1 + s, nc, per_c, in);
+                const int gx = wrap_once(x0 - 1 + lx, Q.na, Q.per_a, in);
+                const int gy = wrap_once(y0 - 1 + ly, Q.nb, Q.per_b, in);
+                if (in) {
+                    const long long q = gx + (long long)Q.na * gy + plane * gz;
+                    st[k] = V4<T>{n[q], n[N + q], n[2 * N + q], T(0)};
+                }
+            }
+        }
+        __syncthreads();   // the previous item's cells are no longer read
+#pragma unroll
+        for (int k = 0; k < KST; ++k) {
+            const int idx = tid + k * NT;
+            if (idx < 3 * P) sN[idx / P][idx % P] = st[k];
+        }
+        __syncthreads();
+        if (x0 + tx >= Q.na || y0 + ty >= Q.nb) continue;
+        const int c = (ty + 1) * W + (tx + 1);
+        const V3<T> ni = lds_cell_xyz(sN[1], c);
+        const FieldTerms<T> f = shape_terms3<T, S, NDMI, W, P>(C, Q, sN, c, ni);
+        const V3<T> g = f.z + f.k + f.j + f.d;
+        const double nx = ni.x, ny = ni.y, nz = ni.z;
+        acc[OBS_EZ] += nx * f.z.x + ny * f.z.y + nz * f.z.z;
+        acc[OBS_EK] += 0.5 * (nx * f.k.x + ny * f.k.y + nz * f.k.z);
+        acc[OBS_EJ] += 0.5 * (nx * f.j.x + ny * f.j.y + nz * f.j.z);
+        acc[OBS_ED] += 0.5 * (nx * f.d.x + ny * f.d.y + nz * f.d.z);
+        const double tx_ = ny * g.z - nz * g.y, ty_ = nz * g.x - nx * g.z, tz_ = nx * g.y - ny * g.x;
+        const double t2 = tx_ * tx_ + ty_ * ty_ + tz_ * tz_;
+        if (!isfinite(t2)) {
+            acc[OBS_NONFINITE] += 1.0;
+        } else {
+            acc[OBS_TMAX] = fmax(acc[OBS_TMAX], sqrt(t2));
+            acc[OBS_T2] += t2;
+        }
+        acc[OBS_MX] += nx;
+        acc[OBS_MY] += ny;
+        acc[OBS_MZ] += nz;
+        const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+        acc[OBS_NDEV] = fmax(acc[OBS_NDEV], fabs(nn - 1.0));
+    }
+    block_reduce<NT / 64>(acc);
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < OBS_NVALS; ++k) partials[blockIdx.x * OBS_NVALS + k] = acc[k];
     }
 }
 

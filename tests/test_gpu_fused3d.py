@@ -72,6 +72,49 @@ def test_fused3d_full_cubic128_thermal(ora):
     assert_close(e.get_spins(), n_ora, "f32", what="cubic128 two thermal steps")
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["sc2_bulk_ragged_37x21x11_openz", "sc1_interfacial_20x18x6_open",
+                                  "sc3_nodmi_17x16x5", "cubic128"])
+def test_observation_on_3d_stencil_tiles_matches_oracle(ora, case, precision):
+    """Energy per term, largest torque, mean spin and norm deviation formed on
+    the 3D stencil tiles (32 x 8 tiles of one plane with its neighbours;
+    ragged tiles, open axes, no DMI, and the 128^3 lattice, whose 8,192 work
+    items exceed the partial rows) against the oracle, and for the ragged
+    case against the generic kernel of the same bonds given as explicit
+    pairs."""
+    announce(f"3d observation {case} {precision}")
+    if case == "cubic128":
+        w = si.WORKLOADS["cubic128_bulkdmi"]
+        geo, ham = w.geometry, w.hamiltonian
+    else:
+        geo, ham = CASES[case]
+    e, s = make_pair(ora, geo, ham, precision)
+    assert e.step_path.startswith("shape3d")
+    n = si.uniform_sphere(s.N, 31)
+    e.set_spins(n)
+    obs, oo = e.observe(), s.observe(n)
+    tol = TOL[precision]
+    scale = np.abs(oo["per_term"]).sum()
+    assert np.abs(np.array(obs["per_term"]) - np.array(oo["per_term"])).max() <= tol * scale
+    assert obs["max_torque"] == pytest.approx(oo["max_torque"], rel=10 * tol)
+    assert np.allclose(obs["M"], oo["M"], atol=10 * tol)
+    if precision == "f64":
+        assert obs["max_norm_dev"] == pytest.approx(oo["max_norm_dev"], abs=1e-14)
+    else:
+        assert obs["max_norm_dev"] < 1e-6
+    if case == "sc2_bulk_ragged_37x21x11_openz":
+        table = {(b[0], b[1], b[2], b[3], b[4]): b for b in s.bonds()}
+        pairs = [(b[0], b[1], (b[2], b[3], b[4]), b[6], b[7]) for k, b in table.items()
+                 if k < (b[1], b[0], -b[2], -b[3], -b[4])]
+        g, _ = make_pair(ora, geo, dataclasses.replace(ham, J=(), D=()), precision)
+        g.set_pairs(pairs)
+        assert not g.step_path.startswith("shape3d")
+        g.set_spins(n)
+        og = g.observe()
+        assert np.abs(np.array(obs["per_term"]) - np.array(og["per_term"])).max() <= 2 * tol * scale
+        assert obs["max_torque"] == pytest.approx(og["max_torque"], rel=10 * tol)
+
+
 def test_fused3d_max_size_lattice_follows_the_periodic_patch(ora):
     """A 1024 x 1024 x 512 periodic simple-cubic lattice (exactly 2^29 sites,
     the 128^3 workload's Hamiltonian, FP32) filled with a periodic tiling of a
