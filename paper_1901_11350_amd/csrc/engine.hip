@@ -1015,6 +1015,24 @@ template <typename T, int S>
 void go_gradient_shape(sp_engine* e, const void* n, void* g) {
     const long long big_tiles = (long long)((e->geo.n[0] + 63) / 64) * ((e->geo.n[1] + 63) / 64);
     if constexpr (sizeof(T) == 4) {
+        if (big_tiles >= 512 && e->geo.n[0] % 64 == 0 && e->geo.n[1] % 64 == 0 &&
+            reinterpret_cast<uintptr_t>(n) % 16 == 0 && reinterpret_cast<uintptr_t>(g) % 16 == 0) {
+            // whole 64 x 64 tiles and 16-byte aligned arrays: 16-byte loads and stores
+            sp::TileMap M{};
+            M.tiles_x = e->geo.n[0] / 64;
+            M.tiles_y = e->geo.n[1] / 64;
+            const int ntiles = M.tiles_x * M.tiles_y;
+            M.xcd_bands = ntiles % 8 == 0 ? 1 : 0;
+            const sp::ShapeCoef<float> C = shape_coef_for<float, S>(e);
+            const sp::Site2D<float> Q = make_site2d<float>(e, nullptr);
+            if (e->shape_ndmi)
+                hipLaunchKernelGGL((sp::k_gradient_shape_v4<S, sp::ShapeTab<S>::NB0>), dim3((unsigned)ntiles), dim3(1024),
+                                   0, e->stream, C, Q, M, static_cast<const float*>(n), static_cast<float*>(g));
+            else
+                hipLaunchKernelGGL((sp::k_gradient_shape_v4<S, 0>), dim3((unsigned)ntiles), dim3(1024), 0, e->stream, C,
+                                   Q, M, static_cast<const float*>(n), static_cast<float*>(g));
+            return;
+        }
         if (big_tiles >= 512) {
             go_gradient_tile<T, S, 64, 64, 1024>(e, n, g);
             return;

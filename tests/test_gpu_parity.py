@@ -374,13 +374,15 @@ def test_call_order_errors(ora):
         e.step_path = "nonsense"
 
 
-@pytest.mark.parametrize("case", ["tri1540x1530", "sq1600x1536_open_2shell"])
+@pytest.mark.parametrize("case", ["tri1540x1530", "tri1536x1472", "sq1600x1536_open_2shell"])
 def test_stencil_gradient_large_tiles_match_oracle(ora, case):
     """Lattices large enough for the 64 x 64 tiles of the stand-alone stencil
     gradient (ragged tiles, open edges): every site against the oracle."""
     announce(f"stencil gradient large tiles {case}")
     if case == "tri1540x1530":
         geo, ham = si.triangular(1540, 1530), HAM1
+    elif case == "tri1536x1472":   # whole 64 x 64 tiles: the 16-byte load and store kernel
+        geo, ham = si.triangular(1536, 1472), HAM1
     else:
         geo, ham = si.square(1600, 1536, periodic=(0, 1, 0)), dataclasses.replace(HAM0, J=(1.0, 0.3))
     e, s = make_pair(ora, geo, ham, "f32")
@@ -388,6 +390,28 @@ def test_stencil_gradient_large_tiles_match_oracle(ora, case):
     n = si.uniform_sphere(s.N, 77)
     e.set_spins(n)
     assert_close(e.gradient(), s.gradient(n), "f32", what=f"stencil gradient {case}")
+
+
+def test_stencil_gradient_to_unaligned_array_matches_aligned(ora):
+    """A gradient written to a device array that is not 16-byte aligned takes
+    the single-float kernel; on a lattice of whole 64 x 64 tiles it must equal,
+    bit for bit, the 16-byte kernel's output to an aligned array."""
+    import torch
+
+    announce("stencil gradient unaligned output")
+    geo, ham = si.square(1600, 1536, periodic=(0, 1, 0)), dataclasses.replace(HAM0, J=(1.0, 0.3))
+    e, s = make_pair(ora, geo, ham, "f32")
+    n = si.uniform_sphere(s.N, 78)
+    e.set_spins(n)
+    g_al = torch.zeros(3 * s.N, dtype=torch.float32, device="cuda")
+    g_buf = torch.zeros(3 * s.N + 1, dtype=torch.float32, device="cuda")
+    g_mis = g_buf[1:]
+    assert g_mis.data_ptr() % 16 != 0
+    e.gradient_dev(g_al)
+    e.gradient_dev(g_mis)
+    e.synchronize()
+    assert torch.equal(g_al, g_mis)
+    assert_close(g_al.double().cpu().numpy().reshape(3, -1), s.gradient(n), "f32", what="16-byte kernel")
 
 
 @pytest.mark.parametrize("path", ["shape2d/64x16x1024", "persist2d/64x16", "twopass"])
