@@ -229,7 +229,11 @@ int sp_get_spins_dev(sp_engine *e, void *n_soa_dev, int64_t N);
 int sp_set_step(sp_engine *e, uint64_t step);
 uint64_t sp_get_step(const sp_engine *e);
 
-/* Gradient dH/dn_i in the embedding space (meV), all terms; B_eff = -g. */
+/* Gradient dH/dn_i in the embedding space (meV), all terms; B_eff = -g.
+ * sp_gradient_dev writes 3N values of the engine precision to device memory
+ * on the engine's stream; on FP32 lattices with a compile-time stencil whose
+ * sides divide into 64 x 64 tiles (at least 512 of them) a 16-byte aligned
+ * g_soa_dev takes the 16-byte load/store kernel (same values, bit for bit). */
 int sp_gradient(sp_engine *e, double *g_soa, int64_t N);
 int sp_gradient_dev(sp_engine *e, void *g_soa_dev, int64_t N);
 /* Energy by terms (double-precision reduction).  per_term may be NULL. */
