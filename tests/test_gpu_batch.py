@@ -151,10 +151,11 @@ def _chain(pk, L=48, M=10):
 
 
 def test_batch_advances_an_attached_gneb_chain():
-    """A chain attached to a batch (its iterations a branch of the chunk
-    graph) ends bit-identical to the same chain iterated on its own, through
-    graph replays, a re-capture and direct chunks; the replicas are the same
-    as in a batch without the chain."""
+    """A chain attached to a batch (its chunk of iterations a graph launched
+    beside the replicas' chunk graph; a side branch of the direct chunks)
+    ends bit-identical to the same chain iterated on its own, through graph
+    replays, a re-capture and direct chunks; the replicas are the same as in
+    a batch without the chain."""
     import paper_1901_11350_amd as pk
     from paper_1901_11350_amd.engine import SpError
 
