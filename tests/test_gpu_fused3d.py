@@ -74,7 +74,7 @@ def test_fused3d_full_cubic128_thermal(ora):
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("case", ["sc2_bulk_ragged_37x21x11_openz", "sc1_interfacial_20x18x6_open",
-                                  "sc3_nodmi_17x16x5", "cubic128"])
+                                  "sc3_nodmi_17x16x5", "sc2_thin_9x9x2", "sc1_40x4x3_periodic_small", "cubic128"])
 def test_observation_on_3d_stencil_tiles_matches_oracle(ora, case, precision):
     """Energy per term, largest torque, mean spin and norm deviation formed on
     the 3D stencil tiles (32 x 8 tiles of one plane with its neighbours;
