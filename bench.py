@@ -1,10 +1,15 @@
 """Benchmark: LLG spin-updates/s of the fused Depondt step on one MI355X.
 
-Workload (default): triangular lattice 512 x 512 (262,144 spins), exchange
-shells J1..J3 = 1, -0.2, -0.1 meV, interfacial DMI 0.2 meV, K = 0.05 meV,
-B = 0.5 T, stochastic LLG at T = 10 K (Philox thermal field), alpha = 0.1,
-dt = 0.5 fs, FP32 spins with FP64 observables every 100 steps.  A "step"
-is one full Depondt step (predictor + corrector) of every spin.
+Workload (default, the largest single-GPU configuration): simple-cubic
+lattice 128^3 (2,097,152 spins), periodic, exchange J1 = 1.0 and J2 = 0.1
+meV, bulk DMI 0.15 meV on the first shell, B = 0.3 T, T = 0, alpha = 0.5,
+dt = 1 fs, FP32 spins, FP64 observables every 100 steps, from a seeded
+conical spiral.  A "step" is one full Depondt step (predictor + corrector)
+of every spin.  The same run also reports, each in a few seconds, the
+stochastic 512^2 triangular workload, the 96-replica batch with its GNEB
+chain, the stand-alone stencil on the 8192^2 probe lattice, and the dipole
+field of the 128x128x4 film (direct sum, FFT convolution, learned field
+with its residual check); --no-extras leaves them out.
 
 Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
@@ -22,60 +27,59 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_UPDATE = {"f32": 24.0, "f64": 48.0}   # read n, write n(t+dt): 3 components each
-# MI355X published vector FP32 peak: 256 CUs x 128 FMA lanes x 2 flops x
-# 2.4 GHz.  This build emits no packed-FP32 instructions, so one wave issues
-# at most 64 FMA lanes per CU per clock (78.6 TFLOP/s); the published figure
-# is still the peak the fraction is taken against.
-VALU_FP32_PEAK_TFLOPS = 157.3
+# Non-packed VALU issue capacity of MI355X: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz = 3.93e13 lane-instructions/s (one wave64 instruction per SIMD
+# every four cycles).  This build emits no packed-FP32 instructions.
+VALU_LANE_INSTR_PER_S = 256 * 64 * 2.4e9
+
+KERNEL_SOURCES = {
+    "k_fused2d_shape": ["paper_1901_11350_amd/csrc/kernels_fused2d.hpp",
+                        "paper_1901_11350_amd/csrc/kernels_field.hpp",
+                        "paper_1901_11350_amd/csrc/device_common.hpp"],
+    "k_fused3d_shape": ["paper_1901_11350_amd/csrc/kernels_fused3d.hpp",
+                        "paper_1901_11350_amd/csrc/kernels_fused2d.hpp",
+                        "paper_1901_11350_amd/csrc/kernels_field.hpp",
+                        "paper_1901_11350_amd/csrc/device_common.hpp"],
+}
 
 
-KERNEL_SOURCES = ["paper_1901_11350_amd/csrc/kernels_fused2d.hpp",
-                  "paper_1901_11350_amd/csrc/kernels_field.hpp",
-                  "paper_1901_11350_amd/csrc/device_common.hpp"]
-
-
-def kernel_source_digest() -> str:
+def kernel_source_digest(kernel: str) -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in KERNEL_SOURCES.get(kernel, []):
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str, step_path: str):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary of this kernel, workload and step path (tile shape), or None when
-    there is none or the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+def counter_record(kernel: str, workload: str, step_path: str):
+    """The committed rocprofv3 counter record of this kernel, workload and
+    step path (profiles/counters_<kernel>_<workload>.json: FETCH_SIZE and
+    WRITE_SIZE scaled by a device copy, VALU instructions per update), or
+    None when there is none or the kernel sources changed since the counters
+    were taken."""
+    path = os.path.join(ROOT, "profiles", f"counters_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_sha256") != kernel_source_digest() or rec.get("step_path") != step_path:
+    if rec.get("kernel_source_sha256") != kernel_source_digest(kernel) or rec.get("step_path") != step_path:
         return None
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return rec
 
 
-def flops_per_update(workload) -> float:
-    """Algorithmic FP32 flops of one Depondt spin-update (FMA = 2 flops):
-    two field evaluations (neighbour sums 3 per bond, 6 per shell for J,
-    8 per in-plane DMI bond or 12 per 3D DMI bond, 9 anisotropy, 3 Zeeman)
-    plus 163 for the two
-    A vectors, their average, two Rodrigues rotations and the
-    renormalisation, plus 15 for Box-Muller at T > 0 (integer Philox
-    operations and transcendentals are not counted)."""
-    h = workload.hamiltonian
-    lat = "tri" if abs(workload.geometry.bravais[1][0] - 0.5) < 1e-12 else "sq"
-    per_shell = {"tri": [6, 6, 6], "sq": [4, 4, 4]} if workload.geometry.n_cells[2] == 1 else \
-        {"tri": [6, 6, 6], "sq": [6, 12, 8]}
-    shells = max(len(h.J), len(h.D))
-    nb = sum(per_shell[lat][:shells])
-    ndmi = sum(per_shell[lat][:len(h.D)]) if any(h.D) else 0
-    per_dmi = 8 if workload.geometry.n_cells[2] == 1 else 12
-    field = 3 * nb + 6 * len(h.J) + per_dmi * ndmi + 9 + 3
-    return 2 * field + 163 + (15 if workload.dynamics.T > 0 else 0)
+def host_info() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
 def cpu_baseline(workload, budget_s: float = 12.0) -> dict:
@@ -87,7 +91,7 @@ def cpu_baseline(workload, budget_s: float = 12.0) -> dict:
     oracle.build(force=False)
     w = workload
     s = oracle.System(w.geometry, w.hamiltonian)
-    n = si.uniform_sphere(s.N, w.init_seed)
+    n = initial_state(w)
     d = w.dynamics
     steps = 0
     t0 = time.perf_counter()
@@ -99,7 +103,8 @@ def cpu_baseline(workload, budget_s: float = 12.0) -> dict:
             break
     cores = oracle.num_threads()
     out = {"value": s.N * steps / el, "unit": "spin-updates/s", "cores": cores, "kind": "oracle",
-           "sample": f"{steps} FP64 Depondt steps of the full {s.N}-spin workload ({el:.1f} s)"}
+           "sample": f"{steps} FP64 Depondt steps of the full {s.N}-spin workload ({el:.1f} s)",
+           "host": host_info()}
     # the same oracle on one core (the paper compares one thread with many)
     oracle.set_num_threads(1)
     try:
@@ -116,6 +121,14 @@ def cpu_baseline(workload, budget_s: float = 12.0) -> dict:
     out["single_core"] = {"value": s.N * steps1 / el1, "cores": 1,
                           "sample": f"{steps1} steps ({el1:.1f} s)"}
     return out
+
+
+def initial_state(w):
+    import spin_inputs as si
+
+    if w.init == "conical_helix":
+        return si.conical_helix(w.geometry, seed=w.init_seed)
+    return si.uniform_sphere(w.geometry.n_sites, w.init_seed)
 
 
 def calibrate_copy(mib: int, reps: int = 5) -> None:
@@ -231,6 +244,11 @@ def bench_batch(args) -> dict:
     gneb["in_batch"] = {"ms_per_step": ms_both / K,
                         "updates_per_s": (total + 32 * geo.n_sites) * K / (ms_both * 1e-3),
                         "note": "replica spin-updates + chain image-spin updates per second; the chain's graph runs beside the replicas' graph"}
+    b.close()
+    g.close()
+    ge.close()
+    for e, _, _ in engines:
+        e.close()
     return {"workload": "batch96_square", "replicas": len(table), "resident_replicas": n_res, "gneb": gneb,
             "total_spins": total, "steps": K, "chunk": args.batch_chunk,
             "spin_updates_per_s": total * K / (ms * 1e-3), "ms_per_step": ms / K,
@@ -285,6 +303,7 @@ def bench_stencil(args) -> dict:
             out[name]["copy_same_bytes_gbps"] = 24.0 * e.N / tc / 1e9
             out[name]["frac_of_copy"] = gbps / out[name]["copy_same_bytes_gbps"]
             del src
+        e.close()
         del g, e
         torch.cuda.empty_cache()
     return out
@@ -413,6 +432,8 @@ def bench_surrogate(args) -> dict:
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_step_fft = ev0.elapsed_time(ev1) / steps
+    e.close()
+    f.close()
     return {"workload": "film128x4_dipolar", "n_sites": N, "train_textures": ntr, "test_textures": nte,
             "epochs": args.sur_epochs, "train_s": train_s, "loss_first_last": [float(losses[0]), float(losses[-1])],
             "heldout_rel_err_mean": float(err.mean()), "heldout_rel_err_max": float(err.max()),
@@ -487,22 +508,108 @@ def bench_tc(args) -> dict:
                     "crossing_K": binder_crossing(llg, 8, 12, temps), "s": t_llg}}
 
 
+KERNEL_OF_PATH = {"fused2d": "k_depondt_fused2d", "twopass": "k_predict+k_correct", "shape3d": "k_fused3d_shape",
+                  "persist2d": "k_persist2d", "shape2d": "k_fused2d_shape"}
+
+
+def time_workload(w, steps: int, warmup: int, observe_every: int, step_path: str = "", autotune: bool = False):
+    """Depondt steps of a workload between HIP events on the engine's stream:
+    the whole run with its observations (the throughput), then the step
+    kernel alone per launch (the roofline's achieved rate)."""
+    import torch
+
+    import paper_1901_11350_amd as pk
+
+    d = w.dynamics
+    stream = work_stream()
+    e = pk.engine_for(w, 0, w.precision, stream=stream)
+    try:
+        e.set_spins(initial_state(w))
+        tuned_ms = e.autotune(d.alpha, d.dt, d.T, d.seed, n_steps=50) if autotune else None
+        if step_path:
+            e.step_path = step_path
+        print(f"[bench] workload={w.name} N={e.N} path={e.step_path} precision={w.precision} "
+              f"autotune_ms={tuned_ms}", file=sys.stderr, flush=True)
+        e.run(d.alpha, d.dt, warmup, T=d.T, seed=d.seed)
+        torch.cuda.synchronize()
+        K = steps
+        oe = observe_every if observe_every and K >= observe_every else 0
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        ev0.record(stream)
+        obs = e.run(d.alpha, d.dt, K, T=d.T, seed=d.seed, observe_every=oe)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        ms = ev0.elapsed_time(ev1)
+        # the step kernel alone (no observations), per launch; the persistent
+        # path runs all steps in one launch, so its figure is per step
+        K2 = max(100, K // 2)
+        ev0.record(stream)
+        e.run(d.alpha, d.dt, K2, T=d.T, seed=d.seed)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        path = e.step_path
+        launches_per_step = 2 if path == "twopass" else 1
+        t_launch = ev0.elapsed_time(ev1) * 1e-3 / (K2 * launches_per_step)
+        last = obs[-1] if obs else e.observe()
+        return {"N": e.N, "steps": K, "observe_every": oe, "ms": ms, "wall_s": wall, "t_launch": t_launch,
+                "launches_per_step": launches_per_step, "path": path, "last": last, "autotune_ms": tuned_ms}
+    finally:
+        e.close()
+
+
+def roofline_of(w, r) -> dict:
+    """HBM roofline of the step kernel: algorithmic bytes (24 B per FP32
+    spin-update: read n, write n') per launch over its average launch time,
+    against 8 TB/s; the VALU ceiling from the committed instruction count."""
+    kernel = KERNEL_OF_PATH.get(r["path"].split("/")[0], "k_fused2d_shape")
+    bytes_per_launch = BYTES_PER_UPDATE[w.precision] * r["N"] / r["launches_per_step"]
+    achieved = bytes_per_launch / r["t_launch"] / 1e9
+    rec = counter_record(kernel, w.name, r["path"])
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBPS,
+           "traffic": (rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]) if rec else None,
+           "kernel": kernel, "algorithmic_bytes_per_launch": bytes_per_launch,
+           "us_per_launch": r["t_launch"] * 1e6}
+    if rec and rec.get("valu_instructions_per_update"):
+        ipu = rec["valu_instructions_per_update"]
+        ceiling = VALU_LANE_INSTR_PER_S / ipu
+        upd = r["N"] / r["launches_per_step"] / r["t_launch"]
+        out["valu"] = {"instructions_per_update": ipu, "lane_instructions_per_s_peak": VALU_LANE_INSTR_PER_S,
+                       "ceiling_updates_per_s": ceiling, "achieved_updates_per_s": upd, "frac": upd / ceiling}
+    return out
+
+
+def bench_config1(args) -> dict:
+    """The stochastic 512^2 triangular workload (T = 10 K), observations
+    every 100 steps, graph-replayed chunks."""
+    import spin_inputs as si
+
+    w = si.WORKLOADS["triangular512_sllg"]
+    r = time_workload(w, args.config1_steps, 200, 100)
+    value = r["N"] * r["steps"] / (r["ms"] * 1e-3)
+    return {"workload": w.name, "n_sites": r["N"], "steps": r["steps"], "ms_per_step": r["ms"] / r["steps"],
+            "spin_updates_per_s": value, "step_path": r["path"], "roofline": roofline_of(w, r)}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--surrogate", action="store_true",
-                    help="also train and time the learned dipole field (reported under 'surrogate')")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (no config-1, batch, stencil, dipole keys)")
+    ap.add_argument("--surrogate", action="store_true", help="(default with the extras; kept for old command lines)")
     ap.add_argument("--sur-train", type=int, default=384)
     ap.add_argument("--sur-test", type=int, default=16)
     ap.add_argument("--sur-epochs", type=int, default=20)
     ap.add_argument("--sur-lr", type=float, default=2e-3)
     ap.add_argument("--sur-steps", type=int, default=20)
-    ap.add_argument("--batch", action="store_true",
-                    help="also time the 96-replica batch (reported under 'batch')")
+    ap.add_argument("--config1-steps", type=int, default=2000)
+    ap.add_argument("--batch", action="store_true", help="(default with the extras; kept for old command lines)")
     ap.add_argument("--batch-steps", type=int, default=256)
     ap.add_argument("--batch-chunk", type=int, default=32)
     ap.add_argument("--gneb-iters", type=int, default=200)
-    ap.add_argument("--stencil", action="store_true",
-                    help="also time the stand-alone stencil field kernel (512^2 and the 8192^2 probe)")
+    ap.add_argument("--stencil", action="store_true", help="(default with the extras; kept for old command lines)")
     ap.add_argument("--stencil-launches", type=int, default=200)
     ap.add_argument("--tc", action="store_true",
                     help="also estimate the ferromagnet's Tc from Binder crossings (reported under 'tc')")
@@ -513,9 +620,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="only run a device copy of this size (counter calibration)")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="triangular512_sllg")
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="cubic128_bulkdmi")
     ap.add_argument("--observe-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--step-path", default="",
@@ -534,7 +641,6 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1901_11350_amd as pk
@@ -543,62 +649,11 @@ def main():
     w = si.WORKLOADS[args.workload]
     d = w.dynamics
     torch.cuda.init()
-    stream = work_stream()
-    e = pk.engine_for(w, 0, w.precision, stream=stream)
-    if w.init == "conical_helix":
-        n0 = si.conical_helix(w.geometry, seed=w.init_seed)
-    else:
-        n0 = si.uniform_sphere(e.N, w.init_seed)
-    e.set_spins(n0)
-    tuned_ms = None
-    if args.autotune and not args.no_autotune:
-        tuned_ms = e.autotune(d.alpha, d.dt, d.T, d.seed, n_steps=50)
-    if args.step_path:
-        e.step_path = args.step_path
-    print(f"[bench] workload={w.name} N={e.N} path={e.step_path} precision={w.precision} "
-          f"autotune_ms={tuned_ms}", file=sys.stderr, flush=True)
-
-    # warm-up
-    e.run(d.alpha, d.dt, args.warmup, T=d.T, seed=d.seed)
-    torch.cuda.synchronize()
-
-    # timed: full runs with observables (the benchmark value)
-    K = args.steps
-    oe = args.observe_every if args.observe_every and K >= args.observe_every else 0
-    t_ev0 = torch.cuda.Event(enable_timing=True)
-    t_ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t_ev0.record(stream)
-    obs = e.run(d.alpha, d.dt, K, T=d.T, seed=d.seed, observe_every=oe)
-    t_ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = t_ev0.elapsed_time(t_ev1)
-    value = e.N * K / (ms * 1e-3)
-
-    # dominant kernel: the step kernel alone (no observables), per launch
-    K2 = max(100, K // 2)
-    k_ev0 = torch.cuda.Event(enable_timing=True)
-    k_ev1 = torch.cuda.Event(enable_timing=True)
-    k_ev0.record(stream)
-    e.run(d.alpha, d.dt, K2, T=d.T, seed=d.seed)
-    k_ev1.record(stream)
-    torch.cuda.synchronize()
-    # per launch; the persistent path runs all K2 steps in one launch, so
-    # its figures are per step of that launch
-    launches_per_step = 2 if e.step_path == "twopass" else 1
-    t_launch = k_ev0.elapsed_time(k_ev1) * 1e-3 / (K2 * launches_per_step)
-    bytes_per_launch = BYTES_PER_UPDATE[w.precision] * e.N / launches_per_step
-    achieved = bytes_per_launch / t_launch / 1e9
-    fpu = flops_per_update(w)
-    tflops = fpu * e.N / launches_per_step / t_launch / 1e12
-    kernel_name = {"fused2d": "k_depondt_fused2d", "twopass": "k_predict+k_correct"}.get(
-        e.step_path.split("/")[0], {"shape3d": "k_fused3d_shape", "persist2d": "k_persist2d"}.get(
-            e.step_path.split("/")[0], "k_fused2d_shape"))
-    traffic = measured_traffic(kernel_name, w.name, e.step_path)
-
-    last = obs[-1] if obs else e.observe()
+    r = time_workload(w, args.steps, args.warmup, args.observe_every, args.step_path,
+                      args.autotune and not args.no_autotune)
+    K = r["steps"]
+    value = r["N"] * K / (r["ms"] * 1e-3)
+    last = r["last"]
     line = {
         "metric": "LLG spin-updates/s at 1 GPU + HBM GB/s; surrogate vs direct dipole speedup at 1e-3",
         "value": value,
@@ -606,33 +661,33 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": ms / K,
+        "ms_per_step": r["ms"] / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": w.precision,
         "data": "synthetic",
-        "config": {"workload": w.name, "n_sites": e.N, "lattice": w.description,
-                   "alpha": d.alpha, "dt_ps": d.dt, "T_K": d.T, "observe_every": oe,
-                   "step_path": e.step_path},
+        "config": {"workload": w.name, "n_sites": r["N"], "lattice": w.description,
+                   "alpha": d.alpha, "dt_ps": d.dt, "T_K": d.T, "observe_every": r["observe_every"],
+                   "step_path": r["path"]},
         "hbm_gbps_algorithmic": value * BYTES_PER_UPDATE[w.precision] / 1e9,
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / VALU_FP32_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": kernel_name, "flops_per_update": fpu,
-                     "algorithmic_bytes_per_launch": bytes_per_launch, "us_per_launch": t_launch * 1e6,
-                     "hbm_achieved_GBps": achieved, "hbm_peak_GBps": HBM_PEAK_GBPS,
-                     "hbm_frac": achieved / HBM_PEAK_GBPS},
-        "wall_s": wall,
-        "final_observation": {"E_per_spin": last["E"] / e.N, "max_norm_dev": last["max_norm_dev"]},
+        "roofline": roofline_of(w, r),
+        "wall_s": r["wall_s"],
+        "final_observation": {"E_per_spin": last["E"] / r["N"], "max_norm_dev": last["max_norm_dev"]},
     }
-    if args.batch:
+    extras = not args.no_extras
+    if extras:
+        line["config1"] = bench_config1(args)
+    if extras or args.batch:
         line["batch"] = bench_batch(args)
-    if args.surrogate:
-        line["surrogate"] = bench_surrogate(args)
+    if extras or args.stencil:
+        line["stencil"] = bench_stencil(args)
+    if extras or args.surrogate:
+        line["dipole"] = bench_surrogate(args)
     if args.tc:
         line["tc"] = bench_tc(args)
-    if args.stencil:
-        line["stencil"] = bench_stencil(args)
+    pk.close_all()
+    torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -229,40 +229,82 @@ int sp_get_spins_dev(sp_engine *e, void *n_soa_dev, int64_t N);
 int sp_set_step(sp_engine *e, uint64_t step);
 uint64_t sp_get_step(const sp_engine *e);
 
-/* Gradient dH/dn_i in the embedding space (meV), all terms; B_eff = -g.
- * sp_gradient_dev writes 3N values of the engine precision to device memory
+/* Gradient dH/dn_i in the embedding space (meV), all terms of the extended
+ * Heisenberg Hamiltonian of Sec. III.A (Zeeman, anisotropy, exchange, DMI,
+ * dipole, on-site Gaussians); the effective field of Sec. III.C is
+ * B_eff = -g (divide by mu_i mu_B for Tesla).  g_soa: 3N doubles written
+ * before return.  SP_E_ORDER before sp_set_spins; SP_E_ARG if N is not the
+ * engine's site count.  sp_gradient_dev writes 3N values of the engine precision to device memory
  * on the engine's stream; on FP32 lattices with a compile-time stencil whose
  * sides divide into 64 x 64 tiles (at least 512 of them) a 16-byte aligned
  * g_soa_dev takes the 16-byte load/store kernel (same values, bit for bit). */
 int sp_gradient(sp_engine *e, double *g_soa, int64_t N);
 int sp_gradient_dev(sp_engine *e, void *g_soa_dev, int64_t N);
-/* Energy by terms (double-precision reduction).  per_term may be NULL. */
+/* Energy of the current state, total and by term (Zeeman, anisotropy,
+ * exchange, DMI, dipole; meV), the Hamiltonian of Sec. III.A evaluated as
+ * E = sum_i n_i.(g_lin + g_quad / 2) with the linear (Zeeman) and quadratic
+ * parts of the gradient (Appendix H), reduced in double precision in a
+ * fixed order.  per_term may be NULL.  SP_E_ORDER before sp_set_spins. */
 int sp_energy(sp_engine *e, double *E_total, double per_term[5]);
-/* All observables of the current state. */
+/* All observables of the current state (sp_observation): the energies of
+ * sp_energy, the maximum torque max_i |n_i x dH/dn_i| (the quantity a
+ * minimiser drives to zero: damping-only LLG of Sec. III.C and the
+ * velocity projection of Appendix D), the mean spin and the largest
+ * deviation of |n_i| from one.  *obs is written before return. */
 int sp_observe(sp_engine *e, sp_observation *obs);
 
 /* One Depondt step (Appendix B): predictor n^p = R(A(n)) n, corrector
  * n(t+dt) = R((A(n) + A(n^p))/2) n with the same thermal normals in both.
  * Advances the step counter by one. */
 int sp_llg_step(sp_engine *e, const sp_llg_params *p);
-/* n_steps Depondt steps.  If observe_every > 0 an observation is taken after
- * every observe_every steps and written to obs[k] (obs must hold
- * n_steps/observe_every entries; may be NULL to only check finiteness).
- * When an observation finds a non-finite torque the remaining steps are
- * skipped and SP_E_NONFINITE is returned (sp_last_error names the step). */
+/* n_steps steps of the LLG equation of Sec. III.C with the solver of p
+ * (Depondt by default, Appendix B), the thermal field drawn per step and
+ * site from the Philox stream.  If observe_every > 0 an observation is
+ * taken after every observe_every steps and written to obs[k] (obs must
+ * hold n_steps/observe_every entries; may be NULL to only check
+ * finiteness).  When an observation finds a non-finite torque the remaining
+ * steps are skipped and SP_E_NONFINITE is returned (sp_last_error names the
+ * step).  Chunks of observe_every steps (32 without observations) are
+ * captured once as HIP graphs and replayed while parameters, buffers and
+ * step path stay the same (sp_set_graph_replay turns this off); results are
+ * the same bit for bit either way. */
 int sp_run(sp_engine *e, const sp_llg_params *p, int64_t n_steps, int64_t observe_every,
            sp_observation *obs);
+/* sp_run with the convergence test of a relaxation (damping-only LLG as a
+ * minimiser, Sec. III.C; the paper prints no criterion): the run stops after
+ * the first observation whose maximum torque max_i |n_i x dH/dn_i| (FP64
+ * reduction) is below tol, or after max_steps steps.  The test runs on the
+ * device (no host synchronisation per observation); the state and the step
+ * counter are those of the observation that passed.  observe_every > 0 and
+ * tol > 0 (SP_E_ARG otherwise).  obs (may be NULL) receives the
+ * observations taken, up to max_steps/observe_every entries;
+ * *steps_done (may be NULL) the steps taken.  SP_E_NONFINITE as sp_run. */
+int sp_run_tol(sp_engine *e, const sp_llg_params *p, int64_t max_steps, int64_t observe_every, double tol,
+               sp_observation *obs, int64_t *steps_done);
+/* Graph replay of sp_run on (enable != 0, the default) or off (direct
+ * launches; cached graphs are freed). */
+int sp_set_graph_replay(sp_engine *e, int enable);
 /* Wait for all work queued on the engine stream. */
 int sp_synchronize(sp_engine *e);
 
-/* Dipole-dipole gradient alone (direct sum over all pairs, open sample);
- * g_soa receives 3N doubles.  Independent of ddi_mode. */
+/* Dipole-dipole gradient alone: the dipolar term of the Hamiltonian of
+ * Sec. III.A (in the physical form 1/2 C_dd sum_{i!=j} mu_i mu_j
+ * [n_i.n_j - 3 (n_i.r)(n_j.r)] / r^3) summed directly over all pairs of the
+ * sample (open, no periodic images); g_soa receives 3N doubles (meV).
+ * Independent of ddi_mode.  sp_dipole_gradient_dev reads n_soa_dev and
+ * writes g_soa_dev (engine precision, 3N each, caller-owned device memory,
+ * engine stream). */
 int sp_dipole_gradient(sp_engine *e, double *g_soa, int64_t N);
 int sp_dipole_gradient_dev(sp_engine *e, const void *n_soa_dev, void *g_soa_dev, int64_t N);
 
-/* Philox4x32-10 + Box-Muller normals exactly as the LLG kernels draw them,
- * for n_sites consecutive sites starting at site0 (SoA, 3*n_sites values in
- * engine precision on the host as double).  For tests of the generator. */
+/* The three independent standard normals per site and step of the
+ * stochastic field of Sec. III.C, exactly as the LLG kernels draw them:
+ * Philox4x32-10 block of counter (site, step_lo, step_hi, replica) and key
+ * (seed_lo, seed_hi), u_k = (x_k + 1/2) 2^-32, Box-Muller on (u0, u1) and
+ * (u2, u3), first three normals; for n_sites consecutive sites starting at
+ * site0.  eta_soa receives 3*n_sites values (engine precision, as double,
+ * SoA); raw4 (may be NULL) the 4*n_sites Philox words.  For tests of the
+ * generator. */
 int sp_thermal_normals(sp_engine *e, uint64_t seed, uint64_t step, uint32_t replica,
                        uint32_t site0, int64_t n_sites, double *eta_soa, uint32_t *raw4);
 
@@ -378,6 +420,16 @@ enum sp_image_type { SP_IMAGE_NORMAL = 0, SP_IMAGE_CLIMBING = 1, SP_IMAGE_FALLIN
 int sp_gneb_set_image_type(sp_gneb *c, int image, int type);
 /* n_iter velocity-projection iterations. */
 int sp_gneb_iterate(sp_gneb *c, int n_iter);
+/* Relaxation of the chain to its minimum energy path: velocity-projection
+ * iterations (Appendix D) with the chain's GNEB forces (Sec. III.D) until the
+ * largest per-spin force |F_{v,i}| of the interior images (FP64 maximum) is
+ * below tol, or max_iter iterations.  The test runs on the device after
+ * every iteration; once it passes the remaining launches return at once, so
+ * the chain is that of the iteration that passed (as after
+ * sp_gneb_iterate(c, *iters_done)).  tol > 0 and max_iter >= 0 (SP_E_ARG
+ * otherwise); SP_E_ORDER while attached to a batch.  *iters_done (may be
+ * NULL) receives the iterations taken. */
+int sp_gneb_iterate_tol(sp_gneb *c, int max_iter, double tol, int *iters_done);
 /* Current chain (n_images*3N doubles). */
 int sp_gneb_get_chain(sp_gneb *c, double *chain);
 /* Of the last force evaluation: image energies E[n_images], geodesic

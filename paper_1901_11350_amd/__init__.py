@@ -10,6 +10,7 @@ from .engine import (  # noqa: F401
     Batch,
     Engine,
     Gneb,
+    close_all,
     SpError,
     engine_for,
     lib,

@@ -73,6 +73,21 @@ void surrogate_free(SurrogateState* s);
 struct FftState;
 void fft_free(FftState* s);
 
+// One captured chunk of sp_run: `steps` step launches (+ an observation),
+// valid for the parameters, buffers and step path it was captured with.
+struct RunGraph {
+    sp_llg_params p;
+    int steps;
+    bool observe;
+    double tol;
+    const void* n_first;     // the buffer the chunk starts from
+    const void* n_other;
+    const double* obs;       // the run's observation array at capture
+    long long obs_cap;
+    std::string path;
+    hipGraphExec_t exec;
+};
+
 struct sp_engine {
     int device = 0;
     int precision = SP_F32;
@@ -133,6 +148,15 @@ struct sp_engine {
     uint32_t pgen = 0;                // every flag is <= pgen between launches
     int* d_pstatus = nullptr;         // persistent path: nonzero after a failed wait
     double* h_pin = nullptr;          // pinned staging for small results
+    // replayed step graphs (sp_run): device step counter + observation index,
+    // a staging row for the chunk's observation, and the cached executables
+    unsigned long long* d_step = nullptr;
+    long long* d_obs_index = nullptr;
+    double* d_obs_stage = nullptr;
+    const unsigned long long* cap_step_dev = nullptr;   // set while capturing
+    unsigned int cap_step_off = 0;
+    bool graphs_on = true;
+    std::vector<RunGraph> graphs;
     SurrogateState* sur = nullptr;    // learned dipole field (sp_ddi_*)
     FftState* fft = nullptr;          // FFT-convolution dipole field (SP_DDI_FFT)
 };
@@ -173,7 +197,13 @@ int dalloc(sp_engine* e, P*& p, size_t bytes) {
     return SP_OK;
 }
 
+void drop_graphs(sp_engine* e) {
+    for (RunGraph& g : e->graphs) (void)hipGraphExecDestroy(g.exec);
+    e->graphs.clear();
+}
+
 void free_state_buffers(sp_engine* e) {
+    drop_graphs(e);
     dfree(e->d_n); dfree(e->d_n2); dfree(e->d_np); dfree(e->d_A); dfree(e->d_g);
     dfree(e->d_gdd); dfree(e->d_gddp); dfree(e->d_pos); dfree(e->d_ddpart);
     void* p = e->d_bond; dfree(p); e->d_bond = nullptr;
@@ -287,6 +317,18 @@ sp::LLGArgs<T> make_llg(const sp_llg_params* p, uint64_t step, uint32_t replica)
     A.key.step_lo = (uint32_t)step;
     A.key.step_hi = (uint32_t)(step >> 32);
     A.key.replica = replica;
+    return A;
+}
+
+// LLG arguments of a step launch of the engine: while a step graph is being
+// captured, the launch reads its Philox step from the device counter.
+template <typename T>
+sp::LLGArgs<T> make_step_llg(const sp_engine* e, const sp_llg_params* p, uint64_t step) {
+    sp::LLGArgs<T> A = make_llg<T>(p, step, p->replica);
+    if (e->cap_step_dev) {
+        A.step_dev = e->cap_step_dev;
+        A.step_off = e->cap_step_off;
+    }
     return A;
 }
 
@@ -405,7 +447,8 @@ int go_observe_shape3(sp_engine* e, const void* n) {
 }
 
 template <typename T>
-int launch_observe(sp_engine* e, const void* n, double* out, long long step, bool with_flag) {
+int launch_observe(sp_engine* e, const void* n, double* out, long long step, bool with_flag,
+                   const unsigned long long* step_dev = nullptr, int step_off = 0, double tol = 0.0) {
     if (e->shape3 >= 0 && !e->ham.ddi && e->ham.n_gauss == 0) {
         int rows;
         switch (e->shape3) {
@@ -414,7 +457,7 @@ int launch_observe(sp_engine* e, const void* n, double* out, long long step, boo
             default: rows = go_observe_shape3<T, sp::SH3_SC3>(e, n); break;
         }
         hipLaunchKernelGGL(sp::k_observe_final, dim3(1), dim3(256), 0, e->stream, e->d_partials, rows, out,
-                           with_flag ? e->d_flag : nullptr, e->d_abort_step, step);
+                           with_flag ? e->d_flag : nullptr, e->d_abort_step, step, step_dev, step_off, tol);
         HIPCHK(e, hipGetLastError());
         return SP_OK;
     }
@@ -429,7 +472,7 @@ int launch_observe(sp_engine* e, const void* n, double* out, long long step, boo
             default: rows = go_observe_shape<T, sp::SH_TRI3>(e, n); break;
         }
         hipLaunchKernelGGL(sp::k_observe_final, dim3(1), dim3(256), 0, e->stream, e->d_partials, rows, out,
-                           with_flag ? e->d_flag : nullptr, e->d_abort_step, step);
+                           with_flag ? e->d_flag : nullptr, e->d_abort_step, step, step_dev, step_off, tol);
         HIPCHK(e, hipGetLastError());
         return SP_OK;
     }
@@ -444,7 +487,7 @@ int launch_observe(sp_engine* e, const void* n, double* out, long long step, boo
                        make_lattice(e), make_coef<T>(e), P, static_cast<const T*>(n), static_cast<const T*>(gdd),
                        e->d_partials);
     hipLaunchKernelGGL(sp::k_observe_final, dim3(1), dim3(256), 0, e->stream, e->d_partials, e->partial_rows, out,
-                       with_flag ? e->d_flag : nullptr, e->d_abort_step, step);
+                       with_flag ? e->d_flag : nullptr, e->d_abort_step, step, step_dev, step_off, tol);
     HIPCHK(e, hipGetLastError());
     return SP_OK;
 }
@@ -502,7 +545,7 @@ template <typename T, int TX, int TY, int R>
 void launch_fused2d(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     dim3 grid((unsigned)((e->geo.n[0] + TX - 1) / TX), (unsigned)((e->geo.n[1] + TY - 1) / TY));
     hipLaunchKernelGGL((sp::k_depondt_fused2d<T, TX, TY, R>), grid, dim3(256), 0, e->stream, make_stencil2d<T>(e),
-                       make_site2d<T>(e, p), make_llg<T>(p, step, p->replica), e->d_flag, static_cast<const T*>(nin),
+                       make_site2d<T>(e, p), make_step_llg<T>(e, p, step), e->d_flag, static_cast<const T*>(nin),
                        static_cast<T*>(nout));
 }
 
@@ -563,7 +606,7 @@ void go_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* n
     const int ntiles = M.tiles_x * M.tiles_y;
     M.xcd_bands = (ntiles >= 8 && ntiles % 8 == 0) ? 1 : 0;
     hipLaunchKernelGGL((sp::k_fused2d_shape<T, S, NDMI, TX, TY, NT, SOLVER>), dim3((unsigned)ntiles), dim3(NT), 0, e->stream,
-                       shape_coef_for<T, S>(e), make_site2d<T>(e, p), make_llg<T>(p, step, p->replica), M, e->d_flag,
+                       shape_coef_for<T, S>(e), make_site2d<T>(e, p), make_step_llg<T>(e, p, step), M, e->d_flag,
                        static_cast<const T*>(nin), static_cast<T*>(nout));
 }
 
@@ -780,7 +823,7 @@ void go_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* 
     Z.xcd_bands = ((txy * nchunks) % 8 == 0) ? 1 : 0;
     hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, NDMI, TX, TY, SOLVER>), dim3((unsigned)(txy * nchunks)),
                        dim3(TX * TY), 0, e->stream, shape_coef3_for<T, S>(e), make_site2d<T>(e, p), Z,
-                       make_llg<T>(p, step, p->replica), e->d_flag, static_cast<const T*>(nin), static_cast<T*>(nout));
+                       make_step_llg<T>(e, p, step), e->d_flag, static_cast<const T*>(nin), static_cast<T*>(nout));
 }
 
 template <typename T, int TX, int TY, int SOLVER>
@@ -850,7 +893,7 @@ int launch_step(sp_engine* e, const sp_llg_params* p, uint64_t step, const void*
     const sp::Lattice L = make_lattice(e);
     const sp::BondCoef<T> C = make_coef<T>(e);
     const sp::Phys<T> P = make_phys<T>(e, p);
-    const sp::LLGArgs<T> A = make_llg<T>(p, step, p->replica);
+    const sp::LLGArgs<T> A = make_step_llg<T>(e, p, step);
     const void* gdd = nullptr;
     const void* gddp = nullptr;
     if (e->ham.ddi) {
@@ -1090,16 +1133,96 @@ int normals_dev(sp_engine* e, uint64_t seed, uint64_t step, uint32_t replica, ui
     return rc;
 }
 
+// Graph replay of sp_run.  Steps are grouped into chunks of C steps (the
+// observation interval, or kGraphChunk when nothing is observed); a chunk is
+// captured once as a HIP graph (C step launches, the observation, and a
+// one-thread kernel that advances the device step and files the observation)
+// and replayed for every later chunk with the same parameters, buffers and
+// step path.  The step kernels of a replayed chunk read the Philox step from
+// the device counter, so the replays reproduce the direct launches bit for bit.
+constexpr int64_t kGraphChunk = 32;
+constexpr int64_t kGraphMaxChunk = 1024;
+constexpr size_t kGraphCache = 8;
+
+bool same_params(const sp_llg_params& a, const sp_llg_params& b) {
+    return a.alpha == b.alpha && a.dt_ps == b.dt_ps && a.T_K == b.T_K && a.seed == b.seed &&
+           a.replica == b.replica && a.solver == b.solver;
+}
+
+std::string path_key(const sp_engine* e) {
+    return std::string(e->path) + "/" + std::to_string(e->tile_cfg) + "/" + std::to_string(e->tile3_cfg);
+}
+
 template <typename T>
-int run_impl(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t observe_every, sp_observation* obs) {
+int capture_chunk(sp_engine* e, const sp_llg_params* p, int C, bool observe, double tol, hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    HIPCHK(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+    void* a = e->d_n;
+    void* b = e->d_n2;
+    int rc = SP_OK;
+    e->cap_step_dev = e->d_step;
+    for (int k = 0; k < C && rc == SP_OK; ++k) {
+        e->cap_step_off = (unsigned int)k;
+        rc = launch_step<T>(e, p, e->step + (uint64_t)k, a, b);
+        std::swap(a, b);
+    }
+    e->cap_step_dev = nullptr;
+    e->cap_step_off = 0;
+    if (rc == SP_OK && observe) rc = launch_observe<T>(e, a, e->d_obs_stage, 0, true, e->d_step, C, tol);
+    if (rc == SP_OK)
+        hipLaunchKernelGGL(sp::k_run_chunk_end, dim3(1), dim3(64), 0, e->stream, e->d_step, e->d_obs_index,
+                           observe ? (const double*)e->d_obs_stage : nullptr, e->d_obs, (long long)e->obs_cap, C);
+    const hipError_t st = hipStreamEndCapture(e->stream, &g);
+    if (rc != SP_OK || st != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return rc != SP_OK ? rc : fail(e, SP_E_HIP, std::string("step graph capture: ") + hipGetErrorString(st));
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t si = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (si != hipSuccess) return fail(e, SP_E_HIP, std::string("step graph instantiate: ") + hipGetErrorString(si));
+    *out = x;
+    return SP_OK;
+}
+
+template <typename T>
+int chunk_graph(sp_engine* e, const sp_llg_params* p, int C, bool observe, double tol, hipGraphExec_t* out) {
+    const std::string pk = path_key(e);
+    for (const RunGraph& g : e->graphs)
+        if (same_params(g.p, *p) && g.steps == C && g.observe == observe && g.tol == tol && g.n_first == e->d_n &&
+            g.n_other == e->d_n2 && g.obs == e->d_obs && g.obs_cap == e->obs_cap && g.path == pk) {
+            *out = g.exec;
+            return SP_OK;
+        }
+    hipGraphExec_t x = nullptr;
+    int rc = capture_chunk<T>(e, p, C, observe, tol, &x);
+    if (rc) return rc;
+    if (e->graphs.size() >= kGraphCache) {
+        (void)hipGraphExecDestroy(e->graphs.front().exec);
+        e->graphs.erase(e->graphs.begin());
+    }
+    e->graphs.push_back(RunGraph{*p, C, observe, tol, e->d_n, e->d_n2, e->d_obs, (long long)e->obs_cap, pk, x});
+    *out = x;
+    return SP_OK;
+}
+
+// Runs n_steps steps (or fewer: a non-finite torque aborts the run, and with
+// tol > 0 an observation whose maximum torque is below tol stops it).  The
+// decision is taken on the device; the host reads it once at the end.
+template <typename T>
+int run_impl(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t observe_every, double tol,
+             sp_observation* obs, int64_t* steps_done) {
     const int64_t n_obs = observe_every > 0 ? n_steps / observe_every : 0;
     int rc;
     if (n_obs > e->obs_cap) {
         if ((rc = dalloc(e, e->d_obs, (size_t)n_obs * sp::OBS_NVALS * sizeof(double)))) return rc;
         e->obs_cap = n_obs;
     }
-    HIPCHK(e, hipMemsetAsync(e->d_flag, 0, sizeof(int), e->stream));
-    HIPCHK(e, hipMemsetAsync(e->d_abort_step, 0, sizeof(long long), e->stream));
+    sp::k_set_run_ctl<<<1, 64, 0, e->stream>>>(e->d_flag, e->d_abort_step, e->d_step, e->d_obs_index,
+                                               (unsigned long long)e->step, 0LL);
+    HIPCHK(e, hipGetLastError());
+    const uint64_t step0 = e->step;
     int64_t k = 0;
     const bool persist = std::strcmp(e->path, "persist2d") == 0 && p->solver == SP_SOLVER_DEPONDT;
     if (persist) {
@@ -1111,19 +1234,33 @@ int run_impl(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t obse
             if ((rc = launch_persist<T>(e, p, (int)chunk))) return rc;
             t += chunk;
             if (observe_every > 0 && t % observe_every == 0) {
-                rc = launch_observe<T>(e, e->d_n, e->d_obs + k * sp::OBS_NVALS, (long long)e->step, true);
+                rc = launch_observe<T>(e, e->d_n, e->d_obs + k * sp::OBS_NVALS, (long long)e->step, true, nullptr,
+                                       0, tol);
                 if (rc) return rc;
                 ++k;
             }
         }
     }
-    for (int64_t t = 0; !persist && t < n_steps; ++t) {
+    int64_t t = 0;
+    const int64_t C = observe_every > 0 ? observe_every : kGraphChunk;
+    if (!persist && e->graphs_on && !e->ham.ddi && C <= kGraphMaxChunk && n_steps >= C) {
+        for (const int64_t chunks = n_steps / C; t < chunks * C; t += C) {
+            hipGraphExec_t x = nullptr;
+            if ((rc = chunk_graph<T>(e, p, (int)C, observe_every > 0, tol, &x))) return rc;
+            HIPCHK(e, hipGraphLaunch(x, e->stream));
+            if (C % 2) std::swap(e->d_n, e->d_n2);
+            e->step += (uint64_t)C;
+            if (observe_every > 0) ++k;
+        }
+    }
+    for (; !persist && t < n_steps; ++t) {
         rc = launch_step<T>(e, p, e->step, e->d_n, e->d_n2);
         if (rc) return rc;
         std::swap(e->d_n, e->d_n2);
         ++e->step;
         if (observe_every > 0 && (t + 1) % observe_every == 0) {
-            rc = launch_observe<T>(e, e->d_n, e->d_obs + k * sp::OBS_NVALS, (long long)e->step, true);
+            rc = launch_observe<T>(e, e->d_n, e->d_obs + k * sp::OBS_NVALS, (long long)e->step, true, nullptr, 0,
+                                   tol);
             if (rc) return rc;
             ++k;
         }
@@ -1132,14 +1269,9 @@ int run_impl(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t obse
     long long astep = 0;
     HIPCHK(e, hipMemcpyAsync(&flag, e->d_flag, sizeof(int), hipMemcpyDeviceToHost, e->stream));
     HIPCHK(e, hipMemcpyAsync(&astep, e->d_abort_step, sizeof(long long), hipMemcpyDeviceToHost, e->stream));
-    if (n_obs > 0 && obs) {
-        std::vector<double> h((size_t)n_obs * sp::OBS_NVALS);
+    std::vector<double> h((size_t)n_obs * sp::OBS_NVALS);
+    if (n_obs > 0 && obs)
         HIPCHK(e, hipMemcpyAsync(h.data(), e->d_obs, h.size() * sizeof(double), hipMemcpyDeviceToHost, e->stream));
-        HIPCHK(e, hipStreamSynchronize(e->stream));
-        const int64_t step0 = (int64_t)e->step - n_steps;
-        for (int64_t q = 0; q < n_obs; ++q)
-            obs_from(&h[(size_t)q * sp::OBS_NVALS], step0 + (q + 1) * observe_every, e->N, &obs[q]);
-    }
     HIPCHK(e, hipStreamSynchronize(e->stream));
     if (persist) {
         int pst = 0;
@@ -1150,7 +1282,21 @@ int run_impl(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t obse
             return fail(e, SP_E_HIP, "persist2d: a tile timed out waiting for its neighbours; spins are invalid");
         }
     }
-    if (flag)
+    int64_t done = n_steps;
+    if (flag == sp::RUN_CONVERGED) {
+        // the steps after the converged observation were skipped: the state
+        // is the one observed, and the buffers swapped once per skipped step
+        done = (int64_t)(astep - (long long)step0);
+        if ((n_steps - done) % 2) std::swap(e->d_n, e->d_n2);
+        e->step = step0 + (uint64_t)done;
+    }
+    if (steps_done) *steps_done = done;
+    if (n_obs > 0 && obs) {
+        const int64_t n_kept = observe_every > 0 ? std::min<int64_t>(n_obs, done / observe_every) : 0;
+        for (int64_t q = 0; q < n_kept; ++q)
+            obs_from(&h[(size_t)q * sp::OBS_NVALS], (int64_t)step0 + (q + 1) * observe_every, e->N, &obs[q]);
+    }
+    if (flag == sp::RUN_NONFINITE)
         return fail(e, SP_E_NONFINITE, "non-finite torque observed after step " + std::to_string(astep) +
                                            "; later steps were skipped");
     return SP_OK;
@@ -1262,7 +1408,8 @@ int sp_create(sp_engine** out, int device, int precision, void* hip_stream) {
         e->own_stream = true;
     }
     if (dalloc(e, e->d_flag, sizeof(int)) || dalloc(e, e->d_abort_step, sizeof(long long)) ||
-        dalloc(e, e->d_pstatus, sizeof(int)) ||
+        dalloc(e, e->d_pstatus, sizeof(int)) || dalloc(e, e->d_step, sizeof(unsigned long long)) ||
+        dalloc(e, e->d_obs_index, sizeof(long long)) || dalloc(e, e->d_obs_stage, sp::OBS_NVALS * sizeof(double)) ||
         hipHostMalloc((void**)&e->h_pin, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         sp_destroy(e);
         return SP_E_NOMEM;
@@ -1275,15 +1422,24 @@ int sp_create(sp_engine** out, int device, int precision, void* hip_stream) {
 void sp_destroy(sp_engine* e) {
     if (!e) return;
     (void)hipSetDevice(e->device);
-    // a borrowed stream may already be destroyed by its owner: wait on the device
-    (void)hipDeviceSynchronize();
+    // Wait for the engine's own work only: its stream if it owns one; a
+    // borrowed stream may already be gone, so then the device is drained.
+    // The flag lines of the persistent path go first, before any other
+    // buffer the last launch touched.
+    if (e->own_stream && e->stream)
+        (void)hipStreamSynchronize(e->stream);
+    else
+        (void)hipDeviceSynchronize();
+    dfree(*reinterpret_cast<void**>(&e->d_pflags));
+    dfree(*reinterpret_cast<void**>(&e->d_pstatus));
     free_state_buffers(e);
     dfree(*reinterpret_cast<void**>(&e->d_partials));
     dfree(*reinterpret_cast<void**>(&e->d_obs));
     dfree(*reinterpret_cast<void**>(&e->d_flag));
     dfree(*reinterpret_cast<void**>(&e->d_abort_step));
-    dfree(*reinterpret_cast<void**>(&e->d_pflags));
-    dfree(*reinterpret_cast<void**>(&e->d_pstatus));
+    dfree(*reinterpret_cast<void**>(&e->d_step));
+    dfree(*reinterpret_cast<void**>(&e->d_obs_index));
+    dfree(*reinterpret_cast<void**>(&e->d_obs_stage));
     if (e->h_pin) (void)hipHostFree(e->h_pin);
     surrogate_free(e->sur);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
@@ -1740,7 +1896,26 @@ int sp_run(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t observ
     if ((rc = check_llg(e, p))) return rc;
     if (n_steps < 0 || observe_every < 0) return fail(e, SP_E_ARG, "n_steps and observe_every must be >= 0");
     (void)hipSetDevice(e->device);
-    return DISPATCH(e, run_impl, e, p, n_steps, observe_every, obs);
+    return DISPATCH(e, run_impl, e, p, n_steps, observe_every, 0.0, obs, nullptr);
+}
+
+int sp_run_tol(sp_engine* e, const sp_llg_params* p, int64_t max_steps, int64_t observe_every, double tol,
+               sp_observation* obs, int64_t* steps_done) {
+    if (steps_done) *steps_done = 0;
+    int rc = check_ready(e, true);
+    if (rc) return rc;
+    if ((rc = check_llg(e, p))) return rc;
+    if (max_steps < 0 || observe_every <= 0) return fail(e, SP_E_ARG, "max_steps must be >= 0, observe_every > 0");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(e, SP_E_ARG, "tol must be finite and > 0");
+    (void)hipSetDevice(e->device);
+    return DISPATCH(e, run_impl, e, p, max_steps, observe_every, tol, obs, steps_done);
+}
+
+int sp_set_graph_replay(sp_engine* e, int enable) {
+    if (!e) return SP_E_ARG;
+    e->graphs_on = enable != 0;
+    if (!e->graphs_on) drop_graphs(e);
+    return SP_OK;
 }
 
 int sp_synchronize(sp_engine* e) {
@@ -1969,6 +2144,8 @@ struct sp_gneb {
     double* s3 = nullptr;   // [3M]: |tau|^2, g.tau, l^2
     double* vf = nullptr;   // [2]
     int* types = nullptr;   // [M] image types (0 normal, 1 climbing, 2 falling)
+    double* fmax = nullptr; // [(M-2) nblk] block maxima of |F_i|^2 (convergence test)
+    int* stop = nullptr;    // [2]: converged flag, iteration that passed
     int64_t iterations = 0;
     sp_batch* batch = nullptr;   // the batch that advances the chain, if attached
     std::string err;
@@ -2012,7 +2189,7 @@ struct sp_batch {
 namespace {
 
 template <typename T>
-int gneb_enqueue(sp_gneb* G, int n_iter, hipStream_t st);
+int gneb_enqueue(sp_gneb* G, int n_iter, hipStream_t st, double tol = 0.0);
 
 int bfail(sp_batch* b, int code, const std::string& msg) {
     if (b) b->err = msg;
@@ -2486,7 +2663,7 @@ bool gneb_tiles(const sp_gneb* G) {
 }
 
 template <typename T, int S>
-void gneb_grad_shape(sp_gneb* G, hipStream_t st) {
+void gneb_grad_shape(sp_gneb* G, hipStream_t st, const int* stop) {
     sp_engine* e = G->e;
     const sp::GnebDims d{G->M, G->N, G->nblk};
     const sp::ShapeCoef<double> C = shape_coef_for<double, S>(e);
@@ -2497,13 +2674,13 @@ void gneb_grad_shape(sp_gneb* G, hipStream_t st) {
     const dim3 grid((unsigned)G->nblk, (unsigned)G->M);
     if (e->shape_ndmi)
         hipLaunchKernelGGL((sp::k_gneb_grad_shape<T, S, sp::ShapeTab<S>::NB0>), grid, dim3(256), 0, st, d, C, Q,
-                           tiles_x, x, g, G->epart);
+                           tiles_x, x, g, G->epart, stop);
     else
-        hipLaunchKernelGGL((sp::k_gneb_grad_shape<T, S, 0>), grid, dim3(256), 0, st, d, C, Q, tiles_x, x, g, G->epart);
+        hipLaunchKernelGGL((sp::k_gneb_grad_shape<T, S, 0>), grid, dim3(256), 0, st, d, C, Q, tiles_x, x, g, G->epart, stop);
 }
 
 template <typename T>
-int gneb_forces(sp_gneb* G, bool update_v, hipStream_t st) {
+int gneb_forces(sp_gneb* G, bool update_v, hipStream_t st, const int* stop = nullptr) {
     sp_engine* e = G->e;
     const sp::GnebDims d{G->M, G->N, G->nblk};
     T* x = static_cast<T*>(G->x);
@@ -2511,24 +2688,26 @@ int gneb_forces(sp_gneb* G, bool update_v, hipStream_t st) {
     T* tau = static_cast<T*>(G->tau);
     if (gneb_tiles(G)) {
         switch (e->shape) {
-            case sp::SH_SQ1: gneb_grad_shape<T, sp::SH_SQ1>(G, st); break;
-            case sp::SH_SQ2: gneb_grad_shape<T, sp::SH_SQ2>(G, st); break;
-            case sp::SH_SQ3: gneb_grad_shape<T, sp::SH_SQ3>(G, st); break;
-            case sp::SH_TRI1: gneb_grad_shape<T, sp::SH_TRI1>(G, st); break;
-            case sp::SH_TRI2: gneb_grad_shape<T, sp::SH_TRI2>(G, st); break;
-            default: gneb_grad_shape<T, sp::SH_TRI3>(G, st); break;
+            case sp::SH_SQ1: gneb_grad_shape<T, sp::SH_SQ1>(G, st, stop); break;
+            case sp::SH_SQ2: gneb_grad_shape<T, sp::SH_SQ2>(G, st, stop); break;
+            case sp::SH_SQ3: gneb_grad_shape<T, sp::SH_SQ3>(G, st, stop); break;
+            case sp::SH_TRI1: gneb_grad_shape<T, sp::SH_TRI1>(G, st, stop); break;
+            case sp::SH_TRI2: gneb_grad_shape<T, sp::SH_TRI2>(G, st, stop); break;
+            default: gneb_grad_shape<T, sp::SH_TRI3>(G, st, stop); break;
         }
     } else {
         hipLaunchKernelGGL((sp::k_gneb_grad<T>), dim3(G->nblk, G->M), dim3(256), 0, st, d, make_lattice(e),
-                           make_coef64(e), make_phys<double>(e, nullptr), x, g, G->epart);
+                           make_coef64(e), make_phys<double>(e, nullptr), x, g, G->epart, stop);
     }
     hipLaunchKernelGGL((sp::k_gneb_tangent<T>), dim3(G->nblk, G->M), dim3(256), 0, st, d, x, g, G->epart, G->E, tau,
-                       G->tpart);
+                       G->tpart, stop);
     hipLaunchKernelGGL((sp::k_gneb_force<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, st, d, (T)G->k,
                        (T)(G->dt / (2.0 * G->m)), update_v ? 1 : 0, x, g, tau, G->tpart, G->s3, G->types,
-                       static_cast<T*>(G->F), static_cast<const T*>(G->Fp), static_cast<T*>(G->v), G->part);
+                       static_cast<T*>(G->F), static_cast<const T*>(G->Fp), static_cast<T*>(G->v), G->part,
+                       stop ? G->fmax : nullptr, stop);
     if (update_v)
-        hipLaunchKernelGGL((sp::k_gneb_sum<2>), dim3(1), dim3(256), 0, st, G->part, (G->M - 2) * G->nblk, G->vf);
+        hipLaunchKernelGGL((sp::k_gneb_sum<2>), dim3(1), dim3(256), 0, st, G->part, (G->M - 2) * G->nblk, G->vf,
+                           stop);
     hipError_t s = hipGetLastError();
     if (s != hipSuccess) return gfail(G, SP_E_HIP, hipGetErrorString(s));
     return SP_OK;
@@ -2546,17 +2725,26 @@ int gneb_project(sp_gneb* G, hipStream_t st) {
 
 // n_iter velocity-projection iterations enqueued on st (also under graph
 // capture); the iteration counter is the caller's business.
+// With tol > 0 every iteration ends with the convergence test (largest
+// per-spin force of the interior images below tol); once it passes, the
+// launches of the remaining iterations return at once, so the chain is the
+// one whose forces passed, projected as after any run.
 template <typename T>
-int gneb_enqueue(sp_gneb* G, int n_iter, hipStream_t st) {
+int gneb_enqueue(sp_gneb* G, int n_iter, hipStream_t st, double tol) {
     const sp::GnebDims d{G->M, G->N, G->nblk};
+    const int* stop = tol > 0.0 ? G->stop : nullptr;
+    if (stop) hipLaunchKernelGGL(sp::k_gneb_clear_stop, dim3(1), dim3(64), 0, st, G->stop, G->stop + 1);
     // the projection of each iteration is applied by the next move; the
     // state between calls is always projected (v, F_prev final)
     for (int it = 0; it < n_iter; ++it) {
         hipLaunchKernelGGL((sp::k_gneb_move<T>), dim3(G->nblk, G->M - 2), dim3(256), 0, st, d, (T)G->dt,
                            (T)(G->dt * G->dt / (2.0 * G->m)), it > 0 ? 1 : 0, G->vf, static_cast<const T*>(G->F),
-                           static_cast<T*>(G->x), static_cast<T*>(G->v), static_cast<T*>(G->Fp));
-        int rc = gneb_forces<T>(G, true, st);
+                           static_cast<T*>(G->x), static_cast<T*>(G->v), static_cast<T*>(G->Fp), stop);
+        int rc = gneb_forces<T>(G, true, st, stop);
         if (rc) return rc;
+        if (stop)
+            hipLaunchKernelGGL(sp::k_gneb_converged, dim3(1), dim3(256), 0, st, G->fmax, (G->M - 2) * G->nblk,
+                               tol * tol, G->stop, G->stop + 1, it);
     }
     if (n_iter > 0) return gneb_project<T>(G, st);
     return SP_OK;
@@ -2602,7 +2790,8 @@ int gneb_download(sp_gneb* G, const void* src, double* out, size_t count) {
 }
 
 void gneb_free(sp_gneb* G) {
-    void* ps[] = {G->x, G->v, G->F, G->Fp, G->g, G->tau, G->part, G->epart, G->tpart, G->E, G->s3, G->vf, G->types};
+    void* ps[] = {G->x,  G->v,  G->F,  G->Fp, G->g,     G->tau,  G->part, G->epart,
+                  G->tpart, G->E, G->s3, G->vf, G->types, G->fmax, G->stop};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }
@@ -2644,14 +2833,17 @@ int sp_gneb_create(sp_gneb** out, sp_engine* e, int n_images, const double* chai
         hipMalloc((void**)&G->E, G->M * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&G->s3, 3 * G->M * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&G->vf, 2 * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&G->types, G->M * sizeof(int)) != hipSuccess) {
+        hipMalloc((void**)&G->types, G->M * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&G->fmax, (size_t)(G->M - 2) * G->nblk * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&G->stop, 2 * sizeof(int)) != hipSuccess) {
         gneb_free(G);
         delete G;
         return fail(e, SP_E_NOMEM, "GNEB allocation failed");
     }
     if (hipMemset(G->v, 0, vb) != hipSuccess || hipMemset(G->F, 0, vb) != hipSuccess ||
         hipMemset(G->Fp, 0, vb) != hipSuccess || hipMemset(G->tau, 0, vb) != hipSuccess ||
-        hipMemset(G->vf, 0, 2 * sizeof(double)) != hipSuccess || hipMemset(G->types, 0, G->M * sizeof(int)) != hipSuccess) {
+        hipMemset(G->vf, 0, 2 * sizeof(double)) != hipSuccess || hipMemset(G->types, 0, G->M * sizeof(int)) != hipSuccess ||
+        hipMemset(G->stop, 0, 2 * sizeof(int)) != hipSuccess) {
         gneb_free(G);
         delete G;
         return fail(e, SP_E_HIP, "GNEB initialisation failed");
@@ -2712,6 +2904,27 @@ int sp_gneb_iterate(sp_gneb* G, int n_iter) {
     const int rc = G->e->precision == SP_F64 ? gneb_iterate<double>(G, n_iter) : gneb_iterate<float>(G, n_iter);
     if (rc) return rc;
     if (hipStreamSynchronize(G->e->stream) != hipSuccess) return gfail(G, SP_E_HIP, "synchronisation failed");
+    return SP_OK;
+}
+
+int sp_gneb_iterate_tol(sp_gneb* G, int max_iter, double tol, int* iters_done) {
+    if (iters_done) *iters_done = 0;
+    if (!G) return SP_E_ARG;
+    if (max_iter < 0) return gfail(G, SP_E_ARG, "max_iter must be >= 0");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return gfail(G, SP_E_ARG, "tol must be finite and > 0");
+    if (G->batch) return gfail(G, SP_E_ORDER, "the chain is attached to a batch: sp_batch_run advances it");
+    (void)hipSetDevice(G->e->device);
+    const int rc = G->e->precision == SP_F64 ? gneb_enqueue<double>(G, max_iter, G->e->stream, tol)
+                                             : gneb_enqueue<float>(G, max_iter, G->e->stream, tol);
+    if (rc) return rc;
+    int st[2] = {0, -1};
+    if (max_iter > 0 &&
+        (hipMemcpyAsync(st, G->stop, sizeof(st), hipMemcpyDeviceToHost, G->e->stream) != hipSuccess ||
+         hipStreamSynchronize(G->e->stream) != hipSuccess))
+        return gfail(G, SP_E_HIP, "synchronisation failed");
+    const int done = st[0] ? st[1] + 1 : max_iter;
+    G->iterations += done;
+    if (iters_done) *iters_done = done;
     return SP_OK;
 }
 

@@ -49,7 +49,23 @@ struct LLGArgs {
     T dt;
     int thermal;
     ThermalKey key;
+    // Replayed step graphs: when set, the Philox step is *step_dev + step_off
+    // (the launch's place in its chunk) instead of the step words of key.
+    const unsigned long long* step_dev;
+    unsigned int step_off;
 };
+
+// The launch's own copy of the LLG arguments with the step of a replayed
+// graph filled in (one uniform load; unchanged when step_dev is null).
+template <typename T>
+__device__ __forceinline__ LLGArgs<T> resolve_step(LLGArgs<T> A) {
+    if (A.step_dev) {
+        const unsigned long long s = *A.step_dev + A.step_off;
+        A.key.step_lo = (uint32_t)s;
+        A.key.step_hi = (uint32_t)(s >> 32);
+    }
+    return A;
+}
 
 // Generic lattice: bonds of basis atom b are bond[bstart[b] .. bstart[b+1]).
 struct Lattice {
@@ -190,11 +206,12 @@ __global__ void __launch_bounds__(256) k_gradient(Lattice L, BondCoef<T> C, Phys
 //   SIB:     np = midpoint (n_i + x_i)/2 with x_i the implicit-midpoint
 //            stage with A_i frozen (Appendix C); Aout unused.
 template <typename T, int SOLVER>
-__global__ void __launch_bounds__(256) k_predict(Lattice L, BondCoef<T> C, Phys<T> P, LLGArgs<T> A,
+__global__ void __launch_bounds__(256) k_predict(Lattice L, BondCoef<T> C, Phys<T> P, LLGArgs<T> A_arg,
                                                  const int* __restrict__ abort_flag,
                                                  const T* __restrict__ n, const T* __restrict__ gdd,
                                                  T* __restrict__ np, T* __restrict__ Aout) {
     if (abort_flag && *abort_flag) return;
+    const LLGArgs<T> A = resolve_step(A_arg);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L.N) return;
     const int beta = basis_of(L, i);
@@ -222,12 +239,13 @@ __global__ void __launch_bounds__(256) k_predict(Lattice L, BondCoef<T> C, Phys<
 //   Heun:    n(t+dt) = normalised n + dt (f + np x A^p)/2;
 //   SIB:     n(t+dt) = midpoint stage of n with A(m) frozen (np holds m).
 template <typename T, int SOLVER>
-__global__ void __launch_bounds__(256) k_correct(Lattice L, BondCoef<T> C, Phys<T> P, LLGArgs<T> A,
+__global__ void __launch_bounds__(256) k_correct(Lattice L, BondCoef<T> C, Phys<T> P, LLGArgs<T> A_arg,
                                                  const int* __restrict__ abort_flag,
                                                  const T* __restrict__ n, const T* __restrict__ np,
                                                  const T* __restrict__ gddp, const T* __restrict__ Ain,
                                                  T* __restrict__ nout) {
     if (abort_flag && *abort_flag) return;
+    const LLGArgs<T> A = resolve_step(A_arg);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L.N) return;
     const int beta = basis_of(L, i);
@@ -300,10 +318,11 @@ __device__ __forceinline__ V3<T> lds_field(const Stencil2D<T>& S, const Site2D<T
 }
 
 template <typename T, int TX, int TY, int R>
-__global__ void __launch_bounds__(256) k_depondt_fused2d(Stencil2D<T> S, Site2D<T> Q, LLGArgs<T> A,
+__global__ void __launch_bounds__(256) k_depondt_fused2d(Stencil2D<T> S, Site2D<T> Q, LLGArgs<T> A_arg,
                                                          const int* __restrict__ abort_flag,
                                                          const T* __restrict__ n, T* __restrict__ nout) {
     if (abort_flag && *abort_flag) return;
+    const LLGArgs<T> A = resolve_step(A_arg);
     constexpr int WN = TX + 4 * R, HN = TY + 4 * R;   // spin tile with 2R halo
     constexpr int WP = TX + 2 * R, HP = TY + 2 * R;   // predictor tile with R halo
     constexpr int PN = WN * HN, PP = WP * HP, PT = TX * TY;

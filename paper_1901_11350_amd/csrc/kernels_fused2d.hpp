@@ -426,10 +426,11 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
 }
 
 template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER = SOLVER_DEPONDT>
-__global__ void __launch_bounds__(NT) k_fused2d_shape(ShapeCoef<T> C, Site2D<T> Q, LLGArgs<T> A, TileMap M,
+__global__ void __launch_bounds__(NT) k_fused2d_shape(ShapeCoef<T> C, Site2D<T> Q, LLGArgs<T> A_arg, TileMap M,
                                                       const int* __restrict__ abort_flag, const T* __restrict__ n,
                                                       T* __restrict__ nout) {
     if (abort_flag && *abort_flag) return;
+    const LLGArgs<T> A = resolve_step(A_arg);
     __shared__ TileLDS<T, S, TX, TY> L;
     const int ntiles = M.tiles_x * M.tiles_y;
     int tile = blockIdx.x;

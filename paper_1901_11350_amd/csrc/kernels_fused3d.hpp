@@ -125,10 +125,11 @@ __device__ __forceinline__ int wrap_plane(int z, int nc, int per, bool& in) {
 }
 
 template <typename T, int S, int NDMI, int TX, int TY, int SOLVER>
-__global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site2D<T> Q, Site3D Z, LLGArgs<T> A,
+__global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site2D<T> Q, Site3D Z, LLGArgs<T> A_arg,
                                                             const int* __restrict__ abort_flag,
                                                             const T* __restrict__ n, T* __restrict__ nout) {
     if (abort_flag && *abort_flag) return;
+    const LLGArgs<T> A = resolve_step(A_arg);
     using PL = PlaneLDS<T, S, TX, TY>;
     constexpr int R = PL::R, WN = PL::WN, PN = PL::PN, WP = PL::WP, PP = PL::PP;
     constexpr int NT = TX * TY;

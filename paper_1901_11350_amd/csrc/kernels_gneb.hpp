@@ -69,6 +69,17 @@ __device__ __forceinline__ void row_sum(const double* __restrict__ part, int nbl
     __syncthreads();
 }
 
+// Maximum over the block (thread 0 receives it).
+__device__ __forceinline__ double block_max(double v) {
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_max(v);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) v = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    return v;
+}
+
 struct GnebDims {
     int M;         // images
     int N;         // spins per image
@@ -78,7 +89,9 @@ struct GnebDims {
 template <typename T>
 __global__ void __launch_bounds__(256) k_gneb_move(GnebDims d, T dt, T half_dt2_m, int project,
                                                    const double* __restrict__ vf_ff, const T* __restrict__ F,
-                                                   T* __restrict__ x, T* __restrict__ v, T* __restrict__ Fp) {
+                                                   T* __restrict__ x, T* __restrict__ v, T* __restrict__ Fp,
+    const int* __restrict__ stop) {
+    if (stop && *stop) return;   // the chain has converged: the rest of the run is skipped
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int im = blockIdx.y + 1;   // interior images only
     if (i >= d.N) return;
@@ -114,7 +127,9 @@ __global__ void __launch_bounds__(256) k_gneb_move(GnebDims d, T dt, T half_dt2_
 template <typename T>
 __global__ void __launch_bounds__(256) k_gneb_grad(GnebDims d, Lattice L, BondCoef<double> C, Phys<double> P,
                                                    const T* __restrict__ x, T* __restrict__ g,
-                                                   double* __restrict__ part) {
+                                                   double* __restrict__ part,
+    const int* __restrict__ stop) {
+    if (stop && *stop) return;   // the chain has converged: the rest of the run is skipped
     // field and energy in FP64 from the stored spins (type T): the image
     // energies decide the tangent's branch, so they are formed in the
     // reference's precision for both engine precisions; g is stored as T
@@ -145,7 +160,9 @@ __global__ void __launch_bounds__(256) k_gneb_grad(GnebDims d, Lattice L, BondCo
 template <typename T, int S, int NDMI>
 __global__ void __launch_bounds__(256) k_gneb_grad_shape(GnebDims d, ShapeCoef<double> C, Site2D<double> Q,
                                                          int tiles_x, const T* __restrict__ x, T* __restrict__ g,
-                                                         double* __restrict__ part) {
+                                                         double* __restrict__ part,
+    const int* __restrict__ stop) {
+    if (stop && *stop) return;   // the chain has converged: the rest of the run is skipped
     constexpr int TX = 64, TY = 4, NT = 256;
     constexpr int R = ShapeTab<S>::R, W = TX + 2 * R, H = TY + 2 * R, P = W * H, KST = (P + NT - 1) / NT;
     __shared__ V4<double> sN[P];
@@ -192,7 +209,9 @@ __global__ void __launch_bounds__(256) k_gneb_grad_shape(GnebDims d, ShapeCoef<d
 // Sum NV-value partials of each of `rows` rows (blocks per row = nblk) in a
 // fixed order: out[row*NV + k].
 template <int NV>
-__global__ void __launch_bounds__(256) k_gneb_sum(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_gneb_sum(const double* __restrict__ part, int nblk, double* __restrict__ out,
+    const int* __restrict__ stop) {
+    if (stop && *stop) return;   // the chain has converged: the rest of the run is skipped
     const int row = blockIdx.x;
     double acc[NV];
 #pragma unroll
@@ -213,7 +232,9 @@ __global__ void __launch_bounds__(256) k_gneb_sum(const double* __restrict__ par
 template <typename T>
 __global__ void __launch_bounds__(256) k_gneb_tangent(GnebDims d, const T* __restrict__ x, const T* __restrict__ g,
                                                       const double* __restrict__ epart, double* __restrict__ E,
-                                                      T* __restrict__ tau, double* __restrict__ part) {
+                                                      T* __restrict__ tau, double* __restrict__ part,
+    const int* __restrict__ stop) {
+    if (stop && *stop) return;   // the chain has converged: the rest of the run is skipped
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int im = blockIdx.y;
     // energies of this image and its neighbours
@@ -275,7 +296,9 @@ __global__ void __launch_bounds__(256) k_gneb_force(GnebDims d, T k_spring, T dt
                                                     const T* __restrict__ tau, const double* __restrict__ tpart,
                                                     double* __restrict__ s3, const int* __restrict__ types,
                                                     T* __restrict__ F, const T* __restrict__ Fp, T* __restrict__ v,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part,
+    double* __restrict__ fmax_part, const int* __restrict__ stop) {
+    if (stop && *stop) return;   // the chain has converged: the rest of the run is skipped
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int im = blockIdx.y + 1;
     // |tau|^2, g.tau, l^2 of this image and of the one before
@@ -310,11 +333,41 @@ __global__ void __launch_bounds__(256) k_gneb_force(GnebDims d, T k_spring, T dt
         }
         acc[1] = (double)dot(f, f);
     }
+    const double f2 = acc[1];
     block_sums<2>(acc);
+    if (fmax_part) {
+        const double m = block_max(f2);
+        if (threadIdx.x == 0) fmax_part[(size_t)(im - 1) * d.nblk + blockIdx.x] = m;
+    }
     if (threadIdx.x == 0) {
         double* o = part + ((size_t)(im - 1) * d.nblk + blockIdx.x) * 2;
         o[0] = acc[0];
         o[1] = acc[1];
+    }
+}
+
+// Convergence test of a chain relaxation: the largest per-spin force
+// |F_{v,i}| over the interior images below tol (compared as squares).  Sets
+// *stop and records the iteration that passed; later launches of the run
+// see *stop and return.
+__global__ void __launch_bounds__(256) k_gneb_converged(const double* __restrict__ fmax_part, int n,
+                                                        double tol2, int* __restrict__ stop,
+                                                        int* __restrict__ stop_iter, int iter) {
+    if (*stop) return;
+    double m = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) m = fmax(m, fmax_part[k]);
+    m = block_max(m);
+    if (threadIdx.x == 0 && m < tol2) {
+        *stop = 1;
+        *stop_iter = iter;
+    }
+}
+
+// Start of a run with a convergence test.
+__global__ void k_gneb_clear_stop(int* __restrict__ stop, int* __restrict__ stop_iter) {
+    if (threadIdx.x == 0) {
+        *stop = 0;
+        *stop_iter = -1;
     }
 }
 

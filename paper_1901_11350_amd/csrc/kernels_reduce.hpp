@@ -102,9 +102,21 @@ __global__ void __launch_bounds__(256) k_observe_partial(Lattice L, BondCoef<T> 
 
 // Final stage: rows of partials -> out[OBS_NVALS]; raises *abort_flag when a
 // non-finite torque was seen, and records the step in abort_step.
+// Run control flags (abort_flag): 0 running; 1 a non-finite torque was seen
+// (the run aborts); 2 the convergence test passed (the run stops).  Step
+// kernels return at once while the flag is nonzero.
+enum { RUN_GO = 0, RUN_NONFINITE = 1, RUN_CONVERGED = 2 };
+
+// Stage 2.  With abort_flag set, the observation also decides whether the
+// run goes on: a non-finite torque aborts it; with tol > 0, a maximum torque
+// |n x g| below tol (the convergence test, in FP64) stops it.  *abort_step
+// records the step of that observation: `step`, or *step_dev + step_off in
+// a replayed graph.
 __global__ void __launch_bounds__(256) k_observe_final(const double* __restrict__ partials, int rows,
                                                        double* __restrict__ out, int* __restrict__ abort_flag,
-                                                       long long* __restrict__ abort_step, long long step) {
+                                                       long long* __restrict__ abort_step, long long step,
+                                                       const unsigned long long* __restrict__ step_dev,
+                                                       int step_off, double tol) {
     double acc[OBS_NVALS];
 #pragma unroll
     for (int k = 0; k < OBS_NVALS; ++k) acc[k] = 0.0;
@@ -119,11 +131,46 @@ __global__ void __launch_bounds__(256) k_observe_final(const double* __restrict_
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < OBS_NVALS; ++k) out[k] = acc[k];
-        if (abort_flag && acc[OBS_NONFINITE] > 0.0 && *abort_flag == 0) {
-            *abort_flag = 1;
-            *abort_step = step;
+        if (abort_flag && *abort_flag == RUN_GO) {
+            const long long s = step_dev ? (long long)(*step_dev + (unsigned long long)step_off) : step;
+            if (acc[OBS_NONFINITE] > 0.0) {
+                *abort_flag = RUN_NONFINITE;
+                *abort_step = s;
+            } else if (tol > 0.0 && acc[OBS_TMAX] < tol) {
+                *abort_flag = RUN_CONVERGED;
+                *abort_step = s;
+            }
         }
     }
+}
+
+// Start of a run: clear the run flag and set the device step and the index
+// of the next observation row (a kernel rather than memsets, so that the
+// same values reach the device in stream order on every path).
+__global__ void k_set_run_ctl(int* __restrict__ flag, long long* __restrict__ abort_step,
+                              unsigned long long* __restrict__ step_dev, long long* __restrict__ obs_index,
+                              unsigned long long step, long long index) {
+    if (threadIdx.x != 0) return;
+    *flag = RUN_GO;
+    *abort_step = 0;
+    *step_dev = step;
+    *obs_index = index;
+}
+
+// End of a replayed chunk of `steps` steps: advance the device step and,
+// when the chunk ends with an observation, move it from the staging row to
+// the next row of the run's observation array (rows past cap are dropped).
+__global__ void k_run_chunk_end(unsigned long long* __restrict__ step_dev, long long* __restrict__ obs_index,
+                                const double* __restrict__ stage, double* __restrict__ obs, long long cap,
+                                int steps) {
+    if (threadIdx.x != 0) return;
+    if (stage) {
+        const long long q = *obs_index;
+        if (q < cap)
+            for (int k = 0; k < OBS_NVALS; ++k) obs[q * OBS_NVALS + k] = stage[k];
+        *obs_index = q + 1;
+    }
+    *step_dev += (unsigned long long)steps;
 }
 
 }  // namespace sp

@@ -9,8 +9,10 @@ raises ``RuntimeError`` -- there is no CPU fallback.
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -28,13 +30,15 @@ EXPORTS = [
     "sp_create", "sp_destroy", "sp_last_error", "sp_version", "sp_set_geometry",
     "sp_set_hamiltonian", "sp_set_pairs", "sp_num_sites", "sp_get_bonds", "sp_set_spins", "sp_get_spins",
     "sp_set_spins_dev", "sp_get_spins_dev", "sp_set_step", "sp_get_step", "sp_gradient",
-    "sp_gradient_dev", "sp_energy", "sp_observe", "sp_llg_step", "sp_run", "sp_synchronize",
+    "sp_gradient_dev", "sp_energy", "sp_observe", "sp_llg_step", "sp_run", "sp_run_tol",
+    "sp_set_graph_replay", "sp_synchronize",
     "sp_dipole_gradient", "sp_dipole_gradient_dev", "sp_thermal_normals", "sp_step_path",
     "sp_set_step_path", "sp_autotune", "sp_mc_run",
     "sp_batch_create", "sp_batch_destroy", "sp_batch_last_error", "sp_batch_add", "sp_batch_run",
     "sp_batch_get_spins", "sp_batch_replica_info", "sp_batch_set_chunk", "sp_batch_get_step",
     "sp_batch_autotune", "sp_batch_add_gneb",
     "sp_gneb_create", "sp_gneb_destroy", "sp_gneb_last_error", "sp_gneb_set_image_type", "sp_gneb_iterate",
+    "sp_gneb_iterate_tol",
     "sp_gneb_get_chain", "sp_gneb_get_forces",
     "sp_ddi_init", "sp_ddi_num_params", "sp_ddi_set_params", "sp_ddi_get_params", "sp_ddi_label_dev",
     "sp_ddi_forward_dev", "sp_ddi_loss_grad_dev", "sp_ddi_train_dev", "sp_ddi_configure", "sp_ddi_stats",
@@ -87,6 +91,23 @@ class sp_observation(ctypes.Structure):
 
 _lib = None
 
+# Every live handle, closed at interpreter exit (batches, then chains, then
+# engines) so that no HIP call is left to finalisers that run while the
+# interpreter and the libraries it loaded are being torn down.
+_live = weakref.WeakSet()
+
+
+def close_all():
+    """Close every Batch, Gneb and Engine still open (in that order)."""
+    objs = list(_live)
+    for kind in (Batch, Gneb, Engine):
+        for o in objs:
+            if isinstance(o, kind):
+                o.close()
+
+
+atexit.register(close_all)
+
 
 def lib():
     """Load ``libsp_engine.so`` (raises if it has not been built)."""
@@ -120,6 +141,9 @@ def lib():
         "sp_observe": (ci, [vp, ctypes.POINTER(sp_observation)]),
         "sp_llg_step": (ci, [vp, ctypes.POINTER(sp_llg_params)]),
         "sp_run": (ci, [vp, ctypes.POINTER(sp_llg_params), i64, i64, ctypes.POINTER(sp_observation)]),
+        "sp_run_tol": (ci, [vp, ctypes.POINTER(sp_llg_params), i64, i64, ctypes.c_double,
+                            ctypes.POINTER(sp_observation), ctypes.POINTER(i64)]),
+        "sp_set_graph_replay": (ci, [vp, ci]),
         "sp_synchronize": (ci, [vp]),
         "sp_dipole_gradient": (ci, [vp, dp, i64]),
         "sp_dipole_gradient_dev": (ci, [vp, vp, vp, i64]),
@@ -147,6 +171,7 @@ def lib():
         "sp_gneb_last_error": (ctypes.c_char_p, [vp]),
         "sp_gneb_set_image_type": (ci, [vp, ci, ci]),
         "sp_gneb_iterate": (ci, [vp, ci]),
+        "sp_gneb_iterate_tol": (ci, [vp, ci, ctypes.c_double, ctypes.POINTER(ci)]),
         "sp_gneb_get_chain": (ci, [vp, dp]),
         "sp_gneb_get_forces": (ci, [vp, dp, dp, dp]),
         "sp_ddi_init": (ci, [vp, ci, ctypes.POINTER(ci), u64]),
@@ -215,6 +240,7 @@ class Engine:
         rc = L.sp_create(ctypes.byref(self._h), device, prec, s)
         if rc != SP_OK:
             raise SpError(rc, "sp_create failed (no HIP device?)")
+        _live.add(self)
         self.N = 0
         self._keep = []
 
@@ -359,6 +385,22 @@ class Engine:
         res = [obs_dict(o) for o in obs[:n_obs]]
         return (res, rc) if not check else res
 
+    def run_tol(self, alpha: float, dt: float, max_steps: int, observe_every: int, tol: float, T: float = 0.0,
+                seed: int = 0, replica: int = 0, solver: str = "depondt"):
+        """Run until an observation's maximum torque is below tol (or
+        max_steps); returns (observations, steps taken)."""
+        p = sp_llg_params(alpha, dt, T, seed, replica, SOLVERS[solver])
+        n_obs = max_steps // observe_every if observe_every > 0 else 0
+        obs = (sp_observation * max(n_obs, 1))()
+        done = ctypes.c_int64()
+        self._check(lib().sp_run_tol(self._h, ctypes.byref(p), max_steps, observe_every, tol,
+                                     obs if n_obs else None, ctypes.byref(done)))
+        n_kept = done.value // observe_every if observe_every > 0 else 0
+        return [obs_dict(o) for o in obs[:min(n_obs, n_kept)]], done.value
+
+    def set_graph_replay(self, enable: bool):
+        self._check(lib().sp_set_graph_replay(self._h, 1 if enable else 0))
+
     def mc_run(self, T: float, cone_deg: float, n_sweeps: int, seed: int = 0, replica: int = 0,
                observe_every: int = 0):
         """Metropolis sweeps; returns (observations, accepted trials)."""
@@ -451,6 +493,7 @@ class Batch:
         rc = L.sp_batch_create(ctypes.byref(self._h), device, s)
         if rc != SP_OK:
             raise SpError(rc, "sp_batch_create failed (no HIP device?)")
+        _live.add(self)
         self.sizes = []
 
     def close(self):
@@ -521,6 +564,7 @@ class Gneb:
         rc = lib().sp_gneb_create(ctypes.byref(self._h), engine._h, self.M, _dp(c), k_spring, vp_dt,
                                   vp_mass)
         engine._check(rc)
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value and _lib is not None:
@@ -543,6 +587,13 @@ class Gneb:
 
     def iterate(self, n_iter: int):
         self._check(lib().sp_gneb_iterate(self._h, n_iter))
+
+    def iterate_tol(self, max_iter: int, tol: float) -> int:
+        """Iterate until the largest per-spin force is below tol; returns the
+        iterations taken."""
+        done = ctypes.c_int()
+        self._check(lib().sp_gneb_iterate_tol(self._h, max_iter, tol, ctypes.byref(done)))
+        return done.value
 
     def chain(self) -> np.ndarray:
         out = np.zeros(self.M * 3 * self.N)

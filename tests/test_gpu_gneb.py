@@ -80,10 +80,46 @@ def _case(name):
     return geo, HAM0, _skyrmion_chain(geo, 32, 5.0), dict(k_spring=1.0, vp_dt=0.1, vp_mass=1.0)
 
 
-@pytest.mark.parametrize("case,iters", [("single_spin", 60), ("square12x10", 40), ("chain32x128x128", 20),
-                                        ("tri128x16_tiles", 20)])
+def chain_sensitivity(ora, geo, ham, chain, kw, iters, trials=3):
+    """How far the oracle's own iteration map carries a rounding-size
+    difference: chains whose interior images start 1e-15 apart (three random
+    perturbations) are iterated beside the unperturbed one.  Returns the
+    largest normwise chain difference (relative to the largest spin
+    component) and force difference (relative to the initial force norm)
+    over `iters` iterations.  The GPU sums in another order than the oracle,
+    so its FP64 chain can part from the oracle's by as much as the map
+    amplifies differences of that size."""
+    s = ora.System(geo, ham)
+    base = ora.Gneb(s, chain, **kw)
+    F0 = np.linalg.norm(base.forces()["F"])
+    rng = np.random.default_rng(12)
+    others = []
+    for _ in range(trials):
+        c = np.array(chain, dtype=np.float64)
+        c[1:-1] += 1e-15 * rng.standard_normal(c[1:-1].shape)
+        c /= np.linalg.norm(c, axis=1, keepdims=True)
+        others.append(ora.Gneb(s, c, **kw))
+    dc = dF = 0.0
+    for _ in range(iters):
+        base.iterate(1)
+        fb = base.forces()["F"]
+        for o in others:
+            o.iterate(1)
+            dc = max(dc, float(np.abs(o.chain - base.chain).max() / np.abs(base.chain).max()))
+            dF = max(dF, float(np.linalg.norm(o.forces()["F"] - fb) / F0))
+    return dc, dF
+
+
+@pytest.mark.parametrize("case,iters", [("single_spin", 30), ("single_spin", 60), ("square12x10", 40),
+                                        ("chain32x128x128", 20), ("tri128x16_tiles", 20)])
 def test_gneb_fp64_iterations_match_oracle(ora, case, iters):
-    announce(f"gneb fp64 {case}")
+    """FP64 chain and forces after `iters` iterations within the 1e-12 bar,
+    or within ten times what the oracle's own iteration map makes of 1e-15
+    perturbations (measured here on the CPU), whichever is larger.  The
+    velocity projection of the bent single-spin chain (vp_dt = 0.5) amplifies
+    such differences about 1e5-fold between iterations 30 and 60, so only its
+    60-iteration case needs the measured bound."""
+    announce(f"gneb fp64 {case} {iters}")
     geo, ham, chain, kw = _case(case)
     e, g, o = _pair(ora, geo, ham, "f64", chain, **kw)
     f0, fo = g.forces(), o.forces()
@@ -93,18 +129,18 @@ def test_gneb_fp64_iterations_match_oracle(ora, case, iters):
     assert np.allclose(f0["l"], fo["l"], rtol=1e-13)
     g.iterate(iters)
     o.iterate(iters)
-    # Each iteration adds rounding-order differences of the FP64 bar (1e-12);
-    # over a few dozen iterations they add up at most linearly.
-    tol = 2e-12 * iters
-    assert_close(g.chain(), o.chain, "f64", tol, what=f"chain after {iters} iterations")
+    sens_c, sens_F = chain_sensitivity(ora, geo, ham, chain, kw, iters)
+    tol_c = max(1e-12, 10 * sens_c)
+    tol_F = max(1e-12, 10 * sens_F)
+    print(f"[gneb] {case}: oracle divergence from 1e-15 over {iters} iterations: chain {sens_c:.2e}, "
+          f"forces {sens_F:.2e}; bounds {tol_c:.1e} / {tol_F:.1e}", flush=True)
+    assert_close(g.chain(), o.chain, "f64", tol_c, what=f"chain after {iters} iterations")
     fg, fo = g.forces(), o.forces()
-    assert np.allclose(fg["E"], fo["E"], rtol=tol, atol=tol * np.abs(fo["E"]).max())
-    # forces shrink as the chain converges: measure their difference on the
-    # scale of the initial forces.  They are recomputed from chains that agree
-    # to `tol`; the force map (curvature of the energy, spring and projection
-    # terms) amplifies that difference by up to ~1e2.
+    assert np.allclose(fg["E"], fo["E"], rtol=tol_c, atol=tol_c * np.abs(fo["E"]).max())
+    # forces shrink as the chain converges: their difference is measured on
+    # the scale of the initial forces, as the sensitivity is
     dF = np.linalg.norm(fg["F"] - fo["F"]) / np.linalg.norm(f0["F"])
-    assert dF <= 100 * tol, f"forces: difference {dF:.3e} of the initial force norm"
+    assert dF <= tol_F, f"forces: difference {dF:.3e} of the initial force norm > {tol_F:.1e}"
 
 
 @pytest.mark.parametrize("case", ["single_spin", "square12x10", "chain32x128x128", "tri128x16_tiles"])
