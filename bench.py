@@ -688,6 +688,7 @@ def main():
         line["tc"] = bench_tc(args)
     pk.close_all()
     torch.cuda.synchronize()
+    print("[bench] every engine, batch and chain closed", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(line), flush=True)
