@@ -289,13 +289,28 @@ int sp_synchronize(sp_engine *e);
 
 /* Dipole-dipole gradient alone: the dipolar term of the Hamiltonian of
  * Sec. III.A (in the physical form 1/2 C_dd sum_{i!=j} mu_i mu_j
- * [n_i.n_j - 3 (n_i.r)(n_j.r)] / r^3) summed directly over all pairs of the
- * sample (open, no periodic images); g_soa receives 3N doubles (meV).
- * Independent of ddi_mode.  sp_dipole_gradient_dev reads n_soa_dev and
+ * [n_i.n_j - 3 (n_i.r)(n_j.r)] / r^3) over all pairs of the sample (open,
+ * no periodic images), evaluated as ddi_mode says: the direct sum
+ * (SP_DDI_DIRECT), the FFT convolution of the same sum (SP_DDI_FFT) or the
+ * learned field with its residual check (SP_DDI_SURROGATE).  g_soa
+ * receives 3N doubles (meV).  sp_dipole_gradient_dev reads n_soa_dev and
  * writes g_soa_dev (engine precision, 3N each, caller-owned device memory,
- * engine stream). */
+ * engine stream).  SP_E_ORDER when ddi_mode is off. */
 int sp_dipole_gradient(sp_engine *e, double *g_soa, int64_t N);
 int sp_dipole_gradient_dev(sp_engine *e, const void *n_soa_dev, void *g_soa_dev, int64_t N);
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The direct
+ * sum of sp_dipole_gradient_dev (whatever ddi_mode, which must not be off)
+ * with its partial sums in a file-scope device array of 32 MiB per GPU
+ * instead of engine memory; it calls no allocating routine.  The caller
+ * passes inputs and outputs as for sp_dipole_gradient_dev (same values, bit
+ * for bit, as its SP_DDI_DIRECT result).  SP_E_ARG when the partial sums
+ * (3 N x slices values of the engine precision; slices = 16 up to 65,536
+ * sites, then about 2^20 / N) exceed 32 MiB, e.g. beyond about 1.4 M sites
+ * in FP64 or 2.8 M in FP32.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (engines on different streams) race and
+ * must be ordered by the caller. */
+int sp_dipole_gradient_dev_noalloc(sp_engine *e, const void *n_soa_dev, void *g_soa_dev, int64_t N);
 
 /* The three independent standard normals per site and step of the
  * stochastic field of Sec. III.C, exactly as the LLG kernels draw them:

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <array>
+#include <mutex>
 #include <set>
 #include <random>
 #include <string>
@@ -375,6 +376,57 @@ int launch_direct_sum(sp_engine* e, const void* n, void* gdd, const int* gate = 
                        static_cast<const T*>(e->d_pos), static_cast<const T*>(n), static_cast<T*>(e->d_ddpart), gate);
     hipLaunchKernelGGL((sp::k_dipole_finish<T>), dim3(blocks_for(3LL * e->N)), dim3(256), 0, e->stream, a,
                        (T)kCdd, static_cast<const T*>(e->d_ddpart), static_cast<T*>(gdd), gate);
+    HIPCHK(e, hipGetLastError());
+    return SP_OK;
+}
+
+// Scratch of sp_dipole_gradient_dev_noalloc: the S slices of partial sums
+// of the direct sum live in this file-scope device array instead of engine
+// memory.  Every GPU the library runs on holds its own copy until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in, not a device address).
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+bool g_scratch_tried[kScratchDevices] = {};
+
+// Looks the array up once per device, with that device current (sp_create
+// calls it after hipSetDevice).  Returns the device address or nullptr.
+void* scratch_for_device(int device) {
+    if (device < 0 || device >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_tried[device]) {
+        void* ptr = nullptr;
+        const hipError_t st = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[device] = st == hipSuccess ? ptr : nullptr;
+        g_scratch_tried[device] = true;
+        if (st != hipSuccess) (void)hipGetLastError();
+    }
+    return g_scratch_ptr[device];
+}
+
+// The direct sum with its partials in `part` (the engine's buffer or the
+// static scratch); the partial kernel writes every element of the
+// slices * 3N values before the finish kernel reads them.
+template <typename T>
+int launch_direct_sum_into(sp_engine* e, const void* n, void* gdd, void* part) {
+    sp::DipoleArgs<T> a{};
+    a.N = e->N;
+    a.cells = e->geo.n[0] * e->geo.n[1] * e->geo.n[2];
+    a.slices = e->dd_slices;
+    const int tiles = (e->N + 255) / 256;
+    a.slice_len = ((tiles + a.slices - 1) / a.slices) * 256;
+    for (int b = 0; b < e->geo.nb; ++b) a.mu[b] = (T)e->ham.mu[b];
+    constexpr int IPT = 2;
+    dim3 grid((unsigned)((e->N + 256 * IPT - 1) / (256 * IPT)), (unsigned)a.slices);
+    hipLaunchKernelGGL((sp::k_dipole_partial<T, IPT>), grid, dim3(256), 0, e->stream, a,
+                       static_cast<const T*>(e->d_pos), static_cast<const T*>(n), static_cast<T*>(part), nullptr);
+    hipLaunchKernelGGL((sp::k_dipole_finish<T>), dim3(blocks_for(3LL * e->N)), dim3(256), 0, e->stream, a,
+                       (T)kCdd, static_cast<const T*>(part), static_cast<T*>(gdd), nullptr);
     HIPCHK(e, hipGetLastError());
     return SP_OK;
 }
@@ -1401,6 +1453,7 @@ int sp_create(sp_engine** out, int device, int precision, void* hip_stream) {
     e->device = device;
     e->precision = precision;
     if (hipSetDevice(device) != hipSuccess) { delete e; return SP_E_HIP; }
+    (void)scratch_for_device(device);
     if (hip_stream) {
         e->stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -1931,6 +1984,22 @@ int sp_dipole_gradient_dev(sp_engine* e, const void* n_soa_dev, void* g_soa_dev,
     if (!e->ham.ddi) return fail(e, SP_E_ORDER, "the Hamiltonian has no dipole term (ddi_mode off)");
     (void)hipSetDevice(e->device);
     return DISPATCH(e, launch_dipole, e, n_soa_dev, g_soa_dev);
+}
+
+int sp_dipole_gradient_dev_noalloc(sp_engine* e, const void* n_soa_dev, void* g_soa_dev, int64_t N) {
+    int rc = check_ready(e, false);
+    if (rc) return rc;
+    if (!n_soa_dev || !g_soa_dev || N != e->N) return fail(e, SP_E_ARG, "array size differs from the number of sites");
+    if (!e->ham.ddi) return fail(e, SP_E_ORDER, "the Hamiltonian has no dipole term (ddi_mode off)");
+    const size_t need = 3 * (size_t)e->N * e->esz() * (size_t)e->dd_slices;
+    if (need > kScratchBytes)
+        return fail(e, SP_E_ARG, "the direct sum of " + std::to_string(e->N) + " sites needs " + std::to_string(need) +
+                                     " bytes of partial sums; the static scratch holds " +
+                                     std::to_string(kScratchBytes));
+    (void)hipSetDevice(e->device);
+    void* part = scratch_for_device(e->device);
+    if (!part) return fail(e, SP_E_HIP, "hipGetSymbolAddress of the static scratch failed on this device");
+    return DISPATCH(e, launch_direct_sum_into, e, n_soa_dev, g_soa_dev, part);
 }
 
 int sp_dipole_gradient(sp_engine* e, double* g_soa, int64_t N) {

@@ -32,7 +32,7 @@ EXPORTS = [
     "sp_set_spins_dev", "sp_get_spins_dev", "sp_set_step", "sp_get_step", "sp_gradient",
     "sp_gradient_dev", "sp_energy", "sp_observe", "sp_llg_step", "sp_run", "sp_run_tol",
     "sp_set_graph_replay", "sp_synchronize",
-    "sp_dipole_gradient", "sp_dipole_gradient_dev", "sp_thermal_normals", "sp_step_path",
+    "sp_dipole_gradient", "sp_dipole_gradient_dev", "sp_dipole_gradient_dev_noalloc", "sp_thermal_normals", "sp_step_path",
     "sp_set_step_path", "sp_autotune", "sp_mc_run",
     "sp_batch_create", "sp_batch_destroy", "sp_batch_last_error", "sp_batch_add", "sp_batch_run",
     "sp_batch_get_spins", "sp_batch_replica_info", "sp_batch_set_chunk", "sp_batch_get_step",
@@ -147,6 +147,7 @@ def lib():
         "sp_synchronize": (ci, [vp]),
         "sp_dipole_gradient": (ci, [vp, dp, i64]),
         "sp_dipole_gradient_dev": (ci, [vp, vp, vp, i64]),
+        "sp_dipole_gradient_dev_noalloc": (ci, [vp, vp, vp, i64]),
         "sp_thermal_normals": (ci, [vp, u64, u64, ctypes.c_uint32, ctypes.c_uint32, i64, dp,
                                     ctypes.POINTER(ctypes.c_uint32)]),
         "sp_step_path": (ctypes.c_char_p, [vp]),
