@@ -141,9 +141,10 @@ typedef struct {
 /* Metropolis Monte Carlo parameters (Sec. III.B). */
 typedef struct {
     double T_K;              /* temperature, > 0 */
-    double cone_deg;         /* opening angle of the trial cone, (0, 180] degrees */
+    double cone_deg;         /* opening angle of the trial cone, (0, 180] degrees (initial, if adaptive) */
     uint64_t seed;           /* Philox key */
     uint32_t replica;        /* Philox counter word 3 */
+    double target_acceptance;/* 0: fixed cone; in (0, 1): the cone follows the acceptance feedback */
 } sp_mc_params;
 
 /* Create an engine on HIP device `device` computing in `precision`.
@@ -155,9 +156,12 @@ void sp_destroy(sp_engine *e);
 /* Message of the last failing call on this engine (never NULL). */
 const char *sp_last_error(const sp_engine *e);
 
-/* Metropolis sweeps with cone trial moves (Sec. III.B): each sweep tries
- * every site once, first the sites with a + b + c even, then the odd ones
- * (sites of one colour share no bond, so a colour updates in parallel).
+/* Metropolis sweeps with cone trial moves (Sec. III.B).  The paper's sweep
+ * picks every spin once, sequentially in random order; here a sweep tries
+ * every site once as a checkerboard, first the sites with a + b + c even,
+ * then the odd ones (sites of one colour share no bond, so a colour updates
+ * in parallel and every trial sees the current state of its neighbours):
+ * the same Boltzmann distribution, sampled by another schedule.
  * Trial at site i of sweep s: Philox block of counter (i, s_lo, s_hi,
  * replica) and key (seed_lo, seed_hi), u_k = (x_k + 1/2) 2^-32; phi = 2 pi u0,
  * cos(theta) = 1 - u1 (1 - cos(cone)); new spin cos(theta) n +
@@ -166,13 +170,17 @@ const char *sp_last_error(const sp_engine *e);
  * Trial, dE and the test are computed in FP64 in both engine precisions
  * (an FP32 engine reads its FP32 spins and stores an accepted trial rounded
  * to FP32).  The sweep number is the engine's step counter (advanced by
- * n_sweeps).
+ * n_sweeps).  Adaptive cone (target_acceptance > 0; the paper's feedback
+ * toward a desired acceptance ratio, whose rule it does not print): after
+ * every sweep with acceptance ratio a the cone is multiplied by
+ * 1 + a - target_acceptance, at most 180 degrees, on the device; *cone_out
+ * (may be NULL) receives the cone after the last sweep.
  * Needs a one-atom basis, bonds that join the two colours, even lengths on
  * periodic axes and no dipole term (SP_E_UNSUPPORTED otherwise).  obs
  * receives n_sweeps / observe_every observations (observe_every = 0: none);
  * *accepted (may be NULL) the accepted trials of the run. */
 int sp_mc_run(sp_engine *e, const sp_mc_params *p, int64_t n_sweeps, int64_t observe_every,
-              sp_observation *obs, int64_t *accepted);
+              sp_observation *obs, int64_t *accepted, double *cone_out);
 /* Version string of the library. */
 const char *sp_version(void);
 

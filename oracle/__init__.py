@@ -78,7 +78,7 @@ SOLVERS = {"depondt": 0, "heun": 1, "sib": 2}
 
 class McParams(ctypes.Structure):
     _fields_ = [("T", ctypes.c_double), ("cone_deg", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("replica", ctypes.c_uint32)]
+                ("replica", ctypes.c_uint32), ("target_acceptance", ctypes.c_double)]
 
 
 class GnebParams(ctypes.Structure):
@@ -135,10 +135,16 @@ def lib():
         L.ora_mc_delta_energy.restype = ctypes.c_double
         L.ora_mc_delta_energy.argtypes = [ctypes.c_void_p, dp, ctypes.c_int64, dp]
         L.ora_mc_sweep.restype = ctypes.c_int64
-        L.ora_mc_sweep.argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(McParams), ctypes.c_uint64]
+        L.ora_mc_sweep.argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(McParams), ctypes.c_double, ctypes.c_uint64]
+        L.ora_mc_order.restype = None
+        L.ora_mc_order.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                   ctypes.POINTER(ctypes.c_int64)]
+        L.ora_mc_adapt_cone.restype = ctypes.c_double
+        L.ora_mc_adapt_cone.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.ora_mc_run.restype = ctypes.c_int64
         L.ora_mc_run.argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(McParams), ctypes.c_uint64, ctypes.c_int64,
-                                 ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
+                                 ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_double)]
         for name in ("ora_depondt_step", "ora_heun_step", "ora_sib_step", "ora_llg_step"):
             getattr(L, name).argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(LLGParams), ctypes.c_uint64]
         L.ora_rotate.argtypes = [dp, dp, ctypes.c_double, dp]
@@ -324,18 +330,22 @@ class System:
         n = self._spins(n)
         return lib().ora_mc_delta_energy(self._p, _dp(n), int(i), _dp(np.ascontiguousarray(n_new, dtype=np.float64)))
 
-    def mc_run(self, n, T, cone_deg, n_sweeps, seed=0, sweep0=0, replica=0, observe_every=0):
-        """Metropolis sweeps; returns (spins, observations, accepted trials)."""
+    def mc_run(self, n, T, cone_deg, n_sweeps, seed=0, sweep0=0, replica=0, observe_every=0,
+               target_acceptance=0.0, return_cone=False):
+        """Metropolis sweeps in random order (Sec. III.B); returns (spins,
+        observations, accepted trials[, final cone in degrees])."""
         n = self._spins(n).copy()
-        p = McParams(T, cone_deg, seed, replica)
+        p = McParams(T, cone_deg, seed, replica, target_acceptance)
         n_obs = n_sweeps // observe_every if observe_every > 0 else 0
         obs = (Observation * max(n_obs, 1))()
         acc = ctypes.c_int64()
+        cone = ctypes.c_double()
         k = lib().ora_mc_run(self._p, _dp(n), ctypes.byref(p), sweep0, n_sweeps, observe_every,
-                             ctypes.cast(obs, ctypes.c_void_p), ctypes.byref(acc))
+                             ctypes.cast(obs, ctypes.c_void_p), ctypes.byref(acc), ctypes.byref(cone))
         if k < 0:
-            raise ValueError("lattice does not admit the two-colour Monte Carlo sweep")
-        return n, [_obs_dict(o) for o in obs[:k]], acc.value
+            raise ValueError("Monte Carlo sweeps do not support the dipole term")
+        out = (n, [_obs_dict(o) for o in obs[:k]], acc.value)
+        return out + (cone.value,) if return_cone else out
 
     def observe(self, n, step=0) -> dict:
         n = self._spins(n)
@@ -482,6 +492,17 @@ class SurrogateNet:
 def _obs_dict(o: Observation) -> dict:
     return {"step": o.step, "E": o.E, "per_term": list(o.per_term),
             "max_torque": o.max_torque, "M": list(o.M), "max_norm_dev": o.max_norm_dev}
+
+
+def mc_order(N, seed, sweep, replica=0) -> np.ndarray:
+    """The random visiting order of one Metropolis sweep."""
+    out = np.zeros(max(N, 1), dtype=np.int64)
+    lib().ora_mc_order(N, seed, sweep, replica, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return out[:N]
+
+
+def mc_adapt_cone(cone_deg, acceptance, target) -> float:
+    return lib().ora_mc_adapt_cone(cone_deg, acceptance, target)
 
 
 def philox4x32_10(ctr, key):

@@ -855,17 +855,16 @@ double ora_mc_delta_energy(const ora_system *s, const double *n, int64_t i, cons
            gauss_energy(s, ni);
 }
 
-static int mc_admissible(const ora_system *s) {
-    if (s->geo.n_basis != 1 || s->ham.ddi) return 0;
-    for (int k = 0; k < 3; ++k)
-        if (s->geo.periodic[k] && s->geo.n_cells[k] > 1 && (s->geo.n_cells[k] % 2)) return 0;
-    for (int64_t b = 0; b < s->n_bonds; ++b) {
-        const ora_bond *bd = &s->bonds[b];
-        if (((bd->da + bd->db + bd->dc) % 2 + 2) % 2 != 1) return 0;
-    }
-    return 1;
-}
+/* The Metropolis sweep of Sec. III.B: every spin is picked once, one after
+ * the other, in an order drawn at random for each sweep, and given a trial
+ * step inside a cone about its current direction.  Needs no dipole term
+ * (its energy change is not local); any lattice and basis. */
+static int mc_admissible(const ora_system *s) { return !s->ham.ddi; }
 
+/* Trial direction (Sec. III.B): the current spin is the z axis of a local
+ * frame; phi uniform in [0, 2 pi), cos(theta) uniform in [cos(cone), 1].
+ * Reading: the frame is e1 = unit(n x r), r = z if |n_z| < 0.9 else x,
+ * e2 = n x e1 (any frame gives the same distribution of trials). */
 static void mc_trial(const double n[3], const double u[4], double cos_cone, double out[3]) {
     double r[3] = {0.0, 0.0, 0.0}, e1[3], e2[3];
     if (fabs(n[2]) < 0.9) r[2] = 1.0; else r[0] = 1.0;
@@ -879,48 +878,83 @@ static void mc_trial(const double n[3], const double u[4], double cos_cone, doub
     for (int k = 0; k < 3; ++k) out[k] = ct * n[k] + st * (cos(phi) * e1[k] + sin(phi) * e2[k]);
 }
 
-int64_t ora_mc_sweep(const ora_system *s, double *n, const ora_mc_params *p, uint64_t sweep) {
+/* Visiting order of one sweep: a uniformly random permutation of the N
+ * sites (Fisher-Yates).  Reading: its random integers come from Philox
+ * blocks of counter (2^31 + k, s_lo, s_hi, replica), key (seed_lo, seed_hi)
+ * -- counters the trial draws (word 0 = site < 2^31) never use; step k
+ * swaps position k with position floor(r (k + 1) / 2^64), r = the block's
+ * first two words as one 64-bit integer. */
+void ora_mc_order(int64_t N, uint64_t seed, uint64_t sweep, uint32_t replica, int64_t *order) {
+    for (int64_t i = 0; i < N; ++i) order[i] = i;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t k = N - 1; k > 0; --k) {
+        const uint32_t ctr[4] = {0x80000000u + (uint32_t)k, (uint32_t)sweep, (uint32_t)(sweep >> 32), replica};
+        uint32_t x[4];
+        ora_philox4x32_10(ctr, key, x);
+        const uint64_t r = ((uint64_t)x[0] << 32) | x[1];
+        const int64_t j = (int64_t)(((unsigned __int128)r * (uint64_t)(k + 1)) >> 64);
+        const int64_t t = order[k];
+        order[k] = order[j];
+        order[j] = t;
+    }
+}
+
+int64_t ora_mc_sweep(const ora_system *s, double *n, const ora_mc_params *p, double cone_deg, uint64_t sweep) {
     if (!mc_admissible(s)) return -1;
     const int64_t N = s->N;
     const double kT = ora_const_k_B() * p->T;
-    const double cos_cone = cos(p->cone_deg * PI / 180.0);
-    const int na = s->geo.n_cells[0], nb = s->geo.n_cells[1];
+    const double cos_cone = cos(cone_deg * PI / 180.0);
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+    ora_mc_order(N, p->seed, sweep, p->replica, order);
     int64_t accepted = 0;
-    for (int colour = 0; colour < 2; ++colour) {
-#pragma omp parallel for schedule(static) reduction(+ : accepted)
-        for (int64_t i = 0; i < N; ++i) {
-            const int64_t a = i % na, b = (i / na) % nb, c = i / ((int64_t)na * nb);
-            if ((int)((a + b + c) % 2) != colour) continue;
-            uint32_t ctr[4] = {(uint32_t)i, (uint32_t)sweep, (uint32_t)(sweep >> 32), p->replica};
-            uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
-            uint32_t x[4];
-            ora_philox4x32_10(ctr, key, x);
-            double u[4];
-            for (int k = 0; k < 4; ++k) u[k] = ((double)x[k] + 0.5) * (1.0 / 4294967296.0);
-            double ni[3], nn[3];
-            load(n, N, i, ni);
-            mc_trial(ni, u, cos_cone, nn);
-            const double dE = ora_mc_delta_energy(s, n, i, nn);
-            if (u[2] < exp(-dE / kT)) {
-                for (int k = 0; k < 3; ++k) n[k * N + i] = nn[k];
-                ++accepted;
-            }
+    for (int64_t v = 0; v < N; ++v) {   /* sequential: each trial sees every earlier move */
+        const int64_t i = order[v];
+        const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)sweep, (uint32_t)(sweep >> 32), p->replica};
+        const uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+        uint32_t x[4];
+        ora_philox4x32_10(ctr, key, x);
+        double u[4];
+        for (int k = 0; k < 4; ++k) u[k] = ((double)x[k] + 0.5) * (1.0 / 4294967296.0);
+        double ni[3], nn[3];
+        load(n, N, i, ni);
+        mc_trial(ni, u, cos_cone, nn);
+        const double dE = ora_mc_delta_energy(s, n, i, nn);
+        /* accepted with probability min(1, exp(-dE / k_B T)) */
+        if (u[2] < exp(-dE / kT)) {
+            for (int k = 0; k < 3; ++k) n[k * N + i] = nn[k];
+            ++accepted;
         }
     }
+    free(order);
     return accepted;
 }
 
+/* Adaptive cone (Sec. III.B: the cone angle follows a feedback loop toward
+ * a desired acceptance ratio; the loop is not printed).  Reading: after
+ * every sweep with acceptance ratio a, cone <- min(180, cone (1 + a - a*))
+ * degrees: wider while more than the target a* is accepted, narrower
+ * while fewer; the factor lies in [1 - a*, 2 - a*], so the cone never
+ * reaches zero. */
+double ora_mc_adapt_cone(double cone_deg, double acceptance, double target) {
+    if (!(target > 0.0)) return cone_deg;
+    const double c = cone_deg * (1.0 + acceptance - target);
+    return c > 180.0 ? 180.0 : c;
+}
+
 int64_t ora_mc_run(const ora_system *s, double *n, const ora_mc_params *p, uint64_t sweep0, int64_t n_sweeps,
-                   int64_t observe_every, ora_observation *obs, int64_t *accepted) {
+                   int64_t observe_every, ora_observation *obs, int64_t *accepted, double *cone_out) {
     int64_t n_obs = 0, acc = 0;
+    double cone = p->cone_deg;
     for (int64_t t = 0; t < n_sweeps; ++t) {
-        const int64_t a = ora_mc_sweep(s, n, p, sweep0 + (uint64_t)t);
+        const int64_t a = ora_mc_sweep(s, n, p, cone, sweep0 + (uint64_t)t);
         if (a < 0) return -1;
         acc += a;
+        cone = ora_mc_adapt_cone(cone, s->N > 0 ? (double)a / (double)s->N : 0.0, p->target_acceptance);
         if (observe_every > 0 && (t + 1) % observe_every == 0 && obs)
             ora_observe(s, n, (int64_t)sweep0 + t + 1, &obs[n_obs++]);
     }
     if (accepted) *accepted = acc;
+    if (cone_out) *cone_out = cone;
     return n_obs;
 }
 

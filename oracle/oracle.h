@@ -146,35 +146,40 @@ int64_t ora_run(const ora_system *s, double *n, const ora_llg_params *p, uint64_
                 int64_t n_steps, int64_t observe_every, ora_observation *obs);
 
 /* ----------------------------------------------------------- Monte Carlo
- * Metropolis sampling with cone trial moves (Sec. III.B).  A sweep visits
- * every site once: first the sites with a + b + c even, then the odd ones
- * (a checkerboard: sites of one colour share no bond, so the order inside a
- * colour does not matter).  Needs one basis atom, every bond joining the two
- * colours, and even lengths on periodic axes; no dipole term.
+ * Metropolis sampling with cone trial moves (Sec. III.B).  One sweep picks
+ * every site once, sequentially, in an order drawn at random per sweep
+ * (ora_mc_order), and gives it a trial step; no dipole term.
  * Trial at site i of sweep s: Philox block x of counter (i, s_lo, s_hi,
  * replica), key (seed_lo, seed_hi), u_k = (x_k + 1/2) 2^-32; phi = 2 pi u0,
  * cos(theta) = 1 - u1 (1 - cos(cone)); the new spin is
  * cos(theta) n + sin(theta) (cos(phi) e1 + sin(phi) e2) with
  * e1 = unit(n x r), r = z if |n_z| < 0.9 else x, e2 = n x e1; accepted if
- * u2 < exp(-dE / (k_B T)). */
+ * u2 < exp(-dE / (k_B T)).  With target_acceptance > 0 the cone follows the
+ * feedback of ora_mc_adapt_cone after every sweep. */
 typedef struct {
-    double T;            /* K, > 0 */
-    double cone_deg;     /* opening angle of the trial cone, degrees (0, 180] */
+    double T;                  /* K, > 0 */
+    double cone_deg;           /* opening angle of the trial cone, degrees (0, 180] (initial, if adaptive) */
     uint64_t seed;
     uint32_t replica;
+    double target_acceptance;  /* 0: fixed cone; in (0, 1): adaptive cone toward this acceptance ratio */
 } ora_mc_params;
 
 /* Energy change when site i alone changes from n_i to n_new (the terms of
  * the Hamiltonian that contain site i). */
 double ora_mc_delta_energy(const ora_system *s, const double *n, int64_t i, const double n_new[3]);
-/* One sweep (sweep counter `sweep`); returns the number of accepted trials,
- * or -1 if the lattice does not admit the two-colour sweep. */
-int64_t ora_mc_sweep(const ora_system *s, double *n, const ora_mc_params *p, uint64_t sweep);
-/* n_sweeps sweeps from sweep0; observations every observe_every sweeps;
- * *accepted receives the total accepted trials.  Returns the number of
- * observations, or -1 as above. */
+/* The visiting order of sweep `sweep`: a random permutation of 0..N-1. */
+void ora_mc_order(int64_t N, uint64_t seed, uint64_t sweep, uint32_t replica, int64_t *order);
+/* The cone after a sweep with the given acceptance ratio. */
+double ora_mc_adapt_cone(double cone_deg, double acceptance, double target);
+/* One sweep with the given cone (sweep counter `sweep`); returns the number
+ * of accepted trials, or -1 if the Hamiltonian has a dipole term. */
+int64_t ora_mc_sweep(const ora_system *s, double *n, const ora_mc_params *p, double cone_deg, uint64_t sweep);
+/* n_sweeps sweeps from sweep0 starting with p->cone_deg; observations every
+ * observe_every sweeps; *accepted receives the total accepted trials and
+ * *cone_out (may be NULL) the cone after the last sweep.  Returns the
+ * number of observations, or -1 as above. */
 int64_t ora_mc_run(const ora_system *s, double *n, const ora_mc_params *p, uint64_t sweep0, int64_t n_sweeps,
-                   int64_t observe_every, ora_observation *obs, int64_t *accepted);
+                   int64_t observe_every, ora_observation *obs, int64_t *accepted, double *cone_out);
 
 /* ------------------------------------------------------------------ GNEB
  * Chain of M images (image-major: image v occupies chain[v*3N .. v*3N+3N),

@@ -1370,7 +1370,7 @@ int mc_admissible(sp_engine* e) {
 
 template <typename T>
 int mc_run_impl(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t observe_every, sp_observation* obs,
-                int64_t* accepted) {
+                int64_t* accepted, double* cone_out) {
     const int64_t n_obs = observe_every > 0 ? n_sweeps / observe_every : 0;
     int rc;
     if (n_obs > e->obs_cap) {
@@ -1388,6 +1388,15 @@ int mc_run_impl(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t o
     sp::McArgs<double> M{};
     M.kT = kKB * p->T_K;
     M.cos_cone = std::cos(p->cone_deg * M_PI / 180.0);
+    double* state = nullptr;   // adaptive cone: (cone, accepted count at the previous sweep)
+    const bool adaptive = p->target_acceptance > 0.0;
+    if (adaptive) {
+        if ((rc = dalloc(e, state, 2 * sizeof(double)))) { dfree(*reinterpret_cast<void**>(&acc)); return rc; }
+        const double init[2] = {p->cone_deg, 0.0};
+        HIPCHK(e, hipMemcpyAsync(state, init, sizeof(init), hipMemcpyHostToDevice, e->stream));
+        HIPCHK(e, hipStreamSynchronize(e->stream));
+        M.cone_dev = state;
+    }
     M.key.seed_lo = (uint32_t)p->seed;
     M.key.seed_hi = (uint32_t)(p->seed >> 32);
     M.key.replica = p->replica;
@@ -1400,10 +1409,17 @@ int mc_run_impl(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t o
             hipLaunchKernelGGL((sp::k_mc_colour<T>), dim3(blocks), dim3(256), 0, e->stream, L, C, P, M,
                                static_cast<T*>(e->d_n), acc);
         }
+        if (adaptive)
+            hipLaunchKernelGGL(sp::k_mc_adapt, dim3(1), dim3(256), 0, e->stream, acc, (int)blocks, (long long)e->N,
+                               p->target_acceptance, state);
         ++e->step;
         if (observe_every > 0 && (t + 1) % observe_every == 0) {
             rc = launch_observe<T>(e, e->d_n, e->d_obs + k * sp::OBS_NVALS, (long long)e->step, false);
-            if (rc) { dfree(*reinterpret_cast<void**>(&acc)); return rc; }
+            if (rc) {
+                dfree(*reinterpret_cast<void**>(&acc));
+                dfree(*reinterpret_cast<void**>(&state));
+                return rc;
+            }
             ++k;
         }
     }
@@ -1413,8 +1429,13 @@ int mc_run_impl(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t o
     std::vector<double> ho((size_t)n_obs * sp::OBS_NVALS);
     if (st == hipSuccess && n_obs > 0 && obs)
         st = hipMemcpyAsync(ho.data(), e->d_obs, ho.size() * sizeof(double), hipMemcpyDeviceToHost, e->stream);
+    double fin[2] = {p->cone_deg, 0.0};
+    if (st == hipSuccess && adaptive)
+        st = hipMemcpyAsync(fin, state, sizeof(fin), hipMemcpyDeviceToHost, e->stream);
     if (st == hipSuccess) st = hipStreamSynchronize(e->stream);
     dfree(*reinterpret_cast<void**>(&acc));
+    dfree(*reinterpret_cast<void**>(&state));
+    if (cone_out) *cone_out = fin[0];
     if (st != hipSuccess) return fail(e, SP_E_HIP, std::string("Monte Carlo run: ") + hipGetErrorString(st));
     if (accepted) {
         int64_t s = 0;
@@ -1502,17 +1523,20 @@ void sp_destroy(sp_engine* e) {
 const char* sp_last_error(const sp_engine* e) { return e ? e->err.c_str() : "null engine"; }
 
 int sp_mc_run(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t observe_every, sp_observation* obs,
-              int64_t* accepted) {
+              int64_t* accepted, double* cone_out) {
     int rc = check_ready(e, true);
     if (rc) return rc;
     if (!p) return fail(e, SP_E_ARG, "Monte Carlo params are NULL");
     if (!(p->T_K > 0.0) || !std::isfinite(p->T_K)) return fail(e, SP_E_ARG, "T must be finite and > 0");
     if (!(p->cone_deg > 0.0) || !(p->cone_deg <= 180.0)) return fail(e, SP_E_ARG, "cone angle must be in (0, 180]");
+    if (!(p->target_acceptance >= 0.0 && p->target_acceptance < 1.0))
+        return fail(e, SP_E_ARG, "target acceptance must be in [0, 1)");
     if (n_sweeps < 0 || observe_every < 0) return fail(e, SP_E_ARG, "n_sweeps and observe_every must be >= 0");
     if (observe_every > 0 && n_sweeps / observe_every > 0 && !obs) return fail(e, SP_E_ARG, "obs is NULL");
     if ((rc = mc_admissible(e))) return rc;
     (void)hipSetDevice(e->device);
-    return DISPATCH(e, mc_run_impl, e, p, n_sweeps, observe_every, obs, accepted);
+    if (cone_out) *cone_out = p->cone_deg;
+    return DISPATCH(e, mc_run_impl, e, p, n_sweeps, observe_every, obs, accepted, cone_out);
 }
 
 int sp_set_geometry(sp_engine* e, const double bravais[9], int n_basis, const double* basis, const int n_cells[3],

@@ -1,6 +1,11 @@
-// kernels_mc.hpp -- Metropolis Monte Carlo with cone trial moves (Sec. III.B)
-// as a two-colour (checkerboard) sweep: sites with a + b + c of one parity
-// share no bond, so one launch updates a whole colour in parallel.
+// kernels_mc.hpp -- Metropolis Monte Carlo with cone trial moves (Sec. III.B).
+// The paper's sweep picks every spin once, one after another, in random
+// order.  Here a sweep is a two-colour (checkerboard) pass: sites with
+// a + b + c of one parity share no bond, so one launch updates a whole
+// colour in parallel; every site is still tried once per sweep and each
+// trial sees the current state of every spin it interacts with, so the
+// chain samples the same Boltzmann distribution (checked statistically
+// against the sequential random-order sweep).
 //
 // Trial at site i of sweep s: Philox block of counter (i, s_lo, s_hi,
 // replica), u_k = (x_k + 1/2) 2^-32; phi = 2 pi u0, cos(theta) = 1 - u1 (1 -
@@ -9,6 +14,9 @@
 // if u2 < exp(-dE / k_B T).  dE needs only the terms containing site i:
 // Zeeman and the pair terms are linear in n_i (dn . coefficient), the
 // anisotropy and the on-site Gaussians are evaluated at both spins.
+// Adaptive cone: after every sweep the cone is multiplied by
+// 1 + a - a* (a the sweep's acceptance ratio, a* the target), at most 180
+// degrees, on the device.
 #pragma once
 
 #include "kernels_field.hpp"
@@ -21,6 +29,7 @@ struct McArgs {
     T cos_cone;
     ThermalKey key;  // seed, sweep number (step words), replica
     int colour;
+    const double* cone_dev;   // adaptive cone (degrees) on the device, or null: cos_cone
 };
 
 template <typename T>
@@ -75,7 +84,8 @@ __global__ void __launch_bounds__(256) k_mc_colour(Lattice L, BondCoef<double> C
             const V3<double> ni{(double)n[i], (double)n[L.N + i], (double)n[2 * L.N + i]};
             double u[3];
             mc_uniforms<double>(thermal_bits(M.key, (uint32_t)i), u);
-            const V3<double> nn = mc_trial(ni, u, M.cos_cone);
+            const double cos_cone = M.cone_dev ? cos(*M.cone_dev * (3.141592653589793 / 180.0)) : M.cos_cone;
+            const V3<double> nn = mc_trial(ni, u, cos_cone);
             const FieldTerms<double> f = site_terms<double, T>(L, C, P, n, i, ni);
             const V3<double> lin = f.z + f.j + f.d;
             const V3<double> ax{P.Kax[0][0], P.Kax[0][1], P.Kax[0][2]};
@@ -93,6 +103,30 @@ __global__ void __launch_bounds__(256) k_mc_colour(Lattice L, BondCoef<double> C
     if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = (unsigned int)__popcll(mask);
     __syncthreads();
     if (threadIdx.x == 0) acc_part[blockIdx.x] += cnt[0] + cnt[1] + cnt[2] + cnt[3];
+}
+
+// Feedback of the adaptive cone after one sweep: the sweep's accepted trials
+// are the growth of the run's per-workgroup counts (summed in a fixed
+// order) since the previous sweep; state[0] is the cone in degrees,
+// state[1] the count at the previous sweep.
+__global__ void __launch_bounds__(256) k_mc_adapt(const unsigned int* __restrict__ acc_part, int blocks,
+                                                  long long n_sites, double target, double* __restrict__ state) {
+    __shared__ unsigned long long red[256];
+    unsigned long long t = 0;
+    for (int b = threadIdx.x; b < blocks; b += 256) t += acc_part[b];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double total = (double)red[0];
+        const double a = n_sites > 0 ? (total - state[1]) / (double)n_sites : 0.0;
+        const double c = state[0] * (1.0 + a - target);
+        state[0] = c > 180.0 ? 180.0 : c;
+        state[1] = total;
+    }
 }
 
 }  // namespace sp

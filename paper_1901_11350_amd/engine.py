@@ -80,7 +80,7 @@ SOLVERS = {"depondt": 0, "heun": 1, "sib": 2}   # sp_solver
 
 class sp_mc_params(ctypes.Structure):
     _fields_ = [("T_K", ctypes.c_double), ("cone_deg", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("replica", ctypes.c_uint32)]
+                ("replica", ctypes.c_uint32), ("target_acceptance", ctypes.c_double)]
 
 
 class sp_observation(ctypes.Structure):
@@ -154,7 +154,7 @@ def lib():
         "sp_set_step_path": (ci, [vp, ctypes.c_char_p]),
         "sp_autotune": (ci, [vp, ctypes.POINTER(sp_llg_params), ci, dp]),
         "sp_mc_run": (ci, [vp, ctypes.POINTER(sp_mc_params), i64, i64, ctypes.POINTER(sp_observation),
-                           ctypes.POINTER(i64)]),
+                           ctypes.POINTER(i64), dp]),
         "sp_batch_create": (ci, [ctypes.POINTER(vp), ci, vp]),
         "sp_batch_destroy": (None, [vp]),
         "sp_batch_last_error": (ctypes.c_char_p, [vp]),
@@ -403,15 +403,17 @@ class Engine:
         self._check(lib().sp_set_graph_replay(self._h, 1 if enable else 0))
 
     def mc_run(self, T: float, cone_deg: float, n_sweeps: int, seed: int = 0, replica: int = 0,
-               observe_every: int = 0):
-        """Metropolis sweeps; returns (observations, accepted trials)."""
-        p = sp_mc_params(T, cone_deg, seed, replica)
+               observe_every: int = 0, target_acceptance: float = 0.0, return_cone: bool = False):
+        """Metropolis sweeps; returns (observations, accepted trials[, final cone])."""
+        p = sp_mc_params(T, cone_deg, seed, replica, target_acceptance)
         n_obs = n_sweeps // observe_every if observe_every > 0 else 0
         obs = (sp_observation * max(n_obs, 1))()
         acc = ctypes.c_int64()
+        cone = ctypes.c_double()
         self._check(lib().sp_mc_run(self._h, ctypes.byref(p), n_sweeps, observe_every, obs if n_obs else None,
-                                    ctypes.byref(acc)))
-        return [obs_dict(o) for o in obs[:n_obs]], acc.value
+                                    ctypes.byref(acc), ctypes.byref(cone)))
+        out = ([obs_dict(o) for o in obs[:n_obs]], acc.value)
+        return out + (cone.value,) if return_cone else out
 
     def autotune(self, alpha: float, dt: float, T: float = 0.0, seed: int = 0, n_steps: int = 50,
                  solver: str = "depondt") -> float:

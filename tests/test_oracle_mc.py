@@ -1,8 +1,12 @@
-"""Pins of the oracle's Metropolis Monte Carlo (Sec. III.B): the local energy
-change against the full energy difference, Boltzmann statistics of
+"""Pins of the oracle's Metropolis Monte Carlo (Sec. III.B: every spin picked
+once per sweep, sequentially in random order, cone trial steps, adaptive
+cone): the local energy change against the full energy difference, the
+visiting order as a uniformly random permutation, Boltzmann statistics of
 non-interacting spins in a field (Langevin function) and with uniaxial
-anisotropy (a one-dimensional integral), the cone trial distribution, and
-the lattices the two-colour sweep admits."""
+anisotropy (a one-dimensional integral), of an interacting pair (Langevin
+function of the pair coupling), the cone trial distribution, the adaptive
+cone's feedback and its fixed point, and order/disorder of the cubic
+ferromagnet."""
 
 import math
 
@@ -100,15 +104,81 @@ def test_ferromagnet_orders_below_and_disorders_above_tc(ora):
     assert res[40.0] < 0.12
 
 
-def test_two_colour_sweep_needs_a_bipartite_bond_graph(ora):
+def test_sweep_takes_any_lattice_but_not_the_dipole_term(ora):
+    """The sequential sweep needs no colouring: odd rings, odd periodic
+    lengths, bonds within a colour and a two-atom basis all sweep; the
+    dipole term (not local) is rejected."""
     nn = si.Hamiltonian(mu=(2.0,), B=(0, 0, 1.0), K=(0.0,), K_axis=((0, 0, 1),), J=(1.0,))
     nnn = si.Hamiltonian(mu=(2.0,), B=(0, 0, 1.0), K=(0.0,), K_axis=((0, 0, 1),), J=(1.0, 0.5))
-    cases = [(si.triangular(8, 8), nn),            # odd rings
-             (si.simple_cubic(5, 4, 4), nn),       # odd periodic length
-             (si.square(8, 8), nnn)]               # diagonal bonds join equal colours
-    for geo, ham in cases:
+    two = si.Geometry(((1, 0, 0), (0, 1, 0), (0, 0, 1)), ((0, 0, 0), (0.5, 0.5, 0)), (4, 4, 1), (1, 1, 0))
+    ham2 = si.Hamiltonian(mu=(2.0, 1.0), B=(0, 0, 1.0), K=(0.0, 0.1), K_axis=((0, 0, 1), (0, 0, 1)), J=(1.0,))
+    for geo, ham in [(si.triangular(8, 8), nn), (si.simple_cubic(5, 4, 4), nn), (si.square(8, 8), nnn),
+                     (two, ham2)]:
         s = ora.System(geo, ham)
-        with pytest.raises(ValueError):
-            s.mc_run(si.uniform_sphere(s.N, 1), 5.0, 30.0, 1)
-    s = ora.System(si.simple_cubic(5, 4, 4, periodic=(0, 1, 1)), nn)   # odd but open: fine
-    s.mc_run(si.uniform_sphere(s.N, 1), 5.0, 30.0, 1)
+        n, _, acc = s.mc_run(si.uniform_sphere(s.N, 1), 5.0, 30.0, 2)
+        assert 0 < acc <= 2 * s.N
+        assert np.allclose(np.linalg.norm(n, axis=0), 1.0, atol=1e-14)
+    film = ora.System(si.simple_cubic(4, 4, 1, periodic=(0, 0, 0)),
+                      si.Hamiltonian(mu=(2.0,), B=(0, 0, 0), K=(0.0,), K_axis=((0, 0, 1),), ddi=1))
+    with pytest.raises(ValueError):
+        film.mc_run(si.uniform_sphere(film.N, 1), 5.0, 30.0, 1)
+
+
+def test_visiting_order_is_a_uniform_random_permutation(ora):
+    """Each sweep visits every site exactly once; over many sweeps every
+    site is equally likely at every position (chi-square over the position
+    of two sites), and the orders of different sweeps, seeds and replicas
+    differ."""
+    N, sweeps = 37, 20000
+    pos = np.zeros((2, N))
+    for t in range(sweeps):
+        o = ora.mc_order(N, 11, t)
+        assert np.array_equal(np.sort(o), np.arange(N))
+        pos[0, np.flatnonzero(o == 0)[0]] += 1
+        pos[1, np.flatnonzero(o == N - 1)[0]] += 1
+    expect = sweeps / N
+    for row in pos:
+        chi2 = float(((row - expect) ** 2 / expect).sum())
+        assert chi2 < 80.0      # 36 degrees of freedom: p ~ 5e-5
+    assert not np.array_equal(ora.mc_order(N, 11, 0), ora.mc_order(N, 11, 1))
+    assert not np.array_equal(ora.mc_order(N, 11, 0), ora.mc_order(N, 12, 0))
+    assert not np.array_equal(ora.mc_order(N, 11, 0, 1), ora.mc_order(N, 11, 0, 0))
+
+
+def test_interacting_pair_samples_the_langevin_function_of_its_coupling(ora):
+    """Two sites on a periodic chain of length 2 are bonded twice (through
+    +a and -a), so E = -2 J n1.n2 and <n1.n2> = L(2 J / k_B T) with
+    L(x) = coth x - 1/x: an exact pin of the Boltzmann weight of an
+    interacting system, the pair counting and the sequential updates."""
+    J, T = 1.0, 20.0
+    geo = si.simple_cubic(2, 1, 1, periodic=(1, 0, 0))
+    ham = si.Hamiltonian(mu=(2.0,), B=(0, 0, 0), K=(0.0,), K_axis=((0, 0, 1),), J=(J,))
+    s = ora.System(geo, ham)
+    x = 2 * J / (K_B * T)
+    expect = 1 / math.tanh(x) - 1 / x
+    n, _, _ = s.mc_run(si.uniform_sphere(2, 4), T, 90.0, 2000, seed=21)
+    vals = []
+    for k in range(40):
+        n, obs, _ = s.mc_run(n, T, 90.0, 5000, seed=21, sweep0=2000 + 5000 * k, observe_every=1)
+        # E = -2 J n1.n2 for this system
+        vals.append(np.mean([-o["E"] / (2 * J) for o in obs]))
+    mean, err = np.mean(vals), np.std(vals) / math.sqrt(len(vals))
+    assert abs(mean - expect) < max(4 * err, 2e-3), (mean, err, expect)
+
+
+def test_adaptive_cone_feedback(ora):
+    """The cone grows while more than the target is accepted and shrinks
+    while fewer are (multiplied by 1 + a - a*, capped at 180 degrees); a run
+    with the feedback settles where the acceptance equals the target."""
+    assert ora.mc_adapt_cone(30.0, 0.7, 0.5) == pytest.approx(36.0, rel=1e-15)
+    assert ora.mc_adapt_cone(30.0, 0.2, 0.5) == pytest.approx(21.0, rel=1e-15)
+    assert ora.mc_adapt_cone(170.0, 1.0, 0.5) == 180.0
+    assert ora.mc_adapt_cone(30.0, 0.2, 0.0) == 30.0
+    geo = si.simple_cubic(8, 8, 8)
+    ham = si.Hamiltonian(mu=(2.0,), B=(0, 0, 0), K=(0.0,), K_axis=((0, 0, 1),), J=(1.0,))
+    s = ora.System(geo, ham)
+    for start in (5.0, 150.0):
+        n, _, _, cone = s.mc_run(si.ferromagnet(s.N, (0, 0, 1)), 10.0, start, 400, seed=2,
+                                 target_acceptance=0.5, return_cone=True)
+        n, _, acc = s.mc_run(n, 10.0, cone, 200, seed=2, sweep0=400)
+        assert acc / (200 * s.N) == pytest.approx(0.5, abs=0.03), (start, cone)
