@@ -115,6 +115,7 @@ struct sp_engine {
     int shape3 = -1;                  // sp::Shape3D matched by a 3D one-atom bond table, or -1
     bool explicit_pairs = false;      // bond table from sp_set_pairs (no compile-time stencil paths)
     int shape3_ndmi = 0;              // DMI on the first shell
+    int shape3_dk = 0;                // sp::Dmi3 of the streamed step kernel
     int tile3_cfg = 0;                // index into the 3D tile configurations
     int persist_cfg = 0;              // index into the persistent-path tile configurations
     std::string path_label;
@@ -845,6 +846,31 @@ int detect_shape3(const sp_engine* e) {
     return -1;
 }
 
+// Whether the six nearest-neighbour bonds carry the bulk DMI form
+// D_b = D0 (da, db, dc) (simple cubic, unit bond vectors) with one D0;
+// *D0 receives it.
+bool bulk_dmi3(const std::vector<HostBond>& bonds, double* D0) {
+    double d0 = 0.0;
+    bool have = false;
+    int found = 0;
+    for (const HostBond& b : bonds) {
+        if (b.shell != 0) continue;
+        const int L1 = std::abs(b.d[0]) + std::abs(b.d[1]) + std::abs(b.d[2]);
+        if (L1 != 1) return false;
+        const double c = b.d[0] * b.D[0] + b.d[1] * b.D[1] + b.d[2] * b.D[2];
+        if (!have) {
+            d0 = c;
+            have = true;
+        }
+        for (int k = 0; k < 3; ++k)
+            if (std::fabs(b.D[k] - d0 * b.d[k]) > 1e-14 * std::fabs(d0)) return false;
+        ++found;
+    }
+    if (found != 6 || d0 == 0.0) return false;
+    if (D0) *D0 = d0;
+    return true;
+}
+
 template <typename T, int S>
 sp::ShapeCoef3<T> shape_coef3_for(const sp_engine* e) {
     using SH = sp::ShapeTab3<S>;
@@ -857,10 +883,12 @@ sp::ShapeCoef3<T> shape_coef3_for(const sp_engine* e) {
                 C.Dy[q] = (T)b.D[1];
                 C.Dz[q] = (T)b.D[2];
             }
+    double d0 = 0.0;
+    if (bulk_dmi3(e->all_bonds, &d0)) C.D0 = (T)d0;
     return C;
 }
 
-template <typename T, int S, int NDMI, int TX, int TY, int SOLVER>
+template <typename T, int S, int DK, int TX, int TY, int SOLVER>
 void go_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     const int target = kTile3Cfgs[e->tile3_cfg].blocks;
     sp::Site3D Z{};
@@ -873,27 +901,27 @@ void go_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* 
     Z.zc = (Z.nc + chunks - 1) / chunks;
     const int nchunks = (Z.nc + Z.zc - 1) / Z.zc;
     Z.xcd_bands = ((txy * nchunks) % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, NDMI, TX, TY, SOLVER>), dim3((unsigned)(txy * nchunks)),
+    hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, DK, TX, TY, SOLVER>), dim3((unsigned)(txy * nchunks)),
                        dim3(TX * TY), 0, e->stream, shape_coef3_for<T, S>(e), make_site2d<T>(e, p), Z,
                        make_step_llg<T>(e, p, step), e->d_flag, static_cast<const T*>(nin), static_cast<T*>(nout));
 }
 
+template <typename T, int S, int TX, int TY, int SOLVER>
+void go_dk3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    if (e->shape3_dk == sp::DK_BULK)
+        go_shape3<T, S, sp::DK_BULK, TX, TY, SOLVER>(e, p, step, nin, nout);
+    else if (e->shape3_dk == sp::DK_GENERAL)
+        go_shape3<T, S, sp::DK_GENERAL, TX, TY, SOLVER>(e, p, step, nin, nout);
+    else
+        go_shape3<T, S, sp::DK_NONE, TX, TY, SOLVER>(e, p, step, nin, nout);
+}
+
 template <typename T, int TX, int TY, int SOLVER>
 void go_tile3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
-    const bool dmi = e->shape3_ndmi != 0;
     switch (e->shape3) {
-        case sp::SH3_SC1:
-            dmi ? go_shape3<T, sp::SH3_SC1, 6, TX, TY, SOLVER>(e, p, step, nin, nout)
-                : go_shape3<T, sp::SH3_SC1, 0, TX, TY, SOLVER>(e, p, step, nin, nout);
-            break;
-        case sp::SH3_SC2:
-            dmi ? go_shape3<T, sp::SH3_SC2, 6, TX, TY, SOLVER>(e, p, step, nin, nout)
-                : go_shape3<T, sp::SH3_SC2, 0, TX, TY, SOLVER>(e, p, step, nin, nout);
-            break;
-        default:
-            dmi ? go_shape3<T, sp::SH3_SC3, 6, TX, TY, SOLVER>(e, p, step, nin, nout)
-                : go_shape3<T, sp::SH3_SC3, 0, TX, TY, SOLVER>(e, p, step, nin, nout);
-            break;
+        case sp::SH3_SC1: go_dk3<T, sp::SH3_SC1, TX, TY, SOLVER>(e, p, step, nin, nout); break;
+        case sp::SH3_SC2: go_dk3<T, sp::SH3_SC2, TX, TY, SOLVER>(e, p, step, nin, nout); break;
+        default: go_dk3<T, sp::SH3_SC3, TX, TY, SOLVER>(e, p, step, nin, nout); break;
     }
 }
 
@@ -1743,6 +1771,7 @@ int install_ham(sp_engine* e, const HostHam& H, const std::vector<HostBond>& bon
     // compile-time simple-cubic stencil (DMI on the first shell only)
     e->shape3 = -1;
     e->shape3_ndmi = 0;
+    e->shape3_dk = sp::DK_NONE;
     // default 3D tile: 32x16 columns, two workgroups per CU (fastest measured
     // on the 128^3 workload); FP64 takes 16x16 (LDS)
     e->tile3_cfg = e->precision == SP_F64 ? 1 : 4;
@@ -1755,6 +1784,8 @@ int install_ham(sp_engine* e, const HostHam& H, const std::vector<HostBond>& bon
             e->shape3 = shp;
             for (const HostBond& b : all_bonds)
                 if (b.shell == 0 && (b.D[0] != 0.0 || b.D[1] != 0.0 || b.D[2] != 0.0)) e->shape3_ndmi = 1;
+            e->shape3_dk = e->shape3_ndmi ? (bulk_dmi3(all_bonds, nullptr) ? sp::DK_BULK : sp::DK_GENERAL)
+                                          : sp::DK_NONE;
             e->path = "shape3d";
         }
     }

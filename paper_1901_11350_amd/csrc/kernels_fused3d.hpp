@@ -60,7 +60,15 @@ template <typename T>
 struct ShapeCoef3 {
     T J[4];
     T Dx[8], Dy[8], Dz[8];   // first-shell bonds only
+    T D0;                    // the bulk form: D_b = D0 r_b on the six first-shell bonds
 };
+
+// DMI of the streamed step kernel: none; any vectors on the first shell; or
+// the bulk form D0 r_b (r_b the bond direction) on the six nearest
+// neighbours, whose sum over the bonds is
+//   sum_b n_b x D0 r_b = D0 [(n_+x - n_-x) x x + (n_+y - n_-y) x y + (n_+z - n_-z) x z]
+// (three differences instead of six cross products).
+enum Dmi3 { DK_NONE = 0, DK_GENERAL = 1, DK_BULK = 2 };
 
 struct Site3D {
     int nc, per_c;
@@ -78,32 +86,52 @@ struct PlaneLDS {
     V4<T> sP[3][PP];   // predictor plane k lives in slot k mod 3
 };
 
-// Field of a site whose own plane sits in ring slot s0 at LDS cell c (pitch
-// W); neighbours in planes c +- 1 sit in slots sm, sp.
-template <typename T, int S, int NDMI, int W, int PL>
+// Field of one site from its 3 x 3 x 3 neighbourhood in LDS: bm, b0 and bp
+// point at cell (-1, -1) of the site's row in the planes below, at and above
+// it (row pitch W), so every neighbour is a non-negative compile-time offset
+// from one of three base addresses.  aniso: the anisotropy term is non-zero.
+template <typename T, int S, int DK, int W>
 __device__ __forceinline__ V3<T> shape_field3(const ShapeCoef3<T>& C, const Site2D<T>& Q,
-                                              const V4<T> (*rings)[PL], int sm, int s0, int sp, int c, V3<T> ni) {
+                                              const V4<T>* __restrict__ bm, const V4<T>* __restrict__ b0,
+                                              const V4<T>* __restrict__ bp, V3<T> ni, bool aniso) {
     using SH = ShapeTab3<S>;
+    static_assert(SH::da[0] == 1 && SH::da[1] == -1 && SH::db[2] == 1 && SH::db[3] == -1 && SH::dc[4] == 1 &&
+                      SH::dc[5] == -1,
+                  "first six bonds are +x, -x, +y, -y, +z, -z");
     V3<T> acc[SH::NS];
 #pragma unroll
     for (int s = 0; s < SH::NS; ++s) acc[s] = V3<T>{T(0), T(0), T(0)};
     V3<T> dm{T(0), T(0), T(0)};
+    V3<T> nn[6];
 #pragma unroll
     for (int q = 0; q < SH::NB; ++q) {
-        const int slot = SH::dc[q] < 0 ? sm : (SH::dc[q] > 0 ? sp : s0);
-        const V3<T> v = lds_cell_xyz(rings[slot], c + SH::da[q] + SH::db[q] * W);
+        const V4<T>* b = SH::dc[q] < 0 ? bm : (SH::dc[q] > 0 ? bp : b0);
+        const V3<T> v = lds_cell_xyz(b, (SH::da[q] + 1) + (SH::db[q] + 1) * W);
         acc[SH::sh[q]].x += v.x;
         acc[SH::sh[q]].y += v.y;
         acc[SH::sh[q]].z += v.z;
-        if (q < NDMI) {
-            // n_j x D
-            dm.x += v.y * C.Dz[q] - v.z * C.Dy[q];
-            dm.y += v.z * C.Dx[q] - v.x * C.Dz[q];
-            dm.z += v.x * C.Dy[q] - v.y * C.Dx[q];
+        if constexpr (DK == DK_GENERAL) {
+            if (q < SH::NB0) {
+                // n_j x D
+                dm.x += v.y * C.Dz[q] - v.z * C.Dy[q];
+                dm.y += v.z * C.Dx[q] - v.x * C.Dz[q];
+                dm.z += v.x * C.Dy[q] - v.y * C.Dx[q];
+            }
         }
+        if (q < 6) nn[q] = v;
     }
-    const T kn = Q.K2 * (Q.Kax[0] * ni.x + Q.Kax[1] * ni.y + Q.Kax[2] * ni.z);
-    V3<T> g{Q.gZ[0] - kn * Q.Kax[0] - dm.x, Q.gZ[1] - kn * Q.Kax[1] - dm.y, Q.gZ[2] - kn * Q.Kax[2] - dm.z};
+    if constexpr (DK == DK_BULK) {
+        dm.x = C.D0 * ((nn[4].y - nn[5].y) - (nn[2].z - nn[3].z));
+        dm.y = C.D0 * ((nn[0].z - nn[1].z) - (nn[4].x - nn[5].x));
+        dm.z = C.D0 * ((nn[2].x - nn[3].x) - (nn[0].y - nn[1].y));
+    }
+    V3<T> g{Q.gZ[0] - dm.x, Q.gZ[1] - dm.y, Q.gZ[2] - dm.z};
+    if (aniso) {
+        const T kn = Q.K2 * (Q.Kax[0] * ni.x + Q.Kax[1] * ni.y + Q.Kax[2] * ni.z);
+        g.x -= kn * Q.Kax[0];
+        g.y -= kn * Q.Kax[1];
+        g.z -= kn * Q.Kax[2];
+    }
 #pragma unroll
     for (int s = 0; s < SH::NS; ++s) {
         g.x -= C.J[s] * acc[s].x;
@@ -124,7 +152,7 @@ __device__ __forceinline__ int wrap_plane(int z, int nc, int per, bool& in) {
     return z < 0 ? z + nc : z;
 }
 
-template <typename T, int S, int NDMI, int TX, int TY, int SOLVER>
+template <typename T, int S, int DK, int TX, int TY, int SOLVER>
 __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site2D<T> Q, Site3D Z, LLGArgs<T> A_arg,
                                                             const int* __restrict__ abort_flag,
                                                             const T* __restrict__ n, T* __restrict__ nout) {
@@ -132,6 +160,7 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
     const LLGArgs<T> A = resolve_step(A_arg);
     using PL = PlaneLDS<T, S, TX, TY>;
     constexpr int R = PL::R, WN = PL::WN, PN = PL::PN, WP = PL::WP, PP = PL::PP;
+    static_assert(R == 1, "one-cell stencil reach");
     constexpr int NT = TX * TY;
     constexpr int RING = PP - TX * TY;
     constexpr int KST = (PN + NT - 1) / NT;
@@ -154,28 +183,63 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
     const long long plane = (long long)NA * NBB;
     const long long N = plane * Z.nc;
     const int tx = tid % TX, tyy = tid / TX;
+    const bool aniso = Q.K2 != T(0);
     // predictor ring slot of plane z (z >= -2)
     auto pslot = [](int z) { return (z + 3) % 3; };
+
+    // Everything in a and b is the same on every plane: the staged cells'
+    // in-plane offsets and in-sample flags, the predictor cells this thread
+    // owns (its site and its ring cells) and their LDS positions.
+    long long ld_off[KST];
+    bool ld_in[KST];
+#pragma unroll
+    for (int k = 0; k < KST; ++k) {
+        const int idx = tid + k * NT;
+        const int ly = idx / WN, lx = idx - ly * WN;
+        bool in = idx < PN;
+        const int gx = wrap_once(x0 - 2 * R + lx, NA, Q.per_a, in);
+        const int gy = wrap_once(y0 - 2 * R + ly, NBB, Q.per_b, in);
+        ld_off[k] = gx + (long long)NA * gy;
+        ld_in[k] = in;
+    }
+    // predictor cell (px, py): LDS cell of its n(t) (pitch WN, halo 2R), of
+    // its output (pitch WP, halo R), in-plane offset and flag
+    bool pi_in = true;
+    long long pi_off;
+    {
+        const int gx = wrap_once(x0 + tx, NA, Q.per_a, pi_in);
+        const int gy = wrap_once(y0 + tyy, NBB, Q.per_b, pi_in);
+        pi_off = gx + (long long)NA * gy;
+    }
+    int rg_px[KRG], rg_py[KRG];
+    bool rg_in[KRG];
+    long long rg_off[KRG];
+#pragma unroll
+    for (int q = 0; q < KRG; ++q) {
+        const int h = tid + q * NT;
+        rg_in[q] = h < RING;
+        int px = 0, py = 0;
+        if (rg_in[q]) ring_cell<R, TX, TY>(h, px, py);
+        const int gx = wrap_once(x0 - R + px, NA, Q.per_a, rg_in[q]);
+        const int gy = wrap_once(y0 - R + py, NBB, Q.per_b, rg_in[q]);
+        rg_px[q] = px;
+        rg_py[q] = py;
+        rg_off[q] = gx + (long long)NA * gy;
+    }
+    const bool own_site = x0 + tx < NA && y0 + tyy < NBB;
 
     // n(t) of plane z (tile + 2R halo): load into registers, later store into
     // ring slot z & 3 (the loads of plane k+2 fly while planes k and k-1 are
     // computed)
     auto load_plane = [&](int z, V3<T>* st) {
         bool zin = true;
-        const int gz = wrap_plane(z, Z.nc, Z.per_c, zin);
+        const long long gz = wrap_plane(z, Z.nc, Z.per_c, zin) * plane;
 #pragma unroll
         for (int k = 0; k < KST; ++k) {
-            const int idx = tid + k * NT;
             st[k] = V3<T>{T(0), T(0), T(0)};
-            if (idx < PN) {
-                const int ly = idx / WN, lx = idx - ly * WN;
-                bool in = zin;
-                const int gx = wrap_once(x0 - 2 * R + lx, NA, Q.per_a, in);
-                const int gy = wrap_once(y0 - 2 * R + ly, NBB, Q.per_b, in);
-                if (in) {
-                    const long long g = gx + (long long)NA * gy + plane * gz;
-                    st[k] = V3<T>{n[g], n[N + g], n[2 * N + g]};
-                }
+            if (zin && ld_in[k]) {
+                const long long g = ld_off[k] + gz;
+                st[k] = V3<T>{n[g], n[N + g], n[2 * N + g]};
             }
         }
     };
@@ -187,28 +251,22 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
             if (idx < PN) dst[idx] = V4<T>{st[k].x, st[k].y, st[k].z, T(0)};
         }
     };
-    // thermal field of predictor-frame cell (px, py) of plane z
-    auto thermal = [&](int px, int py, int z) -> V3<T> {
-        bool in = true;
-        const int gz = wrap_plane(z, Z.nc, Z.per_c, in);
-        const int gx = wrap_once(x0 - R + px, NA, Q.per_a, in);
-        const int gy = wrap_once(y0 - R + py, NBB, Q.per_b, in);
+    // thermal field of a predictor cell of plane z (in-plane offset off)
+    auto thermal = [&](bool in, long long off, long long gz) -> V3<T> {
         if (!A.thermal || !in) return V3<T>{T(0), T(0), T(0)};
-        const long long site = gx + (long long)NA * gy + plane * gz;
-        return Q.sigma * normals3(thermal_bits(A.key, (uint32_t)site), T(0));
+        return Q.sigma * normals3(thermal_bits(A.key, (uint32_t)(off + gz)), T(0));
     };
-    // predictor of cell (px, py) of plane z into predictor slot z & 3
-    auto predict = [&](int px, int py, int z, V3<T> Bth) -> V3<T> {
-        bool in = true;
-        wrap_plane(z, Z.nc, Z.per_c, in);
-        wrap_once(x0 - R + px, NA, Q.per_a, in);
-        wrap_once(y0 - R + py, NBB, Q.per_b, in);
+    // predictor of predictor cell (px, py) of plane z into predictor slot
+    // pslot(z); returns what the corrector needs of the site
+    auto predict = [&](int px, int py, bool in, int z, V3<T> Bth) -> V3<T> {
         V4<T> out{T(0), T(0), T(0), T(0)};
         V3<T> keep{T(0), T(0), T(0)};
         if (in) {
             const int c = (py + R) * WN + (px + R);
             const V3<T> ni = lds_cell_xyz(L.sN[z & 3], c);
-            const V3<T> g = shape_field3<T, S, NDMI, WN, PN>(C, Q, L.sN, (z - 1) & 3, z & 3, (z + 1) & 3, c, ni);
+            const int cb = c - WN - 1;
+            const V3<T> g = shape_field3<T, S, DK, WN>(C, Q, L.sN[(z - 1) & 3] + cb, L.sN[z & 3] + cb,
+                                                       L.sN[(z + 1) & 3] + cb, ni, aniso);
             const V3<T> B = (-Q.inv_mumuB) * g + Bth;
             const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
             V3<T> o;
@@ -235,44 +293,34 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
     store_plane(z0 - 1, st);
     load_plane(z0, st);
     V3<T> keepA{T(0), T(0), T(0)}, keepB{T(0), T(0), T(0)};   // of the previous plane
+    const int cP = (tyy + R) * WP + (tx + R);                  // the site's predictor cell
+    const int cN = (tyy + 2 * R) * WN + (tx + 2 * R);          // the site's n(t) cell
     for (int k = z0 - 1; k <= z1; ++k) {
+        bool zin = true;
+        const long long gz = wrap_plane(k, Z.nc, Z.per_c, zin) * plane;
         // thermal fields of this thread's cells of plane k, then stage n(t) plane k+1
-        const V3<T> bI = thermal(tx + R, tyy + R, k);
+        const V3<T> bI = thermal(zin && pi_in, pi_off, gz);
         V3<T> bR[KRG];
 #pragma unroll
-        for (int q = 0; q < KRG; ++q) {
-            const int h = tid + q * NT;
-            bR[q] = V3<T>{T(0), T(0), T(0)};
-            if (h < RING) {
-                int px, py;
-                ring_cell<R, TX, TY>(h, px, py);
-                bR[q] = thermal(px, py, k);
-            }
-        }
+        for (int q = 0; q < KRG; ++q) bR[q] = thermal(zin && rg_in[q], rg_off[q], gz);
         store_plane(k + 1, st);
         if (k + 2 <= z1 + 1) load_plane(k + 2, st);
         __syncthreads();
-        const V3<T> aI = predict(tx + R, tyy + R, k, bI);
+        const V3<T> aI = predict(tx + R, tyy + R, zin && pi_in, k, bI);
 #pragma unroll
-        for (int q = 0; q < KRG; ++q) {
-            const int h = tid + q * NT;
-            if (h < RING) {
-                int px, py;
-                ring_cell<R, TX, TY>(h, px, py);
-                predict(px, py, k, bR[q]);
-            }
-        }
+        for (int q = 0; q < KRG; ++q)
+            if (tid + q * NT < RING) predict(rg_px[q], rg_py[q], zin && rg_in[q], k, bR[q]);
         __syncthreads();
         // corrector of plane k-1
         const int zc = k - 1;
-        const int gx = x0 + tx, gy = y0 + tyy;
-        if (zc >= z0 && zc < z1 && gx < NA && gy < NBB) {
-            const int c = (tyy + R) * WP + (tx + R);
-            const V3<T> npi = lds_cell_xyz(L.sP[pslot(zc)], c);
-            const V3<T> g = shape_field3<T, S, NDMI, WP, PP>(C, Q, L.sP, pslot(zc - 1), pslot(zc), pslot(zc + 1), c, npi);
+        if (zc >= z0 && zc < z1 && own_site) {
+            const V3<T> npi = lds_cell_xyz(L.sP[pslot(zc)], cP);
+            const int cb = cP - WP - 1;
+            const V3<T> g = shape_field3<T, S, DK, WP>(C, Q, L.sP[pslot(zc - 1)] + cb, L.sP[pslot(zc)] + cb,
+                                                       L.sP[pslot(zc + 1)] + cb, npi, aniso);
             const V3<T> B = (-Q.inv_mumuB) * g + keepB;
             const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
-            const V3<T> ni = lds_cell_xyz(L.sN[zc & 3], (tyy + 2 * R) * WN + (tx + 2 * R));
+            const V3<T> ni = lds_cell_xyz(L.sN[zc & 3], cN);
             V3<T> o;
             if constexpr (SOLVER == SOLVER_HEUN) {
                 o = normalize3(ni + (T(0.5) * A.dt) * (keepA + cross(npi, Ap)));
@@ -282,7 +330,7 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
                 const V3<T> w{T(-0.5) * (keepA.x + Ap.x), T(-0.5) * (keepA.y + Ap.y), T(-0.5) * (keepA.z + Ap.z)};
                 o = renorm_if_float(rotate_fast(ni, w, A.dt));
             }
-            const long long gi = gx + (long long)NA * gy + plane * zc;
+            const long long gi = pi_off + (long long)zc * plane;
             store_out(nout + gi, o.x);
             store_out(nout + N + gi, o.y);
             store_out(nout + 2 * N + gi, o.z);
