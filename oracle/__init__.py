@@ -162,6 +162,12 @@ def lib():
         L.ora_bf16.restype = ctypes.c_double
         L.ora_bf16.argtypes = [ctypes.c_double]
         L.ora_conv_set_exact.argtypes = [ctypes.c_int]
+        L.ora_ddr_check.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.ora_ddr_moments.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
+        L.ora_ddr_backbone.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp]
+        L.ora_ddr_project.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
+        L.ora_ddr_expand.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
         ci = ctypes.c_int
         L.ora_conv3x3_fwd.argtypes = [ci, ci, ci, ci, ci, dp, dp, dp, dp]
         L.ora_conv3x3_bwd.argtypes = [ci, ci, ci, ci, ci, dp, dp, dp, dp, dp, dp]
@@ -346,6 +352,41 @@ class System:
             raise ValueError("Monte Carlo sweeps do not support the dipole term")
         out = (n, [_obs_dict(o) for o in obs[:k]], acc.value)
         return out + (cone.value,) if return_cone else out
+
+    # residual form of the learned dipole field (block images [qb][qa][12])
+    def _ddr_dims(self, B):
+        if lib().ora_ddr_check(self._p, B) != 0:
+            raise ValueError("the residual form needs a one-atom film with sides divisible by the block")
+        na, nb = self.geometry.n_cells[0], self.geometry.n_cells[1]
+        return nb // B, na // B
+
+    def ddr_moments(self, n, B) -> np.ndarray:
+        h, w = self._ddr_dims(B)
+        out = np.zeros((h, w, 12))
+        lib().ora_ddr_moments(self._p, _dp(self._spins(n)), B, _dp(out))
+        return out
+
+    def ddr_backbone(self, n, B, reach, sites=None) -> np.ndarray:
+        """Backbone field (units of C_dd mu^2), shape (3, len(sites))."""
+        self._ddr_dims(B)
+        sites = np.arange(self.N) if sites is None else np.asarray(sites)
+        sites = np.ascontiguousarray(sites, dtype=np.int64)
+        out = np.zeros((len(sites), 3))
+        lib().ora_ddr_backbone(self._p, _dp(self._spins(n)), B, reach,
+                               sites.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(sites), _dp(out))
+        return out.T.copy()
+
+    def ddr_project(self, r, B) -> np.ndarray:
+        h, w = self._ddr_dims(B)
+        out = np.zeros((h, w, 12))
+        lib().ora_ddr_project(self._p, _dp(self._spins(r)), B, _dp(out))
+        return out
+
+    def ddr_expand(self, coef, B) -> np.ndarray:
+        self._ddr_dims(B)
+        out = np.zeros((3, self.N))
+        lib().ora_ddr_expand(self._p, _dp(np.ascontiguousarray(coef, dtype=np.float64)), B, _dp(out))
+        return out
 
     def observe(self, n, step=0) -> dict:
         n = self._spins(n)

@@ -1093,6 +1093,190 @@ void ora_gneb_vp(const ora_system *s, int M, double *chain, double *v, double *F
     free(F);
 }
 
+/* ------------------------------------- learned dipole field: residual form
+ * (not in the paper; a stand-in for its costliest term, the dipolar sum of
+ * Sec. III.A).  Sites of a one-atom film are grouped into blocks of B x B
+ * cells in the plane and every layer.  Block b (pixel (qa, qb) of the block
+ * grid) has the centroid R_b of its sites, the moment M_b = sum_j n_j and
+ * the first moments Q_b[g][c] = sum_j (r_jg - R_bg) n_jc.  The backbone
+ * field of site i, in units of C_dd mu^2 (u = sum_j K(r_j - r_i) n_j,
+ * K(r) = (1 - 3 r^ r^) / |r|^3, r in Angstrom), is summed exactly over the
+ * sites of the blocks within `reach` blocks of i's block along a and b, and
+ * takes every other block as the single dipole M_b at R_b.  The learned
+ * part corrects it per block by c0_b + (r_i - R_b) . c1_b (12 coefficients:
+ * c0[c], then c1[g][c] at 3 + 3 g + c); block images are [qb][qa][12]. */
+
+static void block_of(const ora_system *s, int64_t i, int B, int *qa, int *qb) {
+    int a, b, c, beta;
+    cell_of(s, i, &a, &b, &c, &beta);
+    *qa = a / B;
+    *qb = b / B;
+}
+
+int ora_ddr_check(const ora_system *s, int B) {
+    if (s->geo.n_basis != 1 || B < 1) return -1;
+    if (s->geo.n_cells[0] % B || s->geo.n_cells[1] % B) return -1;
+    return 0;
+}
+
+/* centroids R_b (Angstrom), [qb][qa][3] */
+static void block_centroids(const ora_system *s, int B, double *R) {
+    const int nba = s->geo.n_cells[0] / B, nbb = s->geo.n_cells[1] / B;
+    const int64_t nblk = (int64_t)nba * nbb;
+    int64_t *cnt = (int64_t *)calloc((size_t)nblk, sizeof(int64_t));
+    for (int64_t q = 0; q < 3 * nblk; ++q) R[q] = 0.0;
+    for (int64_t i = 0; i < s->N; ++i) {
+        int qa, qb;
+        block_of(s, i, B, &qa, &qb);
+        const int64_t q = (int64_t)qb * nba + qa;
+        for (int k = 0; k < 3; ++k) R[3 * q + k] += s->pos[k * s->N + i];
+        cnt[q]++;
+    }
+    for (int64_t q = 0; q < nblk; ++q)
+        for (int k = 0; k < 3; ++k) R[3 * q + k] /= (double)cnt[q];
+    free(cnt);
+}
+
+void ora_ddr_moments(const ora_system *s, const double *n, int B, double *feat) {
+    const int nba = s->geo.n_cells[0] / B, nbb = s->geo.n_cells[1] / B;
+    const int64_t nblk = (int64_t)nba * nbb, N = s->N;
+    double *R = (double *)malloc(sizeof(double) * 3 * (size_t)nblk);
+    block_centroids(s, B, R);
+    for (int64_t q = 0; q < 12 * nblk; ++q) feat[q] = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        int qa, qb;
+        block_of(s, i, B, &qa, &qb);
+        const int64_t q = (int64_t)qb * nba + qa;
+        double ni[3], d[3];
+        load(n, N, i, ni);
+        for (int g = 0; g < 3; ++g) d[g] = s->pos[g * N + i] - R[3 * q + g];
+        for (int c = 0; c < 3; ++c) {
+            feat[12 * q + c] += ni[c];
+            for (int g = 0; g < 3; ++g) feat[12 * q + 3 + 3 * g + c] += d[g] * ni[c];
+        }
+    }
+    free(R);
+}
+
+/* u += K(r) v for the vector r from the field point to the source */
+static void add_dipole(const double r[3], const double v[3], double u[3]) {
+    const double d = norm3(r);
+    const double rh[3] = {r[0] / d, r[1] / d, r[2] / d};
+    const double vr = dot3(v, rh), inv3 = 1.0 / (d * d * d);
+    for (int k = 0; k < 3; ++k) u[k] += (v[k] - 3.0 * vr * rh[k]) * inv3;
+}
+
+void ora_ddr_backbone(const ora_system *s, const double *n, int B, int reach, const int64_t *sites, int64_t n_req,
+                      double *u_out) {
+    const int nba = s->geo.n_cells[0] / B, nbb = s->geo.n_cells[1] / B;
+    const int64_t nblk = (int64_t)nba * nbb, N = s->N;
+    double *R = (double *)malloc(sizeof(double) * 3 * (size_t)nblk);
+    double *feat = (double *)malloc(sizeof(double) * 12 * (size_t)nblk);
+    block_centroids(s, B, R);
+    ora_ddr_moments(s, n, B, feat);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < n_req; ++t) {
+        const int64_t i = sites[t];
+        int qa, qb;
+        block_of(s, i, B, &qa, &qb);
+        double pi[3], u[3] = {0.0, 0.0, 0.0};
+        load(s->pos, N, i, pi);
+        /* near: every site of the blocks within reach */
+        for (int64_t j = 0; j < N; ++j) {
+            if (j == i) continue;
+            int ja, jb;
+            block_of(s, j, B, &ja, &jb);
+            if (abs(ja - qa) > reach || abs(jb - qb) > reach) continue;
+            double r[3], nj[3];
+            load(s->pos, N, j, r);
+            for (int k = 0; k < 3; ++k) r[k] -= pi[k];
+            load(n, N, j, nj);
+            add_dipole(r, nj, u);
+        }
+        /* far: one dipole per block */
+        for (int ob = 0; ob < nbb; ++ob)
+            for (int oa = 0; oa < nba; ++oa) {
+                if (abs(oa - qa) <= reach && abs(ob - qb) <= reach) continue;
+                const int64_t q = (int64_t)ob * nba + oa;
+                double r[3];
+                for (int k = 0; k < 3; ++k) r[k] = R[3 * q + k] - pi[k];
+                add_dipole(r, &feat[12 * q], u);
+            }
+        for (int k = 0; k < 3; ++k) u_out[3 * t + k] = u[k];
+    }
+    free(R);
+    free(feat);
+}
+
+/* Least squares per block: r_i ~ c0 + (r_i - R_b) . c1 over the block's
+ * sites, component by component (normal equations of the 4 unknowns,
+ * Gaussian elimination with partial pivoting). */
+void ora_ddr_project(const ora_system *s, const double *r, int B, double *coef) {
+    const int nba = s->geo.n_cells[0] / B, nbb = s->geo.n_cells[1] / B;
+    const int64_t nblk = (int64_t)nba * nbb, N = s->N;
+    double *R = (double *)malloc(sizeof(double) * 3 * (size_t)nblk);
+    double *A = (double *)calloc((size_t)nblk * 16, sizeof(double));
+    double *y = (double *)calloc((size_t)nblk * 12, sizeof(double));
+    block_centroids(s, B, R);
+    for (int64_t i = 0; i < N; ++i) {
+        int qa, qb;
+        block_of(s, i, B, &qa, &qb);
+        const int64_t q = (int64_t)qb * nba + qa;
+        double x[4] = {1.0, 0.0, 0.0, 0.0};
+        for (int g = 0; g < 3; ++g) x[1 + g] = s->pos[g * N + i] - R[3 * q + g];
+        for (int a = 0; a < 4; ++a) {
+            for (int b = 0; b < 4; ++b) A[16 * q + 4 * a + b] += x[a] * x[b];
+            for (int c = 0; c < 3; ++c) y[12 * q + 3 * a + c] += x[a] * r[c * N + i];
+        }
+    }
+    for (int64_t q = 0; q < nblk; ++q) {
+        double M[4][7];
+        for (int a = 0; a < 4; ++a) {
+            for (int b = 0; b < 4; ++b) M[a][b] = A[16 * q + 4 * a + b];
+            for (int c = 0; c < 3; ++c) M[a][4 + c] = y[12 * q + 3 * a + c];
+        }
+        for (int col = 0; col < 4; ++col) {
+            int piv = col;
+            for (int a = col + 1; a < 4; ++a)
+                if (fabs(M[a][col]) > fabs(M[piv][col])) piv = a;
+            for (int b = 0; b < 7; ++b) {
+                const double t = M[col][b];
+                M[col][b] = M[piv][b];
+                M[piv][b] = t;
+            }
+            for (int a = 0; a < 4; ++a) {
+                if (a == col) continue;
+                const double f = M[a][col] / M[col][col];
+                for (int b = col; b < 7; ++b) M[a][b] -= f * M[col][b];
+            }
+        }
+        /* unknowns: row 0 -> c0, rows 1..3 -> c1[g] */
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 3; ++c) coef[12 * q + 3 * a + c] = M[a][4 + c] / M[a][a];
+    }
+    free(R);
+    free(A);
+    free(y);
+}
+
+void ora_ddr_expand(const ora_system *s, const double *coef, int B, double *r) {
+    const int nba = s->geo.n_cells[0] / B, nbb = s->geo.n_cells[1] / B;
+    const int64_t nblk = (int64_t)nba * nbb, N = s->N;
+    double *R = (double *)malloc(sizeof(double) * 3 * (size_t)nblk);
+    block_centroids(s, B, R);
+    for (int64_t i = 0; i < N; ++i) {
+        int qa, qb;
+        block_of(s, i, B, &qa, &qb);
+        const int64_t q = (int64_t)qb * nba + qa;
+        for (int c = 0; c < 3; ++c) {
+            double v = coef[12 * q + c];
+            for (int g = 0; g < 3; ++g) v += (s->pos[g * N + i] - R[3 * q + g]) * coef[12 * q + 3 + 3 * g + c];
+            r[c * N + i] = v;
+        }
+    }
+    free(R);
+}
+
 /* ------------------------------------------------- convolutional surrogate
  * Not in the paper: a learned stand-in for the dipolar field.  Plain loops
  * over the definitions of a zero-padded 3x3 cross-correlation, SiLU, and the

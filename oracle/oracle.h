@@ -204,6 +204,24 @@ void ora_gneb_forces(const ora_system *s, int M, const double *chain, const ora_
 void ora_gneb_vp(const ora_system *s, int M, double *chain, double *v, double *F_prev,
                  const ora_gneb_params *p, int n_iter);
 
+/* ------------------------------------- learned dipole field: residual form
+ * (not in the paper).  Blocks of B x B cells in the plane and every layer of
+ * a one-atom film; block images are [qb][qa][12].  feat: moment M_b[c] at c,
+ * first moments Q_b[g][c] = sum_j (r_jg - R_bg) n_jc at 3 + 3 g + c (R_b the
+ * block's centroid, Angstrom).  Backbone field (units of C_dd mu^2, i.e.
+ * sum_j K(r_j - r_i) n_j with K(r) = (1 - 3 r^ r^)/|r|^3, r in Angstrom):
+ * exact over the sites of the blocks within `reach` blocks of i's block
+ * along a and b, one dipole M_b at R_b for every other block; u_out holds
+ * 3 values per requested site.  Coefficients c0[c] at c, c1[g][c] at
+ * 3 + 3 g + c: correction c0 + (r_i - R_b) . c1; ora_ddr_project fits them
+ * to a field by least squares per block, ora_ddr_expand evaluates them. */
+int ora_ddr_check(const ora_system *s, int B);
+void ora_ddr_moments(const ora_system *s, const double *n, int B, double *feat);
+void ora_ddr_backbone(const ora_system *s, const double *n, int B, int reach, const int64_t *sites, int64_t n_req,
+                      double *u_out);
+void ora_ddr_project(const ora_system *s, const double *r, int B, double *coef);
+void ora_ddr_expand(const ora_system *s, const double *coef, int B, double *r);
+
 /* ------------------------------------------------- convolutional surrogate
  * Layers of a 3x3 convolution, zero padding, NHWC activations
  * x[B][H][W][Cin], weights w[ky][kx][Cin][Cout], bias b[Cout].  The kernels'

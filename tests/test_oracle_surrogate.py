@@ -8,6 +8,8 @@ import pytest
 import torch
 import torch.nn.functional as F
 
+import spin_inputs as si
+
 
 def _bf16_exact(rng, shape, scale=64):
     """Random values exactly representable in bfloat16 (k/scale, |k| <= 127)."""
@@ -165,3 +167,89 @@ def test_dipole_field_is_not_determined_by_a_local_window(ora):
         pred = np.concatenate([(window(tex[k]).T @ Ws[z]).T for z in range(NL)], 1)
         errs.append(np.linalg.norm(G[k] - pred) / np.linalg.norm(G[k]))
     assert min(errs) > 5e-2
+
+
+# --------------------------------------------- residual form of the dipole field
+def _film(na, nb, nc):
+    geo = si.simple_cubic(na, nb, nc, periodic=(0, 0, 0))
+    ham = si.Hamiltonian(mu=(2.0,), B=(0, 0, 0), K=(0.0,), K_axis=((0, 0, 1),), ddi=1)
+    return geo, ham
+
+
+def test_ddr_backbone_with_full_reach_is_the_direct_sum(ora):
+    """When every block lies within reach, the backbone is the exact pair sum
+    (the direct-sum oracle divided by C_dd mu^2)."""
+    geo, ham = _film(12, 8, 3)
+    s = ora.System(geo, ham)
+    n = si.uniform_sphere(s.N, 4)
+    u = s.ddr_backbone(n, 4, 3)
+    g = s.dipole_gradient_sites(n, np.arange(s.N)) / (ora.constants()["C_dd"] * 4.0)
+    assert np.abs(u - g).max() <= 1e-13 * np.abs(g).max()
+
+
+def test_ddr_far_block_is_its_dipole_to_second_order(ora):
+    """One source block far along a chain of blocks: the backbone takes it
+    as its moment at its centroid.  With spins uniform inside the block the
+    first moments vanish (centroid), so the error of that term against the
+    exact sum over the block's sites falls as (block / distance)^2 relative
+    to the term, i.e. 32-fold when the distance doubles (1/D^5)."""
+    geo, ham = _film(96, 4, 2)
+    s = ora.System(geo, ham)
+    B = 4
+    errs, terms = [], []
+    for k in (6, 12):
+        n = np.zeros((3, s.N))
+        a = np.arange(s.N) % 96
+        n[:, (a // B) == k] = np.array([[0.3], [0.5], [0.81]])   # uniform spins in block k only
+        site = 1 + 96 * 2          # a site of block 0
+        u = s.ddr_backbone(n, B, 0, [site])[:, 0]
+        g = s.dipole_gradient_sites(n, [site])[:, 0] / (ora.constants()["C_dd"] * 4.0)
+        errs.append(np.linalg.norm(u - g))
+        terms.append(np.linalg.norm(g))
+    assert errs[0] / terms[0] < 0.01
+    assert 20 < errs[0] / errs[1] < 45
+
+
+def test_ddr_moments_of_linear_textures(ora):
+    """Inside every block n_c = v_c + (r - R_b) . G_c: the moment is the
+    site count times v, and the first moments are G_gc sum_i d_ig^2 (the
+    cross sums of a symmetric grid vanish)."""
+    geo, ham = _film(8, 12, 3)
+    s = ora.System(geo, ham)
+    B = 4
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(3)
+    G = rng.standard_normal((3, 3))
+    pos = np.stack([np.arange(s.N) % 8, (np.arange(s.N) // 8) % 12, np.arange(s.N) // 96]).astype(float)
+    R = np.stack([(pos[0] // B) * B + (B - 1) / 2, (pos[1] // B) * B + (B - 1) / 2, np.full(s.N, 1.0)])
+    d = pos - R
+    n = v[:, None] + np.einsum("gc,gi->ci", G, d)
+    f = s.ddr_moments(n, B)
+    # sums of d_x^2, d_y^2, d_z^2 over a block of B x B x 3 sites
+    ssq = [B * 3 * sum((k - (B - 1) / 2) ** 2 for k in range(B)), B * 3 * sum((k - (B - 1) / 2) ** 2 for k in range(B)),
+           B * B * 2.0]
+    for qb in range(3):
+        for qa in range(2):
+            assert np.allclose(f[qb, qa, :3], B * B * 3 * v, rtol=1e-12)
+            Q = f[qb, qa, 3:].reshape(3, 3)
+            assert np.allclose(Q, G * np.array(ssq)[:, None], rtol=1e-11, atol=1e-11)
+
+
+def test_ddr_projection_is_the_least_squares_fit(ora):
+    """expand then project returns the coefficients; on any field the
+    projection equals a per-block least-squares solve (numpy lstsq)."""
+    geo, ham = _film(8, 8, 2)
+    s = ora.System(geo, ham)
+    B = 4
+    rng = np.random.default_rng(9)
+    coef = rng.standard_normal((2, 2, 12))
+    assert np.allclose(s.ddr_project(s.ddr_expand(coef, B), B), coef, atol=1e-12)
+    r = rng.standard_normal((3, s.N))
+    c = s.ddr_project(r, B)
+    pos = np.stack([np.arange(s.N) % 8, (np.arange(s.N) // 8) % 8, np.arange(s.N) // 64]).astype(float)
+    for qb in range(2):
+        for qa in range(2):
+            m = np.flatnonzero(((pos[0] // B) == qa) & ((pos[1] // B) == qb))
+            X = np.column_stack([np.ones(len(m)), pos[:, m].T - pos[:, m].mean(axis=1)])
+            sol = np.linalg.lstsq(X, r[:, m].T, rcond=None)[0]      # (4, 3)
+            assert np.allclose(c[qb, qa], sol.reshape(-1), atol=1e-12)
