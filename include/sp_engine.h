@@ -478,6 +478,22 @@ int sp_gneb_get_forces(sp_gneb *c, double *E, double *l, double *F);
 /* (Re)create the network: channels[0..n_layers] with channels[0] and
  * channels[n_layers] = 3*Nc, each <= 32; He-normal weights from seed. */
 int sp_ddi_init(sp_engine *e, int n_layers, const int *channels, uint64_t seed);
+/* Residual form of the learned field (the other sp_ddi_* calls then act on
+ * it): the film is cut into blocks of block x block cells and every layer
+ * (block^2 x layers = 64 sites); the backbone sums the sites of the blocks
+ * within `reach` (0..2) blocks of a site's block exactly and every other
+ * block as one dipole (its moment at its centroid); the network (12 input
+ * channels: the block's moment and first moments; 12 output channels: the
+ * coefficients c0, c1 of a correction c0 + (r_i - R_b) . c1 per block) runs
+ * on the block grid and is trained on the least-squares fit of (direct sum
+ * - backbone) per block.  The field is scale x (backbone + correction).
+ * Needs an FP32 engine on a one-atom simple-cubic film whose sides are
+ * multiples of 16 blocks, channels[0] = channels[n_layers] = 12
+ * (SP_E_UNSUPPORTED / SP_E_ARG otherwise).  Replaces any previous network. */
+int sp_ddi_init_residual(sp_engine *e, int n_layers, const int *channels, uint64_t seed, int block, int reach);
+/* Residual form: the backbone field alone (the method without the network),
+ * batch samples, layout as sp_ddi_forward_dev. */
+int sp_ddi_backbone_dev(sp_engine *e, int batch, const void *spins_dev, void *field_dev);
 /* Parameter count and host copies (per layer: w[ky][kx][ci][co] then b[co]). */
 int64_t sp_ddi_num_params(sp_engine *e);
 int sp_ddi_set_params(sp_engine *e, const double *params, int64_t n);

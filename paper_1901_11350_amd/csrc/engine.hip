@@ -23,6 +23,7 @@
 #include "kernels_fused2d.hpp"
 #include "kernels_gneb.hpp"
 #include "kernels_conv.hpp"
+#include "kernels_ddr.hpp"
 #include "kernels_fft.hpp"
 #include "kernels_mc.hpp"
 #include "kernels_fused3d.hpp"

@@ -1,0 +1,222 @@
+// kernels_ddr.hpp -- residual form of the learned dipole field (not in the
+// paper; a stand-in for its costliest term, the dipolar sum of Sec. III.A).
+//
+// The film (one-atom simple cubic, NA x NB cells, NC layers, lattice
+// constant a) is cut into blocks of B x B cells and every layer; block
+// (qa, qb) is pixel (qb, qa) of a block grid.  With u_i = sum_j K(r_j - r_i)
+// n_j, K(r) = (1 - 3 r^ r^)/|r|^3 (the dipole gradient in units of C_dd mu^2):
+//   backbone: exact pair sums over the sites of the blocks within `reach`
+//             blocks of i's block (along a and b), and one dipole
+//             M_b = sum_{j in b} n_j at the block centroid R_b for every
+//             other block;
+//   learned:  a 3x3-convolution network on the block grid maps the block
+//             moments (M_b, and the first moments Q_b[g][c] =
+//             sum_j (r_jg - R_bg) n_jc) to per-block coefficients of the
+//             backbone's error, c0_b + (r_i - R_b) . c1_b, trained on the
+//             least-squares fit of (direct sum - backbone) per block.
+// Channel layout of a block pixel: M or c0 at c = 0..2, Q or c1 at
+// 3 + 3 g + c.
+#pragma once
+
+#include "kernels_conv.hpp"
+
+namespace sp {
+
+struct DdrGeo {
+    int NA, NB, NC, B;      // cells and block side
+    int QA, QB;             // block grid (NA / B, NB / B)
+    int reach;              // exact blocks on each side
+    float a;                // lattice constant (Angstrom)
+    float ca, cb, cc;       // centroid of a block relative to its first cell, in cells
+};
+
+// Block moments of sample b: network input (bf16, NHWC, channels padded to
+// kCP) scaled by in_s0 (moment) and in_s1 (first moments), and the moments
+// themselves (FP32, [b][qb][qa][3]) for the backbone's far field.  One
+// thread per block.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ddr_moments(DdrGeo G, const T* __restrict__ n, int64_t stride_n,
+                                                     float in_s0, float in_s1, __bf16* __restrict__ x0, int b0,
+                                                     float* __restrict__ M0) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    const int b = blockIdx.y;
+    if (q >= G.QA * G.QB) return;
+    const int qa = q % G.QA, qb = q / G.QA;
+    const int64_t N = (int64_t)G.NA * G.NB * G.NC;
+    const T* nb = n + (size_t)b * stride_n;
+    float m[3] = {0.f, 0.f, 0.f}, Q[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int lc = 0; lc < G.NC; ++lc)
+        for (int lb = 0; lb < G.B; ++lb)
+            for (int la = 0; la < G.B; ++la) {
+                const int64_t i = (qa * G.B + la) + (int64_t)G.NA * ((qb * G.B + lb) + (int64_t)G.NB * lc);
+                const float v[3] = {(float)nb[i], (float)nb[N + i], (float)nb[2 * N + i]};
+                const float d[3] = {(la - G.ca) * G.a, (lb - G.cb) * G.a, (lc - G.cc) * G.a};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    m[c] += v[c];
+#pragma unroll
+                    for (int g = 0; g < 3; ++g) Q[3 * g + c] += d[g] * v[c];
+                }
+            }
+    if (M0) {
+        float* o = M0 + ((size_t)b * G.QA * G.QB + q) * 3;
+        o[0] = m[0];
+        o[1] = m[1];
+        o[2] = m[2];
+    }
+    if (x0) {
+        __bf16* o = x0 + ((size_t)(b0 + b) * G.QA * G.QB + q) * kCP;
+        for (int c = 0; c < kCP; ++c) {
+            float v = 0.f;
+            if (c < 3) v = in_s0 * m[c];
+            else if (c < 12) v = in_s1 * Q[c - 3];
+            o[c] = (__bf16)v;
+        }
+    }
+}
+
+// u += K(r) v, r from the field point to the source.
+__device__ __forceinline__ void ddr_add(float rx, float ry, float rz, float vx, float vy, float vz, float& ux,
+                                        float& uy, float& uz) {
+    const float d2 = rx * rx + ry * ry + rz * rz;
+    const float inv = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+    const float inv3 = inv * inv * inv;
+    const float s = 3.f * (vx * rx + vy * ry + vz * rz) * inv * inv;
+    ux += (vx - s * rx) * inv3;
+    uy += (vy - s * ry) * inv3;
+    uz += (vz - s * rz) * inv3;
+}
+
+constexpr int kDdrMaxNear = 2048;   // staged near sources of one target block
+
+// Backbone field (units of C_dd mu^2) of every site of one target block
+// (blockIdx.x) of sample blockIdx.y: 256 threads = 4 slices x 64 targets.
+// The sources of the near blocks are staged in LDS (spin and position
+// relative to the target block's first cell); slice w takes every fourth
+// staged source and every fourth far block; the four partial sums are added
+// in a fixed order.  Requires B * B * NC == 64 (one target per lane).
+template <typename T>
+__global__ void __launch_bounds__(256) k_ddr_backbone(DdrGeo G, const T* __restrict__ n, int64_t stride_n,
+                                                      const float* __restrict__ M0, float* __restrict__ u,
+                                                      int64_t stride_u) {
+    __shared__ float4 sv[kDdrMaxNear];
+    __shared__ float4 sp[kDdrMaxNear];
+    __shared__ float red[3][3][64];
+    const int q = blockIdx.x, b = blockIdx.y;
+    const int qa = q % G.QA, qb = q / G.QA;
+    const int64_t N = (int64_t)G.NA * G.NB * G.NC;
+    const T* nb = n + (size_t)b * stride_n;
+    const float* Mb = M0 + (size_t)b * G.QA * G.QB * 3;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int a0 = qa * G.B, b0 = qb * G.B;
+    const int oa0 = max(0, qa - G.reach), oa1 = min(G.QA - 1, qa + G.reach);
+    const int ob0 = max(0, qb - G.reach), ob1 = min(G.QB - 1, qb + G.reach);
+    const int nwa = oa1 - oa0 + 1;
+    const int n_near = nwa * (ob1 - ob0 + 1) * 64;
+    // stage the near sources (block-major, 64 sites per block)
+    for (int s = tid; s < n_near; s += 256) {
+        const int blk = s >> 6, l = s & 63;
+        const int sa = oa0 + blk % nwa, sb = ob0 + blk / nwa;
+        const int la = l % G.B, lb = (l / G.B) % G.B, lc = l / (G.B * G.B);
+        const int ga = sa * G.B + la, gb = sb * G.B + lb;
+        const int64_t j = ga + (int64_t)G.NA * (gb + (int64_t)G.NB * lc);
+        sv[s] = make_float4((float)nb[j], (float)nb[N + j], (float)nb[2 * N + j], 0.f);
+        sp[s] = make_float4((ga - a0) * G.a, (gb - b0) * G.a, lc * G.a, 0.f);
+    }
+    __syncthreads();
+    const int ta = lane % G.B, tb = (lane / G.B) % G.B, tc = lane / (G.B * G.B);
+    const float px = ta * G.a, py = tb * G.a, pz = tc * G.a;
+    float ux = 0.f, uy = 0.f, uz = 0.f;
+    for (int s = w; s < n_near; s += 4) {
+        const float4 v = sv[s], r = sp[s];
+        ddr_add(r.x - px, r.y - py, r.z - pz, v.x, v.y, v.z, ux, uy, uz);   // the site itself: r = 0 adds 0
+    }
+    // far blocks: one dipole at the centroid
+    const float cx = (G.ca - ta) * G.a, cy = (G.cb - tb) * G.a, cz = (G.cc - tc) * G.a;
+    for (int f = w; f < G.QA * G.QB; f += 4) {
+        const int fa = f % G.QA, fb = f / G.QA;
+        if (fa >= oa0 && fa <= oa1 && fb >= ob0 && fb <= ob1) continue;
+        const float* m = Mb + 3 * f;
+        ddr_add((fa - qa) * G.B * G.a + cx, (fb - qb) * G.B * G.a + cy, cz, m[0], m[1], m[2], ux, uy, uz);
+    }
+    if (w > 0) {
+        red[0][w - 1][lane] = ux;
+        red[1][w - 1][lane] = uy;
+        red[2][w - 1][lane] = uz;
+    }
+    __syncthreads();
+    if (w == 0) {
+        ux += red[0][0][lane] + red[0][1][lane] + red[0][2][lane];
+        uy += red[1][0][lane] + red[1][1][lane] + red[1][2][lane];
+        uz += red[2][0][lane] + red[2][1][lane] + red[2][2][lane];
+        const int64_t i = (a0 + ta) + (int64_t)G.NA * ((b0 + tb) + (int64_t)G.NB * tc);
+        float* ub = u + (size_t)b * stride_u;
+        ub[i] = ux;
+        ub[N + i] = uy;
+        ub[2 * N + i] = uz;
+    }
+}
+
+// Training target of sample b: the per-block least-squares coefficients of
+// r = field / scale - backbone (field in meV, scale = C_dd mu^2), divided by
+// out_s0 (c0) and out_s1 (c1).  For a full block with its centroid at the
+// origin the normal equations are diagonal: c0 = mean r, c1_g =
+// sum d_g r / sum d_g^2.  One thread per block.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ddr_target(DdrGeo G, const T* __restrict__ field, int64_t stride_f,
+                                                    float inv_scale, const float* __restrict__ u, int64_t stride_u,
+                                                    float out_s0, float out_s1, float* __restrict__ target, int b0) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    const int b = blockIdx.y;
+    if (q >= G.QA * G.QB) return;
+    const int qa = q % G.QA, qb = q / G.QA;
+    const int64_t N = (int64_t)G.NA * G.NB * G.NC;
+    const T* fb = field + (size_t)b * stride_f;
+    const float* ub = u + (size_t)b * stride_u;
+    float s0[3] = {0.f, 0.f, 0.f}, s1[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float dd[3] = {0.f, 0.f, 0.f};
+    for (int lc = 0; lc < G.NC; ++lc)
+        for (int lb = 0; lb < G.B; ++lb)
+            for (int la = 0; la < G.B; ++la) {
+                const int64_t i = (qa * G.B + la) + (int64_t)G.NA * ((qb * G.B + lb) + (int64_t)G.NB * lc);
+                const float d[3] = {(la - G.ca) * G.a, (lb - G.cb) * G.a, (lc - G.cc) * G.a};
+#pragma unroll
+                for (int g = 0; g < 3; ++g) dd[g] += d[g] * d[g];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float r = inv_scale * (float)fb[(size_t)c * N + i] - ub[(size_t)c * N + i];
+                    s0[c] += r;
+#pragma unroll
+                    for (int g = 0; g < 3; ++g) s1[3 * g + c] += d[g] * r;
+                }
+            }
+    float* o = target + ((size_t)(b0 + b) * G.QA * G.QB + q) * 12;
+    const float cnt = (float)(G.B * G.B * G.NC);
+    for (int c = 0; c < 3; ++c) o[c] = s0[c] / cnt / out_s0;
+    for (int g = 0; g < 3; ++g)
+        for (int c = 0; c < 3; ++c) o[3 + 3 * g + c] = (dd[g] > 0.f ? s1[3 * g + c] / dd[g] : 0.f) / out_s1;
+}
+
+// The field of the residual form: g_i = scale (u_i + c0_b + (r_i - R_b) . c1_b)
+// with c0 = out_s0 z[0..2], c1 = out_s1 z[3..11] of the network output z
+// (FP32, NHWC with kCP channels).  One thread per site.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ddr_apply(DdrGeo G, const float* __restrict__ u, const float* __restrict__ z,
+                                                   float out_s0, float out_s1, float scale, T* __restrict__ g) {
+    const int64_t N = (int64_t)G.NA * G.NB * G.NC;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const int ga = (int)(i % G.NA), gb = (int)((i / G.NA) % G.NB), gc = (int)(i / ((int64_t)G.NA * G.NB));
+    const int qa = ga / G.B, qb = gb / G.B;
+    const float* zb = z + ((size_t)qb * G.QA + qa) * kCP;
+    const float d[3] = {(ga - qa * G.B - G.ca) * G.a, (gb - qb * G.B - G.cb) * G.a, (gc - G.cc) * G.a};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float v = u[(size_t)c * N + i] + out_s0 * zb[c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v += out_s1 * d[k] * zb[3 + 3 * k + c];
+        g[(size_t)c * N + i] = (T)(scale * v);
+    }
+}
+
+}  // namespace sp

@@ -40,7 +40,8 @@ EXPORTS = [
     "sp_gneb_create", "sp_gneb_destroy", "sp_gneb_last_error", "sp_gneb_set_image_type", "sp_gneb_iterate",
     "sp_gneb_iterate_tol",
     "sp_gneb_get_chain", "sp_gneb_get_forces",
-    "sp_ddi_init", "sp_ddi_num_params", "sp_ddi_set_params", "sp_ddi_get_params", "sp_ddi_label_dev",
+    "sp_ddi_init", "sp_ddi_init_residual", "sp_ddi_backbone_dev", "sp_ddi_num_params", "sp_ddi_set_params",
+    "sp_ddi_get_params", "sp_ddi_label_dev",
     "sp_ddi_forward_dev", "sp_ddi_loss_grad_dev", "sp_ddi_train_dev", "sp_ddi_configure", "sp_ddi_stats",
 ]
 
@@ -176,6 +177,8 @@ def lib():
         "sp_gneb_get_chain": (ci, [vp, dp]),
         "sp_gneb_get_forces": (ci, [vp, dp, dp, dp]),
         "sp_ddi_init": (ci, [vp, ci, ctypes.POINTER(ci), u64]),
+        "sp_ddi_init_residual": (ci, [vp, ci, ctypes.POINTER(ci), u64, ci, ci]),
+        "sp_ddi_backbone_dev": (ci, [vp, ci, vp, vp]),
         "sp_ddi_num_params": (i64, [vp]),
         "sp_ddi_set_params": (ci, [vp, dp, i64]),
         "sp_ddi_get_params": (ci, [vp, dp, i64]),
@@ -431,6 +434,14 @@ class Engine:
     def ddi_init(self, channels, seed: int = 0):
         ch = (ctypes.c_int * len(channels))(*channels)
         self._check(lib().sp_ddi_init(self._h, len(channels) - 1, ch, seed))
+
+    def ddi_init_residual(self, channels, seed: int = 0, block: int = 4, reach: int = 2):
+        ch = (ctypes.c_int * len(channels))(*channels)
+        self._check(lib().sp_ddi_init_residual(self._h, len(channels) - 1, ch, seed, block, reach))
+
+    def ddi_backbone_dev(self, batch: int, spins_t, field_t):
+        self._check(lib().sp_ddi_backbone_dev(self._h, batch, ctypes.c_void_p(spins_t.data_ptr()),
+                                              ctypes.c_void_p(field_t.data_ptr())))
 
     def ddi_num_params(self) -> int:
         return int(lib().sp_ddi_num_params(self._h))
