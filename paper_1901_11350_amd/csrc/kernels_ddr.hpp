@@ -87,20 +87,25 @@ __device__ __forceinline__ void ddr_add(float rx, float ry, float rz, float vx, 
     uz += (vz - s * rz) * inv3;
 }
 
-constexpr int kDdrMaxNear = 2048;   // staged near sources of one target block
+constexpr int kDdrMaxNear = 1600;     // staged near sources of one target block (25 blocks of 64)
+constexpr int kDdrChunk = 1024;       // far-block moments staged per pass
 
 // Backbone field (units of C_dd mu^2) of every site of one target block
 // (blockIdx.x) of sample blockIdx.y: 256 threads = 4 slices x 64 targets.
-// The sources of the near blocks are staged in LDS (spin and position
+// The sources of the near blocks are staged in LDS (spin, and position
 // relative to the target block's first cell); slice w takes every fourth
-// staged source and every fourth far block; the four partial sums are added
-// in a fixed order.  Requires B * B * NC == 64 (one target per lane).
+// staged source.  The far blocks' moments are staged in LDS a chunk of
+// block rows at a time; slice w takes every fourth block row, each row as
+// the column ranges left and right of the near window (no test per
+// block).  The four partial sums are added in a fixed order.  Requires
+// B * B * NC == 64 (one target per lane) and reach <= 2.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ddr_backbone(DdrGeo G, const T* __restrict__ n, int64_t stride_n,
                                                       const float* __restrict__ M0, float* __restrict__ u,
                                                       int64_t stride_u) {
     __shared__ float4 sv[kDdrMaxNear];
     __shared__ float4 sp[kDdrMaxNear];
+    __shared__ float4 sm[kDdrChunk];
     __shared__ float red[3][3][64];
     const int q = blockIdx.x, b = blockIdx.y;
     const int qa = q % G.QA, qb = q / G.QA;
@@ -127,17 +132,45 @@ __global__ void __launch_bounds__(256) k_ddr_backbone(DdrGeo G, const T* __restr
     const int ta = lane % G.B, tb = (lane / G.B) % G.B, tc = lane / (G.B * G.B);
     const float px = ta * G.a, py = tb * G.a, pz = tc * G.a;
     float ux = 0.f, uy = 0.f, uz = 0.f;
-    for (int s = w; s < n_near; s += 4) {
-        const float4 v = sv[s], r = sp[s];
-        ddr_add(r.x - px, r.y - py, r.z - pz, v.x, v.y, v.z, ux, uy, uz);   // the site itself: r = 0 adds 0
+    int s = w;
+    for (; s + 12 < n_near; s += 16) {
+        const float4 v0 = sv[s], r0 = sp[s], v1 = sv[s + 4], r1 = sp[s + 4];
+        const float4 v2 = sv[s + 8], r2 = sp[s + 8], v3 = sv[s + 12], r3 = sp[s + 12];
+        ddr_add(r0.x - px, r0.y - py, r0.z - pz, v0.x, v0.y, v0.z, ux, uy, uz);   // r = 0 (the site) adds 0
+        ddr_add(r1.x - px, r1.y - py, r1.z - pz, v1.x, v1.y, v1.z, ux, uy, uz);
+        ddr_add(r2.x - px, r2.y - py, r2.z - pz, v2.x, v2.y, v2.z, ux, uy, uz);
+        ddr_add(r3.x - px, r3.y - py, r3.z - pz, v3.x, v3.y, v3.z, ux, uy, uz);
     }
-    // far blocks: one dipole at the centroid
-    const float cx = (G.ca - ta) * G.a, cy = (G.cb - tb) * G.a, cz = (G.cc - tc) * G.a;
-    for (int f = w; f < G.QA * G.QB; f += 4) {
-        const int fa = f % G.QA, fb = f / G.QA;
-        if (fa >= oa0 && fa <= oa1 && fb >= ob0 && fb <= ob1) continue;
-        const float* m = Mb + 3 * f;
-        ddr_add((fa - qa) * G.B * G.a + cx, (fb - qb) * G.B * G.a + cy, cz, m[0], m[1], m[2], ux, uy, uz);
+    for (; s < n_near; s += 4) {
+        const float4 v = sv[s], r = sp[s];
+        ddr_add(r.x - px, r.y - py, r.z - pz, v.x, v.y, v.z, ux, uy, uz);
+    }
+    // far blocks: one dipole at the centroid, staged a chunk of rows at a time
+    const float step = G.B * G.a;
+    const float cx = (G.ca - ta) * G.a - qa * step, cy = (G.cb - tb) * G.a - qb * step, cz = (G.cc - tc) * G.a;
+    const int rows_per_chunk = max(1, kDdrChunk / G.QA);
+    for (int r0 = 0; r0 < G.QB; r0 += rows_per_chunk) {
+        const int r1 = min(G.QB, r0 + rows_per_chunk);
+        __syncthreads();   // the previous chunk is no longer read
+        for (int k = tid; k < (r1 - r0) * G.QA; k += 256) {
+            const float* m = Mb + 3 * ((size_t)r0 * G.QA + k);
+            sm[k] = make_float4(m[0], m[1], m[2], 0.f);
+        }
+        __syncthreads();
+        for (int fb = r0 + w; fb < r1; fb += 4) {
+            const float ry = fb * step + cy;
+            const float4* row = sm + (fb - r0) * G.QA;
+            const bool in_rows = fb >= ob0 && fb <= ob1;
+            const int gap0 = in_rows ? oa0 : G.QA, gap1 = in_rows ? oa1 + 1 : G.QA;
+            for (int fa = 0; fa < gap0; ++fa) {
+                const float4 m = row[fa];
+                ddr_add(fa * step + cx, ry, cz, m.x, m.y, m.z, ux, uy, uz);
+            }
+            for (int fa = gap1; fa < G.QA; ++fa) {
+                const float4 m = row[fa];
+                ddr_add(fa * step + cx, ry, cz, m.x, m.y, m.z, ux, uy, uz);
+            }
+        }
     }
     if (w > 0) {
         red[0][w - 1][lane] = ux;

@@ -178,3 +178,101 @@ def test_trained_network_gains_over_the_backbone_against_the_fp64_oracle(ora):
           flush=True)
     assert err_w.mean() < (2.0 / 3.0) * err_o.mean()
     e.close()
+
+
+def test_full_size_film_error_against_the_fp64_oracle(ora):
+    """The 128 x 128 x 4 film: train on 600 textures (a third relaxed
+    skyrmion/bubble textures), then the field error against the FP64 oracle
+    at 256 sampled sites of each of 24 held-out textures, with the network
+    and with the backbone alone."""
+    import torch
+
+    import bench
+    import paper_1901_11350_amd as pk
+
+    announce("residual full-size film 128x128x4")
+    w = si.WORKLOADS["film128x4_dipolar"]
+    geo = w.geometry
+    e = _engine(geo, seed=4)
+    f = pk.Engine(0, "f32")
+    f.set_geometry(geo)
+    f.set_hamiltonian(dataclasses.replace(w.hamiltonian, ddi=3))
+    ntrain, ntest = 600, 24
+    tex = torch.tensor(bench.film_textures(geo, ntrain + ntest, 2024), device="cuda").contiguous()
+    bench.relax_textures(f, tex)
+    lab = torch.zeros_like(tex)
+    torch.cuda.synchronize()
+    e.ddi_label_dev(ntrain + ntest, tex, lab)
+    e.ddi_train_dev(ntrain, tex[:ntrain].contiguous(), lab[:ntrain].contiguous(), epochs=30, batch=8, lr=2e-3,
+                    seed=0)
+    test = tex[ntrain:].contiguous()
+    with_net, without = torch.zeros_like(test), torch.zeros_like(test)
+    e.ddi_forward_dev(ntest, test, with_net)
+    e.ddi_backbone_dev(ntest, test, without)
+    e.synchronize()
+    wn, wo = with_net.cpu().numpy().astype(np.float64), without.cpu().numpy().astype(np.float64)
+    spins = test.cpu().numpy().astype(np.float64)
+    s = _oracle_system(ora, geo)
+    rng = np.random.default_rng(8)
+    err_w, err_o = [], []
+    for b in range(ntest):
+        sites = np.sort(rng.choice(geo.n_sites, 256, replace=False))
+        exact = s.dipole_gradient_sites(spins[b], sites)
+        nrm = np.linalg.norm(exact)
+        err_w.append(np.linalg.norm(wn[b][:, sites] - exact) / nrm)
+        err_o.append(np.linalg.norm(wo[b][:, sites] - exact) / nrm)
+    err_w, err_o = np.array(err_w), np.array(err_o)
+    print(f"[residual] 128x128x4 held-out error vs FP64 oracle: with network mean {err_w.mean():.2e} "
+          f"max {err_w.max():.2e}; backbone alone mean {err_o.mean():.2e} max {err_o.max():.2e}; "
+          f"below 1e-3: {int((err_w < 1e-3).sum())}/{ntest} with, {int((err_o < 1e-3).sum())}/{ntest} without",
+          flush=True)
+    assert err_w.mean() < (2.0 / 3.0) * err_o.mean()
+    e.close()
+    f.close()
+
+
+def test_llg_with_the_learned_field_follows_the_direct_sum():
+    """A trained residual network behind the residual check (tol 1e-3, 256
+    sites) in 20 LLG steps of the 64 x 64 x 4 film: some evaluations pass the
+    check without the direct sum, and the spins stay as close to the
+    direct-sum trajectory as a field error of twice the tolerance allows:
+    per step the rotation differs by at most gamma (1 + alpha) / (1 +
+    alpha^2) |dB| dt with |dB| <= 2 tol max|B_dd| (B_dd in Tesla from the
+    direct sum at the start), summed over the steps."""
+    import torch
+
+    import paper_1901_11350_amd as pk
+
+    announce("residual LLG with check")
+    geo = _film()
+    e = _engine(geo, seed=6)
+    tex = np.stack([_f32(_texture(geo, k)) for k in range(240)])
+    nt = torch.tensor(tex, dtype=torch.float32, device="cuda").contiguous()
+    lab = torch.zeros_like(nt)
+    torch.cuda.synchronize()
+    e.ddi_label_dev(240, nt, lab)
+    e.ddi_train_dev(240, nt, lab, epochs=40, batch=8, lr=2e-3, seed=0)
+    n0 = _texture(geo, 1000 + 2)
+    e.set_hamiltonian(dataclasses.replace(HAM4, ddi=2))
+    e.ddi_configure(1e-3, 256)
+    e.set_spins(n0)
+    e.run(0.3, 0.001, 20)
+    st = e.ddi_stats()
+    got = e.get_spins()
+    d = pk.Engine(0, "f32")
+    d.set_geometry(geo)
+    d.set_hamiltonian(dataclasses.replace(HAM4, ddi=True))
+    d.set_spins(n0)
+    d.run(0.3, 0.001, 20)
+    ref = d.get_spins()
+    d.set_spins(n0)
+    bdd = np.linalg.norm(d.dipole_gradient(), axis=0).max() / (HAM4.mu[0] * 0.057883818060)
+    alpha, dt, gamma = 0.3, 0.001, 0.176085963023
+    bound = 20 * gamma * (1 + alpha) / (1 + alpha ** 2) * (2 * 1e-3 * bdd) * dt
+    print(f"[residual] LLG: {st['evaluations']} evaluations, {st['fallbacks']} fallbacks, last sampled error "
+          f"{st['last_error']:.2e}, max {st['max_error']:.2e}; max spin difference {np.abs(got - ref).max():.2e} "
+          f"(bound {bound:.2e}, max |B_dd| {bdd:.2f} T)", flush=True)
+    assert st["evaluations"] == 40 and st["fallbacks"] < st["evaluations"]
+    assert np.abs(got - ref).max() < bound
+    e.close()
+    d.close()
