@@ -3,7 +3,10 @@
 TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and
 by the benchmark's CPU-baseline leg.  The HIP engine never imports it.
 
-The wrapper marshals NumPy arrays; all arithmetic is in ``oracle.c``.
+The wrapper marshals NumPy arrays; the arithmetic is in ``oracle.c``,
+except the composition of the surrogate network in ``SurrogateNet`` (the
+layer sequence, the relative squared-error loss and the chain rule between
+layers), which is plain NumPy over the C layers.
 """
 
 from __future__ import annotations

@@ -1,7 +1,8 @@
 """GPU tests of the learned dipole-field surrogate: matrix-core convolution
-forward and backward against the FP64 oracle (same bf16 contract), training
-lowers the loss, and the residual check's fallback reproduces the direct
-sum exactly."""
+forward and backward against the FP64 oracle (same bf16 contract), the
+forward against the oracle's exact network within a derived bf16 bound,
+training lowers the loss, and the residual check's fallback reproduces the
+direct sum exactly."""
 
 import dataclasses
 
@@ -113,6 +114,121 @@ def test_surrogate_forward_matches_oracle(ora, channels):
     # normwise bound is one bf16 ulp.
     tol = 1e-5 if len(channels) == 2 else 2.0 ** -8
     assert rel_err(got, ref) <= tol
+
+
+U_BF16 = 2.0 ** -8          # unit roundoff of bfloat16 (8 significant bits)
+U_F32 = 2.0 ** -24
+SILU_LIP = 1.0998           # max |d silu / dz|
+SILU_REL = 2.0 ** -18       # relative error allowed to the FP32 silu (exp, divide)
+
+
+def _bf16_network_bound(ora, ws, bs, x):
+    """Elementwise a-priori bound on |GPU network - exact network| for an
+    input x (FP64), derived layer by layer from the kernel's arithmetic:
+    the input and every weight are rounded to FP32 and then bf16 (relative
+    error u' = u + 2^-23 each), products of bf16 values are exact in FP32 and
+    summed over K = 9 x 32 terms in FP32 (gamma_K), the bias is FP32, a
+    hidden activation is the FP32 silu (relative error 2^-18) rounded to bf16
+    (u).  With e the bound on the layer's input error and a its exact input,
+    the pre-activation error is
+        u' conv(|a| + e, |w|) + conv(e, |w|) + gamma_K (1 + u') conv(|a| + e, |w|)
+        + 2^-24 (|b| + |z| + e_z)
+    and the next input error L e_z + (u + 2^-18)(|silu(z)| + L e_z), L the
+    Lipschitz constant of silu; the last layer's output is FP32 (2^-24).
+    conv(., |w|) is the oracle's exact convolution of absolute values."""
+    u1 = U_BF16 + 2 * U_F32
+    gam = (9 * 32 + 2) * U_F32 / (1 - (9 * 32 + 2) * U_F32)
+    a = np.asarray(x, dtype=np.float64)
+    e = u1 * np.abs(a)
+    with ora.conv_exact():
+        for k, (w, b) in enumerate(zip(ws, bs)):
+            zero = np.zeros(w.shape[3])
+            aw = ora.conv3x3_fwd(np.abs(a) + e, np.abs(w), zero)
+            ew = ora.conv3x3_fwd(e, np.abs(w), zero)
+            z = ora.conv3x3_fwd(a, w, b)
+            ez = u1 * aw + ew + gam * (1 + u1) * aw
+            ez = ez + U_F32 * (np.abs(b) + np.abs(z) + ez)
+            if k + 1 == len(ws):
+                return z, ez + U_F32 * (np.abs(z) + ez)
+            y = ora.silu(z)[0]
+            e = SILU_LIP * ez + (U_BF16 + SILU_REL) * (np.abs(y) + SILU_LIP * ez)
+            a = y
+
+
+def _rounding_model_net(ora, ws, bs, x, rng):
+    """The exact network with every operand the kernel rounds (input, each
+    weight, each stored hidden activation) multiplied by an independent
+    1 + eps, eps uniform in [-u, u]: the random-rounding model of bf16."""
+    def pert(a):
+        return a * (1 + rng.uniform(-U_BF16, U_BF16, a.shape)) if rng is not None else a
+    a = pert(x)
+    with ora.conv_exact():
+        for k, (w, b) in enumerate(zip(ws, bs)):
+            z = ora.conv3x3_fwd(a, pert(w), b)
+            if k + 1 == len(ws):
+                return z
+            a = pert(ora.silu(z)[0])
+
+
+def _forward_against_exact(ora, channels, seed):
+    import torch
+
+    geo = _film()
+    e = _engine(geo)
+    e.ddi_init(channels, seed=7)
+    n_p = sum(9 * a * b + b for a, b in zip(channels[:-1], channels[1:]))
+    p = np.random.default_rng(seed).standard_normal(n_p) * 0.15
+    e.ddi_set_params(p)
+    n = np.stack([si.uniform_sphere(geo.n_sites, seed + 3),
+                  si.skyrmion_ansatz(geo, radius=7.0, noise_rad=0.2, seed=seed + 4)])
+    nt = torch.tensor(n, dtype=torch.float32, device="cuda").contiguous()
+    ft = torch.zeros_like(nt)
+    torch.cuda.synchronize()
+    e.ddi_forward_dev(2, nt, ft)
+    e.synchronize()
+    e.close()
+    got = ft.cpu().numpy().astype(np.float64)
+    ws, bs = _params_to_layers(p, channels)
+    x = _to_nhwc(geo, n.astype(np.float32).astype(np.float64))
+    return geo, got, ws, bs, x
+
+
+def test_one_layer_forward_within_the_rigorous_bf16_bound(ora):
+    """One 3x3 layer with parameters and spins that are not bf16-exact,
+    against the oracle's exact (unrounded FP64) layer: every output within
+    the elementwise bound derived above from the kernel's arithmetic."""
+    announce("surrogate one layer vs exact, rigorous bound")
+    geo, got, ws, bs, x = _forward_against_exact(ora, [12, 12], 55)
+    z, ez = _bf16_network_bound(ora, ws, bs, x)
+    scale = C_DD * HAM4.mu[0] ** 2
+    ref = _field_from_nhwc(geo, z) * scale
+    bound = _field_from_nhwc(geo, ez) * scale * (1 + 4 * U_F32) + 1e-30
+    ratio = (np.abs(got - ref) / bound).max()
+    print(f"[surrogate] one layer: max |dev|/bound {ratio:.3f}, normwise error {np.linalg.norm(got - ref) / np.linalg.norm(ref):.3e}, "
+          f"normwise bound {np.linalg.norm(bound) / np.linalg.norm(ref):.3e}", flush=True)
+    assert ratio <= 1.0
+    assert np.linalg.norm(bound) <= 0.1 * np.linalg.norm(ref)
+
+
+def test_four_layer_forward_within_the_bf16_rounding_model(ora):
+    """The 4-layer 32-channel network (parameters and spins not bf16-exact)
+    against the oracle's exact FP64 network.  Worst-case bounds compound
+    through four layers of 288-term sums to far above the field itself, so
+    the bar is the random-rounding model: the normwise error of the engine
+    must not exceed 1.5 times the largest of four oracle runs of the exact
+    network with every rounded operand perturbed by an independent relative
+    error uniform in [-u, u] (u = 2^-8)."""
+    channels = [12, 32, 32, 32, 12]
+    announce(f"surrogate forward vs exact network {channels}")
+    geo, got, ws, bs, x = _forward_against_exact(ora, channels, 77)
+    z = _rounding_model_net(ora, ws, bs, x, None)
+    model = max(np.linalg.norm(_rounding_model_net(ora, ws, bs, x, np.random.default_rng(1000 + k)) - z)
+                / np.linalg.norm(z) for k in range(4))
+    ref = _field_from_nhwc(geo, z) * C_DD * HAM4.mu[0] ** 2
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"[surrogate] four layers: normwise error {err:.3e}, rounding model {model:.3e}", flush=True)
+    assert err <= 1.5 * model
+    assert model < 0.05
 
 
 def test_surrogate_gradients_match_oracle(ora):
