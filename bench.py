@@ -309,6 +309,48 @@ def bench_stencil(args) -> dict:
     return out
 
 
+def basis_workloads():
+    """Lattices with a basis at about 262,144 spins (FP32, T = 10 K): the
+    honeycomb with three exchange shells and interfacial DMI, the kagome
+    lattice with two, and the two-atom (bcc) cell in 3D."""
+    import spin_inputs as si
+
+    hc = si.Hamiltonian(mu=(2.0, 2.5), B=(0.1, -0.2, 0.5), K=(0.1, 0.05),
+                        K_axis=((0, 0, 1), (0.6, 0.0, 0.8)), J=(1.0, 0.2, -0.1), D=(0.15,))
+    kg = si.Hamiltonian(mu=(2.0, 2.0, 3.0), B=(0.0, 0.0, 0.4), K=(0.1, 0.1, 0.2),
+                        K_axis=((0, 0, 1),) * 3, J=(1.0, -0.2), D=(0.1,))
+    bcc = si.Hamiltonian(mu=(2.0, 3.0), B=(0.2, 0.4, -0.3), K=(0.1, -0.2),
+                         K_axis=((0, 0, 1), (0.6, 0.8, 0.0)), J=(1.0, 0.5), D=(0.1, 0.05), dmi_kind=si.DMI_BULK)
+    bcc_geo = si.Geometry(((1.0, 0, 0), (0, 1.0, 0), (0, 0, 1.0)), ((0, 0, 0), (0.5, 0.5, 0.5)),
+                          (64, 64, 32), (1, 1, 1))
+    dyn = si.Dynamics(alpha=0.1, dt=0.0005, T=10.0, seed=3)
+    return [si.Workload("honeycomb512x256", si.honeycomb(512, 256), hc, dyn, "f32", "uniform", 5,
+                        "honeycomb 512x256 (2 atoms), J1-J3, interfacial D"),
+            si.Workload("kagome512x171", si.kagome(512, 171), kg, dyn, "f32", "uniform", 6,
+                        "kagome 512x171 (3 atoms), J1-J2, interfacial D"),
+            si.Workload("bcc64x64x32", bcc_geo, bcc, dyn, "f32", "uniform", 7,
+                        "two-atom cubic cell 64x64x32, J1-J2, bulk D")]
+
+
+def bench_basis(args) -> dict:
+    """Lattices with a basis: the fused tile step (one launch, 24 B per
+    FP32 spin-update) against the two-pass kernels (60 B) per step."""
+    out = {}
+    for w in basis_workloads():
+        res = {}
+        for path in ("fusedtile", "twopass"):
+            r = time_workload(w, args.basis_steps, 20, 0, step_path=path)
+            res[path] = r
+        ft = res["fusedtile"]
+        out[w.name] = {"n_sites": ft["N"], "steps": args.basis_steps,
+                       "us_per_step_fusedtile": ft["ms"] * 1e3 / ft["steps"],
+                       "us_per_step_twopass": res["twopass"]["ms"] * 1e3 / res["twopass"]["steps"],
+                       "spin_updates_per_s": ft["N"] * ft["steps"] / (ft["ms"] * 1e-3),
+                       "hbm_gbps_algorithmic": BYTES_PER_UPDATE["f32"] * ft["N"] / ft["t_launch"] / 1e9,
+                       "speedup": res["twopass"]["ms"] / ft["ms"], "description": w.description}
+    return out
+
+
 def film_textures(geo, count: int, seed: int):
     """Seeded training/test textures of the dipolar film: a third uniform
     random, a third 1-3 tanh domain walls (Bloch or Neel, random position,
@@ -542,7 +584,7 @@ def bench_tc(args) -> dict:
                     "crossing_K": binder_crossing(llg, 8, 12, temps), "s": t_llg}}
 
 
-KERNEL_OF_PATH = {"fused2d": "k_depondt_fused2d", "twopass": "k_predict+k_correct", "shape3d": "k_fused3d_shape",
+KERNEL_OF_PATH = {"fused2d": "k_depondt_fused2d", "fusedtile": "k_fused_tile", "twopass": "k_predict+k_correct", "shape3d": "k_fused3d_shape",
                   "persist2d": "k_persist2d", "shape2d": "k_fused2d_shape"}
 
 
@@ -643,6 +685,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=256)
     ap.add_argument("--batch-chunk", type=int, default=32)
     ap.add_argument("--gneb-iters", type=int, default=200)
+    ap.add_argument("--basis", action="store_true", help="(default with the extras) lattices with a basis only")
+    ap.add_argument("--basis-steps", type=int, default=500)
     ap.add_argument("--stencil", action="store_true", help="(default with the extras; kept for old command lines)")
     ap.add_argument("--stencil-launches", type=int, default=200)
     ap.add_argument("--tc", action="store_true",
@@ -716,6 +760,8 @@ def main():
         line["batch"] = bench_batch(args)
     if extras or args.stencil:
         line["stencil"] = bench_stencil(args)
+    if extras or args.basis:
+        line["basis"] = bench_basis(args)
     if extras or args.surrogate:
         line["dipole"] = bench_surrogate(args)
     if args.tc:

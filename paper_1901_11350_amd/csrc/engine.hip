@@ -21,6 +21,7 @@
 #include "kernels_reduce.hpp"
 #include "kernels_dipole.hpp"
 #include "kernels_fused2d.hpp"
+#include "kernels_tile.hpp"
 #include "kernels_gneb.hpp"
 #include "kernels_conv.hpp"
 #include "kernels_ddr.hpp"
@@ -108,6 +109,7 @@ struct sp_engine {
     uint64_t step = 0;
     const char* path = "none";
     bool fused_ok = false;
+    bool tile_ok = false;   // the fused tile path takes this lattice (basis, or 3D without a stencil)
     std::vector<HostBond> all_bonds;  // every bond of the requested shells (zero ones included)
     int n_shells = 0;
     int shape = -1;                   // sp::Shape2D matched by the bond table, or -1
@@ -603,6 +605,104 @@ void launch_fused2d(sp_engine* e, const sp_llg_params* p, uint64_t step, const v
                        static_cast<T*>(nout));
 }
 
+// ------------------------------------------------ fused tile path (basis)
+// Lattices with a basis, or 3D bond tables without a compile-time stencil.
+// One thread per owned site, so a tile holds NB x TX x TY x TZ <= 1024
+// sites: 2D FP32 32 x 16 (two atoms) or 16 x 16 (three, four), FP64 16 x 16
+// or 16 x 8; 3D FP32 16 x 8 x 4 (one, two atoms) or 8 x 8 x 4 (three), FP64
+// 8 x 8 x 4 (one, two).  Reach up to 2 in 2D, 1 in 3D.  Every instance
+// stays within the 160 KB of LDS a workgroup may hold.
+bool tile_fits(const sp_engine* e, const HostHam& H, size_t n_bonds) {
+    const HostGeo& g = e->geo;
+    if (H.ddi || H.n_gauss > 0 || g.nb > 4 || n_bonds > (size_t)sp::kMaxStencilB) return false;
+    int rc = 0;
+    for (const HostBond& b : e->bonds) rc = std::max(rc, std::abs(b.d[2]));
+    if (g.n[2] == 1) {
+        if (g.nb == 1 || !e->planar || e->R > 2) return false;
+    } else {
+        if (e->R > 1 || rc > 1 || g.nb > (e->precision == SP_F64 ? 2 : 3)) return false;
+        if (g.per[2] && g.n[2] <= 2) return false;
+    }
+    if (g.per[0] && g.n[0] <= 2 * std::max(e->R, 1)) return false;
+    if (g.per[1] && g.n[1] <= 2 * std::max(e->R, 1)) return false;
+    return true;
+}
+
+template <typename T>
+sp::StencilB<T> make_stencilb(const sp_engine* e) {
+    sp::StencilB<T> S{};
+    S.nb = e->geo.nb;
+    for (int b = 0; b <= S.nb; ++b) S.bstart[b] = e->bstart[b];
+    for (int q = 0; q < (int)e->bonds.size(); ++q) {
+        const HostBond& b = e->bonds[q];
+        S.bj[q] = b.bj;
+        S.da[q] = b.d[0];
+        S.db[q] = b.d[1];
+        S.dc[q] = b.d[2];
+        S.J[q] = (T)b.J;
+        for (int k = 0; k < 3; ++k) S.D[q][k] = (T)b.D[k];
+    }
+    return S;
+}
+
+template <typename T>
+sp::SiteB<T> make_siteb(const sp_engine* e, const sp_llg_params* p) {
+    const sp::Phys<T> P = make_phys<T>(e, p);
+    sp::SiteB<T> Q{};
+    for (int k = 0; k < 3; ++k) {
+        Q.n[k] = e->geo.n[k];
+        Q.per[k] = e->geo.per[k];
+    }
+    for (int b = 0; b < e->geo.nb; ++b) {
+        Q.inv_mumuB[b] = (T)(1.0 / (e->ham.mu[b] * kMuB));
+        for (int k = 0; k < 3; ++k) {
+            Q.gZ[b][k] = P.gZ[b][k];
+            Q.Kax[b][k] = P.Kax[b][k];
+        }
+        Q.K2[b] = P.K2[b];
+        Q.sigma[b] = P.sigma[b];
+    }
+    return Q;
+}
+
+template <typename T, int TX, int TY, int TZ, int R, int RC, int NB>
+void launch_tile_k(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    const dim3 grid((unsigned)((e->geo.n[0] + TX - 1) / TX), (unsigned)((e->geo.n[1] + TY - 1) / TY),
+                    (unsigned)((e->geo.n[2] + TZ - 1) / TZ));
+    hipLaunchKernelGGL((sp::k_fused_tile<T, TX, TY, TZ, R, RC, NB>), grid, dim3(NB * TX * TY * TZ), 0, e->stream,
+                       make_stencilb<T>(e), make_siteb<T>(e, p), make_step_llg<T>(e, p, step), e->d_flag,
+                       static_cast<const T*>(nin), static_cast<T*>(nout));
+}
+
+template <typename T, int R>
+void go_tile2d(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    constexpr bool f32 = sizeof(T) == 4;
+    switch (e->geo.nb) {
+        case 2: launch_tile_k<T, f32 ? 32 : 16, 16, 1, R, 0, 2>(e, p, step, nin, nout); break;
+        case 3: launch_tile_k<T, 16, f32 ? 16 : 8, 1, R, 0, 3>(e, p, step, nin, nout); break;
+        default: launch_tile_k<T, 16, f32 ? 16 : 8, 1, R, 0, 4>(e, p, step, nin, nout); break;
+    }
+}
+
+template <typename T>
+void launch_tile(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    if (e->geo.n[2] == 1) {
+        if (e->R <= 1) go_tile2d<T, 1>(e, p, step, nin, nout);
+        else go_tile2d<T, 2>(e, p, step, nin, nout);
+        return;
+    }
+    if constexpr (sizeof(T) == 4) {
+        switch (e->geo.nb) {
+            case 1: launch_tile_k<T, 16, 8, 4, 1, 1, 1>(e, p, step, nin, nout); break;
+            case 2: launch_tile_k<T, 16, 8, 4, 1, 1, 2>(e, p, step, nin, nout); break;
+            default: launch_tile_k<T, 8, 8, 4, 1, 1, 3>(e, p, step, nin, nout); break;
+        }
+    } else {
+        if (e->geo.nb == 1) launch_tile_k<T, 8, 8, 4, 1, 1, 1>(e, p, step, nin, nout);
+        else launch_tile_k<T, 8, 8, 4, 1, 1, 2>(e, p, step, nin, nout);
+    }
+}
+
 // ------------------------------------------- compile-time-shape fused path
 struct TileCfg {
     const char* name;
@@ -960,6 +1060,11 @@ int launch_step(sp_engine* e, const sp_llg_params* p, uint64_t step, const void*
     }
     if (std::strcmp(e->path, "shape3d") == 0) {
         launch_shape3<T>(e, p, step, nin, nout);
+        HIPCHK(e, hipGetLastError());
+        return SP_OK;
+    }
+    if (std::strcmp(e->path, "fusedtile") == 0 && p->solver == SP_SOLVER_DEPONDT) {
+        launch_tile<T>(e, p, step, nin, nout);
         HIPCHK(e, hipGetLastError());
         return SP_OK;
     }
@@ -1748,7 +1853,8 @@ int install_ham(sp_engine* e, const HostHam& H, const std::vector<HostBond>& bon
     if (g.per[0] && g.n[0] <= 2 * e->R) fused = false;
     if (g.per[1] && g.n[1] <= 2 * e->R) fused = false;
     e->fused_ok = fused;
-    e->path = fused ? "fused2d" : "twopass";
+    e->tile_ok = !fused && tile_fits(e, H, bonds.size());
+    e->path = fused ? "fused2d" : e->tile_ok ? "fusedtile" : "twopass";
     // compile-time stencil: the bond table must match a known shape, DMI may
     // sit on the first shell only, and every DMI vector must be in-plane
     e->shape = -1;
@@ -2088,6 +2194,12 @@ int sp_set_step_path(sp_engine* e, const char* name) {
     } else if (s == "fused2d") {
         if (!e->fused_ok) return fail(e, SP_E_UNSUPPORTED, "fused2d needs a one-atom 2D lattice without dipole");
         e->path = "fused2d";
+    } else if (s == "fusedtile") {
+        if (!e->tile_ok)
+            return fail(e, SP_E_UNSUPPORTED,
+                        "fusedtile needs 2-4 atoms per cell in 2D (reach <= 2) or 1-3 (FP64: 1-2) in 3D (reach <= 1), "
+                        "no dipole or Gaussian terms");
+        e->path = "fusedtile";
     } else if (s.rfind("shape2d", 0) == 0) {
         if (e->shape < 0)
             return fail(e, SP_E_UNSUPPORTED, "shape2d needs a bond table matching a compile-time stencil");
@@ -2163,6 +2275,7 @@ int sp_autotune(sp_engine* e, const sp_llg_params* p, int n_steps, double* ms_pe
             cands.push_back(std::string("shape2d/") + (e->precision == SP_F64 ? kSolverTileF64 : kSolverTileF32));
     } else {
         if (e->fused_ok) cands.push_back("fused2d");
+        if (e->tile_ok) cands.push_back("fusedtile");
         if (e->shape >= 0) {
             const int ncfg = e->precision == SP_F64 ? kNumTileCfgsF64 : kNumTileCfgs;
             for (int k = 0; k < ncfg; ++k) cands.push_back(std::string("shape2d/") + kTileCfgs[k].name);

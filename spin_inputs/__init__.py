@@ -18,6 +18,9 @@ from .workloads import (  # noqa: F401
     square,
     triangular,
     simple_cubic,
+    honeycomb,
+    kagome,
+    fcc_primitive,
     DMI_BULK,
     DMI_INTERFACIAL,
 )

@@ -98,6 +98,27 @@ def triangular(n_a: int, n_b: int, periodic=(1, 1, 0)) -> Geometry:
                     ((0.0, 0.0, 0.0),), (n_a, n_b, 1), tuple(periodic))
 
 
+def honeycomb(n_a: int, n_b: int, periodic=(1, 1, 0)) -> Geometry:
+    """Triangular Bravais lattice with a two-atom basis (nearest-neighbour
+    distance 1/sqrt(3))."""
+    return Geometry(((1.0, 0.0, 0.0), (0.5, math.sqrt(3.0) / 2.0, 0.0), (0.0, 0.0, 1.0)),
+                    ((0.0, 0.0, 0.0), (0.5, math.sqrt(3.0) / 6.0, 0.0)), (n_a, n_b, 1), tuple(periodic))
+
+
+def kagome(n_a: int, n_b: int, periodic=(1, 1, 0)) -> Geometry:
+    """Triangular Bravais lattice with a three-atom basis (corner-sharing
+    triangles, nearest-neighbour distance 1/2)."""
+    return Geometry(((1.0, 0.0, 0.0), (0.5, math.sqrt(3.0) / 2.0, 0.0), (0.0, 0.0, 1.0)),
+                    ((0.0, 0.0, 0.0), (0.5, 0.0, 0.0), (0.25, math.sqrt(3.0) / 4.0, 0.0)), (n_a, n_b, 1),
+                    tuple(periodic))
+
+
+def fcc_primitive(n_a: int, n_b: int, n_c: int, periodic=(1, 1, 1)) -> Geometry:
+    """Face-centred cubic lattice on its primitive (one-atom) cell."""
+    return Geometry(((0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0)),
+                    ((0.0, 0.0, 0.0),), (n_a, n_b, n_c), tuple(periodic))
+
+
 def simple_cubic(n_a: int, n_b: int, n_c: int, periodic=(1, 1, 1)) -> Geometry:
     return Geometry(((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)),
                     ((0.0, 0.0, 0.0),), (n_a, n_b, n_c), tuple(periodic))

@@ -81,7 +81,7 @@ def test_pairs_trajectory_matches_oracle_on_every_path(ora, case, precision):
     assert not e.step_path.startswith(("shape", "persist"))
     n0 = si.uniform_sphere(s.N, 7)
     ref, _ = s.run(n0, 0.3, 0.001, 4, T=20.0, seed=5, step0=3)
-    paths = ["twopass"] + (["fused2d"] if e.step_path == "fused2d" else [])
+    paths = ["twopass"] + ([e.step_path] if e.step_path in ("fused2d", "fusedtile") else [])
     for path in paths:
         e.step_path = path
         e.set_spins(n0)

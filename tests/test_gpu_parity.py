@@ -29,8 +29,20 @@ BASIS2_HAM = si.Hamiltonian(mu=(2.0, 3.0), B=(0.2, 0.4, -0.3), K=(0.1, -0.2),
                             K_axis=((0, 0, 1), (0.6, 0.8, 0.0)), J=(1.0, 0.5), D=(0.1, 0.05),
                             dmi_kind=si.DMI_BULK)
 
+HC_HAM = si.Hamiltonian(mu=(2.0, 2.5), B=(0.1, -0.2, 0.5), K=(0.1, 0.05),
+                        K_axis=((0, 0, 1), (0.6, 0.0, 0.8)), J=(1.0, 0.2, -0.1), D=(0.15,))
+KG_HAM = si.Hamiltonian(mu=(2.0, 2.0, 3.0), B=(0.0, 0.0, 0.4), K=(0.1, 0.1, 0.2),
+                        K_axis=((0, 0, 1), (0, 0, 1), (0, 0, 1)), J=(1.0, -0.2, 0.1), D=(0.1,))
+# the square lattice of spacing 1/2 written as a four-atom cell of spacing 1
+SQ4_GEO = si.Geometry(((1.0, 0, 0), (0, 1.0, 0), (0, 0, 1.0)),
+                      ((0, 0, 0), (0.5, 0, 0), (0, 0.5, 0), (0.5, 0.5, 0)), (16, 12, 1), (1, 1, 0))
+SQ4_HAM = si.Hamiltonian(mu=(2.0,) * 4, B=(0.0, 0.0, 1.0), K=(0.1,) * 4, K_axis=((0, 0, 1),) * 4,
+                         J=(1.0, 0.3), D=(0.3,))
+
 CASES = {
     "square32": (W["square32_fp64"].geometry, HAM0),
+    "honeycomb37x22": (si.honeycomb(37, 22), HC_HAM),
+    "kagome24x19_open": (si.kagome(24, 19, periodic=(1, 0, 0)), KG_HAM),
     "square2x2": (si.square(2, 2), HAM0),
     "tri40x24_ragged": (si.triangular(40, 24), HAM1),
     "tri37x29_open": (si.triangular(37, 29, periodic=(0, 1, 0)), HAM1),
@@ -466,3 +478,92 @@ def test_zero_work_calls_change_nothing(ora, path):
     s0 = b.get_spins(0)
     b.run(0)
     assert b.step == 0 and np.array_equal(b.get_spins(0), s0)
+
+
+TILE_CASES = {
+    "honeycomb37x22": (si.honeycomb(37, 22), HC_HAM),
+    "honeycomb41x19_4shell": (si.honeycomb(41, 19), dataclasses.replace(HC_HAM, J=(1.0, 0.2, -0.1, 0.05))),
+    "honeycomb35x18_open": (si.honeycomb(35, 18, periodic=(0, 1, 0)), HC_HAM),
+    "kagome24x19_open": (si.kagome(24, 19, periodic=(1, 0, 0)), KG_HAM),
+    "square4atom16x12": (SQ4_GEO, SQ4_HAM),
+    "basis2": (BASIS2_GEO, BASIS2_HAM),
+    "bcc12x10x6": (BASIS2_GEO.with_cells((12, 10, 6), (1, 1, 1)), BASIS2_HAM),
+    "fcc9x8x7": (si.fcc_primitive(9, 8, 7),
+                 si.Hamiltonian(mu=(2.0,), B=(0.0, 0.0, 0.3), K=(0.05,), K_axis=((0, 0, 1),), J=(1.0, 0.1),
+                                D=(0.1,), dmi_kind=si.DMI_BULK)),
+}
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(TILE_CASES))
+def test_fused_tile_path_matches_oracle(ora, case, precision):
+    """Lattices with a basis (2D: two to four atoms, reach 1 and 2, ragged
+    and open edges; 3D: two atoms, open and periodic c) and a 3D one-atom
+    lattice without a compile-time stencil take the fused tile path by
+    default; its 4-step stochastic trajectory matches the oracle's, and the
+    two-pass path's."""
+    geo, ham = TILE_CASES[case]
+    announce(f"fused tile {case} {precision}")
+    e, s = make_pair(ora, geo, ham, precision)
+    assert e.step_path == "fusedtile", e.step_path
+    n0 = si.uniform_sphere(s.N, 31)
+    ref, _ = s.run(n0, 0.3, 0.001, 4, T=20.0, seed=13, step0=3)
+    res = {}
+    for path in ["fusedtile", "twopass"]:
+        e.step_path = path
+        e.set_spins(n0)
+        e.step = 3
+        e.run(0.3, 0.001, 4, T=20.0, seed=13)
+        res[path] = e.get_spins()
+        assert_close(res[path], ref, precision, what=f"4 steps {case} [{path}]")
+    assert rel_err(res["fusedtile"], res["twopass"]) <= 2 * TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["honeycomb41x19_4shell", "kagome24x19_open", "bcc12x10x6"])
+def test_fused_tile_trajectory_200_steps(ora, case, precision):
+    """200 damped steps (T = 0) on the fused tile path against the oracle."""
+    geo, ham = TILE_CASES[case]
+    announce(f"fused tile 200 steps {case} {precision}")
+    e, s = make_pair(ora, geo, ham, precision)
+    assert e.step_path == "fusedtile"
+    n0 = si.uniform_sphere(s.N, 37)
+    e.set_spins(n0)
+    e.run(0.3, 0.001, 200)
+    ref, _ = s.run(n0, 0.3, 0.001, 200)
+    assert_close(e.get_spins(), ref, precision, what=f"200 steps {case}")
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_four_atom_cell_equals_the_one_atom_lattice(ora, precision):
+    """The square lattice of spacing 1/2 as a four-atom cell (fused tile path)
+    and as a 32 x 24 one-atom lattice (compile-time stencil path): the same
+    spins give the same trajectory, site by site."""
+    announce(f"four-atom cell vs one-atom lattice {precision}")
+    import paper_1901_11350_amd as pk
+
+    a = pk.Engine(0, precision)
+    a.set_geometry(SQ4_GEO)
+    a.set_hamiltonian(SQ4_HAM)
+    assert a.step_path == "fusedtile"
+    one_geo = si.Geometry(((0.5, 0, 0), (0, 0.5, 0), (0, 0, 1.0)), ((0, 0, 0),), (32, 24, 1), (1, 1, 0))
+    one_ham = si.Hamiltonian(mu=(2.0,), B=(0.0, 0.0, 1.0), K=(0.1,), K_axis=((0, 0, 1),), J=(1.0, 0.3), D=(0.3,))
+    b = pk.Engine(0, precision)
+    b.set_geometry(one_geo)
+    b.set_hamiltonian(one_ham)
+    # site (x, y) of the fine lattice is atom (x % 2) + 2 (y % 2) of cell (x // 2, y // 2)
+    x, y = np.meshgrid(np.arange(32), np.arange(24))
+    x, y = x.ravel(), y.ravel()
+    four = (x // 2) + 16 * ((y // 2) + 12 * ((x % 2) + 2 * (y % 2)))
+    one = x + 32 * y
+    n_one = si.uniform_sphere(32 * 24, 41)
+    n_four = np.zeros_like(n_one)
+    n_four[:, four] = n_one[:, one]
+    a.set_spins(n_four)
+    b.set_spins(n_one)
+    assert_close(a.gradient()[:, four], b.gradient()[:, one], precision, what="gradient")
+    a.run(0.3, 0.001, 50, T=0.0)
+    b.run(0.3, 0.001, 50, T=0.0)
+    assert_close(a.get_spins()[:, four], b.get_spins()[:, one], precision, what="50 steps")
+    a.close()
+    b.close()

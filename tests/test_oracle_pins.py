@@ -569,3 +569,28 @@ def test_philox_matches_rocrand(ora, tmp_path):
         seed, sub, off, *vals = [int(x) for x in line.split()]
         ours = ora.philox4x32_10([off // 4, 0, sub, 0], [seed & 0xFFFFFFFF, seed >> 32])
         assert ours == vals
+
+
+def test_four_atom_cell_equals_the_one_atom_lattice(ora):
+    """Basis handling: the square lattice of spacing 1/2 written as a
+    four-atom cell of spacing 1 has the same shells, bonds, gradient and
+    trajectory as the one-atom lattice, site by site."""
+    geo4 = si.Geometry(((1.0, 0, 0), (0, 1.0, 0), (0, 0, 1.0)),
+                       ((0, 0, 0), (0.5, 0, 0), (0, 0.5, 0), (0.5, 0.5, 0)), (8, 6, 1), (1, 1, 0))
+    ham4 = si.Hamiltonian(mu=(2.0,) * 4, B=(0.0, 0.0, 1.0), K=(0.1,) * 4, K_axis=((0, 0, 1),) * 4,
+                          J=(1.0, 0.3), D=(0.3,))
+    geo1 = si.Geometry(((0.5, 0, 0), (0, 0.5, 0), (0, 0, 1.0)), ((0, 0, 0),), (16, 12, 1), (1, 1, 0))
+    ham1 = si.Hamiltonian(mu=(2.0,), B=(0.0, 0.0, 1.0), K=(0.1,), K_axis=((0, 0, 1),), J=(1.0, 0.3), D=(0.3,))
+    a, b = ora.System(geo4, ham4), ora.System(geo1, ham1)
+    x, y = np.meshgrid(np.arange(16), np.arange(12))
+    x, y = x.ravel(), y.ravel()
+    four = (x // 2) + 8 * ((y // 2) + 6 * ((x % 2) + 2 * (y % 2)))
+    one = x + 16 * y
+    n1 = si.uniform_sphere(16 * 12, 41)
+    n4 = np.zeros_like(n1)
+    n4[:, four] = n1[:, one]
+    assert np.abs(a.gradient(n4)[:, four] - b.gradient(n1)[:, one]).max() < 1e-13
+    assert a.energy(n4) == pytest.approx(b.energy(n1), rel=1e-13)
+    r4, _ = a.run(n4, 0.3, 0.001, 20, T=0.0)
+    r1, _ = b.run(n1, 0.3, 0.001, 20, T=0.0)
+    assert np.abs(r4[:, four] - r1[:, one]).max() < 1e-13
