@@ -612,9 +612,11 @@ void launch_fused2d(sp_engine* e, const sp_llg_params* p, uint64_t step, const v
 // or 16 x 8; 3D FP32 16 x 8 x 4 (one, two atoms) or 8 x 8 x 4 (three), FP64
 // 8 x 8 x 4 (one, two).  Reach up to 2 in 2D, 1 in 3D.  Every instance
 // stays within the 160 KB of LDS a workgroup may hold.
-bool tile_fits(const sp_engine* e, const HostHam& H, size_t n_bonds) {
+int padded_bonds(const sp_engine* e);
+
+bool tile_fits(const sp_engine* e, const HostHam& H) {
     const HostGeo& g = e->geo;
-    if (H.ddi || H.n_gauss > 0 || g.nb > 4 || n_bonds > (size_t)sp::kMaxStencilB) return false;
+    if (H.ddi || H.n_gauss > 0 || g.nb > 4 || padded_bonds(e) > sp::kMaxStencilB) return false;
     int rc = 0;
     for (const HostBond& b : e->bonds) rc = std::max(rc, std::abs(b.d[2]));
     if (g.n[2] == 1) {
@@ -628,21 +630,39 @@ bool tile_fits(const sp_engine* e, const HostHam& H, size_t n_bonds) {
     return true;
 }
 
+// Bond table of the tile kernel whose spin frame is WN x HN (x DN), block
+// PN cells per atom, and predictor frame WP x HP, block PP.
+// Each atom's list is padded to a multiple of four with zero bonds to the
+// site's own cell (offset 0).
 template <typename T>
-sp::StencilB<T> make_stencilb(const sp_engine* e) {
+sp::StencilB<T> make_stencilb(const sp_engine* e, int WN, int HN, int PN, int WP, int HP, int PP) {
     sp::StencilB<T> S{};
     S.nb = e->geo.nb;
-    for (int b = 0; b <= S.nb; ++b) S.bstart[b] = e->bstart[b];
-    for (int q = 0; q < (int)e->bonds.size(); ++q) {
-        const HostBond& b = e->bonds[q];
-        S.bj[q] = b.bj;
-        S.da[q] = b.d[0];
-        S.db[q] = b.d[1];
-        S.dc[q] = b.d[2];
-        S.J[q] = (T)b.J;
-        for (int k = 0; k < 3; ++k) S.D[q][k] = (T)b.D[k];
+    int q = 0;
+    for (int beta = 0; beta < S.nb; ++beta) {
+        S.bstart[beta] = q;
+        for (int k = e->bstart[beta]; k < e->bstart[beta + 1]; ++k, ++q) {
+            const HostBond& b = e->bonds[k];
+            S.offN[q] = PN * b.bj + b.d[0] + WN * (b.d[1] + HN * b.d[2]);
+            S.offP[q] = PP * b.bj + b.d[0] + WP * (b.d[1] + HP * b.d[2]);
+            S.J[q] = (T)b.J;
+            for (int c = 0; c < 3; ++c) S.D[q][c] = (T)b.D[c];
+        }
+        for (; q % 4; ++q) {   // zero bonds (the struct is value-initialised)
+            S.offN[q] = 0;
+            S.offP[q] = 0;
+        }
     }
+    S.bstart[S.nb] = q;
     return S;
+}
+
+// Bonds of the tile kernel's table once each atom's list is padded to a
+// multiple of four.
+int padded_bonds(const sp_engine* e) {
+    int n = 0;
+    for (int b = 0; b < e->geo.nb; ++b) n += (e->bstart[b + 1] - e->bstart[b] + 3) / 4 * 4;
+    return n;
 }
 
 template <typename T>
@@ -669,8 +689,11 @@ template <typename T, int TX, int TY, int TZ, int R, int RC, int NB>
 void launch_tile_k(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     const dim3 grid((unsigned)((e->geo.n[0] + TX - 1) / TX), (unsigned)((e->geo.n[1] + TY - 1) / TY),
                     (unsigned)((e->geo.n[2] + TZ - 1) / TZ));
+    constexpr int WN = TX + 4 * R, HN = TY + 4 * R, DN = TZ + 4 * RC;
+    constexpr int WP = TX + 2 * R, HP = TY + 2 * R, DP = TZ + 2 * RC;
     hipLaunchKernelGGL((sp::k_fused_tile<T, TX, TY, TZ, R, RC, NB>), grid, dim3(NB * TX * TY * TZ), 0, e->stream,
-                       make_stencilb<T>(e), make_siteb<T>(e, p), make_step_llg<T>(e, p, step), e->d_flag,
+                       make_stencilb<T>(e, WN, HN, WN * HN * DN, WP, HP, WP * HP * DP), make_siteb<T>(e, p),
+                       make_step_llg<T>(e, p, step), e->d_flag,
                        static_cast<const T*>(nin), static_cast<T*>(nout));
 }
 
@@ -1853,7 +1876,7 @@ int install_ham(sp_engine* e, const HostHam& H, const std::vector<HostBond>& bon
     if (g.per[0] && g.n[0] <= 2 * e->R) fused = false;
     if (g.per[1] && g.n[1] <= 2 * e->R) fused = false;
     e->fused_ok = fused;
-    e->tile_ok = !fused && tile_fits(e, H, bonds.size());
+    e->tile_ok = !fused && tile_fits(e, H);
     e->path = fused ? "fused2d" : e->tile_ok ? "fusedtile" : "twopass";
     // compile-time stencil: the bond table must match a known shape, DMI may
     // sit on the first shell only, and every DMI vector must be in-plane

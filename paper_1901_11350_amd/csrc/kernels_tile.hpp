@@ -28,14 +28,18 @@ namespace sp {
 
 constexpr int kMaxStencilB = 48;   // directed bonds of all basis atoms together
 
+// Bond q of atom beta (bstart[beta] <= q < bstart[beta + 1]) reaches the
+// LDS cell offN[q] (spin frame) or offP[q] (predictor frame) away from the
+// site's own cell; the host forms both from the bond's target atom and
+// cell offset and the frames' pitches.  Each atom's list is padded to a
+// multiple of four with bonds of zero coupling to the site's own cell
+// (they add exactly zero), so the field loop takes four bonds at a time.
 template <typename T>
 struct StencilB {
     int nb;
     int bstart[kMaxBasis + 1];
-    int bj[kMaxStencilB];
-    int da[kMaxStencilB];
-    int db[kMaxStencilB];
-    int dc[kMaxStencilB];
+    int offN[kMaxStencilB];
+    int offP[kMaxStencilB];
     T J[kMaxStencilB];
     T D[kMaxStencilB][3];
 };
@@ -51,23 +55,40 @@ struct SiteB {
     T sigma[kMaxBasis];
 };
 
-// Field of atom beta at cell c of an NB-block LDS frame (row pitch W, plane
-// pitch WH, block of PL cells per atom).
+// Field of atom beta at cell c of an LDS frame whose bond offsets are off[].
+// beta is wavefront-uniform, so the bond data are scalar loads.
 template <typename T>
 __device__ __forceinline__ V3<T> tile_field(const StencilB<T>& S, const SiteB<T>& Q, int beta,
-                                            const V4<T>* __restrict__ s, int PL, int c, int W, int WH, V3<T> ni) {
+                                            const V4<T>* __restrict__ s, const int* off, int c, V3<T> ni) {
     V3<T> g{Q.gZ[beta][0], Q.gZ[beta][1], Q.gZ[beta][2]};
     const T kn = Q.K2[beta] * (Q.Kax[beta][0] * ni.x + Q.Kax[beta][1] * ni.y + Q.Kax[beta][2] * ni.z);
     g.x -= kn * Q.Kax[beta][0];
     g.y -= kn * Q.Kax[beta][1];
     g.z -= kn * Q.Kax[beta][2];
-    for (int q = S.bstart[beta]; q < S.bstart[beta + 1]; ++q) {
-        const V3<T> nj = lds_cell_xyz(s, PL * S.bj[q] + c + S.da[q] + S.db[q] * W + S.dc[q] * WH);
-        const T J = S.J[q];
-        const T Dx = S.D[q][0], Dy = S.D[q][1], Dz = S.D[q][2];
-        g.x -= J * nj.x + (nj.y * Dz - nj.z * Dy);
-        g.y -= J * nj.y + (nj.z * Dx - nj.x * Dz);
-        g.z -= J * nj.z + (nj.x * Dy - nj.y * Dx);
+    const int q1 = S.bstart[beta + 1];
+    for (int q0 = S.bstart[beta]; q0 < q1; q0 += 4) {
+        // four full-width 16-byte reads in flight together: one empty asm
+        // keeps every padding word live (else the compiler narrows each read
+        // to 12 bytes), placed after all four so they are not serialised
+        V4<T> v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = s[c + off[q0 + k]];
+        T J[4], D[4][3];   // the coefficients' scalar loads overlap the LDS reads
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            J[k] = S.J[q0 + k];
+            D[k][0] = S.D[q0 + k][0];
+            D[k][1] = S.D[q0 + k][1];
+            D[k][2] = S.D[q0 + k][2];
+        }
+        if constexpr (sizeof(T) == 4) asm volatile("" ::"v"(v[0].w), "v"(v[1].w), "v"(v[2].w), "v"(v[3].w));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const V3<T> nj{v[k].x, v[k].y, v[k].z};
+            g.x -= J[k] * nj.x + (nj.y * D[k][2] - nj.z * D[k][1]);
+            g.y -= J[k] * nj.y + (nj.z * D[k][0] - nj.x * D[k][2]);
+            g.z -= J[k] * nj.z + (nj.x * D[k][1] - nj.y * D[k][0]);
+        }
     }
     return g;
 }
@@ -152,7 +173,7 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
         }
     }
     // the owned site (its predictor-frame cell wraps like any other)
-    const int beta = tid / PT, t = tid - beta * PT;
+    const int beta = __builtin_amdgcn_readfirstlane(tid / PT), t = tid - beta * PT;
     const int tz = t / (TX * TY), tr = t - tz * (TX * TY);
     const int ty = tr / TX, tx = tr - ty * TX;
     int ox = x0 + tx, oy = y0 + ty, oz = z0 + tz;
@@ -178,7 +199,7 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
         if (own_in) {
             const int c = ((tz + 2 * RC) * HN + (ty + 2 * R)) * WN + (tx + 2 * R);
             const V3<T> ni = lds_cell_xyz(sN, beta * PN + c);
-            const V3<T> g = tile_field(S, Q, beta, sN, PN, c, WN, WN * HN, ni);
+            const V3<T> g = tile_field(S, Q, beta, sN, S.offN, c, ni);
             const V3<T> B = (-Q.inv_mumuB[beta]) * g + Bth;
             Ai = llg_A(ni, B, A.gp, A.alpha);
             const V3<T> o = rotate_fast(ni, T(-1) * Ai, A.dt);
@@ -187,7 +208,7 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
         sP[beta * PP + pc] = out;
     }
     for (int idx = tid; idx < NB * RINGP; idx += NT) {
-        const int b = idx / RINGP, h = idx - b * RINGP;
+        const int b = __builtin_amdgcn_readfirstlane(idx / RINGP), h = idx - b * RINGP;
         if (h >= RING) continue;
         int px, py, pz;
         tile_ring_cell<TX, TY, TZ, R, RC>(h, px, py, pz);
@@ -196,7 +217,7 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
         if (tile_coord(gx, na, Q.per[0]) & tile_coord(gy, nbc, Q.per[1]) & tile_coord(gz, nc, Q.per[2])) {
             const int c = ((pz + RC) * HN + (py + R)) * WN + (px + R);
             const V3<T> ni = lds_cell_xyz(sN, b * PN + c);
-            const V3<T> g = tile_field(S, Q, b, sN, PN, c, WN, WN * HN, ni);
+            const V3<T> g = tile_field(S, Q, b, sN, S.offN, c, ni);
             V3<T> B = (-Q.inv_mumuB[b]) * g;
             if (A.thermal) {
                 const uint32_t site = (uint32_t)(gx + na * (gy + nbc * gz) + b * block);
@@ -214,7 +235,7 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
     if (!own_site) return;
     const int pc = ((tz + RC) * HP + (ty + R)) * WP + (tx + R);
     const V3<T> npi = lds_cell_xyz(sP, beta * PP + pc);
-    const V3<T> g = tile_field(S, Q, beta, sP, PP, pc, WP, WP * HP, npi);
+    const V3<T> g = tile_field(S, Q, beta, sP, S.offP, pc, npi);
     const V3<T> B = (-Q.inv_mumuB[beta]) * g + Bth;
     const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
     const V3<T> w{T(-0.5) * (Ai.x + Ap.x), T(-0.5) * (Ai.y + Ap.y), T(-0.5) * (Ai.z + Ap.z)};
