@@ -1025,9 +1025,19 @@ void go_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* 
     Z.zc = (Z.nc + chunks - 1) / chunks;
     const int nchunks = (Z.nc + Z.zc - 1) / Z.zc;
     Z.xcd_bands = ((txy * nchunks) % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, DK, TX, TY, SOLVER>), dim3((unsigned)(txy * nchunks)),
-                       dim3(TX * TY), 0, e->stream, shape_coef3_for<T, S>(e), make_site2d<T>(e, p), Z,
-                       make_step_llg<T>(e, p, step), e->d_flag, static_cast<const T*>(nin), static_cast<T*>(nout));
+    const dim3 grid((unsigned)(txy * nchunks)), block(TX * TY);
+    // Depondt steps without anisotropy take the instance that leaves the term out
+    if constexpr (SOLVER == sp::SOLVER_DEPONDT) {
+        if (e->ham.K[0] == 0.0) {
+            hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, DK, TX, TY, SOLVER, false>), grid, block, 0, e->stream,
+                               shape_coef3_for<T, S>(e), make_site2d<T>(e, p), Z, make_step_llg<T>(e, p, step),
+                               e->d_flag, static_cast<const T*>(nin), static_cast<T*>(nout));
+            return;
+        }
+    }
+    hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, DK, TX, TY, SOLVER, true>), grid, block, 0, e->stream,
+                       shape_coef3_for<T, S>(e), make_site2d<T>(e, p), Z, make_step_llg<T>(e, p, step), e->d_flag,
+                       static_cast<const T*>(nin), static_cast<T*>(nout));
 }
 
 template <typename T, int S, int TX, int TY, int SOLVER>

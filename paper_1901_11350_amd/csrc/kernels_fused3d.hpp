@@ -86,39 +86,74 @@ struct PlaneLDS {
     V4<T> sP[3][PP];   // predictor plane k lives in slot k mod 3
 };
 
+// True when bond q is the first of its shell in the stencil's order (folds
+// to a constant once the bond loop is unrolled).
+template <typename SH>
+__device__ constexpr bool first_of_shell(int q) {
+    for (int r = 0; r < q; ++r)
+        if (SH::sh[r] == SH::sh[q]) return false;
+    return true;
+}
+
 // Field of one site from its 3 x 3 x 3 neighbourhood in LDS: bm, b0 and bp
 // point at cell (-1, -1) of the site's row in the planes below, at and above
 // it (row pitch W), so every neighbour is a non-negative compile-time offset
-// from one of three base addresses.  aniso: the anisotropy term is non-zero.
-template <typename T, int S, int DK, int W>
+// from one of three base addresses.  Neighbours are read six at a time as
+// full 16-byte cells, with one empty asm after each group keeping the
+// padding words live (else each read is narrowed to 12 bytes); a group's
+// reads are in flight together.  Shell sums start from their first
+// neighbour.  AN: the anisotropy term is formed (off when K = 0).
+template <typename T, int S, int DK, int W, bool AN>
 __device__ __forceinline__ V3<T> shape_field3(const ShapeCoef3<T>& C, const Site2D<T>& Q,
                                               const V4<T>* __restrict__ bm, const V4<T>* __restrict__ b0,
-                                              const V4<T>* __restrict__ bp, V3<T> ni, bool aniso) {
+                                              const V4<T>* __restrict__ bp, V3<T> ni) {
     using SH = ShapeTab3<S>;
     static_assert(SH::da[0] == 1 && SH::da[1] == -1 && SH::db[2] == 1 && SH::db[3] == -1 && SH::dc[4] == 1 &&
                       SH::dc[5] == -1,
                   "first six bonds are +x, -x, +y, -y, +z, -z");
+    constexpr int G = 6;
     V3<T> acc[SH::NS];
-#pragma unroll
-    for (int s = 0; s < SH::NS; ++s) acc[s] = V3<T>{T(0), T(0), T(0)};
     V3<T> dm{T(0), T(0), T(0)};
     V3<T> nn[6];
 #pragma unroll
-    for (int q = 0; q < SH::NB; ++q) {
-        const V4<T>* b = SH::dc[q] < 0 ? bm : (SH::dc[q] > 0 ? bp : b0);
-        const V3<T> v = lds_cell_xyz(b, (SH::da[q] + 1) + (SH::db[q] + 1) * W);
-        acc[SH::sh[q]].x += v.x;
-        acc[SH::sh[q]].y += v.y;
-        acc[SH::sh[q]].z += v.z;
-        if constexpr (DK == DK_GENERAL) {
-            if (q < SH::NB0) {
-                // n_j x D
-                dm.x += v.y * C.Dz[q] - v.z * C.Dy[q];
-                dm.y += v.z * C.Dx[q] - v.x * C.Dz[q];
-                dm.z += v.x * C.Dy[q] - v.y * C.Dx[q];
+    for (int q0 = 0; q0 < SH::NB; q0 += G) {
+        V4<T> v[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int q = q0 + k;
+            if (q < SH::NB) {
+                const V4<T>* b = SH::dc[q] < 0 ? bm : (SH::dc[q] > 0 ? bp : b0);
+                v[k] = b[(SH::da[q] + 1) + (SH::db[q] + 1) * W];
+            } else {
+                v[k] = v[0];
             }
         }
-        if (q < 6) nn[q] = v;
+        if constexpr (sizeof(T) == 4)
+            asm volatile("" ::"v"(v[0].w), "v"(v[1].w), "v"(v[2].w), "v"(v[3].w), "v"(v[4].w), "v"(v[5].w));
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int q = q0 + k;
+            if (q < SH::NB) {
+                const V3<T> x{v[k].x, v[k].y, v[k].z};
+                const int s = SH::sh[q];
+                if (first_of_shell<SH>(q)) {
+                    acc[s] = x;
+                } else {
+                    acc[s].x += x.x;
+                    acc[s].y += x.y;
+                    acc[s].z += x.z;
+                }
+                if constexpr (DK == DK_GENERAL) {
+                    if (q < SH::NB0) {
+                        // n_j x D
+                        dm.x += x.y * C.Dz[q] - x.z * C.Dy[q];
+                        dm.y += x.z * C.Dx[q] - x.x * C.Dz[q];
+                        dm.z += x.x * C.Dy[q] - x.y * C.Dx[q];
+                    }
+                }
+                if (q < 6) nn[q] = x;
+            }
+        }
     }
     if constexpr (DK == DK_BULK) {
         dm.x = C.D0 * ((nn[4].y - nn[5].y) - (nn[2].z - nn[3].z));
@@ -126,7 +161,7 @@ __device__ __forceinline__ V3<T> shape_field3(const ShapeCoef3<T>& C, const Site
         dm.z = C.D0 * ((nn[2].x - nn[3].x) - (nn[0].y - nn[1].y));
     }
     V3<T> g{Q.gZ[0] - dm.x, Q.gZ[1] - dm.y, Q.gZ[2] - dm.z};
-    if (aniso) {
+    if constexpr (AN) {
         const T kn = Q.K2 * (Q.Kax[0] * ni.x + Q.Kax[1] * ni.y + Q.Kax[2] * ni.z);
         g.x -= kn * Q.Kax[0];
         g.y -= kn * Q.Kax[1];
@@ -152,7 +187,7 @@ __device__ __forceinline__ int wrap_plane(int z, int nc, int per, bool& in) {
     return z < 0 ? z + nc : z;
 }
 
-template <typename T, int S, int DK, int TX, int TY, int SOLVER>
+template <typename T, int S, int DK, int TX, int TY, int SOLVER, bool AN>
 __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site2D<T> Q, Site3D Z, LLGArgs<T> A_arg,
                                                             const int* __restrict__ abort_flag,
                                                             const T* __restrict__ n, T* __restrict__ nout) {
@@ -183,7 +218,6 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
     const long long plane = (long long)NA * NBB;
     const long long N = plane * Z.nc;
     const int tx = tid % TX, tyy = tid / TX;
-    const bool aniso = Q.K2 != T(0);
     // predictor ring slot of plane z (z >= -2)
     auto pslot = [](int z) { return (z + 3) % 3; };
 
@@ -265,8 +299,8 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
             const int c = (py + R) * WN + (px + R);
             const V3<T> ni = lds_cell_xyz(L.sN[z & 3], c);
             const int cb = c - WN - 1;
-            const V3<T> g = shape_field3<T, S, DK, WN>(C, Q, L.sN[(z - 1) & 3] + cb, L.sN[z & 3] + cb,
-                                                       L.sN[(z + 1) & 3] + cb, ni, aniso);
+            const V3<T> g = shape_field3<T, S, DK, WN, AN>(C, Q, L.sN[(z - 1) & 3] + cb, L.sN[z & 3] + cb,
+                                                           L.sN[(z + 1) & 3] + cb, ni);
             const V3<T> B = (-Q.inv_mumuB) * g + Bth;
             const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
             V3<T> o;
@@ -316,8 +350,8 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
         if (zc >= z0 && zc < z1 && own_site) {
             const V3<T> npi = lds_cell_xyz(L.sP[pslot(zc)], cP);
             const int cb = cP - WP - 1;
-            const V3<T> g = shape_field3<T, S, DK, WP>(C, Q, L.sP[pslot(zc - 1)] + cb, L.sP[pslot(zc)] + cb,
-                                                       L.sP[pslot(zc + 1)] + cb, npi, aniso);
+            const V3<T> g = shape_field3<T, S, DK, WP, AN>(C, Q, L.sP[pslot(zc - 1)] + cb, L.sP[pslot(zc)] + cb,
+                                                           L.sP[pslot(zc + 1)] + cb, npi);
             const V3<T> B = (-Q.inv_mumuB) * g + keepB;
             const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
             const V3<T> ni = lds_cell_xyz(L.sN[zc & 3], cN);
