@@ -190,11 +190,70 @@ __device__ __forceinline__ V3<T> lds_cell_xyz(const V4<T>* __restrict__ sv, int 
     return V3<T>{v.x, v.y, v.z};
 }
 
+// True when bond q is the first of its shell in the stencil's order (folds
+// to a constant once a bond loop is unrolled).
+template <typename SH>
+__device__ constexpr bool first_of_shell(int q) {
+    for (int r = 0; r < q; ++r)
+        if (SH::sh[r] == SH::sh[q]) return false;
+    return true;
+}
+
+// shape_field on 16-byte LDS cells: neighbours are read six at a time, with
+// one empty asm after each group keeping the padding words live, so a
+// group's reads are in flight together (one wait per group instead of one
+// per read); shell sums start from their first neighbour.
 template <typename T, int S, int NDMI, int W>
 __device__ __forceinline__ V3<T> shape_field_aos(const ShapeCoef<T>& C, const Site2D<T>& Q,
                                                  const V4<T>* __restrict__ sv, int c, V3<T> ni) {
-    return shape_field<T, S, NDMI, W>(
-        C, Q, [&](int o) { return lds_cell_xyz(sv, o); }, c, ni);
+    using SH = ShapeTab<S>;
+    constexpr int G = 6;
+    V3<T> acc[SH::NS];
+    T dx = T(0), dy = T(0), dz = T(0);
+#pragma unroll
+    for (int q0 = 0; q0 < SH::NB; q0 += G) {
+        V4<T> v[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int q = q0 + k;
+            if (q < SH::NB)
+                v[k] = sv[c + SH::da[q] + SH::db[q] * W];
+            else
+                v[k] = v[0];
+        }
+        if constexpr (sizeof(T) == 4)
+            asm volatile("" ::"v"(v[0].w), "v"(v[1].w), "v"(v[2].w), "v"(v[3].w), "v"(v[4].w), "v"(v[5].w));
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int q = q0 + k;
+            if (q < SH::NB) {
+                const V3<T> nj{v[k].x, v[k].y, v[k].z};
+                const int sh = SH::sh[q];
+                if (first_of_shell<SH>(q)) {
+                    acc[sh] = nj;
+                } else {
+                    acc[sh].x += nj.x;
+                    acc[sh].y += nj.y;
+                    acc[sh].z += nj.z;
+                }
+                if (q < NDMI) {
+                    // n_j x D with D = (Dx, Dy, 0)
+                    dx -= nj.z * C.Dy[q];
+                    dy += nj.z * C.Dx[q];
+                    dz += nj.x * C.Dy[q] - nj.y * C.Dx[q];
+                }
+            }
+        }
+    }
+    const T kn = Q.K2 * (Q.Kax[0] * ni.x + Q.Kax[1] * ni.y + Q.Kax[2] * ni.z);
+    V3<T> g{Q.gZ[0] - kn * Q.Kax[0] - dx, Q.gZ[1] - kn * Q.Kax[1] - dy, Q.gZ[2] - kn * Q.Kax[2] - dz};
+#pragma unroll
+    for (int s = 0; s < SH::NS; ++s) {
+        g.x -= C.J[s] * acc[s].x;
+        g.y -= C.J[s] * acc[s].y;
+        g.z -= C.J[s] * acc[s].z;
+    }
+    return g;
 }
 
 struct TileMap {

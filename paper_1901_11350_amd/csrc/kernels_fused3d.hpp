@@ -86,15 +86,6 @@ struct PlaneLDS {
     V4<T> sP[3][PP];   // predictor plane k lives in slot k mod 3
 };
 
-// True when bond q is the first of its shell in the stencil's order (folds
-// to a constant once the bond loop is unrolled).
-template <typename SH>
-__device__ constexpr bool first_of_shell(int q) {
-    for (int r = 0; r < q; ++r)
-        if (SH::sh[r] == SH::sh[q]) return false;
-    return true;
-}
-
 // Field of one site from its 3 x 3 x 3 neighbourhood in LDS: bm, b0 and bp
 // point at cell (-1, -1) of the site's row in the planes below, at and above
 // it (row pitch W), so every neighbour is a non-negative compile-time offset
