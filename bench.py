@@ -421,10 +421,13 @@ def bench_surrogate(args) -> dict:
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     tex = torch.tensor(film_textures(geo, ntr + nte, 11354), device="cuda").contiguous()
+    print(f"[bench] dipole: {ntr + nte} textures generated ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+          flush=True)
     with torch.cuda.stream(stream):
         relax_textures(f, tex)
     torch.cuda.synchronize()
     data_s = time.perf_counter() - t0
+    print(f"[bench] dipole: every third texture relaxed ({data_s:.1f} s)", file=sys.stderr, flush=True)
     lab = torch.zeros_like(tex)
     ev0.record(stream)
     e.ddi_label_dev(ntr + nte, tex, lab)
@@ -433,8 +436,11 @@ def bench_surrogate(args) -> dict:
     ms_direct = ev0.elapsed_time(ev1) / (ntr + nte)
     e.ddi_init_residual([12, 32, 32, 32, 12], seed=11354, block=4, reach=2)
     t0 = time.perf_counter()
+    print(f"[bench] dipole: labels from the direct sum ({ms_direct:.3f} ms per field); training", file=sys.stderr,
+          flush=True)
     losses = e.ddi_train_dev(ntr, tex[:ntr], lab[:ntr], epochs=args.sur_epochs, batch=8, lr=args.sur_lr, seed=1)
     train_s = time.perf_counter() - t0
+    print(f"[bench] dipole: trained ({train_s:.1f} s)", file=sys.stderr, flush=True)
     test = tex[ntr:].contiguous()
     pred, base = torch.zeros_like(test), torch.zeros_like(test)
     e.ddi_forward_dev(nte, test, pred)
@@ -682,9 +688,9 @@ def main():
     ap.add_argument("--sur-steps", type=int, default=20)
     ap.add_argument("--config1-steps", type=int, default=2000)
     ap.add_argument("--batch", action="store_true", help="(default with the extras; kept for old command lines)")
-    ap.add_argument("--batch-steps", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=1024)
     ap.add_argument("--batch-chunk", type=int, default=32)
-    ap.add_argument("--gneb-iters", type=int, default=200)
+    ap.add_argument("--gneb-iters", type=int, default=1000)
     ap.add_argument("--basis", action="store_true", help="(default with the extras) lattices with a basis only")
     ap.add_argument("--basis-steps", type=int, default=500)
     ap.add_argument("--stencil", action="store_true", help="(default with the extras; kept for old command lines)")
