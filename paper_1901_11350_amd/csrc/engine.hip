@@ -685,45 +685,55 @@ sp::SiteB<T> make_siteb(const sp_engine* e, const sp_llg_params* p) {
     return Q;
 }
 
-template <typename T, int TX, int TY, int TZ, int R, int RC, int NB>
+template <typename T, int TX, int TY, int TZ, int R, int RC, int NB, int SOLVER>
 void launch_tile_k(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     const dim3 grid((unsigned)((e->geo.n[0] + TX - 1) / TX), (unsigned)((e->geo.n[1] + TY - 1) / TY),
                     (unsigned)((e->geo.n[2] + TZ - 1) / TZ));
     constexpr int WN = TX + 4 * R, HN = TY + 4 * R, DN = TZ + 4 * RC;
     constexpr int WP = TX + 2 * R, HP = TY + 2 * R, DP = TZ + 2 * RC;
-    hipLaunchKernelGGL((sp::k_fused_tile<T, TX, TY, TZ, R, RC, NB>), grid, dim3(NB * TX * TY * TZ), 0, e->stream,
+    hipLaunchKernelGGL((sp::k_fused_tile<T, TX, TY, TZ, R, RC, NB, SOLVER>), grid, dim3(NB * TX * TY * TZ), 0, e->stream,
                        make_stencilb<T>(e, WN, HN, WN * HN * DN, WP, HP, WP * HP * DP), make_siteb<T>(e, p),
                        make_step_llg<T>(e, p, step), e->d_flag,
                        static_cast<const T*>(nin), static_cast<T*>(nout));
 }
 
-template <typename T, int R>
+template <typename T, int R, int SOLVER>
 void go_tile2d(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     constexpr bool f32 = sizeof(T) == 4;
     switch (e->geo.nb) {
-        case 2: launch_tile_k<T, f32 ? 32 : 16, 16, 1, R, 0, 2>(e, p, step, nin, nout); break;
-        case 3: launch_tile_k<T, 16, f32 ? 16 : 8, 1, R, 0, 3>(e, p, step, nin, nout); break;
-        default: launch_tile_k<T, 16, f32 ? 16 : 8, 1, R, 0, 4>(e, p, step, nin, nout); break;
+        case 2: launch_tile_k<T, f32 ? 32 : 16, 16, 1, R, 0, 2, SOLVER>(e, p, step, nin, nout); break;
+        case 3: launch_tile_k<T, 16, f32 ? 16 : 8, 1, R, 0, 3, SOLVER>(e, p, step, nin, nout); break;
+        default: launch_tile_k<T, 16, f32 ? 16 : 8, 1, R, 0, 4, SOLVER>(e, p, step, nin, nout); break;
+    }
+}
+
+template <typename T, int SOLVER>
+void go_fused_tile(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
+    if (e->geo.n[2] == 1) {
+        if (e->R <= 1) go_tile2d<T, 1, SOLVER>(e, p, step, nin, nout);
+        else go_tile2d<T, 2, SOLVER>(e, p, step, nin, nout);
+        return;
+    }
+    if constexpr (sizeof(T) == 4) {
+        switch (e->geo.nb) {
+            case 1: launch_tile_k<T, 16, 8, 4, 1, 1, 1, SOLVER>(e, p, step, nin, nout); break;
+            case 2: launch_tile_k<T, 16, 8, 4, 1, 1, 2, SOLVER>(e, p, step, nin, nout); break;
+            default: launch_tile_k<T, 8, 8, 4, 1, 1, 3, SOLVER>(e, p, step, nin, nout); break;
+        }
+    } else {
+        if (e->geo.nb == 1) launch_tile_k<T, 8, 8, 4, 1, 1, 1, SOLVER>(e, p, step, nin, nout);
+        else launch_tile_k<T, 8, 8, 4, 1, 1, 2, SOLVER>(e, p, step, nin, nout);
     }
 }
 
 template <typename T>
 void launch_tile(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
-    if (e->geo.n[2] == 1) {
-        if (e->R <= 1) go_tile2d<T, 1>(e, p, step, nin, nout);
-        else go_tile2d<T, 2>(e, p, step, nin, nout);
-        return;
-    }
-    if constexpr (sizeof(T) == 4) {
-        switch (e->geo.nb) {
-            case 1: launch_tile_k<T, 16, 8, 4, 1, 1, 1>(e, p, step, nin, nout); break;
-            case 2: launch_tile_k<T, 16, 8, 4, 1, 1, 2>(e, p, step, nin, nout); break;
-            default: launch_tile_k<T, 8, 8, 4, 1, 1, 3>(e, p, step, nin, nout); break;
-        }
-    } else {
-        if (e->geo.nb == 1) launch_tile_k<T, 8, 8, 4, 1, 1, 1>(e, p, step, nin, nout);
-        else launch_tile_k<T, 8, 8, 4, 1, 1, 2>(e, p, step, nin, nout);
-    }
+    if (p->solver == SP_SOLVER_HEUN)
+        go_fused_tile<T, sp::SOLVER_HEUN>(e, p, step, nin, nout);
+    else if (p->solver == SP_SOLVER_SIB)
+        go_fused_tile<T, sp::SOLVER_SIB>(e, p, step, nin, nout);
+    else
+        go_fused_tile<T, sp::SOLVER_DEPONDT>(e, p, step, nin, nout);
 }
 
 // ------------------------------------------- compile-time-shape fused path
@@ -1096,7 +1106,7 @@ int launch_step(sp_engine* e, const sp_llg_params* p, uint64_t step, const void*
         HIPCHK(e, hipGetLastError());
         return SP_OK;
     }
-    if (std::strcmp(e->path, "fusedtile") == 0 && p->solver == SP_SOLVER_DEPONDT) {
+    if (std::strcmp(e->path, "fusedtile") == 0) {
         launch_tile<T>(e, p, step, nin, nout);
         HIPCHK(e, hipGetLastError());
         return SP_OK;
@@ -2299,16 +2309,17 @@ int sp_autotune(sp_engine* e, const sp_llg_params* p, int n_steps, double* ms_pe
     if (n_steps < 1 || n_steps > 100000) return fail(e, SP_E_ARG, "n_steps must be in 1..100000");
     (void)hipSetDevice(e->device);
     std::vector<std::string> cands{"twopass"};
+    if (e->tile_ok) cands.push_back("fusedtile");
     if (e->shape3 >= 0)
         for (int k = 0; k < kNumTile3Cfgs; ++k)
             if (e->precision != SP_F64 || k == 1 || k == 3) cands.push_back(std::string("shape3d/") + kTile3Cfgs[k].name);
     if (p->solver != SP_SOLVER_DEPONDT) {
-        // Heun and SIB: the two-pass kernels or the one tile shape they are built for
+        // Heun and SIB: the two-pass kernels, the fused tile or the one tile shape they are built for
         if (e->shape >= 0)
             cands.push_back(std::string("shape2d/") + (e->precision == SP_F64 ? kSolverTileF64 : kSolverTileF32));
     } else {
         if (e->fused_ok) cands.push_back("fused2d");
-        if (e->tile_ok) cands.push_back("fusedtile");
+
         if (e->shape >= 0) {
             const int ncfg = e->precision == SP_F64 ? kNumTileCfgsF64 : kNumTileCfgs;
             for (int k = 0; k < ncfg; ++k) cands.push_back(std::string("shape2d/") + kTileCfgs[k].name);

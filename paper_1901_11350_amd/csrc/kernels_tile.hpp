@@ -3,6 +3,8 @@
 // bond table; also 3D one-atom lattices whose bonds match no compile-time
 // stencil.
 //
+// Depondt, Heun or SIB (template SOLVER), as the other fused kernels.
+//
 // Sites are stored basis-major, i = a + Na (b + Nb (c + Nc beta)), so every
 // basis atom is a block of its own.  A workgroup owns a TX x TY x TZ tile of
 // cells and all NB atoms in it, one thread per owned site (NB * TX * TY * TZ
@@ -133,7 +135,26 @@ __device__ __forceinline__ void tile_ring_cell(int h, int& px, int& py, int& pz)
     }
 }
 
-template <typename T, int TX, int TY, int TZ, int R, int RC, int NB>
+// One predictor of a cell with field g and thermal field Bth: the spin the
+// corrector's field is evaluated on, and (returned through keep) what the
+// corrector needs of the site: Depondt n^p = R(A) n, keeps A; Heun
+// n^p = (n + dt n x A)/|...|, keeps n x A; SIB the midpoint of the
+// implicit stage with A frozen (Appendix C).
+template <typename T, int SOLVER>
+__device__ __forceinline__ V3<T> tile_predict(V3<T> ni, V3<T> B, const LLGArgs<T>& A, V3<T>& keep) {
+    const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
+    if constexpr (SOLVER == SOLVER_HEUN) {
+        keep = cross(ni, Ai);
+        return normalize3(ni + A.dt * keep);
+    } else if constexpr (SOLVER == SOLVER_SIB) {
+        return T(0.5) * (ni + sib_stage(ni, Ai, A.dt));
+    } else {
+        keep = Ai;
+        return rotate_fast(ni, T(-1) * Ai, A.dt);
+    }
+}
+
+template <typename T, int TX, int TY, int TZ, int R, int RC, int NB, int SOLVER>
 __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S, SiteB<T> Q, LLGArgs<T> A_arg,
                                                                   const int* __restrict__ abort_flag,
                                                                   const T* __restrict__ n, T* __restrict__ nout) {
@@ -192,7 +213,7 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
     __syncthreads();
 
     // 2) predictor: the owned site, then the ring
-    V3<T> Ai{T(0), T(0), T(0)};
+    V3<T> keep{T(0), T(0), T(0)};
     {
         const int pc = ((tz + RC) * HP + (ty + R)) * WP + (tx + R);
         V4<T> out{T(0), T(0), T(0), T(0)};
@@ -200,9 +221,7 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
             const int c = ((tz + 2 * RC) * HN + (ty + 2 * R)) * WN + (tx + 2 * R);
             const V3<T> ni = lds_cell_xyz(sN, beta * PN + c);
             const V3<T> g = tile_field(S, Q, beta, sN, S.offN, c, ni);
-            const V3<T> B = (-Q.inv_mumuB[beta]) * g + Bth;
-            Ai = llg_A(ni, B, A.gp, A.alpha);
-            const V3<T> o = rotate_fast(ni, T(-1) * Ai, A.dt);
+            const V3<T> o = tile_predict<T, SOLVER>(ni, (-Q.inv_mumuB[beta]) * g + Bth, A, keep);
             out = V4<T>{o.x, o.y, o.z, T(0)};
         }
         sP[beta * PP + pc] = out;
@@ -223,8 +242,8 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
                 const uint32_t site = (uint32_t)(gx + na * (gy + nbc * gz) + b * block);
                 B = B + Q.sigma[b] * normals3(thermal_bits(A.key, site), T(0));
             }
-            const V3<T> Ar = llg_A(ni, B, A.gp, A.alpha);
-            const V3<T> o = rotate_fast(ni, T(-1) * Ar, A.dt);
+            V3<T> unused;
+            const V3<T> o = tile_predict<T, SOLVER>(ni, B, A, unused);
             out = V4<T>{o.x, o.y, o.z, T(0)};
         }
         sP[b * PP + ((pz * HP) + py) * WP + px] = out;
@@ -238,9 +257,16 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
     const V3<T> g = tile_field(S, Q, beta, sP, S.offP, pc, npi);
     const V3<T> B = (-Q.inv_mumuB[beta]) * g + Bth;
     const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
-    const V3<T> w{T(-0.5) * (Ai.x + Ap.x), T(-0.5) * (Ai.y + Ap.y), T(-0.5) * (Ai.z + Ap.z)};
     const V3<T> ni = lds_cell_xyz(sN, beta * PN + ((tz + 2 * RC) * HN + (ty + 2 * R)) * WN + (tx + 2 * R));
-    const V3<T> o = renorm_if_float(rotate_fast(ni, w, A.dt));
+    V3<T> o;
+    if constexpr (SOLVER == SOLVER_HEUN) {
+        o = normalize3(ni + (T(0.5) * A.dt) * (keep + cross(npi, Ap)));
+    } else if constexpr (SOLVER == SOLVER_SIB) {
+        o = renorm_if_float(sib_stage(ni, Ap, A.dt));
+    } else {
+        const V3<T> w{T(-0.5) * (keep.x + Ap.x), T(-0.5) * (keep.y + Ap.y), T(-0.5) * (keep.z + Ap.z)};
+        o = renorm_if_float(rotate_fast(ni, w, A.dt));
+    }
     const int gi = ox + na * (oy + nbc * oz) + beta * block;
     store_out(nout + gi, o.x);
     store_out(nout + N + gi, o.y);

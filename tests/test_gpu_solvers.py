@@ -134,3 +134,35 @@ def test_batches_reject_other_solvers():
     with pytest.raises(SpError):
         b._check(lib().sp_batch_add(b._h, e._h, ctypes.byref(p)))
     assert b.add(e, 0.3, 0.001) == 0
+
+
+TILE_CASES = {
+    "honeycomb41x19_4shell": (si.honeycomb(41, 19),
+                              si.Hamiltonian(mu=(2.0, 2.5), B=(0.1, -0.2, 0.5), K=(0.1, 0.05),
+                                             K_axis=((0, 0, 1), (0.6, 0.0, 0.8)), J=(1.0, 0.2, -0.1, 0.05),
+                                             D=(0.15,))),
+    "kagome24x19_open": (si.kagome(24, 19, periodic=(1, 0, 0)),
+                         si.Hamiltonian(mu=(2.0, 2.0, 3.0), B=(0.0, 0.0, 0.4), K=(0.1, 0.1, 0.2),
+                                        K_axis=((0, 0, 1),) * 3, J=(1.0, -0.2, 0.1), D=(0.1,))),
+    "basis2": (BASIS2_GEO, BASIS2_HAM),
+}
+
+
+@pytest.mark.parametrize("solver", ["heun", "sib"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(TILE_CASES))
+def test_solver_fused_tile_matches_oracle(ora, case, precision, solver):
+    """Heun and SIB on the fused tile path of lattices with a basis (and on
+    the two-pass kernels) against the oracle's 4-step stochastic trajectory."""
+    geo, ham = TILE_CASES[case]
+    announce(f"{solver} fused tile {case} {precision}")
+    e, s = make_pair(ora, geo, ham, precision)
+    assert e.step_path == "fusedtile"
+    n0 = si.uniform_sphere(s.N, 31)
+    n_ora, _ = s.run(n0, 0.3, 0.001, 4, T=25.0, seed=77, step0=5, solver=solver)
+    for path in ["fusedtile", "twopass"]:
+        e.step_path = path
+        e.set_spins(n0)
+        e.step = 5
+        e.run(0.3, 0.001, 4, T=25.0, seed=77, solver=solver)
+        assert_close(e.get_spins(), n_ora, precision, what=f"{solver} {path} {case}")
