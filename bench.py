@@ -306,6 +306,34 @@ def bench_stencil(args) -> dict:
         e.close()
         del g, e
         torch.cuda.empty_cache()
+    # a lattice with a basis beyond the last-level cache: the honeycomb
+    # (three shells, interfacial DMI) of 4096 x 2048 cells, 16.8M spins, on
+    # the LDS-tiled field of the fused tile path
+    w = basis_workloads()[0]
+    e = pk.Engine(0, "f32", stream=stream)
+    e.set_geometry(w.geometry.with_cells((4096, 2048, 1)))
+    e.set_hamiltonian(w.hamiltonian)
+    e.set_spins_dev(torch.nn.functional.normalize(
+        torch.randn((3, e.N), generator=torch.Generator().manual_seed(5)), dim=0).to("cuda"))
+    g = torch.empty((3, e.N), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        e.gradient_dev(g)
+    torch.cuda.synchronize()
+    K = args.stencil_launches
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(K):
+        e.gradient_dev(g)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t = ev0.elapsed_time(ev1) * 1e-3 / K
+    gbps = 24.0 * e.N / t / 1e9
+    out["honeycomb4096x2048_probe"] = {"n_sites": e.N, "us_per_launch": t * 1e6, "hbm_gbps_algorithmic": gbps,
+                                       "hbm_frac": gbps / HBM_PEAK_GBPS, "kernel": "k_gradient_tile",
+                                       "launches": K, "step_path": e.step_path}
+    e.close()
+    del g, e
+    torch.cuda.empty_cache()
     return out
 
 

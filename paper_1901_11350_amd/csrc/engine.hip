@@ -736,6 +736,48 @@ void launch_tile(sp_engine* e, const sp_llg_params* p, uint64_t step, const void
         go_fused_tile<T, sp::SOLVER_DEPONDT>(e, p, step, nin, nout);
 }
 
+template <typename T, int TX, int TY, int TZ, int R, int RC, int NB>
+void launch_gradient_tile_k(sp_engine* e, const void* n, void* g) {
+    const dim3 grid((unsigned)((e->geo.n[0] + TX - 1) / TX), (unsigned)((e->geo.n[1] + TY - 1) / TY),
+                    (unsigned)((e->geo.n[2] + TZ - 1) / TZ));
+    constexpr int WN = TX + 2 * R, HN = TY + 2 * R, DN = TZ + 2 * RC;
+    hipLaunchKernelGGL((sp::k_gradient_tile<T, TX, TY, TZ, R, RC, NB>), grid, dim3(NB * TX * TY * TZ), 0, e->stream,
+                       make_stencilb<T>(e, WN, HN, WN * HN * DN, WN, HN, WN * HN * DN), make_siteb<T>(e, nullptr),
+                       static_cast<const T*>(n), static_cast<T*>(g));
+}
+
+// The field of a lattice the fused tile path takes, on the same tiles.
+template <typename T>
+void launch_gradient_tile(sp_engine* e, const void* n, void* g) {
+    constexpr bool f32 = sizeof(T) == 4;
+    if (e->geo.n[2] == 1) {
+        if (e->R <= 1) {
+            switch (e->geo.nb) {
+                case 2: launch_gradient_tile_k<T, f32 ? 32 : 16, 16, 1, 1, 0, 2>(e, n, g); break;
+                case 3: launch_gradient_tile_k<T, 16, f32 ? 16 : 8, 1, 1, 0, 3>(e, n, g); break;
+                default: launch_gradient_tile_k<T, 16, f32 ? 16 : 8, 1, 1, 0, 4>(e, n, g); break;
+            }
+        } else {
+            switch (e->geo.nb) {
+                case 2: launch_gradient_tile_k<T, f32 ? 32 : 16, 16, 1, 2, 0, 2>(e, n, g); break;
+                case 3: launch_gradient_tile_k<T, 16, f32 ? 16 : 8, 1, 2, 0, 3>(e, n, g); break;
+                default: launch_gradient_tile_k<T, 16, f32 ? 16 : 8, 1, 2, 0, 4>(e, n, g); break;
+            }
+        }
+        return;
+    }
+    if constexpr (f32) {
+        switch (e->geo.nb) {
+            case 1: launch_gradient_tile_k<T, 16, 8, 4, 1, 1, 1>(e, n, g); break;
+            case 2: launch_gradient_tile_k<T, 16, 8, 4, 1, 1, 2>(e, n, g); break;
+            default: launch_gradient_tile_k<T, 8, 8, 4, 1, 1, 3>(e, n, g); break;
+        }
+    } else {
+        if (e->geo.nb == 1) launch_gradient_tile_k<T, 8, 8, 4, 1, 1, 1>(e, n, g);
+        else launch_gradient_tile_k<T, 8, 8, 4, 1, 1, 2>(e, n, g);
+    }
+}
+
 // ------------------------------------------- compile-time-shape fused path
 struct TileCfg {
     const char* name;
@@ -1324,6 +1366,11 @@ int gradient_dev(sp_engine* e, const void* n, void* g) {
             case sp::SH_TRI2: go_gradient_shape<T, sp::SH_TRI2>(e, n, g); break;
             default: go_gradient_shape<T, sp::SH_TRI3>(e, n, g); break;
         }
+        HIPCHK(e, hipGetLastError());
+        return SP_OK;
+    }
+    if (e->tile_ok) {   // lattices with a basis: LDS tiles (no dipole, no on-site potentials)
+        launch_gradient_tile<T>(e, n, g);
         HIPCHK(e, hipGetLastError());
         return SP_OK;
     }

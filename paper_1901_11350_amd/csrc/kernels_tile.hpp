@@ -273,4 +273,56 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
     store_out(nout + 2 * N + gi, o.z);
 }
 
+// Stand-alone field g = dH/dn (sp_gradient) of the same lattices: every
+// atom's tile plus an (R, R, RC) halo staged in LDS as 16-byte cells, every
+// load issued before the first LDS write, one thread per owned site; one
+// read of n and one write of g per site (24 B per FP32 site).
+template <typename T, int TX, int TY, int TZ, int R, int RC, int NB>
+__global__ void __launch_bounds__(NB * TX * TY * TZ) k_gradient_tile(StencilB<T> S, SiteB<T> Q,
+                                                                     const T* __restrict__ n, T* __restrict__ g) {
+    constexpr int WN = TX + 2 * R, HN = TY + 2 * R, DN = TZ + 2 * RC;
+    constexpr int PN = WN * HN * DN, PT = TX * TY * TZ, NT = NB * PT;
+    constexpr int KS = (NB * PN + NT - 1) / NT;
+    static_assert(PT % 64 == 0, "a tile must hold whole wavefronts of each atom");
+    __shared__ V4<T> sN[NB * PN];
+    const int na = Q.n[0], nbc = Q.n[1], nc = Q.n[2];
+    const int block = na * nbc * nc;
+    const int N = block * NB;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+    const int tid = threadIdx.x;
+    V3<T> ld[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int idx = tid + k * NT;
+        ld[k] = V3<T>{T(0), T(0), T(0)};
+        if (idx < NB * PN) {
+            const int b = idx / PN, r = idx - b * PN;
+            const int lz = r / (WN * HN), rr = r - lz * (WN * HN);
+            const int ly = rr / WN, lx = rr - ly * WN;
+            int gx = x0 - R + lx, gy = y0 - R + ly, gz = z0 - RC + lz;
+            if (tile_coord(gx, na, Q.per[0]) & tile_coord(gy, nbc, Q.per[1]) & tile_coord(gz, nc, Q.per[2])) {
+                const int gi = gx + na * (gy + nbc * gz) + b * block;
+                ld[k] = V3<T>{n[gi], n[N + gi], n[2 * N + gi]};
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int idx = tid + k * NT;
+        if (idx < NB * PN) sN[idx] = V4<T>{ld[k].x, ld[k].y, ld[k].z, T(0)};
+    }
+    __syncthreads();
+    const int beta = __builtin_amdgcn_readfirstlane(tid / PT), t = tid - beta * PT;
+    const int tz = t / (TX * TY), tr = t - tz * (TX * TY);
+    const int ty = tr / TX, tx = tr - ty * TX;
+    const int ox = x0 + tx, oy = y0 + ty, oz = z0 + tz;
+    if (ox >= na || oy >= nbc || oz >= nc) return;
+    const int c = ((tz + RC) * HN + (ty + R)) * WN + (tx + R);
+    const V3<T> gv = tile_field(S, Q, beta, sN, S.offN, c, lds_cell_xyz(sN, beta * PN + c));
+    const int gi = ox + na * (oy + nbc * oz) + beta * block;
+    store_out(g + gi, gv.x);
+    store_out(g + N + gi, gv.y);
+    store_out(g + 2 * N + gi, gv.z);
+}
+
 }  // namespace sp

@@ -500,13 +500,15 @@ def test_fused_tile_path_matches_oracle(ora, case, precision):
     """Lattices with a basis (2D: two to four atoms, reach 1 and 2, ragged
     and open edges; 3D: two atoms, open and periodic c) and a 3D one-atom
     lattice without a compile-time stencil take the fused tile path by
-    default; its 4-step stochastic trajectory matches the oracle's, and the
-    two-pass path's."""
+    default; the field on its tiles and its 4-step stochastic trajectory
+    match the oracle's, and the trajectory the two-pass path's."""
     geo, ham = TILE_CASES[case]
     announce(f"fused tile {case} {precision}")
     e, s = make_pair(ora, geo, ham, precision)
     assert e.step_path == "fusedtile", e.step_path
     n0 = si.uniform_sphere(s.N, 31)
+    e.set_spins(n0)
+    assert_close(e.gradient(), s.gradient(n0), precision, what=f"gradient on tiles {case}")
     ref, _ = s.run(n0, 0.3, 0.001, 4, T=20.0, seed=13, step0=3)
     res = {}
     for path in ["fusedtile", "twopass"]:
