@@ -158,10 +158,15 @@ const char *sp_last_error(const sp_engine *e);
 
 /* Metropolis sweeps with cone trial moves (Sec. III.B).  The paper's sweep
  * picks every spin once, sequentially in random order; here a sweep tries
- * every site once as a checkerboard, first the sites with a + b + c even,
- * then the odd ones (sites of one colour share no bond, so a colour updates
- * in parallel and every trial sees the current state of its neighbours):
- * the same Boltzmann distribution, sampled by another schedule.
+ * every site once, colour after colour, with a periodic colouring of the
+ * sites -- site (a, b, c, beta) takes the colour of its class
+ * (a mod ma, b mod mb, c mod mc, beta), periods 1-6 per axis dividing the
+ * length of each periodic axis, classes coloured by DSATUR on the quotient
+ * graph of the bonds, fewest colours chosen -- so that no bond joins two
+ * sites of one colour (the checkerboard for the simple-cubic nearest-
+ * neighbour lattice): a colour updates in parallel and every trial sees the
+ * current state of its neighbours; the same Boltzmann distribution,
+ * sampled by another schedule.
  * Trial at site i of sweep s: Philox block of counter (i, s_lo, s_hi,
  * replica) and key (seed_lo, seed_hi), u_k = (x_k + 1/2) 2^-32; phi = 2 pi u0,
  * cos(theta) = 1 - u1 (1 - cos(cone)); new spin cos(theta) n +
@@ -175,8 +180,9 @@ const char *sp_last_error(const sp_engine *e);
  * every sweep with acceptance ratio a the cone is multiplied by
  * 1 + a - target_acceptance, at most 180 degrees, on the device; *cone_out
  * (may be NULL) receives the cone after the last sweep.
- * Needs a one-atom basis, bonds that join the two colours, even lengths on
- * periodic axes and no dipole term (SP_E_UNSUPPORTED otherwise).  obs
+ * Any basis; needs no dipole term and a colouring within those periods
+ * (SP_E_UNSUPPORTED otherwise, e.g. a periodic axis too short for its
+ * bonds).  obs
  * receives n_sweeps / observe_every observations (observe_every = 0: none);
  * *accepted (may be NULL) the accepted trials of the run. */
 int sp_mc_run(sp_engine *e, const sp_mc_params *p, int64_t n_sweeps, int64_t observe_every,

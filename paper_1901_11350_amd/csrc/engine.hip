@@ -121,6 +121,9 @@ struct sp_engine {
     int shape3_dk = 0;                // sp::Dmi3 of the streamed step kernel
     int tile3_cfg = 0;                // index into the 3D tile configurations
     int persist_cfg = 0;              // index into the persistent-path tile configurations
+    std::vector<unsigned char> mc_col;  // Metropolis colour of each (cell class, atom)
+    int mc_m[3] = {1, 1, 1};            // periods of the colouring
+    int mc_ncol = 0;
     std::string path_label;
 
     size_t esz() const { return precision == SP_F64 ? 8 : 4; }
@@ -1579,16 +1582,88 @@ int run_impl(sp_engine* e, const sp_llg_params* p, int64_t n_steps, int64_t obse
 }
 
 // ------------------------------------------------------------ Monte Carlo
-int mc_admissible(sp_engine* e) {
+// Colours of a graph by DSATUR (always the uncoloured vertex with the most
+// distinct colours among its neighbours, ties to the higher degree, then
+// the lower index; it takes the smallest colour free there).  Returns the
+// number of colours.
+int dsatur(const std::vector<std::vector<int>>& adj, std::vector<int>& col) {
+    const int n = (int)adj.size();
+    col.assign(n, -1);
+    std::vector<std::set<int>> seen(n);
+    int ncol = 0;
+    for (int step = 0; step < n; ++step) {
+        int v = -1;
+        for (int u = 0; u < n; ++u) {
+            if (col[u] >= 0) continue;
+            if (v < 0 || seen[u].size() > seen[v].size() ||
+                (seen[u].size() == seen[v].size() && adj[u].size() > adj[v].size()))
+                v = u;
+        }
+        int c = 0;
+        while (seen[v].count(c)) ++c;
+        col[v] = c;
+        ncol = std::max(ncol, c + 1);
+        for (int u : adj[v]) seen[u].insert(c);
+    }
+    return ncol;
+}
+
+// Periodic colouring of the sites for the Metropolis sweep: site
+// (a, b, c, beta) takes colour col[((a mod ma) mb + b mod mb) mc + c mod mc][beta],
+// with periods 1-6 per axis (dividing the length of a periodic axis) such
+// that no bond joins two sites of one colour: the quotient graph of the
+// bonds on the ma x mb x mc x n_basis classes must have no loop, and is
+// coloured by DSATUR; the periods giving the fewest colours win (ties to
+// the smaller period product).
+int mc_plan(sp_engine* e) {
     const HostGeo& g = e->geo;
-    if (g.nb != 1) return fail(e, SP_E_UNSUPPORTED, "Monte Carlo sweeps need a one-atom basis");
     if (e->ham.ddi) return fail(e, SP_E_UNSUPPORTED, "Monte Carlo sweeps do not support the dipole term");
+    std::vector<int> cand[3];
     for (int k = 0; k < 3; ++k)
-        if (g.per[k] && g.n[k] > 1 && (g.n[k] % 2))
-            return fail(e, SP_E_UNSUPPORTED, "Monte Carlo sweeps need even lengths on periodic axes");
-    for (const HostBond& b : e->all_bonds)
-        if ((((b.d[0] + b.d[1] + b.d[2]) % 2) + 2) % 2 != 1)
-            return fail(e, SP_E_UNSUPPORTED, "a bond joins two sites of the same checkerboard colour");
+        for (int m = 1; m <= 6; ++m)
+            if (m <= g.n[k] && (!g.per[k] || g.n[k] % m == 0)) cand[k].push_back(m);
+    int best = 1 << 30, best_prod = 1 << 30;
+    for (int ma : cand[0])
+        for (int mb : cand[1])
+            for (int mc : cand[2]) {
+                const int cells = ma * mb * mc, nodes = cells * g.nb;
+                std::vector<std::vector<int>> adj(nodes);
+                bool ok = true;
+                for (int ia = 0; ia < ma && ok; ++ia)
+                    for (int ib = 0; ib < mb && ok; ++ib)
+                        for (int ic = 0; ic < mc && ok; ++ic)
+                            for (int beta = 0; beta < g.nb && ok; ++beta) {
+                                const int u = ((ia * mb + ib) * mc + ic) * g.nb + beta;
+                                for (int q = e->bstart[beta]; q < e->bstart[beta + 1]; ++q) {
+                                    const HostBond& b = e->bonds[q];
+                                    const int ja = ((ia + b.d[0]) % ma + ma) % ma;
+                                    const int jb = ((ib + b.d[1]) % mb + mb) % mb;
+                                    const int jc = ((ic + b.d[2]) % mc + mc) % mc;
+                                    const int v = ((ja * mb + jb) * mc + jc) * g.nb + b.bj;
+                                    if (v == u) {
+                                        ok = false;
+                                        break;
+                                    }
+                                    adj[u].push_back(v);
+                                    adj[v].push_back(u);
+                                }
+                            }
+                if (!ok) continue;
+                std::vector<int> col;
+                const int K = dsatur(adj, col);
+                if (K < best || (K == best && cells < best_prod)) {
+                    best = K;
+                    best_prod = cells;
+                    e->mc_m[0] = ma;
+                    e->mc_m[1] = mb;
+                    e->mc_m[2] = mc;
+                    e->mc_col.assign(col.begin(), col.end());
+                }
+            }
+    if (best == (1 << 30))
+        return fail(e, SP_E_UNSUPPORTED,
+                    "no periodic colouring with periods up to 6 keeps bonded sites apart (lattice too short?)");
+    e->mc_ncol = best;
     return SP_OK;
 }
 
@@ -1603,13 +1678,18 @@ int mc_run_impl(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t o
     }
     const unsigned blocks = blocks_for(e->N);
     unsigned int* acc = nullptr;
-    if ((rc = dalloc(e, acc, blocks * sizeof(unsigned int)))) return rc;
+    if ((rc = dalloc(e, acc, blocks * sizeof(unsigned int) + e->mc_col.size()))) return rc;
     HIPCHK(e, hipMemsetAsync(acc, 0, blocks * sizeof(unsigned int), e->stream));
+    // the colour table rides behind the acceptance counts
+    unsigned char* col = reinterpret_cast<unsigned char*>(acc + blocks);
+    HIPCHK(e, hipMemcpyAsync(col, e->mc_col.data(), e->mc_col.size(), hipMemcpyHostToDevice, e->stream));
     const sp::Lattice L = make_lattice(e);
     // decisions in FP64 for every engine precision: FP64 couplings
     const sp::BondCoef<double> C = make_coef64(e);
     const sp::Phys<double> P = make_phys<double>(e, nullptr);
     sp::McArgs<double> M{};
+    M.col = col;
+    for (int q = 0; q < 3; ++q) M.cm[q] = e->mc_m[q];
     M.kT = kKB * p->T_K;
     M.cos_cone = std::cos(p->cone_deg * M_PI / 180.0);
     double* state = nullptr;   // adaptive cone: (cone, accepted count at the previous sweep)
@@ -1628,7 +1708,7 @@ int mc_run_impl(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t o
     for (int64_t t = 0; t < n_sweeps; ++t) {
         M.key.step_lo = (uint32_t)e->step;
         M.key.step_hi = (uint32_t)(e->step >> 32);
-        for (int colour = 0; colour < 2; ++colour) {
+        for (int colour = 0; colour < e->mc_ncol; ++colour) {
             M.colour = colour;
             hipLaunchKernelGGL((sp::k_mc_colour<T>), dim3(blocks), dim3(256), 0, e->stream, L, C, P, M,
                                static_cast<T*>(e->d_n), acc);
@@ -1757,7 +1837,7 @@ int sp_mc_run(sp_engine* e, const sp_mc_params* p, int64_t n_sweeps, int64_t obs
         return fail(e, SP_E_ARG, "target acceptance must be in [0, 1)");
     if (n_sweeps < 0 || observe_every < 0) return fail(e, SP_E_ARG, "n_sweeps and observe_every must be >= 0");
     if (observe_every > 0 && n_sweeps / observe_every > 0 && !obs) return fail(e, SP_E_ARG, "obs is NULL");
-    if ((rc = mc_admissible(e))) return rc;
+    if ((rc = mc_plan(e))) return rc;
     (void)hipSetDevice(e->device);
     if (cone_out) *cone_out = p->cone_deg;
     return DISPATCH(e, mc_run_impl, e, p, n_sweeps, observe_every, obs, accepted, cone_out);

@@ -1,11 +1,14 @@
 // kernels_mc.hpp -- Metropolis Monte Carlo with cone trial moves (Sec. III.B).
 // The paper's sweep picks every spin once, one after another, in random
-// order.  Here a sweep is a two-colour (checkerboard) pass: sites with
-// a + b + c of one parity share no bond, so one launch updates a whole
-// colour in parallel; every site is still tried once per sweep and each
-// trial sees the current state of every spin it interacts with, so the
-// chain samples the same Boltzmann distribution (checked statistically
-// against the sequential random-order sweep).
+// order.  Here a sweep is a multi-colour pass: the host colours the sites
+// periodically -- colour(i) = table[a mod ma][b mod mb][c mod mc][beta] --
+// so that no bond joins two sites of one colour (two colours, the
+// checkerboard, for the simple-cubic nearest-neighbour lattice; three or
+// more for triangular, second-neighbour or basis lattices), and one launch
+// updates a whole colour in parallel; every site is still tried once per
+// sweep and each trial sees the current state of every spin it interacts
+// with, so the chain samples the same Boltzmann distribution (checked
+// statistically against the sequential random-order sweep).
 //
 // Trial at site i of sweep s: Philox block of counter (i, s_lo, s_hi,
 // replica), u_k = (x_k + 1/2) 2^-32; phi = 2 pi u0, cos(theta) = 1 - u1 (1 -
@@ -30,6 +33,8 @@ struct McArgs {
     ThermalKey key;  // seed, sweep number (step words), replica
     int colour;
     const double* cone_dev;   // adaptive cone (degrees) on the device, or null: cos_cone
+    const unsigned char* col; // colour of (a mod cm[0], b mod cm[1], c mod cm[2], beta), row-major
+    int cm[3];
 };
 
 template <typename T>
@@ -63,7 +68,7 @@ __device__ __forceinline__ V3<T> mc_trial(V3<T> n, const T u[3], T cos_cone) {
                  ct * n.z + st * (cp * e1.z + sp * e2.z)};
 }
 
-// One colour of one sweep (one-atom basis).  acc_part[block] accumulates the
+// One colour of one sweep.  acc_part[block] accumulates the
 // accepted trials of this workgroup's sites over the launches of a run.
 // The accept/reject decision is taken in FP64 for every engine precision
 // (the precision of the FP64 reference): trial spin, energy difference and
@@ -79,8 +84,11 @@ __global__ void __launch_bounds__(256) k_mc_colour(Lattice L, BondCoef<double> C
         const int a = i % L.n[0];
         const int rem = i / L.n[0];
         const int b = rem % L.n[1];
-        const int c = rem / L.n[1];
-        if (((a + b + c) & 1) == M.colour) {
+        const int rem2 = rem / L.n[1];
+        const int c = rem2 % L.n[2];
+        const int beta = rem2 / L.n[2];
+        const int cell = ((a % M.cm[0]) * M.cm[1] + b % M.cm[1]) * M.cm[2] + c % M.cm[2];
+        if (M.col[cell * L.nb + beta] == M.colour) {
             const V3<double> ni{(double)n[i], (double)n[L.N + i], (double)n[2 * L.N + i]};
             double u[3];
             mc_uniforms<double>(thermal_bits(M.key, (uint32_t)i), u);
@@ -88,9 +96,9 @@ __global__ void __launch_bounds__(256) k_mc_colour(Lattice L, BondCoef<double> C
             const V3<double> nn = mc_trial(ni, u, cos_cone);
             const FieldTerms<double> f = site_terms<double, T>(L, C, P, n, i, ni);
             const V3<double> lin = f.z + f.j + f.d;
-            const V3<double> ax{P.Kax[0][0], P.Kax[0][1], P.Kax[0][2]};
+            const V3<double> ax{P.Kax[beta][0], P.Kax[beta][1], P.Kax[beta][2]};
             const double k0 = dot(ax, ni), k1 = dot(ax, nn);
-            const double dE = dot(nn - ni, lin) - 0.5 * P.K2[0] * (k1 * k1 - k0 * k0) +
+            const double dE = dot(nn - ni, lin) - 0.5 * P.K2[beta] * (k1 * k1 - k0 * k0) +
                               (gauss_energy(P, nn) - gauss_energy(P, ni));
             if (u[2] < exp(-dE / M.kT)) {
                 store3(n, L.N, i, V3<T>{(T)nn.x, (T)nn.y, (T)nn.z});

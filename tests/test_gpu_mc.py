@@ -1,4 +1,4 @@
-"""GPU Metropolis Monte Carlo (sp_mc_run, a checkerboard sweep) against the
+"""GPU Metropolis Monte Carlo (sp_mc_run, a multi-colour sweep) against the
 FP64 oracle's sweep of Sec. III.B (every spin once, sequentially in random
 order):
 
@@ -11,7 +11,9 @@ order):
   and the Binder cumulant at three temperatures on L = 8 and 12 agree within
   the combined blocked error bars (the oracle's values are stored by
   tests/golden/make_mc_stats.py);
-* rejected lattices, and the Binder-cumulant crossing at Tc = 1.44 J/k_B."""
+* triangular, honeycomb and kagome lattices, whose parallel sweep needs more
+  than two colours, against the oracle's statistics in the same way;
+* the rejected dipole term, and the Binder-cumulant crossing at Tc = 1.44 J/k_B."""
 
 import json
 import math
@@ -120,16 +122,57 @@ def test_mc_statistics_match_the_random_order_sweep(L):
         assert abs(ref["acceptance"] - doc["target_acceptance"]) < 0.1
 
 
-def test_mc_rejects_lattices_without_two_colours():
+def _lattice_stats():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "mc_lattices_oracle_stats.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("case", ["triangular12x12", "honeycomb8x8_2shell", "kagome6x6"])
+def test_mc_statistics_on_lattices_that_need_more_colours(case):
+    """Triangular, two-shell honeycomb and kagome lattices: bonds join sites
+    of any two-colouring, so the sweep runs a periodic colouring with more
+    colours; <E>/N, <|M|> and U4 match the oracle's sequential random-order
+    chain (tests/golden/make_mc_stats_lattices.py) within four combined
+    standard errors."""
+    import paper_1901_11350_amd as pk
+
+    from golden.make_mc_stats import block_stats
+    from golden.make_mc_stats_lattices import lattice_cases
+
+    doc = _lattice_stats()
+    geo, ham, _ = lattice_cases()[case]
+    for ref in [r for r in doc["results"] if r["case"] == case]:
+        T = ref["T_K"]
+        announce(f"mc statistics {case} T={T}")
+        e = pk.Engine(0, "f32")
+        e.set_geometry(geo)
+        e.set_hamiltonian(ham)
+        e.set_spins(si.ferromagnet(e.N, (0, 0, 1)))
+        _, _, cone = e.mc_run(T, doc["cone0_deg"], doc["thermalisation_sweeps"], seed=doc["seed"] + 1000,
+                              target_acceptance=doc["target_acceptance"], return_cone=True)
+        obs, acc = e.mc_run(T, cone, doc["samples"], seed=doc["seed"] + 1000, observe_every=1)
+        E = np.array([o["E"] for o in obs]) / e.N
+        m = np.array([math.sqrt(o["M"][0] ** 2 + o["M"][1] ** 2 + o["M"][2] ** 2) for o in obs])
+        got = block_stats(E, m, doc["blocks"])
+        e.close()
+        print(f"[mc] {case} T={T}: gpu {got} | oracle {ref}", flush=True)
+        for q in ("E_per_spin", "M_abs", "U4"):
+            err = math.sqrt(got[q + "_err"] ** 2 + ref[q + "_err"] ** 2)
+            assert abs(got[q] - ref[q]) < 4 * err, (case, T, q, got[q], ref[q], err)
+        assert abs(acc / (doc["samples"] * geo.n_sites) - doc["target_acceptance"]) < 0.1
+
+
+def test_mc_rejects_the_dipole_term():
     import paper_1901_11350_amd as pk
     from paper_1901_11350_amd.engine import SpError
 
     e = pk.Engine(0, "f32")
-    e.set_geometry(si.triangular(8, 8))
-    e.set_hamiltonian(si.Hamiltonian(mu=(2.0,), B=(0, 0, 1.0), K=(0.0,), K_axis=((0, 0, 1),), J=(1.0,)))
+    e.set_geometry(si.simple_cubic(6, 6, 2, periodic=(0, 0, 0)))
+    e.set_hamiltonian(si.Hamiltonian(mu=(2.0,), B=(0, 0, 1.0), K=(0.0,), K_axis=((0, 0, 1),), J=(1.0,), ddi=True))
     e.set_spins(si.uniform_sphere(e.N, 1))
     with pytest.raises(SpError):
         e.mc_run(10.0, 30.0, 1)
+    e.close()
 
 
 def binder_scan(precision, sizes, temps, therm, samples, cone=60.0, seed=5):
