@@ -341,7 +341,11 @@ int sp_thermal_normals(sp_engine *e, uint64_t seed, uint64_t step, uint32_t repl
  * ("fused2d", "twopass", ...), for diagnostics. */
 const char *sp_step_path(const sp_engine *e);
 /* Force the step path: "twopass" (any lattice), "fused2d" (one-atom 2D
- * lattice, runtime bond loop), "shape2d[/TXxTYxNT]" (one-atom 2D lattice
+ * lattice, runtime bond loop), "fusedtile" (lattice with a basis -- 2D with
+ * 2-4 atoms and bond reach <= 2, 3D with 1-3 atoms, FP64 1-2, reach 1 --
+ * or a 3D one-atom lattice without a compile-time stencil; no dipole or
+ * Gaussian terms; LDS tiles of every atom, runtime bond table; also the
+ * path of sp_gradient on such lattices), "shape2d[/TXxTYxNT]" (one-atom 2D lattice
  * whose bond table matches a compile-time stencil; optional tile
  * configuration such as "shape2d/32x16x256"), "shape3d[/cfg]" (one-atom
  * simple-cubic lattice with a compile-time stencil) or "persist2d[/TXxTY]"
