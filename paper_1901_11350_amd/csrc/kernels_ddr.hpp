@@ -18,6 +18,8 @@
 // 3 + 3 g + c.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels_conv.hpp"
 
 namespace sp {
@@ -75,13 +77,20 @@ __global__ void __launch_bounds__(256) k_ddr_moments(DdrGeo G, const T* __restri
     }
 }
 
-// u += K(r) v, r from the field point to the source.
+// u += K(r) v, r from the field point to the source; r = 0 adds nothing
+// (NZ: the caller guarantees r != 0, and the test is left out).
+template <bool NZ = false>
 __device__ __forceinline__ void ddr_add(float rx, float ry, float rz, float vx, float vy, float vz, float& ux,
                                         float& uy, float& uz) {
     const float d2 = rx * rx + ry * ry + rz * rz;
-    const float inv = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
-    const float inv3 = inv * inv * inv;
-    const float s = 3.f * (vx * rx + vy * ry + vz * rz) * inv * inv;
+    float inv;
+    if constexpr (NZ)
+        inv = __builtin_amdgcn_rsqf(d2);
+    else
+        inv = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+    const float inv2 = inv * inv;
+    const float inv3 = inv2 * inv;
+    const float s = (vx * rx + vy * ry + vz * rz) * (3.f * inv2);
     ux += (vx - s * rx) * inv3;
     uy += (vy - s * ry) * inv3;
     uz += (vz - s * rz) * inv3;
@@ -91,28 +100,30 @@ constexpr int kDdrMaxNear = 1600;     // staged near sources of one target block
 constexpr int kDdrChunk = 1024;       // far-block moments staged per pass
 
 // Backbone field (units of C_dd mu^2) of every site of one target block
-// (blockIdx.x) of sample blockIdx.y: 256 threads = 4 slices x 64 targets.
-// The sources of the near blocks are staged in LDS (spin, and position
-// relative to the target block's first cell); slice w takes every fourth
-// staged source.  The far blocks' moments are staged in LDS a chunk of
-// block rows at a time; slice w takes every fourth block row, each row as
-// the column ranges left and right of the near window (no test per
-// block).  The four partial sums are added in a fixed order.  Requires
-// B * B * NC == 64 (one target per lane) and reach <= 2.
+// (blockIdx.x) of sample blockIdx.y: 256 threads = 8 source slices x 32
+// lanes, each lane two targets (sites t and t + 32 of the block), so each
+// source read from LDS serves two targets.  The sources of the near blocks
+// are staged in LDS (spin, and position relative to the target block's
+// first cell); slice k takes every eighth staged source.  The far blocks'
+// moments are staged in LDS a chunk of block rows at a time; slice k takes
+// every eighth block row, each row as the column ranges left and right of
+// the near window (no test per block).  The eight partial sums are added in
+// a fixed order.  Requires B * B * NC == 64 and reach <= 2.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ddr_backbone(DdrGeo G, const T* __restrict__ n, int64_t stride_n,
                                                       const float* __restrict__ M0, float* __restrict__ u,
                                                       int64_t stride_u) {
+    constexpr int NS = 8;   // source slices
     __shared__ float4 sv[kDdrMaxNear];
     __shared__ float4 sp[kDdrMaxNear];
     __shared__ float4 sm[kDdrChunk];
-    __shared__ float red[3][3][64];
+    __shared__ float red[NS - 1][6][32];
     const int q = blockIdx.x, b = blockIdx.y;
     const int qa = q % G.QA, qb = q / G.QA;
     const int64_t N = (int64_t)G.NA * G.NB * G.NC;
     const T* nb = n + (size_t)b * stride_n;
     const float* Mb = M0 + (size_t)b * G.QA * G.QB * 3;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 31, k = tid >> 5;
     const int a0 = qa * G.B, b0 = qb * G.B;
     const int oa0 = max(0, qa - G.reach), oa1 = min(G.QA - 1, qa + G.reach);
     const int ob0 = max(0, qb - G.reach), ob1 = min(G.QB - 1, qb + G.reach);
@@ -129,64 +140,94 @@ __global__ void __launch_bounds__(256) k_ddr_backbone(DdrGeo G, const T* __restr
         sp[s] = make_float4((ga - a0) * G.a, (gb - b0) * G.a, lc * G.a, 0.f);
     }
     __syncthreads();
-    const int ta = lane % G.B, tb = (lane / G.B) % G.B, tc = lane / (G.B * G.B);
-    const float px = ta * G.a, py = tb * G.a, pz = tc * G.a;
-    float ux = 0.f, uy = 0.f, uz = 0.f;
-    int s = w;
-    for (; s + 12 < n_near; s += 16) {
-        const float4 v0 = sv[s], r0 = sp[s], v1 = sv[s + 4], r1 = sp[s + 4];
-        const float4 v2 = sv[s + 8], r2 = sp[s + 8], v3 = sv[s + 12], r3 = sp[s + 12];
-        ddr_add(r0.x - px, r0.y - py, r0.z - pz, v0.x, v0.y, v0.z, ux, uy, uz);   // r = 0 (the site) adds 0
-        ddr_add(r1.x - px, r1.y - py, r1.z - pz, v1.x, v1.y, v1.z, ux, uy, uz);
-        ddr_add(r2.x - px, r2.y - py, r2.z - pz, v2.x, v2.y, v2.z, ux, uy, uz);
-        ddr_add(r3.x - px, r3.y - py, r3.z - pz, v3.x, v3.y, v3.z, ux, uy, uz);
-    }
-    for (; s < n_near; s += 4) {
-        const float4 v = sv[s], r = sp[s];
-        ddr_add(r.x - px, r.y - py, r.z - pz, v.x, v.y, v.z, ux, uy, uz);
-    }
+    // the lane's two targets: sites t0 = lane and t1 = lane + 32 of the block
+    const int t0 = lane, t1 = lane + 32;
+    const int ta0 = t0 % G.B, tb0 = (t0 / G.B) % G.B, tc0 = t0 / (G.B * G.B);
+    const int ta1 = t1 % G.B, tb1 = (t1 / G.B) % G.B, tc1 = t1 / (G.B * G.B);
+    const float px0 = ta0 * G.a, py0 = tb0 * G.a, pz0 = tc0 * G.a;
+    const float px1 = ta1 * G.a, py1 = tb1 * G.a, pz1 = tc1 * G.a;
+    float ux0 = 0.f, uy0 = 0.f, uz0 = 0.f, ux1 = 0.f, uy1 = 0.f, uz1 = 0.f;
+    // staged sources [s0, s1) of this slice (s0, s1 multiples of NS); only the
+    // target block's own sources can sit at r = 0 (the site itself adds 0)
+    auto near = [&](int s0, int s1, auto nz) {
+        constexpr bool NZ = decltype(nz)::value;
+        int s = s0 + k;
+        for (; s + NS < s1; s += 2 * NS) {
+            const float4 v0 = sv[s], r0 = sp[s], v1 = sv[s + NS], r1 = sp[s + NS];
+            ddr_add<NZ>(r0.x - px0, r0.y - py0, r0.z - pz0, v0.x, v0.y, v0.z, ux0, uy0, uz0);
+            ddr_add<NZ>(r0.x - px1, r0.y - py1, r0.z - pz1, v0.x, v0.y, v0.z, ux1, uy1, uz1);
+            ddr_add<NZ>(r1.x - px0, r1.y - py0, r1.z - pz0, v1.x, v1.y, v1.z, ux0, uy0, uz0);
+            ddr_add<NZ>(r1.x - px1, r1.y - py1, r1.z - pz1, v1.x, v1.y, v1.z, ux1, uy1, uz1);
+        }
+        for (; s < s1; s += NS) {
+            const float4 v = sv[s], r = sp[s];
+            ddr_add<NZ>(r.x - px0, r.y - py0, r.z - pz0, v.x, v.y, v.z, ux0, uy0, uz0);
+            ddr_add<NZ>(r.x - px1, r.y - py1, r.z - pz1, v.x, v.y, v.z, ux1, uy1, uz1);
+        }
+    };
+    const int own0 = ((qa - oa0) + (qb - ob0) * nwa) * 64;
+    near(0, own0, std::true_type{});
+    near(own0, own0 + 64, std::false_type{});
+    near(own0 + 64, n_near, std::true_type{});
     // far blocks: one dipole at the centroid, staged a chunk of rows at a time
     const float step = G.B * G.a;
-    const float cx = (G.ca - ta) * G.a - qa * step, cy = (G.cb - tb) * G.a - qb * step, cz = (G.cc - tc) * G.a;
+    const float cx0 = (G.ca - ta0) * G.a - qa * step, cy0 = (G.cb - tb0) * G.a - qb * step, cz0 = (G.cc - tc0) * G.a;
+    const float cx1 = (G.ca - ta1) * G.a - qa * step, cy1 = (G.cb - tb1) * G.a - qb * step, cz1 = (G.cc - tc1) * G.a;
     const int rows_per_chunk = max(1, kDdrChunk / G.QA);
     for (int r0 = 0; r0 < G.QB; r0 += rows_per_chunk) {
         const int r1 = min(G.QB, r0 + rows_per_chunk);
         __syncthreads();   // the previous chunk is no longer read
-        for (int k = tid; k < (r1 - r0) * G.QA; k += 256) {
-            const float* m = Mb + 3 * ((size_t)r0 * G.QA + k);
-            sm[k] = make_float4(m[0], m[1], m[2], 0.f);
+        for (int m = tid; m < (r1 - r0) * G.QA; m += 256) {
+            const float* mm = Mb + 3 * ((size_t)r0 * G.QA + m);
+            sm[m] = make_float4(mm[0], mm[1], mm[2], 0.f);
         }
         __syncthreads();
-        for (int fb = r0 + w; fb < r1; fb += 4) {
-            const float ry = fb * step + cy;
+        for (int fb = r0 + k; fb < r1; fb += NS) {
+            const float ry0 = fb * step + cy0, ry1 = fb * step + cy1;
             const float4* row = sm + (fb - r0) * G.QA;
             const bool in_rows = fb >= ob0 && fb <= ob1;
             const int gap0 = in_rows ? oa0 : G.QA, gap1 = in_rows ? oa1 + 1 : G.QA;
+            // a far block's centroid is at least reach + 1/2 blocks away: r != 0
             for (int fa = 0; fa < gap0; ++fa) {
                 const float4 m = row[fa];
-                ddr_add(fa * step + cx, ry, cz, m.x, m.y, m.z, ux, uy, uz);
+                ddr_add<true>(fa * step + cx0, ry0, cz0, m.x, m.y, m.z, ux0, uy0, uz0);
+                ddr_add<true>(fa * step + cx1, ry1, cz1, m.x, m.y, m.z, ux1, uy1, uz1);
             }
             for (int fa = gap1; fa < G.QA; ++fa) {
                 const float4 m = row[fa];
-                ddr_add(fa * step + cx, ry, cz, m.x, m.y, m.z, ux, uy, uz);
+                ddr_add<true>(fa * step + cx0, ry0, cz0, m.x, m.y, m.z, ux0, uy0, uz0);
+                ddr_add<true>(fa * step + cx1, ry1, cz1, m.x, m.y, m.z, ux1, uy1, uz1);
             }
         }
     }
-    if (w > 0) {
-        red[0][w - 1][lane] = ux;
-        red[1][w - 1][lane] = uy;
-        red[2][w - 1][lane] = uz;
+    if (k > 0) {
+        float* r = &red[k - 1][0][0];
+        r[0 * 32 + lane] = ux0;
+        r[1 * 32 + lane] = uy0;
+        r[2 * 32 + lane] = uz0;
+        r[3 * 32 + lane] = ux1;
+        r[4 * 32 + lane] = uy1;
+        r[5 * 32 + lane] = uz1;
     }
     __syncthreads();
-    if (w == 0) {
-        ux += red[0][0][lane] + red[0][1][lane] + red[0][2][lane];
-        uy += red[1][0][lane] + red[1][1][lane] + red[1][2][lane];
-        uz += red[2][0][lane] + red[2][1][lane] + red[2][2][lane];
-        const int64_t i = (a0 + ta) + (int64_t)G.NA * ((b0 + tb) + (int64_t)G.NB * tc);
+    if (k == 0) {
+        for (int j = 0; j < NS - 1; ++j) {
+            ux0 += red[j][0][lane];
+            uy0 += red[j][1][lane];
+            uz0 += red[j][2][lane];
+            ux1 += red[j][3][lane];
+            uy1 += red[j][4][lane];
+            uz1 += red[j][5][lane];
+        }
         float* ub = u + (size_t)b * stride_u;
-        ub[i] = ux;
-        ub[N + i] = uy;
-        ub[2 * N + i] = uz;
+        const int64_t i0 = (a0 + ta0) + (int64_t)G.NA * ((b0 + tb0) + (int64_t)G.NB * tc0);
+        const int64_t i1 = (a0 + ta1) + (int64_t)G.NA * ((b0 + tb1) + (int64_t)G.NB * tc1);
+        ub[i0] = ux0;
+        ub[N + i0] = uy0;
+        ub[2 * N + i0] = uz0;
+        ub[i1] = ux1;
+        ub[N + i1] = uy1;
+        ub[2 * N + i1] = uz1;
     }
 }
 
