@@ -35,45 +35,42 @@ struct DdrGeo {
 // Block moments of sample b: network input (bf16, NHWC, channels padded to
 // kCP) scaled by in_s0 (moment) and in_s1 (first moments), and the moments
 // themselves (FP32, [b][qb][qa][3]) for the backbone's far field.  One
-// thread per block.
+// wavefront per block, one site per lane (B * B * NC == 64), sums by a
+// fixed butterfly of lane exchanges; four blocks per workgroup.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ddr_moments(DdrGeo G, const T* __restrict__ n, int64_t stride_n,
                                                      float in_s0, float in_s1, __bf16* __restrict__ x0, int b0,
                                                      float* __restrict__ M0) {
-    const int q = blockIdx.x * 256 + threadIdx.x;
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
     const int b = blockIdx.y;
-    if (q >= G.QA * G.QB) return;
+    if (q >= G.QA * G.QB) return;   // the whole wavefront
     const int qa = q % G.QA, qb = q / G.QA;
+    const int la = l % G.B, lb = (l / G.B) % G.B, lc = l / (G.B * G.B);
     const int64_t N = (int64_t)G.NA * G.NB * G.NC;
     const T* nb = n + (size_t)b * stride_n;
-    float m[3] = {0.f, 0.f, 0.f}, Q[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int lc = 0; lc < G.NC; ++lc)
-        for (int lb = 0; lb < G.B; ++lb)
-            for (int la = 0; la < G.B; ++la) {
-                const int64_t i = (qa * G.B + la) + (int64_t)G.NA * ((qb * G.B + lb) + (int64_t)G.NB * lc);
-                const float v[3] = {(float)nb[i], (float)nb[N + i], (float)nb[2 * N + i]};
-                const float d[3] = {(la - G.ca) * G.a, (lb - G.cb) * G.a, (lc - G.cc) * G.a};
+    const int64_t i = (qa * G.B + la) + (int64_t)G.NA * ((qb * G.B + lb) + (int64_t)G.NB * lc);
+    const float v[3] = {(float)nb[i], (float)nb[N + i], (float)nb[2 * N + i]};
+    const float d[3] = {(la - G.ca) * G.a, (lb - G.cb) * G.a, (lc - G.cc) * G.a};
+    // acc[c] = m_c, acc[3 + 3 g + c] = Q_gc = sum d_g v_c
+    float acc[12];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    m[c] += v[c];
+    for (int c = 0; c < 3; ++c) {
+        acc[c] = v[c];
 #pragma unroll
-                    for (int g = 0; g < 3; ++g) Q[3 * g + c] += d[g] * v[c];
-                }
-            }
-    if (M0) {
-        float* o = M0 + ((size_t)b * G.QA * G.QB + q) * 3;
-        o[0] = m[0];
-        o[1] = m[1];
-        o[2] = m[2];
+        for (int g = 0; g < 3; ++g) acc[3 + 3 * g + c] = d[g] * v[c];
     }
-    if (x0) {
-        __bf16* o = x0 + ((size_t)(b0 + b) * G.QA * G.QB + q) * kCP;
-        for (int c = 0; c < kCP; ++c) {
-            float v = 0.f;
-            if (c < 3) v = in_s0 * m[c];
-            else if (c < 12) v = in_s1 * Q[c - 3];
-            o[c] = (__bf16)v;
-        }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] += __shfl_xor(acc[k], o, 64);
+    if (M0 && l < 3) M0[((size_t)b * G.QA * G.QB + q) * 3 + l] = acc[l];
+    if (x0 && l < kCP) {
+        float v0 = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            if (l == k) v0 = (k < 3 ? in_s0 : in_s1) * acc[k];
+        x0[((size_t)(b0 + b) * G.QA * G.QB + q) * kCP + l] = (__bf16)v0;
     }
 }
 
