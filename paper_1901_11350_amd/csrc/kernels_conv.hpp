@@ -44,20 +44,25 @@ enum { CONV_SILU = 0, CONV_LINEAR = 1, CONV_SILU_NOZ = 2 };
 //   MODE CONV_SILU:     z (FP32) and y = bf16(silu(z))
 //   MODE CONV_LINEAR:   z (FP32) only
 //   MODE CONV_SILU_NOZ: y only (inference)
-template <int MODE>
+// TR: tile rows (16, or 4 for small grids: four times the workgroups, one
+// row per wavefront); per accumulator the taps and instructions are the
+// same, so both give the same bits.
+template <int MODE, int TR = kTile>
 __global__ void __launch_bounds__(256) k_conv3x3(int H, int W, const __bf16* __restrict__ x,
                                                  const __bf16* __restrict__ wk, const float* __restrict__ bias,
                                                  float* __restrict__ z, __bf16* __restrict__ y) {
-    __shared__ __attribute__((aligned(16))) __bf16 sX[kHalo * kHalo * kCP];
+    static_assert(TR % 4 == 0 && TR <= kTile, "four wavefronts of whole rows");
+    constexpr int RPW = TR / 4;   // rows per wavefront
+    __shared__ __attribute__((aligned(16))) __bf16 sX[(TR + 2) * kHalo * kCP];
     __shared__ __attribute__((aligned(16))) __bf16 sW[9 * kCP * kCP];
     const int b = blockIdx.z;
-    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * TR;
     const int tid = threadIdx.x;
     // weights: 9*32*32 bf16 = 1152 vectors of 8
     for (int v = tid; v < 9 * kCP * kCP / 8; v += 256)
         reinterpret_cast<bf16x8*>(sW)[v] = reinterpret_cast<const bf16x8*>(wk)[v];
-    // input tile with halo: 18*18 pixels x 4 vectors of 8 channels
-    for (int v = tid; v < kHalo * kHalo * 4; v += 256) {
+    // input tile with halo: (TR+2) x 18 pixels x 4 vectors of 8 channels
+    for (int v = tid; v < (TR + 2) * kHalo * 4; v += 256) {
         const int p = v >> 2, q = v & 3;
         const int hy = p / kHalo, hx = p - hy * kHalo;
         const int gy = y0 + hy - 1, gx = x0 + hx - 1;
@@ -74,9 +79,9 @@ __global__ void __launch_bounds__(256) k_conv3x3(int H, int W, const __bf16* __r
 
     const int wave = tid >> 6, lane = tid & 63;
     const int lm = lane & 15, lk = lane >> 4;   // fragment row/col, k group
-    f32x4 acc[4][2];
+    f32x4 acc[RPW][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < RPW; ++r)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) acc[r][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -87,8 +92,8 @@ __global__ void __launch_bounds__(256) k_conv3x3(int H, int W, const __bf16* __r
         for (int nb = 0; nb < 2; ++nb)
             bw[nb] = *reinterpret_cast<const bf16x8*>(sW + (tap * kCP + lm + 16 * nb) * kCP + 8 * lk);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = wave * 4 + r;
+        for (int r = 0; r < RPW; ++r) {
+            const int row = wave * RPW + r;
             const bf16x8 a = *reinterpret_cast<const bf16x8*>(sX + ((row + ky) * kHalo + lm + kx) * kCP + 8 * lk);
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) acc[r][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[nb], acc[r][nb], 0, 0, 0);
@@ -96,8 +101,8 @@ __global__ void __launch_bounds__(256) k_conv3x3(int H, int W, const __bf16* __r
     }
     // D fragment: lane holds pixels 4*lk + j (j = 0..3) of the row, channel lm + 16 nb
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int gy = y0 + wave * 4 + r;
+    for (int r = 0; r < RPW; ++r) {
+        const int gy = y0 + wave * RPW + r;
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
             const int c = lm + 16 * nb;

@@ -231,6 +231,33 @@ def test_four_layer_forward_within_the_bf16_rounding_model(ora):
     assert model < 0.05
 
 
+def test_small_grid_tiles_equal_full_tiles():
+    """A small grid runs the convolutions on 16 x 4 pixel tiles (four times
+    the workgroups), a large batch on 16 x 16 tiles; same taps and
+    instructions per accumulator, so the outputs agree bit for bit (64 x 64
+    film: one sample takes the small tiles, four samples the full ones)."""
+    import torch
+
+    channels = [12, 32, 32, 32, 12]
+    announce("conv tiles 16x4 vs 16x16")
+    geo = _film(64)
+    e = _engine(geo)
+    e.ddi_init(channels, seed=9)
+    n_p = sum(9 * a * b + b for a, b in zip(channels[:-1], channels[1:]))
+    e.ddi_set_params(np.random.default_rng(99).standard_normal(n_p) * 0.15)
+    n = np.stack([si.uniform_sphere(geo.n_sites, 91 + k) for k in range(4)])
+    nt = torch.tensor(n, dtype=torch.float32, device="cuda").contiguous()
+    batch, single = torch.zeros_like(nt), torch.zeros_like(nt)
+    torch.cuda.synchronize()
+    e.ddi_forward_dev(4, nt, batch)
+    for b in range(4):
+        e.ddi_forward_dev(1, nt[b].contiguous(), single[b])
+    e.synchronize()
+    e.close()
+    assert torch.equal(batch, single)
+    assert float(batch.abs().max()) > 0
+
+
 def test_surrogate_gradients_match_oracle(ora):
     import torch
 
