@@ -407,45 +407,80 @@ __global__ void __launch_bounds__(256) k_surrogate_check(int N, int n_sites, int
     stats[3] = fmax(stats[3], err);
 }
 
-// Exact dipole gradient (direct sum over all sources) at a list of target
-// sites, for the surrogate's residual check.  Target sites offset + s *
-// stride, one 1024-thread workgroup per site; each thread accumulates its
-// sources in FP32, the per-thread sums are added in FP64 (fixed-order tree).
+// Exact dipole gradient (direct sum over all sources, meV) at the n_sites
+// target sites offset + s * stride, the reference of the surrogate's
+// residual check: workgroup (g, k) takes the
+// kSitesPerGroup sites of group g and the k-th of kSiteSlices source
+// slices, so each source read serves every site of the group; each thread
+// accumulates its sources in FP32, the workgroup adds the per-thread sums
+// in FP64 (fixed-order tree) into part[(site * kSiteSlices + k) * 3 + c],
+// and k_dipole_sites_finish adds the slices in order.
+constexpr int kSitesPerGroup = 8;
+constexpr int kSiteSlices = 8;
+
 template <typename T>
-__global__ void __launch_bounds__(1024) k_dipole_at_sites(int N, const T* __restrict__ pos, const T* __restrict__ n,
-                                                          int offset, int stride, int n_sites, T mu, T Cdd,
-                                                          double* __restrict__ out) {
-    const int s = blockIdx.x;
-    if (s >= n_sites) return;
-    const int i = offset + s * stride;
-    const T px = pos[i], py = pos[N + i], pz = pos[2 * N + i];
-    T acc[3] = {T(0), T(0), T(0)};
-    for (int j = threadIdx.x; j < N; j += 1024) {
-        const T rx = pos[j] - px, ry = pos[N + j] - py, rz = pos[2 * N + j] - pz;
-        const T d2 = rx * rx + ry * ry + rz * rz;
-        T inv;
-        if constexpr (sizeof(T) == 4) {
-            inv = d2 > T(0) ? __builtin_amdgcn_rsqf(d2) : T(0);
-        } else {
-            inv = d2 > T(0) ? T(1) / sqrt(d2) : T(0);
-        }
-        const T inv3 = inv * inv * inv;
-        const T mx = n[j], my = n[N + j], mz = n[2 * N + j];
-        const T sdot = T(3) * (mx * rx + my * ry + mz * rz) * inv * inv;
-        acc[0] += (mx - sdot * rx) * inv3;
-        acc[1] += (my - sdot * ry) * inv3;
-        acc[2] += (mz - sdot * rz) * inv3;
+__global__ void __launch_bounds__(256) k_dipole_at_sites_part(int N, const T* __restrict__ pos,
+                                                               const T* __restrict__ n, int offset, int stride,
+                                                               int n_sites, double* __restrict__ part) {
+    const int g = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
+    T px[kSitesPerGroup], py[kSitesPerGroup], pz[kSitesPerGroup];
+    T acc[kSitesPerGroup][3];
+#pragma unroll
+    for (int q = 0; q < kSitesPerGroup; ++q) {
+        const int s = min(g * kSitesPerGroup + q, n_sites - 1);
+        const int i = offset + s * stride;
+        px[q] = pos[i];
+        py[q] = pos[N + i];
+        pz[q] = pos[2 * N + i];
+        acc[q][0] = acc[q][1] = acc[q][2] = T(0);
     }
-    __shared__ double red[3][1024];
-    for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = (double)acc[c];
+    const int j0 = (int)((long long)N * k / kSiteSlices), j1 = (int)((long long)N * (k + 1) / kSiteSlices);
+    for (int j = j0 + tid; j < j1; j += 256) {
+        const T sx = pos[j], sy = pos[N + j], sz = pos[2 * N + j];
+        const T mx = n[j], my = n[N + j], mz = n[2 * N + j];
+#pragma unroll
+        for (int q = 0; q < kSitesPerGroup; ++q) {
+            const T rx = sx - px[q], ry = sy - py[q], rz = sz - pz[q];
+            const T d2 = rx * rx + ry * ry + rz * rz;
+            T inv;
+            if constexpr (sizeof(T) == 4) {
+                inv = d2 > T(0) ? __builtin_amdgcn_rsqf(d2) : T(0);
+            } else {
+                inv = d2 > T(0) ? T(1) / sqrt(d2) : T(0);
+            }
+            const T inv3 = inv * inv * inv;
+            const T sdot = T(3) * (mx * rx + my * ry + mz * rz) * inv * inv;
+            acc[q][0] += (mx - sdot * rx) * inv3;
+            acc[q][1] += (my - sdot * ry) * inv3;
+            acc[q][2] += (mz - sdot * rz) * inv3;
+        }
+    }
+    __shared__ double red[kSitesPerGroup * 3][256];
+#pragma unroll
+    for (int q = 0; q < kSitesPerGroup; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) red[3 * q + c][tid] = (double)acc[q][c];
     __syncthreads();
-    for (int st = 512; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st)
-            for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int v = 0; v < kSitesPerGroup * 3; ++v) red[v][tid] += red[v][tid + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
-        for (int c = 0; c < 3; ++c) out[3 * s + c] = (double)(Cdd * mu * mu) * red[c][0];
+    if (tid < kSitesPerGroup * 3) {
+        const int s = g * kSitesPerGroup + tid / 3;
+        if (s < n_sites) part[((size_t)s * kSiteSlices + k) * 3 + tid % 3] = red[tid][0];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dipole_sites_finish(int n_sites, const double* __restrict__ part, T mu,
+                                                              T Cdd, double* __restrict__ out) {
+    const int v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= 3 * n_sites) return;
+    const int s = v / 3, c = v - 3 * s;
+    double t = 0.0;
+    for (int k = 0; k < kSiteSlices; ++k) t += part[((size_t)s * kSiteSlices + k) * 3 + c];
+    out[v] = (double)(Cdd * mu * mu) * t;
 }
 
 }  // namespace sp
