@@ -364,24 +364,37 @@ __global__ void k_sample_norm2_final(int B, const double* __restrict__ part, dou
     out[b] = s;
 }
 
+constexpr int kSitesPerGroup = 4;
+constexpr int kSiteSlices = 16;
+
 // Residual check of a surrogate field at sampled sites: relative error
 // |g_s - exact_s| / |exact_s| over the samples; *need = (error > tol).
+// exact_s = scale * (sum of the kSiteSlices slice sums of
+// k_dipole_at_sites_part, in slice order).
 // stats: [evaluations, fallbacks, last error, max error].
 // Sampled sites are offset + s * stride, s < n_sites.
 // One workgroup of 256 threads; thread t covers samples t, t + 256, ...; the
 // sums are reduced in a fixed-order tree.
 template <typename T>
 __global__ void __launch_bounds__(256) k_surrogate_check(int N, int n_sites, int offset, int stride,
-                                                         const double* __restrict__ exact,
+                                                         const double* __restrict__ part, double scale,
                                                          const T* __restrict__ g, double tol,
                                                          int* __restrict__ need, double* __restrict__ stats) {
     double num = 0.0, den = 0.0;
     for (int s = threadIdx.x; s < n_sites; s += 256) {
         const int i = offset + s * stride;
+        double v[kSiteSlices * 3];   // every slice sum of the site in flight at once
+#pragma unroll
+        for (int k = 0; k < kSiteSlices * 3; ++k) v[k] = part[(size_t)s * kSiteSlices * 3 + k];
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double d = (double)g[(size_t)c * N + i] - exact[3 * s + c];
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < kSiteSlices; ++k) t += v[3 * k + c];
+            const double ex = scale * t;
+            const double d = (double)g[(size_t)c * N + i] - ex;
             num += d * d;
-            den += exact[3 * s + c] * exact[3 * s + c];
+            den += ex * ex;
         }
     }
     __shared__ double red[2][256];
@@ -407,16 +420,14 @@ __global__ void __launch_bounds__(256) k_surrogate_check(int N, int n_sites, int
     stats[3] = fmax(stats[3], err);
 }
 
-// Exact dipole gradient (direct sum over all sources, meV) at the n_sites
+// Exact dipole gradient (direct sum over all sources, in units of C_dd mu^2) at the n_sites
 // target sites offset + s * stride, the reference of the surrogate's
 // residual check: workgroup (g, k) takes the
 // kSitesPerGroup sites of group g and the k-th of kSiteSlices source
 // slices, so each source read serves every site of the group; each thread
 // accumulates its sources in FP32, the workgroup adds the per-thread sums
 // in FP64 (fixed-order tree) into part[(site * kSiteSlices + k) * 3 + c],
-// and k_dipole_sites_finish adds the slices in order.
-constexpr int kSitesPerGroup = 8;
-constexpr int kSiteSlices = 8;
+// and the check adds the slices in order.
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_dipole_at_sites_part(int N, const T* __restrict__ pos,
@@ -470,17 +481,6 @@ __global__ void __launch_bounds__(256) k_dipole_at_sites_part(int N, const T* __
         const int s = g * kSitesPerGroup + tid / 3;
         if (s < n_sites) part[((size_t)s * kSiteSlices + k) * 3 + tid % 3] = red[tid][0];
     }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_dipole_sites_finish(int n_sites, const double* __restrict__ part, T mu,
-                                                              T Cdd, double* __restrict__ out) {
-    const int v = blockIdx.x * 256 + threadIdx.x;
-    if (v >= 3 * n_sites) return;
-    const int s = v / 3, c = v - 3 * s;
-    double t = 0.0;
-    for (int k = 0; k < kSiteSlices; ++k) t += part[((size_t)s * kSiteSlices + k) * 3 + c];
-    out[v] = (double)(Cdd * mu * mu) * t;
 }
 
 }  // namespace sp
