@@ -1002,8 +1002,8 @@ struct Tile3Cfg {
     int TX, TY, blocks;
 };
 constexpr Tile3Cfg kTile3Cfgs[] = {{"32x16", 32, 16, 256}, {"16x16", 16, 16, 768}, {"32x8", 32, 8, 768},
-                                   {"16x16z", 16, 16, 256}, {"32x16b", 32, 16, 512}};
-constexpr int kNumTile3Cfgs = 5;      // FP64 takes the 16x16 tiles only (LDS)
+                                   {"16x16z", 16, 16, 256}, {"32x16b", 32, 16, 512}, {"32x32", 32, 32, 256}};
+constexpr int kNumTile3Cfgs = 6;      // FP64 takes the 16x16 tiles only (LDS)
 
 template <int S>
 bool match_shape3(const sp_engine* e) {
@@ -1123,6 +1123,8 @@ void go_cfg3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* ni
             go_tile3<T, 16, 16, SOLVER>(e, p, step, nin, nout);
         else if (e->tile3_cfg == 2)
             go_tile3<T, 32, 8, SOLVER>(e, p, step, nin, nout);
+        else if (e->tile3_cfg == 5)
+            go_tile3<T, 32, 32, SOLVER>(e, p, step, nin, nout);
         // configurations 0 and 4 share the 32x16 kernel (different chunking)
         else
             go_tile3<T, 32, 16, SOLVER>(e, p, step, nin, nout);
@@ -2049,9 +2051,10 @@ int install_ham(sp_engine* e, const HostHam& H, const std::vector<HostBond>& bon
     e->shape3 = -1;
     e->shape3_ndmi = 0;
     e->shape3_dk = sp::DK_NONE;
-    // default 3D tile: 32x16 columns, two workgroups per CU (fastest measured
-    // on the 128^3 workload); FP64 takes 16x16 (LDS)
-    e->tile3_cfg = e->precision == SP_F64 ? 1 : 4;
+    // default 3D tile: 32x32 columns, one 1024-thread workgroup per CU
+    // (fastest measured on the 128^3 workload: 32.6 us against 33.4 for
+    // 32x16 at two workgroups per CU); FP64 takes 16x16 (LDS)
+    e->tile3_cfg = e->precision == SP_F64 ? 1 : 5;
     if (g.nb == 1 && g.n[2] > 1 && !H.ddi && H.n_gauss == 0 && !explicit_pairs) {
         bool ok = true;
         for (const HostBond& b : all_bonds)
@@ -2387,7 +2390,7 @@ int sp_set_step_path(sp_engine* e, const char* name) {
     } else if (s.rfind("shape3d", 0) == 0) {
         if (e->shape3 < 0)
             return fail(e, SP_E_UNSUPPORTED, "shape3d needs a 3D one-atom bond table matching a compile-time stencil");
-        int cfg = e->precision == SP_F64 ? 1 : 4;
+        int cfg = e->precision == SP_F64 ? 1 : 5;
         if (s.size() > 7) {
             if (s[7] != '/') return fail(e, SP_E_ARG, "unknown step path " + s);
             cfg = -1;

@@ -25,7 +25,7 @@ CASES = {
     "sc2_thin_9x9x2": (si.simple_cubic(9, 9, 2), HAM2),
     "sc1_40x4x3_periodic_small": (si.simple_cubic(40, 4, 3), dataclasses.replace(HAM2, J=(1.0,), D=(0.15,))),
 }
-CFGS = {"f32": ["32x16", "16x16", "32x8", "16x16z", "32x16b"], "f64": ["16x16", "16x16z"]}
+CFGS = {"f32": ["32x16", "16x16", "32x8", "16x16z", "32x16b", "32x32"], "f64": ["16x16", "16x16z"]}
 
 
 @pytest.fixture(autouse=True)
