@@ -569,3 +569,28 @@ def test_four_atom_cell_equals_the_one_atom_lattice(ora, precision):
     assert_close(a.get_spins()[:, four], b.get_spins()[:, one], precision, what="50 steps")
     a.close()
     b.close()
+
+
+STACK3_GEO = si.Geometry(((1.0, 0, 0), (0, 1.0, 0), (0, 0, 1.0)), ((0, 0, 0), (0, 0, 1 / 3), (0.5, 0.5, 2 / 3)),
+                         (12, 10, 6), (1, 1, 1))
+STACK3_HAM = si.Hamiltonian(mu=(2.0, 2.5, 3.0), B=(0.1, 0.0, 0.3), K=(0.1, 0.0, -0.1),
+                            K_axis=((0, 0, 1), (1, 0, 0), (0, 0.6, 0.8)), J=(1.0, 0.4, 0.2), D=(0.1,),
+                            dmi_kind=si.DMI_BULK)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_three_atom_cell_in_3d(ora, precision):
+    """A 3D cell of three atoms (6, 6 and 22 bonds): the fused tile path in
+    FP32 (8 x 8 x 4 tiles of the three atoms), the two-pass path in FP64
+    (the tile would not fit in LDS); field and 4-step stochastic trajectory
+    against the oracle."""
+    announce(f"three-atom 3D cell {precision}")
+    e, s = make_pair(ora, STACK3_GEO, STACK3_HAM, precision)
+    assert e.step_path == ("fusedtile" if precision == "f32" else "twopass"), e.step_path
+    n0 = si.uniform_sphere(s.N, 43)
+    e.set_spins(n0)
+    assert_close(e.gradient(), s.gradient(n0), precision, what="gradient three-atom 3D")
+    e.step = 3
+    e.run(0.3, 0.001, 4, T=20.0, seed=13)
+    ref, _ = s.run(n0, 0.3, 0.001, 4, T=20.0, seed=13, step0=3)
+    assert_close(e.get_spins(), ref, precision, what="4 steps three-atom 3D")
