@@ -1067,6 +1067,28 @@ sp::ShapeCoef3<T> shape_coef3_for(const sp_engine* e) {
     return C;
 }
 
+// The step kernel's coefficients: those of shape_coef3_for divided by
+// mu mu_B (in double, then rounded), and the external field in Tesla.
+template <typename T, int S>
+sp::StepCoef3<T> step_coef3_for(const sp_engine* e) {
+    using SH = sp::ShapeTab3<S>;
+    const double inv = 1.0 / (e->ham.mu[0] * kMuB);
+    sp::StepCoef3<T> C{};
+    for (int s = 0; s < SH::NS; ++s) C.J[s] = (T)(s < e->ham.n_exch ? e->ham.J[s] * inv : 0.0);
+    for (int q = 0; q < SH::NB0; ++q)
+        for (const HostBond& b : e->all_bonds)
+            if (b.d[0] == SH::da[q] && b.d[1] == SH::db[q] && b.d[2] == SH::dc[q] && b.shell == 0) {
+                C.Dx[q] = (T)(b.D[0] * inv);
+                C.Dy[q] = (T)(b.D[1] * inv);
+                C.Dz[q] = (T)(b.D[2] * inv);
+            }
+    double d0 = 0.0;
+    if (bulk_dmi3(e->all_bonds, &d0)) C.D0 = (T)(d0 * inv);
+    C.K2 = (T)(2.0 * e->ham.K[0] * inv);
+    for (int k = 0; k < 3; ++k) C.Bext[k] = (T)e->ham.B[k];
+    return C;
+}
+
 template <typename T, int S, int DK, int TX, int TY, int SOLVER>
 void go_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     const int target = kTile3Cfgs[e->tile3_cfg].blocks;
@@ -1085,13 +1107,13 @@ void go_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* 
     if constexpr (SOLVER == sp::SOLVER_DEPONDT) {
         if (e->ham.K[0] == 0.0) {
             hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, DK, TX, TY, SOLVER, false>), grid, block, 0, e->stream,
-                               shape_coef3_for<T, S>(e), make_site2d<T>(e, p), Z, make_step_llg<T>(e, p, step),
+                               step_coef3_for<T, S>(e), make_site2d<T>(e, p), Z, make_step_llg<T>(e, p, step),
                                e->d_flag, static_cast<const T*>(nin), static_cast<T*>(nout));
             return;
         }
     }
     hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, DK, TX, TY, SOLVER, true>), grid, block, 0, e->stream,
-                       shape_coef3_for<T, S>(e), make_site2d<T>(e, p), Z, make_step_llg<T>(e, p, step), e->d_flag,
+                       step_coef3_for<T, S>(e), make_site2d<T>(e, p), Z, make_step_llg<T>(e, p, step), e->d_flag,
                        static_cast<const T*>(nin), static_cast<T*>(nout));
 }
 

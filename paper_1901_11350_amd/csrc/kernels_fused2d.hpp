@@ -97,21 +97,45 @@ __device__ __forceinline__ void native_sincos(T x, T* s, T* c) {
     }
 }
 
-// Rotation of n about w by |w| dt, in the form
+// LLG rotation vector without its prefactor: with w = B + alpha n x B the
+// equation dn/dt = n x A, A = -gp w, reads dn/dt = gp w x n, so a step
+// turns n about w by gp |w| dt (Depondt's scheme, Appendix B).
+template <typename T>
+__device__ __forceinline__ V3<T> llg_w(V3<T> n, V3<T> B, T alpha) {
+    const V3<T> nxB = cross(n, B);
+    return V3<T>{B.x + alpha * nxB.x, B.y + alpha * nxB.y, B.z + alpha * nxB.z};
+}
+
+// Half-angle factor h of rotate_half for a turn by gp |w| dt: gp dt / 2, in
+// revolutions for FP32 (the unit of the hardware sine and cosine), radians
+// for FP64.
+template <typename T>
+__device__ __forceinline__ T rot_half_factor(T gp, T dt) {
+    if constexpr (sizeof(T) == 4) {
+        return (0.5f * 0.15915494309189535f) * (gp * dt);
+    } else {
+        return T(0.5) * (gp * dt);
+    }
+}
+
+// Rotation of n about w by the angle theta = 2 h |w|, in the form
 //   n' = n + s1 (w x n) + s2 (w (w.n) - |w|^2 n),
 //   s1 = sin(theta)/|w|, s2 = (1 - cos theta)/|w|^2 = 2 sin^2(theta/2)/|w|^2.
+// w = 0 leaves n unchanged: in FP32 the 1e-30 added to |w|^2 keeps 1/|w|
+// finite and is below the rounding of any |w|^2 above 3e-23.
 template <typename T>
-__device__ __forceinline__ V3<T> rotate_fast(V3<T> n, V3<T> w, T dt) {
+__device__ __forceinline__ V3<T> rotate_half(V3<T> n, V3<T> w, T h) {
     const T w2 = dot(w, w);
-    T inv;
+    T inv, sh, ch;
     if constexpr (sizeof(T) == 4) {
-        inv = w2 > 0.0f ? __builtin_amdgcn_rsqf(w2) : 0.0f;
+        inv = __builtin_amdgcn_rsqf(w2 + 1e-30f);
+        const float half = h * (w2 * inv);
+        sh = __builtin_amdgcn_sinf(half);
+        ch = __builtin_amdgcn_cosf(half);
     } else {
         inv = w2 > 0.0 ? 1.0 / sqrt(w2) : 0.0;
+        sincos(h * (w2 * inv), &sh, &ch);
     }
-    const T half = T(0.5) * dt * (w2 * inv);
-    T sh, ch;
-    native_sincos(half, &sh, &ch);
     const T s1 = T(2) * sh * ch * inv;
     const T s2 = T(2) * sh * sh * (inv * inv);
     const V3<T> wxn = cross(w, n);
@@ -326,7 +350,7 @@ __device__ __forceinline__ void ring_cell(int h, int& px, int& py) {
 // Predictor of one predictor-frame cell (px, py) with its thermal field
 // Bth.  Writes to sP what the corrector's field is evaluated on and returns
 // what the corrector needs of the site itself:
-//   Depondt: n^p = R(A) n, returns A;
+//   Depondt: n^p = R(A) n, returns w = B + alpha n x B (A = -gp w);
 //   Heun:    n^p = (n + dt n x A) / |...|, returns f = n x A;
 //   SIB:     x solves the midpoint stage with A frozen; sP holds the
 //            midpoint m = (n + x)/2 (Appendix C), returns nothing.
@@ -345,18 +369,17 @@ __device__ __forceinline__ V3<T> predict_cell(const ShapeCoef<T>& C, const Site2
         const V3<T> ni = lds_cell_xyz(L.sN, c);
         const V3<T> g = shape_field_aos<T, S, NDMI, WN>(C, Q, L.sN, c, ni);
         const V3<T> B = (-Q.inv_mumuB) * g + Bth;
-        const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
         V3<T> o;
         if constexpr (SOLVER == SOLVER_HEUN) {
-            keep = cross(ni, Ai);
+            keep = cross(ni, llg_A(ni, B, A.gp, A.alpha));
             o = normalize3(ni + A.dt * keep);
         } else if constexpr (SOLVER == SOLVER_SIB) {
-            o = T(0.5) * (ni + sib_stage(ni, Ai, A.dt));
+            o = T(0.5) * (ni + sib_stage(ni, llg_A(ni, B, A.gp, A.alpha), A.dt));
         } else {
-            keep = Ai;
+            keep = llg_w(ni, B, A.alpha);
             // n^p only feeds the corrector's field; its FP32 length error
             // (~1 ulp) is left in place, only n(t+dt) is renormalised.
-            o = rotate_fast(ni, T(-1) * Ai, A.dt);
+            o = rotate_half(ni, keep, rot_half_factor(A.gp, A.dt));
         }
         out = V4<T>{o.x, o.y, o.z, T(0)};
     }
@@ -376,17 +399,18 @@ __device__ __forceinline__ V3<T> correct_cell(const ShapeCoef<T>& C, const Site2
     const V3<T> npi = lds_cell_xyz(L.sP, c);
     const V3<T> g = shape_field_aos<T, S, NDMI, WP>(C, Q, L.sP, c, npi);
     const V3<T> B = (-Q.inv_mumuB) * g + keepB;
-    const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
     const V3<T> ni = lds_cell_xyz(L.sN, (ty + 2 * R) * WN + (tx + 2 * R));
     if constexpr (SOLVER == SOLVER_HEUN) {
         // n + dt (f(n) + f(n^p)) / 2, renormalised
-        return normalize3(ni + (T(0.5) * A.dt) * (keepA + cross(npi, Ap)));
+        return normalize3(ni + (T(0.5) * A.dt) * (keepA + cross(npi, llg_A(npi, B, A.gp, A.alpha))));
     } else if constexpr (SOLVER == SOLVER_SIB) {
         // npi is the midpoint m; A(m) drives the second midpoint stage
-        return renorm_if_float(sib_stage(ni, Ap, A.dt));
+        return renorm_if_float(sib_stage(ni, llg_A(npi, B, A.gp, A.alpha), A.dt));
     } else {
-        const V3<T> w{T(-0.5) * (keepA.x + Ap.x), T(-0.5) * (keepA.y + Ap.y), T(-0.5) * (keepA.z + Ap.z)};
-        return renorm_if_float(rotate_fast(ni, w, A.dt));
+        // the mean of the two rotation vectors (A + A^p)/2, up to -gp
+        const V3<T> wp = llg_w(npi, B, A.alpha);
+        const V3<T> w{T(0.5) * (keepA.x + wp.x), T(0.5) * (keepA.y + wp.y), T(0.5) * (keepA.z + wp.z)};
+        return renorm_if_float(rotate_half(ni, w, rot_half_factor(A.gp, A.dt)));
     }
 }
 
@@ -555,7 +579,7 @@ __global__ void __launch_bounds__(NT) k_batch_tiled(ShapeCoef<T> C, Site2D<T> Q,
 // Resident replicas: one workgroup holds a whole LX x LY replica (plus an R
 // halo of periodic images) in LDS and advances it n_steps Depondt steps
 // without touching HBM in between.  Each thread owns the sites
-// tid + j*NT and keeps their rotation vector A and thermal field in
+// tid + j*NT and keeps their rotation vector w and thermal field in
 // registers from predictor to corrector; the halo is refreshed after each
 // phase instead of recomputed.
 template <typename T, int S, int NDMI, int LX, int LY, int NT>
@@ -615,10 +639,10 @@ __global__ void __launch_bounds__(NT) k_batch_resident(ShapeCoef<T> C, Site2D<T>
                     Bth = Q.sigma * normals3(thermal_bits(A.key, (uint32_t)s), T(0));
                     B = B + Bth;
                 }
-                const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
-                keepA[j] = Ai;
+                const V3<T> wi = llg_w(ni, B, A.alpha);
+                keepA[j] = wi;
                 keepB[j] = Bth;
-                const V3<T> o = rotate_fast(ni, T(-1) * Ai, A.dt);
+                const V3<T> o = rotate_half(ni, wi, rot_half_factor(A.gp, A.dt));
                 sP[c] = o.x;
                 sP[P + c] = o.y;
                 sP[2 * P + c] = o.z;
@@ -646,11 +670,11 @@ __global__ void __launch_bounds__(NT) k_batch_resident(ShapeCoef<T> C, Site2D<T>
                 const V3<T> npi{sP[c], sP[P + c], sP[2 * P + c]};
                 const V3<T> g = shape_field_soa<T, S, NDMI, W>(C, Q, sP, sP + P, sP + 2 * P, c, npi);
                 const V3<T> B = (-Q.inv_mumuB) * g + keepB[j];
-                const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
-                const V3<T> w{T(-0.5) * (keepA[j].x + Ap.x), T(-0.5) * (keepA[j].y + Ap.y),
-                              T(-0.5) * (keepA[j].z + Ap.z)};
+                const V3<T> wp = llg_w(npi, B, A.alpha);
+                const V3<T> w{T(0.5) * (keepA[j].x + wp.x), T(0.5) * (keepA[j].y + wp.y),
+                              T(0.5) * (keepA[j].z + wp.z)};
                 const V3<T> ni{sN[c], sN[P + c], sN[2 * P + c]};
-                const V3<T> o = renorm_if_float(rotate_fast(ni, w, A.dt));
+                const V3<T> o = renorm_if_float(rotate_half(ni, w, rot_half_factor(A.gp, A.dt)));
                 sN[c] = o.x;
                 sN[P + c] = o.y;
                 sN[2 * P + c] = o.z;

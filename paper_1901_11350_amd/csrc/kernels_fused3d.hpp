@@ -10,7 +10,7 @@
 // halo; needs n(t) planes k-1..k+1) and the corrector of plane k-1 (needs
 // predictor planes k-2..k), which is written once to HBM.  Only two extra
 // predictor planes per column are recomputed (instead of a full 3D halo),
-// and each thread keeps the rotation vector / Heun slope and the thermal
+// and each thread keeps the rotation vector (Depondt) or slope (Heun) and the thermal
 // field of its own site from the predictor of a plane to its corrector one
 // iteration later.
 #pragma once
@@ -63,6 +63,18 @@ struct ShapeCoef3 {
     T D0;                    // the bulk form: D_b = D0 r_b on the six first-shell bonds
 };
 
+// The same coefficients divided by mu mu_B, for the step kernel: its bond
+// sums then give the field B = -dH/dn / (mu mu_B) in Tesla directly, with
+// the external field as their starting value.
+template <typename T>
+struct StepCoef3 {
+    T J[4];
+    T Dx[8], Dy[8], Dz[8];
+    T D0;
+    T K2;        // 2K / (mu mu_B)
+    T Bext[3];   // external field (Tesla)
+};
+
 // DMI of the streamed step kernel: none; any vectors on the first shell; or
 // the bulk form D0 r_b (r_b the bond direction) on the six nearest
 // neighbours, whose sum over the bonds is
@@ -86,25 +98,28 @@ struct PlaneLDS {
     V4<T> sP[3][PP];   // predictor plane k lives in slot k mod 3
 };
 
-// Field of one site from its 3 x 3 x 3 neighbourhood in LDS: bm, b0 and bp
-// point at cell (-1, -1) of the site's row in the planes below, at and above
-// it (row pitch W), so every neighbour is a non-negative compile-time offset
-// from one of three base addresses.  Neighbours are read six at a time as
-// full 16-byte cells, with one empty asm after each group keeping the
-// padding words live (else each read is narrowed to 12 bytes); a group's
-// reads are in flight together.  Shell sums start from their first
-// neighbour.  AN: the anisotropy term is formed (off when K = 0).
+// Field B = -dH/dn / (mu mu_B) (Tesla) of one site from its 3 x 3 x 3
+// neighbourhood in LDS, starting from base (the external plus thermal
+// field): bm, b0 and bp point at cell (-1, -1) of the site's row in the
+// planes below, at and above it (row pitch W), so every neighbour is a
+// non-negative compile-time offset from one of three base addresses.
+// Neighbours are read six at a time as full 16-byte cells, with one empty
+// asm after each group keeping the padding words live (else each read is
+// narrowed to 12 bytes); a group's reads are in flight together.  Shell
+// sums start from their first neighbour; each coefficient (a scalar
+// register) then enters one multiply-add per component.  AN: the
+// anisotropy term is formed (off when K = 0).
 template <typename T, int S, int DK, int W, bool AN>
-__device__ __forceinline__ V3<T> shape_field3(const ShapeCoef3<T>& C, const Site2D<T>& Q,
-                                              const V4<T>* __restrict__ bm, const V4<T>* __restrict__ b0,
-                                              const V4<T>* __restrict__ bp, V3<T> ni) {
+__device__ __forceinline__ V3<T> shape_B3(const StepCoef3<T>& C, const Site2D<T>& Q, const V4<T>* __restrict__ bm,
+                                          const V4<T>* __restrict__ b0, const V4<T>* __restrict__ bp, V3<T> ni,
+                                          V3<T> base) {
     using SH = ShapeTab3<S>;
     static_assert(SH::da[0] == 1 && SH::da[1] == -1 && SH::db[2] == 1 && SH::db[3] == -1 && SH::dc[4] == 1 &&
                       SH::dc[5] == -1,
                   "first six bonds are +x, -x, +y, -y, +z, -z");
     constexpr int G = 6;
     V3<T> acc[SH::NS];
-    V3<T> dm{T(0), T(0), T(0)};
+    V3<T> B = base;
     V3<T> nn[6];
 #pragma unroll
     for (int q0 = 0; q0 < SH::NB; q0 += G) {
@@ -136,10 +151,10 @@ __device__ __forceinline__ V3<T> shape_field3(const ShapeCoef3<T>& C, const Site
                 }
                 if constexpr (DK == DK_GENERAL) {
                     if (q < SH::NB0) {
-                        // n_j x D
-                        dm.x += x.y * C.Dz[q] - x.z * C.Dy[q];
-                        dm.y += x.z * C.Dx[q] - x.x * C.Dz[q];
-                        dm.z += x.x * C.Dy[q] - x.y * C.Dx[q];
+                        // + n_j x D
+                        B.x += x.y * C.Dz[q] - x.z * C.Dy[q];
+                        B.y += x.z * C.Dx[q] - x.x * C.Dz[q];
+                        B.z += x.x * C.Dy[q] - x.y * C.Dx[q];
                     }
                 }
                 if (q < 6) nn[q] = x;
@@ -147,24 +162,23 @@ __device__ __forceinline__ V3<T> shape_field3(const ShapeCoef3<T>& C, const Site
         }
     }
     if constexpr (DK == DK_BULK) {
-        dm.x = C.D0 * ((nn[4].y - nn[5].y) - (nn[2].z - nn[3].z));
-        dm.y = C.D0 * ((nn[0].z - nn[1].z) - (nn[4].x - nn[5].x));
-        dm.z = C.D0 * ((nn[2].x - nn[3].x) - (nn[0].y - nn[1].y));
+        B.x += C.D0 * ((nn[4].y - nn[5].y) - (nn[2].z - nn[3].z));
+        B.y += C.D0 * ((nn[0].z - nn[1].z) - (nn[4].x - nn[5].x));
+        B.z += C.D0 * ((nn[2].x - nn[3].x) - (nn[0].y - nn[1].y));
     }
-    V3<T> g{Q.gZ[0] - dm.x, Q.gZ[1] - dm.y, Q.gZ[2] - dm.z};
     if constexpr (AN) {
-        const T kn = Q.K2 * (Q.Kax[0] * ni.x + Q.Kax[1] * ni.y + Q.Kax[2] * ni.z);
-        g.x -= kn * Q.Kax[0];
-        g.y -= kn * Q.Kax[1];
-        g.z -= kn * Q.Kax[2];
+        const T kn = C.K2 * (Q.Kax[0] * ni.x + Q.Kax[1] * ni.y + Q.Kax[2] * ni.z);
+        B.x += kn * Q.Kax[0];
+        B.y += kn * Q.Kax[1];
+        B.z += kn * Q.Kax[2];
     }
 #pragma unroll
     for (int s = 0; s < SH::NS; ++s) {
-        g.x -= C.J[s] * acc[s].x;
-        g.y -= C.J[s] * acc[s].y;
-        g.z -= C.J[s] * acc[s].z;
+        B.x += C.J[s] * acc[s].x;
+        B.y += C.J[s] * acc[s].y;
+        B.z += C.J[s] * acc[s].z;
     }
-    return g;
+    return B;
 }
 
 // Plane index with periodic wrap, or in = false outside an open lattice.
@@ -179,11 +193,19 @@ __device__ __forceinline__ int wrap_plane(int z, int nc, int per, bool& in) {
 }
 
 template <typename T, int S, int DK, int TX, int TY, int SOLVER, bool AN>
-__global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site2D<T> Q, Site3D Z, LLGArgs<T> A_arg,
+__global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2D<T> Q, Site3D Z, LLGArgs<T> A_arg,
                                                             const int* __restrict__ abort_flag,
                                                             const T* __restrict__ n, T* __restrict__ nout) {
-    if (abort_flag && *abort_flag) return;
+    // The abort word and the step of a replayed graph are both consumed (by
+    // an empty asm) before the branch on the first, so their loads are in
+    // flight together instead of one after the other.
+    int abort_now = 0;
+    if (abort_flag) abort_now = *abort_flag;
     const LLGArgs<T> A = resolve_step(A_arg);
+    asm volatile("" ::"s"(abort_now), "s"(A.key.step_lo), "s"(A.key.step_hi));
+    if (abort_now) return;
+    const T hrot = rot_half_factor(A.gp, A.dt);
+    const V3<T> Bext{C.Bext[0], C.Bext[1], C.Bext[2]};
     using PL = PlaneLDS<T, S, TX, TY>;
     constexpr int R = PL::R, WN = PL::WN, PN = PL::PN, WP = PL::WP, PP = PL::PP;
     static_assert(R == 1, "one-cell stencil reach");
@@ -282,27 +304,26 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
         return Q.sigma * normals3(thermal_bits(A.key, (uint32_t)(off + gz)), T(0));
     };
     // predictor of predictor cell (px, py) of plane z into predictor slot
-    // pslot(z); returns what the corrector needs of the site
-    auto predict = [&](int px, int py, bool in, int z, V3<T> Bth) -> V3<T> {
+    // pslot(z), base the cell's external plus thermal field; returns what
+    // the corrector needs of the site
+    auto predict = [&](int px, int py, bool in, int z, V3<T> base) -> V3<T> {
         V4<T> out{T(0), T(0), T(0), T(0)};
         V3<T> keep{T(0), T(0), T(0)};
         if (in) {
             const int c = (py + R) * WN + (px + R);
             const V3<T> ni = lds_cell_xyz(L.sN[z & 3], c);
             const int cb = c - WN - 1;
-            const V3<T> g = shape_field3<T, S, DK, WN, AN>(C, Q, L.sN[(z - 1) & 3] + cb, L.sN[z & 3] + cb,
-                                                           L.sN[(z + 1) & 3] + cb, ni);
-            const V3<T> B = (-Q.inv_mumuB) * g + Bth;
-            const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
+            const V3<T> B = shape_B3<T, S, DK, WN, AN>(C, Q, L.sN[(z - 1) & 3] + cb, L.sN[z & 3] + cb,
+                                                       L.sN[(z + 1) & 3] + cb, ni, base);
             V3<T> o;
             if constexpr (SOLVER == SOLVER_HEUN) {
-                keep = cross(ni, Ai);
+                keep = cross(ni, llg_A(ni, B, A.gp, A.alpha));
                 o = normalize3(ni + A.dt * keep);
             } else if constexpr (SOLVER == SOLVER_SIB) {
-                o = T(0.5) * (ni + sib_stage(ni, Ai, A.dt));
+                o = T(0.5) * (ni + sib_stage(ni, llg_A(ni, B, A.gp, A.alpha), A.dt));
             } else {
-                keep = Ai;
-                o = rotate_fast(ni, T(-1) * Ai, A.dt);
+                keep = llg_w(ni, B, A.alpha);
+                o = rotate_half(ni, keep, hrot);
             }
             out = V4<T>{o.x, o.y, o.z, T(0)};
         }
@@ -310,24 +331,41 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
         return keep;
     };
 
-    // pipeline: predictor planes z0-1 .. z1, corrector planes z0 .. z1-1
+    // pipeline: predictor planes z0-1 .. z1, corrector planes z0 .. z1-1.
+    // The first three planes are loaded together: at launch every workgroup
+    // waits for them, so their loads share one memory round trip.
     V3<T> st[KST];
-    load_plane(z0 - 2, st);
-    store_plane(z0 - 2, st);
-    load_plane(z0 - 1, st);
-    store_plane(z0 - 1, st);
-    load_plane(z0, st);
-    V3<T> keepA{T(0), T(0), T(0)}, keepB{T(0), T(0), T(0)};   // of the previous plane
+    {
+        V3<T> s0[KST], s1[KST];
+        load_plane(z0 - 2, s0);
+        load_plane(z0 - 1, s1);
+        load_plane(z0, st);
+        store_plane(z0 - 2, s0);
+        store_plane(z0 - 1, s1);
+    }
+    V3<T> keepA{T(0), T(0), T(0)}, keepB{T(0), T(0), T(0)};   // of the previous plane (keepB: base field)
     const int cP = (tyy + R) * WP + (tx + R);                  // the site's predictor cell
     const int cN = (tyy + 2 * R) * WN + (tx + 2 * R);          // the site's n(t) cell
     for (int k = z0 - 1; k <= z1; ++k) {
         bool zin = true;
         const long long gz = wrap_plane(k, Z.nc, Z.per_c, zin) * plane;
-        // thermal fields of this thread's cells of plane k, then stage n(t) plane k+1
-        const V3<T> bI = thermal(zin && pi_in, pi_off, gz);
+        // external plus thermal fields of this thread's cells of plane k,
+        // then stage n(t) plane k+1.  The empty asm keeps the thermal draws
+        // inside the branch: left
+        // free, the compiler moves the ring cells' draw into the predictor and
+        // runs it at T = 0 too, selecting zero afterwards.
+        V3<T> bI = Bext;
         V3<T> bR[KRG];
 #pragma unroll
-        for (int q = 0; q < KRG; ++q) bR[q] = thermal(zin && rg_in[q], rg_off[q], gz);
+        for (int q = 0; q < KRG; ++q) bR[q] = Bext;
+        if (A.thermal) {
+            bI = Bext + thermal(zin && pi_in, pi_off, gz);
+#pragma unroll
+            for (int q = 0; q < KRG; ++q) {
+                bR[q] = Bext + thermal(zin && rg_in[q], rg_off[q], gz);
+                asm volatile("" : "+v"(bR[q].x), "+v"(bR[q].y), "+v"(bR[q].z));
+            }
+        }
         store_plane(k + 1, st);
         if (k + 2 <= z1 + 1) load_plane(k + 2, st);
         __syncthreads();
@@ -341,19 +379,18 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(ShapeCoef3<T> C, Site
         if (zc >= z0 && zc < z1 && own_site) {
             const V3<T> npi = lds_cell_xyz(L.sP[pslot(zc)], cP);
             const int cb = cP - WP - 1;
-            const V3<T> g = shape_field3<T, S, DK, WP, AN>(C, Q, L.sP[pslot(zc - 1)] + cb, L.sP[pslot(zc)] + cb,
-                                                           L.sP[pslot(zc + 1)] + cb, npi);
-            const V3<T> B = (-Q.inv_mumuB) * g + keepB;
-            const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
+            const V3<T> B = shape_B3<T, S, DK, WP, AN>(C, Q, L.sP[pslot(zc - 1)] + cb, L.sP[pslot(zc)] + cb,
+                                                       L.sP[pslot(zc + 1)] + cb, npi, keepB);
             const V3<T> ni = lds_cell_xyz(L.sN[zc & 3], cN);
             V3<T> o;
             if constexpr (SOLVER == SOLVER_HEUN) {
-                o = normalize3(ni + (T(0.5) * A.dt) * (keepA + cross(npi, Ap)));
+                o = normalize3(ni + (T(0.5) * A.dt) * (keepA + cross(npi, llg_A(npi, B, A.gp, A.alpha))));
             } else if constexpr (SOLVER == SOLVER_SIB) {
-                o = renorm_if_float(sib_stage(ni, Ap, A.dt));
+                o = renorm_if_float(sib_stage(ni, llg_A(npi, B, A.gp, A.alpha), A.dt));
             } else {
-                const V3<T> w{T(-0.5) * (keepA.x + Ap.x), T(-0.5) * (keepA.y + Ap.y), T(-0.5) * (keepA.z + Ap.z)};
-                o = renorm_if_float(rotate_fast(ni, w, A.dt));
+                const V3<T> wp = llg_w(npi, B, A.alpha);
+                const V3<T> w{T(0.5) * (keepA.x + wp.x), T(0.5) * (keepA.y + wp.y), T(0.5) * (keepA.z + wp.z)};
+                o = renorm_if_float(rotate_half(ni, w, hrot));
             }
             const long long gi = pi_off + (long long)zc * plane;
             store_out(nout + gi, o.x);

@@ -137,20 +137,20 @@ __device__ __forceinline__ void tile_ring_cell(int h, int& px, int& py, int& pz)
 
 // One predictor of a cell with field g and thermal field Bth: the spin the
 // corrector's field is evaluated on, and (returned through keep) what the
-// corrector needs of the site: Depondt n^p = R(A) n, keeps A; Heun
-// n^p = (n + dt n x A)/|...|, keeps n x A; SIB the midpoint of the
-// implicit stage with A frozen (Appendix C).
+// corrector needs of the site: Depondt n^p = R(A) n, keeps the rotation
+// vector w = B + alpha n x B (A = -gp w); Heun n^p = (n + dt n x A)/|...|,
+// keeps n x A; SIB the midpoint of the implicit stage with A frozen
+// (Appendix C).
 template <typename T, int SOLVER>
 __device__ __forceinline__ V3<T> tile_predict(V3<T> ni, V3<T> B, const LLGArgs<T>& A, V3<T>& keep) {
-    const V3<T> Ai = llg_A(ni, B, A.gp, A.alpha);
     if constexpr (SOLVER == SOLVER_HEUN) {
-        keep = cross(ni, Ai);
+        keep = cross(ni, llg_A(ni, B, A.gp, A.alpha));
         return normalize3(ni + A.dt * keep);
     } else if constexpr (SOLVER == SOLVER_SIB) {
-        return T(0.5) * (ni + sib_stage(ni, Ai, A.dt));
+        return T(0.5) * (ni + sib_stage(ni, llg_A(ni, B, A.gp, A.alpha), A.dt));
     } else {
-        keep = Ai;
-        return rotate_fast(ni, T(-1) * Ai, A.dt);
+        keep = llg_w(ni, B, A.alpha);
+        return rotate_half(ni, keep, rot_half_factor(A.gp, A.dt));
     }
 }
 
@@ -256,16 +256,16 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
     const V3<T> npi = lds_cell_xyz(sP, beta * PP + pc);
     const V3<T> g = tile_field(S, Q, beta, sP, S.offP, pc, npi);
     const V3<T> B = (-Q.inv_mumuB[beta]) * g + Bth;
-    const V3<T> Ap = llg_A(npi, B, A.gp, A.alpha);
     const V3<T> ni = lds_cell_xyz(sN, beta * PN + ((tz + 2 * RC) * HN + (ty + 2 * R)) * WN + (tx + 2 * R));
     V3<T> o;
     if constexpr (SOLVER == SOLVER_HEUN) {
-        o = normalize3(ni + (T(0.5) * A.dt) * (keep + cross(npi, Ap)));
+        o = normalize3(ni + (T(0.5) * A.dt) * (keep + cross(npi, llg_A(npi, B, A.gp, A.alpha))));
     } else if constexpr (SOLVER == SOLVER_SIB) {
-        o = renorm_if_float(sib_stage(ni, Ap, A.dt));
+        o = renorm_if_float(sib_stage(ni, llg_A(npi, B, A.gp, A.alpha), A.dt));
     } else {
-        const V3<T> w{T(-0.5) * (keep.x + Ap.x), T(-0.5) * (keep.y + Ap.y), T(-0.5) * (keep.z + Ap.z)};
-        o = renorm_if_float(rotate_fast(ni, w, A.dt));
+        const V3<T> wp = llg_w(npi, B, A.alpha);
+        const V3<T> w{T(0.5) * (keep.x + wp.x), T(0.5) * (keep.y + wp.y), T(0.5) * (keep.z + wp.z)};
+        o = renorm_if_float(rotate_half(ni, w, rot_half_factor(A.gp, A.dt)));
     }
     const int gi = ox + na * (oy + nbc * oz) + beta * block;
     store_out(nout + gi, o.x);
