@@ -830,6 +830,26 @@ sp::ShapeCoef<T> shape_coef_for(const sp_engine* e) {
     return C;
 }
 
+// The step kernels' coefficients: those of shape_coef_for divided by
+// mu mu_B (in double, then rounded), anisotropy likewise, and the external
+// field in Tesla.
+template <typename T, int S>
+sp::StepCoef<T> step_coef_for(const sp_engine* e) {
+    using SH = sp::ShapeTab<S>;
+    const double inv = 1.0 / (e->ham.mu[0] * kMuB);
+    sp::StepCoef<T> C{};
+    for (int s = 0; s < SH::NS; ++s) C.J[s] = (T)(s < e->ham.n_exch ? e->ham.J[s] * inv : 0.0);
+    for (int q = 0; q < SH::NB; ++q)
+        for (const HostBond& b : e->all_bonds)
+            if (b.d[0] == SH::da[q] && b.d[1] == SH::db[q] && b.shell == SH::sh[q]) {
+                C.Dx[q] = (T)(b.D[0] * inv);
+                C.Dy[q] = (T)(b.D[1] * inv);
+            }
+    C.K2 = (T)(2.0 * e->ham.K[0] * inv);
+    for (int k = 0; k < 3; ++k) C.Bext[k] = (T)e->ham.B[k];
+    return C;
+}
+
 template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER>
 void go_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* nin, void* nout) {
     sp::TileMap M{};
@@ -838,7 +858,7 @@ void go_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* n
     const int ntiles = M.tiles_x * M.tiles_y;
     M.xcd_bands = (ntiles >= 8 && ntiles % 8 == 0) ? 1 : 0;
     hipLaunchKernelGGL((sp::k_fused2d_shape<T, S, NDMI, TX, TY, NT, SOLVER>), dim3((unsigned)ntiles), dim3(NT), 0, e->stream,
-                       shape_coef_for<T, S>(e), make_site2d<T>(e, p), make_step_llg<T>(e, p, step), M, e->d_flag,
+                       step_coef_for<T, S>(e), make_site2d<T>(e, p), make_step_llg<T>(e, p, step), M, e->d_flag,
                        static_cast<const T*>(nin), static_cast<T*>(nout));
 }
 
@@ -943,7 +963,7 @@ int go_persist(sp_engine* e, const sp_llg_params* p, int n_steps, bool check_onl
     // SP_PERSIST_SPIN_LIMIT lowers the bound (tests of the time-out path)
     M.spin_limit = kPersistSpinLimit;
     if (const char* lim = std::getenv("SP_PERSIST_SPIN_LIMIT")) M.spin_limit = std::max(0, std::atoi(lim));
-    sp::ShapeCoef<T> C = shape_coef_for<T, S>(e);
+    sp::StepCoef<T> C = step_coef_for<T, S>(e);
     sp::Site2D<T> Q = make_site2d<T>(e, p);
     sp::LLGArgs<T> A = make_llg<T>(p, e->step, p->replica);
     const int* abort_flag = e->d_flag;
@@ -2595,6 +2615,7 @@ struct sp_batch {
     std::vector<HostBond> all_bonds;
     int n_shells = 0, shape = -1, shape_ndmi = 0;
     sp::ShapeCoef<float> C{};
+    sp::StepCoef<float> SC{};   // the tiled replicas' step kernel (as the single-engine step)
     sp::Site2D<float> Q{};
     std::vector<BatchRep> reps;
     bool finalized = false;
@@ -2747,10 +2768,10 @@ template <int S, int NDMI>
 void batch_launch_tiled(sp_batch* b, hipStream_t s, int k, int parity) {
     if (!b->n_work) return;
     if (b->cfg == 1)
-        hipLaunchKernelGGL((sp::k_batch_tiled<float, S, NDMI, 64, 16, 1024>), dim3(b->n_work), dim3(1024), 0, s, b->C,
+        hipLaunchKernelGGL((sp::k_batch_tiled<float, S, NDMI, 64, 16, 1024>), dim3(b->n_work), dim3(1024), 0, s, b->SC,
                            b->Q, b->d_reps, b->d_work, b->d_step, k, parity);
     else
-        hipLaunchKernelGGL((sp::k_batch_tiled<float, S, NDMI, 32, 16, 512>), dim3(b->n_work), dim3(512), 0, s, b->C,
+        hipLaunchKernelGGL((sp::k_batch_tiled<float, S, NDMI, 32, 16, 512>), dim3(b->n_work), dim3(512), 0, s, b->SC,
                            b->Q, b->d_reps, b->d_work, b->d_step, k, parity);
 }
 
@@ -2925,12 +2946,12 @@ int sp_batch_add(sp_batch* b, sp_engine* e, const sp_llg_params* p) {
         b->shape = e->shape;
         b->shape_ndmi = e->shape_ndmi;
         switch (e->shape) {
-            case sp::SH_SQ1: b->C = shape_coef_for<float, sp::SH_SQ1>(e); break;
-            case sp::SH_SQ2: b->C = shape_coef_for<float, sp::SH_SQ2>(e); break;
-            case sp::SH_SQ3: b->C = shape_coef_for<float, sp::SH_SQ3>(e); break;
-            case sp::SH_TRI1: b->C = shape_coef_for<float, sp::SH_TRI1>(e); break;
-            case sp::SH_TRI2: b->C = shape_coef_for<float, sp::SH_TRI2>(e); break;
-            default: b->C = shape_coef_for<float, sp::SH_TRI3>(e); break;
+            case sp::SH_SQ1: b->C = shape_coef_for<float, sp::SH_SQ1>(e); b->SC = step_coef_for<float, sp::SH_SQ1>(e); break;
+            case sp::SH_SQ2: b->C = shape_coef_for<float, sp::SH_SQ2>(e); b->SC = step_coef_for<float, sp::SH_SQ2>(e); break;
+            case sp::SH_SQ3: b->C = shape_coef_for<float, sp::SH_SQ3>(e); b->SC = step_coef_for<float, sp::SH_SQ3>(e); break;
+            case sp::SH_TRI1: b->C = shape_coef_for<float, sp::SH_TRI1>(e); b->SC = step_coef_for<float, sp::SH_TRI1>(e); break;
+            case sp::SH_TRI2: b->C = shape_coef_for<float, sp::SH_TRI2>(e); b->SC = step_coef_for<float, sp::SH_TRI2>(e); break;
+            default: b->C = shape_coef_for<float, sp::SH_TRI3>(e); b->SC = step_coef_for<float, sp::SH_TRI3>(e); break;
         }
         b->Q = make_site2d<float>(e, nullptr);
         b->has_template = true;

@@ -86,6 +86,17 @@ struct ShapeCoef {
     T Dx[24], Dy[24];  // per bond (D_z = 0 for in-plane bonds)
 };
 
+// The same divided by mu mu_B, for the step kernels: their bond sums then
+// give the field B = -dH/dn / (mu mu_B) in Tesla directly, starting from
+// the external (plus thermal) field.
+template <typename T>
+struct StepCoef {
+    T J[4];
+    T Dx[24], Dy[24];
+    T K2;        // 2K / (mu mu_B)
+    T Bext[3];   // external field (Tesla)
+};
+
 template <typename T>
 __device__ __forceinline__ void native_sincos(T x, T* s, T* c) {
     if constexpr (sizeof(T) == 4) {
@@ -280,6 +291,65 @@ __device__ __forceinline__ V3<T> shape_field_aos(const ShapeCoef<T>& C, const Si
     return g;
 }
 
+// The field B (Tesla) of a step kernel on 16-byte LDS cells, read as in
+// shape_field_aos, from coefficients divided by mu mu_B and starting from
+// base (external plus thermal field): each coefficient (a scalar register)
+// enters one multiply-add per component.
+template <typename T, int S, int NDMI, int W>
+__device__ __forceinline__ V3<T> shape_B_aos(const StepCoef<T>& C, const Site2D<T>& Q, const V4<T>* __restrict__ sv,
+                                             int c, V3<T> ni, V3<T> base) {
+    using SH = ShapeTab<S>;
+    constexpr int G = 6;
+    V3<T> acc[SH::NS];
+    V3<T> B = base;
+#pragma unroll
+    for (int q0 = 0; q0 < SH::NB; q0 += G) {
+        V4<T> v[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int q = q0 + k;
+            if (q < SH::NB)
+                v[k] = sv[c + SH::da[q] + SH::db[q] * W];
+            else
+                v[k] = v[0];
+        }
+        if constexpr (sizeof(T) == 4)
+            asm volatile("" ::"v"(v[0].w), "v"(v[1].w), "v"(v[2].w), "v"(v[3].w), "v"(v[4].w), "v"(v[5].w));
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int q = q0 + k;
+            if (q < SH::NB) {
+                const V3<T> nj{v[k].x, v[k].y, v[k].z};
+                const int sh = SH::sh[q];
+                if (first_of_shell<SH>(q)) {
+                    acc[sh] = nj;
+                } else {
+                    acc[sh].x += nj.x;
+                    acc[sh].y += nj.y;
+                    acc[sh].z += nj.z;
+                }
+                if (q < NDMI) {
+                    // + n_j x D with D = (Dx, Dy, 0)
+                    B.x -= nj.z * C.Dy[q];
+                    B.y += nj.z * C.Dx[q];
+                    B.z += nj.x * C.Dy[q] - nj.y * C.Dx[q];
+                }
+            }
+        }
+    }
+    const T kn = C.K2 * (Q.Kax[0] * ni.x + Q.Kax[1] * ni.y + Q.Kax[2] * ni.z);
+    B.x += kn * Q.Kax[0];
+    B.y += kn * Q.Kax[1];
+    B.z += kn * Q.Kax[2];
+#pragma unroll
+    for (int s = 0; s < SH::NS; ++s) {
+        B.x += C.J[s] * acc[s].x;
+        B.y += C.J[s] * acc[s].y;
+        B.z += C.J[s] * acc[s].z;
+    }
+    return B;
+}
+
 struct TileMap {
     int tiles_x, tiles_y;
     int xcd_bands;   // 1: XCD-banded mapping (tile count divisible by 8), 0: identity
@@ -319,15 +389,17 @@ __device__ __forceinline__ int cell_site(const Site2D<T>& Q, int x0, int y0, int
     return gx + gy * Q.na;
 }
 
-// Thermal field of a predictor-frame cell: depends only on the site, the
-// step and the seed, so it is formed while the spins are still in flight.
+// External plus thermal field of a predictor-frame cell (the base of
+// shape_B_aos): depends only on the site, the step and the seed, so it is
+// formed while the spins are still in flight.
 template <typename T, int S, int TX, int TY>
-__device__ __forceinline__ V3<T> cell_thermal(const Site2D<T>& Q, const LLGArgs<T>& A, int x0, int y0, int px,
-                                              int py) {
+__device__ __forceinline__ V3<T> cell_base(const StepCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int x0,
+                                           int y0, int px, int py) {
     bool in;
     const int site = cell_site<T, S, TX, TY>(Q, x0, y0, px, py, in);
-    if (!A.thermal || !in) return V3<T>{T(0), T(0), T(0)};
-    return Q.sigma * normals3(thermal_bits(A.key, (uint32_t)site), T(0));
+    const V3<T> Bext{C.Bext[0], C.Bext[1], C.Bext[2]};
+    if (!A.thermal || !in) return Bext;
+    return Bext + Q.sigma * normals3(thermal_bits(A.key, (uint32_t)site), T(0));
 }
 
 // Ring cell h (0 <= h < ring size) of the predictor frame: R rows above and
@@ -347,8 +419,8 @@ __device__ __forceinline__ void ring_cell(int h, int& px, int& py) {
     }
 }
 
-// Predictor of one predictor-frame cell (px, py) with its thermal field
-// Bth.  Writes to sP what the corrector's field is evaluated on and returns
+// Predictor of one predictor-frame cell (px, py) with its external plus
+// thermal field base.  Writes to sP what the corrector's field is evaluated on and returns
 // what the corrector needs of the site itself:
 //   Depondt: n^p = R(A) n, returns w = B + alpha n x B (A = -gp w);
 //   Heun:    n^p = (n + dt n x A) / |...|, returns f = n x A;
@@ -356,8 +428,8 @@ __device__ __forceinline__ void ring_cell(int h, int& px, int& py) {
 //            midpoint m = (n + x)/2 (Appendix C), returns nothing.
 // Cells that fall outside an open lattice hold a zero spin.
 template <typename T, int S, int NDMI, int TX, int TY, int SOLVER>
-__device__ __forceinline__ V3<T> predict_cell(const ShapeCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int x0,
-                                              int y0, int px, int py, TileLDS<T, S, TX, TY>& L, V3<T> Bth) {
+__device__ __forceinline__ V3<T> predict_cell(const StepCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int x0,
+                                              int y0, int px, int py, TileLDS<T, S, TX, TY>& L, V3<T> base) {
     using TL = TileLDS<T, S, TX, TY>;
     constexpr int R = TL::R, WN = TL::WN, WP = TL::WP;
     bool in;
@@ -367,8 +439,7 @@ __device__ __forceinline__ V3<T> predict_cell(const ShapeCoef<T>& C, const Site2
     if (in) {
         const int c = (py + R) * WN + (px + R);
         const V3<T> ni = lds_cell_xyz(L.sN, c);
-        const V3<T> g = shape_field_aos<T, S, NDMI, WN>(C, Q, L.sN, c, ni);
-        const V3<T> B = (-Q.inv_mumuB) * g + Bth;
+        const V3<T> B = shape_B_aos<T, S, NDMI, WN>(C, Q, L.sN, c, ni, base);
         V3<T> o;
         if constexpr (SOLVER == SOLVER_HEUN) {
             keep = cross(ni, llg_A(ni, B, A.gp, A.alpha));
@@ -388,17 +459,16 @@ __device__ __forceinline__ V3<T> predict_cell(const ShapeCoef<T>& C, const Site2
 }
 
 // Corrector of tile site (tx, ty) from the predictor cells in sP, the spin
-// n(t) in sN and what the predictor kept for the site (A or n x A, and the
-// thermal field): returns n(t+dt).
+// n(t) in sN and what the predictor kept for the site (w or n x A, and the
+// external plus thermal field): returns n(t+dt).
 template <typename T, int S, int NDMI, int TX, int TY, int SOLVER>
-__device__ __forceinline__ V3<T> correct_cell(const ShapeCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int tx,
+__device__ __forceinline__ V3<T> correct_cell(const StepCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int tx,
                                               int ty, const TileLDS<T, S, TX, TY>& L, V3<T> keepA, V3<T> keepB) {
     using TL = TileLDS<T, S, TX, TY>;
     constexpr int R = TL::R, WN = TL::WN, WP = TL::WP;
     const int c = (ty + R) * WP + (tx + R);
     const V3<T> npi = lds_cell_xyz(L.sP, c);
-    const V3<T> g = shape_field_aos<T, S, NDMI, WP>(C, Q, L.sP, c, npi);
-    const V3<T> B = (-Q.inv_mumuB) * g + keepB;
+    const V3<T> B = shape_B_aos<T, S, NDMI, WP>(C, Q, L.sP, c, npi, keepB);
     const V3<T> ni = lds_cell_xyz(L.sN, (ty + 2 * R) * WN + (tx + 2 * R));
     if constexpr (SOLVER == SOLVER_HEUN) {
         // n + dt (f(n) + f(n^p)) / 2, renormalised
@@ -419,7 +489,7 @@ __device__ __forceinline__ V3<T> correct_cell(const ShapeCoef<T>& C, const Site2
 // thermal field in registers, and computes their corrector; the ring of
 // predictor cells around the tile is shared out over the threads between.
 template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER = SOLVER_DEPONDT>
-__device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A,
+__device__ __forceinline__ void fused2d_tile(const StepCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A,
                                              int x0, int y0, const T* __restrict__ n, T* __restrict__ nout,
                                              TileLDS<T, S, TX, TY>& L) {
     using TL = TileLDS<T, S, TX, TY>;
@@ -449,13 +519,13 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
             }
         }
     }
-    // 2) thermal fields of the owned cells while the loads are in flight
+    // 2) external plus thermal fields of the owned cells while the loads are in flight
     V3<T> keepB[KPT], ringB[KRG];
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
         const int t = tid + j * NT;
         const int ty = t / TX, tx = t - ty * TX;
-        keepB[j] = cell_thermal<T, S, TX, TY>(Q, A, x0, y0, tx + R, ty + R);
+        keepB[j] = cell_base<T, S, TX, TY>(C, Q, A, x0, y0, tx + R, ty + R);
     }
 #pragma unroll
     for (int k = 0; k < KRG; ++k) {
@@ -464,7 +534,7 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
         if (h < RING) {
             int px, py;
             ring_cell<R, TX, TY>(h, px, py);
-            ringB[k] = cell_thermal<T, S, TX, TY>(Q, A, x0, y0, px, py);
+            ringB[k] = cell_base<T, S, TX, TY>(C, Q, A, x0, y0, px, py);
         }
     }
 #pragma unroll
@@ -509,7 +579,7 @@ __device__ __forceinline__ void fused2d_tile(const ShapeCoef<T>& C, const Site2D
 }
 
 template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER = SOLVER_DEPONDT>
-__global__ void __launch_bounds__(NT) k_fused2d_shape(ShapeCoef<T> C, Site2D<T> Q, LLGArgs<T> A_arg, TileMap M,
+__global__ void __launch_bounds__(NT) k_fused2d_shape(StepCoef<T> C, Site2D<T> Q, LLGArgs<T> A_arg, TileMap M,
                                                       const int* __restrict__ abort_flag, const T* __restrict__ n,
                                                       T* __restrict__ nout) {
     if (abort_flag && *abort_flag) return;
@@ -559,7 +629,7 @@ __device__ __forceinline__ void replica_args(const ReplicaDesc<T>& R, unsigned l
 // (replica, tile) per workgroup.  The step number is *step_base + k, so a
 // captured graph of k = 0..K-1 can be replayed after step_base advances.
 template <typename T, int S, int NDMI, int TX, int TY, int NT>
-__global__ void __launch_bounds__(NT) k_batch_tiled(ShapeCoef<T> C, Site2D<T> Q, const ReplicaDesc<T>* __restrict__ reps,
+__global__ void __launch_bounds__(NT) k_batch_tiled(StepCoef<T> C, Site2D<T> Q, const ReplicaDesc<T>* __restrict__ reps,
                                                     const int2* __restrict__ work,
                                                     const unsigned long long* __restrict__ step_base, int k,
                                                     int parity) {

@@ -14,7 +14,7 @@
 // finished step s-1, i.e. has read everything it needed from it.
 //
 // Per step, the arithmetic is that of the fused one-launch-per-step kernel:
-// the same predictor, corrector and thermal-field routines on the same cells.  The order of the work hides the halo
+// the same predictor, corrector and base-field routines on the same cells.  The order of the work hides the halo
 // traffic: the predictor of the sites at least R from the tile edge needs no
 // halo and runs while the neighbours' flags are awaited; the halo is then
 // loaded, the edge sites and the R-ring of predictor cells are computed, and
@@ -65,7 +65,7 @@ __device__ __forceinline__ bool persist_wait(const uint32_t* flags, int* status,
 }
 
 template <typename T, int S, int NDMI, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) k_persist2d(ShapeCoef<T> C, Site2D<T> Q, LLGArgs<T> A, PersistMap M,
+__global__ void __launch_bounds__(TX * TY) k_persist2d(StepCoef<T> C, Site2D<T> Q, LLGArgs<T> A, PersistMap M,
                                                         const int* __restrict__ abort_flag, T* b0, T* b1,
                                                         uint32_t* flags, int* status) {
     using TL = TileLDS<T, S, TX, TY>;
@@ -137,9 +137,9 @@ __global__ void __launch_bounds__(TX * TY) k_persist2d(ShapeCoef<T> C, Site2D<T>
     V3<T> own{b0[gsite], b0[N + gsite], b0[2 * N + gsite]};
     L.sN[own_c] = V4<T>{own.x, own.y, own.z, T(0)};
     set_step(0);
-    V3<T> Bown = cell_thermal<T, S, TX, TY>(Q, A, x0, y0, tx + R, ty + R);
+    V3<T> Bown = cell_base<T, S, TX, TY>(C, Q, A, x0, y0, tx + R, ty + R);
     V3<T> Bring{T(0), T(0), T(0)};
-    if (rank >= 0 && rank < RING) Bring = cell_thermal<T, S, TX, TY>(Q, A, x0, y0, rpx, rpy);
+    if (rank >= 0 && rank < RING) Bring = cell_base<T, S, TX, TY>(C, Q, A, x0, y0, rpx, rpy);
     if (tid == 0) s_fail = 0;
     __syncthreads();
 
@@ -182,11 +182,11 @@ __global__ void __launch_bounds__(TX * TY) k_persist2d(ShapeCoef<T> C, Site2D<T>
         __hip_atomic_store(nout + gsite, own.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(nout + N + gsite, own.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(nout + 2 * N + gsite, own.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // thermal fields of the next step while the stores drain
+        // external plus thermal fields of the next step while the stores drain
         if (s + 1 < M.n_steps) {
             set_step(s + 1);
-            Bown = cell_thermal<T, S, TX, TY>(Q, A, x0, y0, tx + R, ty + R);
-            if (rank >= 0 && rank < RING) Bring = cell_thermal<T, S, TX, TY>(Q, A, x0, y0, rpx, rpy);
+            Bown = cell_base<T, S, TX, TY>(C, Q, A, x0, y0, tx + R, ty + R);
+            if (rank >= 0 && rank < RING) Bring = cell_base<T, S, TX, TY>(C, Q, A, x0, y0, rpx, rpy);
         }
         // every wave's stores precede the barrier; the one agent-scope
         // release of the flag store then covers the whole tile
