@@ -1123,7 +1123,24 @@ void go_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* 
     const int nchunks = (Z.nc + Z.zc - 1) / Z.zc;
     Z.xcd_bands = ((txy * nchunks) % 8 == 0) ? 1 : 0;
     const dim3 grid((unsigned)(txy * nchunks)), block(TX * TY);
-    // Depondt steps without anisotropy take the instance that leaves the term out
+    // Depondt steps without anisotropy take the instance that leaves the term
+    // out; on the 32 x 32 columns a lattice periodic along every axis takes
+    // the instance without boundary tests
+    if constexpr (SOLVER == sp::SOLVER_DEPONDT && TX * TY == 1024) {
+        if (e->geo.per[0] && e->geo.per[1] && e->geo.per[2]) {
+            if (e->ham.K[0] == 0.0)
+                hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, DK, TX, TY, SOLVER, false, true>), grid, block, 0,
+                                   e->stream, step_coef3_for<T, S>(e), make_site2d<T>(e, p), Z,
+                                   make_step_llg<T>(e, p, step), e->d_flag, static_cast<const T*>(nin),
+                                   static_cast<T*>(nout));
+            else
+                hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, DK, TX, TY, SOLVER, true, true>), grid, block, 0,
+                                   e->stream, step_coef3_for<T, S>(e), make_site2d<T>(e, p), Z,
+                                   make_step_llg<T>(e, p, step), e->d_flag, static_cast<const T*>(nin),
+                                   static_cast<T*>(nout));
+            return;
+        }
+    }
     if constexpr (SOLVER == sp::SOLVER_DEPONDT) {
         if (e->ham.K[0] == 0.0) {
             hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, DK, TX, TY, SOLVER, false>), grid, block, 0, e->stream,

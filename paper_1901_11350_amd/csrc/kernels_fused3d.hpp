@@ -192,7 +192,9 @@ __device__ __forceinline__ int wrap_plane(int z, int nc, int per, bool& in) {
     return z < 0 ? z + nc : z;
 }
 
-template <typename T, int S, int DK, int TX, int TY, int SOLVER, bool AN>
+// PER: every axis periodic (the lattice wraps, no cell is ever outside it),
+// so the boundary tests and the zero fills of outside cells are compiled out.
+template <typename T, int S, int DK, int TX, int TY, int SOLVER, bool AN, bool PER = false>
 __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2D<T> Q, Site3D Z, LLGArgs<T> A_arg,
                                                             const int* __restrict__ abort_flag,
                                                             const T* __restrict__ n, T* __restrict__ nout) {
@@ -237,6 +239,7 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2
     // Everything in a and b is the same on every plane: the staged cells'
     // in-plane offsets and in-sample flags, the predictor cells this thread
     // owns (its site and its ring cells) and their LDS positions.
+    const int per_a = PER ? 1 : Q.per_a, per_b = PER ? 1 : Q.per_b, per_c = PER ? 1 : Z.per_c;
     long long ld_off[KST];
     bool ld_in[KST];
 #pragma unroll
@@ -244,8 +247,8 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2
         const int idx = tid + k * NT;
         const int ly = idx / WN, lx = idx - ly * WN;
         bool in = idx < PN;
-        const int gx = wrap_once(x0 - 2 * R + lx, NA, Q.per_a, in);
-        const int gy = wrap_once(y0 - 2 * R + ly, NBB, Q.per_b, in);
+        const int gx = wrap_once(x0 - 2 * R + lx, NA, per_a, in);
+        const int gy = wrap_once(y0 - 2 * R + ly, NBB, per_b, in);
         ld_off[k] = gx + (long long)NA * gy;
         ld_in[k] = in;
     }
@@ -254,8 +257,8 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2
     bool pi_in = true;
     long long pi_off;
     {
-        const int gx = wrap_once(x0 + tx, NA, Q.per_a, pi_in);
-        const int gy = wrap_once(y0 + tyy, NBB, Q.per_b, pi_in);
+        const int gx = wrap_once(x0 + tx, NA, per_a, pi_in);
+        const int gy = wrap_once(y0 + tyy, NBB, per_b, pi_in);
         pi_off = gx + (long long)NA * gy;
     }
     int rg_px[KRG], rg_py[KRG];
@@ -267,8 +270,8 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2
         rg_in[q] = h < RING;
         int px = 0, py = 0;
         if (rg_in[q]) ring_cell<R, TX, TY>(h, px, py);
-        const int gx = wrap_once(x0 - R + px, NA, Q.per_a, rg_in[q]);
-        const int gy = wrap_once(y0 - R + py, NBB, Q.per_b, rg_in[q]);
+        const int gx = wrap_once(x0 - R + px, NA, per_a, rg_in[q]);
+        const int gy = wrap_once(y0 - R + py, NBB, per_b, rg_in[q]);
         rg_px[q] = px;
         rg_py[q] = py;
         rg_off[q] = gx + (long long)NA * gy;
@@ -280,10 +283,11 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2
     // computed)
     auto load_plane = [&](int z, V3<T>* st) {
         bool zin = true;
-        const long long gz = wrap_plane(z, Z.nc, Z.per_c, zin) * plane;
+        const long long gz = wrap_plane(z, Z.nc, per_c, zin) * plane;
 #pragma unroll
         for (int k = 0; k < KST; ++k) {
-            st[k] = V3<T>{T(0), T(0), T(0)};
+            // (cells past the staged frame are never stored)
+            if constexpr (!PER) st[k] = V3<T>{T(0), T(0), T(0)};
             if (zin && ld_in[k]) {
                 const long long g = ld_off[k] + gz;
                 st[k] = V3<T>{n[g], n[N + g], n[2 * N + g]};
@@ -348,7 +352,7 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2
     const int cN = (tyy + 2 * R) * WN + (tx + 2 * R);          // the site's n(t) cell
     for (int k = z0 - 1; k <= z1; ++k) {
         bool zin = true;
-        const long long gz = wrap_plane(k, Z.nc, Z.per_c, zin) * plane;
+        const long long gz = wrap_plane(k, Z.nc, per_c, zin) * plane;
         // external plus thermal fields of this thread's cells of plane k,
         // then stage n(t) plane k+1.  The empty asm keeps the thermal draws
         // inside the branch: left
@@ -372,7 +376,7 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2
         const V3<T> aI = predict(tx + R, tyy + R, zin && pi_in, k, bI);
 #pragma unroll
         for (int q = 0; q < KRG; ++q)
-            if (tid + q * NT < RING) predict(rg_px[q], rg_py[q], zin && rg_in[q], k, bR[q]);
+            if (tid + q * NT < RING) predict(rg_px[q], rg_py[q], PER || (zin && rg_in[q]), k, bR[q]);
         __syncthreads();
         // corrector of plane k-1
         const int zc = k - 1;
