@@ -857,6 +857,17 @@ void go_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* n
     M.tiles_y = (e->geo.n[1] + TY - 1) / TY;
     const int ntiles = M.tiles_x * M.tiles_y;
     M.xcd_bands = (ntiles >= 8 && ntiles % 8 == 0) ? 1 : 0;
+    // FP32 Depondt on the 64 x 16 x 1024 tiles: a lattice periodic along both
+    // axes takes the instance without boundary tests
+    if constexpr (sizeof(T) == 4 && SOLVER == sp::SOLVER_DEPONDT && TX == 64 && TY == 16 && NT == 1024) {
+        if (e->geo.per[0] && e->geo.per[1]) {
+            hipLaunchKernelGGL((sp::k_fused2d_shape<T, S, NDMI, TX, TY, NT, SOLVER, true>), dim3((unsigned)ntiles),
+                               dim3(NT), 0, e->stream, step_coef_for<T, S>(e), make_site2d<T>(e, p),
+                               make_step_llg<T>(e, p, step), M, e->d_flag, static_cast<const T*>(nin),
+                               static_cast<T*>(nout));
+            return;
+        }
+    }
     hipLaunchKernelGGL((sp::k_fused2d_shape<T, S, NDMI, TX, TY, NT, SOLVER>), dim3((unsigned)ntiles), dim3(NT), 0, e->stream,
                        step_coef_for<T, S>(e), make_site2d<T>(e, p), make_step_llg<T>(e, p, step), M, e->d_flag,
                        static_cast<const T*>(nin), static_cast<T*>(nout));

@@ -379,24 +379,24 @@ struct TileLDS {
 };
 
 // Global site of the predictor-frame cell (px, py), or in = false for a
-// cell outside an open lattice.
-template <typename T, int S, int TX, int TY>
+// cell outside an open lattice (PER: both axes periodic, never).
+template <typename T, int S, int TX, int TY, bool PER = false>
 __device__ __forceinline__ int cell_site(const Site2D<T>& Q, int x0, int y0, int px, int py, bool& in) {
     constexpr int R = ShapeTab<S>::R;
     in = true;
-    const int gx = wrap_once(x0 - R + px, Q.na, Q.per_a, in);
-    const int gy = wrap_once(y0 - R + py, Q.nb, Q.per_b, in);
+    const int gx = wrap_once(x0 - R + px, Q.na, PER ? 1 : Q.per_a, in);
+    const int gy = wrap_once(y0 - R + py, Q.nb, PER ? 1 : Q.per_b, in);
     return gx + gy * Q.na;
 }
 
 // External plus thermal field of a predictor-frame cell (the base of
 // shape_B_aos): depends only on the site, the step and the seed, so it is
 // formed while the spins are still in flight.
-template <typename T, int S, int TX, int TY>
+template <typename T, int S, int TX, int TY, bool PER = false>
 __device__ __forceinline__ V3<T> cell_base(const StepCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int x0,
                                            int y0, int px, int py) {
     bool in;
-    const int site = cell_site<T, S, TX, TY>(Q, x0, y0, px, py, in);
+    const int site = cell_site<T, S, TX, TY, PER>(Q, x0, y0, px, py, in);
     const V3<T> Bext{C.Bext[0], C.Bext[1], C.Bext[2]};
     if (!A.thermal || !in) return Bext;
     return Bext + Q.sigma * normals3(thermal_bits(A.key, (uint32_t)site), T(0));
@@ -427,13 +427,13 @@ __device__ __forceinline__ void ring_cell(int h, int& px, int& py) {
 //   SIB:     x solves the midpoint stage with A frozen; sP holds the
 //            midpoint m = (n + x)/2 (Appendix C), returns nothing.
 // Cells that fall outside an open lattice hold a zero spin.
-template <typename T, int S, int NDMI, int TX, int TY, int SOLVER>
+template <typename T, int S, int NDMI, int TX, int TY, int SOLVER, bool PER = false>
 __device__ __forceinline__ V3<T> predict_cell(const StepCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A, int x0,
                                               int y0, int px, int py, TileLDS<T, S, TX, TY>& L, V3<T> base) {
     using TL = TileLDS<T, S, TX, TY>;
     constexpr int R = TL::R, WN = TL::WN, WP = TL::WP;
     bool in;
-    cell_site<T, S, TX, TY>(Q, x0, y0, px, py, in);
+    cell_site<T, S, TX, TY, PER>(Q, x0, y0, px, py, in);
     V4<T> out{T(0), T(0), T(0), T(0)};
     V3<T> keep{T(0), T(0), T(0)};
     if (in) {
@@ -488,7 +488,7 @@ __device__ __forceinline__ V3<T> correct_cell(const StepCoef<T>& C, const Site2D
 // t owns tile sites t + j NT: it computes their predictor, keeps A and the
 // thermal field in registers, and computes their corrector; the ring of
 // predictor cells around the tile is shared out over the threads between.
-template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER = SOLVER_DEPONDT>
+template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER = SOLVER_DEPONDT, bool PER = false>
 __device__ __forceinline__ void fused2d_tile(const StepCoef<T>& C, const Site2D<T>& Q, const LLGArgs<T>& A,
                                              int x0, int y0, const T* __restrict__ n, T* __restrict__ nout,
                                              TileLDS<T, S, TX, TY>& L) {
@@ -507,12 +507,13 @@ __device__ __forceinline__ void fused2d_tile(const StepCoef<T>& C, const Site2D<
 #pragma unroll
     for (int k = 0; k < KST; ++k) {
         const int idx = tid + k * NT;
-        st[k] = V3<T>{T(0), T(0), T(0)};
+        // (cells past the staged frame are never stored)
+        if constexpr (!PER) st[k] = V3<T>{T(0), T(0), T(0)};
         if (idx < PN) {
             const int ly = idx / WN, lx = idx - ly * WN;
             bool in = true;
-            const int gx = wrap_once(x0 - 2 * R + lx, Q.na, Q.per_a, in);
-            const int gy = wrap_once(y0 - 2 * R + ly, Q.nb, Q.per_b, in);
+            const int gx = wrap_once(x0 - 2 * R + lx, Q.na, PER ? 1 : Q.per_a, in);
+            const int gy = wrap_once(y0 - 2 * R + ly, Q.nb, PER ? 1 : Q.per_b, in);
             if (in) {
                 const int g = gx + gy * Q.na;
                 st[k] = V3<T>{n[g], n[N + g], n[2 * N + g]};
@@ -525,7 +526,7 @@ __device__ __forceinline__ void fused2d_tile(const StepCoef<T>& C, const Site2D<
     for (int j = 0; j < KPT; ++j) {
         const int t = tid + j * NT;
         const int ty = t / TX, tx = t - ty * TX;
-        keepB[j] = cell_base<T, S, TX, TY>(C, Q, A, x0, y0, tx + R, ty + R);
+        keepB[j] = cell_base<T, S, TX, TY, PER>(C, Q, A, x0, y0, tx + R, ty + R);
     }
 #pragma unroll
     for (int k = 0; k < KRG; ++k) {
@@ -534,7 +535,7 @@ __device__ __forceinline__ void fused2d_tile(const StepCoef<T>& C, const Site2D<
         if (h < RING) {
             int px, py;
             ring_cell<R, TX, TY>(h, px, py);
-            ringB[k] = cell_base<T, S, TX, TY>(C, Q, A, x0, y0, px, py);
+            ringB[k] = cell_base<T, S, TX, TY, PER>(C, Q, A, x0, y0, px, py);
         }
     }
 #pragma unroll
@@ -550,7 +551,7 @@ __device__ __forceinline__ void fused2d_tile(const StepCoef<T>& C, const Site2D<
     for (int j = 0; j < KPT; ++j) {
         const int t = tid + j * NT;
         const int ty = t / TX, tx = t - ty * TX;
-        keepA[j] = predict_cell<T, S, NDMI, TX, TY, SOLVER>(C, Q, A, x0, y0, tx + R, ty + R, L, keepB[j]);
+        keepA[j] = predict_cell<T, S, NDMI, TX, TY, SOLVER, PER>(C, Q, A, x0, y0, tx + R, ty + R, L, keepB[j]);
     }
 #pragma unroll
     for (int k = 0; k < KRG; ++k) {
@@ -558,7 +559,7 @@ __device__ __forceinline__ void fused2d_tile(const StepCoef<T>& C, const Site2D<
         if (h < RING) {
             int px, py;
             ring_cell<R, TX, TY>(h, px, py);
-            predict_cell<T, S, NDMI, TX, TY, SOLVER>(C, Q, A, x0, y0, px, py, L, ringB[k]);
+            predict_cell<T, S, NDMI, TX, TY, SOLVER, PER>(C, Q, A, x0, y0, px, py, L, ringB[k]);
         }
     }
     __syncthreads();
@@ -578,7 +579,9 @@ __device__ __forceinline__ void fused2d_tile(const StepCoef<T>& C, const Site2D<
     }
 }
 
-template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER = SOLVER_DEPONDT>
+// PER: both axes periodic, so the boundary tests and zero fills of cells
+// outside the lattice are compiled out.
+template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER = SOLVER_DEPONDT, bool PER = false>
 __global__ void __launch_bounds__(NT) k_fused2d_shape(StepCoef<T> C, Site2D<T> Q, LLGArgs<T> A_arg, TileMap M,
                                                       const int* __restrict__ abort_flag, const T* __restrict__ n,
                                                       T* __restrict__ nout) {
@@ -589,7 +592,7 @@ __global__ void __launch_bounds__(NT) k_fused2d_shape(StepCoef<T> C, Site2D<T> Q
     int tile = blockIdx.x;
     if (M.xcd_bands) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
     const int ty0 = tile / M.tiles_x;
-    fused2d_tile<T, S, NDMI, TX, TY, NT, SOLVER>(C, Q, A, (tile - ty0 * M.tiles_x) * TX, ty0 * TY, n, nout, L);
+    fused2d_tile<T, S, NDMI, TX, TY, NT, SOLVER, PER>(C, Q, A, (tile - ty0 * M.tiles_x) * TX, ty0 * TY, n, nout, L);
 }
 
 // ------------------------------------------------------------ replica batch
