@@ -858,9 +858,11 @@ void go_shape(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* n
     const int ntiles = M.tiles_x * M.tiles_y;
     M.xcd_bands = (ntiles >= 8 && ntiles % 8 == 0) ? 1 : 0;
     // FP32 Depondt on the 64 x 16 x 1024 tiles: a lattice periodic along both
-    // axes takes the instance without boundary tests
+    // axes (whose spins fit 32-bit byte offsets) takes the instance without
+    // boundary tests
     if constexpr (sizeof(T) == 4 && SOLVER == sp::SOLVER_DEPONDT && TX == 64 && TY == 16 && NT == 1024) {
-        if (e->geo.per[0] && e->geo.per[1]) {
+        const long long n_sites = (long long)e->geo.n[0] * e->geo.n[1];
+        if (e->geo.per[0] && e->geo.per[1] && 3 * n_sites * (long long)sizeof(T) < (1ll << 32)) {
             hipLaunchKernelGGL((sp::k_fused2d_shape<T, S, NDMI, TX, TY, NT, SOLVER, true>), dim3((unsigned)ntiles),
                                dim3(NT), 0, e->stream, step_coef_for<T, S>(e), make_site2d<T>(e, p),
                                make_step_llg<T>(e, p, step), M, e->d_flag, static_cast<const T*>(nin),
@@ -1135,10 +1137,11 @@ void go_shape3(sp_engine* e, const sp_llg_params* p, uint64_t step, const void* 
     Z.xcd_bands = ((txy * nchunks) % 8 == 0) ? 1 : 0;
     const dim3 grid((unsigned)(txy * nchunks)), block(TX * TY);
     // Depondt steps without anisotropy take the instance that leaves the term
-    // out; on the 32 x 32 columns a lattice periodic along every axis takes
-    // the instance without boundary tests
+    // out; on the 32 x 32 columns a lattice periodic along every axis (whose
+    // spins fit 32-bit byte offsets) takes the instance without boundary tests
     if constexpr (SOLVER == sp::SOLVER_DEPONDT && TX * TY == 1024) {
-        if (e->geo.per[0] && e->geo.per[1] && e->geo.per[2]) {
+        const long long n_sites = (long long)e->geo.n[0] * e->geo.n[1] * e->geo.n[2];
+        if (e->geo.per[0] && e->geo.per[1] && e->geo.per[2] && 3 * n_sites * (long long)sizeof(T) < (1ll << 32)) {
             if (e->ham.K[0] == 0.0)
                 hipLaunchKernelGGL((sp::k_fused3d_shape<T, S, DK, TX, TY, SOLVER, false, true>), grid, block, 0,
                                    e->stream, step_coef3_for<T, S>(e), make_site2d<T>(e, p), Z,

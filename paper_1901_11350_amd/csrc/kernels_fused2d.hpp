@@ -355,6 +355,18 @@ struct TileMap {
     int xcd_bands;   // 1: XCD-banded mapping (tile count divisible by 8), 0: identity
 };
 
+// Element at a 32-bit byte offset from a base: the address is the base plus
+// the zero-extended offset, which the compiler issues as a scalar-base
+// load or store with a 32-bit vector offset.
+template <typename T>
+__device__ __forceinline__ T at_byte(const T* base, uint32_t off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ T* ptr_byte(T* base, uint32_t off) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+
 // Periodic wrap (or open-boundary rejection) of a staged coordinate.  A tile
 // plus halo can be more than twice as wide as a small lattice, so the wrap
 // is a full modulo, not a single +-n.
@@ -516,7 +528,14 @@ __device__ __forceinline__ void fused2d_tile(const StepCoef<T>& C, const Site2D<
             const int gy = wrap_once(y0 - 2 * R + ly, Q.nb, PER ? 1 : Q.per_b, in);
             if (in) {
                 const int g = gx + gy * Q.na;
-                st[k] = V3<T>{n[g], n[N + g], n[2 * N + g]};
+                if constexpr (PER) {
+                    // 32-bit byte offsets (the host takes this instance only
+                    // when 3N values have them)
+                    const uint32_t b = (uint32_t)g * (uint32_t)sizeof(T);
+                    st[k] = V3<T>{at_byte(n, b), at_byte(n + N, b), at_byte(n + 2 * N, b)};
+                } else {
+                    st[k] = V3<T>{n[g], n[N + g], n[2 * N + g]};
+                }
             }
         }
     }
@@ -573,14 +592,22 @@ __device__ __forceinline__ void fused2d_tile(const StepCoef<T>& C, const Site2D<
         if (gx >= Q.na || gy >= Q.nb) continue;
         const V3<T> o = correct_cell<T, S, NDMI, TX, TY, SOLVER>(C, Q, A, tx, ty, L, keepA[j], keepB[j]);
         const int gi = gx + gy * Q.na;
-        store_out(nout + gi, o.x);
-        store_out(nout + N + gi, o.y);
-        store_out(nout + 2 * N + gi, o.z);
+        if constexpr (PER) {
+            const uint32_t b = (uint32_t)gi * (uint32_t)sizeof(T);
+            store_out(ptr_byte(nout, b), o.x);
+            store_out(ptr_byte(nout + N, b), o.y);
+            store_out(ptr_byte(nout + 2 * N, b), o.z);
+        } else {
+            store_out(nout + gi, o.x);
+            store_out(nout + N + gi, o.y);
+            store_out(nout + 2 * N + gi, o.z);
+        }
     }
 }
 
 // PER: both axes periodic, so the boundary tests and zero fills of cells
-// outside the lattice are compiled out.
+// outside the lattice are compiled out, and spins are addressed by 32-bit
+// byte offsets (the host takes it only when 3N values have them).
 template <typename T, int S, int NDMI, int TX, int TY, int NT, int SOLVER = SOLVER_DEPONDT, bool PER = false>
 __global__ void __launch_bounds__(NT) k_fused2d_shape(StepCoef<T> C, Site2D<T> Q, LLGArgs<T> A_arg, TileMap M,
                                                       const int* __restrict__ abort_flag, const T* __restrict__ n,

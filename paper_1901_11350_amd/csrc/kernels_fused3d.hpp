@@ -193,7 +193,10 @@ __device__ __forceinline__ int wrap_plane(int z, int nc, int per, bool& in) {
 }
 
 // PER: every axis periodic (the lattice wraps, no cell is ever outside it),
-// so the boundary tests and the zero fills of outside cells are compiled out.
+// so the boundary tests and the zero fills of outside cells are compiled
+// out; the host takes it only when 3N floats have 32-bit byte offsets, so
+// sites are addressed by 32-bit offsets from the three component bases
+// (scalar base + vector offset loads and stores, no 64-bit address math).
 template <typename T, int S, int DK, int TX, int TY, int SOLVER, bool AN, bool PER = false>
 __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2D<T> Q, Site3D Z, LLGArgs<T> A_arg,
                                                             const int* __restrict__ abort_flag,
@@ -233,6 +236,12 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2
     const long long plane = (long long)NA * NBB;
     const long long N = plane * Z.nc;
     const int tx = tid % TX, tyy = tid / TX;
+    const T* const nx = n;
+    const T* const ny = n + N;
+    const T* const nz = n + 2 * N;
+    T* const ox_ = nout;
+    T* const oy_ = nout + N;
+    T* const oz_ = nout + 2 * N;
     // predictor ring slot of plane z (z >= -2)
     auto pslot = [](int z) { return (z + 3) % 3; };
 
@@ -289,8 +298,13 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2
             // (cells past the staged frame are never stored)
             if constexpr (!PER) st[k] = V3<T>{T(0), T(0), T(0)};
             if (zin && ld_in[k]) {
-                const long long g = ld_off[k] + gz;
-                st[k] = V3<T>{n[g], n[N + g], n[2 * N + g]};
+                if constexpr (PER) {
+                    const uint32_t b = ((uint32_t)ld_off[k] + (uint32_t)gz) * (uint32_t)sizeof(T);
+                    st[k] = V3<T>{at_byte(nx, b), at_byte(ny, b), at_byte(nz, b)};
+                } else {
+                    const long long g = ld_off[k] + gz;
+                    st[k] = V3<T>{n[g], n[N + g], n[2 * N + g]};
+                }
             }
         }
     };
@@ -396,10 +410,17 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2
                 const V3<T> w{T(0.5) * (keepA.x + wp.x), T(0.5) * (keepA.y + wp.y), T(0.5) * (keepA.z + wp.z)};
                 o = renorm_if_float(rotate_half(ni, w, hrot));
             }
-            const long long gi = pi_off + (long long)zc * plane;
-            store_out(nout + gi, o.x);
-            store_out(nout + N + gi, o.y);
-            store_out(nout + 2 * N + gi, o.z);
+            if constexpr (PER) {
+                const uint32_t b = ((uint32_t)pi_off + (uint32_t)zc * (uint32_t)plane) * (uint32_t)sizeof(T);
+                store_out(ptr_byte(ox_, b), o.x);
+                store_out(ptr_byte(oy_, b), o.y);
+                store_out(ptr_byte(oz_, b), o.z);
+            } else {
+                const long long gi = pi_off + (long long)zc * plane;
+                store_out(nout + gi, o.x);
+                store_out(nout + N + gi, o.y);
+                store_out(nout + 2 * N + gi, o.z);
+            }
         }
         keepA = aI;
         keepB = bI;
