@@ -147,8 +147,11 @@ __device__ __forceinline__ V3<T> rotate_half(V3<T> n, V3<T> w, T h) {
         inv = w2 > 0.0 ? 1.0 / sqrt(w2) : 0.0;
         sincos(h * (w2 * inv), &sh, &ch);
     }
-    const T s1 = T(2) * sh * ch * inv;
-    const T s2 = T(2) * sh * sh * (inv * inv);
+    // t = sin(theta/2) / |w|: s1 = 2 t cos(theta/2), s2 = 2 t^2
+    const T t = sh * inv;
+    const T t2 = t + t;
+    const T s1 = t2 * ch;
+    const T s2 = t2 * t;
     const V3<T> wxn = cross(w, n);
     const T wn = dot(w, n);
     return V3<T>{n.x + s1 * wxn.x + s2 * (w.x * wn - w2 * n.x),
