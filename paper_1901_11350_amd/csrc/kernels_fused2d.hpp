@@ -492,10 +492,10 @@ __device__ __forceinline__ V3<T> correct_cell(const StepCoef<T>& C, const Site2D
         // npi is the midpoint m; A(m) drives the second midpoint stage
         return renorm_if_float(sib_stage(ni, llg_A(npi, B, A.gp, A.alpha), A.dt));
     } else {
-        // the mean of the two rotation vectors (A + A^p)/2, up to -gp
+        // about the mean of the two rotation vectors (A + A^p)/2, up to -gp:
+        // the sum turned by half the angle factor (the halving is exact)
         const V3<T> wp = llg_w(npi, B, A.alpha);
-        const V3<T> w{T(0.5) * (keepA.x + wp.x), T(0.5) * (keepA.y + wp.y), T(0.5) * (keepA.z + wp.z)};
-        return renorm_if_float(rotate_half(ni, w, rot_half_factor(A.gp, A.dt)));
+        return renorm_if_float(rotate_half(ni, keepA + wp, T(0.5) * rot_half_factor(A.gp, A.dt)));
     }
 }
 
@@ -774,10 +774,9 @@ __global__ void __launch_bounds__(NT) k_batch_resident(ShapeCoef<T> C, Site2D<T>
                 const V3<T> g = shape_field_soa<T, S, NDMI, W>(C, Q, sP, sP + P, sP + 2 * P, c, npi);
                 const V3<T> B = (-Q.inv_mumuB) * g + keepB[j];
                 const V3<T> wp = llg_w(npi, B, A.alpha);
-                const V3<T> w{T(0.5) * (keepA[j].x + wp.x), T(0.5) * (keepA[j].y + wp.y),
-                              T(0.5) * (keepA[j].z + wp.z)};
                 const V3<T> ni{sN[c], sN[P + c], sN[2 * P + c]};
-                const V3<T> o = renorm_if_float(rotate_half(ni, w, rot_half_factor(A.gp, A.dt)));
+                const V3<T> o =
+                    renorm_if_float(rotate_half(ni, keepA[j] + wp, T(0.5) * rot_half_factor(A.gp, A.dt)));
                 sN[c] = o.x;
                 sN[P + c] = o.y;
                 sN[2 * P + c] = o.z;

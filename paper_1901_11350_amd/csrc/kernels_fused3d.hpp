@@ -406,9 +406,8 @@ __global__ void __launch_bounds__(TX * TY) k_fused3d_shape(StepCoef3<T> C, Site2
             } else if constexpr (SOLVER == SOLVER_SIB) {
                 o = renorm_if_float(sib_stage(ni, llg_A(npi, B, A.gp, A.alpha), A.dt));
             } else {
-                const V3<T> wp = llg_w(npi, B, A.alpha);
-                const V3<T> w{T(0.5) * (keepA.x + wp.x), T(0.5) * (keepA.y + wp.y), T(0.5) * (keepA.z + wp.z)};
-                o = renorm_if_float(rotate_half(ni, w, hrot));
+                // about the mean rotation vector: the sum by half the angle factor
+                o = renorm_if_float(rotate_half(ni, keepA + llg_w(npi, B, A.alpha), T(0.5) * hrot));
             }
             if constexpr (PER) {
                 const uint32_t b = ((uint32_t)pi_off + (uint32_t)zc * (uint32_t)plane) * (uint32_t)sizeof(T);

@@ -263,9 +263,8 @@ __global__ void __launch_bounds__(NB * TX * TY * TZ) k_fused_tile(StencilB<T> S,
     } else if constexpr (SOLVER == SOLVER_SIB) {
         o = renorm_if_float(sib_stage(ni, llg_A(npi, B, A.gp, A.alpha), A.dt));
     } else {
-        const V3<T> wp = llg_w(npi, B, A.alpha);
-        const V3<T> w{T(0.5) * (keep.x + wp.x), T(0.5) * (keep.y + wp.y), T(0.5) * (keep.z + wp.z)};
-        o = renorm_if_float(rotate_half(ni, w, rot_half_factor(A.gp, A.dt)));
+        // about the mean rotation vector: the sum by half the angle factor
+        o = renorm_if_float(rotate_half(ni, keep + llg_w(npi, B, A.alpha), T(0.5) * rot_half_factor(A.gp, A.dt)));
     }
     const int gi = ox + na * (oy + nbc * oz) + beta * block;
     store_out(nout + gi, o.x);
