@@ -837,14 +837,13 @@ template <typename T, int S>
 sp::StepCoef<T> step_coef_for(const sp_engine* e) {
     using SH = sp::ShapeTab<S>;
     const double inv = 1.0 / (e->ham.mu[0] * kMuB);
+    const sp::ShapeCoef<double> D = shape_coef_for<double, S>(e);
     sp::StepCoef<T> C{};
-    for (int s = 0; s < SH::NS; ++s) C.J[s] = (T)(s < e->ham.n_exch ? e->ham.J[s] * inv : 0.0);
-    for (int q = 0; q < SH::NB; ++q)
-        for (const HostBond& b : e->all_bonds)
-            if (b.d[0] == SH::da[q] && b.d[1] == SH::db[q] && b.shell == SH::sh[q]) {
-                C.Dx[q] = (T)(b.D[0] * inv);
-                C.Dy[q] = (T)(b.D[1] * inv);
-            }
+    for (int s = 0; s < SH::NS; ++s) C.J[s] = (T)(D.J[s] * inv);
+    for (int q = 0; q < SH::NB; ++q) {
+        C.Dx[q] = (T)(D.Dx[q] * inv);
+        C.Dy[q] = (T)(D.Dy[q] * inv);
+    }
     C.K2 = (T)(2.0 * e->ham.K[0] * inv);
     for (int k = 0; k < 3; ++k) C.Bext[k] = (T)e->ham.B[k];
     return C;
@@ -1106,17 +1105,15 @@ template <typename T, int S>
 sp::StepCoef3<T> step_coef3_for(const sp_engine* e) {
     using SH = sp::ShapeTab3<S>;
     const double inv = 1.0 / (e->ham.mu[0] * kMuB);
+    const sp::ShapeCoef3<double> D = shape_coef3_for<double, S>(e);
     sp::StepCoef3<T> C{};
-    for (int s = 0; s < SH::NS; ++s) C.J[s] = (T)(s < e->ham.n_exch ? e->ham.J[s] * inv : 0.0);
-    for (int q = 0; q < SH::NB0; ++q)
-        for (const HostBond& b : e->all_bonds)
-            if (b.d[0] == SH::da[q] && b.d[1] == SH::db[q] && b.d[2] == SH::dc[q] && b.shell == 0) {
-                C.Dx[q] = (T)(b.D[0] * inv);
-                C.Dy[q] = (T)(b.D[1] * inv);
-                C.Dz[q] = (T)(b.D[2] * inv);
-            }
-    double d0 = 0.0;
-    if (bulk_dmi3(e->all_bonds, &d0)) C.D0 = (T)(d0 * inv);
+    for (int s = 0; s < SH::NS; ++s) C.J[s] = (T)(D.J[s] * inv);
+    for (int q = 0; q < SH::NB0; ++q) {
+        C.Dx[q] = (T)(D.Dx[q] * inv);
+        C.Dy[q] = (T)(D.Dy[q] * inv);
+        C.Dz[q] = (T)(D.Dz[q] * inv);
+    }
+    C.D0 = (T)(D.D0 * inv);
     C.K2 = (T)(2.0 * e->ham.K[0] * inv);
     for (int k = 0; k < 3; ++k) C.Bext[k] = (T)e->ham.B[k];
     return C;
