@@ -12,13 +12,14 @@
 // Per workgroup (NT threads, TX x TY output tile):
 //   1. stage n(t) on the tile plus a 2R halo into LDS, one 16-byte cell per
 //      site (periodic axes wrap, open axes pad with zero spins, which drop
-//      out of every bond sum); the thermal fields of the cells a thread
-//      will predict (Philox, counter = global site) are formed while these
-//      loads are in flight;
-//   2. predictor on the tile plus an R halo: field, A = -gp (B + alpha n x B),
-//      n^p = R(A) n into LDS; A and the thermal field of the tile sites stay
-//      in the registers of the thread that owns the site;
-//   3. corrector on the tile: A^p from n^p, n(t+dt) = R((A + A^p)/2) n(t),
+//      out of every bond sum); the external plus thermal field of the cells
+//      a thread will predict (Philox, counter = global site) is formed while
+//      these loads are in flight;
+//   2. predictor on the tile plus an R halo: field B in Tesla (coefficients
+//      divided by mu mu_B on the host), w = B + alpha n x B (A = -gp w),
+//      n^p = R(A) n into LDS; w and the base field of the tile sites stay in
+//      the registers of the thread that owns the site;
+//   3. corrector on the tile: w^p from n^p, n(t+dt) = R((A + A^p)/2) n(t),
 //      written once to HBM.
 // Workgroups are mapped to tiles so that each XCD (workgroups are dealt to
 // the 8 XCDs round-robin) owns a contiguous band of tile rows: neighbouring

@@ -15,8 +15,9 @@
 //      spin, which adds nothing to a field), every load issued before the
 //      first LDS write; the thermal field of the owned site is drawn while
 //      the loads are in flight;
-//   2. predictor of the owned site (A and the thermal field stay in
-//      registers) and of the ring of cells within (R, R, RC) of the tile,
+//   2. predictor of the owned site (its rotation vector, or Heun slope, and
+//      thermal field stay in registers) and of the ring of cells within
+//      (R, R, RC) of the tile,
 //      spread over the workgroup;
 //   3. corrector of the owned site from the predictor field; n(t+dt) is
 //      written once.
